@@ -1,0 +1,247 @@
+/*
+ * ttiga.h - C ABI of the TT-IGA library for MI355X (gfx950).
+ *
+ * The library assembles the isogeometric stiffness operator and load vector of
+ * the 3-D Poisson problem in tensor-train (TT) form and solves the reduced
+ * system in TT.  All arithmetic runs in HIP kernels on one GPU; the host code
+ * behind this header only validates arguments, sizes buffers and sequences
+ * kernel launches.
+ *
+ * Problem statement (Section 3.1): -Laplace u = f on the image of a NURBS
+ * solid (Section 2.3), u = u_bar on Dirichlet faces, zero traction elsewhere.
+ * Discretisation (Section 3.3): B-spline solution space of degree p with n
+ * basis functions per parametric direction (open uniform knots, i.e. the
+ * h-refined space), stiffness K and load F of eqs. Kfinal / ffinal.
+ * TT assembly (Sections 4.2.1 and 4.2.2): metric factors R_ij and f det J are
+ * sampled at Gauss points, compressed to TT with tolerance eps and contracted
+ * against 1-D B-spline matrices; the nine K_ij are summed with TT-rounding
+ * after each addition.  Boundary conditions (Section 4.3) reduce the system to
+ * the interior unknowns.  The TT solve is a preconditioned truncated TT-CG.
+ *
+ * Conventions
+ *   - Flattened multi-index: (i0 * n1 + i1) * n2 + i2 (first direction slowest),
+ *     the lexicographic order of Section 4.1.1.
+ *   - TT cores are stored in the paper's order G_k[r_{k-1}][n_k][r_k], row-major,
+ *     r_0 = r_3 = 1 (Section 4.1.1).
+ *   - TT-matrix cores are stored banded: M_k[r_{k-1}][n_k][2p+1][r_k], entry
+ *     (i, t) holds the 1-D column j = i + t - p; entries whose j falls outside
+ *     [0, n_k) are zero.  Only |i - j| <= p can be non-zero because the 1-D
+ *     factors are products of B-splines whose supports overlap only then.
+ *   - Face order for boundary data: xi0=0, xi0=1, xi1=0, xi1=1, xi2=0, xi2=1.
+ *   - Every call returns TTIGA_OK (0), TTIGA_PENDING (1) or a negative error.
+ *     No C++ exception crosses this interface.  ttiga_last_error() returns
+ *     the message of the last failing call on the calling thread.
+ *   - All device work is enqueued on the stream bound to the context; calls
+ *     that fill a stats struct or copy to host memory synchronise it.
+ *   - A context is not thread-safe: one thread drives it at a time.
+ */
+#ifndef TTIGA_H
+#define TTIGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TTIGA_VERSION_MAJOR 0
+#define TTIGA_VERSION_MINOR 1
+
+#define TTIGA_OK 0
+#define TTIGA_PENDING 1
+#define TTIGA_E_ARG (-1)       /* null pointer, bad size, unsupported option */
+#define TTIGA_E_KNOTS (-2)     /* non-monotone knots, wrong length, end multiplicity != p+1 */
+#define TTIGA_E_GEOM (-3)      /* non-positive weight */
+#define TTIGA_E_DETJ (-4)      /* min det J <= 0 at some Gauss point (folded map) */
+#define TTIGA_E_OOM (-5)       /* workspace exhausted */
+#define TTIGA_E_ADMISSION (-6) /* server: request does not fit now */
+#define TTIGA_E_NOTCONV (-7)   /* iteration limit reached; solution and stats still valid */
+#define TTIGA_E_RANKCAP (-8)   /* a TT rank exceeded options.max_rank */
+#define TTIGA_E_STATE (-9)     /* call out of order (e.g. solve before assemble) */
+#define TTIGA_E_HIP (-10)      /* HIP runtime error; text in ttiga_last_error() */
+
+#define TTIGA_SOURCE_ZERO 0
+#define TTIGA_SOURCE_MANUFACTURED_ANNULUS 1 /* forcing of u = sin(pi r) sin(2 theta) sin(pi z) */
+#define TTIGA_SOURCE_FOURIER 2              /* sum_m a_m sin(pi k_m.(x - origin)/scale + phi_m) */
+
+#define TTIGA_BC_NATURAL 0  /* zero traction: nothing to impose */
+#define TTIGA_BC_ZERO 1     /* homogeneous Dirichlet */
+#define TTIGA_BC_CONSTANT 2 /* u = value on the face */
+
+#define TTIGA_FP64 0
+#define TTIGA_FP32 1
+#define TTIGA_BF16 2
+
+typedef struct ttiga_ctx ttiga_ctx;
+typedef struct ttiga_problem ttiga_problem;
+typedef struct ttiga_tt ttiga_tt; /* library-owned TT tensor (results of standalone ops) */
+
+/* NURBS solid (Section 2.3): degree, open knot vectors (end multiplicity
+ * degree+1, length n_ctrl+degree+1), control points [n0][n1][n2][3] C-order,
+ * weights [n0][n1][n2] or NULL for a B-spline solid.  Host pointers. */
+typedef struct {
+  int degree[3];
+  int n_ctrl[3];
+  const double* knots[3];
+  const double* ctrl_xyz;
+  const double* weights;
+} ttiga_geometry;
+
+/* Solution space (Section 3.3): degree p, n basis per direction (n >= p+1),
+ * n_gauss Gauss-Legendre points per knot span (0 means p+1, at most 8). */
+typedef struct {
+  int degree;
+  int n_basis[3];
+  int n_gauss;
+} ttiga_discretization;
+
+/* Source term f (Section 3.1).  For FOURIER: n_modes entries in a, phi and
+ * n_modes x 3 in k (host pointers, C order). */
+typedef struct {
+  int kind;
+  int n_modes;
+  const double* a;
+  const double* k;
+  const double* phi;
+  double origin[3];
+  double scale;
+} ttiga_source;
+
+/* Boundary data per face (Section 3.1, u = u_bar on Gamma_D). */
+typedef struct {
+  int kind[6];
+  double value[6];
+} ttiga_dirichlet;
+
+typedef struct {
+  double tt_eps;      /* TT tolerance of compression and rounding */
+  double rel_res_tol; /* stop when ||F_I - K_II u||_2 <= tol ||F_I||_2 */
+  int max_iter;
+  int max_rank;       /* cap on every TT rank; exceeding it fails with E_RANKCAP */
+  int precision;      /* TTIGA_FP64 (others: E_ARG in this version) */
+  int precond;        /* 1: separable Laplacian preconditioner, 0: plain TT-CG */
+} ttiga_options;
+
+typedef struct {
+  int status;
+  int rank_R[6][4];  /* TT ranks of R_00, R_11, R_22, R_01, R_02, R_12 (all 0: dropped) */
+  int rank_fJ[4];    /* TT ranks of f det J */
+  int rank_K[4];     /* TT ranks of the assembled K (before boundary reduction) */
+  int rank_F[4];
+  double min_detJ;
+  double max_R_norm;  /* max_ij ||R_ij||_F over the Gauss grid */
+  double time_ms[4];  /* basis+geometry, compression, core assembly+rounding, boundary */
+} ttiga_assembly_stats;
+
+typedef struct {
+  int status;
+  int iterations;
+  double rel_res;    /* true ||F_I - K_II u|| / ||F_I|| of the returned solution */
+  int rank_u[4];
+  int max_rank_seen;
+  double time_ms;
+} ttiga_solve_stats;
+
+/* Plain views of caller-owned device TT data (used by the standalone ops). */
+typedef struct {
+  int n[3];
+  int r[4];
+  const double* core[3]; /* device pointers, layout [r_k][n_k][r_{k+1}] */
+} ttiga_tt_view;
+
+typedef struct {
+  int n[3];
+  int p;                 /* half band width; 2p+1 band entries per row */
+  int r[4];
+  const double* core[3]; /* device pointers, layout [r_k][n_k][2p+1][r_{k+1}] */
+} ttiga_ttm_view;
+
+int ttiga_version(int* major, int* minor);
+
+/* Context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t,
+ * owned by the caller, NULL = the null stream). */
+int ttiga_create(int device, void* hip_stream, ttiga_ctx** out);
+int ttiga_destroy(ttiga_ctx* ctx);
+
+/* Device memory for all library allocations: [dev_ptr, dev_ptr + bytes) is
+ * sub-allocated by the library and must outlive the context and every
+ * problem created on it.  Without a workspace the library allocates device
+ * memory itself.  May be called once, before the first allocation. */
+int ttiga_set_workspace(ttiga_ctx* ctx, void* dev_ptr, size_t bytes);
+
+const char* ttiga_last_error(void);
+
+/* Host-only check of a problem description (no device work): the status
+ * ttiga_problem_create would return for it before touching the GPU. */
+int ttiga_validate(const ttiga_geometry* geo, const ttiga_discretization* disc, const ttiga_source* src,
+                   const ttiga_dirichlet* bc, const ttiga_options* opt);
+
+/* Copy and validate one problem description.  The inputs may be freed on return. */
+int ttiga_problem_create(ttiga_ctx* ctx, const ttiga_geometry* geo, const ttiga_discretization* disc,
+                         const ttiga_source* src, const ttiga_dirichlet* bc, const ttiga_options* opt,
+                         ttiga_problem** out);
+int ttiga_problem_destroy(ttiga_problem* prob);
+
+/* Assembly (Sections 4.2-4.3): basis tables, geometry factors at the Gauss
+ * grid, TT compression, TT cores of the nine K_ij and of F, sum + rounding,
+ * boundary reduction.  K and F stay on the device, owned by the problem. */
+int ttiga_assemble(ttiga_problem* prob, ttiga_assembly_stats* stats);
+
+/* TT solve of K_II u_I = F_I - K_IB u_B.  On E_NOTCONV the solution and stats are valid. */
+int ttiga_solve(ttiga_problem* prob, ttiga_solve_stats* stats);
+
+/* Ranks and mode sizes of the interior solution TT. */
+int ttiga_solution_ranks(const ttiga_problem* prob, int ranks[4], int n[3]);
+
+/* Copy the interior solution cores, concatenated in paper order, to host
+ * memory `dst` holding `count` doubles (E_ARG if too small). */
+int ttiga_get_solution(const ttiga_problem* prob, double* dst, size_t count);
+
+/* Which TT of an assembled problem a query refers to. */
+#define TTIGA_WHICH_K 0        /* full K, banded TT-matrix cores */
+#define TTIGA_WHICH_F 1        /* full F */
+#define TTIGA_WHICH_KII 2      /* interior K_II, banded */
+#define TTIGA_WHICH_RHS 3      /* F_I - K_IB u_B */
+#define TTIGA_WHICH_FACTOR0 10 /* +f, f = 0..6: TT of R_00, R_11, R_22, R_01, R_02, R_12, f det J */
+
+/* Ranks and mode sizes of an assembled TT; for the banded matrices n is the
+ * number of rows per direction and `band` is set to 2p+1 (1 for tensors).
+ * Ranks are all zero for a factor that was truncated to the zero tensor. */
+int ttiga_problem_tt_info(const ttiga_problem* prob, int which, int ranks[4], int n[3], int* band);
+
+/* Copy the cores of an assembled TT to host memory (paper order, concatenated). */
+int ttiga_problem_tt_copy(const ttiga_problem* prob, int which, double* dst, size_t count);
+
+/* Geometry factors (eq. Rxi and the integrand of eq. ffinal) at `count`
+ * parametric points pts[count][3] (host, each coordinate in [0,1]):
+ * out[7][count] (host) = R_00, R_11, R_22, R_01, R_02, R_12, f det J,
+ * det_out[count] (host, may be NULL).  Same kernel as the Gauss-grid sampling. */
+int ttiga_sample_factors(ttiga_problem* prob, const double* pts, size_t count, double* out,
+                         double* det_out);
+
+/* Standalone banded TT-matvec y = K x on caller device data: y is written to a
+ * library-owned TT (ranks r_K * r_x), returned in *out (free with ttiga_tt_free). */
+int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, ttiga_tt** out);
+
+/* Standalone TT-rounding (Oseledets 2011, used after each summation of
+ * Section 4.2.1): y = round(x, eps) with per-unfolding threshold
+ * eps * ||x||_F / sqrt(2). */
+int ttiga_tt_round(ttiga_ctx* ctx, const ttiga_tt_view* x, double eps, ttiga_tt** out);
+
+/* Standalone TT inner product <x, y> (left-to-right contraction), result to host. */
+int ttiga_tt_dot(ttiga_ctx* ctx, const ttiga_tt_view* x, const ttiga_tt_view* y, double* out);
+
+/* TT-SVD of a dense device tensor A[n0][n1][n2] with absolute per-unfolding
+ * threshold delta (randomised range finder above 64 points per mode). */
+int ttiga_tt_compress(ttiga_ctx* ctx, const double* A, const int n[3], double delta, ttiga_tt** out);
+
+int ttiga_tt_info(const ttiga_tt* t, int ranks[4], int n[3]);
+int ttiga_tt_copy(const ttiga_tt* t, double* dst, size_t count); /* to host, paper order */
+int ttiga_tt_free(ttiga_tt* t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTIGA_H */

@@ -1,0 +1,420 @@
+// extern "C" entry points: argument checks, exception -> status code, and the
+// device allocator / context plumbing.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "problem.hpp"
+
+namespace ttiga {
+
+static thread_local std::string g_last_error;
+
+DeviceAllocator::~DeviceAllocator() {
+  for (auto& kv : direct_) (void)hipFree(kv.first);
+}
+
+void DeviceAllocator::set_workspace(void* base, size_t bytes) {
+  TTIGA_CHECK(base_ == nullptr && direct_.empty(), TTIGA_E_STATE,
+              "workspace must be set before the first allocation");
+  TTIGA_CHECK(base && bytes >= 4096, TTIGA_E_ARG, "workspace too small");
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t a = (b + 255) & ~uintptr_t(255);
+  base_ = reinterpret_cast<char*>(a);
+  size_ = (bytes - (a - b)) & ~size_t(255);
+  free_.clear();
+  free_[0] = size_;
+}
+
+void* DeviceAllocator::alloc(size_t bytes) {
+  bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+  if (!base_) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(TTIGA_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    direct_[p] = bytes;
+    in_use_ += bytes;
+    high_water_ = std::max(high_water_, in_use_);
+    return p;
+  }
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= bytes) {
+      const size_t off = it->first, sz = it->second;
+      free_.erase(it);
+      if (sz > bytes) free_[off + bytes] = sz - bytes;
+      used_[off] = bytes;
+      in_use_ += bytes;
+      high_water_ = std::max(high_water_, in_use_);
+      return base_ + off;
+    }
+  }
+  throw Error(TTIGA_E_OOM, "workspace exhausted: need " + std::to_string(bytes) + " bytes, " +
+                               std::to_string(size_ - in_use_) + " free (fragmented)");
+}
+
+void DeviceAllocator::release(void* p) {
+  if (!p) return;
+  if (!base_) {
+    auto it = direct_.find(p);
+    if (it != direct_.end()) {
+      in_use_ -= it->second;
+      (void)hipFree(p);
+      direct_.erase(it);
+    }
+    return;
+  }
+  const size_t off = static_cast<char*>(p) - base_;
+  auto it = used_.find(off);
+  if (it == used_.end()) return;
+  size_t sz = it->second;
+  used_.erase(it);
+  in_use_ -= sz;
+  size_t start = off;
+  auto nx = free_.lower_bound(off);
+  if (nx != free_.end() && nx->first == off + sz) {
+    sz += nx->second;
+    free_.erase(nx);
+  }
+  auto pv = free_.lower_bound(off);
+  if (pv != free_.begin()) {
+    --pv;
+    if (pv->first + pv->second == off) {
+      start = pv->first;
+      sz += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_[start] = sz;
+}
+
+Context::~Context() {
+  if (host_scratch) (void)hipHostFree(host_scratch);
+}
+
+double* Context::host(size_t n) {
+  if (n > host_scratch_doubles) {
+    if (host_scratch) TTIGA_HIP(hipHostFree(host_scratch));
+    host_scratch = nullptr;
+    TTIGA_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_scratch), sizeof(double) * std::max<size_t>(n, 64)));
+    host_scratch_doubles = std::max<size_t>(n, 64);
+  }
+  return host_scratch;
+}
+
+template <class F>
+static int guard(F&& f) {
+  try {
+    f();
+    return TTIGA_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return TTIGA_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return TTIGA_E_ARG;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return TTIGA_E_ARG;
+  }
+}
+
+static void copy_tt_to_host(Context& c, const TT& t, double* dst, size_t count) {
+  const size_t need = t.total_elems();
+  TTIGA_CHECK(dst != nullptr || need == 0, TTIGA_E_ARG, "null destination");
+  TTIGA_CHECK(count >= need, TTIGA_E_ARG, "destination too small: need " + std::to_string(need));
+  size_t off = 0;
+  for (int k = 0; k < 3; ++k) {
+    const size_t ne = t.core_elems(k);
+    if (ne) TTIGA_HIP(hipMemcpyAsync(dst + off, t.c[k].d(), sizeof(double) * ne, hipMemcpyDeviceToHost, c.stream));
+    off += ne;
+  }
+  c.sync();
+}
+
+}  // namespace ttiga
+
+struct ttiga_ctx {
+  ttiga::Context impl;
+};
+
+using namespace ttiga;
+
+// Objects created on a context keep it alive: ttiga_destroy on a context with
+// live problems or TT handles only marks it, and the last object frees it.
+static void ctx_retain(Context* c) { ++c->live_objects; }
+static void ctx_release(Context* c) {
+  if (--c->live_objects == 0 && c->closing && c->on_last_release) c->on_last_release(c);
+}
+
+extern "C" {
+
+int ttiga_version(int* major, int* minor) {
+  if (major) *major = TTIGA_VERSION_MAJOR;
+  if (minor) *minor = TTIGA_VERSION_MINOR;
+  return TTIGA_OK;
+}
+
+const char* ttiga_last_error(void) { return g_last_error.c_str(); }
+
+int ttiga_create(int device, void* hip_stream, ttiga_ctx** out) {
+  return guard([&] {
+    TTIGA_CHECK(out != nullptr, TTIGA_E_ARG, "null output");
+    int count = 0;
+    TTIGA_HIP(hipGetDeviceCount(&count));
+    TTIGA_CHECK(device >= 0 && device < count, TTIGA_E_ARG, "no such HIP device");
+    TTIGA_HIP(hipSetDevice(device));
+    auto* c = new ttiga_ctx();
+    c->impl.on_last_release = [](Context* ic) {
+      (void)hipStreamSynchronize(ic->stream);
+      delete ic->owner;
+    };
+    c->impl.owner = c;
+    c->impl.device = device;
+    c->impl.stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+  });
+}
+
+int ttiga_destroy(ttiga_ctx* ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->impl.stream);
+    if (ctx->impl.live_objects > 0) {
+      ctx->impl.closing = true;
+      return;
+    }
+    delete ctx;
+  });
+}
+
+int ttiga_set_workspace(ttiga_ctx* ctx, void* dev_ptr, size_t bytes) {
+  return guard([&] {
+    TTIGA_CHECK(ctx != nullptr, TTIGA_E_ARG, "null context");
+    ctx->impl.alloc.set_workspace(dev_ptr, bytes);
+  });
+}
+
+int ttiga_problem_create(ttiga_ctx* ctx, const ttiga_geometry* geo, const ttiga_discretization* disc,
+                         const ttiga_source* src, const ttiga_dirichlet* bc, const ttiga_options* opt,
+                         ttiga_problem** out) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && out, TTIGA_E_ARG, "null context or output");
+    TTIGA_HIP(hipSetDevice(ctx->impl.device));
+    auto* p = new Problem(&ctx->impl, geo, disc, src, bc, opt);
+    try {
+      p->upload();
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = new ttiga_problem{p};
+    ctx_retain(&ctx->impl);
+  });
+}
+
+int ttiga_validate(const ttiga_geometry* geo, const ttiga_discretization* disc, const ttiga_source* src,
+                   const ttiga_dirichlet* bc, const ttiga_options* opt) {
+  return guard([&] { Problem probe(nullptr, geo, disc, src, bc, opt); });
+}
+
+int ttiga_problem_destroy(ttiga_problem* prob) {
+  return guard([&] {
+    if (!prob) return;
+    Context* c = prob->impl->ctx;
+    (void)hipStreamSynchronize(c->stream);
+    delete prob->impl;
+    delete prob;
+    ctx_release(c);
+  });
+}
+
+int ttiga_assemble(ttiga_problem* prob, ttiga_assembly_stats* stats) {
+  int code = guard([&] {
+    TTIGA_CHECK(prob != nullptr, TTIGA_E_ARG, "null problem");
+    TTIGA_HIP(hipSetDevice(prob->impl->ctx->device));
+    prob->impl->assemble(stats);
+  });
+  if (stats) stats->status = code;
+  return code;
+}
+
+int ttiga_solve(ttiga_problem* prob, ttiga_solve_stats* stats) {
+  int code = guard([&] {
+    TTIGA_CHECK(prob != nullptr, TTIGA_E_ARG, "null problem");
+    TTIGA_HIP(hipSetDevice(prob->impl->ctx->device));
+    prob->impl->solve(stats);
+  });
+  if (stats && prob && prob->impl->solved) {
+    *stats = prob->impl->last_solve;
+    stats->status = code;
+  } else if (stats) {
+    stats->status = code;
+  }
+  return code;
+}
+
+int ttiga_solution_ranks(const ttiga_problem* prob, int ranks[4], int n[3]) {
+  return guard([&] {
+    TTIGA_CHECK(prob && ranks && n, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(prob->impl->solved, TTIGA_E_STATE, "no solution yet");
+    const TT& u = prob->impl->u;
+    for (int k = 0; k < 4; ++k) ranks[k] = u.r[k];
+    for (int k = 0; k < 3; ++k) n[k] = u.n[k];
+  });
+}
+
+int ttiga_get_solution(const ttiga_problem* prob, double* dst, size_t count) {
+  return guard([&] {
+    TTIGA_CHECK(prob != nullptr, TTIGA_E_ARG, "null problem");
+    TTIGA_CHECK(prob->impl->solved, TTIGA_E_STATE, "no solution yet");
+    copy_tt_to_host(*prob->impl->ctx, prob->impl->u, dst, count);
+  });
+}
+
+int ttiga_problem_tt_info(const ttiga_problem* prob, int which, int ranks[4], int n[3], int* band) {
+  return guard([&] {
+    TTIGA_CHECK(prob && ranks && n, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(prob->impl->assembled, TTIGA_E_STATE, "problem not assembled");
+    const TT* t = prob->impl->which(which);
+    TTIGA_CHECK(t != nullptr, TTIGA_E_ARG, "unknown TT selector");
+    const bool banded = (which == TTIGA_WHICH_K || which == TTIGA_WHICH_KII);
+    const int bw = banded ? 2 * prob->impl->p + 1 : 1;
+    for (int k = 0; k < 4; ++k) ranks[k] = t->r[k];
+    for (int k = 0; k < 3; ++k) n[k] = t->n[k] / bw;
+    if (band) *band = bw;
+  });
+}
+
+int ttiga_problem_tt_copy(const ttiga_problem* prob, int which, double* dst, size_t count) {
+  return guard([&] {
+    TTIGA_CHECK(prob != nullptr, TTIGA_E_ARG, "null problem");
+    TTIGA_CHECK(prob->impl->assembled, TTIGA_E_STATE, "problem not assembled");
+    const TT* t = prob->impl->which(which);
+    TTIGA_CHECK(t != nullptr, TTIGA_E_ARG, "unknown TT selector");
+    copy_tt_to_host(*prob->impl->ctx, *t, dst, count);
+  });
+}
+
+int ttiga_sample_factors(ttiga_problem* prob, const double* pts, size_t count, double* out,
+                         double* det_out) {
+  return guard([&] {
+    TTIGA_CHECK(prob != nullptr, TTIGA_E_ARG, "null problem");
+    TTIGA_HIP(hipSetDevice(prob->impl->ctx->device));
+    prob->impl->sample_points(pts, count, out, det_out);
+  });
+}
+
+int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, ttiga_tt** out) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && K && x && out, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(K->p >= 0 && K->p <= 16, TTIGA_E_ARG, "bad band half-width");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    ttiga_tt_view kv{};
+    const int band = 2 * K->p + 1;
+    for (int k = 0; k < 3; ++k) {
+      TTIGA_CHECK(K->n[k] == x->n[k], TTIGA_E_ARG, "matvec: mode sizes differ");
+      kv.n[k] = K->n[k] * band;
+      kv.core[k] = K->core[k];
+    }
+    for (int k = 0; k < 4; ++k) kv.r[k] = K->r[k];
+    TT Kt, xt;
+    tt_from_view(c, kv, Kt);
+    tt_from_view(c, *x, xt);
+    auto* res = new ttiga_tt{&c, TT()};
+    try {
+      tt_matvec_banded(c, Kt, K->p, xt, res->t);
+      c.sync();
+    } catch (...) {
+      delete res;
+      throw;
+    }
+    *out = res;
+    ctx_retain(&c);
+  });
+}
+
+int ttiga_tt_round(ttiga_ctx* ctx, const ttiga_tt_view* x, double eps, ttiga_tt** out) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && x && out, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(eps > 0.0 && eps < 1.0, TTIGA_E_ARG, "eps must be in (0, 1)");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    auto* res = new ttiga_tt{&c, TT()};
+    try {
+      tt_from_view(c, *x, res->t);
+      tt_round(c, res->t, eps, -1.0, 0);
+      c.sync();
+    } catch (...) {
+      delete res;
+      throw;
+    }
+    *out = res;
+    ctx_retain(&c);
+  });
+}
+
+int ttiga_tt_dot(ttiga_ctx* ctx, const ttiga_tt_view* x, const ttiga_tt_view* y, double* out) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && x && y && out, TTIGA_E_ARG, "null argument");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    for (int k = 0; k < 3; ++k) TTIGA_CHECK(x->n[k] == y->n[k], TTIGA_E_ARG, "dot: mode sizes differ");
+    TT xt, yt;
+    tt_from_view(c, *x, xt);
+    tt_from_view(c, *y, yt);
+    *out = tt_dot_sync(c, xt, yt);
+  });
+}
+
+int ttiga_tt_compress(ttiga_ctx* ctx, const double* A, const int n[3], double delta, ttiga_tt** out) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && A && n && out, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(delta >= 0.0, TTIGA_E_ARG, "delta must be >= 0");
+    for (int k = 0; k < 3; ++k) TTIGA_CHECK(n[k] > 0, TTIGA_E_ARG, "bad mode size");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    auto* res = new ttiga_tt{&c, TT()};
+    try {
+      tt_compress_dense(c, A, n, delta, res->t, 0);
+      c.sync();
+    } catch (...) {
+      delete res;
+      throw;
+    }
+    *out = res;
+    ctx_retain(&c);
+  });
+}
+
+int ttiga_tt_info(const ttiga_tt* t, int ranks[4], int n[3]) {
+  return guard([&] {
+    TTIGA_CHECK(t && ranks && n, TTIGA_E_ARG, "null argument");
+    for (int k = 0; k < 4; ++k) ranks[k] = t->t.r[k];
+    for (int k = 0; k < 3; ++k) n[k] = t->t.n[k];
+  });
+}
+
+int ttiga_tt_copy(const ttiga_tt* t, double* dst, size_t count) {
+  return guard([&] {
+    TTIGA_CHECK(t != nullptr, TTIGA_E_ARG, "null TT");
+    copy_tt_to_host(*t->ctx, t->t, dst, count);
+  });
+}
+
+int ttiga_tt_free(ttiga_tt* t) {
+  return guard([&] {
+    if (!t) return;
+    Context* c = t->ctx;
+    delete t;
+    ctx_release(c);
+  });
+}
+
+}  // extern "C"

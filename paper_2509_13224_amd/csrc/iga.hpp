@@ -1,0 +1,46 @@
+// Device-side descriptions of the geometry and source, and the IGA kernel launchers.
+#pragma once
+
+#include "runtime.hpp"
+
+namespace ttiga {
+
+// Geometry tables for one sampling: per direction the span index and the p_g+1
+// non-zero geometry basis values / derivatives at each sample coordinate.
+struct GeoDev {
+  int pg[3];
+  int m[3];            // control points per direction
+  const double* Pw;    // [m0][m1][m2][4] homogeneous control net
+  const int* span[3];  // per sample coordinate
+  const double* B[3];
+  const double* D[3];
+};
+
+struct SourceDev {
+  int kind;
+  int n_modes;
+  const double* a;    // device
+  const double* k;    // device, n_modes x 3
+  const double* phi;  // device
+  double origin[3];
+  double scale;
+};
+
+void launch_basis_tables(Context& ctx, int n, int p, int g, const double* knots, double* xi,
+                         double* w, double* B, double* D);
+void launch_geo_tables(Context& ctx, int count, const double* xi, int stride, int nb, int pg,
+                       const double* knots, int* span, double* B, double* D);
+void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, const int* Q,
+                         double* F, double* stats8);
+void launch_factors_points(Context& ctx, const GeoDev& geo, const SourceDev& src, long count,
+                           double* out, double* det);
+void launch_assemble_band(Context& ctx, int n, int p, int g, int ra, int rb, const double* G,
+                          const double* w, const double* Brow, const double* Bcol, double* M);
+void launch_assemble_vec(Context& ctx, int n, int p, int g, int ra, int rb, const double* G,
+                         const double* w, const double* B, double* V);
+void launch_slice_band(Context& ctx, int n, int p, int lo, int n2, int ra, int rb, const double* M,
+                       double* O);
+void launch_slice_vec(Context& ctx, int n, int lo, int n2, int ra, int rb, const double* V, double* O);
+void launch_homogeneous(Context& ctx, long count, const double* xyz, const double* wts, double* Pw);
+
+}  // namespace ttiga

@@ -1,0 +1,457 @@
+// Spline, geometry and assembly kernels of the TT-IGA hot path.
+//
+//  k_basis_tables   - Gauss nodes/weights per knot span and the p+1 non-zero
+//                     B-splines and derivatives there (Cox-de Boor recursion and
+//                     derivative formula of Section 2.1); also used for the
+//                     geometry's own knot vectors.
+//  k_factors        - exact NURBS map in homogeneous form (Section 2.3) at each
+//                     sample point, Jacobian, det J and the metric factor
+//                     R = det J J^-1 J^-T = adj(J) adj(J)^T / det J (eq. Rxi),
+//                     plus f(x) det J (eq. ffinal).
+//  k_assemble_band  - TT-matrix core of K_ij in mode d (Section 4.2.1):
+//                     M[a][k][t][b] = sum_q w_q G[a][q][b] Row_q[k] Col_q[k+t-p],
+//                     Row/Col the value or derivative selected by a_ij^(d).
+//  k_assemble_vec   - TT core of F (Section 4.2.2): sum_q w_q G[a][q][b] N_k(q).
+//  k_slice_*        - removal of Dirichlet indices (Section 4.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "iga.hpp"
+
+namespace ttiga {
+
+constexpr int kMaxDeg = 8;
+
+__device__ inline double safe_div(double a, double b) { return b == 0.0 ? 0.0 : a / b; }
+
+// Gauss-Legendre node t (ascending) and weight of the g-point rule on [-1, 1],
+// Newton iteration on the Legendre recurrence.
+__device__ void gauss_legendre(int g, int t, double* x, double* w) {
+  double z = cos(3.141592653589793 * (t + 0.75) / (g + 0.5));
+  double dp = 1.0;
+  for (int it = 0; it < 100; ++it) {
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= g; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (g == 1) { p1 = z; p0 = 1.0; }
+    dp = g * (z * p1 - p0) / (z * z - 1.0);
+    const double dz = p1 / dp;
+    z -= dz;
+    if (fabs(dz) < 1e-16) break;
+  }
+  {
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= g; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (g == 1) { p1 = z; p0 = 1.0; }
+    dp = g * (z * p1 - p0) / (z * z - 1.0);
+  }
+  *x = -z;
+  *w = 2.0 / ((1.0 - z * z) * dp * dp);
+}
+
+// Non-zero basis N_{s-p..s}^p(xi) and derivatives on span s of `knots`.
+__device__ void local_basis(const double* knots, int p, int s, double xi, double* N, double* dN) {
+  double cur[kMaxDeg + 1], prev[kMaxDeg + 1];
+  cur[0] = 1.0;
+  for (int q = 1; q <= p; ++q) {
+    for (int j = 0; j < q; ++j) prev[j] = cur[j];
+    for (int j = 0; j <= q; ++j) {
+      const int i = s - q + j;
+      double v = 0.0;
+      if (j - 1 >= 0) v += safe_div(xi - knots[i], knots[i + q] - knots[i]) * prev[j - 1];
+      if (j <= q - 1) v += safe_div(knots[i + q + 1] - xi, knots[i + q + 1] - knots[i + 1]) * prev[j];
+      cur[j] = v;
+    }
+    if (q == p) {
+      for (int j = 0; j <= p; ++j) {
+        const int i = s - p + j;
+        double d = 0.0;
+        if (j - 1 >= 0) d += p * safe_div(1.0, knots[i + p] - knots[i]) * prev[j - 1];
+        if (j <= p - 1) d -= p * safe_div(1.0, knots[i + p + 1] - knots[i + 1]) * prev[j];
+        dN[j] = d;
+      }
+    }
+  }
+  if (p == 0) dN[0] = 0.0;
+  for (int j = 0; j <= p; ++j) N[j] = cur[j];
+}
+
+// Span s with knots[s] <= xi < knots[s+1], s in [p, nb-1]; xi at the right end maps to
+// the last non-empty span.
+__device__ int find_span(const double* knots, int p, int nb, double xi) {
+  if (xi >= knots[nb]) {
+    int s = nb - 1;
+    while (s > p && knots[s] == knots[s + 1]) --s;
+    return s;
+  }
+  if (xi <= knots[p]) return p;
+  int lo = p, hi = nb;  // knots[lo] <= xi < knots[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (knots[mid] <= xi) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Solution tables: Gauss points of the E = n - p uniform spans (g per span).
+__global__ void k_basis_tables(int n, int p, int g, const double* __restrict__ knots,
+                               double* __restrict__ xi_out, double* __restrict__ w_out,
+                               double* __restrict__ B, double* __restrict__ D) {
+  const int E = n - p;
+  const int Q = E * g;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q) return;
+  const int e = q / g, t = q % g;
+  double x, w;
+  gauss_legendre(g, t, &x, &w);
+  const double a = knots[p + e], b = knots[p + e + 1];
+  const double xi = 0.5 * (a + b) + 0.5 * (b - a) * x;
+  xi_out[q] = xi;
+  w_out[q] = 0.5 * (b - a) * w;
+  double N[kMaxDeg + 1], dN[kMaxDeg + 1];
+  local_basis(knots, p, p + e, xi, N, dN);
+  for (int j = 0; j <= p; ++j) {
+    B[(long)q * (p + 1) + j] = N[j];
+    D[(long)q * (p + 1) + j] = dN[j];
+  }
+}
+
+// Geometry tables at arbitrary parametric points (span + non-zero basis + derivative).
+__global__ void k_geo_tables(int count, const double* __restrict__ xi, int stride, int nb, int pg,
+                             const double* __restrict__ knots, int* __restrict__ span,
+                             double* __restrict__ B, double* __restrict__ D) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const double x = xi[(long)q * stride];
+  const int s = find_span(knots, pg, nb, x);
+  span[q] = s;
+  double N[kMaxDeg + 1], dN[kMaxDeg + 1];
+  local_basis(knots, pg, s, x, N, dN);
+  for (int j = 0; j <= pg; ++j) {
+    B[(long)q * (pg + 1) + j] = N[j];
+    D[(long)q * (pg + 1) + j] = dN[j];
+  }
+}
+
+__device__ double source_value(const SourceDev& src, double x, double y, double z) {
+  if (src.kind == TTIGA_SOURCE_MANUFACTURED_ANNULUS) {
+    const double r = sqrt(x * x + y * y);
+    const double th = atan2(y, x);
+    const double pi = 3.141592653589793;
+    const double radial = (2.0 * pi * pi + 4.0 / (r * r)) * sin(pi * r) - (pi / r) * cos(pi * r);
+    return radial * sin(2.0 * th) * sin(pi * z);
+  }
+  if (src.kind == TTIGA_SOURCE_FOURIER) {
+    const double xs = (x - src.origin[0]) / src.scale, ys = (y - src.origin[1]) / src.scale,
+                 zs = (z - src.origin[2]) / src.scale;
+    double f = 0.0;
+    for (int m = 0; m < src.n_modes; ++m) {
+      const double* k = src.k + 3 * m;
+      f += src.a[m] * sin(3.141592653589793 * (k[0] * xs + k[1] * ys + k[2] * zs) + src.phi[m]);
+    }
+    return f;
+  }
+  return 0.0;
+}
+
+// One sample point: 7 factors and det J.  ga/gb/gc index the per-direction geometry tables.
+__device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, int ib, int ic,
+                              double* out7, double* det_out) {
+  const int p0 = geo.pg[0], p1 = geo.pg[1], p2 = geo.pg[2];
+  const int s0 = geo.span[0][ia], s1 = geo.span[1][ib], s2 = geo.span[2][ic];
+  const double* B0 = geo.B[0] + (long)ia * (p0 + 1);
+  const double* B1 = geo.B[1] + (long)ib * (p1 + 1);
+  const double* B2 = geo.B[2] + (long)ic * (p2 + 1);
+  const double* D0 = geo.D[0] + (long)ia * (p0 + 1);
+  const double* D1 = geo.D[1] + (long)ib * (p1 + 1);
+  const double* D2 = geo.D[2] + (long)ic * (p2 + 1);
+  double H[4] = {0, 0, 0, 0}, dH[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int a = 0; a <= p0; ++a) {
+    for (int b = 0; b <= p1; ++b) {
+      // partial sums over c first (sum factorisation of the inner direction)
+      double h[4] = {0, 0, 0, 0}, h2[4] = {0, 0, 0, 0};
+      const long base = ((long)(s0 - p0 + a) * geo.m[1] + (s1 - p1 + b)) * geo.m[2] + (s2 - p2);
+      for (int c = 0; c <= p2; ++c) {
+        const double* P = geo.Pw + (base + c) * 4;
+        for (int s = 0; s < 4; ++s) {
+          h[s] += B2[c] * P[s];
+          h2[s] += D2[c] * P[s];
+        }
+      }
+      const double bb = B0[a] * B1[b], db0 = D0[a] * B1[b], db1 = B0[a] * D1[b];
+      for (int s = 0; s < 4; ++s) {
+        H[s] += bb * h[s];
+        dH[0][s] += db0 * h[s];
+        dH[1][s] += db1 * h[s];
+        dH[2][s] += bb * h2[s];
+      }
+    }
+  }
+  const double W = H[3];
+  const double x[3] = {H[0] / W, H[1] / W, H[2] / W};
+  double J[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i) J[k][i] = (dH[i][k] - x[k] * dH[i][3]) / W;
+  // adjugate (transpose of the cofactor matrix): J^-1 = adj / det
+  double A[3][3];
+  A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+  // R = det J^-1 J^-T = adj adj^T / det
+  const int pi_[6] = {0, 1, 2, 0, 0, 1}, pj_[6] = {0, 1, 2, 1, 2, 2};
+  for (int f = 0; f < 6; ++f) {
+    const int i = pi_[f], j = pj_[f];
+    out7[f] = (A[i][0] * A[j][0] + A[i][1] * A[j][1] + A[i][2] * A[j][2]) / det;
+  }
+  out7[6] = source_value(src, x[0], x[1], x[2]) * det;
+  *det_out = det;
+}
+
+// Gauss-grid sampling: thread per point (i0, i1, i2), i2 fastest; factor-major output
+// F[f][(i0 Q1 + i1) Q2 + i2].  Per-block partial sums of squares of the 7 factors and
+// the minimum det J go to part[block][8].
+__global__ __launch_bounds__(256) void k_factors_grid(GeoDev geo, SourceDev src, int Q0, int Q1,
+                                                      int Q2, double* __restrict__ F,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[8][256];
+  const long total = (long)Q0 * Q1 * Q2;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 1e300};
+  if (e < total) {
+    const int i2 = e % Q2;
+    const int i1 = (e / Q2) % Q1;
+    const int i0 = e / ((long)Q1 * Q2);
+    double v[7], det;
+    point_factors(geo, src, i0, i1, i2, v, &det);
+    for (int f = 0; f < 7; ++f) {
+      F[(long)f * total + e] = v[f];
+      acc[f] = v[f] * v[f];
+    }
+    acc[7] = det;
+  }
+  for (int f = 0; f < 8; ++f) sh[f][threadIdx.x] = acc[f];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      for (int f = 0; f < 7; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + o];
+      sh[7][threadIdx.x] = fmin(sh[7][threadIdx.x], sh[7][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) part[(long)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_factors_reduce(const double* __restrict__ part, long blocks, double* __restrict__ out) {
+  __shared__ double sh[8][256];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 1e300};
+  for (long b = threadIdx.x; b < blocks; b += blockDim.x) {
+    for (int f = 0; f < 7; ++f) acc[f] += part[b * 8 + f];
+    acc[7] = fmin(acc[7], part[b * 8 + 7]);
+  }
+  for (int f = 0; f < 8; ++f) sh[f][threadIdx.x] = acc[f];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      for (int f = 0; f < 7; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + o];
+      sh[7][threadIdx.x] = fmin(sh[7][threadIdx.x], sh[7][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Scattered points: the geometry tables are indexed by the point itself in all directions.
+__global__ void k_factors_points(GeoDev geo, SourceDev src, long count, double* __restrict__ out,
+                                 double* __restrict__ det_out) {
+  const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  double v[7], det;
+  point_factors(geo, src, (int)q, (int)q, (int)q, v, &det);
+  for (int f = 0; f < 7; ++f) out[(long)f * count + q] = v[f];
+  det_out[q] = det;
+}
+
+__global__ void k_assemble_band(int n, int p, int g, int ra, int rb, const double* __restrict__ G,
+                                const double* __restrict__ w, const double* __restrict__ Brow,
+                                const double* __restrict__ Bcol, double* __restrict__ M) {
+  const int band = 2 * p + 1;
+  const int E = n - p, Q = E * g;
+  const long total = (long)ra * n * band * rb;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e % rb;
+    const int t = (e / rb) % band;
+    const int k = (e / ((long)rb * band)) % n;
+    const int a = e / ((long)rb * band * n);
+    const int l = k + t - p;
+    double acc = 0.0;
+    if (l >= 0 && l < n) {
+      const int elo = max(max(k, l) - p, 0), ehi = min(min(k, l), E - 1);
+      for (int el = elo; el <= ehi; ++el) {
+        for (int gq = 0; gq < g; ++gq) {
+          const int q = el * g + gq;
+          acc += w[q] * G[((long)a * Q + q) * rb + b] * Brow[(long)q * (p + 1) + (k - el)] *
+                 Bcol[(long)q * (p + 1) + (l - el)];
+        }
+      }
+    }
+    M[e] = acc;
+  }
+}
+
+__global__ void k_assemble_vec(int n, int p, int g, int ra, int rb, const double* __restrict__ G,
+                               const double* __restrict__ w, const double* __restrict__ B,
+                               double* __restrict__ V) {
+  const int E = n - p, Q = E * g;
+  const long total = (long)ra * n * rb;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e % rb;
+    const int k = (e / rb) % n;
+    const int a = e / ((long)rb * n);
+    double acc = 0.0;
+    const int elo = max(k - p, 0), ehi = min(k, E - 1);
+    for (int el = elo; el <= ehi; ++el)
+      for (int gq = 0; gq < g; ++gq) {
+        const int q = el * g + gq;
+        acc += w[q] * G[((long)a * Q + q) * rb + b] * B[(long)q * (p + 1) + (k - el)];
+      }
+    V[e] = acc;
+  }
+}
+
+// Banded core restricted to rows/columns [lo, lo + n2): band entries pointing outside vanish.
+__global__ void k_slice_band(int n, int p, int lo, int n2, int ra, int rb, const double* __restrict__ M,
+                             double* __restrict__ O) {
+  const int band = 2 * p + 1;
+  const long total = (long)ra * n2 * band * rb;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e % rb;
+    const int t = (e / rb) % band;
+    const int i2 = (e / ((long)rb * band)) % n2;
+    const int a = e / ((long)rb * band * n2);
+    const int j2 = i2 + t - p;
+    double v = 0.0;
+    if (j2 >= 0 && j2 < n2) v = M[(((long)a * n + (i2 + lo)) * band + t) * rb + b];
+    O[e] = v;
+  }
+}
+
+__global__ void k_slice_vec(int n, int lo, int n2, int ra, int rb, const double* __restrict__ V,
+                            double* __restrict__ O) {
+  const long total = (long)ra * n2 * rb;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e % rb;
+    const int i2 = (e / rb) % n2;
+    const int a = e / ((long)rb * n2);
+    O[e] = V[((long)a * n + (i2 + lo)) * rb + b];
+  }
+}
+
+// Homogeneous control net (w x, w y, w z, w).
+__global__ void k_homogeneous(long count, const double* __restrict__ xyz, const double* __restrict__ wts,
+                              double* __restrict__ Pw) {
+  const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const double w = wts ? wts[q] : 1.0;
+  Pw[q * 4 + 0] = w * xyz[q * 3 + 0];
+  Pw[q * 4 + 1] = w * xyz[q * 3 + 1];
+  Pw[q * 4 + 2] = w * xyz[q * 3 + 2];
+  Pw[q * 4 + 3] = w;
+}
+
+// ------------------------------------------------------------------ launchers
+static int blocks_for(long total, int per = 256) { return (int)((total + per - 1) / per); }
+static int grid_for(long total) {
+  return (int)std::max<long>(1, std::min<long>((total + 255) / 256, 16384));
+}
+
+void launch_basis_tables(Context& ctx, int n, int p, int g, const double* knots, double* xi,
+                         double* w, double* B, double* D) {
+  const int Q = (n - p) * g;
+  hipLaunchKernelGGL(k_basis_tables, dim3(blocks_for(Q)), dim3(256), 0, ctx.stream, n, p, g, knots,
+                     xi, w, B, D);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_geo_tables(Context& ctx, int count, const double* xi, int stride, int nb, int pg,
+                       const double* knots, int* span, double* B, double* D) {
+  hipLaunchKernelGGL(k_geo_tables, dim3(blocks_for(count)), dim3(256), 0, ctx.stream, count, xi,
+                     stride, nb, pg, knots, span, B, D);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, const int* Q,
+                         double* F, double* stats8) {
+  const long total = (long)Q[0] * Q[1] * Q[2];
+  const long blocks = (total + 255) / 256;
+  DBuf part(&ctx.alloc, sizeof(double) * 8 * blocks);
+  hipLaunchKernelGGL(k_factors_grid, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, geo, src, Q[0],
+                     Q[1], Q[2], F, part.d());
+  hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks, stats8);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_factors_points(Context& ctx, const GeoDev& geo, const SourceDev& src, long count,
+                           double* out, double* det) {
+  hipLaunchKernelGGL(k_factors_points, dim3(blocks_for(count)), dim3(256), 0, ctx.stream, geo, src,
+                     count, out, det);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_assemble_band(Context& ctx, int n, int p, int g, int ra, int rb, const double* G,
+                          const double* w, const double* Brow, const double* Bcol, double* M) {
+  const long total = (long)ra * n * (2 * p + 1) * rb;
+  hipLaunchKernelGGL(k_assemble_band, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n, p, g, ra,
+                     rb, G, w, Brow, Bcol, M);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_assemble_vec(Context& ctx, int n, int p, int g, int ra, int rb, const double* G,
+                         const double* w, const double* B, double* V) {
+  const long total = (long)ra * n * rb;
+  hipLaunchKernelGGL(k_assemble_vec, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n, p, g, ra, rb,
+                     G, w, B, V);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_slice_band(Context& ctx, int n, int p, int lo, int n2, int ra, int rb, const double* M,
+                       double* O) {
+  const long total = (long)ra * n2 * (2 * p + 1) * rb;
+  hipLaunchKernelGGL(k_slice_band, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n, p, lo, n2, ra,
+                     rb, M, O);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_slice_vec(Context& ctx, int n, int lo, int n2, int ra, int rb, const double* V, double* O) {
+  const long total = (long)ra * n2 * rb;
+  hipLaunchKernelGGL(k_slice_vec, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n, lo, n2, ra, rb,
+                     V, O);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_homogeneous(Context& ctx, long count, const double* xyz, const double* wts, double* Pw) {
+  hipLaunchKernelGGL(k_homogeneous, dim3(blocks_for(count)), dim3(256), 0, ctx.stream, count, xyz, wts,
+                     Pw);
+  TTIGA_HIP(hipGetLastError());
+}
+
+}  // namespace ttiga

@@ -1,0 +1,571 @@
+// Dense FP64 linear algebra for TT contractions and TT-rounding on gfx950.
+//
+//  * gemm: 64x64 workgroup tiles of v_mfma_f64_16x16x4 (four 64-wide waves,
+//    each owning a 32x32 sub-tile), K staged through LDS 16 at a time, split-K
+//    with a deterministic second-stage reduction for the tall-skinny Gram
+//    products (A^T A with a long contraction) that dominate rounding.
+//  * qr_tall: Householder QR as a tree over row blocks (TSQR), each block
+//    factored in LDS by one workgroup; exact orthogonality also for the
+//    rank-deficient unfoldings that TT sums produce.
+//  * svd_small: one-sided (Hestenes) Jacobi in a single workgroup, round-robin
+//    pair ordering so every wave rotates a disjoint column pair each round.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace ttiga {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;  // workgroup tile edge
+constexpr int GK = 16;  // K step staged in LDS
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double alpha,
+                                                  const double* __restrict__ A, long lda, long sA,
+                                                  const double* __restrict__ B, long ldb, long sB,
+                                                  double beta, double* __restrict__ C, long ldc,
+                                                  long sC, int splits, int kchunk,
+                                                  double* __restrict__ Cpart) {
+  const int bz = blockIdx.z;
+  const int batch = bz / splits, split = bz % splits;
+  A += batch * sA;
+  B += batch * sB;
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  d4_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = kbeg; k0 < kend; k0 += GK) {
+    for (int e = tid; e < GT * GK; e += 256) {
+      int mm, kk;
+      if (TA) { kk = e / GT; mm = e % GT; } else { mm = e / GK; kk = e % GK; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < M && gk < kend) v = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
+      As[kk][mm] = v;
+    }
+    for (int e = tid; e < GT * GK; e += 256) {
+      int nn, kk;
+      if (TB) { nn = e / GK; kk = e % GK; } else { kk = e / GT; nn = e % GT; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      double v = 0.0;
+      if (gn < N && gk < kend) v = TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double a0 = As[kr][wm + (lane & 15)];
+      const double a1 = As[kr][wm + 16 + (lane & 15)];
+      const double b0 = Bs[kr][wn + (lane & 15)];
+      const double b1 = Bs[kr][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of the 16x16x4 f64 MFMA: lane holds column (lane & 15) of rows (lane >> 4) + 4 v.
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + 16 * i + (lane >> 4) + 4 * v;
+        const int col = n0 + wn + 16 * j + (lane & 15);
+        if (row < M && col < N) {
+          const double a = acc[i][j][v];
+          if (splits == 1) {
+            double* c = C + batch * sC + (long)row * ldc + col;
+            *c = (beta == 0.0) ? alpha * a : alpha * a + beta * (*c);
+          } else {
+            Cpart[((long)bz * M + row) * N + col] = a;
+          }
+        }
+      }
+}
+
+__global__ void k_splitk_reduce(int M, int N, int splits, int batches, double alpha,
+                                const double* __restrict__ Cpart, double beta, double* C, long ldc,
+                                long sC) {
+  const long total = (long)batches * M * N;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e / ((long)M * N);
+    const long rc = e % ((long)M * N);
+    const int row = rc / N, col = rc % N;
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += Cpart[((long)(b * splits + k) * M + row) * N + col];
+    double* c = C + b * sC + (long)row * ldc + col;
+    *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
+  }
+}
+
+void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+          long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+          long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0) {
+    // C = beta * C
+    if (beta == 0.0) {
+      for (int b = 0; b < batch; ++b)
+        TTIGA_HIP(hipMemset2DAsync(C + b * sC, ldc * sizeof(double), 0, N * sizeof(double), M,
+                                   ctx.stream));
+      return;
+    }
+    throw Error(TTIGA_E_ARG, "gemm with K=0 and beta!=0 unsupported");
+  }
+  const int tm = (M + GT - 1) / GT, tn = (N + GT - 1) / GT;
+  const long tiles = (long)tm * tn * batch;
+  int splits = 1;
+  if (tiles < 256 && K > 256) {
+    splits = (int)std::min<long>((K + 255) / 256, std::max<long>(1, 512 / tiles));
+  }
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + GK - 1) / GK * GK;
+  splits = (K + kchunk - 1) / kchunk;
+  DBuf part;
+  if (splits > 1) part = DBuf(&ctx.alloc, sizeof(double) * (size_t)batch * splits * M * N);
+  dim3 grid(tn, tm, batch * splits);
+  dim3 block(256);
+#define TTIGA_GEMM_LAUNCH(TA, TB)                                                                 \
+  hipLaunchKernelGGL((k_gemm_f64<TA, TB>), grid, block, 0, ctx.stream, M, N, K, alpha, A, lda, sA, \
+                     B, ldb, sB, beta, C, ldc, sC, splits, kchunk, part.d())
+  if (!ta && !tb) TTIGA_GEMM_LAUNCH(false, false);
+  else if (ta && !tb) TTIGA_GEMM_LAUNCH(true, false);
+  else if (!ta && tb) TTIGA_GEMM_LAUNCH(false, true);
+  else TTIGA_GEMM_LAUNCH(true, true);
+#undef TTIGA_GEMM_LAUNCH
+  TTIGA_HIP(hipGetLastError());
+  if (splits > 1) {
+    const long total = (long)batch * M * N;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(blocks), dim3(256), 0, ctx.stream, M, N, splits,
+                       batch, alpha, part.d(), beta, C, ldc, sC);
+    TTIGA_HIP(hipGetLastError());
+  }
+}
+
+// ------------------------------------------------------- Householder TSQR
+// Householder QR of a tall m x c matrix as a tree (TSQR): the rows are split into
+// nb blocks of at least 2c rows; each workgroup factors its block in LDS
+// (reflectors H_j = I - tau_j v_j v_j^T, v_j[j] = 1), the c x c R factors are
+// stacked and factored again until one block is left.  The thin Q is then built
+// top-down: each block applies its reflectors to [Q_parent slice; 0].
+// Work arrays are column-major W[j * ldw + i] so a column update is contiguous.
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+
+__global__ __launch_bounds__(256) void k_hh_factor(int m, int c, const double* __restrict__ A,
+                                                   long lda, int trans, int nb, int ldw,
+                                                   double* __restrict__ V,
+                                                   double* __restrict__ tau,
+                                                   double* __restrict__ Rout,
+                                                   double* __restrict__ gwork) {
+  extern __shared__ double smem[];
+  __shared__ double s_scale, s_tau;
+  const int blk = blockIdx.x;
+  const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
+  const int nr = (int)(r1 - r0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  double* W = gwork ? gwork + (long)blk * ldw * c : smem;
+  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
+    int i, j;
+    double v;
+    if (trans) { i = e % nr; j = e / nr; v = A[(long)j * lda + r0 + i]; }
+    else { i = e / c; j = e % c; v = A[(r0 + i) * lda + j]; }
+    W[(long)j * ldw + i] = v;
+  }
+  __syncthreads();
+  for (int j = 0; j < c; ++j) {
+    double* wj = W + (long)j * ldw;
+    if (wave == 0) {
+      double ss = 0.0;
+      for (int i = j + 1 + lane; i < nr; i += 64) ss += wj[i] * wj[i];
+      ss = wave_sum(ss);
+      if (lane == 0) {
+        const double alpha = wj[j];
+        if (ss == 0.0) {
+          s_tau = 0.0;
+          s_scale = 0.0;
+        } else {
+          const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+          s_tau = (beta - alpha) / beta;
+          s_scale = 1.0 / (alpha - beta);
+          wj[j] = beta;
+        }
+      }
+    }
+    __syncthreads();
+    const double t = s_tau, sc = s_scale;
+    if (tid == 0) tau[(long)blk * c + j] = t;
+    if (t != 0.0) {
+      for (int i = j + 1 + tid; i < nr; i += blockDim.x) wj[i] *= sc;
+      __syncthreads();
+      for (int k = j + 1 + wave; k < c; k += nwaves) {
+        double* wk = W + (long)k * ldw;
+        double d = 0.0;
+        for (int i = j + 1 + lane; i < nr; i += 64) d += wj[i] * wk[i];
+        d = wave_sum(d) + wk[j];
+        const double f = t * d;
+        if (lane == 0) wk[j] -= f;
+        for (int i = j + 1 + lane; i < nr; i += 64) wk[i] -= f * wj[i];
+      }
+    }
+    __syncthreads();
+  }
+  // R (row j, column k >= j) and the reflectors, block-local column-major in V
+  for (long e = tid; e < (long)c * c; e += blockDim.x) {
+    const int j = e / c, k = e % c;
+    Rout[(long)blk * c * c + e] = (k >= j) ? W[(long)k * ldw + j] : 0.0;
+  }
+  double* Vb = V + r0 * c;
+  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
+    const int j = e / nr, i = e % nr;
+    Vb[e] = (i > j) ? W[(long)j * ldw + i] : (i == j ? 1.0 : 0.0);
+  }
+}
+
+// Qout (m x c, row-major) = H_0 ... H_{c-1} [Qtop slice (c x c); 0] per block;
+// Qtop == nullptr stands for the identity (the root of the tree).
+__global__ __launch_bounds__(256) void k_hh_apply(int m, int c, int nb, int ldw,
+                                                  const double* __restrict__ V,
+                                                  const double* __restrict__ tau,
+                                                  const double* __restrict__ Qtop,
+                                                  double* __restrict__ Qout,
+                                                  double* __restrict__ gwork) {
+  extern __shared__ double smem[];
+  const int blk = blockIdx.x;
+  const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
+  const int nr = (int)(r1 - r0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  double* Y = gwork ? gwork + (long)blk * ldw * c : smem;
+  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
+    const int k = e / nr, i = e % nr;
+    double v = 0.0;
+    if (i < c) v = Qtop ? Qtop[((long)blk * c + i) * c + k] : (i == k ? 1.0 : 0.0);
+    Y[(long)k * ldw + i] = v;
+  }
+  __syncthreads();
+  const double* Vb = V + r0 * c;
+  for (int j = c - 1; j >= 0; --j) {
+    const double t = tau[(long)blk * c + j];
+    if (t == 0.0) continue;
+    const double* vj = Vb + (long)j * nr;
+    for (int k = wave; k < c; k += nwaves) {
+      double* yk = Y + (long)k * ldw;
+      double d = 0.0;
+      for (int i = j + 1 + lane; i < nr; i += 64) d += vj[i] * yk[i];
+      d = wave_sum(d) + yk[j];
+      const double f = t * d;
+      if (lane == 0) yk[j] -= f;
+      for (int i = j + 1 + lane; i < nr; i += 64) yk[i] -= f * vj[i];
+    }
+    __syncthreads();
+  }
+  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
+    const int i = e / c, k = e % c;
+    Qout[(r0 + i) * c + k] = Y[(long)k * ldw + i];
+  }
+}
+
+// Dynamic LDS available to the TSQR kernels, in doubles: the device's per-workgroup
+// limit (160 KiB on gfx950) minus room for their static shared variables; 64 KiB
+// when the larger opt-in is refused.
+static int lds_doubles() {
+  static int cap = -1;
+  if (cap > 0) return cap;
+  int dev = 0, bytes = 65536;
+  TTIGA_HIP(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    bytes = 65536;
+  bytes -= 1024;
+  if (bytes > 65536 - 1024) {
+    const bool ok =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_factor),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      bytes = 65536 - 1024;
+    }
+  }
+  cap = bytes / 8;
+  return cap;
+}
+
+void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
+             double* R) {
+  TTIGA_CHECK(m >= c && c > 0, TTIGA_E_ARG, "qr_tall needs m >= c > 0");
+  const int kLdsDoubles = lds_doubles();
+  struct Level {
+    int m, nb, ldw;
+    bool lds;
+    DBuf V, tau, R, work;
+  };
+  std::vector<Level> lv;
+  const double* in = A;
+  bool tr = transA;
+  long ld = lda;
+  int mm = m;
+  // blocks of at least 2c rows so every level at least halves the rows
+  const int rows_target = std::max(2 * c, (c <= kLdsDoubles / (2 * c)) ? kLdsDoubles / c : 4 * c);
+  while (true) {
+    Level L;
+    L.m = mm;
+    L.nb = std::max(1, (mm + rows_target - 1) / rows_target);
+    L.ldw = (mm + L.nb - 1) / L.nb;
+    L.lds = (long)L.ldw * c <= kLdsDoubles;
+    L.V = DBuf(&ctx.alloc, sizeof(double) * (size_t)mm * c);
+    L.tau = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * c);
+    L.R = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * c * c);
+    if (!L.lds) L.work = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * L.ldw * c);
+    const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
+    hipLaunchKernelGGL(k_hh_factor, dim3(L.nb), dim3(256), shm, ctx.stream, mm, c, in, ld, tr ? 1 : 0,
+                       L.nb, L.ldw, L.V.d(), L.tau.d(), L.R.d(), L.lds ? nullptr : L.work.d());
+    TTIGA_HIP(hipGetLastError());
+    lv.push_back(std::move(L));
+    const Level& last = lv.back();
+    if (last.nb == 1) break;
+    in = last.R.d();
+    tr = false;
+    ld = c;
+    mm = last.nb * c;
+  }
+  copy(ctx, R, lv.back().R.d(), (size_t)c * c);
+  // thin Q, top-down
+  DBuf qprev;
+  for (int l = (int)lv.size() - 1; l >= 0; --l) {
+    Level& L = lv[l];
+    DBuf qout;
+    double* dst = (l == 0) ? Q : (qout = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.m * c), qout.d());
+    const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
+    hipLaunchKernelGGL(k_hh_apply, dim3(L.nb), dim3(256), shm, ctx.stream, L.m, c, L.nb, L.ldw,
+                       L.V.d(), L.tau.d(), qprev.d(), dst, L.lds ? nullptr : L.work.d());
+    TTIGA_HIP(hipGetLastError());
+    qprev = std::move(qout);
+  }
+}
+
+// ------------------------------------------------------------- Jacobi SVD
+
+// One workgroup.  Ucol [c][m] and Vcol [c][c] are column-major work arrays.
+__global__ __launch_bounds__(512) void k_jacobi_svd(int m, int c, const double* __restrict__ A,
+                                                    int transA, long lda, double* __restrict__ Ucol,
+                                                    double* __restrict__ Vcol,
+                                                    double* __restrict__ U, double* __restrict__ S,
+                                                    double* __restrict__ V, int max_sweeps) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = nt >> 6;
+  __shared__ int s_rot;
+  __shared__ int s_perm[1024];
+  __shared__ double s_sig[1024];
+  for (long e = tid; e < (long)m * c; e += nt) {
+    const int i = e % m, j = e / m;
+    Ucol[e] = transA ? A[(long)j * lda + i] : A[(long)i * lda + j];
+  }
+  for (long e = tid; e < (long)c * c; e += nt) Vcol[e] = ((e / c) == (e % c)) ? 1.0 : 0.0;
+  __syncthreads();
+  const int cp = (c + 1) & ~1;
+  const double tol = 1e-15;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < cp - 1; ++rnd) {
+      for (int k = wave; k < cp / 2; k += nwaves) {
+        // circle method: slot 0 fixed, slots 1..cp-1 rotate by rnd
+        const int a = k, b = cp - 1 - k;
+        const int pa = (a == 0) ? 0 : ((a - 1 + rnd) % (cp - 1)) + 1;
+        const int pb = ((b - 1 + rnd) % (cp - 1)) + 1;
+        const int p = min(pa, pb), q = max(pa, pb);
+        if (q >= c) continue;
+        double* up = Ucol + (long)p * m;
+        double* uq = Ucol + (long)q * m;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < m; i += 64) {
+          const double x = up[i], y = uq[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = lane; i < m; i += 64) {
+          const double x = up[i], y = uq[i];
+          up[i] = cs * x - sn * y;
+          uq[i] = sn * x + cs * y;
+        }
+        double* vp = Vcol + (long)p * c;
+        double* vq = Vcol + (long)q * c;
+        for (int i = lane; i < c; i += 64) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = cs * x - sn * y;
+          vq[i] = sn * x + cs * y;
+        }
+        if (lane == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    if (s_rot == 0) break;
+    __syncthreads();
+  }
+  // singular values = column norms
+  for (int j = wave; j < c; j += nwaves) {
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += Ucol[(long)j * m + i] * Ucol[(long)j * m + i];
+    s = wave_sum(s);
+    if (lane == 0) s_sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 0; j < c; ++j) s_perm[j] = j;
+    for (int j = 0; j < c; ++j) {  // selection sort, descending; ties keep index order
+      int best = j;
+      for (int k = j + 1; k < c; ++k)
+        if (s_sig[s_perm[k]] > s_sig[s_perm[best]]) best = k;
+      const int tmp = s_perm[j];
+      s_perm[j] = s_perm[best];
+      s_perm[best] = tmp;
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < c; j += nt) S[j] = s_sig[s_perm[j]];
+  for (long e = tid; e < (long)m * c; e += nt) {
+    const int i = e / c, jj = e % c;
+    const int j = s_perm[jj];
+    const double sg = s_sig[j];
+    U[e] = (sg > 0.0) ? Ucol[(long)j * m + i] / sg : 0.0;
+  }
+  for (long e = tid; e < (long)c * c; e += nt) {
+    const int i = e / c, jj = e % c;
+    V[e] = Vcol[(long)s_perm[jj] * c + i];
+  }
+}
+
+void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
+               double* s, double* V) {
+  TTIGA_CHECK(c > 0 && m >= c && c <= 1024, TTIGA_E_ARG, "svd_small needs 0 < c <= m, c <= 1024");
+  DBuf Ucol(&ctx.alloc, sizeof(double) * (size_t)m * c), Vcol(&ctx.alloc, sizeof(double) * c * c);
+  const int threads = c <= 64 ? 128 : 512;
+  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(threads), 0, ctx.stream, m, c, A, transA ? 1 : 0,
+                     lda, Ucol.d(), Vcol.d(), U, s, V, 40);
+  TTIGA_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ small utilities
+__global__ void k_trunc_rank(const double* __restrict__ s, int c, double eps_rel, double delta_abs,
+                             double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double tot = 0.0;
+  for (int i = 0; i < c; ++i) tot += s[i] * s[i];
+  const double nrm = sqrt(tot);
+  const double delta = (delta_abs >= 0.0) ? delta_abs : eps_rel * nrm / sqrt(2.0);
+  // smallest r with ||s[r:]|| <= delta, accumulating the tail from the end
+  int r = c;
+  double tail = 0.0;
+  for (int i = c - 1; i >= 0; --i) {
+    const double t2 = tail + s[i] * s[i];
+    if (sqrt(t2) <= delta) {
+      tail = t2;
+      r = i;
+    } else {
+      break;
+    }
+  }
+  out[0] = (double)r;
+  out[1] = nrm;
+  out[2] = delta;
+}
+
+int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* norm_out) {
+  // delta >= 0: absolute threshold; delta < 0: relative eps = -delta.
+  double* h = ctx.host(3);
+  DBuf o(&ctx.alloc, 3 * sizeof(double));
+  hipLaunchKernelGGL(k_trunc_rank, dim3(1), dim3(64), 0, ctx.stream, s, c,
+                     delta < 0 ? -delta : 0.0, delta < 0 ? -1.0 : delta, o.d());
+  TTIGA_HIP(hipGetLastError());
+  TTIGA_HIP(hipMemcpyAsync(h, o.d(), 3 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  if (norm_out) {
+    norm_out[0] = h[1];
+    norm_out[1] = h[2];
+  }
+  return (int)h[0];
+}
+
+__global__ void k_fill(double* p, size_t n, double v) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+void fill(Context& ctx, double* p, size_t n, double v) {
+  if (!n) return;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, ctx.stream, p, n, v);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void copy(Context& ctx, double* dst, const double* src, size_t n) {
+  if (!n || dst == src) return;
+  TTIGA_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+}
+
+__global__ void k_sumsq_partial(const double* __restrict__ x, size_t n, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    s += x[e] * x[e];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) s += part[e];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+void sumsq_reduce(Context& ctx, const double* x, size_t n, double* out_dev) {
+  const int blocks = (int)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 1024));
+  DBuf part(&ctx.alloc, sizeof(double) * blocks);
+  hipLaunchKernelGGL(k_sumsq_partial, dim3(blocks), dim3(256), 0, ctx.stream, x, n, part.d());
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks, out_dev);
+  TTIGA_HIP(hipGetLastError());
+}
+
+}  // namespace ttiga

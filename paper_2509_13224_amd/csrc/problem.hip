@@ -1,0 +1,486 @@
+// Problem description, assembly driver and TT solve.
+//
+// Assembly (Sections 4.2-4.3):
+//   1. per direction, Gauss nodes/weights on the solution spans and the solution
+//      and geometry B-spline tables there;
+//   2. the seven factor tensors R_00..R_12, f det J on the Gauss grid (eq. Rxi, ffinal);
+//   3. TT-SVD of each factor: R components to a threshold relative to the largest
+//      ||R_ij||_F (identically vanishing components become rank 0), f det J
+//      relative to its own norm;
+//   4. banded TT-matrix cores of the nine K_ij (selector a_ij^(d)), summed with
+//      TT-rounding after each addition; TT cores of F;
+//   5. Dirichlet indices cut from the cores; constant face data lifted into the
+//      right-hand side F_I - (K u_g)_I.
+// Solve: conjugate gradients on TT tensors with TT-rounding of every update
+// (truncated TT-CG), true-residual replacement every 10 iterations and at the
+// stopping test.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "iga.hpp"
+#include "problem.hpp"
+
+namespace ttiga {
+
+static const int kTermOrder[9][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 0},
+                                     {0, 2}, {2, 0}, {1, 2}, {2, 1}};
+
+static int r_index(int i, int j) {
+  const int a = std::min(i, j), b = std::max(i, j);
+  static const int tab[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  return tab[a][b];
+}
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+static void check_knots(const double* k, int len, int p) {
+  TTIGA_CHECK(k != nullptr, TTIGA_E_ARG, "null knot vector");
+  for (int i = 0; i + 1 < len; ++i)
+    TTIGA_CHECK(k[i] <= k[i + 1], TTIGA_E_KNOTS, "knot vector is not non-decreasing");
+  for (int i = 0; i <= p; ++i) {
+    TTIGA_CHECK(k[i] == k[0], TTIGA_E_KNOTS, "knot vector start multiplicity != p+1");
+    TTIGA_CHECK(k[len - 1 - i] == k[len - 1], TTIGA_E_KNOTS, "knot vector end multiplicity != p+1");
+  }
+  TTIGA_CHECK(k[p + 1] > k[0] || len == 2 * (p + 1), TTIGA_E_KNOTS,
+              "knot vector end multiplicity exceeds p+1");
+  TTIGA_CHECK(k[len - p - 2] < k[len - 1] || len == 2 * (p + 1), TTIGA_E_KNOTS,
+              "knot vector end multiplicity exceeds p+1");
+  TTIGA_CHECK(k[0] == 0.0 && k[len - 1] == 1.0, TTIGA_E_KNOTS, "knot vectors must span [0, 1]");
+}
+
+Problem::Problem(Context* c, const ttiga_geometry* geo, const ttiga_discretization* disc,
+                 const ttiga_source* src, const ttiga_dirichlet* bc, const ttiga_options* opt)
+    : ctx(c) {
+  TTIGA_CHECK(geo && disc && src && bc && opt, TTIGA_E_ARG, "null problem description");
+  // geometry
+  size_t nctrl = 1;
+  for (int d = 0; d < 3; ++d) {
+    pg[d] = geo->degree[d];
+    m[d] = geo->n_ctrl[d];
+    TTIGA_CHECK(pg[d] >= 1 && pg[d] <= 8, TTIGA_E_ARG, "geometry degree must be in [1, 8]");
+    TTIGA_CHECK(m[d] >= pg[d] + 1, TTIGA_E_ARG, "geometry needs n_ctrl >= degree + 1");
+    const int len = m[d] + pg[d] + 1;
+    check_knots(geo->knots[d], len, pg[d]);
+    gknots[d].assign(geo->knots[d], geo->knots[d] + len);
+    nctrl *= (size_t)m[d];
+  }
+  TTIGA_CHECK(geo->ctrl_xyz != nullptr, TTIGA_E_ARG, "null control points");
+  ctrl.assign(geo->ctrl_xyz, geo->ctrl_xyz + 3 * nctrl);
+  weights.assign(nctrl, 1.0);
+  if (geo->weights) {
+    weights.assign(geo->weights, geo->weights + nctrl);
+    for (double w : weights) TTIGA_CHECK(w > 0.0 && std::isfinite(w), TTIGA_E_GEOM, "weights must be positive");
+  }
+  for (double v : ctrl) TTIGA_CHECK(std::isfinite(v), TTIGA_E_GEOM, "non-finite control point");
+  // discretisation
+  p = disc->degree;
+  TTIGA_CHECK(p >= 1 && p <= 8, TTIGA_E_ARG, "solution degree must be in [1, 8]");
+  g = disc->n_gauss > 0 ? disc->n_gauss : p + 1;
+  TTIGA_CHECK(g >= 1 && g <= 8, TTIGA_E_ARG, "n_gauss must be in [0, 8]");
+  for (int d = 0; d < 3; ++d) {
+    n[d] = disc->n_basis[d];
+    TTIGA_CHECK(n[d] >= p + 1, TTIGA_E_ARG, "n_basis must be >= degree + 1");
+    TTIGA_CHECK(n[d] <= (1 << 20), TTIGA_E_ARG, "n_basis too large");
+    E[d] = n[d] - p;
+    Q[d] = E[d] * g;
+  }
+  // source
+  src_kind = src->kind;
+  TTIGA_CHECK(src_kind == TTIGA_SOURCE_ZERO || src_kind == TTIGA_SOURCE_MANUFACTURED_ANNULUS ||
+                  src_kind == TTIGA_SOURCE_FOURIER,
+              TTIGA_E_ARG, "unknown source kind");
+  if (src_kind == TTIGA_SOURCE_FOURIER) {
+    TTIGA_CHECK(src->n_modes >= 0 && src->n_modes <= 4096, TTIGA_E_ARG, "bad n_modes");
+    TTIGA_CHECK(src->n_modes == 0 || (src->a && src->k && src->phi), TTIGA_E_ARG, "null Fourier data");
+    TTIGA_CHECK(src->scale > 0.0, TTIGA_E_ARG, "Fourier scale must be positive");
+    src_a.assign(src->a, src->a + src->n_modes);
+    src_k.assign(src->k, src->k + 3 * src->n_modes);
+    src_phi.assign(src->phi, src->phi + src->n_modes);
+  }
+  for (int d = 0; d < 3; ++d) src_origin[d] = src->origin[d];
+  src_scale = src->scale > 0.0 ? src->scale : 1.0;
+  // boundary data
+  for (int f = 0; f < 6; ++f) {
+    bc_kind[f] = bc->kind[f];
+    bc_value[f] = bc->value[f];
+    TTIGA_CHECK(bc_kind[f] >= TTIGA_BC_NATURAL && bc_kind[f] <= TTIGA_BC_CONSTANT, TTIGA_E_ARG,
+                "unknown boundary kind");
+  }
+  // constant data must be carried by faces of one direction (rank-1 lifting)
+  int dir = -1;
+  for (int f = 0; f < 6; ++f)
+    if (bc_kind[f] == TTIGA_BC_CONSTANT && bc_value[f] != 0.0) {
+      TTIGA_CHECK(dir < 0 || dir == f / 2, TTIGA_E_ARG,
+                  "non-zero constant Dirichlet data on faces of more than one direction");
+      dir = f / 2;
+    }
+  lift_dir = dir;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = bc_kind[2 * d] == TTIGA_BC_NATURAL ? 0 : 1;
+    hi[d] = bc_kind[2 * d + 1] == TTIGA_BC_NATURAL ? n[d] : n[d] - 1;
+    TTIGA_CHECK(hi[d] - lo[d] >= 1, TTIGA_E_ARG, "no interior unknowns");
+  }
+  // options
+  opts = *opt;
+  TTIGA_CHECK(opts.tt_eps > 0.0 && opts.tt_eps < 1.0, TTIGA_E_ARG, "tt_eps must be in (0, 1)");
+  TTIGA_CHECK(opts.rel_res_tol > 0.0, TTIGA_E_ARG, "rel_res_tol must be positive");
+  TTIGA_CHECK(opts.max_iter > 0, TTIGA_E_ARG, "max_iter must be positive");
+  TTIGA_CHECK(opts.precision == TTIGA_FP64, TTIGA_E_ARG, "only TTIGA_FP64 in this version");
+  if (opts.max_rank <= 0) opts.max_rank = 1 << 20;
+}
+
+void Problem::upload() {
+  Context& c = *ctx;
+  const size_t nctrl = (size_t)m[0] * m[1] * m[2];
+  DBuf xyz(&c.alloc, sizeof(double) * 3 * nctrl), w(&c.alloc, sizeof(double) * nctrl);
+  TTIGA_HIP(hipMemcpyAsync(xyz.d(), ctrl.data(), sizeof(double) * 3 * nctrl, hipMemcpyHostToDevice, c.stream));
+  TTIGA_HIP(hipMemcpyAsync(w.d(), weights.data(), sizeof(double) * nctrl, hipMemcpyHostToDevice, c.stream));
+  Pw = DBuf(&c.alloc, sizeof(double) * 4 * nctrl);
+  launch_homogeneous(c, (long)nctrl, xyz.d(), w.d(), Pw.d());
+  for (int d = 0; d < 3; ++d) {
+    gknots_d[d] = DBuf(&c.alloc, sizeof(double) * gknots[d].size());
+    TTIGA_HIP(hipMemcpyAsync(gknots_d[d].d(), gknots[d].data(), sizeof(double) * gknots[d].size(),
+                             hipMemcpyHostToDevice, c.stream));
+    // open uniform solution knots: p+1 zeros, e/E for e = 1..E-1, p+1 ones
+    std::vector<double> kn(n[d] + p + 1);
+    for (int i = 0; i < (int)kn.size(); ++i) {
+      const int e = std::min(std::max(i - p, 0), E[d]);
+      kn[i] = (e == E[d]) ? 1.0 : (double)e / E[d];
+    }
+    sknots_d[d] = DBuf(&c.alloc, sizeof(double) * kn.size());
+    TTIGA_HIP(hipMemcpyAsync(sknots_d[d].d(), kn.data(), sizeof(double) * kn.size(),
+                             hipMemcpyHostToDevice, c.stream));
+  }
+  const int nm = (int)src_a.size();
+  if (nm > 0) {
+    modes_d = DBuf(&c.alloc, sizeof(double) * 5 * nm);
+    std::vector<double> h(5 * nm);
+    std::memcpy(h.data(), src_a.data(), sizeof(double) * nm);
+    std::memcpy(h.data() + nm, src_k.data(), sizeof(double) * 3 * nm);
+    std::memcpy(h.data() + 4 * nm, src_phi.data(), sizeof(double) * nm);
+    TTIGA_HIP(hipMemcpyAsync(modes_d.d(), h.data(), sizeof(double) * 5 * nm, hipMemcpyHostToDevice, c.stream));
+  }
+  c.sync();  // host vectors above go out of scope
+}
+
+SourceDev Problem::source_dev() const {
+  SourceDev s{};
+  s.kind = src_kind;
+  s.n_modes = (int)src_a.size();
+  if (s.n_modes > 0) {
+    s.a = modes_d.d();
+    s.k = modes_d.d() + s.n_modes;
+    s.phi = modes_d.d() + 4 * s.n_modes;
+  }
+  for (int d = 0; d < 3; ++d) s.origin[d] = src_origin[d];
+  s.scale = src_scale;
+  return s;
+}
+
+void Problem::build_tables() {
+  Context& c = *ctx;
+  for (int d = 0; d < 3; ++d) {
+    const int Qd = Q[d];
+    tab_xi[d] = DBuf(&c.alloc, sizeof(double) * Qd);
+    tab_w[d] = DBuf(&c.alloc, sizeof(double) * Qd);
+    tab_B[d] = DBuf(&c.alloc, sizeof(double) * Qd * (p + 1));
+    tab_D[d] = DBuf(&c.alloc, sizeof(double) * Qd * (p + 1));
+    launch_basis_tables(c, n[d], p, g, sknots_d[d].d(), tab_xi[d].d(), tab_w[d].d(), tab_B[d].d(),
+                        tab_D[d].d());
+    gtab_span[d] = DBuf(&c.alloc, sizeof(int) * Qd);
+    gtab_B[d] = DBuf(&c.alloc, sizeof(double) * Qd * (pg[d] + 1));
+    gtab_D[d] = DBuf(&c.alloc, sizeof(double) * Qd * (pg[d] + 1));
+    launch_geo_tables(c, Qd, tab_xi[d].d(), 1, m[d], pg[d], gknots_d[d].d(), gtab_span[d].as<int>(),
+                      gtab_B[d].d(), gtab_D[d].d());
+  }
+}
+
+GeoDev Problem::geo_dev(const DBuf* span, const DBuf* B, const DBuf* D) const {
+  GeoDev gd{};
+  for (int d = 0; d < 3; ++d) {
+    gd.pg[d] = pg[d];
+    gd.m[d] = m[d];
+    gd.span[d] = span[d].as<int>();
+    gd.B[d] = B[d].d();
+    gd.D[d] = D[d].d();
+  }
+  gd.Pw = Pw.d();
+  return gd;
+}
+
+void Problem::assemble(ttiga_assembly_stats* st) {
+  Context& c = *ctx;
+  ttiga_assembly_stats s{};
+  double t0 = now_ms();
+  build_tables();
+  // 2. factor tensors on the Gauss grid
+  const size_t total = (size_t)Q[0] * Q[1] * Q[2];
+  DBuf Fac(&c.alloc, sizeof(double) * 7 * total);
+  DBuf st8(&c.alloc, sizeof(double) * 8);
+  launch_factors_grid(c, geo_dev(gtab_span, gtab_B, gtab_D), source_dev(), Q, Fac.d(), st8.d());
+  double* h = c.host(8);
+  TTIGA_HIP(hipMemcpyAsync(h, st8.d(), 8 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+  double sumsq[7];
+  for (int f = 0; f < 7; ++f) sumsq[f] = h[f];
+  s.min_detJ = h[7];
+  double rmax = 0.0;
+  for (int f = 0; f < 6; ++f) rmax = std::max(rmax, std::sqrt(sumsq[f]));
+  s.max_R_norm = rmax;
+  min_detJ = s.min_detJ;
+  if (!(s.min_detJ > 0.0))
+    throw Error(TTIGA_E_DETJ, "min det J = " + std::to_string(s.min_detJ) + " <= 0 on the Gauss grid");
+  double t1 = now_ms();
+  s.time_ms[0] = t1 - t0;
+  // 3. TT compression
+  const double eps = opts.tt_eps;
+  const double dR = eps * rmax / std::sqrt(2.0);
+  const double dF = eps * std::sqrt(sumsq[6]) / std::sqrt(2.0);
+  for (int f = 0; f < 7; ++f) {
+    TT& dst = (f < 6) ? R[f] : fJ;
+    if (f < 6 && sumsq[f] == 0.0) { dst.set_zero(Q); continue; }
+    if (f == 6 && sumsq[6] == 0.0) { dst.set_zero(Q); continue; }
+    tt_compress_dense(c, Fac.d() + f * total, Q, f < 6 ? dR : dF, dst, opts.max_rank);
+  }
+  Fac.reset();
+  c.sync();
+  double t2 = now_ms();
+  s.time_ms[1] = t2 - t1;
+  for (int f = 0; f < 6; ++f)
+    for (int k = 0; k < 4; ++k) s.rank_R[f][k] = R[f].r[k];
+  for (int k = 0; k < 4; ++k) s.rank_fJ[k] = fJ.r[k];
+  // 4. K as the rounded sum of the nine components, F from f det J
+  const int band = 2 * p + 1;
+  int nb[3] = {n[0] * band, n[1] * band, n[2] * band};
+  K.set_zero(nb);
+  for (int tI = 0; tI < 9; ++tI) {
+    const int i = kTermOrder[tI][0], j = kTermOrder[tI][1];
+    const TT& Rt = R[r_index(i, j)];
+    if (Rt.zero()) continue;
+    TT term;
+    term.alloc(c, nb, Rt.r);
+    for (int d = 0; d < 3; ++d) {
+      const double* row = (d == i) ? tab_D[d].d() : tab_B[d].d();
+      const double* col = (d == j) ? tab_D[d].d() : tab_B[d].d();
+      launch_assemble_band(c, n[d], p, g, Rt.r[d], Rt.r[d + 1], Rt.c[d].d(), tab_w[d].d(), row, col,
+                           term.c[d].d());
+    }
+    if (K.zero()) {
+      K = std::move(term);
+    } else {
+      TT sum;
+      tt_axpby(c, 1.0, K, 1.0, term, sum);
+      tt_round(c, sum, eps, -1.0, opts.max_rank);
+      K = std::move(sum);
+    }
+  }
+  if (!fJ.zero()) {
+    F.alloc(c, n, fJ.r);
+    for (int d = 0; d < 3; ++d)
+      launch_assemble_vec(c, n[d], p, g, fJ.r[d], fJ.r[d + 1], fJ.c[d].d(), tab_w[d].d(), tab_B[d].d(),
+                          F.c[d].d());
+  } else {
+    F.set_zero(n);
+  }
+  c.sync();
+  double t3 = now_ms();
+  s.time_ms[2] = t3 - t2;
+  for (int k = 0; k < 4; ++k) {
+    s.rank_K[k] = K.r[k];
+    s.rank_F[k] = F.r[k];
+  }
+  // 5. boundary reduction
+  reduce_boundary();
+  c.sync();
+  s.time_ms[3] = now_ms() - t3;
+  assembled = true;
+  solved = false;
+  if (st) *st = s;
+}
+
+void Problem::reduce_boundary() {
+  Context& c = *ctx;
+  const int band = 2 * p + 1;
+  int ni[3];
+  for (int d = 0; d < 3; ++d) ni[d] = hi[d] - lo[d];
+  int nbi[3] = {ni[0] * band, ni[1] * band, ni[2] * band};
+  if (K.zero()) throw Error(TTIGA_E_GEOM, "stiffness operator is zero");
+  KII.alloc(c, nbi, K.r);
+  for (int d = 0; d < 3; ++d)
+    launch_slice_band(c, n[d], p, lo[d], ni[d], K.r[d], K.r[d + 1], K.c[d].d(), KII.c[d].d());
+  TT FI;
+  if (!F.zero()) {
+    FI.alloc(c, ni, F.r);
+    for (int d = 0; d < 3; ++d)
+      launch_slice_vec(c, n[d], lo[d], ni[d], F.r[d], F.r[d + 1], F.c[d].d(), FI.c[d].d());
+  } else {
+    FI.set_zero(ni);
+  }
+  if (lift_dir >= 0) {
+    // u_g: rank 1; direction lift_dir carries the two face constants, the others are
+    // ones except at Dirichlet ends of later directions (later faces win at edges).
+    TT ug;
+    int r1[4] = {1, 1, 1, 1};
+    ug.alloc(c, n, r1);
+    for (int d = 0; d < 3; ++d) {
+      std::vector<double> v(n[d], 0.0);
+      if (d == lift_dir) {
+        if (bc_kind[2 * d] == TTIGA_BC_CONSTANT) v[0] = bc_value[2 * d];
+        if (bc_kind[2 * d + 1] == TTIGA_BC_CONSTANT) v[n[d] - 1] = bc_value[2 * d + 1];
+      } else {
+        std::fill(v.begin(), v.end(), 1.0);
+        if (d > lift_dir) {
+          if (bc_kind[2 * d] != TTIGA_BC_NATURAL) v[0] = 0.0;
+          if (bc_kind[2 * d + 1] != TTIGA_BC_NATURAL) v[n[d] - 1] = 0.0;
+        }
+      }
+      TTIGA_HIP(hipMemcpyAsync(ug.c[d].d(), v.data(), sizeof(double) * n[d], hipMemcpyHostToDevice,
+                               c.stream));
+      c.sync();
+    }
+    TT Kug, KugI;
+    tt_matvec_banded(c, K, p, ug, Kug);
+    KugI.alloc(c, ni, Kug.r);
+    for (int d = 0; d < 3; ++d)
+      launch_slice_vec(c, n[d], lo[d], ni[d], Kug.r[d], Kug.r[d + 1], Kug.c[d].d(), KugI.c[d].d());
+    TT sum;
+    tt_axpby(c, 1.0, FI, -1.0, KugI, sum);
+    tt_round(c, sum, opts.tt_eps * 1e-2, -1.0, opts.max_rank);
+    rhs = std::move(sum);
+  } else {
+    rhs = std::move(FI);
+  }
+}
+
+// Truncated TT-CG (conjugate gradients with TT-rounding of each update).
+void Problem::solve(ttiga_solve_stats* st) {
+  TTIGA_CHECK(assembled, TTIGA_E_STATE, "solve before assemble");
+  Context& c = *ctx;
+  ttiga_solve_stats s{};
+  const double t0 = now_ms();
+  const double eps = opts.tt_eps, tol = opts.rel_res_tol;
+  const double eps_x = std::min(eps, 0.1 * tol);
+  int ni[3];
+  for (int d = 0; d < 3; ++d) ni[d] = hi[d] - lo[d];
+  u.set_zero(ni);
+  int status = TTIGA_OK;
+  int max_seen = 0;
+  auto seen = [&](const TT& t) {
+    for (int k = 1; k < 3; ++k) max_seen = std::max(max_seen, t.r[k]);
+  };
+  if (rhs.zero()) {
+    s.iterations = 0;
+    s.rel_res = 0.0;
+  } else {
+    const double nb = std::sqrt(std::max(tt_dot_sync(c, rhs, rhs), 0.0));
+    TT r, pdir;
+    tt_copy(c, rhs, r);
+    tt_copy(c, rhs, pdir);
+    double rho = tt_dot_sync(c, r, r);
+    int it = 0;
+    bool conv = false;
+    double true_res = 1.0;
+    while (it < opts.max_iter) {
+      ++it;
+      TT q;
+      tt_matvec_banded(c, KII, p, pdir, q);
+      seen(q);
+      tt_round(c, q, eps, -1.0, opts.max_rank);
+      const double pq = tt_dot_sync(c, pdir, q);
+      const double alpha = rho / pq;
+      TT xn, rn;
+      tt_axpby(c, 1.0, u, alpha, pdir, xn);
+      tt_round(c, xn, eps_x, -1.0, opts.max_rank);
+      u = std::move(xn);
+      tt_axpby(c, 1.0, r, -alpha, q, rn);
+      tt_round(c, rn, eps, -1.0, opts.max_rank);
+      r = std::move(rn);
+      const double est = std::sqrt(std::max(tt_dot_sync(c, r, r), 0.0)) / nb;
+      if (it % 10 == 0 || est <= tol) {
+        TT Ku, tr;
+        tt_matvec_banded(c, KII, p, u, Ku);
+        seen(Ku);
+        tt_axpby(c, 1.0, rhs, -1.0, Ku, tr);
+        double nrm = 0.0;
+        tt_round(c, tr, eps_x, -1.0, opts.max_rank, &nrm);
+        r = std::move(tr);
+        true_res = nrm / nb;
+        if (true_res <= tol) {
+          conv = true;
+          break;
+        }
+      }
+      const double rho_new = tt_dot_sync(c, r, r);
+      const double beta = rho_new / rho;
+      rho = rho_new;
+      TT pn;
+      tt_axpby(c, 1.0, r, beta, pdir, pn);
+      tt_round(c, pn, eps, -1.0, opts.max_rank);
+      pdir = std::move(pn);
+      seen(u);
+    }
+    if (!conv) {
+      TT Ku, tr;
+      tt_matvec_banded(c, KII, p, u, Ku);
+      tt_axpby(c, 1.0, rhs, -1.0, Ku, tr);
+      double nrm = 0.0;
+      tt_round(c, tr, eps_x, -1.0, 0, &nrm);
+      true_res = nrm / nb;
+      status = TTIGA_E_NOTCONV;
+    }
+    s.iterations = it;
+    s.rel_res = true_res;
+  }
+  for (int k = 0; k < 4; ++k) s.rank_u[k] = u.r[k];
+  s.max_rank_seen = max_seen;
+  s.status = status;
+  c.sync();
+  s.time_ms = now_ms() - t0;
+  solved = true;
+  last_solve = s;
+  if (st) *st = s;
+  if (status != TTIGA_OK) throw Error(status, "TT-CG did not reach rel_res_tol within max_iter");
+}
+
+const TT* Problem::which(int w) const {
+  if (w == TTIGA_WHICH_K) return &K;
+  if (w == TTIGA_WHICH_F) return &F;
+  if (w == TTIGA_WHICH_KII) return &KII;
+  if (w == TTIGA_WHICH_RHS) return &rhs;
+  if (w >= TTIGA_WHICH_FACTOR0 && w < TTIGA_WHICH_FACTOR0 + 6) return &R[w - TTIGA_WHICH_FACTOR0];
+  if (w == TTIGA_WHICH_FACTOR0 + 6) return &fJ;
+  return nullptr;
+}
+
+void Problem::sample_points(const double* pts, size_t count, double* out, double* det_out) {
+  Context& c = *ctx;
+  TTIGA_CHECK(pts && out && count > 0, TTIGA_E_ARG, "sample_factors: null or empty input");
+  for (size_t q = 0; q < 3 * count; ++q)
+    TTIGA_CHECK(pts[q] >= 0.0 && pts[q] <= 1.0, TTIGA_E_ARG, "sample point outside [0,1]^3");
+  DBuf P(&c.alloc, sizeof(double) * 3 * count);
+  TTIGA_HIP(hipMemcpyAsync(P.d(), pts, sizeof(double) * 3 * count, hipMemcpyHostToDevice, c.stream));
+  DBuf span[3], B[3], D[3];
+  for (int d = 0; d < 3; ++d) {
+    span[d] = DBuf(&c.alloc, sizeof(int) * count);
+    B[d] = DBuf(&c.alloc, sizeof(double) * count * (pg[d] + 1));
+    D[d] = DBuf(&c.alloc, sizeof(double) * count * (pg[d] + 1));
+    launch_geo_tables(c, (int)count, P.d() + d, 3, m[d], pg[d], gknots_d[d].d(), span[d].as<int>(),
+                      B[d].d(), D[d].d());
+  }
+  DBuf O(&c.alloc, sizeof(double) * 7 * count), Dt(&c.alloc, sizeof(double) * count);
+  launch_factors_points(c, geo_dev(span, B, D), source_dev(), (long)count, O.d(), Dt.d());
+  TTIGA_HIP(hipMemcpyAsync(out, O.d(), sizeof(double) * 7 * count, hipMemcpyDeviceToHost, c.stream));
+  if (det_out)
+    TTIGA_HIP(hipMemcpyAsync(det_out, Dt.d(), sizeof(double) * count, hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+}
+
+}  // namespace ttiga

@@ -1,0 +1,54 @@
+// One TT-IGA problem: validated host copy of the description plus its device state.
+#pragma once
+
+#include <vector>
+
+#include "iga.hpp"
+
+namespace ttiga {
+
+struct Problem {
+  Context* ctx;
+  // description
+  int pg[3], m[3];
+  std::vector<double> gknots[3], ctrl, weights;
+  int p, g, n[3], E[3], Q[3];
+  int src_kind;
+  std::vector<double> src_a, src_k, src_phi;
+  double src_origin[3], src_scale;
+  int bc_kind[6];
+  double bc_value[6];
+  int lift_dir = -1;
+  int lo[3], hi[3];  // interior index range per direction
+  ttiga_options opts;
+  // device inputs
+  DBuf Pw, gknots_d[3], sknots_d[3], modes_d;
+  // per-direction tables at the Gauss nodes
+  DBuf tab_xi[3], tab_w[3], tab_B[3], tab_D[3];
+  DBuf gtab_span[3], gtab_B[3], gtab_D[3];
+  // TT state
+  TT R[6], fJ, K, F, KII, rhs, u;
+  double min_detJ = 0.0;
+  bool assembled = false, solved = false;
+  ttiga_solve_stats last_solve{};
+
+  Problem(Context* c, const ttiga_geometry* geo, const ttiga_discretization* disc,
+          const ttiga_source* src, const ttiga_dirichlet* bc, const ttiga_options* opt);
+  void assemble(ttiga_assembly_stats* st);
+  void solve(ttiga_solve_stats* st);
+  const TT* which(int w) const;
+  void sample_points(const double* pts, size_t count, double* out, double* det_out);
+  void upload();  // device copies of the small inputs
+
+ private:
+  void build_tables();
+  void reduce_boundary();
+  SourceDev source_dev() const;
+  GeoDev geo_dev(const DBuf* span, const DBuf* B, const DBuf* D) const;
+};
+
+}  // namespace ttiga
+
+struct ttiga_problem {
+  ttiga::Problem* impl;
+};

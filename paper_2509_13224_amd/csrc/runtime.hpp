@@ -1,0 +1,162 @@
+// Internal runtime of the TT-IGA library: context, device allocator, TT handles,
+// and the host-side drivers that sequence the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ttiga.h"
+
+struct ttiga_ctx;
+
+namespace ttiga {
+
+// Errors travel as exceptions inside the library and become status codes at the C ABI.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define TTIGA_HIP(call)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw ::ttiga::Error(TTIGA_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define TTIGA_CHECK(cond, code, msg) \
+  do {                               \
+    if (!(cond)) throw ::ttiga::Error((code), (msg)); \
+  } while (0)
+
+// First-fit sub-allocator over one device buffer, or direct hipMalloc when no
+// workspace was given.  All blocks are 256-byte aligned.
+class DeviceAllocator {
+ public:
+  ~DeviceAllocator();
+  void set_workspace(void* base, size_t bytes);
+  void* alloc(size_t bytes);
+  void release(void* p);
+  size_t in_use() const { return in_use_; }
+  size_t high_water() const { return high_water_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0;
+  std::map<size_t, size_t> free_;   // offset -> size
+  std::map<size_t, size_t> used_;   // offset -> size
+  std::map<void*, size_t> direct_;  // hipMalloc'd blocks when no workspace
+  size_t in_use_ = 0, high_water_ = 0;
+};
+
+// A device buffer owned by the allocator; freed when the handle dies.
+struct DBuf {
+  DeviceAllocator* a = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(DeviceAllocator* al, size_t b) : a(al), bytes(b) { p = b ? al->alloc(b) : nullptr; }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      a = o.a; p = o.p; bytes = o.bytes;
+      o.a = nullptr; o.p = nullptr; o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() {
+    if (a && p) a->release(p);
+    p = nullptr; bytes = 0;
+  }
+  double* d() const { return static_cast<double*>(p); }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  DeviceAllocator alloc;
+  // pinned host staging for small readbacks (ranks, scalars)
+  double* host_scratch = nullptr;
+  size_t host_scratch_doubles = 0;
+  uint64_t rng_counter = 0x5eed;  // sketch seeds advance deterministically per context
+  // problems and TT handles alive on this context; ttiga_destroy defers the
+  // deletion until the last of them is destroyed
+  int live_objects = 0;
+  bool closing = false;
+  void (*on_last_release)(Context*) = nullptr;  // frees the owning C handle
+  struct ::ttiga_ctx* owner = nullptr;
+  ~Context();
+  double* host(size_t n);
+  void sync() { TTIGA_HIP(hipStreamSynchronize(stream)); }
+};
+
+// TT tensor with d = 3 cores in paper order [r_k][n_k][r_{k+1}] (FP64, device).
+struct TT {
+  int n[3] = {0, 0, 0};
+  int r[4] = {0, 0, 0, 0};  // all zero: the exact zero tensor
+  DBuf c[3];
+  bool zero() const { return r[1] == 0; }
+  size_t core_elems(int k) const { return (size_t)r[k] * n[k] * r[k + 1]; }
+  size_t total_elems() const { return core_elems(0) + core_elems(1) + core_elems(2); }
+  void alloc(Context& ctx, const int* nn, const int* rr);
+  void set_zero(const int* nn) {
+    for (int k = 0; k < 3; ++k) { n[k] = nn[k]; c[k].reset(); }
+    for (int k = 0; k < 4; ++k) r[k] = 0;
+  }
+};
+
+// Library-owned TT tensor returned through the C ABI.
+}  // namespace ttiga
+
+struct ttiga_tt {
+  ttiga::Context* ctx;
+  ttiga::TT t;
+};
+
+namespace ttiga {
+
+// ----------------------------------------------------------------- kernel API
+// Dense linear algebra on the stream (kernels_linalg.hip).
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]; row-major operands.
+void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+          long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+          long sC, int batch = 1);
+// Q (m x c, row-major, orthonormal columns) and R (c x c, upper) with op(A) = Q R (Householder TSQR).
+void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
+             double* R);
+// One-sided Jacobi SVD of op(A) (m x c, m >= c): U (m x c), s (c, descending), V (c x c).
+void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
+               double* s, double* V);
+// Smallest r with ||s[r:]|| <= delta (delta < 0: -delta * ||s|| / sqrt(2) relative).
+int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* norm_out);
+void fill(Context& ctx, double* p, size_t n, double v);
+void copy(Context& ctx, double* dst, const double* src, size_t n);
+void sumsq_reduce(Context& ctx, const double* x, size_t n, double* out_dev);
+
+// TT algebra (tt_ops.cpp / kernels_tt.hip).
+void tt_from_view(Context& ctx, const ttiga_tt_view& v, TT& out);
+void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_rank,
+              double* norm_out = nullptr);
+void tt_axpby(Context& ctx, double alpha, const TT& x, double beta, const TT& y, TT& out);
+void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* beta, const TT& y,
+                  TT& out);
+double tt_dot_sync(Context& ctx, const TT& x, const TT& y);
+void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev);
+void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y);
+void tt_compress_dense(Context& ctx, const double* A, const int* n, double delta, TT& out,
+                       int max_rank);
+void tt_copy(Context& ctx, const TT& src, TT& dst);
+
+}  // namespace ttiga

@@ -1,0 +1,438 @@
+// TT algebra on the device (Section 4.1.1 format; rounding and TT-SVD of
+// Oseledets 2011, which the paper cites for its TT format and for the
+// rounding after each summation in Section 4.2.1).
+//
+// Cores live in paper order [r_k][n_k][r_{k+1}], row-major, so the unfolding
+// (r_k n_k) x r_{k+1} is a plain row-major matrix and r_k x (n_k r_{k+1}) is its
+// transpose view: every contraction below is one strided GEMM.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "runtime.hpp"
+
+namespace ttiga {
+
+void TT::alloc(Context& ctx, const int* nn, const int* rr) {
+  for (int k = 0; k < 3; ++k) n[k] = nn[k];
+  for (int k = 0; k < 4; ++k) r[k] = rr[k];
+  for (int k = 0; k < 3; ++k) c[k] = DBuf(&ctx.alloc, sizeof(double) * core_elems(k));
+}
+
+// --------------------------------------------------------------- kernels
+// y[(b a)][i][(b' a')] = sum_t M[b][i][t][b'] x[a][i+t-p][a'] over in-range columns.
+__global__ void k_matvec_banded(int n, int p, int rK0, int rK1, int rx0, int rx1,
+                                const double* __restrict__ M, const double* __restrict__ X,
+                                double* __restrict__ Y) {
+  const long R1 = (long)rK1 * rx1;
+  const long total = (long)rK0 * rx0 * n * R1;
+  const int band = 2 * p + 1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int a2 = e % rx1;
+    const int b2 = (e / rx1) % rK1;
+    const int i = (e / R1) % n;
+    const long ba = e / (R1 * n);
+    const int a = ba % rx0, b = ba / rx0;
+    const double* Mrow = M + (((long)b * n + i) * band) * rK1 + b2;
+    double s = 0.0;
+    for (int t = 0; t < band; ++t) {
+      const int j = i + t - p;
+      if (j < 0 || j >= n) continue;
+      s += Mrow[(long)t * rK1] * X[((long)a * n + j) * rx1 + a2];
+    }
+    Y[e] = s;
+  }
+}
+
+// out core k of alpha x + beta y (block structure of the TT sum).
+__global__ void k_axpby_core(int k, int d, int n, int rx0, int rx1, int ry0, int ry1,
+                             const double* __restrict__ X, const double* __restrict__ Yc,
+                             const double* alpha_p, double alpha, const double* beta_p,
+                             double beta, double* __restrict__ O) {
+  const double al = alpha_p ? *alpha_p : alpha;
+  const double be = beta_p ? *beta_p : beta;
+  const int o0 = (k == 0) ? 1 : rx0 + ry0;
+  const int o1 = (k == d - 1) ? 1 : rx1 + ry1;
+  const long total = (long)o0 * n * o1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e % o1;
+    const int i = (e / o1) % n;
+    const int a = e / ((long)o1 * n);
+    double v = 0.0;
+    if (k == 0) {
+      if (b < rx1) v = al * X[(long)i * rx1 + b];
+      else v = be * Yc[(long)i * ry1 + (b - rx1)];
+    } else if (k == d - 1) {
+      if (a < rx0) v = X[(long)a * n + i];
+      else v = Yc[(long)(a - rx0) * n + i];
+    } else {
+      if (a < rx0 && b < rx1) v = X[((long)a * n + i) * rx1 + b];
+      else if (a >= rx0 && b >= rx1) v = Yc[((long)(a - rx0) * n + i) * ry1 + (b - rx1)];
+    }
+    O[e] = v;
+  }
+}
+
+__global__ void k_scale_copy(const double* __restrict__ X, long n, const double* alpha_p,
+                             double alpha, double* __restrict__ O) {
+  const double al = alpha_p ? *alpha_p : alpha;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x)
+    O[e] = al * X[e];
+}
+
+// US[i][j] = U[i][j] * s[j] for j < s_cols (U is m x ldu).
+__global__ void k_scale_cols(const double* __restrict__ U, int m, int ldu, const double* __restrict__ s,
+                             int cols, double* __restrict__ O) {
+  const long total = (long)m * cols;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = e / cols, j = e % cols;
+    O[e] = U[(long)i * ldu + j] * s[j];
+  }
+}
+
+// Identity core [m][m] (m x m row-major).
+__global__ void k_eye(int m, double* __restrict__ O) {
+  const long total = (long)m * m;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x)
+    O[e] = ((e / m) == (e % m)) ? 1.0 : 0.0;
+}
+
+
+// O (rows x s) = first s columns of U (rows x ld)
+__global__ void k_copy_cols(const double* __restrict__ U, int rows, int ld, int s,
+                            double* __restrict__ O) {
+  const long total = (long)rows * s;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x)
+    O[e] = U[(e / s) * ld + (e % s)];
+}
+
+// O (s x rows) = transpose of the first s columns of V (rows x ld)
+__global__ void k_transpose_cols(const double* __restrict__ V, int rows, int ld, int s,
+                                 double* __restrict__ O) {
+  const long total = (long)rows * s;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int j = e / rows, i = e % rows;
+    O[e] = V[(long)i * ld + j];
+  }
+}
+
+// O[i][:] = s[i] * V[i][:] for a row-major (rows x M) matrix
+__global__ void k_scale_rows(const double* __restrict__ V, int rows, long M, const double* __restrict__ s,
+                             double* __restrict__ O) {
+  const long total = (long)rows * M;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x)
+    O[e] = s[e / M] * V[e];
+}
+
+// Standard normal numbers from a counter-based hash (SplitMix64 finaliser + Box-Muller).
+__device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_gaussian(double* __restrict__ O, long n, uint64_t seed) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x) {
+    const uint64_t h1 = mix64(seed * 0x9e3779b97f4a7c15ULL + 2 * (uint64_t)e + 1);
+    const uint64_t h2 = mix64(h1 ^ 0xda942042e4dd58b5ULL);
+    const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    O[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+static int grid_for(long total) {
+  return (int)std::max<long>(1, std::min<long>((total + 255) / 256, 16384));
+}
+
+// --------------------------------------------------------------- host ops
+void tt_copy(Context& ctx, const TT& src, TT& dst) {
+  if (src.zero()) { dst.set_zero(src.n); return; }
+  dst.alloc(ctx, src.n, src.r);
+  for (int k = 0; k < 3; ++k) copy(ctx, dst.c[k].d(), src.c[k].d(), src.core_elems(k));
+}
+
+void tt_from_view(Context& ctx, const ttiga_tt_view& v, TT& out) {
+  int n[3], r[4];
+  for (int k = 0; k < 3; ++k) n[k] = v.n[k];
+  for (int k = 0; k < 4; ++k) r[k] = v.r[k];
+  TTIGA_CHECK(r[0] == 1 && r[3] == 1, TTIGA_E_ARG, "TT view needs r0 = r3 = 1");
+  for (int k = 0; k < 3; ++k) TTIGA_CHECK(n[k] > 0 && r[k + 1] > 0 && v.core[k], TTIGA_E_ARG, "bad TT view");
+  out.alloc(ctx, n, r);
+  for (int k = 0; k < 3; ++k) copy(ctx, out.c[k].d(), v.core[k], out.core_elems(k));
+}
+
+void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y) {
+  // K is stored as a TT with mode sizes n_k (2p+1).
+  int n[3], r[4];
+  for (int k = 0; k < 3; ++k) n[k] = x.n[k];
+  if (K.zero() || x.zero()) { y.set_zero(n); return; }
+  for (int k = 0; k < 3; ++k)
+    TTIGA_CHECK(K.n[k] == x.n[k] * (2 * p + 1), TTIGA_E_ARG, "matvec: mode sizes differ");
+  for (int k = 0; k < 4; ++k) r[k] = K.r[k] * x.r[k];
+  y.alloc(ctx, n, r);
+  for (int k = 0; k < 3; ++k) {
+    const long total = (long)y.core_elems(k);
+    hipLaunchKernelGGL(k_matvec_banded, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n[k], p,
+                       K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].d(), x.c[k].d(), y.c[k].d());
+  }
+  TTIGA_HIP(hipGetLastError());
+}
+
+static void axpby_impl(Context& ctx, const double* ap, double a, const TT& x, const double* bp,
+                       double b, const TT& y, TT& out) {
+  if (x.zero() && y.zero()) { out.set_zero(x.n); return; }
+  if (x.zero() || y.zero()) {
+    const TT& s = x.zero() ? y : x;
+    const double* sp = x.zero() ? bp : ap;
+    const double sv = x.zero() ? b : a;
+    out.alloc(ctx, s.n, s.r);
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(s.core_elems(0))), dim3(256), 0, ctx.stream,
+                       s.c[0].d(), (long)s.core_elems(0), sp, sv, out.c[0].d());
+    for (int k = 1; k < 3; ++k) copy(ctx, out.c[k].d(), s.c[k].d(), s.core_elems(k));
+    TTIGA_HIP(hipGetLastError());
+    return;
+  }
+  for (int k = 0; k < 3; ++k) TTIGA_CHECK(x.n[k] == y.n[k], TTIGA_E_ARG, "axpby: mode sizes differ");
+  int r[4] = {1, x.r[1] + y.r[1], x.r[2] + y.r[2], 1};
+  out.alloc(ctx, x.n, r);
+  for (int k = 0; k < 3; ++k) {
+    const long total = (long)out.core_elems(k);
+    hipLaunchKernelGGL(k_axpby_core, dim3(grid_for(total)), dim3(256), 0, ctx.stream, k, 3, x.n[k],
+                       x.r[k], x.r[k + 1], y.r[k], y.r[k + 1], x.c[k].d(), y.c[k].d(), ap, a, bp, b,
+                       out.c[k].d());
+  }
+  TTIGA_HIP(hipGetLastError());
+}
+
+void tt_axpby(Context& ctx, double alpha, const TT& x, double beta, const TT& y, TT& out) {
+  axpby_impl(ctx, nullptr, alpha, x, nullptr, beta, y, out);
+}
+
+void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* beta, const TT& y,
+                  TT& out) {
+  axpby_impl(ctx, alpha, 0.0, x, beta, 0.0, y, out);
+}
+
+void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev) {
+  if (x.zero() || y.zero()) { fill(ctx, out_dev, 1, 0.0); return; }
+  // L_k (rx_k x ry_k); L_0 = [1].
+  DBuf L(&ctx.alloc, sizeof(double));
+  fill(ctx, L.d(), 1, 1.0);
+  for (int k = 0; k < 3; ++k) {
+    const int rx0 = x.r[k], rx1 = x.r[k + 1], ry0 = y.r[k], ry1 = y.r[k + 1], n = x.n[k];
+    // T[b][i][a'] = sum_a L[a][b] x[a][i][a']   : (ry0 x rx0)^T-view * (rx0 x n rx1)
+    DBuf T(&ctx.alloc, sizeof(double) * (size_t)ry0 * n * rx1);
+    gemm(ctx, true, false, ry0, n * rx1, rx0, 1.0, L.d(), ry0, 0, x.c[k].d(), (long)n * rx1, 0, 0.0,
+         T.d(), (long)n * rx1, 0);
+    // L'[a'][b'] = sum_{b,i} T[(b i)][a'] y[(b i)][b']
+    DBuf Ln(&ctx.alloc, sizeof(double) * (size_t)rx1 * ry1);
+    gemm(ctx, true, false, rx1, ry1, ry0 * n, 1.0, T.d(), rx1, 0, y.c[k].d(), ry1, 0, 0.0, Ln.d(),
+         ry1, 0);
+    L = std::move(Ln);
+  }
+  copy(ctx, out_dev, L.d(), 1);
+}
+
+double tt_dot_sync(Context& ctx, const TT& x, const TT& y) {
+  DBuf o(&ctx.alloc, sizeof(double));
+  tt_dot_dev(ctx, x, y, o.d());
+  double* h = ctx.host(1);
+  TTIGA_HIP(hipMemcpyAsync(h, o.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  return h[0];
+}
+
+// Truncated SVD of B (r x M, row-major): B ~= U_s diag(S_s) Vt_s with orthonormal U_s
+// (r x s) and orthonormal rows Vt_s (s x M).  The rank is chosen by trunc_rank_sync:
+// delta >= 0 is an absolute threshold, delta < 0 means relative eps = -delta.
+struct TruncSVD {
+  int s = 0;
+  DBuf U, S, Vt;
+  double norm = 0.0, delta = 0.0;
+};
+
+static TruncSVD truncated_svd(Context& ctx, const double* B, int r, long M, double delta) {
+  TruncSVD o;
+  if (M >= r) {
+    // B^T = Q T (M x r), B = T^T Q^T, svd(T^T) = Ut S W^T, so B = Ut S (Q W)^T
+    DBuf Q(&ctx.alloc, sizeof(double) * M * r), T(&ctx.alloc, sizeof(double) * r * r);
+    qr_tall(ctx, B, true, (int)M, r, M, Q.d(), T.d());
+    DBuf Ut(&ctx.alloc, sizeof(double) * r * r), W(&ctx.alloc, sizeof(double) * r * r);
+    o.S = DBuf(&ctx.alloc, sizeof(double) * r);
+    svd_small(ctx, T.d(), true, r, r, r, Ut.d(), o.S.d(), W.d());
+    double nd[2];
+    o.s = trunc_rank_sync(ctx, o.S.d(), r, delta, nd);
+    o.norm = nd[0];
+    o.delta = nd[1];
+    if (o.s == 0) return o;
+    o.Vt = DBuf(&ctx.alloc, sizeof(double) * o.s * M);
+    gemm(ctx, true, true, o.s, (int)M, r, 1.0, W.d(), r, 0, Q.d(), r, 0, 0.0, o.Vt.d(), M, 0);
+    o.U = DBuf(&ctx.alloc, sizeof(double) * r * o.s);
+    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long)r * o.s)), dim3(256), 0, ctx.stream, Ut.d(),
+                       r, r, o.s, o.U.d());
+  } else {
+    // tall: B = Q T (r x M), svd(T) = Ut S V^T, so B = (Q Ut) S V^T
+    const int c = (int)M;
+    DBuf Q(&ctx.alloc, sizeof(double) * (size_t)r * c), T(&ctx.alloc, sizeof(double) * c * c);
+    qr_tall(ctx, B, false, r, c, c, Q.d(), T.d());
+    DBuf Ut(&ctx.alloc, sizeof(double) * c * c), V(&ctx.alloc, sizeof(double) * c * c);
+    o.S = DBuf(&ctx.alloc, sizeof(double) * c);
+    svd_small(ctx, T.d(), false, c, c, c, Ut.d(), o.S.d(), V.d());
+    double nd[2];
+    o.s = trunc_rank_sync(ctx, o.S.d(), c, delta, nd);
+    o.norm = nd[0];
+    o.delta = nd[1];
+    if (o.s == 0) return o;
+    o.U = DBuf(&ctx.alloc, sizeof(double) * (size_t)r * o.s);
+    gemm(ctx, false, false, r, o.s, c, 1.0, Q.d(), c, 0, Ut.d(), c, 0, 0.0, o.U.d(), o.s, 0);
+    o.Vt = DBuf(&ctx.alloc, sizeof(double) * o.s * M);
+    hipLaunchKernelGGL(k_transpose_cols, dim3(grid_for((long)c * o.s)), dim3(256), 0, ctx.stream,
+                       V.d(), c, c, o.s, o.Vt.d());
+  }
+  TTIGA_HIP(hipGetLastError());
+  return o;
+}
+
+void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_rank,
+              double* norm_out) {
+  if (x.zero()) {
+    if (norm_out) norm_out[0] = 0.0;
+    return;
+  }
+  // Phase 1: left-orthogonalise cores 0 and 1 (QR of the (r_k n_k) x r_{k+1} unfoldings).
+  for (int k = 0; k < 2; ++k) {
+    const int m = x.r[k] * x.n[k], c = x.r[k + 1];
+    const int nn = x.n[k + 1], r2 = x.r[k + 2];
+    if (m >= c) {
+      DBuf Q(&ctx.alloc, sizeof(double) * (size_t)m * c), R(&ctx.alloc, sizeof(double) * c * c);
+      qr_tall(ctx, x.c[k].d(), false, m, c, c, Q.d(), R.d());
+      DBuf nxt(&ctx.alloc, sizeof(double) * (size_t)c * nn * r2);
+      gemm(ctx, false, false, c, nn * r2, c, 1.0, R.d(), c, 0, x.c[k + 1].d(), (long)nn * r2, 0, 0.0,
+           nxt.d(), (long)nn * r2, 0);
+      x.c[k] = std::move(Q);
+      x.c[k + 1] = std::move(nxt);
+    } else {
+      // wide unfolding: Q = I_m, R = the unfolding itself; the rank drops to m
+      DBuf nxt(&ctx.alloc, sizeof(double) * (size_t)m * nn * r2);
+      gemm(ctx, false, false, m, nn * r2, c, 1.0, x.c[k].d(), c, 0, x.c[k + 1].d(), (long)nn * r2, 0,
+           0.0, nxt.d(), (long)nn * r2, 0);
+      DBuf I(&ctx.alloc, sizeof(double) * (size_t)m * m);
+      hipLaunchKernelGGL(k_eye, dim3(grid_for((long)m * m)), dim3(256), 0, ctx.stream, m, I.d());
+      TTIGA_HIP(hipGetLastError());
+      x.c[k] = std::move(I);
+      x.c[k + 1] = std::move(nxt);
+      x.r[k + 1] = m;
+    }
+  }
+  // Phase 2: right-to-left truncated SVDs of the r_k x (n_k r_{k+1}) unfoldings; the
+  // whole norm sits in the last core, so the first SVD fixes the threshold.
+  double delta = delta_abs >= 0.0 ? delta_abs : -eps_rel;
+  for (int k = 2; k >= 1; --k) {
+    const int r = x.r[k];
+    const long M = (long)x.n[k] * x.r[k + 1];
+    TruncSVD t = truncated_svd(ctx, x.c[k].d(), r, M, delta);
+    if (k == 2) {
+      if (norm_out) norm_out[0] = t.norm;
+      delta = t.delta;
+    }
+    if (t.s == 0) {
+      x.set_zero(x.n);
+      return;
+    }
+    if (max_rank > 0 && t.s > max_rank)
+      throw Error(TTIGA_E_RANKCAP, "TT rank " + std::to_string(t.s) + " exceeds max_rank");
+    // core_{k-1} <- core_{k-1} * U_s S_s   ((r_{k-1} n_{k-1}) x r) * (r x s)
+    DBuf US(&ctx.alloc, sizeof(double) * r * t.s);
+    hipLaunchKernelGGL(k_scale_cols, dim3(grid_for((long)r * t.s)), dim3(256), 0, ctx.stream, t.U.d(),
+                       r, t.s, t.S.d(), t.s, US.d());
+    TTIGA_HIP(hipGetLastError());
+    const int mprev = x.r[k - 1] * x.n[k - 1];
+    DBuf prev(&ctx.alloc, sizeof(double) * (size_t)mprev * t.s);
+    gemm(ctx, false, false, mprev, t.s, r, 1.0, x.c[k - 1].d(), r, 0, US.d(), t.s, 0, 0.0, prev.d(),
+         t.s, 0);
+    x.c[k] = std::move(t.Vt);
+    x.c[k - 1] = std::move(prev);
+    x.r[k] = t.s;
+  }
+}
+
+// Left factor of an (m x M) row-major matrix A to the absolute threshold delta:
+// A ~= U (m x s, orthonormal columns) * C (s x M).  Exact SVD when min(m, M) <= kExact,
+// otherwise a randomised range finder: Y = A * Omega with Gaussian Omega (M x l),
+// U_y = orth(Y), B = U_y^T A, truncated SVD of B; the sketch width l starts at 48
+// and doubles while the truncated rank leaves fewer than 12 spare columns.
+static constexpr int kExact = 64;
+
+static int left_factor(Context& ctx, const double* A, int m, long M, double delta, DBuf& U,
+                       DBuf& C) {
+  if (m <= kExact || M <= kExact) {
+    TruncSVD t = truncated_svd(ctx, A, m, M, delta);
+    if (t.s == 0) return 0;
+    U = std::move(t.U);
+    C = DBuf(&ctx.alloc, sizeof(double) * t.s * M);
+    hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)t.s * M)), dim3(256), 0, ctx.stream,
+                       t.Vt.d(), t.s, M, t.S.d(), C.d());
+    TTIGA_HIP(hipGetLastError());
+    return t.s;
+  }
+  int l = std::min(m, 48);
+  while (true) {
+    DBuf Om(&ctx.alloc, sizeof(double) * M * l), Y(&ctx.alloc, sizeof(double) * (size_t)m * l);
+    const uint64_t seed = ++ctx.rng_counter;
+    hipLaunchKernelGGL(k_gaussian, dim3(grid_for(M * l)), dim3(256), 0, ctx.stream, Om.d(), M * l,
+                       seed);
+    TTIGA_HIP(hipGetLastError());
+    gemm(ctx, false, false, m, l, (int)M, 1.0, A, M, 0, Om.d(), l, 0, 0.0, Y.d(), l, 0);
+    DBuf Qy(&ctx.alloc, sizeof(double) * (size_t)m * l), Ry(&ctx.alloc, sizeof(double) * l * l);
+    qr_tall(ctx, Y.d(), false, m, l, l, Qy.d(), Ry.d());
+    DBuf B(&ctx.alloc, sizeof(double) * l * M);
+    gemm(ctx, true, false, l, (int)M, m, 1.0, Qy.d(), l, 0, A, M, 0, 0.0, B.d(), M, 0);
+    TruncSVD t = truncated_svd(ctx, B.d(), l, M, delta);
+    if (t.s == 0) return 0;
+    if (t.s > l - 12 && l < m) {
+      l = std::min(m, 2 * l);
+      continue;
+    }
+    U = DBuf(&ctx.alloc, sizeof(double) * (size_t)m * t.s);
+    gemm(ctx, false, false, m, t.s, l, 1.0, Qy.d(), l, 0, t.U.d(), t.s, 0, 0.0, U.d(), t.s, 0);
+    C = DBuf(&ctx.alloc, sizeof(double) * t.s * M);
+    hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)t.s * M)), dim3(256), 0, ctx.stream,
+                       t.Vt.d(), t.s, M, t.S.d(), C.d());
+    TTIGA_HIP(hipGetLastError());
+    return t.s;
+  }
+}
+
+// TT-SVD (Oseledets 2011, Alg. 1) of a dense device tensor A[n0][n1][n2] with an
+// absolute per-unfolding threshold delta: A_(0) = U0 C0, then C0 reshaped
+// (s0 n1) x n2 = U1 C1; cores U0, U1 (left-orthonormal) and C1.
+void tt_compress_dense(Context& ctx, const double* A, const int* n, double delta, TT& out,
+                       int max_rank) {
+  DBuf U0, C0;
+  const long M0 = (long)n[1] * n[2];
+  const int s0 = left_factor(ctx, A, n[0], M0, delta, U0, C0);
+  if (s0 == 0) { out.set_zero(n); return; }
+  DBuf U1, C1;
+  const int s1 = left_factor(ctx, C0.d(), s0 * n[1], n[2], delta, U1, C1);
+  if (s1 == 0) { out.set_zero(n); return; }
+  if (max_rank > 0 && (s0 > max_rank || s1 > max_rank))
+    throw Error(TTIGA_E_RANKCAP, "compressed factor rank exceeds max_rank");
+  for (int k = 0; k < 3; ++k) out.n[k] = n[k];
+  out.r[0] = 1; out.r[1] = s0; out.r[2] = s1; out.r[3] = 1;
+  out.c[0] = std::move(U0);
+  out.c[1] = std::move(U1);
+  out.c[2] = std::move(C1);
+}
+
+}  // namespace ttiga

@@ -1,0 +1,388 @@
+"""ctypes binding of libttiga.so (the C ABI in include/ttiga.h).
+
+Argument marshalling only: every step of assembly and solve runs in the
+library's HIP kernels.  PyTorch provides device memory (workspace and operand
+buffers) and the stream; nothing here computes on the CPU.  Loading fails
+loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttiga.so")
+
+TTIGA_OK = 0
+TTIGA_PENDING = 1
+TTIGA_E_ARG = -1
+TTIGA_E_KNOTS = -2
+TTIGA_E_GEOM = -3
+TTIGA_E_DETJ = -4
+TTIGA_E_OOM = -5
+TTIGA_E_ADMISSION = -6
+TTIGA_E_NOTCONV = -7
+TTIGA_E_RANKCAP = -8
+TTIGA_E_STATE = -9
+TTIGA_E_HIP = -10
+
+WHICH_K, WHICH_F, WHICH_KII, WHICH_RHS, WHICH_FACTOR0 = 0, 1, 2, 3, 10
+
+EXPORTED = (
+    "ttiga_version", "ttiga_create", "ttiga_destroy", "ttiga_set_workspace", "ttiga_last_error",
+    "ttiga_validate", "ttiga_problem_create", "ttiga_problem_destroy", "ttiga_assemble", "ttiga_solve",
+    "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
+    "ttiga_sample_factors", "ttiga_tt_matvec", "ttiga_tt_round", "ttiga_tt_dot",
+    "ttiga_tt_compress", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free",
+)
+
+c_int_p = ctypes.POINTER(ctypes.c_int)
+c_dbl_p = ctypes.POINTER(ctypes.c_double)
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int * 3), ("n_ctrl", ctypes.c_int * 3),
+                ("knots", c_dbl_p * 3), ("ctrl_xyz", c_dbl_p), ("weights", c_dbl_p)]
+
+
+class Discretization(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int), ("n_basis", ctypes.c_int * 3), ("n_gauss", ctypes.c_int)]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n_modes", ctypes.c_int), ("a", c_dbl_p), ("k", c_dbl_p),
+                ("phi", c_dbl_p), ("origin", ctypes.c_double * 3), ("scale", ctypes.c_double)]
+
+
+class Dirichlet(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int * 6), ("value", ctypes.c_double * 6)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tt_eps", ctypes.c_double), ("rel_res_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("max_rank", ctypes.c_int),
+                ("precision", ctypes.c_int), ("precond", ctypes.c_int)]
+
+
+class AssemblyStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("rank_R", (ctypes.c_int * 4) * 6),
+                ("rank_fJ", ctypes.c_int * 4), ("rank_K", ctypes.c_int * 4),
+                ("rank_F", ctypes.c_int * 4), ("min_detJ", ctypes.c_double),
+                ("max_R_norm", ctypes.c_double), ("time_ms", ctypes.c_double * 4)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("rank_u", ctypes.c_int * 4), ("max_rank_seen", ctypes.c_int),
+                ("time_ms", ctypes.c_double)]
+
+
+class TTView(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("r", ctypes.c_int * 4), ("core", ctypes.c_void_p * 3)]
+
+
+class TTMView(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("p", ctypes.c_int), ("r", ctypes.c_int * 4),
+                ("core", ctypes.c_void_p * 3)]
+
+
+class TTIGAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ttiga error {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def load(path=LIB_PATH):
+    """Load libttiga.so and declare its signatures; raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with paper_2509_13224_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    sig = {
+        "ttiga_version": (ctypes.c_int, [c_int_p, c_int_p]),
+        "ttiga_create": (ctypes.c_int, [ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "ttiga_destroy": (ctypes.c_int, [vp]),
+        "ttiga_set_workspace": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+        "ttiga_last_error": (ctypes.c_char_p, []),
+        "ttiga_problem_create": (ctypes.c_int, [vp, ctypes.POINTER(Geometry), ctypes.POINTER(Discretization),
+                                                ctypes.POINTER(Source), ctypes.POINTER(Dirichlet),
+                                                ctypes.POINTER(Options), ctypes.POINTER(vp)]),
+        "ttiga_validate": (ctypes.c_int, [ctypes.POINTER(Geometry), ctypes.POINTER(Discretization),
+                                          ctypes.POINTER(Source), ctypes.POINTER(Dirichlet),
+                                          ctypes.POINTER(Options)]),
+        "ttiga_problem_destroy": (ctypes.c_int, [vp]),
+        "ttiga_assemble": (ctypes.c_int, [vp, ctypes.POINTER(AssemblyStats)]),
+        "ttiga_solve": (ctypes.c_int, [vp, ctypes.POINTER(SolveStats)]),
+        "ttiga_solution_ranks": (ctypes.c_int, [vp, c_int_p, c_int_p]),
+        "ttiga_get_solution": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t]),
+        "ttiga_problem_tt_info": (ctypes.c_int, [vp, ctypes.c_int, c_int_p, c_int_p, c_int_p]),
+        "ttiga_problem_tt_copy": (ctypes.c_int, [vp, ctypes.c_int, c_dbl_p, ctypes.c_size_t]),
+        "ttiga_sample_factors": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t, c_dbl_p, c_dbl_p]),
+        "ttiga_tt_matvec": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView),
+                                           ctypes.POINTER(vp)]),
+        "ttiga_tt_round": (ctypes.c_int, [vp, ctypes.POINTER(TTView), ctypes.c_double, ctypes.POINTER(vp)]),
+        "ttiga_tt_dot": (ctypes.c_int, [vp, ctypes.POINTER(TTView), ctypes.POINTER(TTView), c_dbl_p]),
+        "ttiga_tt_compress": (ctypes.c_int, [vp, vp, c_int_p, ctypes.c_double, ctypes.POINTER(vp)]),
+        "ttiga_tt_info": (ctypes.c_int, [vp, c_int_p, c_int_p]),
+        "ttiga_tt_copy": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t]),
+        "ttiga_tt_free": (ctypes.c_int, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(lib, code, ok=(TTIGA_OK,)):
+    if code not in ok:
+        raise TTIGAError(code, lib.ttiga_last_error().decode())
+    return code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(c_dbl_p)
+
+
+def _ranks_of(cores):
+    return [1, cores[0].shape[-1], cores[1].shape[-1], 1]
+
+
+def split_cores(flat, n, r, band=1):
+    """Concatenated paper-order cores -> list of arrays [r_k][n_k][(band)][r_{k+1}]."""
+    out, off = [], 0
+    for k in range(3):
+        cnt = r[k] * n[k] * band * r[k + 1]
+        shape = (r[k], n[k], band, r[k + 1]) if band > 1 else (r[k], n[k], r[k + 1])
+        out.append(np.asarray(flat[off:off + cnt]).reshape(shape))
+        off += cnt
+    return out
+
+
+class Context:
+    """ttiga_create on a device and stream (default: torch's current stream on cuda:0).
+
+    The library sub-allocates everything from one torch-owned device buffer of
+    ``workspace_bytes`` (default 1 GiB); 0 lets the library allocate by itself.
+    """
+
+    def __init__(self, device=0, stream=None, workspace_bytes=1 << 30):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.ttiga_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        self._ws = None
+        if workspace_bytes:
+            self._ws = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+            _check(self.lib, self.lib.ttiga_set_workspace(self.h, ctypes.c_void_p(self._ws.data_ptr()),
+                                                          ctypes.c_size_t(self._ws.numel())))
+
+    def close(self):
+        if self.h:
+            self.lib.ttiga_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- problems
+    def problem_create(self, pr, precond=0):
+        return ProblemHandle(self, pr, precond)
+
+    # ---------------------------------------------------------------- standalone ops
+    def _view(self, cores_dev):
+        v = TTView()
+        for k in range(3):
+            v.n[k] = cores_dev[k].shape[1]
+            v.core[k] = cores_dev[k].data_ptr()
+        r = _ranks_of(cores_dev)
+        for k in range(4):
+            v.r[k] = r[k]
+        return v
+
+    def _take(self, handle):
+        r = (ctypes.c_int * 4)()
+        n = (ctypes.c_int * 3)()
+        _check(self.lib, self.lib.ttiga_tt_info(handle, r, n))
+        r, n = list(r), list(n)
+        total = sum(r[k] * n[k] * r[k + 1] for k in range(3))
+        flat = np.zeros(max(total, 1))
+        _check(self.lib, self.lib.ttiga_tt_copy(handle, _dptr(flat), ctypes.c_size_t(flat.size)))
+        self.lib.ttiga_tt_free(handle)
+        if r[1] == 0:
+            return None
+        return split_cores(flat, n, r)
+
+    def tt_matvec(self, K_cores_dev, p, x_cores_dev):
+        """y = K x; K banded cores [r][n][2p+1][r'] and x cores [r][n][r'] as device tensors."""
+        kv = TTMView()
+        kv.p = p
+        rK = [1, K_cores_dev[0].shape[-1], K_cores_dev[1].shape[-1], 1]
+        for k in range(3):
+            kv.n[k] = K_cores_dev[k].shape[1]
+            kv.core[k] = K_cores_dev[k].data_ptr()
+        for k in range(4):
+            kv.r[k] = rK[k]
+        xv = self._view(x_cores_dev)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.ttiga_tt_matvec(self.h, ctypes.byref(kv), ctypes.byref(xv), ctypes.byref(h)))
+        return self._take(h)
+
+    def tt_round(self, cores_dev, eps):
+        v = self._view(cores_dev)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.ttiga_tt_round(self.h, ctypes.byref(v), ctypes.c_double(eps), ctypes.byref(h)))
+        return self._take(h)
+
+    def tt_dot(self, x_dev, y_dev):
+        a, b = self._view(x_dev), self._view(y_dev)
+        out = ctypes.c_double()
+        _check(self.lib, self.lib.ttiga_tt_dot(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(out)))
+        return out.value
+
+    def tt_compress(self, A_dev, delta):
+        n = (ctypes.c_int * 3)(*A_dev.shape)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.ttiga_tt_compress(self.h, ctypes.c_void_p(A_dev.data_ptr()), n,
+                                                    ctypes.c_double(delta), ctypes.byref(h)))
+        return self._take(h)
+
+
+def describe(pr, precond=0):
+    """ctypes structs of a workloads.Problem; returns (structs tuple, keep-alive list)."""
+    geo = pr.geometry
+    keep = []
+
+    def arr(x):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        keep.append(a)
+        return a
+
+    g = Geometry()
+    for d in range(3):
+        g.degree[d] = int(geo.degree[d])
+        g.n_ctrl[d] = int(geo.ctrl.shape[d])
+        g.knots[d] = _dptr(arr(geo.knots[d]))
+    g.ctrl_xyz = _dptr(arr(geo.ctrl))
+    g.weights = _dptr(arr(geo.weights)) if geo.weights is not None else None
+    disc = Discretization()
+    disc.degree = int(pr.disc.degree)
+    for d in range(3):
+        disc.n_basis[d] = int(pr.disc.n_basis[d])
+    disc.n_gauss = int(pr.disc.n_gauss)
+    src = Source()
+    src.kind = int(pr.source.kind)
+    src.n_modes = int(len(pr.source.a))
+    src.a = _dptr(arr(pr.source.a))
+    src.k = _dptr(arr(np.asarray(pr.source.k).reshape(-1, 3)))
+    src.phi = _dptr(arr(pr.source.phi))
+    for d in range(3):
+        src.origin[d] = float(pr.source.origin[d])
+    src.scale = float(pr.source.scale)
+    bc = Dirichlet()
+    for f in range(6):
+        bc.kind[f] = int(pr.dirichlet.kind[f])
+        bc.value[f] = float(pr.dirichlet.value[f])
+    o = Options()
+    o.tt_eps = pr.options.tt_eps
+    o.rel_res_tol = pr.options.rel_res_tol
+    o.max_iter = pr.options.max_iter
+    o.max_rank = pr.options.max_rank
+    o.precision = pr.options.precision
+    o.precond = precond
+    return (g, disc, src, bc, o), keep
+
+
+def validate(pr, precond=0):
+    """ttiga_validate: host-only status of a description (0 = acceptable)."""
+    lib = load()
+    (g, disc, src, bc, o), keep = describe(pr, precond)
+    code = lib.ttiga_validate(ctypes.byref(g), ctypes.byref(disc), ctypes.byref(src), ctypes.byref(bc),
+                              ctypes.byref(o))
+    return code, lib.ttiga_last_error().decode()
+
+
+class ProblemHandle:
+    """ttiga_problem_create from a workloads.Problem description."""
+
+    def __init__(self, ctx, pr, precond=0):
+        self.ctx, self.lib = ctx, ctx.lib
+        (g, disc, src, bc, o), keep = describe(pr, precond)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.ttiga_problem_create(ctx.h, ctypes.byref(g), ctypes.byref(disc), ctypes.byref(src),
+                                                       ctypes.byref(bc), ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.ttiga_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def assemble(self):
+        st = AssemblyStats()
+        _check(self.lib, self.lib.ttiga_assemble(self.h, ctypes.byref(st)))
+        return dict(rank_R=[list(r) for r in st.rank_R], rank_fJ=list(st.rank_fJ), rank_K=list(st.rank_K),
+                    rank_F=list(st.rank_F), min_detJ=st.min_detJ, max_R_norm=st.max_R_norm,
+                    time_ms=list(st.time_ms))
+
+    def solve(self, allow_notconv=False):
+        st = SolveStats()
+        ok = (TTIGA_OK, TTIGA_E_NOTCONV) if allow_notconv else (TTIGA_OK,)
+        code = _check(self.lib, self.lib.ttiga_solve(self.h, ctypes.byref(st)), ok)
+        return dict(status=code, iterations=st.iterations, rel_res=st.rel_res, rank_u=list(st.rank_u),
+                    max_rank_seen=st.max_rank_seen, time_ms=st.time_ms)
+
+    def solution(self):
+        r = (ctypes.c_int * 4)()
+        n = (ctypes.c_int * 3)()
+        _check(self.lib, self.lib.ttiga_solution_ranks(self.h, r, n))
+        r, n = list(r), list(n)
+        total = sum(r[k] * n[k] * r[k + 1] for k in range(3))
+        flat = np.zeros(max(total, 1))
+        _check(self.lib, self.lib.ttiga_get_solution(self.h, _dptr(flat), ctypes.c_size_t(flat.size)))
+        if r[1] == 0:
+            return None
+        return split_cores(flat, n, r)
+
+    def tt(self, which):
+        r = (ctypes.c_int * 4)()
+        n = (ctypes.c_int * 3)()
+        band = ctypes.c_int()
+        _check(self.lib, self.lib.ttiga_problem_tt_info(self.h, which, r, n, ctypes.byref(band)))
+        r, n, band = list(r), list(n), band.value
+        total = sum(r[k] * n[k] * band * r[k + 1] for k in range(3))
+        flat = np.zeros(max(total, 1))
+        _check(self.lib, self.lib.ttiga_problem_tt_copy(self.h, which, _dptr(flat), ctypes.c_size_t(flat.size)))
+        if r[1] == 0:
+            return None
+        return split_cores(flat, n, r, band)
+
+    def sample_factors(self, pts):
+        pts = np.ascontiguousarray(np.asarray(pts, dtype=np.float64))
+        count = pts.shape[0]
+        out = np.zeros((7, count))
+        det = np.zeros(count)
+        _check(self.lib, self.lib.ttiga_sample_factors(self.h, _dptr(pts), ctypes.c_size_t(count), _dptr(out), _dptr(det)))
+        return out, det

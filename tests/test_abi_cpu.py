@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol, and
+validates problem descriptions without touching a GPU."""
+import copy
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2509_13224_amd import ttiga
+from workloads.problem import BC_CONSTANT, BC_NATURAL, Dirichlet
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ttiga.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(ttiga_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_matches_binding_list():
+    assert declared_functions() == sorted(ttiga.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ttiga.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version():
+    import ctypes
+    lib = ttiga.load()
+    a, b = ctypes.c_int(), ctypes.c_int()
+    assert lib.ttiga_version(ctypes.byref(a), ctypes.byref(b)) == 0
+    assert (a.value, b.value) == (0, 1)
+
+
+def test_validate_accepts_workloads():
+    for pr in (W.c1_problem(), W.c2_problem(n=64), W.c3_problem(n=64, precision=0)):
+        assert ttiga.validate(pr)[0] == 0, pr.name
+    for pr in W.c4_requests(6, precision=0):
+        assert ttiga.validate(pr)[0] == 0, pr.name
+
+
+def _bad(mutate):
+    pr = copy.deepcopy(W.c1_problem())
+    mutate(pr)
+    return ttiga.validate(pr)
+
+
+def test_validate_rejects_bad_knots():
+    def nonmono(pr):
+        pr.geometry.knots[1] = np.array([0, 0, 0.5, 0.2, 1, 1.0])
+    assert _bad(nonmono)[0] == ttiga.TTIGA_E_KNOTS
+
+    def short_mult(pr):
+        pr.geometry.knots[1] = np.array([0, 0, 0.5, 1, 1, 1.0])
+    assert _bad(short_mult)[0] == ttiga.TTIGA_E_KNOTS
+
+    def not_unit(pr):
+        pr.geometry.knots[2] = np.array([0, 0, 2, 2.0])
+    assert _bad(not_unit)[0] == ttiga.TTIGA_E_KNOTS
+
+    def too_few_ctrl(pr):
+        pr.geometry.ctrl = pr.geometry.ctrl[:, :2]
+        pr.geometry.weights = pr.geometry.weights[:, :2]
+    assert _bad(too_few_ctrl)[0] == ttiga.TTIGA_E_ARG
+
+
+def test_validate_rejects_nonpositive_weight():
+    def neg(pr):
+        pr.geometry.weights = pr.geometry.weights.copy()
+        pr.geometry.weights[0, 1, 0] = -0.5
+    assert _bad(neg)[0] == ttiga.TTIGA_E_GEOM
+
+
+def test_validate_rejects_bad_discretisation_and_options():
+    def small_n(pr):
+        pr.disc.n_basis = (2, 16, 16)
+    assert _bad(small_n)[0] == ttiga.TTIGA_E_ARG
+
+    def bad_eps(pr):
+        pr.options.tt_eps = 0.0
+    assert _bad(bad_eps)[0] == ttiga.TTIGA_E_ARG
+
+    def bad_prec(pr):
+        pr.options.precision = 7
+    assert _bad(bad_prec)[0] == ttiga.TTIGA_E_ARG
+
+
+def test_validate_constant_dirichlet_rules():
+    geo = W.annulus_sector(0.5, 1.0, math.pi / 2, 1.0)
+    ok = Dirichlet(kind=(BC_CONSTANT, BC_CONSTANT) + (BC_NATURAL,) * 4, value=(1.0, 2.0, 0, 0, 0, 0))
+    assert ttiga.validate(W.small_problem(geo, 8, 2, W.zero_source(), dirichlet=ok))[0] == 0
+    two_dirs = Dirichlet(kind=(BC_CONSTANT,) * 2 + (BC_CONSTANT,) + (BC_NATURAL,) * 3,
+                         value=(1.0, 2.0, 3.0, 0, 0, 0))
+    code, msg = ttiga.validate(W.small_problem(geo, 8, 2, W.zero_source(), dirichlet=two_dirs))
+    assert code == ttiga.TTIGA_E_ARG and "more than one direction" in msg

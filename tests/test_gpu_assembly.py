@@ -1,0 +1,116 @@
+"""GPU parity of the assembly path (basis tables, geometry factors, TT compression, TT cores of
+K and F, boundary reduction) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry, sparse_iga, tt, tt_iga
+from tests.gpu_helpers import banded_to_dense_cores, say
+from workloads.problem import BC_CONSTANT, BC_NATURAL, Dirichlet
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    from paper_2509_13224_amd import ttiga
+    return ttiga.Context()
+
+
+CASES = {
+    "annulus_c1": lambda: W.c1_problem(),
+    "twisted_p3_n9": lambda: W.small_problem(W.twisted_box(1.2), 9, 3, W.fourier_source(W.twisted_box(1.2), 5),
+                                             eps=1e-10),
+    "bumpy_p2_n7": lambda: W.small_problem(W.bumpy_cube(), 7, 2, W.fourier_source(W.bumpy_cube(), 9), eps=1e-8),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_factors_at_points(ctx, name):
+    """Every R_ij and f det J sample within 1e-13 relative of the oracle (scattered points)."""
+    say("factors", name)
+    pr = CASES[name]()
+    h = ctx.problem_create(pr)
+    rng = np.random.default_rng(3)
+    pts = np.concatenate([rng.uniform(0, 1, size=(500, 3)),
+                          np.array([[0, 0, 0], [1, 1, 1], [0, 1, 0.5], [1, 0, 0.25]])])
+    got, det = h.sample_factors(pts)
+    ref, dref = geometry.sample_factors_points(pr, pts)
+    scale = np.max(np.abs(ref[:6]))
+    assert np.max(np.abs(got[:6] - ref[:6])) <= 1e-13 * scale
+    assert np.max(np.abs(got[6] - ref[6])) <= 1e-13 * max(np.max(np.abs(ref[6])), 1e-300)
+    assert np.max(np.abs(det - dref)) <= 1e-13 * np.max(np.abs(dref))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_assembled_operator_and_load(ctx, name):
+    say("assemble", name)
+    pr = CASES[name]()
+    eps = pr.options.tt_eps
+    h = ctx.problem_create(pr)
+    st = h.assemble()
+    K_sp, F_sp = sparse_iga.assemble(pr)
+    p = pr.disc.degree
+    Kd = K_sp.toarray()
+    KT = banded_to_dense_cores(h.tt(0), p)
+    tol_K = max(1e-12, 10 * eps)
+    assert np.linalg.norm(tt.mat_full(KT) - Kd) <= tol_K * np.linalg.norm(Kd)
+    FT = h.tt(1)
+    assert np.linalg.norm(tt.full(FT).ravel() - F_sp) <= max(1e-12, 10 * eps) * np.linalg.norm(F_sp)
+    # reduced system equals the oracle's reduced system
+    Ko = tt_iga.assemble_K(pr, tt_iga.factor_tts(pr)[0])
+    Fo = tt_iga.assemble_F(pr, tt_iga.factor_tts(pr)[1])
+    KIIo, rhso = tt_iga.reduce_system(pr, Ko, Fo)
+    KII = banded_to_dense_cores(h.tt(2), p)
+    ref = tt.mat_full(KIIo)
+    assert np.linalg.norm(tt.mat_full(KII) - ref) <= tol_K * np.linalg.norm(ref)
+    rhs = h.tt(3)
+    assert np.linalg.norm(tt.full(rhs) - tt.full(rhso)) <= max(1e-12, 10 * eps) * np.linalg.norm(tt.full(rhso))
+    assert st["min_detJ"] > 0
+
+
+def test_annulus_ranks_exact(ctx):
+    """Quarter annulus: R_ii rank (1,1), R_ij (i != j) rank 0, f det J rank (1,1), K ranks (3,2)."""
+    say("annulus ranks")
+    h = ctx.problem_create(W.c1_problem())
+    st = h.assemble()
+    assert st["rank_R"][:3] == [[1, 1, 1, 1]] * 3
+    assert st["rank_R"][3:] == [[0, 0, 0, 0]] * 3
+    assert st["rank_fJ"] == [1, 1, 1, 1]
+    assert st["rank_K"] == [1, 3, 2, 1]
+
+
+def test_constant_dirichlet_lifting(ctx):
+    say("lifting ring")
+    geo = W.annulus_sector(0.5, 1.0, math.pi / 2, 1.0)
+    bc = Dirichlet(kind=(BC_CONSTANT, BC_CONSTANT) + (BC_NATURAL,) * 4, value=(1.0, 2.0, 0, 0, 0, 0))
+    pr = W.small_problem(geo, 8, 2, W.zero_source(), dirichlet=bc, eps=1e-12, tol=1e-12)
+    h = ctx.problem_create(pr)
+    h.assemble()
+    Ko = tt_iga.assemble_K(pr, tt_iga.factor_tts(pr)[0])
+    _, rhso = tt_iga.reduce_system(pr, Ko, None)
+    rhs = h.tt(3)
+    ref = tt.full(rhso)
+    assert np.linalg.norm(tt.full(rhs) - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_folded_geometry_reports_detj(ctx):
+    from paper_2509_13224_amd import ttiga
+    say("folded")
+    geo = W.twisted_box(0.3)
+    geo.ctrl = geo.ctrl.copy()
+    geo.ctrl[..., 0] *= -1.0  # mirror: det J < 0 everywhere
+    h = ctx.problem_create(W.small_problem(geo, 6, 2, W.zero_source()))
+    with pytest.raises(ttiga.TTIGAError) as e:
+        h.assemble()
+    assert e.value.code == ttiga.TTIGA_E_DETJ
+
+
+def test_solve_before_assemble_is_state_error(ctx):
+    from paper_2509_13224_amd import ttiga
+    h = ctx.problem_create(W.c1_problem(n=6))
+    with pytest.raises(ttiga.TTIGAError) as e:
+        h.solve()
+    assert e.value.code == ttiga.TTIGA_E_STATE
