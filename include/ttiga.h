@@ -116,7 +116,9 @@ typedef struct {
 
 typedef struct {
   double tt_eps;      /* TT tolerance of compression and rounding */
-  double rel_res_tol; /* stop when ||F_I - K_II u||_2 <= tol ||F_I||_2 */
+  double rel_res_tol; /* plain TT-CG: stop when ||F_I - K_II u||_2 <= tol ||F_I||_2;
+                         with precond: when ||P^-1 (F_I - K_II u)||_2 <= tol ||u||_2, an
+                         estimate of the relative error of u (P^-1 K is near the identity) */
   int max_iter;
   int max_rank;       /* cap on every TT rank; exceeding it fails with E_RANKCAP */
   int precision;      /* TTIGA_FP64 (others: E_ARG in this version) */
@@ -138,8 +140,11 @@ typedef struct {
   int status;
   int iterations;
   double rel_res;    /* true ||F_I - K_II u|| / ||F_I|| of the returned solution */
+  double rel_pres;   /* ||P^-1 r|| / ||u||, the error estimate of the stopping test (precond only) */
   int rank_u[4];
   int max_rank_seen;
+  int precond_terms; /* exponential-sum terms of the preconditioner (0: none) */
+  double precond_err;/* max relative error of that sum on the spectrum interval */
   double time_ms;
 } ttiga_solve_stats;
 
@@ -235,6 +240,23 @@ int ttiga_tt_dot(ttiga_ctx* ctx, const ttiga_tt_view* x, const ttiga_tt_view* y,
 /* TT-SVD of a dense device tensor A[n0][n1][n2] with absolute per-unfolding
  * threshold delta (randomised range finder above 64 points per mode). */
 int ttiga_tt_compress(ttiga_ctx* ctx, const double* A, const int n[3], double delta, ttiga_tt** out);
+
+/* Per-kernel-class timing: HIP events recorded around each instrumented launch
+ * on the context stream, plus the algorithmic flops and bytes of the launch
+ * (operation counts of the method, not of any padding).  enable = 1 starts,
+ * 0 stops, -1 clears the counters. */
+typedef struct {
+  char name[32];
+  long launches;
+  double total_ms;
+  double flops;
+  double bytes;
+} ttiga_kernel_stat;
+
+int ttiga_profile(ttiga_ctx* ctx, int enable);
+
+/* Copies up to `capacity` entries; *count receives the number of kernel classes. */
+int ttiga_profile_read(ttiga_ctx* ctx, ttiga_kernel_stat* out, int capacity, int* count);
 
 int ttiga_tt_info(const ttiga_tt* t, int ranks[4], int n[3]);
 int ttiga_tt_copy(const ttiga_tt* t, double* dst, size_t count); /* to host, paper order */

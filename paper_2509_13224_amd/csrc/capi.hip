@@ -94,6 +94,61 @@ Context::~Context() {
   if (host_scratch) (void)hipHostFree(host_scratch);
 }
 
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  TTIGA_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Profiler::flush() {
+  for (auto& p : pending) {
+    TTIGA_HIP(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    TTIGA_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    KernelStat& k = stats[p.name];
+    k.launches += 1;
+    k.ms += ms;
+    k.flops += p.flops;
+    k.bytes += p.bytes;
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+Profiler::~Profiler() {
+  for (auto& p : pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Context& c, const char* name, double flops, double bytes)
+    : c_(&c), name_(name), flops_(flops), bytes_(bytes) {
+  if (!c.prof.on) return;
+  a_ = c.prof.get();
+  TTIGA_HIP(hipEventRecord(a_, c.stream));
+}
+
+ProfScope::~ProfScope() {
+  if (!a_) return;
+  hipEvent_t b = c_->prof.get();
+  if (hipEventRecord(b, c_->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    c_->prof.pool.push_back(b);
+    c_->prof.pool.push_back(a_);
+    return;
+  }
+  c_->prof.pending.push_back({name_, a_, b, flops_, bytes_});
+  if (c_->prof.pending.size() > 4096) c_->prof.flush();
+}
+
 double* Context::host(size_t n) {
   if (n > host_scratch_doubles) {
     if (host_scratch) TTIGA_HIP(hipHostFree(host_scratch));
@@ -390,6 +445,42 @@ int ttiga_tt_compress(ttiga_ctx* ctx, const double* A, const int n[3], double de
     }
     *out = res;
     ctx_retain(&c);
+  });
+}
+
+int ttiga_profile(ttiga_ctx* ctx, int enable) {
+  return guard([&] {
+    TTIGA_CHECK(ctx != nullptr, TTIGA_E_ARG, "null context");
+    Profiler& pr = ctx->impl.prof;
+    if (enable < 0) {  // reset
+      pr.flush();
+      pr.stats.clear();
+      return;
+    }
+    if (!enable) pr.flush();
+    pr.on = enable != 0;
+  });
+}
+
+int ttiga_profile_read(ttiga_ctx* ctx, ttiga_kernel_stat* out, int capacity, int* count) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && count, TTIGA_E_ARG, "null argument");
+    Profiler& pr = ctx->impl.prof;
+    pr.flush();
+    int i = 0;
+    for (auto& kv : pr.stats) {
+      if (out && i < capacity) {
+        ttiga_kernel_stat& o = out[i];
+        std::memset(&o, 0, sizeof(o));
+        std::strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+        o.launches = kv.second.launches;
+        o.total_ms = kv.second.ms;
+        o.flops = kv.second.flops;
+        o.bytes = kv.second.bytes;
+      }
+      ++i;
+    }
+    *count = i;
   });
 }
 

@@ -404,6 +404,12 @@ void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, 
   const long total = (long)Q[0] * Q[1] * Q[2];
   const long blocks = (total + 255) / 256;
   DBuf part(&ctx.alloc, sizeof(double) * 8 * blocks);
+  // per point: homogeneous map and its three derivatives over the (p_g+1)^3 local net
+  // (inner sums over the last direction first), the adjugate, det J, R and f det J;
+  // bytes: the seven factor values written (tables and net are cache-resident)
+  const double pg0 = geo.pg[0] + 1, pg1 = geo.pg[1] + 1, pg2 = geo.pg[2] + 1;
+  const double per_pt = pg0 * pg1 * (16.0 * pg2 + 35.0) + 150.0 + (double)src.n_modes * 10.0;
+  ProfScope prof(ctx, "geometry_factors", per_pt * total, 56.0 * total);
   hipLaunchKernelGGL(k_factors_grid, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, geo, src, Q[0],
                      Q[1], Q[2], F, part.d());
   hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks, stats8);
@@ -420,6 +426,7 @@ void launch_factors_points(Context& ctx, const GeoDev& geo, const SourceDev& src
 void launch_assemble_band(Context& ctx, int n, int p, int g, int ra, int rb, const double* G,
                           const double* w, const double* Brow, const double* Bcol, double* M) {
   const long total = (long)ra * n * (2 * p + 1) * rb;
+  ProfScope prof(ctx, "assemble_cores", 4.0 * total * (p + 1) * g, 8.0 * (total + (double)ra * rb * (n - p) * g));
   hipLaunchKernelGGL(k_assemble_band, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n, p, g, ra,
                      rb, G, w, Brow, Bcol, M);
   TTIGA_HIP(hipGetLastError());

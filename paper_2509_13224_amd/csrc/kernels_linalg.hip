@@ -137,6 +137,8 @@ void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, con
   splits = (K + kchunk - 1) / kchunk;
   DBuf part;
   if (splits > 1) part = DBuf(&ctx.alloc, sizeof(double) * (size_t)batch * splits * M * N);
+  ProfScope prof(ctx, "gemm_f64", 2.0 * M * N * (double)K * batch,
+                 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N));
   dim3 grid(tn, tm, batch * splits);
   dim3 block(256);
 #define TTIGA_GEMM_LAUNCH(TA, TB)                                                                 \
@@ -171,14 +173,17 @@ __device__ inline double wave_sum(double v) {
 }
 
 
-__global__ __launch_bounds__(256) void k_hh_factor(int m, int c, const double* __restrict__ A,
-                                                   long lda, int trans, int nb, int ldw,
-                                                   double* __restrict__ V,
-                                                   double* __restrict__ tau,
-                                                   double* __restrict__ Rout,
-                                                   double* __restrict__ gwork) {
+// Column k of the block belongs to wave k % nwaves for the whole factorisation,
+// so a reflector needs one barrier: the owner of column j forms v_j and tau_j,
+// then every wave applies H_j to the columns it owns.
+__global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* __restrict__ A,
+                                                    long lda, int trans, int nb, int ldw,
+                                                    double* __restrict__ V,
+                                                    double* __restrict__ tau,
+                                                    double* __restrict__ Rout,
+                                                    double* __restrict__ gwork) {
   extern __shared__ double smem[];
-  __shared__ double s_scale, s_tau;
+  __shared__ double s_tau[1024];
   const int blk = blockIdx.x;
   const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
   const int nr = (int)(r1 - r0);
@@ -194,42 +199,39 @@ __global__ __launch_bounds__(256) void k_hh_factor(int m, int c, const double* _
   __syncthreads();
   for (int j = 0; j < c; ++j) {
     double* wj = W + (long)j * ldw;
-    if (wave == 0) {
+    if (wave == j % nwaves) {
       double ss = 0.0;
       for (int i = j + 1 + lane; i < nr; i += 64) ss += wj[i] * wj[i];
       ss = wave_sum(ss);
+      const double alpha = wj[j];
+      double t = 0.0, sc = 0.0, beta = alpha;
+      if (ss != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+        t = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+      if (t != 0.0)
+        for (int i = j + 1 + lane; i < nr; i += 64) wj[i] *= sc;
       if (lane == 0) {
-        const double alpha = wj[j];
-        if (ss == 0.0) {
-          s_tau = 0.0;
-          s_scale = 0.0;
-        } else {
-          const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-          s_tau = (beta - alpha) / beta;
-          s_scale = 1.0 / (alpha - beta);
-          wj[j] = beta;
-        }
+        wj[j] = beta;
+        s_tau[j] = t;
       }
     }
     __syncthreads();
-    const double t = s_tau, sc = s_scale;
-    if (tid == 0) tau[(long)blk * c + j] = t;
-    if (t != 0.0) {
-      for (int i = j + 1 + tid; i < nr; i += blockDim.x) wj[i] *= sc;
-      __syncthreads();
-      for (int k = j + 1 + wave; k < c; k += nwaves) {
-        double* wk = W + (long)k * ldw;
-        double d = 0.0;
-        for (int i = j + 1 + lane; i < nr; i += 64) d += wj[i] * wk[i];
-        d = wave_sum(d) + wk[j];
-        const double f = t * d;
-        if (lane == 0) wk[j] -= f;
-        for (int i = j + 1 + lane; i < nr; i += 64) wk[i] -= f * wj[i];
-      }
+    const double t = s_tau[j];
+    if (t == 0.0) continue;
+    for (int k = j + 1 + ((wave - (j + 1) % nwaves + nwaves) % nwaves); k < c; k += nwaves) {
+      double* wk = W + (long)k * ldw;
+      double d = 0.0;
+      for (int i = j + 1 + lane; i < nr; i += 64) d += wj[i] * wk[i];
+      d = wave_sum(d) + wk[j];
+      const double f = t * d;
+      if (lane == 0) wk[j] -= f;
+      for (int i = j + 1 + lane; i < nr; i += 64) wk[i] -= f * wj[i];
     }
-    __syncthreads();
   }
-  // R (row j, column k >= j) and the reflectors, block-local column-major in V
+  __syncthreads();
+  for (int j = tid; j < c; j += blockDim.x) tau[(long)blk * c + j] = s_tau[j];
   for (long e = tid; e < (long)c * c; e += blockDim.x) {
     const int j = e / c, k = e % c;
     Rout[(long)blk * c * c + e] = (k >= j) ? W[(long)k * ldw + j] : 0.0;
@@ -242,33 +244,42 @@ __global__ __launch_bounds__(256) void k_hh_factor(int m, int c, const double* _
 }
 
 // Qout (m x c, row-major) = H_0 ... H_{c-1} [Qtop slice (c x c); 0] per block;
-// Qtop == nullptr stands for the identity (the root of the tree).
-__global__ __launch_bounds__(256) void k_hh_apply(int m, int c, int nb, int ldw,
-                                                  const double* __restrict__ V,
-                                                  const double* __restrict__ tau,
-                                                  const double* __restrict__ Qtop,
-                                                  double* __restrict__ Qout,
-                                                  double* __restrict__ gwork) {
+// Qtop == nullptr stands for the identity (the root of the tree).  Each wave owns
+// columns k = wave, wave + nwaves, ... and applies all reflectors to them with no
+// barrier; the reflectors are staged in LDS after the work columns when they fit.
+__global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw, int v_in_lds,
+                                                   const double* __restrict__ V,
+                                                   const double* __restrict__ tau,
+                                                   const double* __restrict__ Qtop,
+                                                   double* __restrict__ Qout,
+                                                   double* __restrict__ gwork) {
   extern __shared__ double smem[];
+  __shared__ double s_tau[1024];
   const int blk = blockIdx.x;
   const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
   const int nr = (int)(r1 - r0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
   double* Y = gwork ? gwork + (long)blk * ldw * c : smem;
+  const double* Vb = V + r0 * c;
+  if (v_in_lds) {
+    double* Vs = smem + (long)ldw * c;
+    for (long e = tid; e < (long)nr * c; e += blockDim.x) Vs[e] = Vb[e];
+    Vb = Vs;
+  }
   for (long e = tid; e < (long)nr * c; e += blockDim.x) {
     const int k = e / nr, i = e % nr;
     double v = 0.0;
     if (i < c) v = Qtop ? Qtop[((long)blk * c + i) * c + k] : (i == k ? 1.0 : 0.0);
     Y[(long)k * ldw + i] = v;
   }
+  for (int j = tid; j < c; j += blockDim.x) s_tau[j] = tau[(long)blk * c + j];
   __syncthreads();
-  const double* Vb = V + r0 * c;
-  for (int j = c - 1; j >= 0; --j) {
-    const double t = tau[(long)blk * c + j];
-    if (t == 0.0) continue;
-    const double* vj = Vb + (long)j * nr;
-    for (int k = wave; k < c; k += nwaves) {
-      double* yk = Y + (long)k * ldw;
+  for (int k = wave; k < c; k += nwaves) {
+    double* yk = Y + (long)k * ldw;
+    for (int j = c - 1; j >= 0; --j) {
+      const double t = s_tau[j];
+      if (t == 0.0) continue;
+      const double* vj = Vb + (long)j * nr;
       double d = 0.0;
       for (int i = j + 1 + lane; i < nr; i += 64) d += vj[i] * yk[i];
       d = wave_sum(d) + yk[j];
@@ -276,17 +287,27 @@ __global__ __launch_bounds__(256) void k_hh_apply(int m, int c, int nb, int ldw,
       if (lane == 0) yk[j] -= f;
       for (int i = j + 1 + lane; i < nr; i += 64) yk[i] -= f * vj[i];
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (long e = tid; e < (long)nr * c; e += blockDim.x) {
     const int i = e / c, k = e % c;
     Qout[(r0 + i) * c + k] = Y[(long)k * ldw + i];
   }
 }
 
+__global__ void k_jacobi_svd(int m, int c, const double* __restrict__ A, int transA, long lda,
+                             double* __restrict__ gwork, double* __restrict__ U, double* __restrict__ S,
+                             double* __restrict__ V, int max_sweeps);
+
+// static LDS of k_jacobi_svd (pair flags, permutation, singular values) and of the
+// TSQR kernels (reflector scalars), with margin
+constexpr int kJacobiStatic = 16384;
+constexpr int kTsqrStatic = 8192 + 512;
+
 // Dynamic LDS available to the TSQR kernels, in doubles: the device's per-workgroup
-// limit (160 KiB on gfx950) minus room for their static shared variables; 64 KiB
-// when the larger opt-in is refused.
+// limit (160 KiB on gfx950) minus their static shared variables; about 56 KiB when
+// the larger opt-in is refused.  The Jacobi kernel gets the same budget minus its own
+// larger static part.
 static int lds_doubles() {
   static int cap = -1;
   if (cap > 0) return cap;
@@ -294,21 +315,27 @@ static int lds_doubles() {
   TTIGA_HIP(hipGetDevice(&dev));
   if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     bytes = 65536;
-  bytes -= 1024;
-  if (bytes > 65536 - 1024) {
+  int dyn = bytes - kJacobiStatic;  // the larger static part bounds both budgets
+  if (bytes > 65536) {
     const bool ok =
         hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_factor),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess &&
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
+            hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
-      bytes = 65536 - 1024;
+      dyn = 65536 - kJacobiStatic;
     }
   }
-  cap = bytes / 8;
+  cap = dyn / 8;
   return cap;
 }
+
+// one wave per owned column up to 16 waves
+static int qr_threads(int c) { return 64 * std::min(16, std::max(1, c)); }
 
 void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
              double* R) {
@@ -316,7 +343,7 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
   const int kLdsDoubles = lds_doubles();
   struct Level {
     int m, nb, ldw;
-    bool lds;
+    bool lds, v_lds;
     DBuf V, tau, R, work;
   };
   std::vector<Level> lv;
@@ -324,20 +351,27 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
   bool tr = transA;
   long ld = lda;
   int mm = m;
-  // blocks of at least 2c rows so every level at least halves the rows
-  const int rows_target = std::max(2 * c, (c <= kLdsDoubles / (2 * c)) ? kLdsDoubles / c : 4 * c);
+  // blocks of at least 2c rows so every level at least halves the rows; prefer blocks
+  // whose work columns and reflectors both fit in LDS (2 rows c doubles), then blocks
+  // whose work columns alone fit, else global-memory work arrays
+  const int rows_both = kLdsDoubles / (2 * c), rows_work = kLdsDoubles / c;
+  const int rows_target =
+      rows_both >= 2 * c ? rows_both : (rows_work >= 2 * c ? rows_work : 4 * c);
   while (true) {
     Level L;
     L.m = mm;
     L.nb = std::max(1, (mm + rows_target - 1) / rows_target);
     L.ldw = (mm + L.nb - 1) / L.nb;
     L.lds = (long)L.ldw * c <= kLdsDoubles;
+    L.v_lds = 2L * L.ldw * c <= kLdsDoubles;
     L.V = DBuf(&ctx.alloc, sizeof(double) * (size_t)mm * c);
     L.tau = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * c);
     L.R = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * c * c);
     if (!L.lds) L.work = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * L.ldw * c);
     const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
-    hipLaunchKernelGGL(k_hh_factor, dim3(L.nb), dim3(256), shm, ctx.stream, mm, c, in, ld, tr ? 1 : 0,
+    ProfScope prof(ctx, "tsqr_factor", 2.0 * mm * c * c - L.nb * (2.0 / 3.0) * c * c * c,
+                   8.0 * (2.0 * mm * c + (double)L.nb * c * c));
+    hipLaunchKernelGGL(k_hh_factor, dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, mm, c, in, ld, tr ? 1 : 0,
                        L.nb, L.ldw, L.V.d(), L.tau.d(), L.R.d(), L.lds ? nullptr : L.work.d());
     TTIGA_HIP(hipGetLastError());
     lv.push_back(std::move(L));
@@ -355,22 +389,79 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     Level& L = lv[l];
     DBuf qout;
     double* dst = (l == 0) ? Q : (qout = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.m * c), qout.d());
-    const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
-    hipLaunchKernelGGL(k_hh_apply, dim3(L.nb), dim3(256), shm, ctx.stream, L.m, c, L.nb, L.ldw,
-                       L.V.d(), L.tau.d(), qprev.d(), dst, L.lds ? nullptr : L.work.d());
+    const size_t shm = L.lds ? (L.v_lds ? 2 : 1) * sizeof(double) * (size_t)L.ldw * c : 0;
+    ProfScope prof(ctx, "tsqr_apply", 4.0 * c * c * (double)L.m - 2.0 * c * c * c * L.nb,
+                   8.0 * (2.0 * L.m * c + (double)L.nb * c * c));
+    hipLaunchKernelGGL(k_hh_apply, dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, L.m, c, L.nb, L.ldw,
+                       L.v_lds ? 1 : 0, L.V.d(), L.tau.d(), qprev.d(), dst, L.lds ? nullptr : L.work.d());
     TTIGA_HIP(hipGetLastError());
     qprev = std::move(qout);
   }
 }
 
+// ------------------------------------------------------------------ Cholesky
+// One workgroup: upper Cholesky factor R of an SPD matrix G (c x c, row-major),
+// R^T R = G, and its inverse Rinv (upper).  Used for the 1-D mass matrices of
+// the preconditioner (a few hundred rows).
+__global__ __launch_bounds__(256) void k_chol_inv(int c, const double* __restrict__ G,
+                                                  double* __restrict__ R, double* __restrict__ Rinv,
+                                                  double* __restrict__ status) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (long e = tid; e < (long)c * c; e += nt) {
+    const int i = e / c, k = e % c;
+    R[e] = (k < i) ? 0.0 : G[e];
+  }
+  __syncthreads();
+  for (int j = 0; j < c; ++j) {
+    if (tid == 0) {
+      const double d = R[(long)j * c + j];
+      if (!(d > 0.0)) status[0] = 1.0;  // not positive definite
+      R[(long)j * c + j] = sqrt(fmax(d, 1e-300));
+    }
+    __syncthreads();
+    const double d = R[(long)j * c + j];
+    for (int k = j + 1 + tid; k < c; k += nt) R[(long)j * c + k] /= d;
+    __syncthreads();
+    const int rem = c - j - 1;
+    for (long e = tid; e < (long)rem * rem; e += nt) {
+      const int i = j + 1 + e / rem, k = j + 1 + e % rem;
+      if (k >= i) R[(long)i * c + k] -= R[(long)j * c + i] * R[(long)j * c + k];
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < c; j += nt) {
+    for (int i = j + 1; i < c; ++i) Rinv[(long)i * c + j] = 0.0;
+    Rinv[(long)j * c + j] = 1.0 / R[(long)j * c + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int k = i + 1; k <= j; ++k) acc += R[(long)i * c + k] * Rinv[(long)k * c + j];
+      Rinv[(long)i * c + j] = -acc / R[(long)i * c + i];
+    }
+  }
+}
+
+bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* Rinv) {
+  DBuf st(&ctx.alloc, sizeof(double));
+  fill(ctx, st.d(), 1, 0.0);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, ctx.stream, c, G, R, Rinv, st.d());
+  TTIGA_HIP(hipGetLastError());
+  double* h = ctx.host(1);
+  TTIGA_HIP(hipMemcpyAsync(h, st.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  return h[0] == 0.0;
+}
+
 // ------------------------------------------------------------- Jacobi SVD
 
-// One workgroup.  Ucol [c][m] and Vcol [c][c] are column-major work arrays.
-__global__ __launch_bounds__(512) void k_jacobi_svd(int m, int c, const double* __restrict__ A,
-                                                    int transA, long lda, double* __restrict__ Ucol,
-                                                    double* __restrict__ Vcol,
-                                                    double* __restrict__ U, double* __restrict__ S,
-                                                    double* __restrict__ V, int max_sweeps) {
+// One workgroup.  Ucol [c][m] and Vcol [c][c] are column-major work arrays, in LDS
+// when gwork is null (dynamic shared memory of (m + c) c doubles), else in gwork.
+__global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double* __restrict__ A,
+                                                     int transA, long lda, double* __restrict__ gwork,
+                                                     double* __restrict__ U, double* __restrict__ S,
+                                                     double* __restrict__ V, int max_sweeps) {
+  extern __shared__ double smem[];
+  double* Ucol = gwork ? gwork : smem;
+  double* Vcol = Ucol + (long)m * c;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = nt >> 6;
   __shared__ int s_rot;
@@ -381,9 +472,21 @@ __global__ __launch_bounds__(512) void k_jacobi_svd(int m, int c, const double* 
     Ucol[e] = transA ? A[(long)j * lda + i] : A[(long)i * lda + j];
   }
   for (long e = tid; e < (long)c * c; e += nt) Vcol[e] = ((e / c) == (e % c)) ? 1.0 : 0.0;
+  __shared__ double s_f2[16];
+  {
+    double f = 0.0;
+    for (long e = tid; e < (long)m * c; e += nt) f += Ucol[e] * Ucol[e];
+    f = wave_sum(f);
+    if (lane == 0) s_f2[wave] = f;
+  }
   __syncthreads();
+  double f2 = 0.0;
+  for (int w = 0; w < nwaves; ++w) f2 += s_f2[w];
   const int cp = (c + 1) & ~1;
-  const double tol = 1e-15;
+  // rotate a pair unless it is orthogonal to working accuracy (m u, the rounding level
+  // of a length-m dot product), or both columns are below 1e-15 of the Frobenius norm
+  // (they cannot affect any truncation decision)
+  const double tol = 2.220446049250313e-16 * m, floor2 = 1e-30 * f2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
@@ -404,10 +507,13 @@ __global__ __launch_bounds__(512) void k_jacobi_svd(int m, int c, const double* 
           be += y * y;
           ga += x * y;
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) continue;
+        for (int off = 32; off > 0; off >>= 1) {
+          al += __shfl_xor(al, off, 64);
+          be += __shfl_xor(be, off, 64);
+          ga += __shfl_xor(ga, off, 64);
+        }
+        const double pq = sqrt(al) * sqrt(be);
+        if (ga == 0.0 || !(fabs(ga) > tol * pq) || pq <= floor2) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
@@ -466,10 +572,17 @@ __global__ __launch_bounds__(512) void k_jacobi_svd(int m, int c, const double* 
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V) {
   TTIGA_CHECK(c > 0 && m >= c && c <= 1024, TTIGA_E_ARG, "svd_small needs 0 < c <= m, c <= 1024");
-  DBuf Ucol(&ctx.alloc, sizeof(double) * (size_t)m * c), Vcol(&ctx.alloc, sizeof(double) * c * c);
-  const int threads = c <= 64 ? 128 : 512;
-  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(threads), 0, ctx.stream, m, c, A, transA ? 1 : 0,
-                     lda, Ucol.d(), Vcol.d(), U, s, V, 40);
+  const long need = (long)(m + c) * c;
+  const bool lds = need <= lds_doubles();
+  DBuf work;
+  if (!lds) work = DBuf(&ctx.alloc, sizeof(double) * need);
+  // one wave per column pair of a round, up to 16 waves
+  const int threads = 64 * std::min(16, std::max(2, (c + 1) / 2));
+  // counted at a nominal 8 sweeps of c(c-1)/2 pair rotations: 3 dots, U and V updates
+  ProfScope prof(ctx, "jacobi_svd", 8.0 * 0.5 * c * (c - 1.0) * (12.0 * m + 6.0 * c),
+                 8.0 * (2.0 * m * c + 2.0 * c * c + c));
+  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(threads), lds ? sizeof(double) * need : 0, ctx.stream,
+                     m, c, A, transA ? 1 : 0, lda, lds ? nullptr : work.d(), U, s, V, 40);
   TTIGA_HIP(hipGetLastError());
 }
 

@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "iga.hpp"
+#include "precond.hpp"
 
 namespace ttiga {
 
@@ -28,6 +29,7 @@ struct Problem {
   DBuf gtab_span[3], gtab_B[3], gtab_D[3];
   // TT state
   TT R[6], fJ, K, F, KII, rhs, u;
+  Precond pc;
   double min_detJ = 0.0;
   bool assembled = false, solved = false;
   ttiga_solve_stats last_solve{};
@@ -41,6 +43,8 @@ struct Problem {
   void upload();  // device copies of the small inputs
 
  private:
+  void solve_cg(ttiga_solve_stats& s);
+  void solve_pcg(ttiga_solve_stats& s);
   void build_tables();
   void reduce_boundary();
   SourceDev source_dev() const;

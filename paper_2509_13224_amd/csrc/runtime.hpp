@@ -83,7 +83,45 @@ struct DBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Opt-in per-kernel-class timing with HIP events on the context stream, with the
+// algorithmic flops and bytes of each launch (for roofline fractions).
+struct KernelStat {
+  long launches = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+
+struct Profiler {
+  bool on = false;
+  std::map<std::string, KernelStat> stats;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  void flush();  // waits for recorded events and folds them into stats
+  ~Profiler();
+};
+
+struct Context;
+
+// Records events around the launches issued while it lives (when profiling is on).
+class ProfScope {
+ public:
+  ProfScope(Context& c, const char* name, double flops, double bytes);
+  ~ProfScope();
+
+ private:
+  Context* c_;
+  const char* name_;
+  double flops_, bytes_;
+  hipEvent_t a_ = nullptr;
+};
+
 struct Context {
+  Profiler prof;
   int device = 0;
   hipStream_t stream = nullptr;
   DeviceAllocator alloc;
@@ -139,6 +177,8 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
 // One-sided Jacobi SVD of op(A) (m x c, m >= c): U (m x c), s (c, descending), V (c x c).
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V);
+// Upper Cholesky factor R (R^T R = G) and R^-1 of an SPD c x c matrix; false if G is not SPD.
+bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* Rinv);
 // Smallest r with ||s[r:]|| <= delta (delta < 0: -delta * ||s|| / sqrt(2) relative).
 int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* norm_out);
 void fill(Context& ctx, double* p, size_t n, double v);
@@ -148,7 +188,13 @@ void sumsq_reduce(Context& ctx, const double* x, size_t n, double* out_dev);
 // TT algebra (tt_ops.cpp / kernels_tt.hip).
 void tt_from_view(Context& ctx, const ttiga_tt_view& v, TT& out);
 void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_rank,
-              double* norm_out = nullptr);
+              double* norm_out = nullptr, bool left_orthogonal = false);
+// Rounding that first projects high-rank trains onto a Gaussian sketch of width
+// hint + 10 (randomised TT-rounding) and then truncates deterministically; hint
+// is updated to the resulting rank.
+void tt_round_auto(Context& ctx, TT& x, double eps_rel, int max_rank, int& hint);
+// out core d of x multiplied along mode d by op(Mat) (n x n row-major).
+void tt_mode_product(Context& ctx, TT& x, int d, const double* Mat, bool trans);
 void tt_axpby(Context& ctx, double alpha, const TT& x, double beta, const TT& y, TT& out);
 void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* beta, const TT& y,
                   TT& out);

@@ -183,6 +183,11 @@ void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y) {
   y.alloc(ctx, n, r);
   for (int k = 0; k < 3; ++k) {
     const long total = (long)y.core_elems(k);
+    // algorithmic work: the in-range band entries only; bytes: K core, x core, y core
+    const double band_nnz = (double)n[k] * (2 * p + 1) - (double)p * (p + 1);
+    ProfScope prof(ctx, "tt_matvec_banded",
+                   2.0 * band_nnz * K.r[k] * K.r[k + 1] * x.r[k] * x.r[k + 1],
+                   8.0 * ((double)K.core_elems(k) + (double)x.core_elems(k) + (double)total));
     hipLaunchKernelGGL(k_matvec_banded, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n[k], p,
                        K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].d(), x.c[k].d(), y.c[k].d());
   }
@@ -208,6 +213,7 @@ static void axpby_impl(Context& ctx, const double* ap, double a, const TT& x, co
   out.alloc(ctx, x.n, r);
   for (int k = 0; k < 3; ++k) {
     const long total = (long)out.core_elems(k);
+    ProfScope prof(ctx, "tt_axpby", 0.0, 8.0 * (total + (double)x.core_elems(k) + (double)y.core_elems(k)));
     hipLaunchKernelGGL(k_axpby_core, dim3(grid_for(total)), dim3(256), 0, ctx.stream, k, 3, x.n[k],
                        x.r[k], x.r[k + 1], y.r[k], y.r[k + 1], x.c[k].d(), y.c[k].d(), ap, a, bp, b,
                        out.c[k].d());
@@ -282,13 +288,14 @@ static TruncSVD truncated_svd(Context& ctx, const double* B, int r, long M, doub
     hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long)r * o.s)), dim3(256), 0, ctx.stream, Ut.d(),
                        r, r, o.s, o.U.d());
   } else {
-    // tall: B = Q T (r x M), svd(T) = Ut S V^T, so B = (Q Ut) S V^T
+    // tall: B = Q T (r x M); Jacobi on the rows of T (converges in about half the
+    // sweeps of its columns): T^T = V S Ut^T, so B = (Q Ut) S V^T
     const int c = (int)M;
     DBuf Q(&ctx.alloc, sizeof(double) * (size_t)r * c), T(&ctx.alloc, sizeof(double) * c * c);
     qr_tall(ctx, B, false, r, c, c, Q.d(), T.d());
     DBuf Ut(&ctx.alloc, sizeof(double) * c * c), V(&ctx.alloc, sizeof(double) * c * c);
     o.S = DBuf(&ctx.alloc, sizeof(double) * c);
-    svd_small(ctx, T.d(), false, c, c, c, Ut.d(), o.S.d(), V.d());
+    svd_small(ctx, T.d(), true, c, c, c, V.d(), o.S.d(), Ut.d());
     double nd[2];
     o.s = trunc_rank_sync(ctx, o.S.d(), c, delta, nd);
     o.norm = nd[0];
@@ -305,13 +312,13 @@ static TruncSVD truncated_svd(Context& ctx, const double* B, int r, long M, doub
 }
 
 void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_rank,
-              double* norm_out) {
+              double* norm_out, bool left_orthogonal) {
   if (x.zero()) {
     if (norm_out) norm_out[0] = 0.0;
     return;
   }
   // Phase 1: left-orthogonalise cores 0 and 1 (QR of the (r_k n_k) x r_{k+1} unfoldings).
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < (left_orthogonal ? 0 : 2); ++k) {
     const int m = x.r[k] * x.n[k], c = x.r[k + 1];
     const int nn = x.n[k + 1], r2 = x.r[k + 2];
     if (m >= c) {
@@ -433,6 +440,91 @@ void tt_compress_dense(Context& ctx, const double* A, const int* n, double delta
   out.c[0] = std::move(U0);
   out.c[1] = std::move(U1);
   out.c[2] = std::move(C1);
+}
+
+// Randomised projection of x onto ranks (l1, l2): Gaussian TT Omega with cores
+// O2 (l1 x n2 x l2), O3 (l2 x n3); right interfaces W3 = X3 O3^T, W2 = (X2 x3 W3) O2^T;
+// then left to right Q1 = orth(X1 W2), Z2 = (Q1^T X1) X2, Q2 = orth(Z2 W3), last core
+// (Q2^T Z2) X3.  The result is left-orthogonal with ranks (l1, l2).
+static void tt_sketch_project(Context& ctx, const TT& x, int l1, int l2, TT& y) {
+  const int n0 = x.n[0], n1 = x.n[1], n2 = x.n[2], R1 = x.r[1], R2 = x.r[2];
+  DBuf O2(&ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2), O3(&ctx.alloc, sizeof(double) * (size_t)l2 * n2);
+  hipLaunchKernelGGL(k_gaussian, dim3(grid_for((long)l1 * n1 * l2)), dim3(256), 0, ctx.stream, O2.d(),
+                     (long)l1 * n1 * l2, ++ctx.rng_counter);
+  hipLaunchKernelGGL(k_gaussian, dim3(grid_for((long)l2 * n2)), dim3(256), 0, ctx.stream, O3.d(),
+                     (long)l2 * n2, ++ctx.rng_counter);
+  TTIGA_HIP(hipGetLastError());
+  DBuf W3(&ctx.alloc, sizeof(double) * (size_t)R2 * l2);
+  gemm(ctx, false, true, R2, l2, n2, 1.0, x.c[2].d(), n2, 0, O3.d(), n2, 0, 0.0, W3.d(), l2, 0);
+  DBuf T(&ctx.alloc, sizeof(double) * (size_t)R1 * n1 * l2);
+  gemm(ctx, false, false, R1 * n1, l2, R2, 1.0, x.c[1].d(), R2, 0, W3.d(), l2, 0, 0.0, T.d(), l2, 0);
+  DBuf W2(&ctx.alloc, sizeof(double) * (size_t)R1 * l1);
+  gemm(ctx, false, true, R1, l1, n1 * l2, 1.0, T.d(), (long)n1 * l2, 0, O2.d(), (long)n1 * l2, 0, 0.0,
+       W2.d(), l1, 0);
+  DBuf Y1(&ctx.alloc, sizeof(double) * (size_t)n0 * l1);
+  gemm(ctx, false, false, n0, l1, R1, 1.0, x.c[0].d(), R1, 0, W2.d(), l1, 0, 0.0, Y1.d(), l1, 0);
+  DBuf Q1(&ctx.alloc, sizeof(double) * (size_t)n0 * l1), Rq(&ctx.alloc, sizeof(double) * (size_t)l1 * l1);
+  qr_tall(ctx, Y1.d(), false, n0, l1, l1, Q1.d(), Rq.d());
+  DBuf M1(&ctx.alloc, sizeof(double) * (size_t)l1 * R1);
+  gemm(ctx, true, false, l1, R1, n0, 1.0, Q1.d(), l1, 0, x.c[0].d(), R1, 0, 0.0, M1.d(), R1, 0);
+  DBuf Z2(&ctx.alloc, sizeof(double) * (size_t)l1 * n1 * R2);
+  gemm(ctx, false, false, l1, n1 * R2, R1, 1.0, M1.d(), R1, 0, x.c[1].d(), (long)n1 * R2, 0, 0.0, Z2.d(),
+       (long)n1 * R2, 0);
+  DBuf Y2(&ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2);
+  gemm(ctx, false, false, l1 * n1, l2, R2, 1.0, Z2.d(), R2, 0, W3.d(), l2, 0, 0.0, Y2.d(), l2, 0);
+  DBuf Q2(&ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2), Rq2(&ctx.alloc, sizeof(double) * (size_t)l2 * l2);
+  qr_tall(ctx, Y2.d(), false, l1 * n1, l2, l2, Q2.d(), Rq2.d());
+  DBuf M2(&ctx.alloc, sizeof(double) * (size_t)l2 * R2);
+  gemm(ctx, true, false, l2, R2, l1 * n1, 1.0, Q2.d(), l2, 0, Z2.d(), R2, 0, 0.0, M2.d(), R2, 0);
+  DBuf C3(&ctx.alloc, sizeof(double) * (size_t)l2 * n2);
+  gemm(ctx, false, false, l2, n2, R2, 1.0, M2.d(), R2, 0, x.c[2].d(), n2, 0, 0.0, C3.d(), n2, 0);
+  y.n[0] = n0; y.n[1] = n1; y.n[2] = n2;
+  y.r[0] = 1; y.r[1] = l1; y.r[2] = l2; y.r[3] = 1;
+  y.c[0] = std::move(Q1);
+  y.c[1] = std::move(Q2);
+  y.c[2] = std::move(C3);
+}
+
+void tt_round_auto(Context& ctx, TT& x, double eps_rel, int max_rank, int& hint) {
+  if (x.zero()) return;
+  int l = std::max(hint, 1) + 10;
+  while (true) {
+    const int l1 = std::min(l, std::min(x.r[1], x.n[0]));
+    const int l2 = std::min(l, std::min(x.r[2], x.n[2]));
+    // trains already near the sketch width, or sketches that would not shrink them:
+    // deterministic rounding
+    if ((x.r[1] <= l1 + 6 && x.r[2] <= l2 + 6) || l1 * x.n[1] < l2) {
+      tt_round(ctx, x, eps_rel, -1.0, max_rank);
+      hint = x.zero() ? 1 : std::max(x.r[1], x.r[2]);
+      return;
+    }
+    TT y;
+    tt_sketch_project(ctx, x, l1, l2, y);
+    tt_round(ctx, y, eps_rel, -1.0, max_rank, nullptr, true);
+    if (y.zero()) {
+      x.set_zero(x.n);
+      return;
+    }
+    const bool sat1 = y.r[1] > l1 - 4 && l1 < std::min(x.r[1], x.n[0]);
+    const bool sat2 = y.r[2] > l2 - 4 && l2 < std::min(x.r[2], x.n[2]);
+    if (sat1 || sat2) {  // the sketch may have cut real directions: widen it
+      l += 12;
+      continue;
+    }
+    hint = std::max(y.r[1], y.r[2]);
+    x = std::move(y);
+    return;
+  }
+}
+
+void tt_mode_product(Context& ctx, TT& x, int d, const double* Mat, bool trans) {
+  if (x.zero()) return;
+  const int ra = x.r[d], n = x.n[d], rb = x.r[d + 1];
+  DBuf out(&ctx.alloc, sizeof(double) * x.core_elems(d));
+  // out[a] (n x rb) = op(Mat) (n x n) * X[a] (n x rb), batched over a
+  gemm(ctx, trans, false, n, rb, n, 1.0, Mat, n, 0, x.c[d].d(), rb, (long)n * rb, 0.0, out.d(), rb,
+       (long)n * rb, ra);
+  x.c[d] = std::move(out);
 }
 
 }  // namespace ttiga

@@ -33,7 +33,8 @@ EXPORTED = (
     "ttiga_validate", "ttiga_problem_create", "ttiga_problem_destroy", "ttiga_assemble", "ttiga_solve",
     "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
     "ttiga_sample_factors", "ttiga_tt_matvec", "ttiga_tt_round", "ttiga_tt_dot",
-    "ttiga_tt_compress", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free",
+    "ttiga_tt_compress", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free", "ttiga_profile",
+    "ttiga_profile_read",
 )
 
 c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -73,7 +74,8 @@ class AssemblyStats(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("rel_res", ctypes.c_double),
-                ("rank_u", ctypes.c_int * 4), ("max_rank_seen", ctypes.c_int),
+                ("rel_pres", ctypes.c_double), ("rank_u", ctypes.c_int * 4), ("max_rank_seen", ctypes.c_int),
+                ("precond_terms", ctypes.c_int), ("precond_err", ctypes.c_double),
                 ("time_ms", ctypes.c_double)]
 
 
@@ -84,6 +86,11 @@ class TTView(ctypes.Structure):
 class TTMView(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("p", ctypes.c_int), ("r", ctypes.c_int * 4),
                 ("core", ctypes.c_void_p * 3)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_long), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 class TTIGAError(RuntimeError):
@@ -132,6 +139,8 @@ def load(path=LIB_PATH):
         "ttiga_tt_info": (ctypes.c_int, [vp, c_int_p, c_int_p]),
         "ttiga_tt_copy": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t]),
         "ttiga_tt_free": (ctypes.c_int, [vp]),
+        "ttiga_profile": (ctypes.c_int, [vp, ctypes.c_int]),
+        "ttiga_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(KernelStat), ctypes.c_int, c_int_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -200,6 +209,19 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # ---------------------------------------------------------------- profiling
+    def profile(self, enable):
+        _check(self.lib, self.lib.ttiga_profile(self.h, int(enable)))
+
+    def profile_read(self):
+        cnt = ctypes.c_int()
+        _check(self.lib, self.lib.ttiga_profile_read(self.h, None, 0, ctypes.byref(cnt)))
+        arr = (KernelStat * max(cnt.value, 1))()
+        _check(self.lib, self.lib.ttiga_profile_read(self.h, arr, cnt.value, ctypes.byref(cnt)))
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                           flops=arr[i].flops, bytes=arr[i].bytes)
+                for i in range(cnt.value)}
 
     # ---------------------------------------------------------------- problems
     def problem_create(self, pr, precond=0):
@@ -351,8 +373,9 @@ class ProblemHandle:
         st = SolveStats()
         ok = (TTIGA_OK, TTIGA_E_NOTCONV) if allow_notconv else (TTIGA_OK,)
         code = _check(self.lib, self.lib.ttiga_solve(self.h, ctypes.byref(st)), ok)
-        return dict(status=code, iterations=st.iterations, rel_res=st.rel_res, rank_u=list(st.rank_u),
-                    max_rank_seen=st.max_rank_seen, time_ms=st.time_ms)
+        return dict(status=code, iterations=st.iterations, rel_res=st.rel_res, rel_pres=st.rel_pres,
+                    rank_u=list(st.rank_u), max_rank_seen=st.max_rank_seen, precond_terms=st.precond_terms,
+                    precond_err=st.precond_err, time_ms=st.time_ms)
 
     def solution(self):
         r = (ctypes.c_int * 4)()

@@ -87,3 +87,24 @@ def test_max_iter_reports_notconv(ctx):
     st = h.solve(allow_notconv=True)
     assert st["status"] == ttiga.TTIGA_E_NOTCONV and st["iterations"] == 1
     assert h.solution() is not None
+
+
+@pytest.mark.parametrize("name", ["annulus_c1", "twisted_p3_n10", "bumpy_p3_n9"])
+def test_preconditioned_solve_matches_sparse(ctx, name):
+    """Flexible PCG with the separable preconditioner reaches the same discrete solution."""
+    say("pcg", name)
+    if name == "annulus_c1":
+        pr = W.c1_problem(eps=1e-12, tol=1e-12)
+    elif name == "twisted_p3_n10":
+        geo = W.twisted_box(1.0)
+        pr = W.small_problem(geo, 10, 3, W.fourier_source(geo, 21), eps=1e-11, tol=1e-11)
+    else:
+        geo = W.bumpy_cube()
+        pr = W.small_problem(geo, 9, 3, W.fourier_source(geo, 4), eps=1e-11, tol=1e-11)
+    u_h = sparse_iga.solve(pr)
+    h = ctx.problem_create(pr, precond=1)
+    h.assemble()
+    st = h.solve()
+    u = _full(pr, h.solution()).ravel()
+    assert np.linalg.norm(u - u_h) <= 1e-8 * np.linalg.norm(u_h), st
+    assert st["iterations"] <= 40, st
