@@ -145,6 +145,7 @@ typedef struct {
   int max_rank_seen;
   int precond_terms; /* exponential-sum terms of the preconditioner (0: none) */
   double precond_err;/* max relative error of that sum on the spectrum interval */
+  double precond_setup_ms; /* preconditioner set-up time within time_ms */
   double time_ms;
 } ttiga_solve_stats;
 

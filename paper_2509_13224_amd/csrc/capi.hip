@@ -2,6 +2,7 @@
 // device allocator / context plumbing.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -129,9 +130,13 @@ Profiler::~Profiler() {
   for (auto e : pool) (void)hipEventDestroy(e);
 }
 
-ProfScope::ProfScope(Context& c, const char* name, double flops, double bytes)
+ProfScope::ProfScope(Context& c, const char* name, double flops, double bytes, int size)
     : c_(&c), name_(name), flops_(flops), bytes_(bytes) {
   if (!c.prof.on) return;
+  if (c.prof.detail && size >= 0) {
+    const int b = size <= 16 ? 16 : size <= 32 ? 32 : size <= 64 ? 64 : size <= 128 ? 128 : 1024;
+    name_ += "_c" + std::to_string(b);
+  }
   a_ = c.prof.get();
   TTIGA_HIP(hipEventRecord(a_, c.stream));
 }
@@ -459,6 +464,8 @@ int ttiga_profile(ttiga_ctx* ctx, int enable) {
     }
     if (!enable) pr.flush();
     pr.on = enable != 0;
+    const char* env = std::getenv("TTIGA_PROF_DETAIL");
+    pr.detail = env && env[0] == '1';
   });
 }
 

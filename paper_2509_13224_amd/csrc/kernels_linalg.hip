@@ -176,6 +176,7 @@ __device__ inline double wave_sum(double v) {
 // Column k of the block belongs to wave k % nwaves for the whole factorisation,
 // so a reflector needs one barrier: the owner of column j forms v_j and tau_j,
 // then every wave applies H_j to the columns it owns.
+template <bool kLds>
 __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* __restrict__ A,
                                                     long lda, int trans, int nb, int ldw,
                                                     double* __restrict__ V,
@@ -188,7 +189,8 @@ __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* 
   const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
   const int nr = (int)(r1 - r0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  double* W = gwork ? gwork + (long)blk * ldw * c : smem;
+  // the storage is a template choice so LDS accesses compile to ds_* instructions
+  double* W = kLds ? smem : gwork + (long)blk * ldw * c;
   for (long e = tid; e < (long)nr * c; e += blockDim.x) {
     int i, j;
     double v;
@@ -220,14 +222,34 @@ __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* 
     __syncthreads();
     const double t = s_tau[j];
     if (t == 0.0) continue;
-    for (int k = j + 1 + ((wave - (j + 1) % nwaves + nwaves) % nwaves); k < c; k += nwaves) {
-      double* wk = W + (long)k * ldw;
-      double d = 0.0;
-      for (int i = j + 1 + lane; i < nr; i += 64) d += wj[i] * wk[i];
-      d = wave_sum(d) + wk[j];
-      const double f = t * d;
-      if (lane == 0) wk[j] -= f;
-      for (int i = j + 1 + lane; i < nr; i += 64) wk[i] -= f * wj[i];
+    // H_j on the owned columns k > j, eight at a time: the partial dot products are
+    // formed first and reduced together so the shuffle latencies overlap
+    const int k0 = j + 1 + ((wave - (j + 1) % nwaves + nwaves) % nwaves);
+    for (int kb = k0; kb < c; kb += 8 * nwaves) {
+      double d[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) d[q] = 0.0;
+      for (int i = j + 1 + lane; i < nr; i += 64) {
+        const double v = wj[i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = kb + q * nwaves;
+          if (k < c) d[q] += v * W[(long)k * ldw + i];
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d[q] += __shfl_xor(d[q], off, 64);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = kb + q * nwaves;
+        if (k >= c) continue;
+        double* wk = W + (long)k * ldw;
+        const double f = t * (d[q] + wk[j]);
+        if (lane == 0) wk[j] -= f;
+        for (int i = j + 1 + lane; i < nr; i += 64) wk[i] -= f * wj[i];
+      }
     }
   }
   __syncthreads();
@@ -247,7 +269,8 @@ __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* 
 // Qtop == nullptr stands for the identity (the root of the tree).  Each wave owns
 // columns k = wave, wave + nwaves, ... and applies all reflectors to them with no
 // barrier; the reflectors are staged in LDS after the work columns when they fit.
-__global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw, int v_in_lds,
+template <bool kLds, bool kVLds>
+__global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw,
                                                    const double* __restrict__ V,
                                                    const double* __restrict__ tau,
                                                    const double* __restrict__ Qtop,
@@ -259,13 +282,12 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
   const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
   const int nr = (int)(r1 - r0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  double* Y = gwork ? gwork + (long)blk * ldw * c : smem;
-  const double* Vb = V + r0 * c;
-  if (v_in_lds) {
-    double* Vs = smem + (long)ldw * c;
-    for (long e = tid; e < (long)nr * c; e += blockDim.x) Vs[e] = Vb[e];
-    Vb = Vs;
-  }
+  double* Y = kLds ? smem : gwork + (long)blk * ldw * c;
+  const double* Vg = V + r0 * c;
+  double* Vs = smem + (long)ldw * c;
+  if (kVLds)
+    for (long e = tid; e < (long)nr * c; e += blockDim.x) Vs[e] = Vg[e];
+  const double* Vb = kVLds ? Vs : Vg;
   for (long e = tid; e < (long)nr * c; e += blockDim.x) {
     const int k = e / nr, i = e % nr;
     double v = 0.0;
@@ -274,18 +296,37 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
   }
   for (int j = tid; j < c; j += blockDim.x) s_tau[j] = tau[(long)blk * c + j];
   __syncthreads();
-  for (int k = wave; k < c; k += nwaves) {
-    double* yk = Y + (long)k * ldw;
+  // each wave applies all reflectors to its owned columns, eight columns at a time so the
+  // eight dot-product reductions of one reflector overlap
+  for (int kb = wave; kb < c; kb += 8 * nwaves) {
     for (int j = c - 1; j >= 0; --j) {
       const double t = s_tau[j];
       if (t == 0.0) continue;
       const double* vj = Vb + (long)j * nr;
-      double d = 0.0;
-      for (int i = j + 1 + lane; i < nr; i += 64) d += vj[i] * yk[i];
-      d = wave_sum(d) + yk[j];
-      const double f = t * d;
-      if (lane == 0) yk[j] -= f;
-      for (int i = j + 1 + lane; i < nr; i += 64) yk[i] -= f * vj[i];
+      double d[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) d[q] = 0.0;
+      for (int i = j + 1 + lane; i < nr; i += 64) {
+        const double v = vj[i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = kb + q * nwaves;
+          if (k < c) d[q] += v * Y[(long)k * ldw + i];
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d[q] += __shfl_xor(d[q], off, 64);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = kb + q * nwaves;
+        if (k >= c) continue;
+        double* yk = Y + (long)k * ldw;
+        const double f = t * (d[q] + yk[j]);
+        if (lane == 0) yk[j] -= f;
+        for (int i = j + 1 + lane; i < nr; i += 64) yk[i] -= f * vj[i];
+      }
     }
   }
   __syncthreads();
@@ -295,6 +336,7 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
   }
 }
 
+template <bool kLds>
 __global__ void k_jacobi_svd(int m, int c, const double* __restrict__ A, int transA, long lda,
                              double* __restrict__ gwork, double* __restrict__ U, double* __restrict__ S,
                              double* __restrict__ V, int max_sweeps);
@@ -318,11 +360,13 @@ static int lds_doubles() {
   int dyn = bytes - kJacobiStatic;  // the larger static part bounds both budgets
   if (bytes > 65536) {
     const bool ok =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_factor),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_factor<true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd<true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
             hipSuccess;
     if (!ok) {
@@ -351,12 +395,12 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
   bool tr = transA;
   long ld = lda;
   int mm = m;
-  // blocks of at least 2c rows so every level at least halves the rows; prefer blocks
-  // whose work columns and reflectors both fit in LDS (2 rows c doubles), then blocks
-  // whose work columns alone fit, else global-memory work arrays
-  const int rows_both = kLdsDoubles / (2 * c), rows_work = kLdsDoubles / c;
-  const int rows_target =
-      rows_both >= 2 * c ? rows_both : (rows_work >= 2 * c ? rows_work : 4 * c);
+  // blocks of at least 2c rows so every level at least halves the rows, as tall as the
+  // LDS holds the work columns (each tree level costs a launch of c dependent steps, so
+  // fewer, taller blocks win); the apply step keeps the reflectors in LDS only when
+  // both fit and otherwise streams them from L2
+  const int rows_work = kLdsDoubles / c;
+  const int rows_target = rows_work >= 2 * c ? rows_work : 4 * c;
   while (true) {
     Level L;
     L.m = mm;
@@ -370,9 +414,13 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     if (!L.lds) L.work = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * L.ldw * c);
     const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
     ProfScope prof(ctx, "tsqr_factor", 2.0 * mm * c * c - L.nb * (2.0 / 3.0) * c * c * c,
-                   8.0 * (2.0 * mm * c + (double)L.nb * c * c));
-    hipLaunchKernelGGL(k_hh_factor, dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, mm, c, in, ld, tr ? 1 : 0,
-                       L.nb, L.ldw, L.V.d(), L.tau.d(), L.R.d(), L.lds ? nullptr : L.work.d());
+                   8.0 * (2.0 * mm * c + (double)L.nb * c * c), c);
+    if (L.lds)
+      hipLaunchKernelGGL(k_hh_factor<true>, dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, mm, c, in, ld,
+                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), L.R.d(), nullptr);
+    else
+      hipLaunchKernelGGL(k_hh_factor<false>, dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, mm, c, in, ld,
+                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), L.R.d(), L.work.d());
     TTIGA_HIP(hipGetLastError());
     lv.push_back(std::move(L));
     const Level& last = lv.back();
@@ -391,9 +439,16 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     double* dst = (l == 0) ? Q : (qout = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.m * c), qout.d());
     const size_t shm = L.lds ? (L.v_lds ? 2 : 1) * sizeof(double) * (size_t)L.ldw * c : 0;
     ProfScope prof(ctx, "tsqr_apply", 4.0 * c * c * (double)L.m - 2.0 * c * c * c * L.nb,
-                   8.0 * (2.0 * L.m * c + (double)L.nb * c * c));
-    hipLaunchKernelGGL(k_hh_apply, dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, L.m, c, L.nb, L.ldw,
-                       L.v_lds ? 1 : 0, L.V.d(), L.tau.d(), qprev.d(), dst, L.lds ? nullptr : L.work.d());
+                   8.0 * (2.0 * L.m * c + (double)L.nb * c * c), c);
+    if (L.v_lds)
+      hipLaunchKernelGGL((k_hh_apply<true, true>), dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, L.m, c,
+                         L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
+    else if (L.lds)
+      hipLaunchKernelGGL((k_hh_apply<true, false>), dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, L.m, c,
+                         L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
+    else
+      hipLaunchKernelGGL((k_hh_apply<false, false>), dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, L.m, c,
+                         L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, L.work.d());
     TTIGA_HIP(hipGetLastError());
     qprev = std::move(qout);
   }
@@ -455,12 +510,13 @@ bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* R
 
 // One workgroup.  Ucol [c][m] and Vcol [c][c] are column-major work arrays, in LDS
 // when gwork is null (dynamic shared memory of (m + c) c doubles), else in gwork.
+template <bool kLds>
 __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double* __restrict__ A,
                                                      int transA, long lda, double* __restrict__ gwork,
                                                      double* __restrict__ U, double* __restrict__ S,
                                                      double* __restrict__ V, int max_sweeps) {
   extern __shared__ double smem[];
-  double* Ucol = gwork ? gwork : smem;
+  double* Ucol = kLds ? smem : gwork;
   double* Vcol = Ucol + (long)m * c;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = nt >> 6;
@@ -483,6 +539,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
   double f2 = 0.0;
   for (int w = 0; w < nwaves; ++w) f2 += s_f2[w];
   const int cp = (c + 1) & ~1;
+  // a column pair is handled by a group of G lanes (G a power of two dividing 64): short
+  // columns use small groups so more pairs of a round run at once
+  const int G = (m <= 32) ? 8 : ((m <= 128) ? 16 : 64);
+  const int gl = lane % G, grp = wave * (64 / G) + lane / G, ngroups = nwaves * (64 / G);
   // rotate a pair unless it is orthogonal to working accuracy (m u, the rounding level
   // of a length-m dot product), or both columns are below 1e-15 of the Frobenius norm
   // (they cannot affect any truncation decision)
@@ -491,7 +551,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int rnd = 0; rnd < cp - 1; ++rnd) {
-      for (int k = wave; k < cp / 2; k += nwaves) {
+      for (int k = grp; k < cp / 2; k += ngroups) {
         // circle method: slot 0 fixed, slots 1..cp-1 rotate by rnd
         const int a = k, b = cp - 1 - k;
         const int pa = (a == 0) ? 0 : ((a - 1 + rnd) % (cp - 1)) + 1;
@@ -501,13 +561,13 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
         double* up = Ucol + (long)p * m;
         double* uq = Ucol + (long)q * m;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += G) {
           const double x = up[i], y = uq[i];
           al += x * x;
           be += y * y;
           ga += x * y;
         }
-        for (int off = 32; off > 0; off >>= 1) {
+        for (int off = G >> 1; off > 0; off >>= 1) {
           al += __shfl_xor(al, off, 64);
           be += __shfl_xor(be, off, 64);
           ga += __shfl_xor(ga, off, 64);
@@ -517,19 +577,19 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
         const double zeta = (be - al) / (2.0 * ga);
         const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += G) {
           const double x = up[i], y = uq[i];
           up[i] = cs * x - sn * y;
           uq[i] = sn * x + cs * y;
         }
         double* vp = Vcol + (long)p * c;
         double* vq = Vcol + (long)q * c;
-        for (int i = lane; i < c; i += 64) {
+        for (int i = gl; i < c; i += G) {
           const double x = vp[i], y = vq[i];
           vp[i] = cs * x - sn * y;
           vq[i] = sn * x + cs * y;
         }
-        if (lane == 0) s_rot = 1;
+        if (gl == 0) s_rot = 1;
       }
       __syncthreads();
     }
@@ -576,13 +636,19 @@ void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long ld
   const bool lds = need <= lds_doubles();
   DBuf work;
   if (!lds) work = DBuf(&ctx.alloc, sizeof(double) * need);
-  // one wave per column pair of a round, up to 16 waves
-  const int threads = 64 * std::min(16, std::max(2, (c + 1) / 2));
+  // enough lane groups for all column pairs of a round, up to 16 waves
+  const int G = (m <= 32) ? 8 : ((m <= 128) ? 16 : 64);
+  const int pairs = (c + 1) / 2;
+  const int threads = 64 * std::min(16, std::max(1, (pairs * G + 63) / 64));
   // counted at a nominal 8 sweeps of c(c-1)/2 pair rotations: 3 dots, U and V updates
   ProfScope prof(ctx, "jacobi_svd", 8.0 * 0.5 * c * (c - 1.0) * (12.0 * m + 6.0 * c),
-                 8.0 * (2.0 * m * c + 2.0 * c * c + c));
-  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(threads), lds ? sizeof(double) * need : 0, ctx.stream,
-                     m, c, A, transA ? 1 : 0, lda, lds ? nullptr : work.d(), U, s, V, 40);
+                 8.0 * (2.0 * m * c + 2.0 * c * c + c), c);
+  if (lds)
+    hipLaunchKernelGGL(k_jacobi_svd<true>, dim3(1), dim3(threads), sizeof(double) * need, ctx.stream, m, c,
+                       A, transA ? 1 : 0, lda, nullptr, U, s, V, 40);
+  else
+    hipLaunchKernelGGL(k_jacobi_svd<false>, dim3(1), dim3(threads), 0, ctx.stream, m, c, A, transA ? 1 : 0,
+                       lda, work.d(), U, s, V, 40);
   TTIGA_HIP(hipGetLastError());
 }
 

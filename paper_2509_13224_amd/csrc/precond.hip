@@ -16,7 +16,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "precond.hpp"
@@ -86,42 +88,56 @@ __global__ void k_exp_hadamard(int k, int R, int n, int ra, int rb, const double
   }
 }
 
-void Precond::setup(Problem& P) {
+static std::shared_ptr<EigenBasis> eigenbasis(Problem& P, int d) {
   Context& ctx = *P.ctx;
   const int p = P.p, band = 2 * p + 1;
+  const int n = P.n[d], Q = P.Q[d], m = P.hi[d] - P.lo[d];
+  const std::array<int, 5> key = {n, p, P.g, P.lo[d], P.hi[d]};
+  auto it = ctx.plans.find(key);
+  if (it != ctx.plans.end()) return std::static_pointer_cast<EigenBasis>(it->second);
+  auto e = std::make_shared<EigenBasis>();
+  e->ni = m;
+  DBuf ones(&ctx.alloc, sizeof(double) * Q);
+  fill(ctx, ones.d(), Q, 1.0);
+  DBuf mb(&ctx.alloc, sizeof(double) * n * band), ab(&ctx.alloc, sizeof(double) * n * band);
+  launch_assemble_band(ctx, n, p, P.g, 1, 1, ones.d(), P.tab_w[d].d(), P.tab_B[d].d(), P.tab_B[d].d(), mb.d());
+  launch_assemble_band(ctx, n, p, P.g, 1, 1, ones.d(), P.tab_w[d].d(), P.tab_D[d].d(), P.tab_D[d].d(), ab.d());
+  DBuf mi(&ctx.alloc, sizeof(double) * m * band), ai(&ctx.alloc, sizeof(double) * m * band);
+  launch_slice_band(ctx, n, p, P.lo[d], m, 1, 1, mb.d(), mi.d());
+  launch_slice_band(ctx, n, p, P.lo[d], m, 1, 1, ab.d(), ai.d());
+  DBuf Md(&ctx.alloc, sizeof(double) * m * m), Ad(&ctx.alloc, sizeof(double) * m * m);
+  hipLaunchKernelGGL(k_band_to_dense, dim3(grid_for((long)m * m)), dim3(256), 0, ctx.stream, m, p, mi.d(), Md.d());
+  hipLaunchKernelGGL(k_band_to_dense, dim3(grid_for((long)m * m)), dim3(256), 0, ctx.stream, m, p, ai.d(), Ad.d());
+  TTIGA_HIP(hipGetLastError());
+  DBuf Rm(&ctx.alloc, sizeof(double) * m * m), Rmi(&ctx.alloc, sizeof(double) * m * m);
+  TTIGA_CHECK(cholesky_inverse(ctx, Md.d(), m, Rm.d(), Rmi.d()), TTIGA_E_ARG,
+              "1-D mass matrix is not positive definite");
+  // S = Rmi^T A Rmi, symmetric positive semi-definite; its SVD is its eigendecomposition
+  DBuf T1(&ctx.alloc, sizeof(double) * m * m), S(&ctx.alloc, sizeof(double) * m * m);
+  gemm(ctx, false, false, m, m, m, 1.0, Ad.d(), m, 0, Rmi.d(), m, 0, 0.0, T1.d(), m, 0);
+  gemm(ctx, true, false, m, m, m, 1.0, Rmi.d(), m, 0, T1.d(), m, 0, 0.0, S.d(), m, 0);
+  DBuf U(&ctx.alloc, sizeof(double) * m * m), W(&ctx.alloc, sizeof(double) * m * m);
+  e->lam = DBuf(&ctx.alloc, sizeof(double) * m);
+  svd_small(ctx, S.d(), false, m, m, m, U.d(), e->lam.d(), W.d());
+  e->V = DBuf(&ctx.alloc, sizeof(double) * m * m);
+  gemm(ctx, false, false, m, m, m, 1.0, Rmi.d(), m, 0, W.d(), m, 0, 0.0, e->V.d(), m, 0);
+  double* h = ctx.host(2);
+  TTIGA_HIP(hipMemcpyAsync(h, e->lam.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  TTIGA_HIP(hipMemcpyAsync(h + 1, e->lam.d() + (m - 1), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  e->lam_max = h[0];
+  e->lam_min = h[1];
+  ctx.plans[key] = e;
+  return e;
+}
+
+void Precond::setup(Problem& P) {
+  Context& ctx = *P.ctx;
   for (int d = 0; d < 3; ++d) {
-    const int n = P.n[d], Q = P.Q[d], m = P.hi[d] - P.lo[d];
-    ni[d] = m;
-    DBuf ones(&ctx.alloc, sizeof(double) * Q);
-    fill(ctx, ones.d(), Q, 1.0);
-    DBuf mb(&ctx.alloc, sizeof(double) * n * band), ab(&ctx.alloc, sizeof(double) * n * band);
-    launch_assemble_band(ctx, n, p, P.g, 1, 1, ones.d(), P.tab_w[d].d(), P.tab_B[d].d(), P.tab_B[d].d(), mb.d());
-    launch_assemble_band(ctx, n, p, P.g, 1, 1, ones.d(), P.tab_w[d].d(), P.tab_D[d].d(), P.tab_D[d].d(), ab.d());
-    DBuf mi(&ctx.alloc, sizeof(double) * m * band), ai(&ctx.alloc, sizeof(double) * m * band);
-    launch_slice_band(ctx, n, p, P.lo[d], m, 1, 1, mb.d(), mi.d());
-    launch_slice_band(ctx, n, p, P.lo[d], m, 1, 1, ab.d(), ai.d());
-    DBuf Md(&ctx.alloc, sizeof(double) * m * m), Ad(&ctx.alloc, sizeof(double) * m * m);
-    hipLaunchKernelGGL(k_band_to_dense, dim3(grid_for((long)m * m)), dim3(256), 0, ctx.stream, m, p, mi.d(), Md.d());
-    hipLaunchKernelGGL(k_band_to_dense, dim3(grid_for((long)m * m)), dim3(256), 0, ctx.stream, m, p, ai.d(), Ad.d());
-    TTIGA_HIP(hipGetLastError());
-    DBuf Rm(&ctx.alloc, sizeof(double) * m * m), Rmi(&ctx.alloc, sizeof(double) * m * m);
-    TTIGA_CHECK(cholesky_inverse(ctx, Md.d(), m, Rm.d(), Rmi.d()), TTIGA_E_ARG,
-                "1-D mass matrix is not positive definite");
-    // S = Rmi^T A Rmi, symmetric positive semi-definite; its SVD is its eigendecomposition
-    DBuf T1(&ctx.alloc, sizeof(double) * m * m), S(&ctx.alloc, sizeof(double) * m * m);
-    gemm(ctx, false, false, m, m, m, 1.0, Ad.d(), m, 0, Rmi.d(), m, 0, 0.0, T1.d(), m, 0);
-    gemm(ctx, true, false, m, m, m, 1.0, Rmi.d(), m, 0, T1.d(), m, 0, 0.0, S.d(), m, 0);
-    DBuf U(&ctx.alloc, sizeof(double) * m * m), W(&ctx.alloc, sizeof(double) * m * m);
-    lam[d] = DBuf(&ctx.alloc, sizeof(double) * m);
-    svd_small(ctx, S.d(), false, m, m, m, U.d(), lam[d].d(), W.d());
-    V[d] = DBuf(&ctx.alloc, sizeof(double) * m * m);
-    gemm(ctx, false, false, m, m, m, 1.0, Rmi.d(), m, 0, W.d(), m, 0, 0.0, V[d].d(), m, 0);
-    double* h = ctx.host(2);
-    TTIGA_HIP(hipMemcpyAsync(h, lam[d].d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-    TTIGA_HIP(hipMemcpyAsync(h + 1, lam[d].d() + (m - 1), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-    ctx.sync();
-    lam_max[d] = h[0];
-    lam_min[d] = h[1];
+    eb[d] = eigenbasis(P, d);
+    ni[d] = eb[d]->ni;
+    lam_min[d] = eb[d]->lam_min;
+    lam_max[d] = eb[d]->lam_max;
   }
   // c_d = mean of R_dd over the parametric cube, from its TT cores
   for (int d = 0; d < 3; ++d) {
@@ -181,7 +197,7 @@ void Precond::setup(Problem& P) {
   for (int d = 0; d < 3; ++d) {
     etab[d] = DBuf(&ctx.alloc, sizeof(double) * R * ni[d]);
     hipLaunchKernelGGL(k_exp_table, dim3(grid_for((long)R * ni[d])), dim3(256), 0, ctx.stream, R, ni[d],
-                       dtau.d(), d == 0 ? dw.d() : d1.d(), c[d], lam[d].d(), etab[d].d());
+                       dtau.d(), d == 0 ? dw.d() : d1.d(), c[d], eb[d]->lam.d(), etab[d].d());
   }
   TTIGA_HIP(hipGetLastError());
   ctx.sync();  // host vectors above go out of scope
@@ -195,7 +211,7 @@ void Precond::apply(Context& ctx, const TT& r, TT& z, double eps, int max_rank, 
   }
   TT w;
   tt_copy(ctx, r, w);
-  for (int d = 0; d < 3; ++d) tt_mode_product(ctx, w, d, V[d].d(), true);
+  for (int d = 0; d < 3; ++d) tt_mode_product(ctx, w, d, eb[d]->V.d(), true);
   int rr[4] = {1, R * w.r[1], R * w.r[2], 1};
   TT hz;
   hz.alloc(ctx, w.n, rr);
@@ -207,7 +223,7 @@ void Precond::apply(Context& ctx, const TT& r, TT& z, double eps, int max_rank, 
   }
   TTIGA_HIP(hipGetLastError());
   tt_round_auto(ctx, hz, eps, max_rank, hint);
-  for (int d = 0; d < 3; ++d) tt_mode_product(ctx, hz, d, V[d].d(), false);
+  for (int d = 0; d < 3; ++d) tt_mode_product(ctx, hz, d, eb[d]->V.d(), false);
   z = std::move(hz);
 }
 

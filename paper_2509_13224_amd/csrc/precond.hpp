@@ -7,10 +7,21 @@ namespace ttiga {
 
 struct Problem;
 
+// Generalised eigenbasis of the 1-D interior stiffness/mass pencil (a, m) of one
+// direction: V^T m V = I, V^T a V = diag(lam), eigenvalues descending.  It depends
+// only on the knot vector, degree, quadrature and the boundary cut, so it is
+// computed once per discretisation and shared.
+struct EigenBasis {
+  int ni = 0;
+  DBuf V, lam;
+  double lam_min = 0.0, lam_max = 0.0;
+};
+
 struct Precond {
   bool ready = false;
   int ni[3] = {0, 0, 0};
-  DBuf V[3], lam[3], etab[3];
+  std::shared_ptr<EigenBasis> eb[3];
+  DBuf etab[3];
   double c[3] = {1, 1, 1};
   double lam_min[3] = {0, 0, 0}, lam_max[3] = {0, 0, 0};
   double s_min = 0, s_max = 0, approx_err = 0;

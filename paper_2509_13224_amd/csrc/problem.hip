@@ -373,7 +373,9 @@ void Problem::solve(ttiga_solve_stats* st) {
     s.rel_res = 0.0;
     s.status = TTIGA_OK;
   } else if (opts.precond) {
+    const double ts = now_ms();
     if (!pc.ready) pc.setup(*this);
+    s.precond_setup_ms = now_ms() - ts;
     solve_pcg(s);
   } else {
     solve_cg(s);
@@ -468,7 +470,12 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
 }
 
 // Flexible preconditioned truncated TT-CG (Polak-Ribiere beta, clipped at 0),
-// preconditioner applied with a loose re-compression.  With the preconditioner
+// preconditioner applied with a loose re-compression.  The directions, residuals and
+// products shrink with the error, so they are truncated with a relaxed relative
+// tolerance eps_k = 0.1 tol / est_k (est_k the current error estimate, capped at 1e-3):
+// their absolute truncation error stays at the tol level, as in relaxed inexact
+// Krylov methods, instead of resolving ever finer detail of ever smaller vectors
+// (which makes their TT ranks grow every iteration).  With the preconditioner
 // the stopping test is ||P^-1 r|| <= tol ||x||: since P^-1 K is close to the
 // identity, P^-1 r estimates the error x - u itself, so the test bounds the
 // relative 2-norm error of the iterate; the plain residual of a truncated iterate
@@ -478,11 +485,12 @@ void Problem::solve_pcg(ttiga_solve_stats& s) {
   Context& c = *ctx;
   const double tol = opts.rel_res_tol;
   // every rounding inside the iteration injects a relative error into the residual
-  // recursion, so it must sit below the residual target; the iterate is kept a decade
-  // tighter still, the preconditioner only needs two digits
-  const double eps = std::min(opts.tt_eps, 0.3 * tol);
-  const double eps_x = std::min(opts.tt_eps, 0.1 * tol);
-  const double eps_p = std::max(eps, 1e-2);
+  // recursion, so it must sit below the error target; truncating the iterate by a
+  // relative delta moves P^-1 r by about delta (P^-1 K is near the identity), so the
+  // iterate takes the same tolerance; the preconditioner only needs two digits
+  const double eps0 = std::min(opts.tt_eps, 0.3 * tol);
+  const double eps_x = std::min(opts.tt_eps, 0.3 * tol);
+  double eps = eps0;
   double best = 1.0;
   int best_it = 0;
   int max_seen = 0;
@@ -493,7 +501,8 @@ void Problem::solve_pcg(ttiga_solve_stats& s) {
   TT r, z, pdir;
   tt_copy(c, rhs, r);
   int hq = 8, hx = 8, hr = 8, hp = 8, hz = 8;
-  pc.apply(c, r, z, eps_p, opts.max_rank, hz);
+  auto eps_p = [&]() { return std::max(eps, 1e-2); };
+  pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
   tt_copy(c, z, pdir);
   double rho = tt_dot_sync(c, r, z);
   int it = 0;
@@ -520,7 +529,7 @@ void Problem::solve_pcg(ttiga_solve_stats& s) {
       true_res = true_residual(c, KII, p, rhs, u, nb, eps_x, opts.max_rank, r, hr);
       replaced = true;
     }
-    pc.apply(c, r, z, eps_p, opts.max_rank, hz);
+    pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
     seen(z);
     double rho_new = tt_dot_sync(c, r, z);
     auto err_est = [&]() {
@@ -530,7 +539,7 @@ void Problem::solve_pcg(ttiga_solve_stats& s) {
     pres = err_est();
     if (pres <= tol && !replaced) {
       true_res = true_residual(c, KII, p, rhs, u, nb, eps_x, opts.max_rank, r, hr);
-      pc.apply(c, r, z, eps_p, opts.max_rank, hz);
+      pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
       rho_new = tt_dot_sync(c, r, z);
       pres = err_est();
     }
@@ -538,6 +547,7 @@ void Problem::solve_pcg(ttiga_solve_stats& s) {
       conv = true;
       break;
     }
+    eps = std::min(1e-3, std::max(eps0, 0.1 * tol / std::max(pres, 1e-300)));
     // stagnation: no halving of the best preconditioned residual in 15 iterations
     if (pres < 0.5 * best) {
       best = pres;

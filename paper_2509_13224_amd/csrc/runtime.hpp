@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstddef>
 #include <cstdint>
 #include <map>
@@ -92,6 +93,7 @@ struct KernelStat {
 
 struct Profiler {
   bool on = false;
+  bool detail = false;  // append a size bucket to kernel names (diagnostics)
   std::map<std::string, KernelStat> stats;
   struct Pending {
     std::string name;
@@ -110,12 +112,13 @@ struct Context;
 // Records events around the launches issued while it lives (when profiling is on).
 class ProfScope {
  public:
-  ProfScope(Context& c, const char* name, double flops, double bytes);
+  // size >= 0 is bucketed into the name when detailed profiling is on
+  ProfScope(Context& c, const char* name, double flops, double bytes, int size = -1);
   ~ProfScope();
 
  private:
   Context* c_;
-  const char* name_;
+  std::string name_;
   double flops_, bytes_;
   hipEvent_t a_ = nullptr;
 };
@@ -125,6 +128,10 @@ struct Context {
   int device = 0;
   hipStream_t stream = nullptr;
   DeviceAllocator alloc;
+  // discretisation-level plans reused across problems (the 1-D eigenbases of the
+  // preconditioner), keyed by (n, p, g, lo, hi); declared after the allocator so
+  // they are released before it
+  std::map<std::array<int, 5>, std::shared_ptr<void>> plans;
   // pinned host staging for small readbacks (ranks, scalars)
   double* host_scratch = nullptr;
   size_t host_scratch_doubles = 0;

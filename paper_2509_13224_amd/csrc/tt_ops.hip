@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "runtime.hpp"
 
@@ -485,9 +487,19 @@ static void tt_sketch_project(Context& ctx, const TT& x, int l1, int l2, TT& y) 
   y.c[2] = std::move(C3);
 }
 
+static bool trace_rounding() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("TTIGA_TRACE_ROUND");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
 void tt_round_auto(Context& ctx, TT& x, double eps_rel, int max_rank, int& hint) {
   if (x.zero()) return;
   int l = std::max(hint, 1) + 10;
+  const int in1 = x.r[1], in2 = x.r[2];
   while (true) {
     const int l1 = std::min(l, std::min(x.r[1], x.n[0]));
     const int l2 = std::min(l, std::min(x.r[2], x.n[2]));
@@ -496,6 +508,8 @@ void tt_round_auto(Context& ctx, TT& x, double eps_rel, int max_rank, int& hint)
     if ((x.r[1] <= l1 + 6 && x.r[2] <= l2 + 6) || l1 * x.n[1] < l2) {
       tt_round(ctx, x, eps_rel, -1.0, max_rank);
       hint = x.zero() ? 1 : std::max(x.r[1], x.r[2]);
+      if (trace_rounding())
+        std::fprintf(stderr, "[round] det in (%d,%d) l %d eps %.1e -> (%d,%d)\n", in1, in2, l, eps_rel, x.r[1], x.r[2]);
       return;
     }
     TT y;
@@ -512,6 +526,8 @@ void tt_round_auto(Context& ctx, TT& x, double eps_rel, int max_rank, int& hint)
       continue;
     }
     hint = std::max(y.r[1], y.r[2]);
+    if (trace_rounding())
+      std::fprintf(stderr, "[round] rnd in (%d,%d) l (%d,%d) eps %.1e -> (%d,%d)\n", in1, in2, l1, l2, eps_rel, y.r[1], y.r[2]);
     x = std::move(y);
     return;
   }

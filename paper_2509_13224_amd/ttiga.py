@@ -76,7 +76,7 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("rel_pres", ctypes.c_double), ("rank_u", ctypes.c_int * 4), ("max_rank_seen", ctypes.c_int),
                 ("precond_terms", ctypes.c_int), ("precond_err", ctypes.c_double),
-                ("time_ms", ctypes.c_double)]
+                ("precond_setup_ms", ctypes.c_double), ("time_ms", ctypes.c_double)]
 
 
 class TTView(ctypes.Structure):
@@ -375,7 +375,7 @@ class ProblemHandle:
         code = _check(self.lib, self.lib.ttiga_solve(self.h, ctypes.byref(st)), ok)
         return dict(status=code, iterations=st.iterations, rel_res=st.rel_res, rel_pres=st.rel_pres,
                     rank_u=list(st.rank_u), max_rank_seen=st.max_rank_seen, precond_terms=st.precond_terms,
-                    precond_err=st.precond_err, time_ms=st.time_ms)
+                    precond_err=st.precond_err, precond_setup_ms=st.precond_setup_ms, time_ms=st.time_ms)
 
     def solution(self):
         r = (ctypes.c_int * 4)()
