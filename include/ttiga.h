@@ -123,6 +123,11 @@ typedef struct {
   int max_rank;       /* cap on every TT rank; exceeding it fails with E_RANKCAP */
   int precision;      /* TTIGA_FP64 (others: E_ARG in this version) */
   int precond;        /* 1: separable Laplacian preconditioner, 0: plain TT-CG */
+  size_t sample_chunk_bytes; /* 0: automatic (the Gauss-grid factor samples are held whole
+                         up to 2 GiB, beyond that sampled and compressed in chunks of
+                         second-direction slabs of at most 2 GiB); > 0: always stream in
+                         chunks of at most this many bytes (at least one slab) when the
+                         first direction has more than 64 Gauss points */
 } ttiga_options;
 
 typedef struct {

@@ -30,8 +30,10 @@ void launch_basis_tables(Context& ctx, int n, int p, int g, const double* knots,
                          double* w, double* B, double* D);
 void launch_geo_tables(Context& ctx, int count, const double* xi, int stride, int nb, int pg,
                        const double* knots, int* span, double* B, double* D);
+// Samples the slabs b0 .. b0+c1-1 of the second direction into F[7][Q0][c1][Q2]; stats8
+// receives (or, with accumulate, is merged with) the 7 sums of squares and min det J.
 void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, const int* Q,
-                         double* F, double* stats8);
+                         int b0, int c1, double* F, double* stats8, bool accumulate = false);
 void launch_factors_points(Context& ctx, const GeoDev& geo, const SourceDev& src, long count,
                            double* out, double* det);
 void launch_assemble_band(Context& ctx, int n, int p, int g, int ra, int rb, const double* G,

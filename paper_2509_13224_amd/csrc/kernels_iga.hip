@@ -223,20 +223,21 @@ __device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, i
   *det_out = det;
 }
 
-// Gauss-grid sampling: thread per point (i0, i1, i2), i2 fastest; factor-major output
-// F[f][(i0 Q1 + i1) Q2 + i2].  Per-block partial sums of squares of the 7 factors and
-// the minimum det J go to part[block][8].
-__global__ __launch_bounds__(256) void k_factors_grid(GeoDev geo, SourceDev src, int Q0, int Q1,
-                                                      int Q2, double* __restrict__ F,
+// Gauss-grid sampling of the slabs b0 .. b0+c1-1 of the second direction (all of the
+// first and third): thread per point (i0, i1, i2), i2 fastest; factor-major output
+// F[f][(i0 c1 + i1 - b0) Q2 + i2].  Per-block partial sums of squares of the 7 factors
+// and the minimum det J go to part[block][8].
+__global__ __launch_bounds__(256) void k_factors_grid(GeoDev geo, SourceDev src, int Q0, int b0,
+                                                      int c1, int Q2, double* __restrict__ F,
                                                       double* __restrict__ part) {
   __shared__ double sh[8][256];
-  const long total = (long)Q0 * Q1 * Q2;
+  const long total = (long)Q0 * c1 * Q2;
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 1e300};
   if (e < total) {
     const int i2 = e % Q2;
-    const int i1 = (e / Q2) % Q1;
-    const int i0 = e / ((long)Q1 * Q2);
+    const int i1 = b0 + (int)((e / Q2) % c1);
+    const int i0 = (int)(e / ((long)c1 * Q2));
     double v[7], det;
     point_factors(geo, src, i0, i1, i2, v, &det);
     for (int f = 0; f < 7; ++f) {
@@ -257,7 +258,10 @@ __global__ __launch_bounds__(256) void k_factors_grid(GeoDev geo, SourceDev src,
   if (threadIdx.x < 8) part[(long)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_factors_reduce(const double* __restrict__ part, long blocks, double* __restrict__ out) {
+// Reduces the per-block partials; with accumulate the result is merged into out
+// (sums added, minimum kept), so slabs sampled one chunk after another give one total.
+__global__ void k_factors_reduce(const double* __restrict__ part, long blocks, int accumulate,
+                                 double* __restrict__ out) {
   __shared__ double sh[8][256];
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 1e300};
   for (long b = threadIdx.x; b < blocks; b += blockDim.x) {
@@ -273,7 +277,12 @@ __global__ void k_factors_reduce(const double* __restrict__ part, long blocks, d
     }
     __syncthreads();
   }
-  if (threadIdx.x < 8) out[threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < 8) {
+    const double v = sh[threadIdx.x][0];
+    if (!accumulate) out[threadIdx.x] = v;
+    else if (threadIdx.x < 7) out[threadIdx.x] += v;
+    else out[7] = fmin(out[7], v);
+  }
 }
 
 // Scattered points: the geometry tables are indexed by the point itself in all directions.
@@ -400,8 +409,9 @@ void launch_geo_tables(Context& ctx, int count, const double* xi, int stride, in
 }
 
 void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, const int* Q,
-                         double* F, double* stats8) {
-  const long total = (long)Q[0] * Q[1] * Q[2];
+                         int b0, int c1, double* F, double* stats8, bool accumulate) {
+  TTIGA_CHECK(b0 >= 0 && c1 > 0 && b0 + c1 <= Q[1], TTIGA_E_ARG, "factor slab range out of the grid");
+  const long total = (long)Q[0] * c1 * Q[2];
   const long blocks = (total + 255) / 256;
   DBuf part(&ctx.alloc, sizeof(double) * 8 * blocks);
   // per point: homogeneous map and its three derivatives over the (p_g+1)^3 local net
@@ -411,8 +421,9 @@ void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, 
   const double per_pt = pg0 * pg1 * (16.0 * pg2 + 35.0) + 150.0 + (double)src.n_modes * 10.0;
   ProfScope prof(ctx, "geometry_factors", per_pt * total, 56.0 * total);
   hipLaunchKernelGGL(k_factors_grid, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, geo, src, Q[0],
-                     Q[1], Q[2], F, part.d());
-  hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks, stats8);
+                     b0, c1, Q[2], F, part.d());
+  hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks,
+                     accumulate ? 1 : 0, stats8);
   TTIGA_HIP(hipGetLastError());
 }
 

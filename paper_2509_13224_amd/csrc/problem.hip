@@ -221,36 +221,58 @@ void Problem::assemble(ttiga_assembly_stats* st) {
   ttiga_assembly_stats s{};
   double t0 = now_ms();
   build_tables();
-  // 2. factor tensors on the Gauss grid
+  // 2. factor tensors on the Gauss grid, 3. TT compression
   const size_t total = (size_t)Q[0] * Q[1] * Q[2];
-  DBuf Fac(&c.alloc, sizeof(double) * 7 * total);
+  const size_t slab_bytes = sizeof(double) * 7 * (size_t)Q[0] * Q[2];
+  const size_t kWholeLimit = size_t(2) << 30;
+  const bool streamed = (opts.sample_chunk_bytes > 0 || slab_bytes * Q[1] > kWholeLimit) &&
+                        Q[0] > kExactSvdSize && (size_t)Q[1] * Q[2] > (size_t)kExactSvdSize;
+  const GeoDev gd = geo_dev(gtab_span, gtab_B, gtab_D);
+  const SourceDev sd = source_dev();
   DBuf st8(&c.alloc, sizeof(double) * 8);
-  launch_factors_grid(c, geo_dev(gtab_span, gtab_B, gtab_D), source_dev(), Q, Fac.d(), st8.d());
-  double* h = c.host(8);
-  TTIGA_HIP(hipMemcpyAsync(h, st8.d(), 8 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-  c.sync();
-  double sumsq[7];
-  for (int f = 0; f < 7; ++f) sumsq[f] = h[f];
-  s.min_detJ = h[7];
-  double rmax = 0.0;
-  for (int f = 0; f < 6; ++f) rmax = std::max(rmax, std::sqrt(sumsq[f]));
-  s.max_R_norm = rmax;
-  min_detJ = s.min_detJ;
-  if (!(s.min_detJ > 0.0))
-    throw Error(TTIGA_E_DETJ, "min det J = " + std::to_string(s.min_detJ) + " <= 0 on the Gauss grid");
-  double t1 = now_ms();
-  s.time_ms[0] = t1 - t0;
-  // 3. TT compression
   const double eps = opts.tt_eps;
-  const double dR = eps * rmax / std::sqrt(2.0);
-  const double dF = eps * std::sqrt(sumsq[6]) / std::sqrt(2.0);
-  for (int f = 0; f < 7; ++f) {
-    TT& dst = (f < 6) ? R[f] : fJ;
-    if (f < 6 && sumsq[f] == 0.0) { dst.set_zero(Q); continue; }
-    if (f == 6 && sumsq[6] == 0.0) { dst.set_zero(Q); continue; }
-    tt_compress_dense(c, Fac.d() + f * total, Q, f < 6 ? dR : dF, dst, opts.max_rank);
+  double t1 = 0.0;
+  // norms, det J check and the compression thresholds from the 8 gathered statistics
+  auto thresholds = [&](std::vector<double>& delta) {
+    double* h = c.host(8);
+    TTIGA_HIP(hipMemcpyAsync(h, st8.d(), 8 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    double sumsq[7];
+    for (int f = 0; f < 7; ++f) sumsq[f] = h[f];
+    s.min_detJ = h[7];
+    double rmax = 0.0;
+    for (int f = 0; f < 6; ++f) rmax = std::max(rmax, std::sqrt(sumsq[f]));
+    s.max_R_norm = rmax;
+    min_detJ = s.min_detJ;
+    if (!(s.min_detJ > 0.0))
+      throw Error(TTIGA_E_DETJ, "min det J = " + std::to_string(s.min_detJ) + " <= 0 on the Gauss grid");
+    const double dR = eps * rmax / std::sqrt(2.0);
+    const double dF = eps * std::sqrt(sumsq[6]) / std::sqrt(2.0);
+    delta.assign(7, 0.0);
+    for (int f = 0; f < 7; ++f) delta[f] = (sumsq[f] == 0.0) ? -1.0 : (f < 6 ? dR : dF);
+    t1 = now_ms();
+    s.time_ms[0] = t1 - t0;
+  };
+  TT fac[7];
+  if (streamed) {
+    const size_t budget = opts.sample_chunk_bytes > 0 ? opts.sample_chunk_bytes : kWholeLimit;
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(Q[1], budget / slab_bytes));
+    auto produce = [&](int b, int cnt, double* buf) {
+      launch_factors_grid(c, gd, sd, Q, b, cnt, buf, st8.d(), b > 0);
+    };
+    tt_compress_streamed(c, 7, Q, chunk, produce, thresholds, fac, opts.max_rank);
+  } else {
+    DBuf Fac(&c.alloc, sizeof(double) * 7 * total);
+    launch_factors_grid(c, gd, sd, Q, 0, Q[1], Fac.d(), st8.d(), false);
+    std::vector<double> delta;
+    thresholds(delta);
+    for (int f = 0; f < 7; ++f) {
+      if (delta[f] < 0.0) { fac[f].set_zero(Q); continue; }
+      tt_compress_dense(c, Fac.d() + f * total, Q, delta[f], fac[f], opts.max_rank);
+    }
   }
-  Fac.reset();
+  for (int f = 0; f < 6; ++f) R[f] = std::move(fac[f]);
+  fJ = std::move(fac[6]);
   c.sync();
   double t2 = now_ms();
   s.time_ms[1] = t2 - t1;

@@ -7,6 +7,7 @@
 #include <array>
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -211,5 +212,15 @@ void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y);
 void tt_compress_dense(Context& ctx, const double* A, const int* n, double delta, TT& out,
                        int max_rank);
 void tt_copy(Context& ctx, const TT& src, TT& dst);
+// Streamed TT-SVD of nt tensors of shape n produced in chunks of second-direction slabs:
+// produce(b, c, buf) writes slabs b .. b+c-1 of every tensor into buf[t][n0][c][n2];
+// thresholds(delta) is called once, after the first pass, and sets the absolute
+// per-unfolding thresholds (negative: the tensor is zero).
+using ChunkFn = std::function<void(int a, int c, double* buf)>;
+using ThresholdFn = std::function<void(std::vector<double>& delta)>;
+void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const ChunkFn& produce,
+                          const ThresholdFn& thresholds, TT* out, int max_rank);
+// Sizes at or below which TT-SVD unfoldings are factored exactly instead of sketched.
+constexpr int kExactSvdSize = 64;
 
 }  // namespace ttiga

@@ -381,7 +381,7 @@ void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_ran
 // otherwise a randomised range finder: Y = A * Omega with Gaussian Omega (M x l),
 // U_y = orth(Y), B = U_y^T A, truncated SVD of B; the sketch width l starts at 48
 // and doubles while the truncated rank leaves fewer than 12 spare columns.
-static constexpr int kExact = 64;
+static constexpr int kExact = kExactSvdSize;
 
 static int left_factor(Context& ctx, const double* A, int m, long M, double delta, DBuf& U,
                        DBuf& C) {
@@ -442,6 +442,122 @@ void tt_compress_dense(Context& ctx, const double* A, const int* n, double delta
   out.c[0] = std::move(U0);
   out.c[1] = std::move(U1);
   out.c[2] = std::move(C1);
+}
+
+// Slab-streamed TT-SVD of nt tensors A_t[n0][n1][n2] that exist only one chunk of
+// second-direction slabs (all i0, a range of i1, all i2) at a time.  The first
+// unfolding A_t (n0 x n1 n2) goes through the randomised range finder in two passes over
+// the chunks: Y_t = A_t Omega (n0 x l, one Gaussian Omega shared by all tensors) summed
+// over the column blocks, Q_t = orth(Y_t), then B_t = Q_t^T A_t (l x n1 n2), one column
+// block per chunk; the truncated SVD of B_t gives the first core Q_t U_s and
+// C_t = S_s V_s^T, which is factored like a dense tensor.  The thresholds are set after
+// the first pass (they depend on norms gathered while producing); a negative threshold
+// marks a tensor as exactly zero.  A tensor whose truncated rank leaves fewer than 12
+// spare sketch columns is redone with twice the width.
+void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const ChunkFn& produce,
+                          const ThresholdFn& thresholds, TT* out, int max_rank) {
+  const int n0 = n[0], n1 = n[1], n2 = n[2];
+  const long M = (long)n1 * n2;
+  TTIGA_CHECK(nt > 0 && chunk > 0 && n0 > kExact && M > kExact && M <= INT32_MAX, TTIGA_E_ARG,
+              "streamed compression needs more than 64 rows and columns");
+  chunk = std::min(chunk, n1);
+  DBuf buf(&ctx.alloc, sizeof(double) * (size_t)nt * n0 * chunk * n2);
+  std::vector<double> delta(nt, 0.0);
+  std::vector<char> todo(nt, 1);
+  bool have_delta = false;
+  int L = std::min(n0, 48);
+  while (true) {
+    bool any = false;
+    for (int t = 0; t < nt; ++t) any = any || todo[t];
+    if (!any) break;
+    // pass 1: range sketches, summed over the column blocks
+    std::vector<DBuf> Y(nt);
+    {
+      DBuf Om(&ctx.alloc, sizeof(double) * (size_t)M * L);
+      hipLaunchKernelGGL(k_gaussian, dim3(grid_for(M * L)), dim3(256), 0, ctx.stream, Om.d(), M * L,
+                         ++ctx.rng_counter);
+      TTIGA_HIP(hipGetLastError());
+      for (int t = 0; t < nt; ++t)
+        if (todo[t]) Y[t] = DBuf(&ctx.alloc, sizeof(double) * (size_t)n0 * L);
+      for (int b = 0; b < n1; b += chunk) {
+        const int c = std::min(chunk, n1 - b);
+        const long w = (long)c * n2;
+        produce(b, c, buf.d());
+        for (int t = 0; t < nt; ++t)
+          if (todo[t])
+            gemm(ctx, false, false, n0, L, (int)w, 1.0, buf.d() + (size_t)t * n0 * w, w, 0,
+                 Om.d() + (size_t)b * n2 * L, L, 0, b == 0 ? 0.0 : 1.0, Y[t].d(), L, 0);
+      }
+    }
+    if (!have_delta) {
+      thresholds(delta);
+      have_delta = true;
+      for (int t = 0; t < nt; ++t)
+        if (delta[t] < 0.0) {
+          todo[t] = 0;
+          out[t].set_zero(n);
+          Y[t].reset();
+        }
+    }
+    // orthonormal bases of the sketches
+    std::vector<DBuf> Qy(nt), B(nt);
+    for (int t = 0; t < nt; ++t) {
+      if (!todo[t]) continue;
+      Qy[t] = DBuf(&ctx.alloc, sizeof(double) * (size_t)n0 * L);
+      DBuf Ry(&ctx.alloc, sizeof(double) * L * L);
+      qr_tall(ctx, Y[t].d(), false, n0, L, L, Qy[t].d(), Ry.d());
+      Y[t].reset();
+      B[t] = DBuf(&ctx.alloc, sizeof(double) * (size_t)L * M);
+    }
+    // pass 2: projections B_t = Q_t^T A_t, one column block per chunk
+    for (int b = 0; b < n1; b += chunk) {
+      const int c = std::min(chunk, n1 - b);
+      const long w = (long)c * n2;
+      produce(b, c, buf.d());
+      for (int t = 0; t < nt; ++t)
+        if (todo[t])
+          gemm(ctx, true, false, L, (int)w, n0, 1.0, Qy[t].d(), L, 0, buf.d() + (size_t)t * n0 * w, w,
+               0, 0.0, B[t].d() + (size_t)b * n2, M, 0);
+    }
+    bool widen = false;
+    for (int t = 0; t < nt; ++t) {
+      if (!todo[t]) continue;
+      TruncSVD sv = truncated_svd(ctx, B[t].d(), L, M, delta[t]);
+      B[t].reset();
+      if (sv.s == 0) {
+        out[t].set_zero(n);
+        todo[t] = 0;
+        continue;
+      }
+      if (sv.s > L - 12 && L < n0) {
+        widen = true;
+        continue;
+      }
+      const int s0 = sv.s;
+      DBuf U0(&ctx.alloc, sizeof(double) * (size_t)n0 * s0);
+      gemm(ctx, false, false, n0, s0, L, 1.0, Qy[t].d(), L, 0, sv.U.d(), s0, 0, 0.0, U0.d(), s0, 0);
+      DBuf C0(&ctx.alloc, sizeof(double) * (size_t)s0 * M);
+      hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)s0 * M)), dim3(256), 0, ctx.stream,
+                         sv.Vt.d(), s0, M, sv.S.d(), C0.d());
+      TTIGA_HIP(hipGetLastError());
+      DBuf U1, C1;
+      const int s1 = left_factor(ctx, C0.d(), s0 * n1, n2, delta[t], U1, C1);
+      todo[t] = 0;
+      if (s1 == 0) {
+        out[t].set_zero(n);
+        continue;
+      }
+      if (max_rank > 0 && (s0 > max_rank || s1 > max_rank))
+        throw Error(TTIGA_E_RANKCAP, "compressed factor rank exceeds max_rank");
+      TT& o = out[t];
+      for (int k = 0; k < 3; ++k) o.n[k] = n[k];
+      o.r[0] = 1; o.r[1] = s0; o.r[2] = s1; o.r[3] = 1;
+      o.c[0] = std::move(U0);
+      o.c[1] = std::move(U1);
+      o.c[2] = std::move(C1);
+    }
+    if (widen) L = std::min(n0, 2 * L);
+  }
 }
 
 // Randomised projection of x onto ranks (l1, l2): Gaussian TT Omega with cores

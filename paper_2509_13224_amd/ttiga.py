@@ -62,7 +62,8 @@ class Dirichlet(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("tt_eps", ctypes.c_double), ("rel_res_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("max_rank", ctypes.c_int),
-                ("precision", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("precond", ctypes.c_int),
+                ("sample_chunk_bytes", ctypes.c_size_t)]
 
 
 class AssemblyStats(ctypes.Structure):
@@ -328,6 +329,7 @@ def describe(pr, precond=0):
     o.max_rank = pr.options.max_rank
     o.precision = pr.options.precision
     o.precond = precond
+    o.sample_chunk_bytes = int(getattr(pr.options, "sample_chunk_bytes", 0))
     return (g, disc, src, bc, o), keep
 
 

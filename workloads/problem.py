@@ -91,6 +91,7 @@ class Options:
     max_rank: int = 256
     precision: int = PREC_FP64
     refine: int = 1
+    sample_chunk_bytes: int = 0  # 0: automatic; > 0: stream the Gauss-grid sampling in chunks
 
 
 @dataclass
