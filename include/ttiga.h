@@ -267,6 +267,84 @@ int ttiga_profile_read(ttiga_ctx* ctx, ttiga_kernel_stat* out, int capacity, int
 int ttiga_tt_info(const ttiga_tt* t, int ranks[4], int n[3]);
 int ttiga_tt_copy(const ttiga_tt* t, double* dst, size_t count); /* to host, paper order */
 int ttiga_tt_free(ttiga_tt* t);
+/* Device view of a library-owned TT (pointers valid until ttiga_tt_free). */
+int ttiga_tt_view_of(const ttiga_tt* t, ttiga_tt_view* view);
+
+/* ------------------------------------------------------------------------
+ * Many independent problems at once.
+ *
+ * Each problem is the whole pipeline of Sections 4.2-4.3 followed by the TT
+ * solve, as in ttiga_assemble + ttiga_solve.  An executor runs them on several
+ * lanes: one host worker thread and one HIP stream each (default priority),
+ * so the latency-bound steps of different problems (small QR/SVD sweeps,
+ * host-side rank decisions) overlap on the device.  Device memory comes from a
+ * pool carved out of the context's workspace; a problem starts only when its
+ * footprint estimate fits what the running problems leave of the pool
+ * (continuous batching: a problem is admitted as soon as a lane and the
+ * memory free up), and every problem runs in an arena of that size (overruns
+ * are served from the pool).  The sketch seeds are reset per problem and every
+ * reduction has a fixed order, so a result does not depend on the other
+ * problems in the mix or on the lane it ran on.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const ttiga_geometry* geo;
+  const ttiga_discretization* disc;
+  const ttiga_source* src;
+  const ttiga_dirichlet* bc;
+  const ttiga_options* opt;
+} ttiga_request;
+
+typedef struct {
+  int status;               /* TTIGA_OK, TTIGA_E_NOTCONV (solution still valid) or the error */
+  int lane;                 /* executor lane that ran it */
+  int rank_u[4];            /* solution TT ranks (all 0 if there is no solution) */
+  int n[3];                 /* interior sizes of the solution */
+  ttiga_assembly_stats assembly;
+  ttiga_solve_stats solve;
+  double queue_ms;          /* submission -> start */
+  double run_ms;            /* start -> solution resident */
+  double latency_ms;        /* submission -> solution resident */
+  size_t footprint_bytes;   /* admitted footprint estimate */
+  size_t peak_bytes;        /* high-water mark of the problem's device memory */
+  char error[128];          /* message of a failed problem */
+} ttiga_result;
+
+/* Host-only: footprint estimate (bytes) that admission uses for a request. */
+int ttiga_footprint(const ttiga_request* req, size_t* bytes);
+
+/* Batched mode: assemble and solve count problems on `lanes` lanes within
+ * hbm_budget bytes of the context's workspace (0: the largest free block less
+ * 1 GiB).  Problems start largest footprint first.  On return solutions[i] is
+ * a library-owned TT on the context (free with ttiga_tt_free), or NULL when
+ * problem i failed; results[i] holds its status and statistics.  The call
+ * itself fails only on bad arguments or when the pool cannot be set up; a
+ * problem that fails does not affect the others. */
+int ttiga_solve_batch(ttiga_ctx* ctx, int count, const ttiga_request* reqs, int lanes,
+                      size_t hbm_budget, ttiga_tt** solutions, ttiga_result* results);
+
+/* Serving mode.  A server owns a pool of hbm_budget bytes of the context's
+ * workspace and `lanes` lanes.  ttiga_server_submit copies and validates the
+ * request and queues it (first come, first served; a later problem that fits
+ * may start before an earlier one that does not, a bounded number of times);
+ * it returns TTIGA_E_ADMISSION when the request's footprint exceeds the whole
+ * pool or `max_queue` requests are already waiting.  ttiga_server_poll
+ * returns TTIGA_PENDING while the request waits or runs (wait_ms > 0 blocks up
+ * to that long, < 0 until it is done) and TTIGA_OK once `out` holds the
+ * result.  Solutions stay resident in the pool until ttiga_server_release.
+ * Submit, poll, solution access and release may be called from any thread. */
+typedef struct ttiga_server ttiga_server;
+
+int ttiga_server_create(ttiga_ctx* ctx, size_t hbm_budget, int lanes, int max_queue,
+                        ttiga_server** out);
+int ttiga_server_submit(ttiga_server* srv, const ttiga_request* req, unsigned long long* ticket);
+int ttiga_server_poll(ttiga_server* srv, unsigned long long ticket, int wait_ms, ttiga_result* out);
+/* Device view of a finished request's solution (valid until release). */
+int ttiga_server_solution(ttiga_server* srv, unsigned long long ticket, ttiga_tt_view* view);
+/* Host copy of a finished request's solution cores, paper order. */
+int ttiga_server_copy_solution(ttiga_server* srv, unsigned long long ticket, double* dst, size_t count);
+int ttiga_server_release(ttiga_server* srv, unsigned long long ticket);
+/* Waits for running and queued requests, then frees the pool and the lanes. */
+int ttiga_server_destroy(ttiga_server* srv);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,7 @@
 #include <cstring>
 #include <string>
 
-#include "problem.hpp"
+#include "engine.hpp"
 
 namespace ttiga {
 
@@ -14,9 +14,14 @@ static thread_local std::string g_last_error;
 
 DeviceAllocator::~DeviceAllocator() {
   for (auto& kv : direct_) (void)hipFree(kv.first);
+  if (spill_parent_) {
+    for (void* p : deferred_) spill_parent_->release(p);
+    for (auto& kv : spilled_) spill_parent_->release(kv.first);
+  }
 }
 
 void DeviceAllocator::set_workspace(void* base, size_t bytes) {
+  std::lock_guard<std::mutex> lk(mu_);
   TTIGA_CHECK(base_ == nullptr && direct_.empty(), TTIGA_E_STATE,
               "workspace must be set before the first allocation");
   TTIGA_CHECK(base && bytes >= 4096, TTIGA_E_ARG, "workspace too small");
@@ -28,13 +33,13 @@ void DeviceAllocator::set_workspace(void* base, size_t bytes) {
   free_[0] = size_;
 }
 
-void* DeviceAllocator::alloc(size_t bytes) {
-  bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+void* DeviceAllocator::alloc_locked(size_t bytes) {
+  if (!base_ && spill_parent_) return nullptr;  // an arena without a region of its own
   if (!base_) {
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess || !p) {
       (void)hipGetLastError();
-      throw Error(TTIGA_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+      return nullptr;
     }
     direct_[p] = bytes;
     in_use_ += bytes;
@@ -52,12 +57,65 @@ void* DeviceAllocator::alloc(size_t bytes) {
       return base_ + off;
     }
   }
-  throw Error(TTIGA_E_OOM, "workspace exhausted: need " + std::to_string(bytes) + " bytes, " +
-                               std::to_string(size_ - in_use_) + " free (fragmented)");
+  return nullptr;
+}
+
+void* DeviceAllocator::try_alloc(size_t bytes) {
+  bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (void* p = alloc_locked(bytes)) return p;
+  }
+  if (!spill_parent_) return nullptr;
+  void* p = spill_parent_->try_alloc(bytes);
+  if (p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    spilled_[p] = bytes;
+    in_use_ += bytes;
+    high_water_ = std::max(high_water_, in_use_);
+  }
+  return p;
+}
+
+void* DeviceAllocator::alloc(size_t bytes) {
+  void* p = try_alloc(bytes);
+  if (!p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    throw Error(TTIGA_E_OOM, "device memory exhausted: need " + std::to_string(bytes) + " bytes, " +
+                                 std::to_string(size_ - std::min(size_, in_use_)) +
+                                 " free in the arena (fragmented or spilled)");
+  }
+  return p;
+}
+
+size_t DeviceAllocator::largest_free() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  size_t m = 0;
+  for (auto& kv : free_) m = std::max(m, kv.second);
+  return m;
+}
+
+void DeviceAllocator::flush_deferred() {
+  std::vector<void*> d;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    d.swap(deferred_);
+  }
+  for (void* p : d) spill_parent_->release(p);
 }
 
 void DeviceAllocator::release(void* p) {
   if (!p) return;
+  std::lock_guard<std::mutex> lk(mu_);
+  if (!spilled_.empty()) {
+    auto sp = spilled_.find(p);
+    if (sp != spilled_.end()) {
+      in_use_ -= sp->second;
+      spilled_.erase(sp);
+      deferred_.push_back(p);
+      return;
+    }
+  }
   if (!base_) {
     auto it = direct_.find(p);
     if (it != direct_.end()) {
@@ -107,6 +165,7 @@ hipEvent_t Profiler::get() {
 }
 
 void Profiler::flush() {
+  std::lock_guard<std::mutex> lk(mu);
   for (auto& p : pending) {
     TTIGA_HIP(hipEventSynchronize(p.b));
     float ms = 0.f;
@@ -120,6 +179,20 @@ void Profiler::flush() {
     pool.push_back(p.b);
   }
   pending.clear();
+}
+
+void Profiler::merge_into(Profiler& dst) {
+  flush();
+  std::lock_guard<std::mutex> lk(dst.mu);
+  std::lock_guard<std::mutex> lk_own(mu);
+  for (auto& kv : stats) {
+    KernelStat& k = dst.stats[kv.first];
+    k.launches += kv.second.launches;
+    k.ms += kv.second.ms;
+    k.flops += kv.second.flops;
+    k.bytes += kv.second.bytes;
+  }
+  stats.clear();
 }
 
 Profiler::~Profiler() {
@@ -256,7 +329,7 @@ int ttiga_destroy(ttiga_ctx* ctx) {
 int ttiga_set_workspace(ttiga_ctx* ctx, void* dev_ptr, size_t bytes) {
   return guard([&] {
     TTIGA_CHECK(ctx != nullptr, TTIGA_E_ARG, "null context");
-    ctx->impl.alloc.set_workspace(dev_ptr, bytes);
+    ctx->impl.alloc->set_workspace(dev_ptr, bytes);
   });
 }
 
@@ -459,6 +532,7 @@ int ttiga_profile(ttiga_ctx* ctx, int enable) {
     Profiler& pr = ctx->impl.prof;
     if (enable < 0) {  // reset
       pr.flush();
+      std::lock_guard<std::mutex> lk(pr.mu);
       pr.stats.clear();
       return;
     }
@@ -474,6 +548,7 @@ int ttiga_profile_read(ttiga_ctx* ctx, ttiga_kernel_stat* out, int capacity, int
     TTIGA_CHECK(ctx && count, TTIGA_E_ARG, "null argument");
     Profiler& pr = ctx->impl.prof;
     pr.flush();
+    std::lock_guard<std::mutex> lk(pr.mu);
     int i = 0;
     for (auto& kv : pr.stats) {
       if (out && i < capacity) {
@@ -503,6 +578,171 @@ int ttiga_tt_copy(const ttiga_tt* t, double* dst, size_t count) {
   return guard([&] {
     TTIGA_CHECK(t != nullptr, TTIGA_E_ARG, "null TT");
     copy_tt_to_host(*t->ctx, t->t, dst, count);
+  });
+}
+
+int ttiga_tt_view_of(const ttiga_tt* t, ttiga_tt_view* view) {
+  return guard([&] {
+    TTIGA_CHECK(t && view, TTIGA_E_ARG, "null argument");
+    for (int k = 0; k < 3; ++k) view->n[k] = t->t.n[k];
+    for (int k = 0; k < 4; ++k) view->r[k] = t->t.r[k];
+    for (int k = 0; k < 3; ++k) view->core[k] = t->t.c[k].d();
+  });
+}
+
+static std::unique_ptr<Problem> problem_from_request(const ttiga_request* req) {
+  TTIGA_CHECK(req != nullptr, TTIGA_E_ARG, "null request");
+  return std::make_unique<Problem>(nullptr, req->geo, req->disc, req->src, req->bc, req->opt);
+}
+
+int ttiga_footprint(const ttiga_request* req, size_t* bytes) {
+  return guard([&] {
+    TTIGA_CHECK(bytes != nullptr, TTIGA_E_ARG, "null output");
+    *bytes = problem_from_request(req)->footprint_estimate();
+  });
+}
+
+// Default pool: the largest free block of the workspace (or of the device) less 1 GiB.
+static size_t default_budget(Context& c) {
+  size_t avail = c.alloc->largest_free();
+  if (c.alloc->capacity() == 0) {
+    size_t free_b = 0, total_b = 0;
+    TTIGA_HIP(hipMemGetInfo(&free_b, &total_b));
+    avail = free_b;
+  }
+  const size_t reserve = size_t(1) << 30;
+  TTIGA_CHECK(avail > reserve + (size_t(64) << 20), TTIGA_E_OOM, "no device memory left for a pool");
+  return avail - reserve;
+}
+
+int ttiga_solve_batch(ttiga_ctx* ctx, int count, const ttiga_request* reqs, int lanes,
+                      size_t hbm_budget, ttiga_tt** solutions, ttiga_result* results) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && count >= 0 && (count == 0 || (reqs && solutions && results)), TTIGA_E_ARG,
+                "null argument");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    for (int i = 0; i < count; ++i) {
+      solutions[i] = nullptr;
+      std::memset(&results[i], 0, sizeof(ttiga_result));
+    }
+    if (count == 0) return;
+    std::vector<std::unique_ptr<Problem>> probs(count);
+    std::vector<size_t> fp(count, 0);
+    for (int i = 0; i < count; ++i) {
+      const int code = guard([&] {
+        probs[i] = problem_from_request(&reqs[i]);
+        fp[i] = probs[i]->footprint_estimate();
+      });
+      if (code != TTIGA_OK) {
+        results[i].status = code;
+        std::strncpy(results[i].error, g_last_error.c_str(), sizeof(results[i].error) - 1);
+      }
+    }
+    const size_t budget = hbm_budget ? hbm_budget : default_budget(c);
+    Engine eng(&c, budget, lanes, count);
+    // largest footprint first: the big problems overlap with the many small ones
+    std::vector<int> order;
+    for (int i = 0; i < count; ++i)
+      if (probs[i]) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fp[a] > fp[b]; });
+    std::vector<unsigned long long> ticket(count, 0);
+    for (int i : order) {
+      const int code = guard([&] { ticket[i] = eng.submit(std::move(probs[i])); });
+      if (code != TTIGA_OK) {
+        results[i].status = code;
+        std::strncpy(results[i].error, g_last_error.c_str(), sizeof(results[i].error) - 1);
+      }
+    }
+    eng.wait_all();
+    for (int i = 0; i < count; ++i) {
+      if (!ticket[i]) continue;
+      eng.poll(ticket[i], 0, &results[i]);
+      if (results[i].status != TTIGA_OK && results[i].status != TTIGA_E_NOTCONV) continue;
+      const TT& u = eng.solution(ticket[i]);
+      auto* res = new ttiga_tt{&c, TT{}};
+      const int code = guard([&] { tt_copy(c, u, res->t); });
+      if (code != TTIGA_OK) {
+        delete res;
+        results[i].status = code;
+        std::strncpy(results[i].error, g_last_error.c_str(), sizeof(results[i].error) - 1);
+        continue;
+      }
+      solutions[i] = res;
+      ctx_retain(&c);
+    }
+    c.sync();
+  });
+}
+
+int ttiga_server_create(ttiga_ctx* ctx, size_t hbm_budget, int lanes, int max_queue,
+                        ttiga_server** out) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && out, TTIGA_E_ARG, "null argument");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    const size_t budget = hbm_budget ? hbm_budget : default_budget(c);
+    auto* s = new ttiga_server{nullptr};
+    try {
+      s->engine = new Engine(&c, budget, lanes, max_queue > 0 ? max_queue : 1024);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+    ctx_retain(&c);
+  });
+}
+
+int ttiga_server_submit(ttiga_server* srv, const ttiga_request* req, unsigned long long* ticket) {
+  return guard([&] {
+    TTIGA_CHECK(srv && ticket, TTIGA_E_ARG, "null argument");
+    *ticket = srv->engine->submit(problem_from_request(req));
+  });
+}
+
+int ttiga_server_poll(ttiga_server* srv, unsigned long long ticket, int wait_ms, ttiga_result* out) {
+  int st = TTIGA_OK;
+  const int code = guard([&] {
+    TTIGA_CHECK(srv != nullptr, TTIGA_E_ARG, "null server");
+    st = srv->engine->poll(ticket, wait_ms, out);
+  });
+  return code != TTIGA_OK ? code : st;
+}
+
+int ttiga_server_solution(ttiga_server* srv, unsigned long long ticket, ttiga_tt_view* view) {
+  return guard([&] {
+    TTIGA_CHECK(srv && view, TTIGA_E_ARG, "null argument");
+    const TT& u = srv->engine->solution(ticket);
+    for (int k = 0; k < 3; ++k) view->n[k] = u.n[k];
+    for (int k = 0; k < 4; ++k) view->r[k] = u.r[k];
+    for (int k = 0; k < 3; ++k) view->core[k] = u.c[k].d();
+  });
+}
+
+int ttiga_server_copy_solution(ttiga_server* srv, unsigned long long ticket, double* dst, size_t count) {
+  return guard([&] {
+    TTIGA_CHECK(srv != nullptr, TTIGA_E_ARG, "null server");
+    Engine& e = *srv->engine;
+    TTIGA_HIP(hipSetDevice(e.root()->device));
+    copy_tt_to_host(*e.root(), e.solution(ticket), dst, count);
+  });
+}
+
+int ttiga_server_release(ttiga_server* srv, unsigned long long ticket) {
+  return guard([&] {
+    TTIGA_CHECK(srv != nullptr, TTIGA_E_ARG, "null server");
+    srv->engine->release(ticket);
+  });
+}
+
+int ttiga_server_destroy(ttiga_server* srv) {
+  return guard([&] {
+    if (!srv) return;
+    Context* c = srv->engine->root();
+    delete srv->engine;
+    delete srv;
+    ctx_release(c);
   });
 }
 

@@ -413,7 +413,7 @@ void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, 
   TTIGA_CHECK(b0 >= 0 && c1 > 0 && b0 + c1 <= Q[1], TTIGA_E_ARG, "factor slab range out of the grid");
   const long total = (long)Q[0] * c1 * Q[2];
   const long blocks = (total + 255) / 256;
-  DBuf part(&ctx.alloc, sizeof(double) * 8 * blocks);
+  DBuf part(ctx.alloc, sizeof(double) * 8 * blocks);
   // per point: homogeneous map and its three derivatives over the (p_g+1)^3 local net
   // (inner sums over the last direction first), the adjugate, det J, R and f det J;
   // bytes: the seven factor values written (tables and net are cache-resident)

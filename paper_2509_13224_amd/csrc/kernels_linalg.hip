@@ -136,7 +136,7 @@ void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, con
   kchunk = (kchunk + GK - 1) / GK * GK;
   splits = (K + kchunk - 1) / kchunk;
   DBuf part;
-  if (splits > 1) part = DBuf(&ctx.alloc, sizeof(double) * (size_t)batch * splits * M * N);
+  if (splits > 1) part = DBuf(ctx.alloc, sizeof(double) * (size_t)batch * splits * M * N);
   ProfScope prof(ctx, "gemm_f64", 2.0 * M * N * (double)K * batch,
                  8.0 * batch * ((double)M * K + (double)K * N + (double)M * N));
   dim3 grid(tn, tm, batch * splits);
@@ -351,30 +351,31 @@ constexpr int kTsqrStatic = 8192 + 512;
 // the larger opt-in is refused.  The Jacobi kernel gets the same budget minus its own
 // larger static part.
 static int lds_doubles() {
-  static int cap = -1;
-  if (cap > 0) return cap;
-  int dev = 0, bytes = 65536;
-  TTIGA_HIP(hipGetDevice(&dev));
-  if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-    bytes = 65536;
-  int dyn = bytes - kJacobiStatic;  // the larger static part bounds both budgets
-  if (bytes > 65536) {
-    const bool ok =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_factor<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
-            hipSuccess;
-    if (!ok) {
-      (void)hipGetLastError();
-      dyn = 65536 - kJacobiStatic;
+  // computed once (thread-safe static initialisation)
+  static const int cap = [] {
+    int dev = 0, bytes = 65536;
+    TTIGA_HIP(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      bytes = 65536;
+    int dyn = bytes - kJacobiStatic;  // the larger static part bounds both budgets
+    if (bytes > 65536) {
+      const bool ok =
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_factor<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
+              hipSuccess;
+      if (!ok) {
+        (void)hipGetLastError();
+        dyn = 65536 - kJacobiStatic;
+      }
     }
-  }
-  cap = dyn / 8;
+    return dyn / 8;
+  }();
   return cap;
 }
 
@@ -408,10 +409,10 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     L.ldw = (mm + L.nb - 1) / L.nb;
     L.lds = (long)L.ldw * c <= kLdsDoubles;
     L.v_lds = 2L * L.ldw * c <= kLdsDoubles;
-    L.V = DBuf(&ctx.alloc, sizeof(double) * (size_t)mm * c);
-    L.tau = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * c);
-    L.R = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * c * c);
-    if (!L.lds) L.work = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.nb * L.ldw * c);
+    L.V = DBuf(ctx.alloc, sizeof(double) * (size_t)mm * c);
+    L.tau = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * c);
+    L.R = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * c * c);
+    if (!L.lds) L.work = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * L.ldw * c);
     const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
     ProfScope prof(ctx, "tsqr_factor", 2.0 * mm * c * c - L.nb * (2.0 / 3.0) * c * c * c,
                    8.0 * (2.0 * mm * c + (double)L.nb * c * c), c);
@@ -436,7 +437,7 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
   for (int l = (int)lv.size() - 1; l >= 0; --l) {
     Level& L = lv[l];
     DBuf qout;
-    double* dst = (l == 0) ? Q : (qout = DBuf(&ctx.alloc, sizeof(double) * (size_t)L.m * c), qout.d());
+    double* dst = (l == 0) ? Q : (qout = DBuf(ctx.alloc, sizeof(double) * (size_t)L.m * c), qout.d());
     const size_t shm = L.lds ? (L.v_lds ? 2 : 1) * sizeof(double) * (size_t)L.ldw * c : 0;
     ProfScope prof(ctx, "tsqr_apply", 4.0 * c * c * (double)L.m - 2.0 * c * c * c * L.nb,
                    8.0 * (2.0 * L.m * c + (double)L.nb * c * c), c);
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(int c, const double* __restric
 }
 
 bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* Rinv) {
-  DBuf st(&ctx.alloc, sizeof(double));
+  DBuf st(ctx.alloc, sizeof(double));
   fill(ctx, st.d(), 1, 0.0);
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, ctx.stream, c, G, R, Rinv, st.d());
   TTIGA_HIP(hipGetLastError());
@@ -635,7 +636,7 @@ void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long ld
   const long need = (long)(m + c) * c;
   const bool lds = need <= lds_doubles();
   DBuf work;
-  if (!lds) work = DBuf(&ctx.alloc, sizeof(double) * need);
+  if (!lds) work = DBuf(ctx.alloc, sizeof(double) * need);
   // enough lane groups for all column pairs of a round, up to 16 waves
   const int G = (m <= 32) ? 8 : ((m <= 128) ? 16 : 64);
   const int pairs = (c + 1) / 2;
@@ -680,7 +681,7 @@ __global__ void k_trunc_rank(const double* __restrict__ s, int c, double eps_rel
 int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* norm_out) {
   // delta >= 0: absolute threshold; delta < 0: relative eps = -delta.
   double* h = ctx.host(3);
-  DBuf o(&ctx.alloc, 3 * sizeof(double));
+  DBuf o(ctx.alloc, 3 * sizeof(double));
   hipLaunchKernelGGL(k_trunc_rank, dim3(1), dim3(64), 0, ctx.stream, s, c,
                      delta < 0 ? -delta : 0.0, delta < 0 ? -1.0 : delta, o.d());
   TTIGA_HIP(hipGetLastError());
@@ -741,7 +742,7 @@ __global__ void k_sum_final(const double* __restrict__ part, int n, double* __re
 
 void sumsq_reduce(Context& ctx, const double* x, size_t n, double* out_dev) {
   const int blocks = (int)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 1024));
-  DBuf part(&ctx.alloc, sizeof(double) * blocks);
+  DBuf part(ctx.alloc, sizeof(double) * blocks);
   hipLaunchKernelGGL(k_sumsq_partial, dim3(blocks), dim3(256), 0, ctx.stream, x, n, part.d());
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks, out_dev);
   TTIGA_HIP(hipGetLastError());

@@ -93,42 +93,46 @@ static std::shared_ptr<EigenBasis> eigenbasis(Problem& P, int d) {
   const int p = P.p, band = 2 * p + 1;
   const int n = P.n[d], Q = P.Q[d], m = P.hi[d] - P.lo[d];
   const std::array<int, 5> key = {n, p, P.g, P.lo[d], P.hi[d]};
-  auto it = ctx.plans.find(key);
-  if (it != ctx.plans.end()) return std::static_pointer_cast<EigenBasis>(it->second);
+  {
+    std::lock_guard<std::mutex> lk(ctx.plans->mu);
+    auto it = ctx.plans->map.find(key);
+    if (it != ctx.plans->map.end()) return std::static_pointer_cast<EigenBasis>(it->second);
+  }
   auto e = std::make_shared<EigenBasis>();
   e->ni = m;
-  DBuf ones(&ctx.alloc, sizeof(double) * Q);
+  DBuf ones(ctx.alloc, sizeof(double) * Q);
   fill(ctx, ones.d(), Q, 1.0);
-  DBuf mb(&ctx.alloc, sizeof(double) * n * band), ab(&ctx.alloc, sizeof(double) * n * band);
+  DBuf mb(ctx.alloc, sizeof(double) * n * band), ab(ctx.alloc, sizeof(double) * n * band);
   launch_assemble_band(ctx, n, p, P.g, 1, 1, ones.d(), P.tab_w[d].d(), P.tab_B[d].d(), P.tab_B[d].d(), mb.d());
   launch_assemble_band(ctx, n, p, P.g, 1, 1, ones.d(), P.tab_w[d].d(), P.tab_D[d].d(), P.tab_D[d].d(), ab.d());
-  DBuf mi(&ctx.alloc, sizeof(double) * m * band), ai(&ctx.alloc, sizeof(double) * m * band);
+  DBuf mi(ctx.alloc, sizeof(double) * m * band), ai(ctx.alloc, sizeof(double) * m * band);
   launch_slice_band(ctx, n, p, P.lo[d], m, 1, 1, mb.d(), mi.d());
   launch_slice_band(ctx, n, p, P.lo[d], m, 1, 1, ab.d(), ai.d());
-  DBuf Md(&ctx.alloc, sizeof(double) * m * m), Ad(&ctx.alloc, sizeof(double) * m * m);
+  DBuf Md(ctx.alloc, sizeof(double) * m * m), Ad(ctx.alloc, sizeof(double) * m * m);
   hipLaunchKernelGGL(k_band_to_dense, dim3(grid_for((long)m * m)), dim3(256), 0, ctx.stream, m, p, mi.d(), Md.d());
   hipLaunchKernelGGL(k_band_to_dense, dim3(grid_for((long)m * m)), dim3(256), 0, ctx.stream, m, p, ai.d(), Ad.d());
   TTIGA_HIP(hipGetLastError());
-  DBuf Rm(&ctx.alloc, sizeof(double) * m * m), Rmi(&ctx.alloc, sizeof(double) * m * m);
+  DBuf Rm(ctx.alloc, sizeof(double) * m * m), Rmi(ctx.alloc, sizeof(double) * m * m);
   TTIGA_CHECK(cholesky_inverse(ctx, Md.d(), m, Rm.d(), Rmi.d()), TTIGA_E_ARG,
               "1-D mass matrix is not positive definite");
   // S = Rmi^T A Rmi, symmetric positive semi-definite; its SVD is its eigendecomposition
-  DBuf T1(&ctx.alloc, sizeof(double) * m * m), S(&ctx.alloc, sizeof(double) * m * m);
+  DBuf T1(ctx.alloc, sizeof(double) * m * m), S(ctx.alloc, sizeof(double) * m * m);
   gemm(ctx, false, false, m, m, m, 1.0, Ad.d(), m, 0, Rmi.d(), m, 0, 0.0, T1.d(), m, 0);
   gemm(ctx, true, false, m, m, m, 1.0, Rmi.d(), m, 0, T1.d(), m, 0, 0.0, S.d(), m, 0);
-  DBuf U(&ctx.alloc, sizeof(double) * m * m), W(&ctx.alloc, sizeof(double) * m * m);
-  e->lam = DBuf(&ctx.alloc, sizeof(double) * m);
+  DBuf U(ctx.alloc, sizeof(double) * m * m), W(ctx.alloc, sizeof(double) * m * m);
+  e->lam = DBuf(ctx.plan_alloc, sizeof(double) * m);
   svd_small(ctx, S.d(), false, m, m, m, U.d(), e->lam.d(), W.d());
-  e->V = DBuf(&ctx.alloc, sizeof(double) * m * m);
+  e->V = DBuf(ctx.plan_alloc, sizeof(double) * m * m);
   gemm(ctx, false, false, m, m, m, 1.0, Rmi.d(), m, 0, W.d(), m, 0, 0.0, e->V.d(), m, 0);
   double* h = ctx.host(2);
   TTIGA_HIP(hipMemcpyAsync(h, e->lam.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
   TTIGA_HIP(hipMemcpyAsync(h + 1, e->lam.d() + (m - 1), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-  ctx.sync();
+  ctx.sync();  // the plan is complete before other streams can find it
   e->lam_max = h[0];
   e->lam_min = h[1];
-  ctx.plans[key] = e;
-  return e;
+  std::lock_guard<std::mutex> lk(ctx.plans->mu);
+  auto ins = ctx.plans->map.emplace(key, e);
+  return std::static_pointer_cast<EigenBasis>(ins.first->second);
 }
 
 void Precond::setup(Problem& P) {
@@ -146,12 +150,12 @@ void Precond::setup(Problem& P) {
     if (Rt.zero()) continue;
     DBuf v[3];
     for (int k = 0; k < 3; ++k) {
-      v[k] = DBuf(&ctx.alloc, sizeof(double) * Rt.r[k] * Rt.r[k + 1]);
+      v[k] = DBuf(ctx.alloc, sizeof(double) * Rt.r[k] * Rt.r[k + 1]);
       hipLaunchKernelGGL(k_weighted_core_sum, dim3((Rt.r[k] * Rt.r[k + 1] + 255) / 256), dim3(256), 0, ctx.stream,
                          Rt.r[k], P.Q[k], Rt.r[k + 1], Rt.c[k].d(), P.tab_w[k].d(), v[k].d());
     }
     TTIGA_HIP(hipGetLastError());
-    DBuf t01(&ctx.alloc, sizeof(double) * Rt.r[2]), res(&ctx.alloc, sizeof(double));
+    DBuf t01(ctx.alloc, sizeof(double) * Rt.r[2]), res(ctx.alloc, sizeof(double));
     gemm(ctx, false, false, 1, Rt.r[2], Rt.r[1], 1.0, v[0].d(), Rt.r[1], 0, v[1].d(), Rt.r[2], 0, 0.0, t01.d(), Rt.r[2], 0);
     gemm(ctx, false, false, 1, 1, Rt.r[2], 1.0, t01.d(), Rt.r[2], 0, v[2].d(), 1, 0, 0.0, res.d(), 1, 0);
     double* h = ctx.host(1);
@@ -190,12 +194,12 @@ void Precond::setup(Problem& P) {
   }
   R = (int)tau.size();
   std::vector<double> ones(R, 1.0);
-  DBuf dtau(&ctx.alloc, sizeof(double) * R), dw(&ctx.alloc, sizeof(double) * R), d1(&ctx.alloc, sizeof(double) * R);
+  DBuf dtau(ctx.alloc, sizeof(double) * R), dw(ctx.alloc, sizeof(double) * R), d1(ctx.alloc, sizeof(double) * R);
   TTIGA_HIP(hipMemcpyAsync(dtau.d(), tau.data(), sizeof(double) * R, hipMemcpyHostToDevice, ctx.stream));
   TTIGA_HIP(hipMemcpyAsync(dw.d(), wt.data(), sizeof(double) * R, hipMemcpyHostToDevice, ctx.stream));
   TTIGA_HIP(hipMemcpyAsync(d1.d(), ones.data(), sizeof(double) * R, hipMemcpyHostToDevice, ctx.stream));
   for (int d = 0; d < 3; ++d) {
-    etab[d] = DBuf(&ctx.alloc, sizeof(double) * R * ni[d]);
+    etab[d] = DBuf(ctx.alloc, sizeof(double) * R * ni[d]);
     hipLaunchKernelGGL(k_exp_table, dim3(grid_for((long)R * ni[d])), dim3(256), 0, ctx.stream, R, ni[d],
                        dtau.d(), d == 0 ? dw.d() : d1.d(), c[d], eb[d]->lam.d(), etab[d].d());
   }

@@ -140,13 +140,13 @@ Problem::Problem(Context* c, const ttiga_geometry* geo, const ttiga_discretizati
 void Problem::upload() {
   Context& c = *ctx;
   const size_t nctrl = (size_t)m[0] * m[1] * m[2];
-  DBuf xyz(&c.alloc, sizeof(double) * 3 * nctrl), w(&c.alloc, sizeof(double) * nctrl);
+  DBuf xyz(c.alloc, sizeof(double) * 3 * nctrl), w(c.alloc, sizeof(double) * nctrl);
   TTIGA_HIP(hipMemcpyAsync(xyz.d(), ctrl.data(), sizeof(double) * 3 * nctrl, hipMemcpyHostToDevice, c.stream));
   TTIGA_HIP(hipMemcpyAsync(w.d(), weights.data(), sizeof(double) * nctrl, hipMemcpyHostToDevice, c.stream));
-  Pw = DBuf(&c.alloc, sizeof(double) * 4 * nctrl);
+  Pw = DBuf(c.alloc, sizeof(double) * 4 * nctrl);
   launch_homogeneous(c, (long)nctrl, xyz.d(), w.d(), Pw.d());
   for (int d = 0; d < 3; ++d) {
-    gknots_d[d] = DBuf(&c.alloc, sizeof(double) * gknots[d].size());
+    gknots_d[d] = DBuf(c.alloc, sizeof(double) * gknots[d].size());
     TTIGA_HIP(hipMemcpyAsync(gknots_d[d].d(), gknots[d].data(), sizeof(double) * gknots[d].size(),
                              hipMemcpyHostToDevice, c.stream));
     // open uniform solution knots: p+1 zeros, e/E for e = 1..E-1, p+1 ones
@@ -155,13 +155,13 @@ void Problem::upload() {
       const int e = std::min(std::max(i - p, 0), E[d]);
       kn[i] = (e == E[d]) ? 1.0 : (double)e / E[d];
     }
-    sknots_d[d] = DBuf(&c.alloc, sizeof(double) * kn.size());
+    sknots_d[d] = DBuf(c.alloc, sizeof(double) * kn.size());
     TTIGA_HIP(hipMemcpyAsync(sknots_d[d].d(), kn.data(), sizeof(double) * kn.size(),
                              hipMemcpyHostToDevice, c.stream));
   }
   const int nm = (int)src_a.size();
   if (nm > 0) {
-    modes_d = DBuf(&c.alloc, sizeof(double) * 5 * nm);
+    modes_d = DBuf(c.alloc, sizeof(double) * 5 * nm);
     std::vector<double> h(5 * nm);
     std::memcpy(h.data(), src_a.data(), sizeof(double) * nm);
     std::memcpy(h.data() + nm, src_k.data(), sizeof(double) * 3 * nm);
@@ -189,15 +189,15 @@ void Problem::build_tables() {
   Context& c = *ctx;
   for (int d = 0; d < 3; ++d) {
     const int Qd = Q[d];
-    tab_xi[d] = DBuf(&c.alloc, sizeof(double) * Qd);
-    tab_w[d] = DBuf(&c.alloc, sizeof(double) * Qd);
-    tab_B[d] = DBuf(&c.alloc, sizeof(double) * Qd * (p + 1));
-    tab_D[d] = DBuf(&c.alloc, sizeof(double) * Qd * (p + 1));
+    tab_xi[d] = DBuf(c.alloc, sizeof(double) * Qd);
+    tab_w[d] = DBuf(c.alloc, sizeof(double) * Qd);
+    tab_B[d] = DBuf(c.alloc, sizeof(double) * Qd * (p + 1));
+    tab_D[d] = DBuf(c.alloc, sizeof(double) * Qd * (p + 1));
     launch_basis_tables(c, n[d], p, g, sknots_d[d].d(), tab_xi[d].d(), tab_w[d].d(), tab_B[d].d(),
                         tab_D[d].d());
-    gtab_span[d] = DBuf(&c.alloc, sizeof(int) * Qd);
-    gtab_B[d] = DBuf(&c.alloc, sizeof(double) * Qd * (pg[d] + 1));
-    gtab_D[d] = DBuf(&c.alloc, sizeof(double) * Qd * (pg[d] + 1));
+    gtab_span[d] = DBuf(c.alloc, sizeof(int) * Qd);
+    gtab_B[d] = DBuf(c.alloc, sizeof(double) * Qd * (pg[d] + 1));
+    gtab_D[d] = DBuf(c.alloc, sizeof(double) * Qd * (pg[d] + 1));
     launch_geo_tables(c, Qd, tab_xi[d].d(), 1, m[d], pg[d], gknots_d[d].d(), gtab_span[d].as<int>(),
                       gtab_B[d].d(), gtab_D[d].d());
   }
@@ -220,6 +220,7 @@ void Problem::assemble(ttiga_assembly_stats* st) {
   Context& c = *ctx;
   ttiga_assembly_stats s{};
   double t0 = now_ms();
+  c.rng_counter = kAssembleSeed;
   build_tables();
   // 2. factor tensors on the Gauss grid, 3. TT compression
   const size_t total = (size_t)Q[0] * Q[1] * Q[2];
@@ -229,7 +230,7 @@ void Problem::assemble(ttiga_assembly_stats* st) {
                         Q[0] > kExactSvdSize && (size_t)Q[1] * Q[2] > (size_t)kExactSvdSize;
   const GeoDev gd = geo_dev(gtab_span, gtab_B, gtab_D);
   const SourceDev sd = source_dev();
-  DBuf st8(&c.alloc, sizeof(double) * 8);
+  DBuf st8(c.alloc, sizeof(double) * 8);
   const double eps = opts.tt_eps;
   double t1 = 0.0;
   // norms, det J check and the compression thresholds from the 8 gathered statistics
@@ -262,7 +263,7 @@ void Problem::assemble(ttiga_assembly_stats* st) {
     };
     tt_compress_streamed(c, 7, Q, chunk, produce, thresholds, fac, opts.max_rank);
   } else {
-    DBuf Fac(&c.alloc, sizeof(double) * 7 * total);
+    DBuf Fac(c.alloc, sizeof(double) * 7 * total);
     launch_factors_grid(c, gd, sd, Q, 0, Q[1], Fac.d(), st8.d(), false);
     std::vector<double> delta;
     thresholds(delta);
@@ -382,11 +383,40 @@ void Problem::reduce_boundary() {
   }
 }
 
+// Upper estimate of the device memory one assembly + solve needs, for admission by an
+// executor: the larger of the sampling/compression phase (whole-grid samples and one
+// TT-SVD's temporaries, or one streamed chunk, the shared sketch matrix and the seven
+// projections with their QR) and the solve phase (a few trains of rank 48 times the
+// operator band, the product and preconditioner trains at the same rank), plus the
+// resident tables.  Overruns are served from the executor's pool, so an estimate that is
+// low costs admission accuracy, not correctness.
+size_t Problem::footprint_estimate() const {
+  const double Q0 = Q[0], Q1 = Q[1], Q2 = Q[2];
+  const double pts = Q0 * Q1 * Q2, slab = 7.0 * Q0 * Q2 * 8.0;
+  const double whole_limit = 2.0 * 1073741824.0;
+  const bool streamed = (opts.sample_chunk_bytes > 0 || slab * Q1 > whole_limit) &&
+                        Q[0] > kExactSvdSize && Q1 * Q2 > kExactSvdSize;
+  double sampling;
+  if (streamed) {
+    const double budget = opts.sample_chunk_bytes > 0 ? (double)opts.sample_chunk_bytes : whole_limit;
+    const double chunk = std::max(1.0, std::min(Q1, std::floor(budget / slab)));
+    sampling = slab * chunk + Q1 * Q2 * 48.0 * 8.0 * (1.0 + 7.0 + 2.0) + 64.0 * Q0 * 48.0 * 8.0;
+  } else {
+    sampling = 7.0 * pts * 8.0 + 3.0 * pts * 8.0;
+  }
+  const double nmax = std::max(n[0], std::max(n[1], n[2]));
+  const double rbar = std::min(48, opts.max_rank > 0 ? opts.max_rank : 48);
+  const double solve = 40.0 * rbar * rbar * nmax * (2.0 * p + 1.0) * 8.0;
+  const double tables = 8.0 * (Q0 + Q1 + Q2) * (4.0 * (p + 1) + 8.0) + 8.0 * 4.0 * m[0] * m[1] * m[2];
+  return (size_t)(std::max(sampling, solve) + tables + (64u << 20));
+}
+
 void Problem::solve(ttiga_solve_stats* st) {
   TTIGA_CHECK(assembled, TTIGA_E_STATE, "solve before assemble");
   Context& c = *ctx;
   ttiga_solve_stats s{};
   const double t0 = now_ms();
+  c.rng_counter = kSolveSeed;
   int ni[3];
   for (int d = 0; d < 3; ++d) ni[d] = hi[d] - lo[d];
   u.set_zero(ni);
@@ -612,17 +642,17 @@ void Problem::sample_points(const double* pts, size_t count, double* out, double
   TTIGA_CHECK(pts && out && count > 0, TTIGA_E_ARG, "sample_factors: null or empty input");
   for (size_t q = 0; q < 3 * count; ++q)
     TTIGA_CHECK(pts[q] >= 0.0 && pts[q] <= 1.0, TTIGA_E_ARG, "sample point outside [0,1]^3");
-  DBuf P(&c.alloc, sizeof(double) * 3 * count);
+  DBuf P(c.alloc, sizeof(double) * 3 * count);
   TTIGA_HIP(hipMemcpyAsync(P.d(), pts, sizeof(double) * 3 * count, hipMemcpyHostToDevice, c.stream));
   DBuf span[3], B[3], D[3];
   for (int d = 0; d < 3; ++d) {
-    span[d] = DBuf(&c.alloc, sizeof(int) * count);
-    B[d] = DBuf(&c.alloc, sizeof(double) * count * (pg[d] + 1));
-    D[d] = DBuf(&c.alloc, sizeof(double) * count * (pg[d] + 1));
+    span[d] = DBuf(c.alloc, sizeof(int) * count);
+    B[d] = DBuf(c.alloc, sizeof(double) * count * (pg[d] + 1));
+    D[d] = DBuf(c.alloc, sizeof(double) * count * (pg[d] + 1));
     launch_geo_tables(c, (int)count, P.d() + d, 3, m[d], pg[d], gknots_d[d].d(), span[d].as<int>(),
                       B[d].d(), D[d].d());
   }
-  DBuf O(&c.alloc, sizeof(double) * 7 * count), Dt(&c.alloc, sizeof(double) * count);
+  DBuf O(c.alloc, sizeof(double) * 7 * count), Dt(c.alloc, sizeof(double) * count);
   launch_factors_points(c, geo_dev(span, B, D), source_dev(), (long)count, O.d(), Dt.d());
   TTIGA_HIP(hipMemcpyAsync(out, O.d(), sizeof(double) * 7 * count, hipMemcpyDeviceToHost, c.stream));
   if (det_out)

@@ -8,6 +8,10 @@
 
 namespace ttiga {
 
+// sketch seeds of the assembly and of the solve (see Context::rng_counter)
+constexpr uint64_t kAssembleSeed = 0xa55e3b1e00000000ull;
+constexpr uint64_t kSolveSeed = 0x501fe00000000000ull;
+
 struct Problem {
   Context* ctx;
   // description
@@ -41,6 +45,7 @@ struct Problem {
   const TT* which(int w) const;
   void sample_points(const double* pts, size_t count, double* out, double* det_out);
   void upload();  // device copies of the small inputs
+  size_t footprint_estimate() const;
 
  private:
   void solve_cg(ttiga_solve_stats& s);

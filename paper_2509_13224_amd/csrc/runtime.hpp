@@ -10,6 +10,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -39,22 +40,36 @@ struct Error : std::runtime_error {
   } while (0)
 
 // First-fit sub-allocator over one device buffer, or direct hipMalloc when no
-// workspace was given.  All blocks are 256-byte aligned.
+// workspace was given.  All blocks are 256-byte aligned.  Calls are serialised by a
+// mutex, so one allocator can feed several per-job arenas on other threads.  An
+// arena may name a spill parent: requests it cannot place are taken from the parent,
+// and their release is deferred until flush_deferred() (called once the arena's
+// stream has drained), so another stream cannot reuse memory still being read.
 class DeviceAllocator {
  public:
   ~DeviceAllocator();
   void set_workspace(void* base, size_t bytes);
+  void set_spill_parent(DeviceAllocator* parent) { spill_parent_ = parent; }
   void* alloc(size_t bytes);
+  void* try_alloc(size_t bytes);  // nullptr instead of E_OOM
   void release(void* p);
+  void flush_deferred();
   size_t in_use() const { return in_use_; }
   size_t high_water() const { return high_water_; }
+  size_t capacity() const { return size_; }
+  size_t largest_free() const;
 
  private:
+  void* alloc_locked(size_t bytes);
+  mutable std::mutex mu_;
   char* base_ = nullptr;
   size_t size_ = 0;
   std::map<size_t, size_t> free_;   // offset -> size
   std::map<size_t, size_t> used_;   // offset -> size
   std::map<void*, size_t> direct_;  // hipMalloc'd blocks when no workspace
+  DeviceAllocator* spill_parent_ = nullptr;
+  std::map<void*, size_t> spilled_;  // live blocks taken from the parent
+  std::vector<void*> deferred_;      // released spills awaiting flush_deferred()
   size_t in_use_ = 0, high_water_ = 0;
 };
 
@@ -93,6 +108,7 @@ struct KernelStat {
 };
 
 struct Profiler {
+  std::mutex mu;  // guards stats while per-job profilers merge into this one
   bool on = false;
   bool detail = false;  // append a size bucket to kernel names (diagnostics)
   std::map<std::string, KernelStat> stats;
@@ -105,6 +121,7 @@ struct Profiler {
   std::vector<hipEvent_t> pool;
   hipEvent_t get();
   void flush();  // waits for recorded events and folds them into stats
+  void merge_into(Profiler& dst);  // flush, then add the stats to dst and clear them
   ~Profiler();
 };
 
@@ -124,19 +141,33 @@ class ProfScope {
   hipEvent_t a_ = nullptr;
 };
 
+// Discretisation-level plans reused across problems (the 1-D eigenbases of the
+// preconditioner), keyed by (n, p, g, lo, hi).  Shared by the per-job contexts of an
+// executor, so lookups and inserts take the mutex; a plan is inserted only after the
+// stream that computed it has drained.
+struct PlanCache {
+  std::mutex mu;
+  std::map<std::array<int, 5>, std::shared_ptr<void>> map;
+};
+
 struct Context {
   Profiler prof;
   int device = 0;
   hipStream_t stream = nullptr;
-  DeviceAllocator alloc;
-  // discretisation-level plans reused across problems (the 1-D eigenbases of the
-  // preconditioner), keyed by (n, p, g, lo, hi); declared after the allocator so
-  // they are released before it
-  std::map<std::array<int, 5>, std::shared_ptr<void>> plans;
+  // device memory: the context's own allocator, or a per-job arena of an executor
+  DeviceAllocator own_alloc;
+  DeviceAllocator* alloc = &own_alloc;
+  // where plans are allocated: memory that lives as long as the plan cache
+  DeviceAllocator* plan_alloc = &own_alloc;
+  // declared after the allocator so that cached plans are released before it
+  PlanCache own_plans;
+  PlanCache* plans = &own_plans;
   // pinned host staging for small readbacks (ranks, scalars)
   double* host_scratch = nullptr;
   size_t host_scratch_doubles = 0;
-  uint64_t rng_counter = 0x5eed;  // sketch seeds advance deterministically per context
+  // sketch seeds; reset at the start of every assembly and solve, so a problem's
+  // results do not depend on what ran before it on the context
+  uint64_t rng_counter = 0x5eed;
   // problems and TT handles alive on this context; ttiga_destroy defers the
   // deletion until the last of them is destroyed
   int live_objects = 0;

@@ -19,7 +19,7 @@ namespace ttiga {
 void TT::alloc(Context& ctx, const int* nn, const int* rr) {
   for (int k = 0; k < 3; ++k) n[k] = nn[k];
   for (int k = 0; k < 4; ++k) r[k] = rr[k];
-  for (int k = 0; k < 3; ++k) c[k] = DBuf(&ctx.alloc, sizeof(double) * core_elems(k));
+  for (int k = 0; k < 3; ++k) c[k] = DBuf(ctx.alloc, sizeof(double) * core_elems(k));
 }
 
 // --------------------------------------------------------------- kernels
@@ -235,16 +235,16 @@ void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* 
 void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev) {
   if (x.zero() || y.zero()) { fill(ctx, out_dev, 1, 0.0); return; }
   // L_k (rx_k x ry_k); L_0 = [1].
-  DBuf L(&ctx.alloc, sizeof(double));
+  DBuf L(ctx.alloc, sizeof(double));
   fill(ctx, L.d(), 1, 1.0);
   for (int k = 0; k < 3; ++k) {
     const int rx0 = x.r[k], rx1 = x.r[k + 1], ry0 = y.r[k], ry1 = y.r[k + 1], n = x.n[k];
     // T[b][i][a'] = sum_a L[a][b] x[a][i][a']   : (ry0 x rx0)^T-view * (rx0 x n rx1)
-    DBuf T(&ctx.alloc, sizeof(double) * (size_t)ry0 * n * rx1);
+    DBuf T(ctx.alloc, sizeof(double) * (size_t)ry0 * n * rx1);
     gemm(ctx, true, false, ry0, n * rx1, rx0, 1.0, L.d(), ry0, 0, x.c[k].d(), (long)n * rx1, 0, 0.0,
          T.d(), (long)n * rx1, 0);
     // L'[a'][b'] = sum_{b,i} T[(b i)][a'] y[(b i)][b']
-    DBuf Ln(&ctx.alloc, sizeof(double) * (size_t)rx1 * ry1);
+    DBuf Ln(ctx.alloc, sizeof(double) * (size_t)rx1 * ry1);
     gemm(ctx, true, false, rx1, ry1, ry0 * n, 1.0, T.d(), rx1, 0, y.c[k].d(), ry1, 0, 0.0, Ln.d(),
          ry1, 0);
     L = std::move(Ln);
@@ -253,7 +253,7 @@ void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev) {
 }
 
 double tt_dot_sync(Context& ctx, const TT& x, const TT& y) {
-  DBuf o(&ctx.alloc, sizeof(double));
+  DBuf o(ctx.alloc, sizeof(double));
   tt_dot_dev(ctx, x, y, o.d());
   double* h = ctx.host(1);
   TTIGA_HIP(hipMemcpyAsync(h, o.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
@@ -274,38 +274,38 @@ static TruncSVD truncated_svd(Context& ctx, const double* B, int r, long M, doub
   TruncSVD o;
   if (M >= r) {
     // B^T = Q T (M x r), B = T^T Q^T, svd(T^T) = Ut S W^T, so B = Ut S (Q W)^T
-    DBuf Q(&ctx.alloc, sizeof(double) * M * r), T(&ctx.alloc, sizeof(double) * r * r);
+    DBuf Q(ctx.alloc, sizeof(double) * M * r), T(ctx.alloc, sizeof(double) * r * r);
     qr_tall(ctx, B, true, (int)M, r, M, Q.d(), T.d());
-    DBuf Ut(&ctx.alloc, sizeof(double) * r * r), W(&ctx.alloc, sizeof(double) * r * r);
-    o.S = DBuf(&ctx.alloc, sizeof(double) * r);
+    DBuf Ut(ctx.alloc, sizeof(double) * r * r), W(ctx.alloc, sizeof(double) * r * r);
+    o.S = DBuf(ctx.alloc, sizeof(double) * r);
     svd_small(ctx, T.d(), true, r, r, r, Ut.d(), o.S.d(), W.d());
     double nd[2];
     o.s = trunc_rank_sync(ctx, o.S.d(), r, delta, nd);
     o.norm = nd[0];
     o.delta = nd[1];
     if (o.s == 0) return o;
-    o.Vt = DBuf(&ctx.alloc, sizeof(double) * o.s * M);
+    o.Vt = DBuf(ctx.alloc, sizeof(double) * o.s * M);
     gemm(ctx, true, true, o.s, (int)M, r, 1.0, W.d(), r, 0, Q.d(), r, 0, 0.0, o.Vt.d(), M, 0);
-    o.U = DBuf(&ctx.alloc, sizeof(double) * r * o.s);
+    o.U = DBuf(ctx.alloc, sizeof(double) * r * o.s);
     hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long)r * o.s)), dim3(256), 0, ctx.stream, Ut.d(),
                        r, r, o.s, o.U.d());
   } else {
     // tall: B = Q T (r x M); Jacobi on the rows of T (converges in about half the
     // sweeps of its columns): T^T = V S Ut^T, so B = (Q Ut) S V^T
     const int c = (int)M;
-    DBuf Q(&ctx.alloc, sizeof(double) * (size_t)r * c), T(&ctx.alloc, sizeof(double) * c * c);
+    DBuf Q(ctx.alloc, sizeof(double) * (size_t)r * c), T(ctx.alloc, sizeof(double) * c * c);
     qr_tall(ctx, B, false, r, c, c, Q.d(), T.d());
-    DBuf Ut(&ctx.alloc, sizeof(double) * c * c), V(&ctx.alloc, sizeof(double) * c * c);
-    o.S = DBuf(&ctx.alloc, sizeof(double) * c);
+    DBuf Ut(ctx.alloc, sizeof(double) * c * c), V(ctx.alloc, sizeof(double) * c * c);
+    o.S = DBuf(ctx.alloc, sizeof(double) * c);
     svd_small(ctx, T.d(), true, c, c, c, V.d(), o.S.d(), Ut.d());
     double nd[2];
     o.s = trunc_rank_sync(ctx, o.S.d(), c, delta, nd);
     o.norm = nd[0];
     o.delta = nd[1];
     if (o.s == 0) return o;
-    o.U = DBuf(&ctx.alloc, sizeof(double) * (size_t)r * o.s);
+    o.U = DBuf(ctx.alloc, sizeof(double) * (size_t)r * o.s);
     gemm(ctx, false, false, r, o.s, c, 1.0, Q.d(), c, 0, Ut.d(), c, 0, 0.0, o.U.d(), o.s, 0);
-    o.Vt = DBuf(&ctx.alloc, sizeof(double) * o.s * M);
+    o.Vt = DBuf(ctx.alloc, sizeof(double) * o.s * M);
     hipLaunchKernelGGL(k_transpose_cols, dim3(grid_for((long)c * o.s)), dim3(256), 0, ctx.stream,
                        V.d(), c, c, o.s, o.Vt.d());
   }
@@ -324,19 +324,19 @@ void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_ran
     const int m = x.r[k] * x.n[k], c = x.r[k + 1];
     const int nn = x.n[k + 1], r2 = x.r[k + 2];
     if (m >= c) {
-      DBuf Q(&ctx.alloc, sizeof(double) * (size_t)m * c), R(&ctx.alloc, sizeof(double) * c * c);
+      DBuf Q(ctx.alloc, sizeof(double) * (size_t)m * c), R(ctx.alloc, sizeof(double) * c * c);
       qr_tall(ctx, x.c[k].d(), false, m, c, c, Q.d(), R.d());
-      DBuf nxt(&ctx.alloc, sizeof(double) * (size_t)c * nn * r2);
+      DBuf nxt(ctx.alloc, sizeof(double) * (size_t)c * nn * r2);
       gemm(ctx, false, false, c, nn * r2, c, 1.0, R.d(), c, 0, x.c[k + 1].d(), (long)nn * r2, 0, 0.0,
            nxt.d(), (long)nn * r2, 0);
       x.c[k] = std::move(Q);
       x.c[k + 1] = std::move(nxt);
     } else {
       // wide unfolding: Q = I_m, R = the unfolding itself; the rank drops to m
-      DBuf nxt(&ctx.alloc, sizeof(double) * (size_t)m * nn * r2);
+      DBuf nxt(ctx.alloc, sizeof(double) * (size_t)m * nn * r2);
       gemm(ctx, false, false, m, nn * r2, c, 1.0, x.c[k].d(), c, 0, x.c[k + 1].d(), (long)nn * r2, 0,
            0.0, nxt.d(), (long)nn * r2, 0);
-      DBuf I(&ctx.alloc, sizeof(double) * (size_t)m * m);
+      DBuf I(ctx.alloc, sizeof(double) * (size_t)m * m);
       hipLaunchKernelGGL(k_eye, dim3(grid_for((long)m * m)), dim3(256), 0, ctx.stream, m, I.d());
       TTIGA_HIP(hipGetLastError());
       x.c[k] = std::move(I);
@@ -362,12 +362,12 @@ void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_ran
     if (max_rank > 0 && t.s > max_rank)
       throw Error(TTIGA_E_RANKCAP, "TT rank " + std::to_string(t.s) + " exceeds max_rank");
     // core_{k-1} <- core_{k-1} * U_s S_s   ((r_{k-1} n_{k-1}) x r) * (r x s)
-    DBuf US(&ctx.alloc, sizeof(double) * r * t.s);
+    DBuf US(ctx.alloc, sizeof(double) * r * t.s);
     hipLaunchKernelGGL(k_scale_cols, dim3(grid_for((long)r * t.s)), dim3(256), 0, ctx.stream, t.U.d(),
                        r, t.s, t.S.d(), t.s, US.d());
     TTIGA_HIP(hipGetLastError());
     const int mprev = x.r[k - 1] * x.n[k - 1];
-    DBuf prev(&ctx.alloc, sizeof(double) * (size_t)mprev * t.s);
+    DBuf prev(ctx.alloc, sizeof(double) * (size_t)mprev * t.s);
     gemm(ctx, false, false, mprev, t.s, r, 1.0, x.c[k - 1].d(), r, 0, US.d(), t.s, 0, 0.0, prev.d(),
          t.s, 0);
     x.c[k] = std::move(t.Vt);
@@ -389,7 +389,7 @@ static int left_factor(Context& ctx, const double* A, int m, long M, double delt
     TruncSVD t = truncated_svd(ctx, A, m, M, delta);
     if (t.s == 0) return 0;
     U = std::move(t.U);
-    C = DBuf(&ctx.alloc, sizeof(double) * t.s * M);
+    C = DBuf(ctx.alloc, sizeof(double) * t.s * M);
     hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)t.s * M)), dim3(256), 0, ctx.stream,
                        t.Vt.d(), t.s, M, t.S.d(), C.d());
     TTIGA_HIP(hipGetLastError());
@@ -397,15 +397,15 @@ static int left_factor(Context& ctx, const double* A, int m, long M, double delt
   }
   int l = std::min(m, 48);
   while (true) {
-    DBuf Om(&ctx.alloc, sizeof(double) * M * l), Y(&ctx.alloc, sizeof(double) * (size_t)m * l);
+    DBuf Om(ctx.alloc, sizeof(double) * M * l), Y(ctx.alloc, sizeof(double) * (size_t)m * l);
     const uint64_t seed = ++ctx.rng_counter;
     hipLaunchKernelGGL(k_gaussian, dim3(grid_for(M * l)), dim3(256), 0, ctx.stream, Om.d(), M * l,
                        seed);
     TTIGA_HIP(hipGetLastError());
     gemm(ctx, false, false, m, l, (int)M, 1.0, A, M, 0, Om.d(), l, 0, 0.0, Y.d(), l, 0);
-    DBuf Qy(&ctx.alloc, sizeof(double) * (size_t)m * l), Ry(&ctx.alloc, sizeof(double) * l * l);
+    DBuf Qy(ctx.alloc, sizeof(double) * (size_t)m * l), Ry(ctx.alloc, sizeof(double) * l * l);
     qr_tall(ctx, Y.d(), false, m, l, l, Qy.d(), Ry.d());
-    DBuf B(&ctx.alloc, sizeof(double) * l * M);
+    DBuf B(ctx.alloc, sizeof(double) * l * M);
     gemm(ctx, true, false, l, (int)M, m, 1.0, Qy.d(), l, 0, A, M, 0, 0.0, B.d(), M, 0);
     TruncSVD t = truncated_svd(ctx, B.d(), l, M, delta);
     if (t.s == 0) return 0;
@@ -413,9 +413,9 @@ static int left_factor(Context& ctx, const double* A, int m, long M, double delt
       l = std::min(m, 2 * l);
       continue;
     }
-    U = DBuf(&ctx.alloc, sizeof(double) * (size_t)m * t.s);
+    U = DBuf(ctx.alloc, sizeof(double) * (size_t)m * t.s);
     gemm(ctx, false, false, m, t.s, l, 1.0, Qy.d(), l, 0, t.U.d(), t.s, 0, 0.0, U.d(), t.s, 0);
-    C = DBuf(&ctx.alloc, sizeof(double) * t.s * M);
+    C = DBuf(ctx.alloc, sizeof(double) * t.s * M);
     hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)t.s * M)), dim3(256), 0, ctx.stream,
                        t.Vt.d(), t.s, M, t.S.d(), C.d());
     TTIGA_HIP(hipGetLastError());
@@ -461,7 +461,7 @@ void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const C
   TTIGA_CHECK(nt > 0 && chunk > 0 && n0 > kExact && M > kExact && M <= INT32_MAX, TTIGA_E_ARG,
               "streamed compression needs more than 64 rows and columns");
   chunk = std::min(chunk, n1);
-  DBuf buf(&ctx.alloc, sizeof(double) * (size_t)nt * n0 * chunk * n2);
+  DBuf buf(ctx.alloc, sizeof(double) * (size_t)nt * n0 * chunk * n2);
   std::vector<double> delta(nt, 0.0);
   std::vector<char> todo(nt, 1);
   bool have_delta = false;
@@ -473,12 +473,12 @@ void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const C
     // pass 1: range sketches, summed over the column blocks
     std::vector<DBuf> Y(nt);
     {
-      DBuf Om(&ctx.alloc, sizeof(double) * (size_t)M * L);
+      DBuf Om(ctx.alloc, sizeof(double) * (size_t)M * L);
       hipLaunchKernelGGL(k_gaussian, dim3(grid_for(M * L)), dim3(256), 0, ctx.stream, Om.d(), M * L,
                          ++ctx.rng_counter);
       TTIGA_HIP(hipGetLastError());
       for (int t = 0; t < nt; ++t)
-        if (todo[t]) Y[t] = DBuf(&ctx.alloc, sizeof(double) * (size_t)n0 * L);
+        if (todo[t]) Y[t] = DBuf(ctx.alloc, sizeof(double) * (size_t)n0 * L);
       for (int b = 0; b < n1; b += chunk) {
         const int c = std::min(chunk, n1 - b);
         const long w = (long)c * n2;
@@ -503,11 +503,11 @@ void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const C
     std::vector<DBuf> Qy(nt), B(nt);
     for (int t = 0; t < nt; ++t) {
       if (!todo[t]) continue;
-      Qy[t] = DBuf(&ctx.alloc, sizeof(double) * (size_t)n0 * L);
-      DBuf Ry(&ctx.alloc, sizeof(double) * L * L);
+      Qy[t] = DBuf(ctx.alloc, sizeof(double) * (size_t)n0 * L);
+      DBuf Ry(ctx.alloc, sizeof(double) * L * L);
       qr_tall(ctx, Y[t].d(), false, n0, L, L, Qy[t].d(), Ry.d());
       Y[t].reset();
-      B[t] = DBuf(&ctx.alloc, sizeof(double) * (size_t)L * M);
+      B[t] = DBuf(ctx.alloc, sizeof(double) * (size_t)L * M);
     }
     // pass 2: projections B_t = Q_t^T A_t, one column block per chunk
     for (int b = 0; b < n1; b += chunk) {
@@ -534,9 +534,9 @@ void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const C
         continue;
       }
       const int s0 = sv.s;
-      DBuf U0(&ctx.alloc, sizeof(double) * (size_t)n0 * s0);
+      DBuf U0(ctx.alloc, sizeof(double) * (size_t)n0 * s0);
       gemm(ctx, false, false, n0, s0, L, 1.0, Qy[t].d(), L, 0, sv.U.d(), s0, 0, 0.0, U0.d(), s0, 0);
-      DBuf C0(&ctx.alloc, sizeof(double) * (size_t)s0 * M);
+      DBuf C0(ctx.alloc, sizeof(double) * (size_t)s0 * M);
       hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)s0 * M)), dim3(256), 0, ctx.stream,
                          sv.Vt.d(), s0, M, sv.S.d(), C0.d());
       TTIGA_HIP(hipGetLastError());
@@ -566,35 +566,35 @@ void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const C
 // (Q2^T Z2) X3.  The result is left-orthogonal with ranks (l1, l2).
 static void tt_sketch_project(Context& ctx, const TT& x, int l1, int l2, TT& y) {
   const int n0 = x.n[0], n1 = x.n[1], n2 = x.n[2], R1 = x.r[1], R2 = x.r[2];
-  DBuf O2(&ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2), O3(&ctx.alloc, sizeof(double) * (size_t)l2 * n2);
+  DBuf O2(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2), O3(ctx.alloc, sizeof(double) * (size_t)l2 * n2);
   hipLaunchKernelGGL(k_gaussian, dim3(grid_for((long)l1 * n1 * l2)), dim3(256), 0, ctx.stream, O2.d(),
                      (long)l1 * n1 * l2, ++ctx.rng_counter);
   hipLaunchKernelGGL(k_gaussian, dim3(grid_for((long)l2 * n2)), dim3(256), 0, ctx.stream, O3.d(),
                      (long)l2 * n2, ++ctx.rng_counter);
   TTIGA_HIP(hipGetLastError());
-  DBuf W3(&ctx.alloc, sizeof(double) * (size_t)R2 * l2);
+  DBuf W3(ctx.alloc, sizeof(double) * (size_t)R2 * l2);
   gemm(ctx, false, true, R2, l2, n2, 1.0, x.c[2].d(), n2, 0, O3.d(), n2, 0, 0.0, W3.d(), l2, 0);
-  DBuf T(&ctx.alloc, sizeof(double) * (size_t)R1 * n1 * l2);
+  DBuf T(ctx.alloc, sizeof(double) * (size_t)R1 * n1 * l2);
   gemm(ctx, false, false, R1 * n1, l2, R2, 1.0, x.c[1].d(), R2, 0, W3.d(), l2, 0, 0.0, T.d(), l2, 0);
-  DBuf W2(&ctx.alloc, sizeof(double) * (size_t)R1 * l1);
+  DBuf W2(ctx.alloc, sizeof(double) * (size_t)R1 * l1);
   gemm(ctx, false, true, R1, l1, n1 * l2, 1.0, T.d(), (long)n1 * l2, 0, O2.d(), (long)n1 * l2, 0, 0.0,
        W2.d(), l1, 0);
-  DBuf Y1(&ctx.alloc, sizeof(double) * (size_t)n0 * l1);
+  DBuf Y1(ctx.alloc, sizeof(double) * (size_t)n0 * l1);
   gemm(ctx, false, false, n0, l1, R1, 1.0, x.c[0].d(), R1, 0, W2.d(), l1, 0, 0.0, Y1.d(), l1, 0);
-  DBuf Q1(&ctx.alloc, sizeof(double) * (size_t)n0 * l1), Rq(&ctx.alloc, sizeof(double) * (size_t)l1 * l1);
+  DBuf Q1(ctx.alloc, sizeof(double) * (size_t)n0 * l1), Rq(ctx.alloc, sizeof(double) * (size_t)l1 * l1);
   qr_tall(ctx, Y1.d(), false, n0, l1, l1, Q1.d(), Rq.d());
-  DBuf M1(&ctx.alloc, sizeof(double) * (size_t)l1 * R1);
+  DBuf M1(ctx.alloc, sizeof(double) * (size_t)l1 * R1);
   gemm(ctx, true, false, l1, R1, n0, 1.0, Q1.d(), l1, 0, x.c[0].d(), R1, 0, 0.0, M1.d(), R1, 0);
-  DBuf Z2(&ctx.alloc, sizeof(double) * (size_t)l1 * n1 * R2);
+  DBuf Z2(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * R2);
   gemm(ctx, false, false, l1, n1 * R2, R1, 1.0, M1.d(), R1, 0, x.c[1].d(), (long)n1 * R2, 0, 0.0, Z2.d(),
        (long)n1 * R2, 0);
-  DBuf Y2(&ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2);
+  DBuf Y2(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2);
   gemm(ctx, false, false, l1 * n1, l2, R2, 1.0, Z2.d(), R2, 0, W3.d(), l2, 0, 0.0, Y2.d(), l2, 0);
-  DBuf Q2(&ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2), Rq2(&ctx.alloc, sizeof(double) * (size_t)l2 * l2);
+  DBuf Q2(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2), Rq2(ctx.alloc, sizeof(double) * (size_t)l2 * l2);
   qr_tall(ctx, Y2.d(), false, l1 * n1, l2, l2, Q2.d(), Rq2.d());
-  DBuf M2(&ctx.alloc, sizeof(double) * (size_t)l2 * R2);
+  DBuf M2(ctx.alloc, sizeof(double) * (size_t)l2 * R2);
   gemm(ctx, true, false, l2, R2, l1 * n1, 1.0, Q2.d(), l2, 0, Z2.d(), R2, 0, 0.0, M2.d(), R2, 0);
-  DBuf C3(&ctx.alloc, sizeof(double) * (size_t)l2 * n2);
+  DBuf C3(ctx.alloc, sizeof(double) * (size_t)l2 * n2);
   gemm(ctx, false, false, l2, n2, R2, 1.0, M2.d(), R2, 0, x.c[2].d(), n2, 0, 0.0, C3.d(), n2, 0);
   y.n[0] = n0; y.n[1] = n1; y.n[2] = n2;
   y.r[0] = 1; y.r[1] = l1; y.r[2] = l2; y.r[3] = 1;
@@ -604,12 +604,11 @@ static void tt_sketch_project(Context& ctx, const TT& x, int l1, int l2, TT& y) 
 }
 
 static bool trace_rounding() {
-  static int v = -1;
-  if (v < 0) {
+  static const bool v = [] {
     const char* e = std::getenv("TTIGA_TRACE_ROUND");
-    v = (e && e[0] == '1') ? 1 : 0;
-  }
-  return v == 1;
+    return e && e[0] == '1';
+  }();
+  return v;
 }
 
 void tt_round_auto(Context& ctx, TT& x, double eps_rel, int max_rank, int& hint) {
@@ -652,7 +651,7 @@ void tt_round_auto(Context& ctx, TT& x, double eps_rel, int max_rank, int& hint)
 void tt_mode_product(Context& ctx, TT& x, int d, const double* Mat, bool trans) {
   if (x.zero()) return;
   const int ra = x.r[d], n = x.n[d], rb = x.r[d + 1];
-  DBuf out(&ctx.alloc, sizeof(double) * x.core_elems(d));
+  DBuf out(ctx.alloc, sizeof(double) * x.core_elems(d));
   // out[a] (n x rb) = op(Mat) (n x n) * X[a] (n x rb), batched over a
   gemm(ctx, trans, false, n, rb, n, 1.0, Mat, n, 0, x.c[d].d(), rb, (long)n * rb, 0.0, out.d(), rb,
        (long)n * rb, ra);

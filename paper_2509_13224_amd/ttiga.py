@@ -34,7 +34,9 @@ EXPORTED = (
     "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
     "ttiga_sample_factors", "ttiga_tt_matvec", "ttiga_tt_round", "ttiga_tt_dot",
     "ttiga_tt_compress", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free", "ttiga_profile",
-    "ttiga_profile_read",
+    "ttiga_profile_read", "ttiga_tt_view_of", "ttiga_footprint", "ttiga_solve_batch",
+    "ttiga_server_create", "ttiga_server_submit", "ttiga_server_poll", "ttiga_server_solution",
+    "ttiga_server_copy_solution", "ttiga_server_release", "ttiga_server_destroy",
 )
 
 c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -94,6 +96,28 @@ class KernelStat(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("geo", ctypes.POINTER(Geometry)), ("disc", ctypes.POINTER(Discretization)),
+                ("src", ctypes.POINTER(Source)), ("bc", ctypes.POINTER(Dirichlet)),
+                ("opt", ctypes.POINTER(Options))]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("lane", ctypes.c_int), ("rank_u", ctypes.c_int * 4),
+                ("n", ctypes.c_int * 3), ("assembly", AssemblyStats), ("solve", SolveStats),
+                ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("error", ctypes.c_char * 128)]
+
+
+def _result_dict(r):
+    return dict(status=r.status, lane=r.lane, rank_u=list(r.rank_u), n=list(r.n),
+                iterations=r.solve.iterations, rel_res=r.solve.rel_res, rel_pres=r.solve.rel_pres,
+                max_rank_seen=r.solve.max_rank_seen, rank_K=list(r.assembly.rank_K),
+                queue_ms=r.queue_ms, run_ms=r.run_ms, latency_ms=r.latency_ms,
+                footprint_bytes=r.footprint_bytes, peak_bytes=r.peak_bytes, error=r.error.decode())
+
+
 class TTIGAError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"ttiga error {code}: {msg}")
@@ -142,6 +166,19 @@ def load(path=LIB_PATH):
         "ttiga_tt_free": (ctypes.c_int, [vp]),
         "ttiga_profile": (ctypes.c_int, [vp, ctypes.c_int]),
         "ttiga_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(KernelStat), ctypes.c_int, c_int_p]),
+        "ttiga_tt_view_of": (ctypes.c_int, [vp, ctypes.POINTER(TTView)]),
+        "ttiga_footprint": (ctypes.c_int, [ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)]),
+        "ttiga_solve_batch": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(Request), ctypes.c_int,
+                                             ctypes.c_size_t, ctypes.POINTER(vp), ctypes.POINTER(Result)]),
+        "ttiga_server_create": (ctypes.c_int, [vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(vp)]),
+        "ttiga_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(Request),
+                                               ctypes.POINTER(ctypes.c_ulonglong)]),
+        "ttiga_server_poll": (ctypes.c_int, [vp, ctypes.c_ulonglong, ctypes.c_int, ctypes.POINTER(Result)]),
+        "ttiga_server_solution": (ctypes.c_int, [vp, ctypes.c_ulonglong, ctypes.POINTER(TTView)]),
+        "ttiga_server_copy_solution": (ctypes.c_int, [vp, ctypes.c_ulonglong, c_dbl_p, ctypes.c_size_t]),
+        "ttiga_server_release": (ctypes.c_int, [vp, ctypes.c_ulonglong]),
+        "ttiga_server_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -227,6 +264,25 @@ class Context:
     # ---------------------------------------------------------------- problems
     def problem_create(self, pr, precond=0):
         return ProblemHandle(self, pr, precond)
+
+    def solve_batch(self, problems, lanes=4, hbm_budget=0, precond=1):
+        """ttiga_solve_batch over workloads.Problem descriptions.
+
+        Returns a list of (result dict, solution cores on the host or None)."""
+        count = len(problems)
+        reqs, keep = make_requests(problems, precond)
+        sols = (ctypes.c_void_p * max(count, 1))()
+        res = (Result * max(count, 1))()
+        _check(self.lib, self.lib.ttiga_solve_batch(self.h, count, reqs, int(lanes), ctypes.c_size_t(hbm_budget),
+                                                    sols, res))
+        out = []
+        for i in range(count):
+            cores = self._take(ctypes.c_void_p(sols[i])) if sols[i] else None
+            out.append((_result_dict(res[i]), cores))
+        return out
+
+    def server(self, hbm_budget=0, lanes=4, max_queue=1024):
+        return Server(self, hbm_budget, lanes, max_queue)
 
     # ---------------------------------------------------------------- standalone ops
     def _view(self, cores_dev):
@@ -331,6 +387,82 @@ def describe(pr, precond=0):
     o.precond = precond
     o.sample_chunk_bytes = int(getattr(pr.options, "sample_chunk_bytes", 0))
     return (g, disc, src, bc, o), keep
+
+
+def make_requests(problems, precond=1):
+    """ctypes array of ttiga_request for a list of workloads.Problem (plus keep-alive list)."""
+    keep = []
+    reqs = (Request * max(len(problems), 1))()
+    for i, pr in enumerate(problems):
+        structs, k = describe(pr, precond)
+        keep.append((structs, k))
+        g, disc, src, bc, o = structs
+        reqs[i].geo = ctypes.pointer(g)
+        reqs[i].disc = ctypes.pointer(disc)
+        reqs[i].src = ctypes.pointer(src)
+        reqs[i].bc = ctypes.pointer(bc)
+        reqs[i].opt = ctypes.pointer(o)
+    return reqs, keep
+
+
+def footprint(pr, precond=1):
+    """ttiga_footprint: the admission estimate in bytes (host only)."""
+    lib = load()
+    reqs, keep = make_requests([pr], precond)
+    out = ctypes.c_size_t()
+    _check(lib, lib.ttiga_footprint(reqs, ctypes.byref(out)))
+    return out.value
+
+
+class Server:
+    """ttiga_server_*: continuous batching of TT-IGA solves on one context."""
+
+    def __init__(self, ctx, hbm_budget=0, lanes=4, max_queue=1024):
+        self.ctx, self.lib = ctx, ctx.lib
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.ttiga_server_create(ctx.h, ctypes.c_size_t(hbm_budget), int(lanes),
+                                                      int(max_queue), ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, pr, precond=1):
+        """Returns a ticket; raises TTIGAError (code TTIGA_E_ADMISSION) when refused."""
+        reqs, keep = make_requests([pr], precond)
+        t = ctypes.c_ulonglong()
+        _check(self.lib, self.lib.ttiga_server_submit(self.h, reqs, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket, wait_ms=0):
+        """None while pending, else the result dict."""
+        r = Result()
+        code = _check(self.lib, self.lib.ttiga_server_poll(self.h, ticket, int(wait_ms), ctypes.byref(r)),
+                      (TTIGA_OK, TTIGA_PENDING))
+        return None if code == TTIGA_PENDING else _result_dict(r)
+
+    def solution(self, ticket):
+        """Host copy of the solution cores (paper order)."""
+        v = TTView()
+        _check(self.lib, self.lib.ttiga_server_solution(self.h, ticket, ctypes.byref(v)))
+        r, n = list(v.r), list(v.n)
+        total = sum(r[k] * n[k] * r[k + 1] for k in range(3))
+        flat = np.zeros(max(total, 1))
+        _check(self.lib, self.lib.ttiga_server_copy_solution(self.h, ticket, _dptr(flat), ctypes.c_size_t(flat.size)))
+        if r[1] == 0:
+            return None
+        return split_cores(flat, n, r)
+
+    def release(self, ticket):
+        _check(self.lib, self.lib.ttiga_server_release(self.h, ticket))
+
+    def close(self):
+        if self.h:
+            self.lib.ttiga_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def validate(pr, precond=0):

@@ -99,3 +99,23 @@ def test_validate_constant_dirichlet_rules():
                          value=(1.0, 2.0, 3.0, 0, 0, 0))
     code, msg = ttiga.validate(W.small_problem(geo, 8, 2, W.zero_source(), dirichlet=two_dirs))
     assert code == ttiga.TTIGA_E_ARG and "more than one direction" in msg
+
+
+def test_footprint_estimate_orders_requests():
+    """Admission estimates (host only): grow with the grid, and the slab-streamed sampling
+    keeps the n=256 problem far below the 58 GB of whole-grid factor samples."""
+    from workloads.problem import PREC_FP64
+    f16 = ttiga.footprint(W.c1_problem(n=16))
+    f64 = ttiga.footprint(W.c2_problem(n=64))
+    f256 = ttiga.footprint(W.c2_problem(n=256))
+    c3 = W.c3_problem(n=512)
+    c3.options.precision = PREC_FP64
+    f512 = ttiga.footprint(c3)
+    assert 0 < f16 < f64 < f256 < f512
+    whole_256 = 7 * 1012 ** 3 * 8
+    assert f256 < whole_256 / 4 and f256 < 16 << 30
+    assert f512 < 64 << 30
+    # forcing small chunks shrinks the estimate of a mid-size problem
+    pr = W.c2_problem(n=64)
+    pr.options.sample_chunk_bytes = 64 << 20
+    assert ttiga.footprint(pr) < f64
