@@ -121,7 +121,10 @@ typedef struct {
                          estimate of the relative error of u (P^-1 K is near the identity) */
   int max_iter;
   int max_rank;       /* cap on every TT rank; exceeding it fails with E_RANKCAP */
-  int precision;      /* TTIGA_FP64 (others: E_ARG in this version) */
+  int precision;      /* TTIGA_FP64; or TTIGA_FP32 / TTIGA_BF16: K_II stored in that type and
+                         its products with FP32 arithmetic inside the corrections of an
+                         iterative refinement whose residual, updates and roundings are
+                         FP64 (needs precond = 1) */
   int precond;        /* 1: separable Laplacian preconditioner, 0: plain TT-CG */
   size_t sample_chunk_bytes; /* 0: automatic (the Gauss-grid factor samples are held whole
                          up to 2 GiB, beyond that sampled and compressed in chunks of
@@ -152,6 +155,7 @@ typedef struct {
   double precond_err;/* max relative error of that sum on the spectrum interval */
   double precond_setup_ms; /* preconditioner set-up time within time_ms */
   double time_ms;
+  int refine_steps;  /* mixed precision: FP64 refinement steps (iterations counts the inner ones) */
 } ttiga_solve_stats;
 
 /* Plain views of caller-owned device TT data (used by the standalone ops). */
@@ -234,6 +238,13 @@ int ttiga_sample_factors(ttiga_problem* prob, const double* pts, size_t count, d
 /* Standalone banded TT-matvec y = K x on caller device data: y is written to a
  * library-owned TT (ranks r_K * r_x), returned in *out (free with ttiga_tt_free). */
 int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, ttiga_tt** out);
+
+/* The same product with the operator cores rounded to dtype (TTIGA_FP32 or TTIGA_BF16,
+ * round to nearest even; BF16 through FP32), the vector cores to FP32, FP32 products
+ * and band sums, and the result cores in FP64: the contraction of the mixed-precision
+ * solve, exposed for accuracy checks and timing. */
+int ttiga_tt_matvec_lowp(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, int dtype,
+                         ttiga_tt** out);
 
 /* Standalone TT-rounding (Oseledets 2011, used after each summation of
  * Section 4.2.1): y = round(x, eps) with per-unfolding threshold

@@ -473,6 +473,40 @@ int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view
   });
 }
 
+int ttiga_tt_matvec_lowp(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, int dtype,
+                         ttiga_tt** out) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && K && x && out, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(K->p >= 0 && K->p <= 16, TTIGA_E_ARG, "bad band half-width");
+    TTIGA_CHECK(dtype == TTIGA_FP32 || dtype == TTIGA_BF16, TTIGA_E_ARG, "dtype must be TTIGA_FP32 or TTIGA_BF16");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    ttiga_tt_view kv{};
+    const int band = 2 * K->p + 1;
+    for (int k = 0; k < 3; ++k) {
+      TTIGA_CHECK(K->n[k] == x->n[k], TTIGA_E_ARG, "matvec: mode sizes differ");
+      kv.n[k] = K->n[k] * band;
+      kv.core[k] = K->core[k];
+    }
+    for (int k = 0; k < 4; ++k) kv.r[k] = K->r[k];
+    TT Kt, xt;
+    tt_from_view(c, kv, Kt);
+    tt_from_view(c, *x, xt);
+    LowpTT Kl;
+    tt_to_lowp(c, Kt, dtype, Kl);
+    auto* res = new ttiga_tt{&c, TT()};
+    try {
+      tt_matvec_banded_lp(c, Kl, K->p, xt, res->t);
+      c.sync();
+    } catch (...) {
+      delete res;
+      throw;
+    }
+    *out = res;
+    ctx_retain(&c);
+  });
+}
+
 int ttiga_tt_round(ttiga_ctx* ctx, const ttiga_tt_view* x, double eps, ttiga_tt** out) {
   return guard([&] {
     TTIGA_CHECK(ctx && x && out, TTIGA_E_ARG, "null argument");

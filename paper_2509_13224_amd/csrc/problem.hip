@@ -133,7 +133,10 @@ Problem::Problem(Context* c, const ttiga_geometry* geo, const ttiga_discretizati
   TTIGA_CHECK(opts.tt_eps > 0.0 && opts.tt_eps < 1.0, TTIGA_E_ARG, "tt_eps must be in (0, 1)");
   TTIGA_CHECK(opts.rel_res_tol > 0.0, TTIGA_E_ARG, "rel_res_tol must be positive");
   TTIGA_CHECK(opts.max_iter > 0, TTIGA_E_ARG, "max_iter must be positive");
-  TTIGA_CHECK(opts.precision == TTIGA_FP64, TTIGA_E_ARG, "only TTIGA_FP64 in this version");
+  TTIGA_CHECK(opts.precision == TTIGA_FP64 || opts.precision == TTIGA_FP32 || opts.precision == TTIGA_BF16,
+              TTIGA_E_ARG, "precision must be TTIGA_FP64, TTIGA_FP32 or TTIGA_BF16");
+  TTIGA_CHECK(opts.precision == TTIGA_FP64 || opts.precond == 1, TTIGA_E_ARG,
+              "mixed precision refines around the preconditioned solver (precond = 1)");
   if (opts.max_rank <= 0) opts.max_rank = 1 << 20;
 }
 
@@ -428,7 +431,10 @@ void Problem::solve(ttiga_solve_stats* st) {
     const double ts = now_ms();
     if (!pc.ready) pc.setup(*this);
     s.precond_setup_ms = now_ms() - ts;
-    solve_pcg(s);
+    if (opts.precision == TTIGA_FP64)
+      solve_pcg(s);
+    else
+      solve_mixed(s);
   } else {
     solve_cg(s);
   }
@@ -441,11 +447,13 @@ void Problem::solve(ttiga_solve_stats* st) {
   if (s.status != TTIGA_OK) throw Error(s.status, "TT-CG did not reach rel_res_tol within max_iter");
 }
 
-// ||b - K_II x|| / ||b||, with the residual train b - K_II x rounded at eps_x (replaces r).
-static double true_residual(Context& c, const TT& KII, int p, const TT& b, const TT& x, double nb,
+using Matvec = std::function<void(const TT&, TT&)>;
+
+// ||b - K x|| / ||b||, with the residual train b - K x rounded at eps_x (replaces r).
+static double true_residual(Context& c, const Matvec& mv, const TT& b, const TT& x, double nb,
                             double eps_x, int max_rank, TT& r, int& hint) {
   TT Kx, tr;
-  tt_matvec_banded(c, KII, p, x, Kx);
+  mv(x, Kx);
   tt_axpby(c, 1.0, b, -1.0, Kx, tr);
   if (eps_x < 1e-9) {
     // near cancellation a sketch of [b, -K x] loses digits; Householder orthogonalisation
@@ -468,6 +476,7 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
   const double tol = opts.rel_res_tol;
   const double eps = std::min(opts.tt_eps, 0.3 * tol);
   const double eps_x = std::min(opts.tt_eps, 0.1 * tol);
+  const Matvec mv = [&](const TT& v, TT& out) { tt_matvec_banded(c, KII, p, v, out); };
   int max_seen = 0;
   auto seen = [&](const TT& t) {
     for (int k = 1; k < 3; ++k) max_seen = std::max(max_seen, t.r[k]);
@@ -496,7 +505,7 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
     r = std::move(rn);
     const double est = std::sqrt(std::max(tt_dot_sync(c, r, r), 0.0)) / nb;
     if (it % 10 == 0 || est <= tol) {
-      true_res = true_residual(c, KII, p, rhs, u, nb, eps_x, opts.max_rank, r, hr);
+      true_res = true_residual(c, mv, rhs, u, nb, eps_x, opts.max_rank, r, hr);
       if (true_res <= tol) {
         conv = true;
         break;
@@ -513,7 +522,7 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
   }
   if (!conv) {
     TT tmp;
-    true_res = true_residual(c, KII, p, rhs, u, nb, eps_x, 0, tmp, hr);
+    true_res = true_residual(c, mv, rhs, u, nb, eps_x, 0, tmp, hr);
   }
   s.iterations = it;
   s.rel_res = true_res;
@@ -533,78 +542,81 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
 // relative 2-norm error of the iterate; the plain residual of a truncated iterate
 // is amplified by kappa(K) and would stall near kappa * eps.  The test is
 // confirmed on the true residual b - K x every 10 iterations and before stopping.
-void Problem::solve_pcg(ttiga_solve_stats& s) {
+PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int max_iter,
+                        const LowpTT* Klp, int& max_seen) {
   Context& c = *ctx;
-  const double tol = opts.rel_res_tol;
+  const Matvec mv = [&](const TT& v, TT& out) {
+    if (Klp)
+      tt_matvec_banded_lp(c, *Klp, p, v, out);
+    else
+      tt_matvec_banded(c, KII, p, v, out);
+  };
   // every rounding inside the iteration injects a relative error into the residual
   // recursion, so it must sit below the error target; truncating the iterate by a
   // relative delta moves P^-1 r by about delta (P^-1 K is near the identity), so the
   // iterate takes the same tolerance; the preconditioner only needs two digits
-  const double eps0 = std::min(opts.tt_eps, 0.3 * tol);
-  const double eps_x = std::min(opts.tt_eps, 0.3 * tol);
+  const double eps0 = eps_floor;
+  const double eps_x = eps_floor;
   double eps = eps0;
   double best = 1.0;
   int best_it = 0;
-  int max_seen = 0;
   auto seen = [&](const TT& t) {
     for (int k = 1; k < 3; ++k) max_seen = std::max(max_seen, t.r[k]);
   };
-  const double nb = std::sqrt(std::max(tt_dot_sync(c, rhs, rhs), 0.0));
+  const double nb = std::sqrt(std::max(tt_dot_sync(c, b, b), 0.0));
   TT r, z, pdir;
-  tt_copy(c, rhs, r);
+  tt_copy(c, b, r);
   int hq = 8, hx = 8, hr = 8, hp = 8, hz = 8;
   auto eps_p = [&]() { return std::max(eps, 1e-2); };
   pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
   tt_copy(c, z, pdir);
   double rho = tt_dot_sync(c, r, z);
-  int it = 0;
-  bool conv = false;
-  double true_res = 1.0, pres = 1.0;
-  while (it < opts.max_iter) {
-    ++it;
+  PcgRun o;
+  while (o.it < max_iter) {
+    ++o.it;
     TT q;
-    tt_matvec_banded(c, KII, p, pdir, q);
+    mv(pdir, q);
     seen(q);
     tt_round_auto(c, q, eps, opts.max_rank, hq);
     const double alpha = rho / tt_dot_sync(c, pdir, q);
     TT xn, rn;
-    tt_axpby(c, 1.0, u, alpha, pdir, xn);
+    tt_axpby(c, 1.0, x, alpha, pdir, xn);
     tt_round_auto(c, xn, eps_x, opts.max_rank, hx);
-    u = std::move(xn);
-    seen(u);
+    x = std::move(xn);
+    seen(x);
     tt_axpby(c, 1.0, r, -alpha, q, rn);
     tt_round_auto(c, rn, eps, opts.max_rank, hr);
     TT r_old = std::move(r);
     r = std::move(rn);
     bool replaced = false;
-    if (it % 10 == 0) {
-      true_res = true_residual(c, KII, p, rhs, u, nb, eps_x, opts.max_rank, r, hr);
+    if (o.it % 10 == 0) {
+      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr);
       replaced = true;
     }
     pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
     seen(z);
     double rho_new = tt_dot_sync(c, r, z);
     auto err_est = [&]() {
-      const double zz = tt_dot_sync(c, z, z), xx = tt_dot_sync(c, u, u);
+      const double zz = tt_dot_sync(c, z, z), xx = tt_dot_sync(c, x, x);
       return std::sqrt(std::max(zz, 0.0) / std::max(xx, 1e-300));
     };
-    pres = err_est();
-    if (pres <= tol && !replaced) {
-      true_res = true_residual(c, KII, p, rhs, u, nb, eps_x, opts.max_rank, r, hr);
+    o.pres = err_est();
+    if (o.pres <= tol && !replaced) {
+      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr);
       pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
       rho_new = tt_dot_sync(c, r, z);
-      pres = err_est();
+      o.pres = err_est();
     }
-    if (pres <= tol) {
-      conv = true;
+    if (o.pres <= tol) {
+      o.conv = true;
       break;
     }
-    eps = std::min(1e-3, std::max(eps0, 0.1 * tol / std::max(pres, 1e-300)));
+    eps = std::min(1e-3, std::max(eps0, 0.1 * tol / std::max(o.pres, 1e-300)));
     // stagnation: no halving of the best preconditioned residual in 15 iterations
-    if (pres < 0.5 * best) {
-      best = pres;
-      best_it = it;
-    } else if (it - best_it >= 15) {
+    if (o.pres < 0.5 * best) {
+      best = o.pres;
+      best_it = o.it;
+    } else if (o.it - best_it >= 15) {
       break;
     }
     const double beta = std::max(0.0, (rho_new - tt_dot_sync(c, r_old, z)) / rho);
@@ -614,13 +626,82 @@ void Problem::solve_pcg(ttiga_solve_stats& s) {
     tt_round_auto(c, pn, eps, opts.max_rank, hp);
     pdir = std::move(pn);
   }
-  if (!conv) {
+  if (!o.conv) {
     TT tmp;
-    true_res = true_residual(c, KII, p, rhs, u, nb, eps_x, 0, tmp, hr);
+    o.true_res = true_residual(c, mv, b, x, nb, eps_x, 0, tmp, hr);
   }
-  s.iterations = it;
+  return o;
+}
+
+// Flexible preconditioned truncated TT-CG in FP64 on K_II u = rhs.
+void Problem::solve_pcg(ttiga_solve_stats& s) {
+  const double tol = opts.rel_res_tol;
+  int max_seen = 0;
+  const PcgRun o = pcg_run(rhs, u, tol, std::min(opts.tt_eps, 0.3 * tol), opts.max_iter, nullptr, max_seen);
+  s.iterations = o.it;
+  s.rel_res = o.true_res;
+  s.rel_pres = o.pres;
+  s.max_rank_seen = max_seen;
+  s.precond_terms = pc.R;
+  s.precond_err = pc.approx_err;
+  s.status = o.conv ? TTIGA_OK : TTIGA_E_NOTCONV;
+}
+
+// Mixed precision by iterative refinement: the operator is stored in FP32 or BF16 (the
+// cores of K_II rounded once), and each correction d solves K d = r with the same
+// flexible PCG whose products K v take the low-precision cores with FP32 arithmetic,
+// to a loose relative tolerance t.  The update u + d, the residual r = rhs - K u (FP64
+// product), its rounding, the preconditioned error estimate and every QR/SVD stay in
+// FP64.  A correction of relative accuracy t reduces the error by about
+// max(t, kappa u_low); with FP32 (u = 6e-8) that is a few steps for any mesh here,
+// with BF16 (u = 3.9e-3) only small meshes contract at all, so a step that does not
+// halve the estimate ends the refinement (E_NOTCONV).  Since a correction is only
+// needed to relative accuracy t, the residual it starts from and the trains inside its
+// solve are truncated relative to their own norms at a fraction of t, not at the final
+// tolerance: the residual of an accurate iterate is rough, and resolving it to 1e-8 of
+// its norm would cost ranks in the hundreds for digits the correction cannot use.
+void Problem::solve_mixed(ttiga_solve_stats& s) {
+  Context& c = *ctx;
+  if (Klp.r[1] == 0) tt_to_lowp(c, KII, opts.precision, Klp);
+  const Matvec mv = [&](const TT& v, TT& out) { tt_matvec_banded(c, KII, p, v, out); };
+  const double tol = opts.rel_res_tol;
+  const double eps_x = std::min(opts.tt_eps, 0.3 * tol);
+  const double floor_in = opts.precision == TTIGA_BF16 ? 3e-2 : 1e-3;
+  const double eps_r = std::max(eps_x, 0.1 * floor_in);
+  const double nb = std::sqrt(std::max(tt_dot_sync(c, rhs, rhs), 0.0));
+  TT r;
+  tt_copy(c, rhs, r);
+  double est = 1.0, prev = 1e300, true_res = 1.0;
+  int inner = 0, steps = 0, max_seen = 0, hx = 8, hr = 8, hz = 8;
+  bool conv = false;
+  while (steps < kMaxRefineSteps && inner < opts.max_iter) {
+    ++steps;
+    const double tol_in = std::max(floor_in, 0.3 * tol / est);
+    TT d;
+    d.set_zero(u.n);
+    const PcgRun o = pcg_run(r, d, tol_in, std::min(0.1, 0.3 * tol_in), opts.max_iter - inner, &Klp, max_seen);
+    inner += o.it;
+    if (d.zero()) break;
+    TT un;
+    tt_axpby(c, 1.0, u, 1.0, d, un);
+    tt_round_auto(c, un, eps_x, opts.max_rank, hx);
+    u = std::move(un);
+    true_res = true_residual(c, mv, rhs, u, nb, eps_r, opts.max_rank, r, hr);
+    TT z;
+    pc.apply(c, r, z, 1e-2, opts.max_rank, hz);
+    const double zz = tt_dot_sync(c, z, z), uu = tt_dot_sync(c, u, u);
+    est = std::sqrt(std::max(zz, 0.0) / std::max(uu, 1e-300));
+    if (est <= tol) {
+      conv = true;
+      break;
+    }
+    if (est > 0.5 * prev) break;  // the low-precision corrections no longer contract
+    prev = est;
+  }
+  s.iterations = inner;
+  s.refine_steps = steps;
   s.rel_res = true_res;
-  s.rel_pres = pres;
+  s.rel_pres = est;
   s.max_rank_seen = max_seen;
   s.precond_terms = pc.R;
   s.precond_err = pc.approx_err;

@@ -12,6 +12,15 @@ namespace ttiga {
 constexpr uint64_t kAssembleSeed = 0xa55e3b1e00000000ull;
 constexpr uint64_t kSolveSeed = 0x501fe00000000000ull;
 
+// Outcome of one flexible PCG run.
+struct PcgRun {
+  int it = 0;
+  double pres = 1.0, true_res = 1.0;
+  bool conv = false;
+};
+
+constexpr int kMaxRefineSteps = 12;
+
 struct Problem {
   Context* ctx;
   // description
@@ -33,6 +42,7 @@ struct Problem {
   DBuf gtab_span[3], gtab_B[3], gtab_D[3];
   // TT state
   TT R[6], fJ, K, F, KII, rhs, u;
+  LowpTT Klp;  // K_II in FP32 or BF16 for the mixed-precision solve
   Precond pc;
   double min_detJ = 0.0;
   bool assembled = false, solved = false;
@@ -50,6 +60,9 @@ struct Problem {
  private:
   void solve_cg(ttiga_solve_stats& s);
   void solve_pcg(ttiga_solve_stats& s);
+  void solve_mixed(ttiga_solve_stats& s);
+  PcgRun pcg_run(const TT& b, TT& x, double tol, double eps_floor, int max_iter, const LowpTT* Klp,
+                 int& max_seen);
   void build_tables();
   void reduce_boundary();
   SourceDev source_dev() const;

@@ -194,6 +194,14 @@ struct TT {
   }
 };
 
+// TT-matrix cores stored in FP32 or BF16 (raw 16-bit) for low-precision products.
+struct LowpTT {
+  int dtype = TTIGA_FP32;
+  int n[3] = {0, 0, 0};
+  int r[4] = {0, 0, 0, 0};
+  DBuf c[3];
+};
+
 // Library-owned TT tensor returned through the C ABI.
 }  // namespace ttiga
 
@@ -240,6 +248,10 @@ void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* 
 double tt_dot_sync(Context& ctx, const TT& x, const TT& y);
 void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev);
 void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y);
+// FP64 cores -> FP32 or BF16 cores (round to nearest even, BF16 through FP32).
+void tt_to_lowp(Context& ctx, const TT& src, int dtype, LowpTT& dst);
+// y = K x with K in FP32/BF16, x rounded to FP32, FP32 products and band sums, y in FP64.
+void tt_matvec_banded_lp(Context& ctx, const LowpTT& K, int p, const TT& x, TT& y);
 void tt_compress_dense(Context& ctx, const double* A, const int* n, double delta, TT& out,
                        int max_rank);
 void tt_copy(Context& ctx, const TT& src, TT& dst);

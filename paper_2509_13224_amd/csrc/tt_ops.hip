@@ -48,6 +48,53 @@ __global__ void k_matvec_banded(int n, int p, int rK0, int rK1, int rx0, int rx1
   }
 }
 
+// Low-precision operands.  BF16 is kept as its 16 raw bits: FP32 rounded to nearest
+// even on the upper half (so FP64 -> BF16 rounds through FP32), NaN kept quiet.
+__device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float lp_to_f32(float v) { return v; }
+__device__ inline float lp_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline void lp_store(float* p, double v) { *p = (float)v; }
+__device__ inline void lp_store(uint16_t* p, double v) { *p = f32_to_bf16((float)v); }
+
+template <class T>
+__global__ void k_to_lowp(const double* __restrict__ src, long n, T* __restrict__ dst) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    lp_store(dst + e, src[e]);
+}
+
+// The banded product of k_matvec_banded with the operator core in FP32 or BF16 and the
+// vector core in FP32, products and sums over the band in FP32; the output core is
+// written in FP64 for the FP64 rounding that follows.
+template <class TK>
+__global__ void k_matvec_banded_lp(int n, int p, int rK0, int rK1, int rx0, int rx1,
+                                   const TK* __restrict__ M, const float* __restrict__ X,
+                                   double* __restrict__ Y) {
+  const long R1 = (long)rK1 * rx1;
+  const long total = (long)rK0 * rx0 * n * R1;
+  const int band = 2 * p + 1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int a2 = e % rx1;
+    const int b2 = (e / rx1) % rK1;
+    const int i = (e / R1) % n;
+    const long ba = e / (R1 * n);
+    const int a = ba % rx0, b = ba / rx0;
+    const TK* Mrow = M + (((long)b * n + i) * band) * rK1 + b2;
+    float s = 0.0f;
+    for (int t = 0; t < band; ++t) {
+      const int j = i + t - p;
+      if (j < 0 || j >= n) continue;
+      s += lp_to_f32(Mrow[(long)t * rK1]) * X[((long)a * n + j) * rx1 + a2];
+    }
+    Y[e] = (double)s;
+  }
+}
+
 // out core k of alpha x + beta y (block structure of the TT sum).
 __global__ void k_axpby_core(int k, int d, int n, int rx0, int rx1, int ry0, int ry1,
                              const double* __restrict__ X, const double* __restrict__ Yc,
@@ -192,6 +239,60 @@ void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y) {
                    8.0 * ((double)K.core_elems(k) + (double)x.core_elems(k) + (double)total));
     hipLaunchKernelGGL(k_matvec_banded, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n[k], p,
                        K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].d(), x.c[k].d(), y.c[k].d());
+  }
+  TTIGA_HIP(hipGetLastError());
+}
+
+static size_t lowp_bytes(int dtype) { return dtype == TTIGA_BF16 ? 2 : 4; }
+
+void tt_to_lowp(Context& ctx, const TT& src, int dtype, LowpTT& dst) {
+  TTIGA_CHECK(dtype == TTIGA_FP32 || dtype == TTIGA_BF16, TTIGA_E_ARG, "low precision is FP32 or BF16");
+  dst.dtype = dtype;
+  for (int k = 0; k < 3; ++k) dst.n[k] = src.n[k];
+  for (int k = 0; k < 4; ++k) dst.r[k] = src.r[k];
+  for (int k = 0; k < 3; ++k) {
+    const long ne = (long)src.core_elems(k);
+    dst.c[k] = DBuf(ctx.alloc, lowp_bytes(dtype) * std::max<long>(ne, 1));
+    if (!ne) continue;
+    if (dtype == TTIGA_FP32)
+      hipLaunchKernelGGL(k_to_lowp<float>, dim3(grid_for(ne)), dim3(256), 0, ctx.stream, src.c[k].d(), ne,
+                         dst.c[k].as<float>());
+    else
+      hipLaunchKernelGGL(k_to_lowp<uint16_t>, dim3(grid_for(ne)), dim3(256), 0, ctx.stream, src.c[k].d(),
+                         ne, dst.c[k].as<uint16_t>());
+  }
+  TTIGA_HIP(hipGetLastError());
+}
+
+void tt_matvec_banded_lp(Context& ctx, const LowpTT& K, int p, const TT& x, TT& y) {
+  const int band = 2 * p + 1;
+  if (x.zero() || K.r[1] == 0) { y.set_zero(x.n); return; }
+  int n[3], r[4];
+  for (int k = 0; k < 3; ++k) {
+    n[k] = x.n[k];
+    TTIGA_CHECK(K.n[k] == n[k] * band, TTIGA_E_ARG, "matvec: operator and vector sizes differ");
+  }
+  for (int k = 0; k < 4; ++k) r[k] = K.r[k] * x.r[k];
+  y.alloc(ctx, n, r);
+  const size_t kb = lowp_bytes(K.dtype);
+  for (int k = 0; k < 3; ++k) {
+    const long total = (long)y.core_elems(k);
+    const long nx = (long)x.core_elems(k);
+    const double band_nnz = (double)n[k] * band - (double)p * (p + 1);
+    ProfScope prof(ctx, K.dtype == TTIGA_BF16 ? "tt_matvec_bf16" : "tt_matvec_fp32",
+                   2.0 * band_nnz * K.r[k] * K.r[k + 1] * x.r[k] * x.r[k + 1],
+                   (double)kb * K.r[k] * K.r[k + 1] * n[k] * band + 12.0 * nx + 8.0 * (double)total);
+    DBuf x32(ctx.alloc, sizeof(float) * nx);
+    hipLaunchKernelGGL(k_to_lowp<float>, dim3(grid_for(nx)), dim3(256), 0, ctx.stream, x.c[k].d(), nx,
+                       x32.as<float>());
+    if (K.dtype == TTIGA_FP32)
+      hipLaunchKernelGGL(k_matvec_banded_lp<float>, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n[k], p,
+                         K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].as<float>(), x32.as<float>(),
+                         y.c[k].d());
+    else
+      hipLaunchKernelGGL(k_matvec_banded_lp<uint16_t>, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n[k],
+                         p, K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].as<uint16_t>(), x32.as<float>(),
+                         y.c[k].d());
   }
   TTIGA_HIP(hipGetLastError());
 }

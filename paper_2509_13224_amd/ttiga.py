@@ -33,7 +33,7 @@ EXPORTED = (
     "ttiga_validate", "ttiga_problem_create", "ttiga_problem_destroy", "ttiga_assemble", "ttiga_solve",
     "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
     "ttiga_sample_factors", "ttiga_tt_matvec", "ttiga_tt_round", "ttiga_tt_dot",
-    "ttiga_tt_compress", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free", "ttiga_profile",
+    "ttiga_tt_compress", "ttiga_tt_matvec_lowp", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free", "ttiga_profile",
     "ttiga_profile_read", "ttiga_tt_view_of", "ttiga_footprint", "ttiga_solve_batch",
     "ttiga_server_create", "ttiga_server_submit", "ttiga_server_poll", "ttiga_server_solution",
     "ttiga_server_copy_solution", "ttiga_server_release", "ttiga_server_destroy",
@@ -79,7 +79,8 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("rel_pres", ctypes.c_double), ("rank_u", ctypes.c_int * 4), ("max_rank_seen", ctypes.c_int),
                 ("precond_terms", ctypes.c_int), ("precond_err", ctypes.c_double),
-                ("precond_setup_ms", ctypes.c_double), ("time_ms", ctypes.c_double)]
+                ("precond_setup_ms", ctypes.c_double), ("time_ms", ctypes.c_double),
+                ("refine_steps", ctypes.c_int)]
 
 
 class TTView(ctypes.Structure):
@@ -114,6 +115,7 @@ def _result_dict(r):
     return dict(status=r.status, lane=r.lane, rank_u=list(r.rank_u), n=list(r.n),
                 iterations=r.solve.iterations, rel_res=r.solve.rel_res, rel_pres=r.solve.rel_pres,
                 max_rank_seen=r.solve.max_rank_seen, rank_K=list(r.assembly.rank_K),
+                refine_steps=r.solve.refine_steps,
                 queue_ms=r.queue_ms, run_ms=r.run_ms, latency_ms=r.latency_ms,
                 footprint_bytes=r.footprint_bytes, peak_bytes=r.peak_bytes, error=r.error.decode())
 
@@ -158,6 +160,8 @@ def load(path=LIB_PATH):
         "ttiga_sample_factors": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t, c_dbl_p, c_dbl_p]),
         "ttiga_tt_matvec": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView),
                                            ctypes.POINTER(vp)]),
+        "ttiga_tt_matvec_lowp": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView), ctypes.c_int,
+                                                ctypes.POINTER(vp)]),
         "ttiga_tt_round": (ctypes.c_int, [vp, ctypes.POINTER(TTView), ctypes.c_double, ctypes.POINTER(vp)]),
         "ttiga_tt_dot": (ctypes.c_int, [vp, ctypes.POINTER(TTView), ctypes.POINTER(TTView), c_dbl_p]),
         "ttiga_tt_compress": (ctypes.c_int, [vp, vp, c_int_p, ctypes.c_double, ctypes.POINTER(vp)]),
@@ -308,8 +312,10 @@ class Context:
             return None
         return split_cores(flat, n, r)
 
-    def tt_matvec(self, K_cores_dev, p, x_cores_dev):
-        """y = K x; K banded cores [r][n][2p+1][r'] and x cores [r][n][r'] as device tensors."""
+    def tt_matvec(self, K_cores_dev, p, x_cores_dev, dtype=None):
+        """y = K x; K banded cores [r][n][2p+1][r'] and x cores [r][n][r'] as device tensors.
+
+        dtype TTIGA_FP32 / TTIGA_BF16 (1 / 2) selects the low-precision product."""
         kv = TTMView()
         kv.p = p
         rK = [1, K_cores_dev[0].shape[-1], K_cores_dev[1].shape[-1], 1]
@@ -320,7 +326,11 @@ class Context:
             kv.r[k] = rK[k]
         xv = self._view(x_cores_dev)
         h = ctypes.c_void_p()
-        _check(self.lib, self.lib.ttiga_tt_matvec(self.h, ctypes.byref(kv), ctypes.byref(xv), ctypes.byref(h)))
+        if dtype:
+            _check(self.lib, self.lib.ttiga_tt_matvec_lowp(self.h, ctypes.byref(kv), ctypes.byref(xv), int(dtype),
+                                                           ctypes.byref(h)))
+        else:
+            _check(self.lib, self.lib.ttiga_tt_matvec(self.h, ctypes.byref(kv), ctypes.byref(xv), ctypes.byref(h)))
         return self._take(h)
 
     def tt_round(self, cores_dev, eps):
@@ -509,7 +519,8 @@ class ProblemHandle:
         code = _check(self.lib, self.lib.ttiga_solve(self.h, ctypes.byref(st)), ok)
         return dict(status=code, iterations=st.iterations, rel_res=st.rel_res, rel_pres=st.rel_pres,
                     rank_u=list(st.rank_u), max_rank_seen=st.max_rank_seen, precond_terms=st.precond_terms,
-                    precond_err=st.precond_err, precond_setup_ms=st.precond_setup_ms, time_ms=st.time_ms)
+                    precond_err=st.precond_err, precond_setup_ms=st.precond_setup_ms, time_ms=st.time_ms,
+                    refine_steps=st.refine_steps)
 
     def solution(self):
         r = (ctypes.c_int * 4)()

@@ -119,3 +119,15 @@ def test_footprint_estimate_orders_requests():
     pr = W.c2_problem(n=64)
     pr.options.sample_chunk_bytes = 64 << 20
     assert ttiga.footprint(pr) < f64
+
+
+def test_validate_mixed_precision_rules():
+    """FP32/BF16 refine around the preconditioned solver: accepted with precond=1 only."""
+    from workloads.problem import PREC_BF16, PREC_FP32
+    for prec in (PREC_FP32, PREC_BF16):
+        pr = W.c2_problem(n=64, precision=prec)
+        assert ttiga.validate(pr, precond=1)[0] == ttiga.TTIGA_OK
+        code, msg = ttiga.validate(pr, precond=0)
+        assert code == ttiga.TTIGA_E_ARG and "precond" in msg
+    for pr in W.c4_requests(4):  # the batched family is FP32 by default
+        assert ttiga.validate(pr, precond=1)[0] == ttiga.TTIGA_OK
