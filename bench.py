@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of TT-IGA solves on one MI355X.
 
-One step is the whole hot path for one problem: TT assembly (basis tables,
-geometry factors on the Gauss grid, TT compression, TT cores of K and F,
-summation with rounding, boundary reduction), the preconditioned TT-CG solve,
-and the copy of the solution cores to the host.  The workload is the
-plain-vs-mixed annulus case: quarter annulus (radii 1..2, 90 degrees) extruded
-over z in [0, 1], degree-3 B-splines with 256 basis functions per direction
-(16.7M DOF), f from 8 seeded Fourier modes, TT tolerance 1e-6, FP64.
+One solve is the whole hot path for one problem: TT assembly (basis tables, geometry
+factors on the Gauss grid streamed through the TT-SVD, TT cores of K and F, summation
+with rounding, boundary reduction), the preconditioned TT-CG solve, and the solution
+cores resident on the device.  The workload is the plain-vs-mixed annulus case:
+quarter annulus (radii 1..2, 90 degrees) extruded over z in [0, 1], degree-3 B-splines
+with 256 basis functions per direction (16.7M DOF), f from 8 seeded Fourier modes, TT
+tolerance 1e-6.
 
-Problem descriptions (control net, knots, source parameters; a few KB) are
-uploaded before the timed region.  After timing, every timed solution is
-compared with an FP64 reference solve at eps/10 and tol/10 in the coefficient
-2-norm (computed exactly in TT); a solve counts only if it is within 1e-6.
+One timed step is a batch of --batch such problems (Fourier seeds seed0 + b) run on
+--lanes concurrent lanes of the library's executor (FP64 path); `value` is solves per
+second over the timed steps, counting only solves within 1e-6 (relative, coefficient
+2-norm) of an FP64 reference solve of the same problem at eps/10, tol/10.  Problem
+descriptions (a few KB each) are host inputs; everything else happens on the device.
 
-The JSON line carries the roofline of the kernel class with the most GPU time
-in the timed region (HIP events around every launch of that class, on the
-library's stream) and, on request, the oracle's CPU rate on a bounded sample.
+Beside it the JSON line reports: the single-solve latency of the plain FP64 path with
+the roofline of its dominant kernel class (HIP events around every launch of that
+class, on the library's stream) and the TT-matvec rate; the mixed-precision (FP32
+operator, FP64 refinement) batch; the batched family (mixed sizes and geometries,
+FP32) with its throughput; Poisson-arrival serving of the same family with p50/p99
+latency; and, on request, the oracle's CPU rate on a bounded sample.
 """
 import argparse
 import json
@@ -35,6 +39,8 @@ PEAKS = {  # MI355X published peaks
 KERNEL_BOUND = {
     "gemm_f64": "mfma",
     "tt_matvec_banded": "hbm",
+    "tt_matvec_fp32": "hbm",
+    "tt_matvec_bf16": "hbm",
     "tt_axpby": "hbm",
     "precond_scaling": "hbm",
     "geometry_factors": "alu",
@@ -43,6 +49,7 @@ KERNEL_BOUND = {
     "jacobi_svd": "alu",
     "assemble_cores": "alu",
 }
+SERVE_SEED = 2025_0913_05
 
 
 def roofline_entry(name, st):
@@ -60,13 +67,31 @@ def roofline_entry(name, st):
             "algorithmic_per_launch": (st["bytes"] if bound == "hbm" else st["flops"]) / max(st["launches"], 1)}
 
 
-def tt_rel_diff(ctx, a, b):
-    """||a - b|| / ||b|| for host TT cores, via device inner products."""
-    import torch
-    da = [torch.from_numpy(c.copy()).cuda() for c in a]
-    db = [torch.from_numpy(c.copy()).cuda() for c in b]
-    aa, ab, bb = ctx.tt_dot(da, da), ctx.tt_dot(da, db), ctx.tt_dot(db, db)
-    return (max(aa - 2 * ab + bb, 0.0) ** 0.5) / (bb ** 0.5)
+def tt_rel_diff(a, b):
+    """||a - b|| / ||b|| for host TT cores: the difference train left-orthogonalised by QR,
+    its norm read from the last core (no cancellation between <a,a>, <a,b>, <b,b>)."""
+    import numpy as np
+
+    def orth_norm(cores):
+        cores = [c.copy() for c in cores]
+        for k in range(len(cores) - 1):
+            r0, n, r1 = cores[k].shape
+            q, r = np.linalg.qr(cores[k].reshape(r0 * n, r1))
+            cores[k + 1] = np.tensordot(r, cores[k + 1], axes=([1], [0]))
+        return float(np.linalg.norm(cores[-1]))
+
+    d = []
+    for k, (A, B) in enumerate(zip(a, b)):
+        if k == 0:
+            d.append(np.concatenate([A, -B], axis=2))
+        elif k == len(a) - 1:
+            d.append(np.concatenate([A, B], axis=0))
+        else:
+            C = np.zeros((A.shape[0] + B.shape[0], A.shape[1], A.shape[2] + B.shape[2]))
+            C[:A.shape[0], :, :A.shape[2]] = A
+            C[A.shape[0]:, :, A.shape[2]:] = B
+            d.append(C)
+    return orth_norm(d) / orth_norm(b)
 
 
 def cpu_baseline(n, slabs):
@@ -75,13 +100,14 @@ def cpu_baseline(n, slabs):
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
         threadpool_limits = None
+    import contextlib
+
     import workloads as W
     from oracle import geometry
     pr = W.c2_problem(n=n)
     grid = geometry.gauss_grid(pr)
     Q0 = len(grid[0][0])
     sub = [(grid[0][0][:slabs], grid[0][1][:slabs]), grid[1], grid[2]]
-    import contextlib
     limit = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
     with limit:
         t0 = time.perf_counter()
@@ -97,69 +123,139 @@ def cpu_baseline(n, slabs):
             "seconds_sampled": dt}
 
 
+def log(*a):
+    """Progress on stderr (the JSON result line is the only stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def serve(ctx, reqs, rate, lanes, seed):
+    """Poisson arrivals at `rate` requests/s into a server; returns latencies and throughput."""
+    import threading
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=len(reqs))
+    srv = ctx.server(lanes=lanes)
+    tickets = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def producer():
+        t = t0
+        for i, pr in enumerate(reqs):
+            t += gaps[i]
+            delay = t - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = srv.submit(pr)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    results = [srv.poll(t, wait_ms=-1) for t in tickets]
+    t1 = time.perf_counter()
+    sols = [srv.solution(t) if r["status"] in (0, -7) else None for t, r in zip(tickets, results)]
+    for t in tickets:
+        srv.release(t)
+    srv.close()
+    return results, sols, t1 - t0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3, help="timed batches")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="basis functions per direction")
+    ap.add_argument("--batch", type=int, default=8, help="problems per step")
+    ap.add_argument("--lanes", type=int, default=8, help="concurrent executor lanes")
+    ap.add_argument("--family", type=int, default=64, help="requests of the batched family (0: skip)")
+    ap.add_argument("--serve", type=int, default=48, help="requests per serving rate (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=8)
-    ap.add_argument("--workspace-gib", type=float, default=120.0)
+    ap.add_argument("--workspace-gib", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the TT-IGA solve here is a "
               "single-device hot path; see DESIGN.md for how it would shard", file=sys.stderr)
         sys.exit(2)
+    # one hardware queue per lane (HIP's default is 4), set before the runtime starts
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.lanes))))
 
     import torch
 
     import workloads as W
     from paper_2509_13224_amd import ttiga
+    from workloads.problem import PREC_FP32, PREC_FP64
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = ttiga.Context(device=0, workspace_bytes=int(args.workspace_gib * 2**30))
-    pr = W.c2_problem(n=args.n)
+    base = W.c2_problem(n=args.n)
+    eps, tol = base.options.tt_eps, base.options.rel_res_tol
+    seeds = [W.configs.C2_SEED + b for b in range(args.batch)]
+    plain = [W.c2_problem(n=args.n, seed=s) for s in seeds]
+    mixed = [W.c2_problem(n=args.n, seed=s, precision=PREC_FP32) for s in seeds]
+    refs_pr = [W.c2_problem(n=args.n, seed=s, eps=eps / 10, tol=tol / 10) for s in seeds]
 
-    def one(h):
-        h.assemble()
-        st = h.solve()
-        return st, h.solution()
-
-    for _ in range(args.warmup):
-        h = ctx.problem_create(pr, precond=1)
-        one(h)
-        h.close()
-    handles = [ctx.problem_create(pr, precond=1) for _ in range(args.steps)]
+    # 1. plain FP64 single solve: latency, roofline of the dominant kernel class
+    log("single FP64 solve")
+    h = ctx.problem_create(base, precond=1)
+    h.assemble()
+    h.solve()
+    h.close()
     torch.cuda.synchronize()
     ctx.profile(-1)
     ctx.profile(1)
-    t0 = time.perf_counter()
-    results = [one(h) for h in handles]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    lat = []
+    for _ in range(2):
+        h = ctx.problem_create(base, precond=1)
+        t0 = time.perf_counter()
+        h.assemble()
+        st1 = h.solve()
+        u1 = h.solution()
+        lat.append(time.perf_counter() - t0)
+        h.close()
     ctx.profile(0)
     prof = ctx.profile_read()
-    for h in handles:
-        h.close()
-    elapsed = t1 - t0
-
-    # accuracy gate: FP64 reference at eps/10, tol/10
-    ref_pr = W.c2_problem(n=args.n, eps=pr.options.tt_eps / 10, tol=pr.options.rel_res_tol / 10)
-    href = ctx.problem_create(ref_pr, precond=1)
-    href.assemble()
-    ref_st = href.solve()
-    ref = href.solution()
-    href.close()
-    errs = [tt_rel_diff(ctx, sol, ref) for _, sol in results]
-    passed = [e <= 1e-6 for e in errs]
-
     dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     roof = roofline_entry(dom[0], dom[1])
     mv = prof.get("tt_matvec_banded")
+
+    # 2. headline: batches of C2 problems on the executor lanes (FP64)
+    log("batched FP64 steps")
+    for _ in range(args.warmup):
+        ctx.solve_batch(plain, lanes=args.lanes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [ctx.solve_batch(plain, lanes=args.lanes) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # 3. mixed precision batch (FP32 operator inside FP64 refinement)
+    log("mixed FP32 batch")
+    t0 = time.perf_counter()
+    mixed_out = ctx.solve_batch(mixed, lanes=args.lanes)
+    mixed_s = time.perf_counter() - t0
+
+    # accuracy gate: FP64 references at eps/10, tol/10
+    log("references")
+    refs = [u for _, u in ctx.solve_batch(refs_pr, lanes=args.lanes)]
+    errs = [[tt_rel_diff(u, refs[b]) if u is not None else float("inf") for b, (_, u) in enumerate(run)]
+            for run in runs]
+    passed = sum(e <= 1e-6 for run in errs for e in run)
+    mixed_err = [tt_rel_diff(u, refs[b]) if u is not None else float("inf") for b, (_, u) in enumerate(mixed_out)]
+    single_err = tt_rel_diff(u1, refs[0])
+
     out = {
         "metric": "solves/s at 1e-6 rel-L2 (plain vs batched/mixed); TT-matvec TFLOP/s; p99 lat",
-        "value": sum(passed) / elapsed,
+        "value": passed / elapsed,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -169,21 +265,62 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded Fourier source, exact NURBS annulus)",
-        "config": {"workload": f"quarter annulus r 1..2, 90 deg, z 0..1; degree 3, n={args.n}/dir "
-                               f"({args.n ** 3} DOF); f = 8 seeded Fourier modes; TT eps 1e-6; plain FP64 "
-                               f"with separable preconditioner", "precision": "fp64", "tt_eps": 1e-6,
-                   "rel_err_tol": pr.options.rel_res_tol},
+        "data": "synthetic (seeded Fourier sources, exact NURBS annulus)",
+        "config": {"workload": (f"quarter annulus r 1..2, 90 deg, z 0..1; degree 3, n={args.n}/dir "
+                                f"({args.n ** 3} DOF); f = 8 seeded Fourier modes; TT eps {eps}; FP64 with "
+                                f"separable preconditioner; step = {args.batch} such problems "
+                                f"(seeds {seeds[0]}..{seeds[-1]}) on {args.lanes} executor lanes"),
+                   "precision": "fp64", "tt_eps": eps, "rel_err_tol": tol, "batch": args.batch,
+                   "lanes": args.lanes},
         "roofline": roof,
-        "accuracy": {"rel_l2_vs_ref_max": max(errs), "all_within_1e-6": all(passed),
-                     "reference": "FP64 GPU solve at eps 1e-7, tol 1e-8", "ref_iterations": ref_st["iterations"]},
-        "solve": {k: results[-1][0][k] for k in ("iterations", "rel_res", "rel_pres", "rank_u",
-                                                  "max_rank_seen", "precond_terms")},
+        "accuracy": {"rel_err_vs_ref_max": max(max(r) for r in errs), "passed": passed,
+                     "solves": args.batch * args.steps,
+                     "reference": f"FP64 solve of the same problem at eps {eps / 10:g}, tol {tol / 10:g}"},
+        "plain_single": {"solves_per_s": 1.0 / (sum(lat) / len(lat)), "latency_ms": 1e3 * sum(lat) / len(lat),
+                         "rel_err": single_err, "iterations": st1["iterations"], "rank_u": st1["rank_u"],
+                         "max_rank_seen": st1["max_rank_seen"]},
+        "mixed_fp32": {"solves_per_s": sum(e <= 1e-6 for e in mixed_err) / mixed_s,
+                       "rel_err_vs_ref_max": max(mixed_err),
+                       "refine_steps": [r["refine_steps"] for r, _ in mixed_out],
+                       "note": "FP32 operator store and products inside FP64 iterative refinement"},
         "tt_matvec_tflops": (mv["flops"] / (mv["total_ms"] * 1e-3) / 1e12) if mv else None,
-        "kernels": {k: {"ms_per_step": v["total_ms"] / args.steps, "launches_per_step": v["launches"] / args.steps}
-                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]},
+        "kernels_single_solve": {k: {"ms": v["total_ms"] / 2, "launches": v["launches"] / 2}
+                                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]},
     }
+
+    # 4. batched family (mixed sizes/geometries, FP32 mixed) and 5. serving of it
+    if args.family > 0:
+        log("batched family")
+        fam = W.c4_requests(count=args.family, precision=PREC_FP32)
+        fam_ref_pr = W.c4_requests(count=args.family, precision=PREC_FP64, eps=1e-7, tol=1e-8)
+        t0 = time.perf_counter()
+        fam_out = ctx.solve_batch(fam, lanes=args.lanes)
+        fam_s = time.perf_counter() - t0
+        fam_refs = [u for _, u in ctx.solve_batch(fam_ref_pr, lanes=args.lanes)]
+        fam_err = [tt_rel_diff(u, ur) if (u is not None and ur is not None) else float("inf")
+                   for (_, u), ur in zip(fam_out, fam_refs)]
+        fam_ok = sum(e <= 1e-6 for e in fam_err)
+        sat = fam_ok / fam_s
+        out["batched_family"] = {"requests": args.family, "solves_per_s": sat, "passed": fam_ok,
+                                 "rel_err_max": max(fam_err), "seconds": fam_s,
+                                 "workload": "n in {32,64,128,256}, p in {2,3}, annulus sector or twisted box, "
+                                             "seeded Fourier source, FP32 mixed, seeds 10000+b"}
+        if args.serve > 0:
+            sreqs = fam[:args.serve]
+            lines = []
+            for frac in (0.5, 1.0):
+                log("serving at", frac, "x saturation")
+                res, sols, secs = serve(ctx, sreqs, frac * sat, args.lanes, SERVE_SEED)
+                serr = [tt_rel_diff(u, ur) if (u is not None and ur is not None) else float("inf")
+                        for u, ur in zip(sols, fam_refs[:args.serve])]
+                lat_ms = [r["latency_ms"] for r in res]
+                lines.append({"rate_per_s": frac * sat, "solves_per_s": sum(e <= 1e-6 for e in serr) / secs,
+                              "p50_ms": percentile(lat_ms, 50), "p99_ms": percentile(lat_ms, 99),
+                              "mean_queue_ms": sum(r["queue_ms"] for r in res) / len(res),
+                              "rel_err_max": max(serr)})
+            out["serving"] = {"requests": len(sreqs), "arrival": f"Poisson, seed {SERVE_SEED}", "rates": lines}
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_slabs)
     print(json.dumps(out), flush=True)
 
