@@ -24,7 +24,13 @@ struct SourceDev {
   const double* phi;  // device
   double origin[3];
   double scale;
+  // largest |k| component when every wave vector is integral and at most kMaxIntWave
+  // (the phases e^{i pi k.x} are then products of powers of three unit phasors), else -1
+  int int_kmax;
 };
+
+constexpr int kMaxIntWave = 8;
+constexpr int kMaxRowModes = 64;  // Fourier modes whose phase shifts the row kernel caches
 
 void launch_basis_tables(Context& ctx, int n, int p, int g, const double* knots, double* xi,
                          double* w, double* B, double* D);

@@ -163,6 +163,38 @@ __device__ double source_value(const SourceDev& src, double x, double y, double 
   return 0.0;
 }
 
+// Fourier source with integral wave vectors: with u_d = e^{i pi (x_d - o_d) / scale},
+// e^{i (pi k.x_hat + phi)} = e^{i phi} prod_d u_d^{k_d}, so three sincos and a few complex
+// products replace one sine per mode; the powers come from repeated multiplication (a
+// few ulps for |k_d| <= 8).
+__device__ double fourier_int(const SourceDev& src, double x, double y, double z, const double* cph,
+                              const double* sph) {
+  const double pi = 3.141592653589793;
+  const double xs[3] = {(x - src.origin[0]) / src.scale, (y - src.origin[1]) / src.scale,
+                        (z - src.origin[2]) / src.scale};
+  double ur[3], ui[3];
+  for (int d = 0; d < 3; ++d) sincos(pi * xs[d], &ui[d], &ur[d]);
+  double f = 0.0;
+  for (int m = 0; m < src.n_modes; ++m) {
+    double re = 1.0, im = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const int k = (int)src.k[3 * m + d];
+      const double si = k < 0 ? -ui[d] : ui[d];
+      for (int j = 0; j < (k < 0 ? -k : k); ++j) {
+        const double t = re * ur[d] - im * si;
+        im = re * si + im * ur[d];
+        re = t;
+      }
+    }
+    // sin(theta + phi) = Im(e^{i theta} e^{i phi})
+    f += src.a[m] * (im * cph[m] + re * sph[m]);
+  }
+  return f;
+}
+
+__device__ void factors_from_sums(const double H[4], const double dH[3][4], const SourceDev& src,
+                                  const double* cph, const double* sph, double* out7, double* det_out);
+
 // One sample point: 7 factors and det J.  ga/gb/gc index the per-direction geometry tables.
 __device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, int ib, int ic,
                               double* out7, double* det_out) {
@@ -196,6 +228,15 @@ __device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, i
       }
     }
   }
+  factors_from_sums(H, dH, src, nullptr, nullptr, out7, det_out);
+}
+
+// The 7 factors and det J at one point from the homogeneous sums H (x w, y w, z w, w)
+// and their derivatives dH[i] along xi_i: the quotient rule gives the Jacobian, the
+// adjugate gives J^-1 det J, and R = adj adj^T / det J.  cph/sph, when given, hold
+// cos and sin of the Fourier phase shifts (integral wave vectors only).
+__device__ void factors_from_sums(const double H[4], const double dH[3][4], const SourceDev& src,
+                                  const double* cph, const double* sph, double* out7, double* det_out) {
   const double W = H[3];
   const double x[3] = {H[0] / W, H[1] / W, H[2] / W};
   double J[3][3];
@@ -219,7 +260,8 @@ __device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, i
     const int i = pi_[f], j = pj_[f];
     out7[f] = (A[i][0] * A[j][0] + A[i][1] * A[j][1] + A[i][2] * A[j][2]) / det;
   }
-  out7[6] = source_value(src, x[0], x[1], x[2]) * det;
+  const double f = cph ? fourier_int(src, x[0], x[1], x[2], cph, sph) : source_value(src, x[0], x[1], x[2]);
+  out7[6] = f * det;
   *det_out = det;
 }
 
@@ -256,6 +298,89 @@ __global__ __launch_bounds__(256) void k_factors_grid(GeoDev geo, SourceDev src,
     __syncthreads();
   }
   if (threadIdx.x < 8) part[(long)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Gauss-grid sampling by rows: one block per row (i0, i1) of the slabs b0 .. b0+c1-1 of the
+// second direction, threads over i2.  Sum factorisation: the homogeneous net summed over
+// the first two directions with B0 B1, D0 B1 and B0 D1 (value and the two in-plane
+// derivatives) is formed once per row for every net index of the third direction, so a
+// point only needs p_g2+1 terms per sum.  Output and partial statistics as k_factors_grid.
+__global__ __launch_bounds__(256) void k_factors_rows(GeoDev geo, SourceDev src, int b0, int c1, int Q2,
+                                                      double* __restrict__ F, double* __restrict__ part) {
+  extern __shared__ double T[];  // [3][m2][4]
+  __shared__ double cph[kMaxRowModes], sph[kMaxRowModes];
+  __shared__ double red[8][4];
+  const int row = blockIdx.x;
+  const int i0 = row / c1, i1 = b0 + row % c1;
+  const int p0 = geo.pg[0], p1 = geo.pg[1], p2 = geo.pg[2];
+  const int m1 = geo.m[1], m2 = geo.m[2];
+  const int s0 = geo.span[0][i0], s1 = geo.span[1][i1];
+  const double* B0 = geo.B[0] + (long)i0 * (p0 + 1);
+  const double* D0 = geo.D[0] + (long)i0 * (p0 + 1);
+  const double* B1 = geo.B[1] + (long)i1 * (p1 + 1);
+  const double* D1 = geo.D[1] + (long)i1 * (p1 + 1);
+  for (int e = threadIdx.x; e < 3 * m2 * 4; e += blockDim.x) {
+    const int v = e / (m2 * 4), c = (e / 4) % m2, sc = e % 4;
+    double acc = 0.0;
+    for (int a = 0; a <= p0; ++a) {
+      const double wa = (v == 1) ? D0[a] : B0[a];
+      for (int b = 0; b <= p1; ++b) {
+        const double wb = (v == 2) ? D1[b] : B1[b];
+        acc += wa * wb * geo.Pw[(((long)(s0 - p0 + a) * m1 + (s1 - p1 + b)) * m2 + c) * 4 + sc];
+      }
+    }
+    T[e] = acc;
+  }
+  const bool fast_src = src.kind == TTIGA_SOURCE_FOURIER && src.int_kmax >= 0 && src.n_modes <= kMaxRowModes;
+  if (fast_src)
+    for (int m = threadIdx.x; m < src.n_modes; m += blockDim.x) sincos(src.phi[m], &sph[m], &cph[m]);
+  __syncthreads();
+  const long total = (long)gridDim.x * Q2;
+  const long base = (long)row * Q2;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 1e300};
+  for (int i2 = threadIdx.x; i2 < Q2; i2 += blockDim.x) {
+    const int s2 = geo.span[2][i2];
+    const double* B2 = geo.B[2] + (long)i2 * (p2 + 1);
+    const double* D2 = geo.D[2] + (long)i2 * (p2 + 1);
+    double H[4] = {0, 0, 0, 0}, dH[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    for (int c = 0; c <= p2; ++c) {
+      const int cc = s2 - p2 + c;
+      const double* t0 = T + (0 * m2 + cc) * 4;
+      const double* t1 = T + (1 * m2 + cc) * 4;
+      const double* t2 = T + (2 * m2 + cc) * 4;
+      for (int sc = 0; sc < 4; ++sc) {
+        H[sc] += B2[c] * t0[sc];
+        dH[0][sc] += B2[c] * t1[sc];
+        dH[1][sc] += B2[c] * t2[sc];
+        dH[2][sc] += D2[c] * t0[sc];
+      }
+    }
+    double v[7], det;
+    factors_from_sums(H, dH, src, fast_src ? cph : nullptr, fast_src ? sph : nullptr, v, &det);
+    for (int f = 0; f < 7; ++f) {
+      F[(long)f * total + base + i2] = v[f];
+      acc[f] += v[f] * v[f];
+    }
+    acc[7] = fmin(acc[7], det);
+  }
+  // block reduction: within each 64-lane wave by shuffles, then across the waves
+  for (int f = 0; f < 8; ++f) {
+    double x = acc[f];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double y = __shfl_xor(x, o, 64);
+      x = (f < 7) ? x + y : fmin(x, y);
+    }
+    acc[f] = x;
+  }
+  const int wave = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+  if ((threadIdx.x & 63) == 0)
+    for (int f = 0; f < 8; ++f) red[f][wave] = acc[f];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    double x = red[threadIdx.x][0];
+    for (int w = 1; w < nw; ++w) x = (threadIdx.x < 7) ? x + red[threadIdx.x][w] : fmin(x, red[threadIdx.x][w]);
+    part[(long)blockIdx.x * 8 + threadIdx.x] = x;
+  }
 }
 
 // Reduces the per-block partials; with accumulate the result is merged into out
@@ -412,18 +537,30 @@ void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, 
                          int b0, int c1, double* F, double* stats8, bool accumulate) {
   TTIGA_CHECK(b0 >= 0 && c1 > 0 && b0 + c1 <= Q[1], TTIGA_E_ARG, "factor slab range out of the grid");
   const long total = (long)Q[0] * c1 * Q[2];
-  const long blocks = (total + 255) / 256;
-  DBuf part(ctx.alloc, sizeof(double) * 8 * blocks);
-  // per point: homogeneous map and its three derivatives over the (p_g+1)^3 local net
-  // (inner sums over the last direction first), the adjugate, det J, R and f det J;
-  // bytes: the seven factor values written (tables and net are cache-resident)
-  const double pg0 = geo.pg[0] + 1, pg1 = geo.pg[1] + 1, pg2 = geo.pg[2] + 1;
-  const double per_pt = pg0 * pg1 * (16.0 * pg2 + 35.0) + 150.0 + (double)src.n_modes * 10.0;
+  // per point: the p_g2+1-term sums of the value and three derivatives of the homogeneous
+  // map, the quotient rule, adjugate, det J, R and f det J (per row the sums over the
+  // first two directions are shared); bytes: the seven factor values written
+  const double pg2 = geo.pg[2] + 1;
+  const double src_flops = src.kind == TTIGA_SOURCE_FOURIER ? 20.0 * src.n_modes + 60.0 : 40.0;
+  const double per_pt = 32.0 * pg2 + 150.0 + src_flops;
   ProfScope prof(ctx, "geometry_factors", per_pt * total, 56.0 * total);
-  hipLaunchKernelGGL(k_factors_grid, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, geo, src, Q[0],
-                     b0, c1, Q[2], F, part.d());
-  hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks,
-                     accumulate ? 1 : 0, stats8);
+  const size_t tbytes = sizeof(double) * 3 * geo.m[2] * 4;
+  if (tbytes <= 32768) {
+    const long rows = (long)Q[0] * c1;
+    const int threads = Q[2] >= 192 ? 256 : (Q[2] >= 128 ? 192 : (Q[2] >= 64 ? 128 : 64));
+    DBuf part(ctx.alloc, sizeof(double) * 8 * rows);
+    hipLaunchKernelGGL(k_factors_rows, dim3((unsigned)rows), dim3(threads), tbytes, ctx.stream, geo, src, b0,
+                       c1, Q[2], F, part.d());
+    hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), rows,
+                       accumulate ? 1 : 0, stats8);
+  } else {
+    const long blocks = (total + 255) / 256;
+    DBuf part(ctx.alloc, sizeof(double) * 8 * blocks);
+    hipLaunchKernelGGL(k_factors_grid, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, geo, src, Q[0],
+                       b0, c1, Q[2], F, part.d());
+    hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks,
+                       accumulate ? 1 : 0, stats8);
+  }
   TTIGA_HIP(hipGetLastError());
 }
 

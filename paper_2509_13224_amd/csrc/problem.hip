@@ -22,6 +22,7 @@
 #include <cstring>
 
 #include "iga.hpp"
+
 #include "problem.hpp"
 
 namespace ttiga {
@@ -185,6 +186,16 @@ SourceDev Problem::source_dev() const {
   }
   for (int d = 0; d < 3; ++d) s.origin[d] = src_origin[d];
   s.scale = src_scale;
+  s.int_kmax = -1;
+  if (src_kind == TTIGA_SOURCE_FOURIER) {
+    int km = 0;
+    bool integral = true;
+    for (double v : src_k) {
+      if (!(std::fabs(v) <= kMaxIntWave) || v != std::floor(v)) integral = false;
+      else km = std::max(km, (int)std::fabs(v));
+    }
+    if (integral) s.int_kmax = km;
+  }
   return s;
 }
 
@@ -667,7 +678,7 @@ void Problem::solve_mixed(ttiga_solve_stats& s) {
   const double tol = opts.rel_res_tol;
   const double eps_x = std::min(opts.tt_eps, 0.3 * tol);
   const double floor_in = opts.precision == TTIGA_BF16 ? 3e-2 : 1e-3;
-  const double eps_r = std::max(eps_x, 0.1 * floor_in);
+  const double eps_r = std::max(eps_x, floor_in);
   const double nb = std::sqrt(std::max(tt_dot_sync(c, rhs, rhs), 0.0));
   TT r;
   tt_copy(c, rhs, r);

@@ -174,6 +174,18 @@ __global__ void k_transpose_cols(const double* __restrict__ V, int rows, int ld,
 }
 
 // O[i][:] = s[i] * V[i][:] for a row-major (rows x M) matrix
+// Singular values from Gram eigenvalues (negative rounding noise clamped to 0), and the
+// reciprocals of the leading ones.
+__global__ void k_gram_sigma(const double* __restrict__ lam, int c, double* __restrict__ S) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < c) S[i] = sqrt(fmax(lam[i], 0.0));
+}
+
+__global__ void k_reciprocal(const double* __restrict__ S, int s, double* __restrict__ R) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < s) R[i] = 1.0 / S[i];
+}
+
 __global__ void k_scale_rows(const double* __restrict__ V, int rows, long M, const double* __restrict__ s,
                              double* __restrict__ O) {
   const long total = (long)rows * M;
@@ -371,7 +383,45 @@ struct TruncSVD {
   double norm = 0.0, delta = 0.0;
 };
 
-static TruncSVD truncated_svd(Context& ctx, const double* B, int r, long M, double delta) {
+// Truncated SVD of a wide r x M matrix through its Gram matrix: G = B B^T by one MFMA
+// GEMM, one-sided Jacobi on G (for a symmetric positive semi-definite matrix the SVD is
+// the eigendecomposition, lam = sigma^2, eigenvectors in V), U_s the leading
+// eigenvectors and V_s^T = S_s^-1 U_s^T B.  Squaring resolves singular values down to
+// about sqrt(u) ||B|| and the rows of V_s^T are orthonormal to about u (sigma_1 /
+// sigma_s)^2, so this route is taken only for relative thresholds of 1e-6 and above.
+static TruncSVD truncated_svd_gram(Context& ctx, const double* B, int r, long M, double delta) {
+  TruncSVD o;
+  DBuf G(ctx.alloc, sizeof(double) * r * r);
+  gemm(ctx, false, true, r, r, (int)M, 1.0, B, M, 0, B, M, 0, 0.0, G.d(), r, 0);
+  DBuf E(ctx.alloc, sizeof(double) * r * r), lam(ctx.alloc, sizeof(double) * r), V(ctx.alloc, sizeof(double) * r * r);
+  svd_small(ctx, G.d(), false, r, r, r, E.d(), lam.d(), V.d());
+  o.S = DBuf(ctx.alloc, sizeof(double) * r);
+  hipLaunchKernelGGL(k_gram_sigma, dim3((r + 255) / 256), dim3(256), 0, ctx.stream, lam.d(), r, o.S.d());
+  TTIGA_HIP(hipGetLastError());
+  double nd[2];
+  o.s = trunc_rank_sync(ctx, o.S.d(), r, delta, nd);
+  o.norm = nd[0];
+  o.delta = nd[1];
+  if (o.s == 0) return o;
+  o.U = DBuf(ctx.alloc, sizeof(double) * r * o.s);
+  hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long)r * o.s)), dim3(256), 0, ctx.stream, V.d(), r, r, o.s,
+                     o.U.d());
+  DBuf W(ctx.alloc, sizeof(double) * o.s * M), inv(ctx.alloc, sizeof(double) * o.s);
+  gemm(ctx, true, false, o.s, (int)M, r, 1.0, V.d(), r, 0, B, M, 0, 0.0, W.d(), M, 0);
+  hipLaunchKernelGGL(k_reciprocal, dim3((o.s + 255) / 256), dim3(256), 0, ctx.stream, o.S.d(), o.s, inv.d());
+  o.Vt = DBuf(ctx.alloc, sizeof(double) * o.s * M);
+  hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)o.s * M)), dim3(256), 0, ctx.stream, W.d(), o.s, M,
+                     inv.d(), o.Vt.d());
+  TTIGA_HIP(hipGetLastError());
+  return o;
+}
+
+// relative rounding thresholds at or above which the right-to-left sweep uses the Gram route
+static constexpr double kGramEps = 1e-6;
+
+static TruncSVD truncated_svd(Context& ctx, const double* B, int r, long M, double delta,
+                              bool gram = false) {
+  if (gram && M >= r) return truncated_svd_gram(ctx, B, r, M, delta);
   TruncSVD o;
   if (M >= r) {
     // B^T = Q T (M x r), B = T^T Q^T, svd(T^T) = Ut S W^T, so B = Ut S (Q W)^T
@@ -448,10 +498,11 @@ void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_ran
   // Phase 2: right-to-left truncated SVDs of the r_k x (n_k r_{k+1}) unfoldings; the
   // whole norm sits in the last core, so the first SVD fixes the threshold.
   double delta = delta_abs >= 0.0 ? delta_abs : -eps_rel;
+  const bool gram = delta_abs < 0.0 && eps_rel >= kGramEps;
   for (int k = 2; k >= 1; --k) {
     const int r = x.r[k];
     const long M = (long)x.n[k] * x.r[k + 1];
-    TruncSVD t = truncated_svd(ctx, x.c[k].d(), r, M, delta);
+    TruncSVD t = truncated_svd(ctx, x.c[k].d(), r, M, delta, gram);
     if (k == 2) {
       if (norm_out) norm_out[0] = t.norm;
       delta = t.delta;
