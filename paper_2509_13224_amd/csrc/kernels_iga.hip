@@ -169,11 +169,10 @@ __device__ double source_value(const SourceDev& src, double x, double y, double 
 // few ulps for |k_d| <= 8).
 __device__ double fourier_int(const SourceDev& src, double x, double y, double z, const double* cph,
                               const double* sph) {
-  const double pi = 3.141592653589793;
-  const double xs[3] = {(x - src.origin[0]) / src.scale, (y - src.origin[1]) / src.scale,
-                        (z - src.origin[2]) / src.scale};
+  const double is = 1.0 / src.scale;
+  const double xs[3] = {(x - src.origin[0]) * is, (y - src.origin[1]) * is, (z - src.origin[2]) * is};
   double ur[3], ui[3];
-  for (int d = 0; d < 3; ++d) sincos(pi * xs[d], &ui[d], &ur[d]);
+  for (int d = 0; d < 3; ++d) sincospi(xs[d], &ui[d], &ur[d]);
   double f = 0.0;
   for (int m = 0; m < src.n_modes; ++m) {
     double re = 1.0, im = 0.0;
@@ -237,11 +236,11 @@ __device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, i
 // cos and sin of the Fourier phase shifts (integral wave vectors only).
 __device__ void factors_from_sums(const double H[4], const double dH[3][4], const SourceDev& src,
                                   const double* cph, const double* sph, double* out7, double* det_out) {
-  const double W = H[3];
-  const double x[3] = {H[0] / W, H[1] / W, H[2] / W};
+  const double iW = 1.0 / H[3];
+  const double x[3] = {H[0] * iW, H[1] * iW, H[2] * iW};
   double J[3][3];
   for (int k = 0; k < 3; ++k)
-    for (int i = 0; i < 3; ++i) J[k][i] = (dH[i][k] - x[k] * dH[i][3]) / W;
+    for (int i = 0; i < 3; ++i) J[k][i] = (dH[i][k] - x[k] * dH[i][3]) * iW;
   // adjugate (transpose of the cofactor matrix): J^-1 = adj / det
   double A[3][3];
   A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
@@ -256,9 +255,10 @@ __device__ void factors_from_sums(const double H[4], const double dH[3][4], cons
   const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
   // R = det J^-1 J^-T = adj adj^T / det
   const int pi_[6] = {0, 1, 2, 0, 0, 1}, pj_[6] = {0, 1, 2, 1, 2, 2};
+  const double idet = 1.0 / det;
   for (int f = 0; f < 6; ++f) {
     const int i = pi_[f], j = pj_[f];
-    out7[f] = (A[i][0] * A[j][0] + A[i][1] * A[j][1] + A[i][2] * A[j][2]) / det;
+    out7[f] = (A[i][0] * A[j][0] + A[i][1] * A[j][1] + A[i][2] * A[j][2]) * idet;
   }
   const double f = cph ? fourier_int(src, x[0], x[1], x[2], cph, sph) : source_value(src, x[0], x[1], x[2]);
   out7[6] = f * det;

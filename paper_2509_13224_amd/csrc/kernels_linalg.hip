@@ -336,7 +336,7 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
   }
 }
 
-template <bool kLds>
+template <int kMode>
 __global__ void k_jacobi_svd(int m, int c, const double* __restrict__ A, int transA, long lda,
                              double* __restrict__ gwork, double* __restrict__ U, double* __restrict__ S,
                              double* __restrict__ V, int max_sweeps);
@@ -366,7 +366,10 @@ static int lds_doubles() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
           hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
-          hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd<true>),
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd<2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
+              hipSuccess &&
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd<1>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
               hipSuccess;
       if (!ok) {
@@ -509,16 +512,19 @@ bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* R
 
 // ------------------------------------------------------------- Jacobi SVD
 
-// One workgroup.  Ucol [c][m] and Vcol [c][c] are column-major work arrays, in LDS
-// when gwork is null (dynamic shared memory of (m + c) c doubles), else in gwork.
-template <bool kLds>
+// One workgroup.  Ucol [c][m] and Vcol [c][c] are column-major work arrays.  kMode 2:
+// both in LDS (dynamic shared memory of (m + c) c doubles); 1: Ucol in LDS (m c doubles),
+// Vcol in gwork (the dot products of a round read only Ucol, so the critical path stays in
+// LDS); 0: both in gwork.  With V null the right vectors are not accumulated.
+template <int kMode>
 __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double* __restrict__ A,
                                                      int transA, long lda, double* __restrict__ gwork,
                                                      double* __restrict__ U, double* __restrict__ S,
                                                      double* __restrict__ V, int max_sweeps) {
   extern __shared__ double smem[];
-  double* Ucol = kLds ? smem : gwork;
-  double* Vcol = Ucol + (long)m * c;
+  double* Ucol = kMode >= 1 ? smem : gwork;
+  double* Vcol = kMode == 2 ? smem + (long)m * c : (kMode == 1 ? gwork : gwork + (long)m * c);
+  const bool want_v = V != nullptr;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = nt >> 6;
   __shared__ int s_rot;
@@ -528,7 +534,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
     const int i = e % m, j = e / m;
     Ucol[e] = transA ? A[(long)j * lda + i] : A[(long)i * lda + j];
   }
-  for (long e = tid; e < (long)c * c; e += nt) Vcol[e] = ((e / c) == (e % c)) ? 1.0 : 0.0;
+  if (want_v)
+    for (long e = tid; e < (long)c * c; e += nt) Vcol[e] = ((e / c) == (e % c)) ? 1.0 : 0.0;
   __shared__ double s_f2[16];
   {
     double f = 0.0;
@@ -583,12 +590,14 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
           up[i] = cs * x - sn * y;
           uq[i] = sn * x + cs * y;
         }
-        double* vp = Vcol + (long)p * c;
-        double* vq = Vcol + (long)q * c;
-        for (int i = gl; i < c; i += G) {
-          const double x = vp[i], y = vq[i];
-          vp[i] = cs * x - sn * y;
-          vq[i] = sn * x + cs * y;
+        if (want_v) {
+          double* vp = Vcol + (long)p * c;
+          double* vq = Vcol + (long)q * c;
+          for (int i = gl; i < c; i += G) {
+            const double x = vp[i], y = vq[i];
+            vp[i] = cs * x - sn * y;
+            vq[i] = sn * x + cs * y;
+          }
         }
         if (gl == 0) s_rot = 1;
       }
@@ -605,16 +614,16 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
     if (lane == 0) s_sig[j] = sqrt(s);
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int j = 0; j < c; ++j) s_perm[j] = j;
-    for (int j = 0; j < c; ++j) {  // selection sort, descending; ties keep index order
-      int best = j;
-      for (int k = j + 1; k < c; ++k)
-        if (s_sig[s_perm[k]] > s_sig[s_perm[best]]) best = k;
-      const int tmp = s_perm[j];
-      s_perm[j] = s_perm[best];
-      s_perm[best] = tmp;
+  // descending order by ranking (ties keep index order): column j goes to the slot
+  // counting the columns before it in that order
+  for (int j = tid; j < c; j += nt) {
+    const double sj = s_sig[j];
+    int rank = 0;
+    for (int k = 0; k < c; ++k) {
+      const double sk = s_sig[k];
+      rank += (sk > sj || (sk == sj && k < j)) ? 1 : 0;
     }
+    s_perm[rank] = j;
   }
   __syncthreads();
   for (int j = tid; j < c; j += nt) S[j] = s_sig[s_perm[j]];
@@ -624,32 +633,40 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
     const double sg = s_sig[j];
     U[e] = (sg > 0.0) ? Ucol[(long)j * m + i] / sg : 0.0;
   }
-  for (long e = tid; e < (long)c * c; e += nt) {
-    const int i = e / c, jj = e % c;
-    V[e] = Vcol[(long)s_perm[jj] * c + i];
-  }
+  if (want_v)
+    for (long e = tid; e < (long)c * c; e += nt) {
+      const int i = e / c, jj = e % c;
+      V[e] = Vcol[(long)s_perm[jj] * c + i];
+    }
 }
 
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V) {
   TTIGA_CHECK(c > 0 && m >= c && c <= 1024, TTIGA_E_ARG, "svd_small needs 0 < c <= m, c <= 1024");
-  const long need = (long)(m + c) * c;
-  const bool lds = need <= lds_doubles();
+  const long uc = (long)m * c, vc = V ? (long)c * c : 0;
+  const long cap = lds_doubles();
+  const int mode = (uc + vc <= cap) ? 2 : (uc <= cap ? 1 : 0);
   DBuf work;
-  if (!lds) work = DBuf(ctx.alloc, sizeof(double) * need);
+  const long gneed = mode == 2 ? 0 : (mode == 1 ? vc : uc + vc);
+  if (gneed > 0) work = DBuf(ctx.alloc, sizeof(double) * gneed);
   // enough lane groups for all column pairs of a round, up to 16 waves
   const int G = (m <= 32) ? 8 : ((m <= 128) ? 16 : 64);
   const int pairs = (c + 1) / 2;
   const int threads = 64 * std::min(16, std::max(1, (pairs * G + 63) / 64));
-  // counted at a nominal 8 sweeps of c(c-1)/2 pair rotations: 3 dots, U and V updates
-  ProfScope prof(ctx, "jacobi_svd", 8.0 * 0.5 * c * (c - 1.0) * (12.0 * m + 6.0 * c),
-                 8.0 * (2.0 * m * c + 2.0 * c * c + c), c);
-  if (lds)
-    hipLaunchKernelGGL(k_jacobi_svd<true>, dim3(1), dim3(threads), sizeof(double) * need, ctx.stream, m, c,
-                       A, transA ? 1 : 0, lda, nullptr, U, s, V, 40);
+  // counted at a nominal 8 sweeps of c(c-1)/2 pair rotations: 3 dots, U (and V) updates
+  const double per_rot = 12.0 * m + (V ? 6.0 * c : 0.0);
+  ProfScope prof(ctx, "jacobi_svd", 8.0 * 0.5 * c * (c - 1.0) * per_rot,
+                 8.0 * (2.0 * m * c + (V ? 2.0 * c * c : 0.0) + c), c);
+  const size_t lds_bytes = sizeof(double) * (mode == 2 ? uc + vc : (mode == 1 ? uc : 0));
+  if (mode == 2)
+    hipLaunchKernelGGL(k_jacobi_svd<2>, dim3(1), dim3(threads), lds_bytes, ctx.stream, m, c, A,
+                       transA ? 1 : 0, lda, nullptr, U, s, V, 40);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_jacobi_svd<1>, dim3(1), dim3(threads), lds_bytes, ctx.stream, m, c, A,
+                       transA ? 1 : 0, lda, work.d(), U, s, V, 40);
   else
-    hipLaunchKernelGGL(k_jacobi_svd<false>, dim3(1), dim3(threads), 0, ctx.stream, m, c, A, transA ? 1 : 0,
-                       lda, work.d(), U, s, V, 40);
+    hipLaunchKernelGGL(k_jacobi_svd<0>, dim3(1), dim3(threads), 0, ctx.stream, m, c, A, transA ? 1 : 0, lda,
+                       work.d(), U, s, V, 40);
   TTIGA_HIP(hipGetLastError());
 }
 

@@ -221,7 +221,8 @@ void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, con
 // Q (m x c, row-major, orthonormal columns) and R (c x c, upper) with op(A) = Q R (Householder TSQR).
 void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
              double* R);
-// One-sided Jacobi SVD of op(A) (m x c, m >= c): U (m x c), s (c, descending), V (c x c).
+// One-sided Jacobi SVD of op(A) (m x c, m >= c): U (m x c), s (c, descending), V (c x c);
+// V may be null when the right vectors are not needed.
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V);
 // Upper Cholesky factor R (R^T R = G) and R^-1 of an SPD c x c matrix; false if G is not SPD.

@@ -385,16 +385,18 @@ struct TruncSVD {
 
 // Truncated SVD of a wide r x M matrix through its Gram matrix: G = B B^T by one MFMA
 // GEMM, one-sided Jacobi on G (for a symmetric positive semi-definite matrix the SVD is
-// the eigendecomposition, lam = sigma^2, eigenvectors in V), U_s the leading
-// eigenvectors and V_s^T = S_s^-1 U_s^T B.  Squaring resolves singular values down to
+// the eigendecomposition, lam = sigma^2, eigenvectors = its left vectors V), U_s the
+// leading eigenvectors and V_s^T = S_s^-1 U_s^T B.  Squaring resolves singular values down to
 // about sqrt(u) ||B|| and the rows of V_s^T are orthonormal to about u (sigma_1 /
 // sigma_s)^2, so this route is taken only for relative thresholds of 1e-6 and above.
 static TruncSVD truncated_svd_gram(Context& ctx, const double* B, int r, long M, double delta) {
   TruncSVD o;
   DBuf G(ctx.alloc, sizeof(double) * r * r);
   gemm(ctx, false, true, r, r, (int)M, 1.0, B, M, 0, B, M, 0, 0.0, G.d(), r, 0);
-  DBuf E(ctx.alloc, sizeof(double) * r * r), lam(ctx.alloc, sizeof(double) * r), V(ctx.alloc, sizeof(double) * r * r);
-  svd_small(ctx, G.d(), false, r, r, r, E.d(), lam.d(), V.d());
+  // one-sided Jacobi on G: G W = E diag(lam) with orthonormal columns E; for a symmetric
+  // positive semi-definite G these are its eigenvectors, so W is not accumulated
+  DBuf V(ctx.alloc, sizeof(double) * r * r), lam(ctx.alloc, sizeof(double) * r);
+  svd_small(ctx, G.d(), false, r, r, r, V.d(), lam.d(), nullptr);
   o.S = DBuf(ctx.alloc, sizeof(double) * r);
   hipLaunchKernelGGL(k_gram_sigma, dim3((r + 255) / 256), dim3(256), 0, ctx.stream, lam.d(), r, o.S.d());
   TTIGA_HIP(hipGetLastError());
