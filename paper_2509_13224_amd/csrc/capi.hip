@@ -150,6 +150,7 @@ void DeviceAllocator::release(void* p) {
 }
 
 Context::~Context() {
+  release_blas(blas);
   if (host_scratch) (void)hipHostFree(host_scratch);
 }
 

@@ -10,9 +10,15 @@
 //  * svd_small: one-sided (Hestenes) Jacobi in a single workgroup, round-robin
 //    pair ordering so every wave rotates a disjoint column pair each round.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "runtime.hpp"
@@ -112,25 +118,17 @@ __global__ void k_splitk_reduce(int M, int N, int splits, int batches, double al
   }
 }
 
-void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
-          long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
-          long sC, int batch) {
-  if (M <= 0 || N <= 0 || batch <= 0) return;
-  if (K <= 0) {
-    // C = beta * C
-    if (beta == 0.0) {
-      for (int b = 0; b < batch; ++b)
-        TTIGA_HIP(hipMemset2DAsync(C + b * sC, ldc * sizeof(double), 0, N * sizeof(double), M,
-                                   ctx.stream));
-      return;
-    }
-    throw Error(TTIGA_E_ARG, "gemm with K=0 and beta!=0 unsupported");
-  }
+// The hand-written kernel; split_scale multiplies the number of K splits chosen for
+// grids of fewer than 256 tiles.
+static void gemm_hand(Context& ctx, int split_scale, bool ta, bool tb, int M, int N, int K, double alpha,
+                      const double* A, long lda, long sA, const double* B, long ldb, long sB, double beta,
+                      double* C, long ldc, long sC, int batch) {
   const int tm = (M + GT - 1) / GT, tn = (N + GT - 1) / GT;
   const long tiles = (long)tm * tn * batch;
   int splits = 1;
   if (tiles < 256 && K > 256) {
     splits = (int)std::min<long>((K + 255) / 256, std::max<long>(1, 512 / tiles));
+    splits = (int)std::min<long>((long)splits * split_scale, (K + GK - 1) / GK);
   }
   int kchunk = (K + splits - 1) / splits;
   kchunk = (kchunk + GK - 1) / GK * GK;
@@ -157,6 +155,136 @@ void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, con
                        batch, alpha, part.d(), beta, C, ldc, sC);
     TTIGA_HIP(hipGetLastError());
   }
+}
+
+// rocBLAS handle of a context, created on first use, bound to the context's stream, with
+// atomics disabled so that reductions keep a fixed order.
+static rocblas_handle blas_handle(Context& ctx) {
+  if (!ctx.blas) {
+    rocblas_handle h = nullptr;
+    TTIGA_CHECK(rocblas_create_handle(&h) == rocblas_status_success, TTIGA_E_HIP, "rocblas_create_handle failed");
+    rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
+    ctx.blas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(ctx.blas);
+  TTIGA_CHECK(rocblas_set_stream(h, ctx.stream) == rocblas_status_success, TTIGA_E_HIP, "rocblas_set_stream failed");
+  return h;
+}
+
+void release_blas(void* handle) {
+  if (handle) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
+}
+
+// rocBLAS dgemm on the row-major operands: a row-major X is the column-major X^T, so
+// C^T = op(B)^T op(A)^T is one column-major product with the operands swapped.
+static void gemm_blas(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+                      long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+                      long sC, int batch) {
+  rocblas_handle h = blas_handle(ctx);
+  ProfScope prof(ctx, "gemm_f64_blas", 2.0 * M * N * (double)K * batch,
+                 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N));
+  const rocblas_operation opB = tb ? rocblas_operation_transpose : rocblas_operation_none;
+  const rocblas_operation opA = ta ? rocblas_operation_transpose : rocblas_operation_none;
+  rocblas_status st;
+  if (batch == 1)
+    st = rocblas_dgemm(h, opB, opA, N, M, K, &alpha, B, (int)ldb, A, (int)lda, &beta, C, (int)ldc);
+  else
+    st = rocblas_dgemm_strided_batched(h, opB, opA, N, M, K, &alpha, B, (int)ldb, sB, A, (int)lda, sA, &beta, C,
+                                       (int)ldc, sC, batch);
+  TTIGA_CHECK(st == rocblas_status_success, TTIGA_E_HIP, std::string("rocblas_dgemm: ") + rocblas_status_to_string(st));
+}
+
+// Autotuner: GEMM shapes fall into buckets (transposes, ceil log2 of M, N, K, batched);
+// the first call of a bucket with beta = 0 times every implementation on its own operands
+// (one untimed and one timed run each, HIP events on the context stream) and the fastest
+// serves the bucket from then on (and recomputes this call's result if it did not run
+// last).  The table is process-wide and filled under a lock, so every problem, alone or
+// among others, uses the same implementation for the same shape.  TTIGA_GEMM=hand or
+// =blas pins the choice.
+namespace {
+enum GemmImpl { kGemmHand = 0, kGemmHandDeep = 1, kGemmBlas = 2, kGemmImpls = 3 };
+struct GemmTuner {
+  std::mutex mu;
+  std::map<std::array<int, 6>, int> choice;
+};
+GemmTuner& gemm_tuner() {
+  static GemmTuner t;
+  return t;
+}
+int ceil_log2(long v) {
+  int b = 0;
+  while ((1L << b) < v) ++b;
+  return b;
+}
+int pinned_impl() {
+  static const int v = [] {
+    const char* e = std::getenv("TTIGA_GEMM");
+    if (e && std::strcmp(e, "hand") == 0) return (int)kGemmHand;
+    if (e && std::strcmp(e, "blas") == 0) return (int)kGemmBlas;
+    return -1;
+  }();
+  return v;
+}
+}  // namespace
+
+void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+          long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+          long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0) {
+    // C = beta * C
+    if (beta == 0.0) {
+      for (int b = 0; b < batch; ++b)
+        TTIGA_HIP(hipMemset2DAsync(C + b * sC, ldc * sizeof(double), 0, N * sizeof(double), M,
+                                   ctx.stream));
+      return;
+    }
+    throw Error(TTIGA_E_ARG, "gemm with K=0 and beta!=0 unsupported");
+  }
+  auto run = [&](int impl) {
+    if (impl == kGemmBlas)
+      gemm_blas(ctx, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+    else
+      gemm_hand(ctx, impl == kGemmHandDeep ? 4 : 1, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc,
+                sC, batch);
+  };
+  if (pinned_impl() >= 0) return run(pinned_impl());
+  const std::array<int, 6> key = {(ta ? 1 : 0) + (tb ? 2 : 0), ceil_log2(M), ceil_log2(N), ceil_log2(K),
+                                  batch > 1 ? 1 : 0, 0};
+  GemmTuner& T = gemm_tuner();
+  std::unique_lock<std::mutex> lk(T.mu);
+  auto it = T.choice.find(key);
+  if (it != T.choice.end()) {
+    const int impl = it->second;
+    lk.unlock();
+    return run(impl);
+  }
+  if (beta != 0.0) {
+    lk.unlock();
+    return run(kGemmHand);
+  }
+  hipEvent_t e0, e1;
+  TTIGA_HIP(hipEventCreate(&e0));
+  TTIGA_HIP(hipEventCreate(&e1));
+  float best_ms = 0.f;
+  int best = kGemmHand;
+  for (int impl = 0; impl < kGemmImpls; ++impl) {
+    run(impl);
+    TTIGA_HIP(hipEventRecord(e0, ctx.stream));
+    run(impl);
+    TTIGA_HIP(hipEventRecord(e1, ctx.stream));
+    TTIGA_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TTIGA_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (impl == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = impl;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best != kGemmImpls - 1) run(best);
+  T.choice[key] = best;
 }
 
 // ------------------------------------------------------- Householder TSQR

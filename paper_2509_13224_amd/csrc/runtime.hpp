@@ -162,6 +162,8 @@ struct Context {
   // declared after the allocator so that cached plans are released before it
   PlanCache own_plans;
   PlanCache* plans = &own_plans;
+  // rocBLAS handle (created on first use by gemm, bound to this context's stream)
+  void* blas = nullptr;
   // pinned host staging for small readbacks (ranks, scalars)
   double* host_scratch = nullptr;
   size_t host_scratch_doubles = 0;
@@ -215,6 +217,9 @@ namespace ttiga {
 // ----------------------------------------------------------------- kernel API
 // Dense linear algebra on the stream (kernels_linalg.hip).
 // C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]; row-major operands.
+void release_blas(void* handle);
+// C = alpha op(A) op(B) + beta C through the GEMM autotuner (hand-written MFMA kernel or
+// rocBLAS, chosen per shape bucket by timing).
 void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
           long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
           long sC, int batch = 1);
