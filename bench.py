@@ -50,6 +50,11 @@ KERNEL_BOUND = {
     "assemble_cores": "alu",
 }
 SERVE_SEED = 2025_0913_05
+# HBM bytes per dispatch of a kernel class measured by rocprofv3 --pmc on `bench.py
+# --single-only` (FETCH_SIZE scaled by the 1 GiB copy calibration, WRITE_SIZE), in KiB;
+# profiles/tsqr_apply_annulus_n256.md has the commands.  Valid only for the kernel code
+# it was taken on.
+MEASURED_TRAFFIC_KIB = {"tsqr_apply": (7493.0, 10829.2)}
 
 
 def roofline_entry(name, st):
@@ -181,6 +186,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=8)
     ap.add_argument("--workspace-gib", type=float, default=200.0)
+    ap.add_argument("--single-only", action="store_true",
+                    help="only the single-solve phase (value = its solve rate): the run whose kernel "
+                         "averages a rocprofv3 trace can be compared with the roofline line")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0,
+                    help="only copy this many GiB device-to-device three times (scale of the HBM "
+                         "byte counters) and exit")
+    ap.add_argument("--traffic-kib", type=str, default="",
+                    help="measured FETCH_SIZE,WRITE_SIZE of the roofline kernel (KiB per dispatch, "
+                         "already scaled by the copy calibration) to report as roofline.traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the TT-IGA solve here is a "
@@ -190,6 +204,16 @@ def main():
     os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.lanes))))
 
     import torch
+
+    if args.calibrate_copy > 0:
+        nbytes = int(args.calibrate_copy * 2**30)
+        x = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": nbytes, "dispatches": 3}), flush=True)
+        return
 
     import workloads as W
     from paper_2509_13224_amd import ttiga
@@ -226,7 +250,25 @@ def main():
     prof = ctx.profile_read()
     dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     roof = roofline_entry(dom[0], dom[1])
+    if args.traffic_kib:
+        fetch_kib, write_kib = (float(v) for v in args.traffic_kib.split(","))
+        roof["traffic"] = 1024.0 * (fetch_kib + write_kib)
+    elif dom[0] in MEASURED_TRAFFIC_KIB:
+        roof["traffic"] = 1024.0 * sum(MEASURED_TRAFFIC_KIB[dom[0]])
     mv = prof.get("tt_matvec_banded")
+
+    if args.single_only:
+        print(json.dumps({
+            "metric": "solves/s at 1e-6 rel-L2 (plain vs batched/mixed); TT-matvec TFLOP/s; p99 lat",
+            "value": 1.0 / (sum(lat) / len(lat)), "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
+            "warmup": 1, "ms_per_step": 1e3 * sum(lat) / len(lat), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded Fourier source, exact NURBS annulus)",
+            "config": {"workload": f"single FP64 solve, annulus degree 3, n={args.n}/dir, TT eps {eps}"},
+            "roofline": roof, "iterations": st1["iterations"], "rank_u": st1["rank_u"],
+            "kernels": {k: {"ms": v["total_ms"] / len(lat), "launches": v["launches"] / len(lat),
+                            "avg_launch_us": 1e3 * v["total_ms"] / max(v["launches"], 1)}
+                        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:10]}}), flush=True)
+        return
 
     # 2. headline: batches of C2 problems on the executor lanes (FP64)
     log("batched FP64 steps")
