@@ -295,11 +295,99 @@ void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, con
 // top-down: each block applies its reflectors to [Q_parent slice; 0].
 // Work arrays are column-major W[j * ldw + i] so a column update is contiguous.
 
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Lane moves within rows of 16 lanes by DPP (a VALU operand modifier, a few cycles) instead
+// of LDS permutes; a double moves as its two 32-bit halves.  Controls (gfx9 encoding):
+// quad_perm [2,3,0,1] 0x4E and [1,0,3,2] 0xB1 (partner lane^2 and lane^1), row_ror:8 0x128
+// (lane^8 within the row), row_mirror 0x140 (i <-> 15-i), row_half_mirror 0x141 (i <-> 7-i).
+template <int kCtrl>
+__device__ inline double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffu), kCtrl, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over aligned groups of G lanes (G = 8 or 16), every lane of a group receiving it:
+// the mirrors pair lane i with its reflection, the quad permutations finish the group.
+template <int G>
+__device__ inline double group_sum(double v) {
+  if (G >= 16) v += dpp_f64<0x140>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0xB1>(v);
   return v;
 }
 
+__device__ inline double wave_sum(double v) {
+  v = group_sum<16>(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+__device__ inline double readlane_f64(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffu), src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sums of eight per-lane partials d[0..7] over the 64 lanes of a wave.  Three exchange
+// steps (lane offsets 32, 16, 8) each send half of the values a lane still carries to
+// its partner and add the half received, so a lane ends with one column, (lane >> 3) & 7;
+// offsets 4, 2, 1 finish that column's sum, and the eight totals are read from lanes 8q.
+// Three LDS permutes and a few DPP moves instead of the forty-eight shuffles of eight
+// separate butterflies.
+__device__ inline void wave_sum8(double d[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+  double e[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double keep = h5 ? d[q + 4] : d[q], send = h5 ? d[q] : d[q + 4];
+    e[q] = keep + __shfl_xor(send, 32, 64);
+  }
+  double f[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double keep = h4 ? e[q + 2] : e[q], send = h4 ? e[q] : e[q + 2];
+    f[q] = keep + __shfl_xor(send, 16, 64);
+  }
+  double g = (h3 ? f[1] : f[0]) + dpp_f64<0x128>(h3 ? f[0] : f[1]);
+  g = group_sum<8>(g);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) d[q] = readlane_f64(g, 8 * q);
+}
+
+
+// col[q][i] -= f[q] * v[i] for q < NQ and the rows i = i0, i0 + 64, ... < nr of one lane:
+// one pass over the rows for all columns of a batch, so the loads of different columns
+// overlap.
+template <int NQ>
+__device__ inline void update_batch(double* const* col, const double* f, const double* v, int i0, int nr) {
+  for (int i = i0; i < nr; i += 64) {
+    const double x = v[i];
+    double y[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) y[q] = col[q][i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) col[q][i] = y[q] - f[q] * x;
+  }
+}
+
+__device__ inline void update_batch_n(int nq, double* const* col, const double* f, const double* v, int i0,
+                                      int nr) {
+  switch (nq) {
+    case 1: update_batch<1>(col, f, v, i0, nr); break;
+    case 2: update_batch<2>(col, f, v, i0, nr); break;
+    case 3: update_batch<3>(col, f, v, i0, nr); break;
+    case 4: update_batch<4>(col, f, v, i0, nr); break;
+    case 5: update_batch<5>(col, f, v, i0, nr); break;
+    case 6: update_batch<6>(col, f, v, i0, nr); break;
+    case 7: update_batch<7>(col, f, v, i0, nr); break;
+    default: update_batch<8>(col, f, v, i0, nr); break;
+  }
+}
 
 // Column k of the block belongs to wave k % nwaves for the whole factorisation,
 // so a reflector needs one barrier: the owner of column j forms v_j and tau_j,
@@ -316,7 +404,8 @@ __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* 
   const int blk = blockIdx.x;
   const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
   const int nr = (int)(r1 - r0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, nwaves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform within the wave
   // the storage is a template choice so LDS accesses compile to ds_* instructions
   double* W = kLds ? smem : gwork + (long)blk * ldw * c;
   for (long e = tid; e < (long)nr * c; e += blockDim.x) {
@@ -351,33 +440,33 @@ __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* 
     const double t = s_tau[j];
     if (t == 0.0) continue;
     // H_j on the owned columns k > j, eight at a time: the partial dot products are
-    // formed first and reduced together so the shuffle latencies overlap
+    // formed first and reduced together.  Columns of a batch past c alias its first column
+    // (read, never written), so the row loop has no per-column branches.
     const int k0 = j + 1 + ((wave - (j + 1) % nwaves + nwaves) % nwaves);
     for (int kb = k0; kb < c; kb += 8 * nwaves) {
+      const int nq = min(8, (c - kb + nwaves - 1) / nwaves);
+      double* col[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) col[q] = W + (long)(kb + (q < nq ? q : 0) * nwaves) * ldw;
       double d[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) d[q] = 0.0;
       for (int i = j + 1 + lane; i < nr; i += 64) {
+        // all eight loads issued before the products, so their latencies overlap
         const double v = wj[i];
+        double x[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int k = kb + q * nwaves;
-          if (k < c) d[q] += v * W[(long)k * ldw + i];
-        }
+        for (int q = 0; q < 8; ++q) x[q] = col[q][i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d[q] += v * x[q];
       }
+      wave_sum8(d);
+      double f[8];
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) d[q] += __shfl_xor(d[q], off, 64);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = kb + q * nwaves;
-        if (k >= c) continue;
-        double* wk = W + (long)k * ldw;
-        const double f = t * (d[q] + wk[j]);
-        if (lane == 0) wk[j] -= f;
-        for (int i = j + 1 + lane; i < nr; i += 64) wk[i] -= f * wj[i];
-      }
+      for (int q = 0; q < 8; ++q) f[q] = t * (d[q] + col[q][j]);
+      if (lane == 0)
+        for (int q = 0; q < nq; ++q) col[q][j] -= f[q];
+      update_batch_n(nq, col, f, wj, j + 1 + lane, nr);
     }
   }
   __syncthreads();
@@ -409,7 +498,8 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
   const int blk = blockIdx.x;
   const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
   const int nr = (int)(r1 - r0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, nwaves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform within the wave
   double* Y = kLds ? smem : gwork + (long)blk * ldw * c;
   const double* Vg = V + r0 * c;
   double* Vs = smem + (long)ldw * c;
@@ -427,6 +517,10 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
   // each wave applies all reflectors to its owned columns, eight columns at a time so the
   // eight dot-product reductions of one reflector overlap
   for (int kb = wave; kb < c; kb += 8 * nwaves) {
+    const int nq = min(8, (c - kb + nwaves - 1) / nwaves);
+    double* col[8];  // columns past c alias the batch's first (read, never written)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) col[q] = Y + (long)(kb + (q < nq ? q : 0) * nwaves) * ldw;
     for (int j = c - 1; j >= 0; --j) {
       const double t = s_tau[j];
       if (t == 0.0) continue;
@@ -436,25 +530,19 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
       for (int q = 0; q < 8; ++q) d[q] = 0.0;
       for (int i = j + 1 + lane; i < nr; i += 64) {
         const double v = vj[i];
+        double x[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int k = kb + q * nwaves;
-          if (k < c) d[q] += v * Y[(long)k * ldw + i];
-        }
+        for (int q = 0; q < 8; ++q) x[q] = col[q][i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d[q] += v * x[q];
       }
+      wave_sum8(d);
+      double f[8];
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) d[q] += __shfl_xor(d[q], off, 64);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = kb + q * nwaves;
-        if (k >= c) continue;
-        double* yk = Y + (long)k * ldw;
-        const double f = t * (d[q] + yk[j]);
-        if (lane == 0) yk[j] -= f;
-        for (int i = j + 1 + lane; i < nr; i += 64) yk[i] -= f * vj[i];
-      }
+      for (int q = 0; q < 8; ++q) f[q] = t * (d[q] + col[q][j]);
+      if (lane == 0)
+        for (int q = 0; q < nq; ++q) col[q][j] -= f[q];
+      update_batch_n(nq, col, f, vj, j + 1 + lane, nr);
     }
   }
   __syncthreads();
@@ -697,16 +785,27 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
         double* up = Ucol + (long)p * m;
         double* uq = Ucol + (long)q * m;
         double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll 4
         for (int i = gl; i < m; i += G) {
           const double x = up[i], y = uq[i];
           al += x * x;
           be += y * y;
           ga += x * y;
         }
-        for (int off = G >> 1; off > 0; off >>= 1) {
-          al += __shfl_xor(al, off, 64);
-          be += __shfl_xor(be, off, 64);
-          ga += __shfl_xor(ga, off, 64);
+        if (G == 8) {
+          al = group_sum<8>(al);
+          be = group_sum<8>(be);
+          ga = group_sum<8>(ga);
+        } else {
+          al = group_sum<16>(al);
+          be = group_sum<16>(be);
+          ga = group_sum<16>(ga);
+          if (G == 64)
+            for (int off = 16; off < 64; off <<= 1) {
+              al += __shfl_xor(al, off, 64);
+              be += __shfl_xor(be, off, 64);
+              ga += __shfl_xor(ga, off, 64);
+            }
         }
         const double pq = sqrt(al) * sqrt(be);
         if (ga == 0.0 || !(fabs(ga) > tol * pq) || pq <= floor2) continue;
