@@ -131,7 +131,15 @@ typedef struct {
                          second-direction slabs of at most 2 GiB); > 0: always stream in
                          chunks of at most this many bytes (at least one slab) when the
                          first direction has more than 64 Gauss points */
+  int compression;    /* TTIGA_COMPRESS_AUTO (0): grids above 64 points per direction are
+                         compressed by cross approximation of the first unfolding (sampled
+                         column fibers, pivoted interpolation slices), verified on random
+                         grid points, with TT-SVD as the fallback; TTIGA_COMPRESS_SVD (1):
+                         TT-SVD of the whole (or streamed) Gauss-grid samples only */
 } ttiga_options;
+
+#define TTIGA_COMPRESS_AUTO 0
+#define TTIGA_COMPRESS_SVD 1
 
 typedef struct {
   int status;
@@ -142,6 +150,9 @@ typedef struct {
   double min_detJ;
   double max_R_norm;  /* max_ij ||R_ij||_F over the Gauss grid */
   double time_ms[4];  /* basis+geometry, compression, core assembly+rounding, boundary */
+  int compression_path; /* 0 TT-SVD of the whole grid, 1 streamed TT-SVD, 2 cross approximation,
+                           3 cross rejected by its probe check, then streamed TT-SVD */
+  long long samples;  /* factor sample points evaluated (det J-only points not counted) */
 } ttiga_assembly_stats;
 
 typedef struct {

@@ -38,8 +38,14 @@ void launch_geo_tables(Context& ctx, int count, const double* xi, int stride, in
                        const double* knots, int* span, double* B, double* D);
 // Samples the slabs b0 .. b0+c1-1 of the second direction into F[7][Q0][c1][Q2]; stats8
 // receives (or, with accumulate, is merged with) the 7 sums of squares and min det J.
+// rows0 (device, nrows0 entries) restricts the first direction to the listed indices
+// (F[7][nrows0][c1][Q2]); det_only gathers min det J alone and stores nothing.
 void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, const int* Q,
-                         int b0, int c1, double* F, double* stats8, bool accumulate = false);
+                         int b0, int c1, double* F, double* stats8, bool accumulate = false,
+                         const int* rows0 = nullptr, int nrows0 = 0, bool det_only = false);
+// Grid points (i0[q], i1[q], i2[q]) (device index arrays): out[7][count], det (optional).
+void launch_factors_at(Context& ctx, const GeoDev& geo, const SourceDev& src, long count, const int* i0,
+                       const int* i1, const int* i2, double* out, double* det);
 void launch_factors_points(Context& ctx, const GeoDev& geo, const SourceDev& src, long count,
                            double* out, double* det);
 void launch_assemble_band(Context& ctx, int n, int p, int g, int ra, int rb, const double* G,

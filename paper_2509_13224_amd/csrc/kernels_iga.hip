@@ -194,6 +194,16 @@ __device__ double fourier_int(const SourceDev& src, double x, double y, double z
 __device__ void factors_from_sums(const double H[4], const double dH[3][4], const SourceDev& src,
                                   const double* cph, const double* sph, double* out7, double* det_out);
 
+// det J alone from the homogeneous sums (the quotient rule for J, then the 3 x 3 determinant).
+__device__ double jacobian_det(const double H[4], const double dH[3][4]) {
+  const double iW = 1.0 / H[3];
+  double J[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i) J[k][i] = (dH[i][k] - H[k] * iW * dH[i][3]) * iW;
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
 // One sample point: 7 factors and det J.  ga/gb/gc index the per-direction geometry tables.
 __device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, int ib, int ic,
                               double* out7, double* det_out) {
@@ -305,13 +315,17 @@ __global__ __launch_bounds__(256) void k_factors_grid(GeoDev geo, SourceDev src,
 // the first two directions with B0 B1, D0 B1 and B0 D1 (value and the two in-plane
 // derivatives) is formed once per row for every net index of the third direction, so a
 // point only needs p_g2+1 terms per sum.  Output and partial statistics as k_factors_grid.
+//
+// rows0 (optional) lists the first-direction indices to sample (block row r samples
+// i0 = rows0[r / c1]); det_only computes det J alone (minimum into part, nothing stored).
 __global__ __launch_bounds__(256) void k_factors_rows(GeoDev geo, SourceDev src, int b0, int c1, int Q2,
+                                                      const int* __restrict__ rows0, int det_only,
                                                       double* __restrict__ F, double* __restrict__ part) {
   extern __shared__ double T[];  // [3][m2][4]
   __shared__ double cph[kMaxRowModes], sph[kMaxRowModes];
   __shared__ double red[8][4];
   const int row = blockIdx.x;
-  const int i0 = row / c1, i1 = b0 + row % c1;
+  const int i0 = rows0 ? rows0[row / c1] : row / c1, i1 = b0 + row % c1;
   const int p0 = geo.pg[0], p1 = geo.pg[1], p2 = geo.pg[2];
   const int m1 = geo.m[1], m2 = geo.m[2];
   const int s0 = geo.span[0][i0], s1 = geo.span[1][i1];
@@ -354,6 +368,10 @@ __global__ __launch_bounds__(256) void k_factors_rows(GeoDev geo, SourceDev src,
         dH[1][sc] += B2[c] * t2[sc];
         dH[2][sc] += D2[c] * t0[sc];
       }
+    }
+    if (det_only) {
+      acc[7] = fmin(acc[7], jacobian_det(H, dH));
+      continue;
     }
     double v[7], det;
     factors_from_sums(H, dH, src, fast_src ? cph : nullptr, fast_src ? sph : nullptr, v, &det);
@@ -411,6 +429,18 @@ __global__ void k_factors_reduce(const double* __restrict__ part, long blocks, i
 }
 
 // Scattered points: the geometry tables are indexed by the point itself in all directions.
+// Grid points given by their three indices: out[f][q] and det_out[q] (optional).
+__global__ void k_factors_at(GeoDev geo, SourceDev src, long count, const int* __restrict__ i0,
+                             const int* __restrict__ i1, const int* __restrict__ i2, double* __restrict__ out,
+                             double* __restrict__ det_out) {
+  const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  double v[7], det;
+  point_factors(geo, src, i0[q], i1[q], i2[q], v, &det);
+  for (int f = 0; f < 7; ++f) out[(long)f * count + q] = v[f];
+  if (det_out) det_out[q] = det;
+}
+
 __global__ void k_factors_points(GeoDev geo, SourceDev src, long count, double* __restrict__ out,
                                  double* __restrict__ det_out) {
   const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -534,26 +564,30 @@ void launch_geo_tables(Context& ctx, int count, const double* xi, int stride, in
 }
 
 void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, const int* Q,
-                         int b0, int c1, double* F, double* stats8, bool accumulate) {
+                         int b0, int c1, double* F, double* stats8, bool accumulate, const int* rows0,
+                         int nrows0, bool det_only) {
   TTIGA_CHECK(b0 >= 0 && c1 > 0 && b0 + c1 <= Q[1], TTIGA_E_ARG, "factor slab range out of the grid");
-  const long total = (long)Q[0] * c1 * Q[2];
+  const long n0 = rows0 ? nrows0 : Q[0];
+  const long total = n0 * c1 * Q[2];
   // per point: the p_g2+1-term sums of the value and three derivatives of the homogeneous
   // map, the quotient rule, adjugate, det J, R and f det J (per row the sums over the
   // first two directions are shared); bytes: the seven factor values written
   const double pg2 = geo.pg[2] + 1;
   const double src_flops = src.kind == TTIGA_SOURCE_FOURIER ? 20.0 * src.n_modes + 60.0 : 40.0;
   const double per_pt = 32.0 * pg2 + 150.0 + src_flops;
-  ProfScope prof(ctx, "geometry_factors", per_pt * total, 56.0 * total);
+  ProfScope prof(ctx, det_only ? "geometry_detj" : "geometry_factors",
+                 (det_only ? 32.0 * pg2 + 40.0 : per_pt) * total, det_only ? 0.0 : 56.0 * total);
   const size_t tbytes = sizeof(double) * 3 * geo.m[2] * 4;
   if (tbytes <= 32768) {
-    const long rows = (long)Q[0] * c1;
+    const long rows = n0 * c1;
     const int threads = Q[2] >= 192 ? 256 : (Q[2] >= 128 ? 192 : (Q[2] >= 64 ? 128 : 64));
     DBuf part(ctx.alloc, sizeof(double) * 8 * rows);
     hipLaunchKernelGGL(k_factors_rows, dim3((unsigned)rows), dim3(threads), tbytes, ctx.stream, geo, src, b0,
-                       c1, Q[2], F, part.d());
+                       c1, Q[2], rows0, det_only ? 1 : 0, F, part.d());
     hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), rows,
                        accumulate ? 1 : 0, stats8);
   } else {
+    TTIGA_CHECK(!rows0 && !det_only, TTIGA_E_ARG, "geometry net too large for row sampling");
     const long blocks = (total + 255) / 256;
     DBuf part(ctx.alloc, sizeof(double) * 8 * blocks);
     hipLaunchKernelGGL(k_factors_grid, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, geo, src, Q[0],
@@ -561,6 +595,14 @@ void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, 
     hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks,
                        accumulate ? 1 : 0, stats8);
   }
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_factors_at(Context& ctx, const GeoDev& geo, const SourceDev& src, long count, const int* i0,
+                       const int* i1, const int* i2, double* out, double* det) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_factors_at, dim3(blocks_for(count)), dim3(256), 0, ctx.stream, geo, src, count, i0, i1,
+                     i2, out, det);
   TTIGA_HIP(hipGetLastError());
 }
 

@@ -867,6 +867,77 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
     }
 }
 
+// Interpolation rows of an n x k matrix Q with orthonormal columns: column-pivoted
+// Gram-Schmidt on the rows of Q (QR with column pivoting of Q^T): step l takes the row
+// with the largest residual norm and removes its direction from every row, so the k rows
+// chosen span the column space as well as any greedy choice can (the selection of
+// Q-DEIM).  One workgroup; W (n x k) is a global work copy; norms live in LDS.
+__global__ __launch_bounds__(1024) void k_pivot_rows(int n, int k, const double* __restrict__ Q,
+                                                     double* __restrict__ W, int* __restrict__ rows) {
+  extern __shared__ double nrm[];  // n residual norms (negative once chosen)
+  __shared__ double s_v[256];
+  __shared__ double s_best[32];
+  __shared__ int s_bi[32];
+  __shared__ int s_p;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  for (long e = tid; e < (long)n * k; e += nt) W[e] = Q[e];
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) {
+    double ss = 0.0;
+    for (int j = 0; j < k; ++j) ss += W[(long)i * k + j] * W[(long)i * k + j];
+    nrm[i] = ss;
+  }
+  __syncthreads();
+  for (int l = 0; l < k; ++l) {
+    // pivot: largest residual norm (ties: smallest index)
+    double best = -1.0;
+    int bi = n;
+    for (int i = tid; i < n; i += nt)
+      if (nrm[i] > best) { best = nrm[i]; bi = i; }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { s_best[wave] = best; s_bi[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = s_best[0];
+      int p = s_bi[0];
+      for (int w = 1; w < nw; ++w)
+        if (s_best[w] > b || (s_best[w] == b && s_bi[w] < p)) { b = s_best[w]; p = s_bi[w]; }
+      s_p = p;
+      rows[l] = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    const double np_ = sqrt(fmax(nrm[p], 0.0));
+    for (int j = tid; j < k; j += nt) s_v[j] = np_ > 0.0 ? W[(long)p * k + j] / np_ : 0.0;
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) {
+      if (nrm[i] < 0.0) continue;
+      double cf = 0.0;
+      for (int j = 0; j < k; ++j) cf += W[(long)i * k + j] * s_v[j];
+      double ss = 0.0;
+      for (int j = 0; j < k; ++j) {
+        const double w = W[(long)i * k + j] - cf * s_v[j];
+        W[(long)i * k + j] = w;
+        ss += w * w;
+      }
+      nrm[i] = (i == p) ? -1.0 : ss;
+    }
+    __syncthreads();
+  }
+}
+
+void pivot_rows(Context& ctx, const double* Q, int n, int k, int* rows) {
+  TTIGA_CHECK(n > 0 && k > 0 && k <= 256 && k <= n && n <= 6144, TTIGA_E_ARG, "pivot_rows: bad shape");
+  DBuf W(ctx.alloc, sizeof(double) * (size_t)n * k);
+  ProfScope prof(ctx, "pivot_rows", 4.0 * n * (double)k * k, 16.0 * n * (double)k * k);
+  hipLaunchKernelGGL(k_pivot_rows, dim3(1), dim3(1024), sizeof(double) * n, ctx.stream, n, k, Q, W.d(), rows);
+  TTIGA_HIP(hipGetLastError());
+}
+
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V) {
   TTIGA_CHECK(c > 0 && m >= c && c <= 1024, TTIGA_E_ARG, "svd_small needs 0 < c <= m, c <= 1024");

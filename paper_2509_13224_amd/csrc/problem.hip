@@ -19,6 +19,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "iga.hpp"
@@ -230,6 +232,206 @@ GeoDev Problem::geo_dev(const DBuf* span, const DBuf* B, const DBuf* D) const {
   return gd;
 }
 
+// Host-side index choices of the cross approximation (columns, extra rows, probe points)
+// come from a SplitMix64 stream seeded from the context counter, which restarts at every
+// assembly, so they do not depend on what ran before.
+static uint64_t splitmix(uint64_t& state) {
+  uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Cross approximation of the first unfolding A_(0) (Q0 x Q1 Q2) of the seven factors, the
+// sampled-entries alternative to full-grid TT-SVD (the role TT-cross plays in the paper):
+//  1. L random columns (fibres along the first direction, shared by the factors); per
+//     factor the orthonormal basis U of their span (truncated SVD at 1e-2 eps relative);
+//     a basis within 8 of L means the columns may miss directions: L doubles;
+//  2. interpolation rows: the pivoted rows of each U (column-pivoted QR of U^T), their
+//     union I plus 8 random rows;
+//  3. the slices A[I, :, :] only (|I| of Q0), streamed in second-direction chunks, give
+//     X = U[I, :]^+ A[I, :], so that A_(0) ~= U X (interpolation through the rows I);
+//  4. ||A||_F ~= ||X||_F sets the thresholds; U, X continue as in TT-SVD (truncated SVD
+//     of X, dense factorisation of the rest);
+//  5. 2048 random grid points compare the TTs with directly sampled values: a factor
+//     off by more than 10 eps (its threshold scale, RMS per point) rejects the result
+//     and the caller falls back to TT-SVD.
+bool Problem::compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, ttiga_assembly_stats& s) {
+  Context& c = *ctx;
+  const int n0 = Q[0], n1 = Q[1], n2 = Q[2];
+  const long M = (long)n1 * n2;
+  const double eps = opts.tt_eps;
+  uint64_t rs = c.rng_counter;
+  auto rnd = [&](int hi) { return (int)(splitmix(rs) % (uint64_t)hi); };
+  static const bool trace = [] {
+    const char* e = std::getenv("TTIGA_TRACE_CROSS");
+    return e && e[0] == '1';
+  }();
+  auto reject = [&](const char* why) {
+    if (trace) std::fprintf(stderr, "[cross] rejected: %s\n", why);
+    return false;
+  };
+  const int cap = std::min(n0 / 2, 256);
+  int L = std::min(cap, 48);
+  std::vector<DBuf> U(7);
+  std::vector<int> k(7, 0);
+  while (true) {
+    // 1. column fibres
+    std::vector<int> hi0((size_t)n0 * L), hi1((size_t)n0 * L), hi2((size_t)n0 * L);
+    for (int j = 0; j < L; ++j) {
+      const int a = rnd(n1), b = rnd(n2);
+      for (int i = 0; i < n0; ++i) {
+        hi0[(size_t)i * L + j] = i;
+        hi1[(size_t)i * L + j] = a;
+        hi2[(size_t)i * L + j] = b;
+      }
+    }
+    const long cnt = (long)n0 * L;
+    DBuf idx(c.alloc, sizeof(int) * 3 * cnt), Cf(c.alloc, sizeof(double) * 7 * cnt);
+    int* di = idx.as<int>();
+    TTIGA_HIP(hipMemcpyAsync(di, hi0.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(di + cnt, hi1.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(di + 2 * cnt, hi2.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+    launch_factors_at(c, gd, sd, cnt, di, di + cnt, di + 2 * cnt, Cf.d(), nullptr);
+    s.samples += cnt;
+    c.sync();  // the host index arrays go out of scope
+    // the metric entries share one scale (the largest of their samples), as in the TT-SVD
+    // thresholds: an entry that vanishes analytically is sampled as roundoff and must
+    // come out empty, not as a full-rank basis of noise
+    DBuf csq(c.alloc, sizeof(double) * 7);
+    fill(c, csq.d(), 7, 0.0);
+    for (int t = 0; t < 7; ++t) sumsq_reduce(c, Cf.d() + (size_t)t * cnt, (size_t)cnt, csq.d() + t);
+    double* hc = c.host(7);
+    TTIGA_HIP(hipMemcpyAsync(hc, csq.d(), 7 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    double cmax = 0.0;
+    for (int t = 0; t < 6; ++t) cmax = std::max(cmax, std::sqrt(std::max(hc[t], 0.0)));
+    const double cscale[7] = {cmax, cmax, cmax, cmax, cmax, cmax, std::sqrt(std::max(hc[6], 0.0))};
+    bool saturated = false;
+    for (int t = 0; t < 7; ++t) {
+      k[t] = cscale[t] > 0.0 ? column_basis(c, Cf.d() + (size_t)t * cnt, n0, L, 0.1 * eps * cscale[t], U[t]) : 0;
+      if (k[t] > L - 8) saturated = true;
+    }
+    if (trace)
+      std::fprintf(stderr, "[cross] L %d column ranks %d %d %d %d %d %d %d\n", L, k[0], k[1], k[2], k[3], k[4], k[5],
+                   k[6]);
+    if (!saturated) break;
+    if (L == cap) return reject("column ranks saturate the largest sample");
+    L = std::min(cap, 2 * L);
+  }
+  // 2. interpolation rows
+  std::vector<char> pick(n0, 0);
+  for (int t = 0; t < 7; ++t) {
+    if (k[t] == 0) continue;
+    DBuf rows(c.alloc, sizeof(int) * k[t]);
+    pivot_rows(c, U[t].d(), n0, k[t], rows.as<int>());
+    std::vector<int> hr(k[t]);
+    TTIGA_HIP(hipMemcpyAsync(hr.data(), rows.d(), sizeof(int) * k[t], hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    for (int r : hr) pick[r] = 1;
+  }
+  for (int e = 0; e < 8; ++e) pick[rnd(n0)] = 1;
+  std::vector<int> I;
+  for (int i = 0; i < n0; ++i)
+    if (pick[i]) I.push_back(i);
+  const int nI = (int)I.size();
+  if (trace) std::fprintf(stderr, "[cross] %d interpolation rows of %d\n", nI, n0);
+  if (2 * nI > n0) return reject("interpolation rows cover half the grid");
+  DBuf Id(c.alloc, sizeof(int) * nI);
+  TTIGA_HIP(hipMemcpyAsync(Id.d(), I.data(), sizeof(int) * nI, hipMemcpyHostToDevice, c.stream));
+  // interpolation operators X = P^+ A[I, :] with P = U[I, :] (|I| x k)
+  std::vector<DBuf> Pinv(7), X(7);
+  for (int t = 0; t < 7; ++t) {
+    if (k[t] == 0) continue;
+    const int kt = k[t];
+    DBuf P(c.alloc, sizeof(double) * nI * kt), Up(c.alloc, sizeof(double) * nI * kt),
+        Sp(c.alloc, sizeof(double) * kt), Vp(c.alloc, sizeof(double) * kt * kt);
+    gather_rows(c, U[t].d(), kt, Id.as<int>(), nI, P.d());
+    svd_small(c, P.d(), false, nI, kt, kt, Up.d(), Sp.d(), Vp.d());
+    double* h = c.host(2);
+    TTIGA_HIP(hipMemcpyAsync(h, Sp.d(), sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(h + 1, Sp.d() + (kt - 1), sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    if (!(h[1] > 1e-8 * h[0])) return reject("interpolation rows do not determine the basis");
+    // P^+ = V S^-1 U^T
+    DBuf VS(c.alloc, sizeof(double) * kt * kt);
+    scale_cols_inv(c, Vp.d(), kt, kt, Sp.d(), VS.d());
+    Pinv[t] = DBuf(c.alloc, sizeof(double) * kt * nI);
+    gemm(c, false, true, kt, nI, kt, 1.0, VS.d(), kt, 0, Up.d(), kt, 0, 0.0, Pinv[t].d(), nI, 0);
+    X[t] = DBuf(c.alloc, sizeof(double) * (size_t)kt * M);
+  }
+  // 3. the slices, in second-direction chunks of at most 2 GiB
+  {
+    const size_t slab = sizeof(double) * 7 * (size_t)nI * n2;
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(n1, (size_t(2) << 30) / slab));
+    DBuf buf(c.alloc, slab * chunk), st(c.alloc, sizeof(double) * 8);
+    for (int b = 0; b < n1; b += chunk) {
+      const int cn = std::min(chunk, n1 - b);
+      const long w = (long)cn * n2;
+      launch_factors_grid(c, gd, sd, Q, b, cn, buf.d(), st.d(), false, Id.as<int>(), nI, false);
+      for (int t = 0; t < 7; ++t)
+        if (k[t])
+          gemm(c, false, false, k[t], (int)w, nI, 1.0, Pinv[t].d(), nI, 0, buf.d() + (size_t)t * nI * w, w, 0,
+               0.0, X[t].d() + (size_t)b * n2, M, 0);
+    }
+    s.samples += (long long)nI * M;
+  }
+  // 4. thresholds from ||X|| and the TT-SVD tail
+  DBuf ssq(c.alloc, sizeof(double) * 7);
+  fill(c, ssq.d(), 7, 0.0);
+  for (int t = 0; t < 7; ++t)
+    if (k[t]) sumsq_reduce(c, X[t].d(), (size_t)k[t] * M, ssq.d() + t);
+  double* h = c.host(7);
+  TTIGA_HIP(hipMemcpyAsync(h, ssq.d(), 7 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+  double nrm[7], rmax = 0.0;
+  for (int t = 0; t < 7; ++t) nrm[t] = std::sqrt(std::max(h[t], 0.0));
+  for (int t = 0; t < 6; ++t) rmax = std::max(rmax, nrm[t]);
+  s.max_R_norm = rmax;
+  const double scale[7] = {rmax, rmax, rmax, rmax, rmax, rmax, nrm[6]};
+  for (int t = 0; t < 7; ++t) {
+    if (k[t] == 0 || nrm[t] == 0.0) {
+      fac[t].set_zero(Q);
+      continue;
+    }
+    tt_from_first_unfolding(c, U[t].d(), k[t], X[t].d(), Q, eps * scale[t] / std::sqrt(2.0), 0, fac[t],
+                            opts.max_rank);
+  }
+  // 5. probe check on random grid points
+  const int P = 2048;
+  std::vector<int> p0(P), p1(P), p2(P);
+  for (int q = 0; q < P; ++q) {
+    p0[q] = rnd(n0);
+    p1[q] = rnd(n1);
+    p2[q] = rnd(n2);
+  }
+  DBuf pid(c.alloc, sizeof(int) * 3 * P), ref(c.alloc, sizeof(double) * 7 * P), got(c.alloc, sizeof(double) * 7 * P);
+  int* dp = pid.as<int>();
+  TTIGA_HIP(hipMemcpyAsync(dp, p0.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
+  TTIGA_HIP(hipMemcpyAsync(dp + P, p1.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
+  TTIGA_HIP(hipMemcpyAsync(dp + 2 * P, p2.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
+  launch_factors_at(c, gd, sd, P, dp, dp + P, dp + 2 * P, ref.d(), nullptr);
+  for (int t = 0; t < 7; ++t) tt_eval_points(c, fac[t], P, dp, dp + P, dp + 2 * P, got.d() + (size_t)t * P);
+  std::vector<double> hr((size_t)7 * P), hg((size_t)7 * P);
+  TTIGA_HIP(hipMemcpyAsync(hr.data(), ref.d(), sizeof(double) * 7 * P, hipMemcpyDeviceToHost, c.stream));
+  TTIGA_HIP(hipMemcpyAsync(hg.data(), got.d(), sizeof(double) * 7 * P, hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+  s.samples += P;
+  const double npts = (double)n0 * M;
+  for (int t = 0; t < 7; ++t) {
+    double e2 = 0.0;
+    for (int q = 0; q < P; ++q) {
+      const double d = hg[(size_t)t * P + q] - hr[(size_t)t * P + q];
+      e2 += d * d;
+    }
+    // RMS error per point against the threshold scale spread over the grid
+    const double rms = std::sqrt(e2 / P), allowed = 10.0 * eps * scale[t] / std::sqrt(npts);
+    if (trace) std::fprintf(stderr, "[cross] factor %d probe rms %.3e allowed %.3e\n", t, rms, allowed);
+    if (!(rms <= allowed) && !(scale[t] == 0.0 && e2 == 0.0)) return reject("probe error above 10 eps");
+  }
+  return true;
+}
+
 void Problem::assemble(ttiga_assembly_stats* st) {
   Context& c = *ctx;
   ttiga_assembly_stats s{};
@@ -269,7 +471,27 @@ void Problem::assemble(ttiga_assembly_stats* st) {
     s.time_ms[0] = t1 - t0;
   };
   TT fac[7];
-  if (streamed) {
+  const bool cross = opts.compression == TTIGA_COMPRESS_AUTO && Q[0] > 2 * kExactSvdSize &&
+                     (size_t)Q[1] * Q[2] > (size_t)(2 * kExactSvdSize);
+  bool done = false;
+  if (cross) {
+    // det J on the whole grid (the E_DETJ guarantee), then the cross approximation
+    launch_factors_grid(c, gd, sd, Q, 0, Q[1], nullptr, st8.d(), false, nullptr, 0, true);
+    double* h = c.host(8);
+    TTIGA_HIP(hipMemcpyAsync(h, st8.d(), 8 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    s.min_detJ = min_detJ = h[7];
+    if (!(s.min_detJ > 0.0))
+      throw Error(TTIGA_E_DETJ, "min det J = " + std::to_string(s.min_detJ) + " <= 0 on the Gauss grid");
+    done = compress_cross(gd, sd, fac, s);
+    s.compression_path = done ? 2 : 3;
+    t1 = now_ms();
+    s.time_ms[0] = t1 - t0;
+  }
+  if (done) {
+  } else if (streamed || cross) {
+    if (!cross) s.compression_path = 1;
+    s.samples += 2 * (long long)total;
     const size_t budget = opts.sample_chunk_bytes > 0 ? opts.sample_chunk_bytes : kWholeLimit;
     const int chunk = (int)std::max<size_t>(1, std::min<size_t>(Q[1], budget / slab_bytes));
     auto produce = [&](int b, int cnt, double* buf) {
@@ -277,6 +499,8 @@ void Problem::assemble(ttiga_assembly_stats* st) {
     };
     tt_compress_streamed(c, 7, Q, chunk, produce, thresholds, fac, opts.max_rank);
   } else {
+    s.compression_path = 0;
+    s.samples += (long long)total;
     DBuf Fac(c.alloc, sizeof(double) * 7 * total);
     launch_factors_grid(c, gd, sd, Q, 0, Q[1], Fac.d(), st8.d(), false);
     std::vector<double> delta;

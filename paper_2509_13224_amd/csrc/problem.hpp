@@ -58,6 +58,7 @@ struct Problem {
   size_t footprint_estimate() const;
 
  private:
+  bool compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, ttiga_assembly_stats& s);
   void solve_cg(ttiga_solve_stats& s);
   void solve_pcg(ttiga_solve_stats& s);
   void solve_mixed(ttiga_solve_stats& s);

@@ -230,6 +230,9 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
 // V may be null when the right vectors are not needed.
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V);
+// k interpolation rows of an n x k matrix with orthonormal columns (column-pivoted QR of
+// Q^T), written to the device array rows.
+void pivot_rows(Context& ctx, const double* Q, int n, int k, int* rows);
 // Upper Cholesky factor R (R^T R = G) and R^-1 of an SPD c x c matrix; false if G is not SPD.
 bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* Rinv);
 // Smallest r with ||s[r:]|| <= delta (delta < 0: -delta * ||s|| / sqrt(2) relative).
@@ -269,6 +272,22 @@ using ChunkFn = std::function<void(int a, int c, double* buf)>;
 using ThresholdFn = std::function<void(std::vector<double>& delta)>;
 void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const ChunkFn& produce,
                           const ThresholdFn& thresholds, TT* out, int max_rank);
+// TT of A from an orthonormal basis Qb (n0 x L) of its first unfolding and B (L x n1 n2)
+// with A_(0) ~= Qb B: truncated SVD of B at delta, first core Qb U_s, the rest factored like
+// a dense tensor.  With spare > 0 it returns false (out untouched) when the truncated rank
+// leaves fewer than spare columns of L.
+bool tt_from_first_unfolding(Context& ctx, const double* Qb, int L, const double* B, const int* n, double delta,
+                             int spare, TT& out, int max_rank);
+// Orthonormal basis U (m x k) of the columns of C (m x L, m >= L) from its truncated SVD
+// with tail delta (Frobenius; delta < 0: relative to ||C||); returns k (0: C is below it).
+int column_basis(Context& ctx, const double* C, int m, int L, double delta, DBuf& U);
+// out[i][j] = A[i][j] / S[j] for an m x cols row-major A.
+void scale_cols_inv(Context& ctx, const double* A, int m, int cols, const double* S, double* out);
+// out (nr x k) = rows `rows` (device) of A (n x k), row-major.
+void gather_rows(Context& ctx, const double* A, int k, const int* rows, int nr, double* out);
+// Values of x at grid points (device index arrays, count entries) into out.
+void tt_eval_points(Context& ctx, const TT& x, long count, const int* i0, const int* i1, const int* i2,
+                    double* out);
 // Sizes at or below which TT-SVD unfoldings are factored exactly instead of sketched.
 constexpr int kExactSvdSize = 64;
 

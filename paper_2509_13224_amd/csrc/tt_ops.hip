@@ -678,42 +678,109 @@ void tt_compress_streamed(Context& ctx, int nt, const int* n, int chunk, const C
     bool widen = false;
     for (int t = 0; t < nt; ++t) {
       if (!todo[t]) continue;
-      TruncSVD sv = truncated_svd(ctx, B[t].d(), L, M, delta[t]);
+      const bool fits = tt_from_first_unfolding(ctx, Qy[t].d(), L, B[t].d(), n, delta[t], L < n0 ? 12 : 0,
+                                                out[t], max_rank);
       B[t].reset();
-      if (sv.s == 0) {
-        out[t].set_zero(n);
-        todo[t] = 0;
-        continue;
-      }
-      if (sv.s > L - 12 && L < n0) {
+      if (!fits) {
         widen = true;
         continue;
       }
-      const int s0 = sv.s;
-      DBuf U0(ctx.alloc, sizeof(double) * (size_t)n0 * s0);
-      gemm(ctx, false, false, n0, s0, L, 1.0, Qy[t].d(), L, 0, sv.U.d(), s0, 0, 0.0, U0.d(), s0, 0);
-      DBuf C0(ctx.alloc, sizeof(double) * (size_t)s0 * M);
-      hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)s0 * M)), dim3(256), 0, ctx.stream,
-                         sv.Vt.d(), s0, M, sv.S.d(), C0.d());
-      TTIGA_HIP(hipGetLastError());
-      DBuf U1, C1;
-      const int s1 = left_factor(ctx, C0.d(), s0 * n1, n2, delta[t], U1, C1);
       todo[t] = 0;
-      if (s1 == 0) {
-        out[t].set_zero(n);
-        continue;
-      }
-      if (max_rank > 0 && (s0 > max_rank || s1 > max_rank))
-        throw Error(TTIGA_E_RANKCAP, "compressed factor rank exceeds max_rank");
-      TT& o = out[t];
-      for (int k = 0; k < 3; ++k) o.n[k] = n[k];
-      o.r[0] = 1; o.r[1] = s0; o.r[2] = s1; o.r[3] = 1;
-      o.c[0] = std::move(U0);
-      o.c[1] = std::move(U1);
-      o.c[2] = std::move(C1);
     }
     if (widen) L = std::min(n0, 2 * L);
   }
+}
+
+bool tt_from_first_unfolding(Context& ctx, const double* Qb, int L, const double* B, const int* n, double delta,
+                             int spare, TT& out, int max_rank) {
+  const int n0 = n[0], n1 = n[1], n2 = n[2];
+  const long M = (long)n1 * n2;
+  TruncSVD sv = truncated_svd(ctx, B, L, M, delta);
+  if (sv.s == 0) {
+    out.set_zero(n);
+    return true;
+  }
+  if (spare > 0 && sv.s > L - spare) return false;
+  const int s0 = sv.s;
+  DBuf U0(ctx.alloc, sizeof(double) * (size_t)n0 * s0);
+  gemm(ctx, false, false, n0, s0, L, 1.0, Qb, L, 0, sv.U.d(), s0, 0, 0.0, U0.d(), s0, 0);
+  DBuf C0(ctx.alloc, sizeof(double) * (size_t)s0 * M);
+  hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)s0 * M)), dim3(256), 0, ctx.stream, sv.Vt.d(), s0, M,
+                     sv.S.d(), C0.d());
+  TTIGA_HIP(hipGetLastError());
+  DBuf U1, C1;
+  const int s1 = left_factor(ctx, C0.d(), s0 * n1, n2, delta, U1, C1);
+  if (s1 == 0) {
+    out.set_zero(n);
+    return true;
+  }
+  if (max_rank > 0 && (s0 > max_rank || s1 > max_rank))
+    throw Error(TTIGA_E_RANKCAP, "compressed factor rank exceeds max_rank");
+  for (int k = 0; k < 3; ++k) out.n[k] = n[k];
+  out.r[0] = 1; out.r[1] = s0; out.r[2] = s1; out.r[3] = 1;
+  out.c[0] = std::move(U0);
+  out.c[1] = std::move(U1);
+  out.c[2] = std::move(C1);
+  return true;
+}
+
+int column_basis(Context& ctx, const double* C, int m, int L, double delta, DBuf& U) {
+  TTIGA_CHECK(m >= L && L > 0, TTIGA_E_ARG, "column_basis needs m >= L > 0");
+  TruncSVD t = truncated_svd(ctx, C, m, L, delta);
+  if (t.s == 0) return 0;
+  U = std::move(t.U);
+  return t.s;
+}
+
+__global__ void k_gather_rows(const double* __restrict__ A, int k, const int* __restrict__ rows, int nr,
+                              double* __restrict__ out) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)nr * k) return;
+  out[e] = A[(long)rows[e / k] * k + e % k];
+}
+
+void scale_cols_inv(Context& ctx, const double* A, int m, int cols, const double* S, double* out) {
+  DBuf inv(ctx.alloc, sizeof(double) * cols);
+  hipLaunchKernelGGL(k_reciprocal, dim3((cols + 255) / 256), dim3(256), 0, ctx.stream, S, cols, inv.d());
+  hipLaunchKernelGGL(k_scale_cols, dim3(grid_for((long)m * cols)), dim3(256), 0, ctx.stream, A, m, cols, inv.d(),
+                     cols, out);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void gather_rows(Context& ctx, const double* A, int k, const int* rows, int nr, double* out) {
+  if ((long)nr * k <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3(grid_for((long)nr * k)), dim3(256), 0, ctx.stream, A, k, rows, nr, out);
+  TTIGA_HIP(hipGetLastError());
+}
+
+// Values of a TT at grid points (i0[q], i1[q], i2[q]): one thread per point contracts
+// G0[i0, :] G1[:, i1, :] G2[:, i2].
+__global__ void k_tt_eval(int r1, int r2, int n1, int n2, const double* __restrict__ G0,
+                          const double* __restrict__ G1, const double* __restrict__ G2, long count,
+                          const int* __restrict__ i0, const int* __restrict__ i1, const int* __restrict__ i2,
+                          double* __restrict__ out) {
+  const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const double* g0 = G0 + (long)i0[q] * r1;
+  double v = 0.0;
+  for (int b = 0; b < r2; ++b) {
+    double t = 0.0;
+    for (int a = 0; a < r1; ++a) t += g0[a] * G1[((long)a * n1 + i1[q]) * r2 + b];
+    v += t * G2[(long)b * n2 + i2[q]];
+  }
+  out[q] = v;
+}
+
+void tt_eval_points(Context& ctx, const TT& x, long count, const int* i0, const int* i1, const int* i2,
+                    double* out) {
+  if (count <= 0) return;
+  if (x.zero()) {
+    fill(ctx, out, count, 0.0);
+    return;
+  }
+  hipLaunchKernelGGL(k_tt_eval, dim3(grid_for(count)), dim3(256), 0, ctx.stream, x.r[1], x.r[2], x.n[1], x.n[2],
+                     x.c[0].d(), x.c[1].d(), x.c[2].d(), count, i0, i1, i2, out);
+  TTIGA_HIP(hipGetLastError());
 }
 
 // Randomised projection of x onto ranks (l1, l2): Gaussian TT Omega with cores

@@ -65,14 +65,15 @@ class Options(ctypes.Structure):
     _fields_ = [("tt_eps", ctypes.c_double), ("rel_res_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("max_rank", ctypes.c_int),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int),
-                ("sample_chunk_bytes", ctypes.c_size_t)]
+                ("sample_chunk_bytes", ctypes.c_size_t), ("compression", ctypes.c_int)]
 
 
 class AssemblyStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("rank_R", (ctypes.c_int * 4) * 6),
                 ("rank_fJ", ctypes.c_int * 4), ("rank_K", ctypes.c_int * 4),
                 ("rank_F", ctypes.c_int * 4), ("min_detJ", ctypes.c_double),
-                ("max_R_norm", ctypes.c_double), ("time_ms", ctypes.c_double * 4)]
+                ("max_R_norm", ctypes.c_double), ("time_ms", ctypes.c_double * 4),
+                ("compression_path", ctypes.c_int), ("samples", ctypes.c_longlong)]
 
 
 class SolveStats(ctypes.Structure):
@@ -396,6 +397,7 @@ def describe(pr, precond=0):
     o.precision = pr.options.precision
     o.precond = precond
     o.sample_chunk_bytes = int(getattr(pr.options, "sample_chunk_bytes", 0))
+    o.compression = int(getattr(pr.options, "compression", 0))
     return (g, disc, src, bc, o), keep
 
 
@@ -511,7 +513,7 @@ class ProblemHandle:
         _check(self.lib, self.lib.ttiga_assemble(self.h, ctypes.byref(st)))
         return dict(rank_R=[list(r) for r in st.rank_R], rank_fJ=list(st.rank_fJ), rank_K=list(st.rank_K),
                     rank_F=list(st.rank_F), min_detJ=st.min_detJ, max_R_norm=st.max_R_norm,
-                    time_ms=list(st.time_ms))
+                    time_ms=list(st.time_ms), compression_path=st.compression_path, samples=st.samples)
 
     def solve(self, allow_notconv=False):
         st = SolveStats()

@@ -117,11 +117,11 @@ def test_solve_before_assemble_is_state_error(ctx):
 
 
 def _tt_rel_dist(a, b):
-    """||a - b|| / ||b|| for host TT cores (banded operators: merged (i, t) mode index)."""
+    """||a - b|| / ||b|| for host TT cores (banded operators: merged (i, t) mode index), by
+    the QR-orthogonalised norm of the difference train (cost r^3 n, no cancellation)."""
     a = [c.reshape(c.shape[0], -1, c.shape[-1]) for c in a]
     b = [c.reshape(c.shape[0], -1, c.shape[-1]) for c in b]
-    aa, ab, bb = tt.dot(a, a), tt.dot(a, b), tt.dot(b, b)
-    return math.sqrt(max(aa - 2.0 * ab + bb, 0.0) / bb)
+    return tt.norm(tt.add(a, tt.scale(b, -1.0))) / tt.norm(b)
 
 
 @pytest.mark.parametrize("geo_name", ["bumpy", "twisted"])
@@ -137,8 +137,10 @@ def test_streamed_compression(ctx, geo_name):
     pr = W.small_problem(geo, 24, 3, W.fourier_source(geo, 7), eps=eps)
     Q = 84
     pr.options.sample_chunk_bytes = 7 * Q * Q * 8 * 5
+    pr.options.compression = 1
     h = ctx.problem_create(pr)
-    h.assemble()
+    st = h.assemble()
+    assert st["compression_path"] == 1 and st["samples"] == 2 * Q ** 3
     samples, _ = geometry.sample_factors_grid(pr)
     assert samples.shape == (7, Q, Q, Q)
     rmax = max(np.linalg.norm(samples[f]) for f in range(6))
@@ -175,3 +177,42 @@ def test_grid_factors_match_oracle_samples(ctx, name):
         ref_norm = rmax if f < 6 else max(np.linalg.norm(samples[6]), 1e-300)
         got = np.zeros_like(samples[f]) if cores is None else tt.full(cores)
         assert np.linalg.norm(got - samples[f]) <= 1e-12 * ref_norm, f
+
+
+@pytest.mark.parametrize("geo_name", ["bumpy", "twisted", "annulus"])
+def test_cross_compression(ctx, geo_name):
+    """Cross approximation of the first unfolding (148 Gauss points per direction): every
+    factor TT within 10 eps of the oracle's Gauss-grid samples although only a small part
+    of the grid is sampled, and the same K^TT and F^TT as TT-SVD of the whole grid.  The
+    bumpy cube's factors have column ranks near 50 at this size, so its interpolation rows
+    would cover most of the grid: cross declines and TT-SVD runs (either way the factors
+    must match)."""
+    from paper_2509_13224_amd import ttiga
+    say("cross", geo_name)
+    geo = {"bumpy": W.bumpy_cube(), "twisted": W.twisted_box(1.0),
+           "annulus": W.annulus_sector(1.0, 2.0, math.pi / 2, 1.0)}[geo_name]
+    eps = 1e-8
+    pr = W.small_problem(geo, 40, 3, W.fourier_source(geo, 11), eps=eps)
+    Q = 148
+    h = ctx.problem_create(pr)
+    st = h.assemble()
+    if geo_name == "bumpy":
+        assert st["compression_path"] in (2, 3), st["compression_path"]
+    else:
+        assert st["compression_path"] == 2, st["compression_path"]
+        assert st["samples"] < Q ** 3 / 3
+    say("cross", geo_name, "path", st["compression_path"], "samples", st["samples"], "oracle sampling")
+    samples, _ = geometry.sample_factors_grid(pr)
+    rmax = max(np.linalg.norm(samples[f]) for f in range(6))
+    for f in range(7):
+        cores = h.tt(ttiga.WHICH_FACTOR0 + f)
+        ref_norm = rmax if f < 6 else np.linalg.norm(samples[6])
+        got = np.zeros_like(samples[f]) if cores is None else tt.full(cores)
+        assert np.linalg.norm(got - samples[f]) <= 10 * eps * ref_norm, f
+    say("cross", geo_name, "TT-SVD assembly for comparison")
+    pr.options.compression = 1
+    h2 = ctx.problem_create(pr)
+    h2.assemble()
+    say("cross", geo_name, "compare K, F")
+    assert _tt_rel_dist(h.tt(ttiga.WHICH_K), h2.tt(ttiga.WHICH_K)) <= 20 * eps
+    assert _tt_rel_dist(h.tt(ttiga.WHICH_F), h2.tt(ttiga.WHICH_F)) <= 20 * eps

@@ -92,6 +92,7 @@ class Options:
     precision: int = PREC_FP64
     refine: int = 1
     sample_chunk_bytes: int = 0  # 0: automatic; > 0: stream the Gauss-grid sampling in chunks
+    compression: int = 0  # 0: cross approximation where it pays, verified, TT-SVD fallback; 1: TT-SVD only
 
 
 @dataclass
