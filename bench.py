@@ -200,8 +200,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the TT-IGA solve here is a "
               "single-device hot path; see DESIGN.md for how it would shard", file=sys.stderr)
         sys.exit(2)
-    # one hardware queue per lane (HIP's default is 4), set before the runtime starts
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.lanes))))
+    # one hardware queue per lane plus the context's and torch's streams (HIP's default is 4;
+    # two streams on one queue serialise), set before the runtime starts
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.lanes + 2))))
 
     import torch
 

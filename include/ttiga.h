@@ -340,7 +340,13 @@ int ttiga_footprint(const ttiga_request* req, size_t* bytes);
  * a library-owned TT on the context (free with ttiga_tt_free), or NULL when
  * problem i failed; results[i] holds its status and statistics.  The call
  * itself fails only on bad arguments or when the pool cannot be set up; a
- * problem that fails does not affect the others. */
+ * problem that fails does not affect the others.  Each lane is a host thread
+ * with its own HIP stream; lanes overlap on the device only when the HIP
+ * runtime gives every active stream its own hardware queue
+ * (GPU_MAX_HW_QUEUES >= lanes + the caller's streams, set before the runtime
+ * starts).  Per-discretisation plans (the preconditioner's 1-D eigenbases)
+ * are computed once per context, kept in its workspace, and shared by all
+ * batches and servers built on it. */
 int ttiga_solve_batch(ttiga_ctx* ctx, int count, const ttiga_request* reqs, int lanes,
                       size_t hbm_budget, ttiga_tt** solutions, ttiga_result* results);
 

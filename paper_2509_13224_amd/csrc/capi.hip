@@ -208,7 +208,13 @@ ProfScope::ProfScope(Context& c, const char* name, double flops, double bytes, i
     : c_(&c), name_(name), flops_(flops), bytes_(bytes) {
   if (!c.prof.on) return;
   if (c.prof.detail && size >= 0) {
-    const int b = size <= 16 ? 16 : size <= 32 ? 32 : size <= 64 ? 64 : size <= 128 ? 128 : 1024;
+    static const int edges[] = {16, 32, 48, 64, 96, 128, 160, 192, 256, 384, 512, 1024};
+    int b = 1 << 30;
+    for (int e : edges)
+      if (size <= e) {
+        b = e;
+        break;
+      }
     name_ += "_c" + std::to_string(b);
   }
   a_ = c.prof.get();

@@ -161,8 +161,10 @@ void Engine::run(Job& j, Lane& lane, int index) {
     if (chunk.p) arena.set_workspace(chunk.p, chunk.bytes);
     arena.set_spill_parent(&pool_);
     c.alloc = &arena;
-    c.plan_alloc = &pool_;
-    c.plans = &plans_;
+    // plans live in the root context: computed once, kept across batches and servers
+    c.plan_alloc = root_->plan_alloc;
+    c.plan_stream = root_->stream;
+    c.plans = root_->plans;
     c.prof.on = root_->prof.on;
     c.prof.detail = root_->prof.detail;
     Problem& P = *j.prob;
@@ -206,6 +208,7 @@ void Engine::run(Job& j, Lane& lane, int index) {
     arena.flush_deferred();
     c.alloc = &c.own_alloc;
     c.plan_alloc = &c.own_alloc;
+    c.plan_stream = nullptr;
     c.plans = &c.own_plans;
     if (c.prof.on) {
       try {

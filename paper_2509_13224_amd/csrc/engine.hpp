@@ -53,8 +53,7 @@ class Engine {
 
   Context* root_;
   DBuf region_;           // the pool's memory in the root allocator
-  DeviceAllocator pool_;  // arenas, spills, plans and resident solutions
-  PlanCache plans_;       // destroyed before the pool
+  DeviceAllocator pool_;  // arenas, spills and resident solutions
   std::map<unsigned long long, std::unique_ptr<Job>> jobs_;  // destroyed before the pool
   std::vector<std::unique_ptr<Lane>> lanes_;
   std::vector<std::thread> threads_;

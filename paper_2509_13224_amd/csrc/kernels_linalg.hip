@@ -555,7 +555,7 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
 template <int kMode>
 __global__ void k_jacobi_svd(int m, int c, const double* __restrict__ A, int transA, long lda,
                              double* __restrict__ gwork, double* __restrict__ U, double* __restrict__ S,
-                             double* __restrict__ V, int max_sweeps);
+                             double* __restrict__ V, int max_sweeps, int G);
 
 // static LDS of k_jacobi_svd (pair flags, permutation, singular values) and of the
 // TSQR kernels (reflector scalars), with margin
@@ -736,7 +736,7 @@ template <int kMode>
 __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double* __restrict__ A,
                                                      int transA, long lda, double* __restrict__ gwork,
                                                      double* __restrict__ U, double* __restrict__ S,
-                                                     double* __restrict__ V, int max_sweeps) {
+                                                     double* __restrict__ V, int max_sweeps, int G) {
   extern __shared__ double smem[];
   double* Ucol = kMode >= 1 ? smem : gwork;
   double* Vcol = kMode == 2 ? smem + (long)m * c : (kMode == 1 ? gwork : gwork + (long)m * c);
@@ -763,9 +763,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
   double f2 = 0.0;
   for (int w = 0; w < nwaves; ++w) f2 += s_f2[w];
   const int cp = (c + 1) & ~1;
-  // a column pair is handled by a group of G lanes (G a power of two dividing 64): short
-  // columns use small groups so more pairs of a round run at once
-  const int G = (m <= 32) ? 8 : ((m <= 128) ? 16 : 64);
+  // a column pair is handled by a group of G lanes (8, 16, 32 or 64)
   const int gl = lane % G, grp = wave * (64 / G) + lane / G, ngroups = nwaves * (64 / G);
   // rotate a pair unless it is orthogonal to working accuracy (m u, the rounding level
   // of a length-m dot product), or both columns are below 1e-15 of the Frobenius norm
@@ -800,12 +798,11 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
           al = group_sum<16>(al);
           be = group_sum<16>(be);
           ga = group_sum<16>(ga);
-          if (G == 64)
-            for (int off = 16; off < 64; off <<= 1) {
-              al += __shfl_xor(al, off, 64);
-              be += __shfl_xor(be, off, 64);
-              ga += __shfl_xor(ga, off, 64);
-            }
+          for (int off = 16; off < G; off <<= 1) {
+            al += __shfl_xor(al, off, 64);
+            be += __shfl_xor(be, off, 64);
+            ga += __shfl_xor(ga, off, 64);
+          }
         }
         const double pq = sqrt(al) * sqrt(be);
         if (ga == 0.0 || !(fabs(ga) > tol * pq) || pq <= floor2) continue;
@@ -938,6 +935,30 @@ void pivot_rows(Context& ctx, const double* Q, int n, int k, int* rows) {
   TTIGA_HIP(hipGetLastError());
 }
 
+// Lanes per column pair of a Jacobi round.  A round is ceil(pairs / groups) pair steps
+// in sequence per group, each ceil(m / G) loads per lane plus log2(G) reduction steps (16
+// waves at most), so short columns and many pairs favour small groups.  TTIGA_JACOBI_G
+// (8, 16, 32 or 64) overrides the choice for measurements.
+static int jacobi_group(int m, int pairs) {
+  static const int forced = [] {
+    const char* e = std::getenv("TTIGA_JACOBI_G");
+    const int g = e ? std::atoi(e) : 0;
+    return (g == 8 || g == 16 || g == 32 || g == 64) ? g : 0;
+  }();
+  if (forced) return forced;
+  int best = 8;
+  double best_cost = 1e300;
+  for (int G = 8, lg = 3; G <= 64; G *= 2, ++lg) {
+    const int groups = 16 * (64 / G);
+    const double cost = (double)((pairs + groups - 1) / groups) * ((m + G - 1) / G + 2.0 * lg);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = G;
+    }
+  }
+  return best;
+}
+
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V) {
   TTIGA_CHECK(c > 0 && m >= c && c <= 1024, TTIGA_E_ARG, "svd_small needs 0 < c <= m, c <= 1024");
@@ -947,9 +968,9 @@ void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long ld
   DBuf work;
   const long gneed = mode == 2 ? 0 : (mode == 1 ? vc : uc + vc);
   if (gneed > 0) work = DBuf(ctx.alloc, sizeof(double) * gneed);
-  // enough lane groups for all column pairs of a round, up to 16 waves
-  const int G = (m <= 32) ? 8 : ((m <= 128) ? 16 : 64);
   const int pairs = (c + 1) / 2;
+  const int G = jacobi_group(m, pairs);
+  // enough lane groups for all column pairs of a round, up to 16 waves
   const int threads = 64 * std::min(16, std::max(1, (pairs * G + 63) / 64));
   // counted at a nominal 8 sweeps of c(c-1)/2 pair rotations: 3 dots, U (and V) updates
   const double per_rot = 12.0 * m + (V ? 6.0 * c : 0.0);
@@ -958,13 +979,13 @@ void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long ld
   const size_t lds_bytes = sizeof(double) * (mode == 2 ? uc + vc : (mode == 1 ? uc : 0));
   if (mode == 2)
     hipLaunchKernelGGL(k_jacobi_svd<2>, dim3(1), dim3(threads), lds_bytes, ctx.stream, m, c, A,
-                       transA ? 1 : 0, lda, nullptr, U, s, V, 40);
+                       transA ? 1 : 0, lda, nullptr, U, s, V, 40, G);
   else if (mode == 1)
     hipLaunchKernelGGL(k_jacobi_svd<1>, dim3(1), dim3(threads), lds_bytes, ctx.stream, m, c, A,
-                       transA ? 1 : 0, lda, work.d(), U, s, V, 40);
+                       transA ? 1 : 0, lda, work.d(), U, s, V, 40, G);
   else
     hipLaunchKernelGGL(k_jacobi_svd<0>, dim3(1), dim3(threads), 0, ctx.stream, m, c, A, transA ? 1 : 0, lda,
-                       work.d(), U, s, V, 40);
+                       work.d(), U, s, V, 40, G);
   TTIGA_HIP(hipGetLastError());
 }
 

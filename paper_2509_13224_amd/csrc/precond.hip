@@ -93,11 +93,28 @@ static std::shared_ptr<EigenBasis> eigenbasis(Problem& P, int d) {
   const int p = P.p, band = 2 * p + 1;
   const int n = P.n[d], Q = P.Q[d], m = P.hi[d] - P.lo[d];
   const std::array<int, 5> key = {n, p, P.g, P.lo[d], P.hi[d]};
+  PlanCache& pc = *ctx.plans;
   {
-    std::lock_guard<std::mutex> lk(ctx.plans->mu);
-    auto it = ctx.plans->map.find(key);
-    if (it != ctx.plans->map.end()) return std::static_pointer_cast<EigenBasis>(it->second);
+    std::unique_lock<std::mutex> lk(pc.mu);
+    while (true) {
+      auto it = pc.map.find(key);
+      if (it != pc.map.end()) return std::static_pointer_cast<EigenBasis>(it->second);
+      if (pc.busy.insert(key).second) break;  // this caller computes it
+      pc.cv.wait(lk);
+    }
   }
+  // whatever happens below, the key leaves `busy` and waiters look again
+  struct Done {
+    PlanCache& pc;
+    const std::array<int, 5>& key;
+    ~Done() {
+      {
+        std::lock_guard<std::mutex> lk(pc.mu);
+        pc.busy.erase(key);
+      }
+      pc.cv.notify_all();
+    }
+  } done{pc, key};
   auto e = std::make_shared<EigenBasis>();
   e->ni = m;
   DBuf ones(ctx.alloc, sizeof(double) * Q);
@@ -121,8 +138,17 @@ static std::shared_ptr<EigenBasis> eigenbasis(Problem& P, int d) {
   gemm(ctx, true, false, m, m, m, 1.0, Rmi.d(), m, 0, T1.d(), m, 0, 0.0, S.d(), m, 0);
   DBuf U(ctx.alloc, sizeof(double) * m * m), W(ctx.alloc, sizeof(double) * m * m);
   e->lam = DBuf(ctx.plan_alloc, sizeof(double) * m);
-  svd_small(ctx, S.d(), false, m, m, m, U.d(), e->lam.d(), W.d());
   e->V = DBuf(ctx.plan_alloc, sizeof(double) * m * m);
+  if (ctx.plan_stream && ctx.plan_stream != ctx.stream) {
+    // plan memory may have been released by work still queued on the plan allocator's
+    // stream: this stream writes it only after that work
+    hipEvent_t ev;
+    TTIGA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    TTIGA_HIP(hipEventRecord(ev, ctx.plan_stream));
+    TTIGA_HIP(hipStreamWaitEvent(ctx.stream, ev, 0));
+    TTIGA_HIP(hipEventDestroy(ev));
+  }
+  svd_small(ctx, S.d(), false, m, m, m, U.d(), e->lam.d(), W.d());
   gemm(ctx, false, false, m, m, m, 1.0, Rmi.d(), m, 0, W.d(), m, 0, 0.0, e->V.d(), m, 0);
   double* h = ctx.host(2);
   TTIGA_HIP(hipMemcpyAsync(h, e->lam.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
@@ -130,8 +156,8 @@ static std::shared_ptr<EigenBasis> eigenbasis(Problem& P, int d) {
   ctx.sync();  // the plan is complete before other streams can find it
   e->lam_max = h[0];
   e->lam_min = h[1];
-  std::lock_guard<std::mutex> lk(ctx.plans->mu);
-  auto ins = ctx.plans->map.emplace(key, e);
+  std::lock_guard<std::mutex> lk(pc.mu);
+  auto ins = pc.map.emplace(key, e);
   return std::static_pointer_cast<EigenBasis>(ins.first->second);
 }
 

@@ -5,12 +5,14 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <condition_variable>
 #include <cstddef>
 #include <cstdint>
 #include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -145,9 +147,14 @@ class ProfScope {
 // preconditioner), keyed by (n, p, g, lo, hi).  Shared by the per-job contexts of an
 // executor, so lookups and inserts take the mutex; a plan is inserted only after the
 // stream that computed it has drained.
+// Per-discretisation data (1-D eigenbases of the preconditioner), computed once and shared
+// by every problem of a context and of the executors built on it.  A plan being computed
+// is listed in `busy`; others asking for it wait on `cv` instead of computing it again.
 struct PlanCache {
   std::mutex mu;
+  std::condition_variable cv;
   std::map<std::array<int, 5>, std::shared_ptr<void>> map;
+  std::set<std::array<int, 5>> busy;
 };
 
 struct Context {
@@ -157,8 +164,11 @@ struct Context {
   // device memory: the context's own allocator, or a per-job arena of an executor
   DeviceAllocator own_alloc;
   DeviceAllocator* alloc = &own_alloc;
-  // where plans are allocated: memory that lives as long as the plan cache
+  // where plans are allocated: memory that lives as long as the plan cache; plan_stream is
+  // the stream that releases plan_alloc's memory (null: this context's own stream), which
+  // work on a plan's buffers must follow
   DeviceAllocator* plan_alloc = &own_alloc;
+  hipStream_t plan_stream = nullptr;
   // declared after the allocator so that cached plans are released before it
   PlanCache own_plans;
   PlanCache* plans = &own_plans;

@@ -116,8 +116,9 @@ def _result_dict(r):
     return dict(status=r.status, lane=r.lane, rank_u=list(r.rank_u), n=list(r.n),
                 iterations=r.solve.iterations, rel_res=r.solve.rel_res, rel_pres=r.solve.rel_pres,
                 max_rank_seen=r.solve.max_rank_seen, rank_K=list(r.assembly.rank_K),
-                refine_steps=r.solve.refine_steps,
-                queue_ms=r.queue_ms, run_ms=r.run_ms, latency_ms=r.latency_ms,
+                refine_steps=r.solve.refine_steps, assembly_ms=list(r.assembly.time_ms),
+                compression_path=r.assembly.compression_path, solve_ms=r.solve.time_ms,
+                precond_setup_ms=r.solve.precond_setup_ms, queue_ms=r.queue_ms, run_ms=r.run_ms, latency_ms=r.latency_ms,
                 footprint_bytes=r.footprint_bytes, peak_bytes=r.peak_bytes, error=r.error.decode())
 
 
