@@ -39,10 +39,14 @@ void launch_geo_tables(Context& ctx, int count, const double* xi, int stride, in
 // Samples the slabs b0 .. b0+c1-1 of the second direction into F[7][Q0][c1][Q2]; stats8
 // receives (or, with accumulate, is merged with) the 7 sums of squares and min det J.
 // rows0 (device, nrows0 entries) restricts the first direction to the listed indices
-// (F[7][nrows0][c1][Q2]); det_only gathers min det J alone and stores nothing.
+// (F[7][nrows0][c1][Q2]).
 void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, const int* Q,
                          int b0, int c1, double* F, double* stats8, bool accumulate = false,
-                         const int* rows0 = nullptr, int nrows0 = 0, bool det_only = false);
+                         const int* rows0 = nullptr, int nrows0 = 0);
+// Minimum of det J over the whole Gauss grid into *min_out (device), nothing else; needs
+// detj_rows_fit (the rows of a block in LDS: at most 170 control points in the third direction).
+bool detj_rows_fit(const GeoDev& geo);
+void launch_detj_min(Context& ctx, const GeoDev& geo, const int* Q, double* min_out);
 // Grid points (i0[q], i1[q], i2[q]) (device index arrays): out[7][count], det (optional).
 void launch_factors_at(Context& ctx, const GeoDev& geo, const SourceDev& src, long count, const int* i0,
                        const int* i1, const int* i2, double* out, double* det);

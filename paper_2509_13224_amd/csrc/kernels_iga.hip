@@ -317,9 +317,9 @@ __global__ __launch_bounds__(256) void k_factors_grid(GeoDev geo, SourceDev src,
 // point only needs p_g2+1 terms per sum.  Output and partial statistics as k_factors_grid.
 //
 // rows0 (optional) lists the first-direction indices to sample (block row r samples
-// i0 = rows0[r / c1]); det_only computes det J alone (minimum into part, nothing stored).
+// i0 = rows0[r / c1]).
 __global__ __launch_bounds__(256) void k_factors_rows(GeoDev geo, SourceDev src, int b0, int c1, int Q2,
-                                                      const int* __restrict__ rows0, int det_only,
+                                                      const int* __restrict__ rows0,
                                                       double* __restrict__ F, double* __restrict__ part) {
   extern __shared__ double T[];  // [3][m2][4]
   __shared__ double cph[kMaxRowModes], sph[kMaxRowModes];
@@ -368,10 +368,6 @@ __global__ __launch_bounds__(256) void k_factors_rows(GeoDev geo, SourceDev src,
         dH[1][sc] += B2[c] * t2[sc];
         dH[2][sc] += D2[c] * t0[sc];
       }
-    }
-    if (det_only) {
-      acc[7] = fmin(acc[7], jacobian_det(H, dH));
-      continue;
     }
     double v[7], det;
     factors_from_sums(H, dH, src, fast_src ? cph : nullptr, fast_src ? sph : nullptr, v, &det);
@@ -426,6 +422,88 @@ __global__ void k_factors_reduce(const double* __restrict__ part, long blocks, i
     else if (threadIdx.x < 7) out[threadIdx.x] += v;
     else out[7] = fmin(out[7], v);
   }
+}
+
+// Minimum of det J over the slabs b0 .. b0+c1-1 of the second direction of the Gauss grid
+// (the positivity check of the map; nothing else is computed or stored).  Each wave takes
+// one grid row (i0, i1) at a time, four rows per block and iteration, with the row's sums
+// over the first two directions staged in LDS as in k_factors_rows; blocks stride over the
+// rows with the same trip count, so every wave reaches every barrier.  part[block] receives
+// the block's minimum.
+__global__ __launch_bounds__(256) void k_detj_rows(GeoDev geo, int b0, int c1, int Q2, long rows, int iters,
+                                                   double* __restrict__ part) {
+  extern __shared__ double T[];  // [4 waves][3][m2][4]
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p0 = geo.pg[0], p1 = geo.pg[1], p2 = geo.pg[2];
+  const int m1 = geo.m[1], m2 = geo.m[2];
+  const int tsz = 12 * m2;
+  double* Tw = T + w * tsz;
+  double mn = 1e300;
+  for (int it = 0; it < iters; ++it) {
+    const long row = ((long)it * gridDim.x + blockIdx.x) * 4 + w;
+    const bool live = row < rows;
+    if (live) {
+      const int i0 = (int)(row / c1), i1 = b0 + (int)(row % c1);
+      const int s0 = geo.span[0][i0], s1 = geo.span[1][i1];
+      const double* B0 = geo.B[0] + (long)i0 * (p0 + 1);
+      const double* D0 = geo.D[0] + (long)i0 * (p0 + 1);
+      const double* B1 = geo.B[1] + (long)i1 * (p1 + 1);
+      const double* D1 = geo.D[1] + (long)i1 * (p1 + 1);
+      for (int e = lane; e < tsz; e += 64) {
+        const int v = e / (m2 * 4), c = (e / 4) % m2, sc = e % 4;
+        double acc = 0.0;
+        for (int a = 0; a <= p0; ++a) {
+          const double wa = (v == 1) ? D0[a] : B0[a];
+          for (int b = 0; b <= p1; ++b) {
+            const double wb = (v == 2) ? D1[b] : B1[b];
+            acc += wa * wb * geo.Pw[(((long)(s0 - p0 + a) * m1 + (s1 - p1 + b)) * m2 + c) * 4 + sc];
+          }
+        }
+        Tw[e] = acc;
+      }
+    }
+    __syncthreads();
+    if (live)
+      for (int i2 = lane; i2 < Q2; i2 += 64) {
+        const int s2 = geo.span[2][i2];
+        const double* B2 = geo.B[2] + (long)i2 * (p2 + 1);
+        const double* D2 = geo.D[2] + (long)i2 * (p2 + 1);
+        double H[4] = {0, 0, 0, 0}, dH[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+        for (int c = 0; c <= p2; ++c) {
+          const int cc = s2 - p2 + c;
+          const double* t0 = Tw + (0 * m2 + cc) * 4;
+          const double* t1 = Tw + (1 * m2 + cc) * 4;
+          const double* t2 = Tw + (2 * m2 + cc) * 4;
+          const double b2 = B2[c], d2 = D2[c];
+          for (int sc = 0; sc < 4; ++sc) {
+            H[sc] += b2 * t0[sc];
+            dH[0][sc] += b2 * t1[sc];
+            dH[1][sc] += b2 * t2[sc];
+            dH[2][sc] += d2 * t0[sc];
+          }
+        }
+        mn = fmin(mn, jacobian_det(H, dH));
+      }
+    __syncthreads();
+  }
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+  if (lane == 0) red[w] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
+__global__ void k_min_reduce(const double* __restrict__ part, long count, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double v = 1e300;
+  for (long b = threadIdx.x; b < count; b += blockDim.x) v = fmin(v, part[b]);
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 // Scattered points: the geometry tables are indexed by the point itself in all directions.
@@ -563,9 +641,25 @@ void launch_geo_tables(Context& ctx, int count, const double* xi, int stride, in
   TTIGA_HIP(hipGetLastError());
 }
 
+bool detj_rows_fit(const GeoDev& geo) { return 4 * 12 * (size_t)geo.m[2] * sizeof(double) <= 65536; }
+
+void launch_detj_min(Context& ctx, const GeoDev& geo, const int* Q, double* min_out) {
+  TTIGA_CHECK(detj_rows_fit(geo), TTIGA_E_ARG, "geometry net too large for the det J rows kernel");
+  const long rows = (long)Q[0] * Q[1];
+  const long total = rows * Q[2];
+  ProfScope prof(ctx, "geometry_detj", (32.0 * (geo.pg[2] + 1) + 40.0) * total, 0.0);
+  const int blocks = (int)std::min<long>((rows + 3) / 4, 8192);
+  const int iters = (int)((rows + 4L * blocks - 1) / (4L * blocks));
+  DBuf part(ctx.alloc, sizeof(double) * blocks);
+  hipLaunchKernelGGL(k_detj_rows, dim3(blocks), dim3(256), sizeof(double) * 4 * 12 * geo.m[2], ctx.stream, geo,
+                     0, Q[1], Q[2], rows, iters, part.d());
+  hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), (long)blocks, min_out);
+  TTIGA_HIP(hipGetLastError());
+}
+
 void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, const int* Q,
                          int b0, int c1, double* F, double* stats8, bool accumulate, const int* rows0,
-                         int nrows0, bool det_only) {
+                         int nrows0) {
   TTIGA_CHECK(b0 >= 0 && c1 > 0 && b0 + c1 <= Q[1], TTIGA_E_ARG, "factor slab range out of the grid");
   const long n0 = rows0 ? nrows0 : Q[0];
   const long total = n0 * c1 * Q[2];
@@ -575,19 +669,18 @@ void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, 
   const double pg2 = geo.pg[2] + 1;
   const double src_flops = src.kind == TTIGA_SOURCE_FOURIER ? 20.0 * src.n_modes + 60.0 : 40.0;
   const double per_pt = 32.0 * pg2 + 150.0 + src_flops;
-  ProfScope prof(ctx, det_only ? "geometry_detj" : "geometry_factors",
-                 (det_only ? 32.0 * pg2 + 40.0 : per_pt) * total, det_only ? 0.0 : 56.0 * total);
+  ProfScope prof(ctx, "geometry_factors", per_pt * total, 56.0 * total);
   const size_t tbytes = sizeof(double) * 3 * geo.m[2] * 4;
   if (tbytes <= 32768) {
     const long rows = n0 * c1;
     const int threads = Q[2] >= 192 ? 256 : (Q[2] >= 128 ? 192 : (Q[2] >= 64 ? 128 : 64));
     DBuf part(ctx.alloc, sizeof(double) * 8 * rows);
     hipLaunchKernelGGL(k_factors_rows, dim3((unsigned)rows), dim3(threads), tbytes, ctx.stream, geo, src, b0,
-                       c1, Q[2], rows0, det_only ? 1 : 0, F, part.d());
+                       c1, Q[2], rows0, F, part.d());
     hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), rows,
                        accumulate ? 1 : 0, stats8);
   } else {
-    TTIGA_CHECK(!rows0 && !det_only, TTIGA_E_ARG, "geometry net too large for row sampling");
+    TTIGA_CHECK(!rows0, TTIGA_E_ARG, "geometry net too large for row sampling");
     const long blocks = (total + 255) / 256;
     DBuf part(ctx.alloc, sizeof(double) * 8 * blocks);
     hipLaunchKernelGGL(k_factors_grid, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, geo, src, Q[0],

@@ -935,28 +935,17 @@ void pivot_rows(Context& ctx, const double* Q, int n, int k, int* rows) {
   TTIGA_HIP(hipGetLastError());
 }
 
-// Lanes per column pair of a Jacobi round.  A round is ceil(pairs / groups) pair steps
-// in sequence per group, each ceil(m / G) loads per lane plus log2(G) reduction steps (16
-// waves at most), so short columns and many pairs favour small groups.  TTIGA_JACOBI_G
-// (8, 16, 32 or 64) overrides the choice for measurements.
-static int jacobi_group(int m, int pairs) {
+// Lanes per column pair of a Jacobi round: 16 (a DPP row) was fastest for every size
+// measured (c = m = 24..256; 8, 32 and 64 lose up to 1.1x, 1.3x and 2.7x), 8 for columns
+// of at most 16.  TTIGA_JACOBI_G (8, 16, 32 or 64) overrides the choice for measurements.
+static int jacobi_group(int m) {
   static const int forced = [] {
     const char* e = std::getenv("TTIGA_JACOBI_G");
     const int g = e ? std::atoi(e) : 0;
     return (g == 8 || g == 16 || g == 32 || g == 64) ? g : 0;
   }();
   if (forced) return forced;
-  int best = 8;
-  double best_cost = 1e300;
-  for (int G = 8, lg = 3; G <= 64; G *= 2, ++lg) {
-    const int groups = 16 * (64 / G);
-    const double cost = (double)((pairs + groups - 1) / groups) * ((m + G - 1) / G + 2.0 * lg);
-    if (cost < best_cost) {
-      best_cost = cost;
-      best = G;
-    }
-  }
-  return best;
+  return m <= 16 ? 8 : 16;
 }
 
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
@@ -969,7 +958,7 @@ void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long ld
   const long gneed = mode == 2 ? 0 : (mode == 1 ? vc : uc + vc);
   if (gneed > 0) work = DBuf(ctx.alloc, sizeof(double) * gneed);
   const int pairs = (c + 1) / 2;
-  const int G = jacobi_group(m, pairs);
+  const int G = jacobi_group(m);
   // enough lane groups for all column pairs of a round, up to 16 waves
   const int threads = 64 * std::min(16, std::max(1, (pairs * G + 63) / 64));
   // counted at a nominal 8 sweeps of c(c-1)/2 pair rotations: 3 dots, U (and V) updates

@@ -368,7 +368,7 @@ bool Problem::compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, tti
     for (int b = 0; b < n1; b += chunk) {
       const int cn = std::min(chunk, n1 - b);
       const long w = (long)cn * n2;
-      launch_factors_grid(c, gd, sd, Q, b, cn, buf.d(), st.d(), false, Id.as<int>(), nI, false);
+      launch_factors_grid(c, gd, sd, Q, b, cn, buf.d(), st.d(), false, Id.as<int>(), nI);
       for (int t = 0; t < 7; ++t)
         if (k[t])
           gemm(c, false, false, k[t], (int)w, nI, 1.0, Pinv[t].d(), nI, 0, buf.d() + (size_t)t * nI * w, w, 0,
@@ -472,15 +472,15 @@ void Problem::assemble(ttiga_assembly_stats* st) {
   };
   TT fac[7];
   const bool cross = opts.compression == TTIGA_COMPRESS_AUTO && Q[0] > 2 * kExactSvdSize &&
-                     (size_t)Q[1] * Q[2] > (size_t)(2 * kExactSvdSize);
+                     (size_t)Q[1] * Q[2] > (size_t)(2 * kExactSvdSize) && detj_rows_fit(gd);
   bool done = false;
   if (cross) {
     // det J on the whole grid (the E_DETJ guarantee), then the cross approximation
-    launch_factors_grid(c, gd, sd, Q, 0, Q[1], nullptr, st8.d(), false, nullptr, 0, true);
-    double* h = c.host(8);
-    TTIGA_HIP(hipMemcpyAsync(h, st8.d(), 8 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    launch_detj_min(c, gd, Q, st8.d());
+    double* h = c.host(1);
+    TTIGA_HIP(hipMemcpyAsync(h, st8.d(), sizeof(double), hipMemcpyDeviceToHost, c.stream));
     c.sync();
-    s.min_detJ = min_detJ = h[7];
+    s.min_detJ = min_detJ = h[0];
     if (!(s.min_detJ > 0.0))
       throw Error(TTIGA_E_DETJ, "min det J = " + std::to_string(s.min_detJ) + " <= 0 on the Gauss grid");
     done = compress_cross(gd, sd, fac, s);

@@ -96,13 +96,16 @@ def test_constant_dirichlet_lifting(ctx):
     assert np.linalg.norm(tt.full(rhs) - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
-def test_folded_geometry_reports_detj(ctx):
+@pytest.mark.parametrize("n", [6, 40])
+def test_folded_geometry_reports_detj(ctx, n):
+    """n = 40 (148 Gauss points per direction) takes the cross path, whose det J pass
+    covers the whole grid before any sampling."""
     from paper_2509_13224_amd import ttiga
-    say("folded")
+    say("folded", n)
     geo = W.twisted_box(0.3)
     geo.ctrl = geo.ctrl.copy()
     geo.ctrl[..., 0] *= -1.0  # mirror: det J < 0 everywhere
-    h = ctx.problem_create(W.small_problem(geo, 6, 2, W.zero_source()))
+    h = ctx.problem_create(W.small_problem(geo, n, 2, W.zero_source()))
     with pytest.raises(ttiga.TTIGAError) as e:
         h.assemble()
     assert e.value.code == ttiga.TTIGA_E_DETJ
@@ -169,8 +172,10 @@ def test_grid_factors_match_oracle_samples(ctx, name):
     pr.options.tt_eps = 1e-14
     pr.options.rel_res_tol = 1e-12
     h = ctx.problem_create(pr)
-    h.assemble()
-    samples, _ = geometry.sample_factors_grid(pr)
+    st = h.assemble()
+    samples, detj = geometry.sample_factors_grid(pr)
+    # the sampling kernels report the minimum of det J over the Gauss grid
+    assert abs(st["min_detJ"] - detj.min()) <= 1e-12 * np.abs(detj).max()
     rmax = max(np.linalg.norm(samples[f]) for f in range(6))
     for f in range(7):
         cores = h.tt(ttiga.WHICH_FACTOR0 + f)
@@ -202,7 +207,9 @@ def test_cross_compression(ctx, geo_name):
         assert st["compression_path"] == 2, st["compression_path"]
         assert st["samples"] < Q ** 3 / 3
     say("cross", geo_name, "path", st["compression_path"], "samples", st["samples"], "oracle sampling")
-    samples, _ = geometry.sample_factors_grid(pr)
+    samples, detj = geometry.sample_factors_grid(pr)
+    # the positivity pass of the cross path evaluates det J at every Gauss point
+    assert abs(st["min_detJ"] - detj.min()) <= 1e-12 * np.abs(detj).max()
     rmax = max(np.linalg.norm(samples[f]) for f in range(6))
     for f in range(7):
         cores = h.tt(ttiga.WHICH_FACTOR0 + f)
