@@ -179,8 +179,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3, help="timed batches")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="basis functions per direction")
-    ap.add_argument("--batch", type=int, default=8, help="problems per step")
-    ap.add_argument("--lanes", type=int, default=8, help="concurrent executor lanes")
+    ap.add_argument("--batch", type=int, default=16, help="problems per step")
+    ap.add_argument("--lanes", type=int, default=16, help="concurrent executor lanes")
     ap.add_argument("--family", type=int, default=64, help="requests of the batched family (0: skip)")
     ap.add_argument("--serve", type=int, default=48, help="requests per serving rate (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -200,9 +200,17 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the TT-IGA solve here is a "
               "single-device hot path; see DESIGN.md for how it would shard", file=sys.stderr)
         sys.exit(2)
-    # one hardware queue per lane plus the context's and torch's streams (HIP's default is 4;
-    # two streams on one queue serialise), set before the runtime starts
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.lanes + 2))))
+    # one hardware queue per lane plus the context's and torch's streams (HIP's default is 4,
+    # and an environment may preset it; two streams on one queue serialise), raised before
+    # the runtime starts
+    want = min(32, max(4, args.lanes + 2))
+    try:
+        have = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+    except ValueError:
+        have = 4
+    if have < want:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(want)
+    log(f"GPU_MAX_HW_QUEUES={os.environ.get('GPU_MAX_HW_QUEUES')}")
 
     import torch
 
@@ -277,7 +285,13 @@ def main():
         ctx.solve_batch(plain, lanes=args.lanes)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = [ctx.solve_batch(plain, lanes=args.lanes) for _ in range(args.steps)]
+    runs, step_ms = [], []
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        runs.append(ctx.solve_batch(plain, lanes=args.lanes))
+        step_ms.append(1e3 * (time.perf_counter() - ts))
+        log(f"step {len(runs)}: {step_ms[-1]:.0f} ms, slowest problem "
+            f"{max(r['run_ms'] for r, _ in runs[-1]):.0f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -304,6 +318,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps,
+        "step_ms": step_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
