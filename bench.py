@@ -47,6 +47,8 @@ KERNEL_BOUND = {
     "tsqr_factor": "alu",
     "tsqr_apply": "alu",
     "jacobi_svd": "alu",
+    "jacobi_eig": "alu",
+    "geometry_detj": "alu",
     "assemble_cores": "alu",
 }
 SERVE_SEED = 2025_0913_05

@@ -557,6 +557,10 @@ __global__ void k_jacobi_svd(int m, int c, const double* __restrict__ A, int tra
                              double* __restrict__ gwork, double* __restrict__ U, double* __restrict__ S,
                              double* __restrict__ V, int max_sweeps, int G);
 
+template <bool kLds>
+__global__ void k_pchol(int r, const double* __restrict__ G, double tau_rel, double* __restrict__ L,
+                        double* __restrict__ gwork, int* __restrict__ rank_out);
+
 // static LDS of k_jacobi_svd (pair flags, permutation, singular values) and of the
 // TSQR kernels (reflector scalars), with margin
 constexpr int kJacobiStatic = 16384;
@@ -586,6 +590,9 @@ static int lds_doubles() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
               hipSuccess &&
           hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd<1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
+              hipSuccess &&
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
               hipSuccess;
       if (!ok) {
@@ -726,6 +733,141 @@ bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* R
   return h[0] == 0.0;
 }
 
+// ------------------------------------------------- pivoted Cholesky (Gram route)
+// G = L L^T for a symmetric positive semi-definite G (r x r, row-major), with L (r x k,
+// row-major, leading dimension r) in the original index order: step j takes the largest
+// remaining diagonal entry of the Schur complement as pivot p_j, so column j vanishes on
+// the rows pivoted before it and no permutation has to be undone.  The factorisation stops
+// at the first pivot at most tau_rel max_i G_ii (rank k = that step; every diagonal entry
+// of the Schur complement left out is then below that level).  One workgroup: the working
+// copy W in LDS (kLds) or in gwork; diagonal, pivot column and the list of remaining
+// indices in LDS after W.
+template <bool kLds>
+__global__ __launch_bounds__(1024) void k_pchol(int r, const double* __restrict__ G, double tau_rel,
+                                               double* __restrict__ L, double* __restrict__ gwork,
+                                               int* __restrict__ rank_out) {
+  extern __shared__ double sm[];
+  double* W = kLds ? sm : gwork;
+  double* dg = sm + (kLds ? (long)r * r : 0);
+  double* lcol = dg + r;
+  int* rem = reinterpret_cast<int*>(lcol + r);
+  __shared__ double s_best[16];
+  __shared__ int s_bi[16];
+  __shared__ int s_p, s_stop;
+  __shared__ double s_ljj, s_tau;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  for (long e = tid; e < (long)r * r; e += nt) {
+    W[e] = G[e];
+    L[e] = 0.0;
+  }
+  for (int i = tid; i < r; i += nt) rem[i] = i;
+  __syncthreads();
+  for (int i = tid; i < r; i += nt) dg[i] = W[(long)i * r + i];
+  __syncthreads();
+  // largest entry among dg[rem[0 .. nr)] (ties: the first position), into s_best / s_bi
+  auto pick = [&](int nr) {
+    double best = -INFINITY;
+    int bi = nr;
+    for (int t = tid; t < nr; t += nt) {
+      const double v = dg[rem[t]];
+      if (v > best) {
+        best = v;
+        bi = t;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      s_best[wave] = best;
+      s_bi[wave] = bi;
+    }
+  };
+  int nr = r, k = r;
+  for (int j = 0; j < r; ++j) {
+    pick(nr);
+    __syncthreads();
+    if (tid == 0) {
+      double best = s_best[0];
+      int bi = s_bi[0];
+      for (int w = 1; w < nw; ++w)
+        if (s_best[w] > best || (s_best[w] == best && s_bi[w] < bi)) {
+          best = s_best[w];
+          bi = s_bi[w];
+        }
+      if (j == 0) s_tau = tau_rel * fmax(best, 0.0);
+      if (!(best > s_tau) || bi >= nr) {
+        s_stop = 1;
+      } else {
+        s_stop = 0;
+        s_p = rem[bi];
+        rem[bi] = rem[nr - 1];
+        s_ljj = sqrt(best);
+      }
+    }
+    __syncthreads();
+    if (s_stop) {
+      k = j;
+      break;
+    }
+    const int p = s_p;
+    const double ljj = s_ljj;
+    nr -= 1;
+    if (tid == 0) L[(long)p * r + j] = ljj;
+    for (int t = tid; t < nr; t += nt) {
+      const int a = rem[t];
+      const double l = W[(long)a * r + p] / ljj;
+      lcol[a] = l;
+      L[(long)a * r + j] = l;
+    }
+    __syncthreads();
+    // Schur complement on the remaining indices (a wave per row, lanes along the row)
+    for (int ia = wave; ia < nr; ia += nw) {
+      const int a = rem[ia];
+      const double la = lcol[a];
+      double* wa = W + (long)a * r;
+      for (int ib = lane; ib < nr; ib += 64) {
+        const int b = rem[ib];
+        const double v = wa[b] - la * lcol[b];
+        wa[b] = v;
+        if (a == b) dg[a] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *rank_out = k;
+}
+
+static bool pchol_lds_fit(int r) {
+  return (long)r * r + 2L * r + (r + 1) / 2 <= (long)lds_doubles();
+}
+
+int pivoted_cholesky(Context& ctx, const double* G, int r, double* L, double tau_rel) {
+  TTIGA_CHECK(r > 0 && r <= 1024, TTIGA_E_ARG, "pivoted_cholesky needs 0 < r <= 1024");
+  const bool lds = pchol_lds_fit(r);
+  DBuf work, rk(ctx.alloc, sizeof(int));
+  if (!lds) work = DBuf(ctx.alloc, sizeof(double) * (size_t)r * r);
+  const size_t shm = sizeof(double) * ((lds ? (size_t)r * r : 0) + 2 * (size_t)r) + sizeof(int) * (size_t)r;
+  ProfScope prof(ctx, "gram_cholesky", (double)r * r * r / 3.0, 8.0 * 2.0 * r * r, r);
+  const int threads = 64 * std::min(16, std::max(1, (r + 63) / 64 * 4));
+  if (lds)
+    hipLaunchKernelGGL(k_pchol<true>, dim3(1), dim3(threads), shm, ctx.stream, r, G, tau_rel, L, nullptr,
+                       rk.as<int>());
+  else
+    hipLaunchKernelGGL(k_pchol<false>, dim3(1), dim3(threads), shm, ctx.stream, r, G, tau_rel, L, work.d(),
+                       rk.as<int>());
+  TTIGA_HIP(hipGetLastError());
+  int* h = reinterpret_cast<int*>(ctx.host(1));
+  TTIGA_HIP(hipMemcpyAsync(h, rk.d(), sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  return *h;
+}
+
 // ------------------------------------------------------------- Jacobi SVD
 
 // One workgroup.  Ucol [c][m] and Vcol [c][c] are column-major work arrays.  kMode 2:
@@ -769,26 +911,54 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
   // of a length-m dot product), or both columns are below 1e-15 of the Frobenius norm
   // (they cannot affect any truncation decision)
   const double tol = 2.220446049250313e-16 * m, floor2 = 1e-30 * f2;
+  // columns of at most kRegs G entries stay in registers from the dot products to the
+  // rotation (one LDS read per round instead of two)
+  constexpr int kRegs = 8;
+  const bool in_regs = m <= G * kRegs;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int rnd = 0; rnd < cp - 1; ++rnd) {
       for (int k = grp; k < cp / 2; k += ngroups) {
-        // circle method: slot 0 fixed, slots 1..cp-1 rotate by rnd
+        // circle method: slot 0 fixed, slots 1..cp-1 rotate by rnd (a - 1 + rnd and
+        // b - 1 + rnd stay below 2 (cp - 1), so one subtraction wraps them)
         const int a = k, b = cp - 1 - k;
-        const int pa = (a == 0) ? 0 : ((a - 1 + rnd) % (cp - 1)) + 1;
-        const int pb = ((b - 1 + rnd) % (cp - 1)) + 1;
+        int pa = 0;
+        if (a != 0) {
+          pa = a - 1 + rnd;
+          if (pa >= cp - 1) pa -= cp - 1;
+          pa += 1;
+        }
+        int pb = b - 1 + rnd;
+        if (pb >= cp - 1) pb -= cp - 1;
+        pb += 1;
         const int p = min(pa, pb), q = max(pa, pb);
         if (q >= c) continue;
         double* up = Ucol + (long)p * m;
         double* uq = Ucol + (long)q * m;
         double al = 0.0, be = 0.0, ga = 0.0;
+        double xr[kRegs], yr[kRegs];
+        if (in_regs) {
+#pragma unroll
+          for (int r = 0; r < kRegs; ++r) {
+            const int i = gl + r * G;
+            xr[r] = i < m ? up[i] : 0.0;
+            yr[r] = i < m ? uq[i] : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < kRegs; ++r) {
+            al += xr[r] * xr[r];
+            be += yr[r] * yr[r];
+            ga += xr[r] * yr[r];
+          }
+        } else {
 #pragma unroll 4
-        for (int i = gl; i < m; i += G) {
-          const double x = up[i], y = uq[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+          for (int i = gl; i < m; i += G) {
+            const double x = up[i], y = uq[i];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
         }
         if (G == 8) {
           al = group_sum<8>(al);
@@ -806,13 +976,34 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
         }
         const double pq = sqrt(al) * sqrt(be);
         if (ga == 0.0 || !(fabs(ga) > tol * pq) || pq <= floor2) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int i = gl; i < m; i += G) {
-          const double x = up[i], y = uq[i];
-          up[i] = cs * x - sn * y;
-          uq[i] = sn * x + cs * y;
+        // the rotation annihilating ga: with d = be - al, h = sqrt(d^2 + 4 ga^2) and
+        // u = |d| + h, tan = sign(d) 2 ga / u and 1 + tan^2 = 2 h u / u^2, so
+        // cos = u / sqrt(2 h u) and sin = sign(d) 2 ga / sqrt(2 h u) (three dependent
+        // roots/reciprocals); d and 2 ga are first scaled by a power of two (exactly)
+        // so that their squares cannot overflow
+        double d = be - al, g2 = 2.0 * ga;
+        const int ex = ilogb(fmax(fabs(d), fabs(g2)));
+        d = ldexp(d, -ex);
+        g2 = ldexp(g2, -ex);
+        const double h = sqrt(d * d + g2 * g2);
+        const double u = fabs(d) + h;
+        const double rw = rsqrt(2.0 * h * u);
+        const double cs = u * rw, sn = copysign(1.0, d) * g2 * rw;
+        if (in_regs) {
+#pragma unroll
+          for (int r = 0; r < kRegs; ++r) {
+            const int i = gl + r * G;
+            if (i < m) {
+              up[i] = cs * xr[r] - sn * yr[r];
+              uq[i] = sn * xr[r] + cs * yr[r];
+            }
+          }
+        } else {
+          for (int i = gl; i < m; i += G) {
+            const double x = up[i], y = uq[i];
+            up[i] = cs * x - sn * y;
+            uq[i] = sn * x + cs * y;
+          }
         }
         if (want_v) {
           double* vp = Vcol + (long)p * c;
@@ -949,7 +1140,7 @@ static int jacobi_group(int m) {
 }
 
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
-               double* s, double* V) {
+               double* s, double* V, const char* prof_name) {
   TTIGA_CHECK(c > 0 && m >= c && c <= 1024, TTIGA_E_ARG, "svd_small needs 0 < c <= m, c <= 1024");
   const long uc = (long)m * c, vc = V ? (long)c * c : 0;
   const long cap = lds_doubles();
@@ -963,7 +1154,7 @@ void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long ld
   const int threads = 64 * std::min(16, std::max(1, (pairs * G + 63) / 64));
   // counted at a nominal 8 sweeps of c(c-1)/2 pair rotations: 3 dots, U (and V) updates
   const double per_rot = 12.0 * m + (V ? 6.0 * c : 0.0);
-  ProfScope prof(ctx, "jacobi_svd", 8.0 * 0.5 * c * (c - 1.0) * per_rot,
+  ProfScope prof(ctx, prof_name, 8.0 * 0.5 * c * (c - 1.0) * per_rot,
                  8.0 * (2.0 * m * c + (V ? 2.0 * c * c : 0.0) + c), c);
   const size_t lds_bytes = sizeof(double) * (mode == 2 ? uc + vc : (mode == 1 ? uc : 0));
   if (mode == 2)

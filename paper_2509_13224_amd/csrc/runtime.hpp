@@ -237,14 +237,19 @@ void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, con
 void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
              double* R);
 // One-sided Jacobi SVD of op(A) (m x c, m >= c): U (m x c), s (c, descending), V (c x c);
-// V may be null when the right vectors are not needed.
+// V may be null when the right vectors are not needed.  prof_name labels the launch in
+// the profile.
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
-               double* s, double* V);
+               double* s, double* V, const char* prof_name = "jacobi_svd");
 // k interpolation rows of an n x k matrix with orthonormal columns (column-pivoted QR of
 // Q^T), written to the device array rows.
 void pivot_rows(Context& ctx, const double* Q, int n, int k, int* rows);
 // Upper Cholesky factor R (R^T R = G) and R^-1 of an SPD c x c matrix; false if G is not SPD.
 bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* Rinv);
+// Pivoted Cholesky G = L L^T of a symmetric positive semi-definite G (r x r, row-major):
+// L (r x r buffer, row-major; columns >= k are zero) in the original index order, stopped
+// at the first pivot at most tau_rel max_i G_ii; returns k (host synchronisation).
+int pivoted_cholesky(Context& ctx, const double* G, int r, double* L, double tau_rel);
 // Smallest r with ||s[r:]|| <= delta (delta < 0: -delta * ||s|| / sqrt(2) relative).
 int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* norm_out);
 void fill(Context& ctx, double* p, size_t n, double v);

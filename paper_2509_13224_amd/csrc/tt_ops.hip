@@ -175,13 +175,7 @@ __global__ void k_transpose_cols(const double* __restrict__ V, int rows, int ld,
 }
 
 // O[i][:] = s[i] * V[i][:] for a row-major (rows x M) matrix
-// Singular values from Gram eigenvalues (negative rounding noise clamped to 0), and the
-// reciprocals of the leading ones.
-__global__ void k_gram_sigma(const double* __restrict__ lam, int c, double* __restrict__ S) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < c) S[i] = sqrt(fmax(lam[i], 0.0));
-}
-
+// Reciprocals of the leading singular values.
 __global__ void k_reciprocal(const double* __restrict__ S, int s, double* __restrict__ R) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < s) R[i] = 1.0 / S[i];
@@ -385,33 +379,38 @@ struct TruncSVD {
 };
 
 // Truncated SVD of a wide r x M matrix through its Gram matrix: G = B B^T by one MFMA
-// GEMM, one-sided Jacobi on G (for a symmetric positive semi-definite matrix the SVD is
-// the eigendecomposition, lam = sigma^2, eigenvectors = its left vectors V), U_s the
-// leading eigenvectors and V_s^T = S_s^-1 U_s^T B.  Squaring resolves singular values down to
-// about sqrt(u) ||B|| and the rows of V_s^T are orthonormal to about u (sigma_1 /
-// sigma_s)^2, so this route is taken only for relative thresholds of 1e-6 and above.
+// GEMM, then the eigendecomposition of G: a pivoted Cholesky factor G = L L^T (r x k,
+// stopped at pivots below u max G_ii) and a one-sided Jacobi SVD of L = E S W^T, so
+// G = E S^2 E^T: E are the eigenvectors of G, S = sqrt(lam) the singular values of B
+// (Jacobi on L converges in the sweeps of Jacobi on a triangular factor, about a third of
+// those of Jacobi on G itself).  U_s the leading eigenvectors and V_s^T = S_s^-1 U_s^T B.
+// Squaring resolves singular values down to about sqrt(u) ||B|| and the rows of V_s^T are
+// orthonormal to about u (sigma_1 / sigma_s)^2, so this route is taken only for relative
+// thresholds of 1e-6 and above; the Schur complement left out of L has trace at most
+// r u max G_ii, far below their square.
 static TruncSVD truncated_svd_gram(Context& ctx, const double* B, int r, long M, double delta) {
   TruncSVD o;
   DBuf G(ctx.alloc, sizeof(double) * r * r);
   gemm(ctx, false, true, r, r, (int)M, 1.0, B, M, 0, B, M, 0, 0.0, G.d(), r, 0);
-  // one-sided Jacobi on G: G W = E diag(lam) with orthonormal columns E; for a symmetric
-  // positive semi-definite G these are its eigenvectors, so W is not accumulated (a
-  // two-sided cyclic Jacobi eigensolver was measured slower at every size up to 128)
-  DBuf V(ctx.alloc, sizeof(double) * r * r), lam(ctx.alloc, sizeof(double) * r);
-  svd_small(ctx, G.d(), false, r, r, r, V.d(), lam.d(), nullptr);
+  DBuf L(ctx.alloc, sizeof(double) * r * r);
+  const int k = pivoted_cholesky(ctx, G.d(), r, L.d(), 2.220446049250313e-16);
   o.S = DBuf(ctx.alloc, sizeof(double) * r);
-  hipLaunchKernelGGL(k_gram_sigma, dim3((r + 255) / 256), dim3(256), 0, ctx.stream, lam.d(), r, o.S.d());
-  TTIGA_HIP(hipGetLastError());
+  fill(ctx, o.S.d(), r, 0.0);
+  DBuf V;  // r x k eigenvectors, row-major
+  if (k > 0) {
+    V = DBuf(ctx.alloc, sizeof(double) * r * k);
+    svd_small(ctx, L.d(), false, r, k, r, V.d(), o.S.d(), nullptr, "jacobi_eig");
+  }
   double nd[2];
   o.s = trunc_rank_sync(ctx, o.S.d(), r, delta, nd);
   o.norm = nd[0];
   o.delta = nd[1];
   if (o.s == 0) return o;
   o.U = DBuf(ctx.alloc, sizeof(double) * r * o.s);
-  hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long)r * o.s)), dim3(256), 0, ctx.stream, V.d(), r, r, o.s,
+  hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long)r * o.s)), dim3(256), 0, ctx.stream, V.d(), r, k, o.s,
                      o.U.d());
   DBuf W(ctx.alloc, sizeof(double) * o.s * M), inv(ctx.alloc, sizeof(double) * o.s);
-  gemm(ctx, true, false, o.s, (int)M, r, 1.0, V.d(), r, 0, B, M, 0, 0.0, W.d(), M, 0);
+  gemm(ctx, true, false, o.s, (int)M, r, 1.0, V.d(), k, 0, B, M, 0, 0.0, W.d(), M, 0);
   hipLaunchKernelGGL(k_reciprocal, dim3((o.s + 255) / 256), dim3(256), 0, ctx.stream, o.S.d(), o.s, inv.d());
   o.Vt = DBuf(ctx.alloc, sizeof(double) * o.s * M);
   hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)o.s * M)), dim3(256), 0, ctx.stream, W.d(), o.s, M,
