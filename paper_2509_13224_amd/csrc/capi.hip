@@ -151,7 +151,22 @@ void DeviceAllocator::release(void* p) {
 
 Context::~Context() {
   release_blas(blas);
+  if (sync_event) (void)hipEventDestroy(sync_event);
   if (host_scratch) (void)hipHostFree(host_scratch);
+}
+
+void Context::sync() {
+  static const bool blocking = [] {
+    const char* e = std::getenv("TTIGA_BLOCKING_SYNC");
+    return e && e[0] == '1';
+  }();
+  if (!blocking) {
+    TTIGA_HIP(hipStreamSynchronize(stream));
+    return;
+  }
+  if (!sync_event) TTIGA_HIP(hipEventCreateWithFlags(&sync_event, hipEventBlockingSync | hipEventDisableTiming));
+  TTIGA_HIP(hipEventRecord(sync_event, stream));
+  TTIGA_HIP(hipEventSynchronize(sync_event));
 }
 
 hipEvent_t Profiler::get() {
@@ -238,7 +253,10 @@ double* Context::host(size_t n) {
   if (n > host_scratch_doubles) {
     if (host_scratch) TTIGA_HIP(hipHostFree(host_scratch));
     host_scratch = nullptr;
-    TTIGA_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_scratch), sizeof(double) * std::max<size_t>(n, 64)));
+    host_dev = nullptr;
+    TTIGA_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_scratch), sizeof(double) * std::max<size_t>(n, 64),
+                            hipHostMallocCoherent));
+    TTIGA_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&host_dev), host_scratch, 0));
     host_scratch_doubles = std::max<size_t>(n, 64);
   }
   return host_scratch;

@@ -605,6 +605,17 @@ static int lds_doubles() {
   return cap;
 }
 
+// Dynamic LDS for a single-workgroup factorisation kernel: with TTIGA_EXCLUSIVE_CU=1 the
+// whole budget is requested, so that no workgroup of another stream shares the compute unit
+// (measurement switch for concurrent lanes).
+static size_t lds_request(size_t need) {
+  static const bool exclusive = [] {
+    const char* e = std::getenv("TTIGA_EXCLUSIVE_CU");
+    return e && e[0] == '1';
+  }();
+  return exclusive ? std::max(need, sizeof(double) * (size_t)lds_doubles()) : need;
+}
+
 // one wave per owned column up to 16 waves
 static int qr_threads(int c) { return 64 * std::min(16, std::max(1, c)); }
 
@@ -637,17 +648,19 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     L.v_lds = 2L * L.ldw * c <= kLdsDoubles;
     L.V = DBuf(ctx.alloc, sizeof(double) * (size_t)mm * c);
     L.tau = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * c);
-    L.R = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * c * c);
+    // the root of the tree writes its R straight to the caller's buffer
+    if (L.nb > 1) L.R = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * c * c);
+    double* Rout = L.nb > 1 ? L.R.d() : R;
     if (!L.lds) L.work = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * L.ldw * c);
     const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
     ProfScope prof(ctx, "tsqr_factor", 2.0 * mm * c * c - L.nb * (2.0 / 3.0) * c * c * c,
                    8.0 * (2.0 * mm * c + (double)L.nb * c * c), c);
     if (L.lds)
-      hipLaunchKernelGGL(k_hh_factor<true>, dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, mm, c, in, ld,
-                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), L.R.d(), nullptr);
+      hipLaunchKernelGGL(k_hh_factor<true>, dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, mm, c, in, ld,
+                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, nullptr);
     else
       hipLaunchKernelGGL(k_hh_factor<false>, dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, mm, c, in, ld,
-                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), L.R.d(), L.work.d());
+                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, L.work.d());
     TTIGA_HIP(hipGetLastError());
     lv.push_back(std::move(L));
     const Level& last = lv.back();
@@ -657,7 +670,6 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     ld = c;
     mm = last.nb * c;
   }
-  copy(ctx, R, lv.back().R.d(), (size_t)c * c);
   // thin Q, top-down
   DBuf qprev;
   for (int l = (int)lv.size() - 1; l >= 0; --l) {
@@ -668,10 +680,10 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     ProfScope prof(ctx, "tsqr_apply", 4.0 * c * c * (double)L.m - 2.0 * c * c * c * L.nb,
                    8.0 * (2.0 * L.m * c + (double)L.nb * c * c), c);
     if (L.v_lds)
-      hipLaunchKernelGGL((k_hh_apply<true, true>), dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, L.m, c,
+      hipLaunchKernelGGL((k_hh_apply<true, true>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, L.m, c,
                          L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
     else if (L.lds)
-      hipLaunchKernelGGL((k_hh_apply<true, false>), dim3(L.nb), dim3(qr_threads(c)), shm, ctx.stream, L.m, c,
+      hipLaunchKernelGGL((k_hh_apply<true, false>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, L.m, c,
                          L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
     else
       hipLaunchKernelGGL((k_hh_apply<false, false>), dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, L.m, c,
@@ -850,20 +862,20 @@ static bool pchol_lds_fit(int r) {
 int pivoted_cholesky(Context& ctx, const double* G, int r, double* L, double tau_rel) {
   TTIGA_CHECK(r > 0 && r <= 1024, TTIGA_E_ARG, "pivoted_cholesky needs 0 < r <= 1024");
   const bool lds = pchol_lds_fit(r);
-  DBuf work, rk(ctx.alloc, sizeof(int));
+  DBuf work;
   if (!lds) work = DBuf(ctx.alloc, sizeof(double) * (size_t)r * r);
+  int* rk = reinterpret_cast<int*>(ctx.host_device(1));
+  const int* h = reinterpret_cast<const int*>(ctx.host_scratch);
   const size_t shm = sizeof(double) * ((lds ? (size_t)r * r : 0) + 2 * (size_t)r) + sizeof(int) * (size_t)r;
   ProfScope prof(ctx, "gram_cholesky", (double)r * r * r / 3.0, 8.0 * 2.0 * r * r, r);
   const int threads = 64 * std::min(16, std::max(1, (r + 63) / 64 * 4));
   if (lds)
-    hipLaunchKernelGGL(k_pchol<true>, dim3(1), dim3(threads), shm, ctx.stream, r, G, tau_rel, L, nullptr,
-                       rk.as<int>());
+    hipLaunchKernelGGL(k_pchol<true>, dim3(1), dim3(threads), lds_request(shm), ctx.stream, r, G, tau_rel, L, nullptr,
+                       rk);
   else
     hipLaunchKernelGGL(k_pchol<false>, dim3(1), dim3(threads), shm, ctx.stream, r, G, tau_rel, L, work.d(),
-                       rk.as<int>());
+                       rk);
   TTIGA_HIP(hipGetLastError());
-  int* h = reinterpret_cast<int*>(ctx.host(1));
-  TTIGA_HIP(hipMemcpyAsync(h, rk.d(), sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
   ctx.sync();
   return *h;
 }
@@ -1158,10 +1170,10 @@ void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long ld
                  8.0 * (2.0 * m * c + (V ? 2.0 * c * c : 0.0) + c), c);
   const size_t lds_bytes = sizeof(double) * (mode == 2 ? uc + vc : (mode == 1 ? uc : 0));
   if (mode == 2)
-    hipLaunchKernelGGL(k_jacobi_svd<2>, dim3(1), dim3(threads), lds_bytes, ctx.stream, m, c, A,
+    hipLaunchKernelGGL(k_jacobi_svd<2>, dim3(1), dim3(threads), lds_request(lds_bytes), ctx.stream, m, c, A,
                        transA ? 1 : 0, lda, nullptr, U, s, V, 40, G);
   else if (mode == 1)
-    hipLaunchKernelGGL(k_jacobi_svd<1>, dim3(1), dim3(threads), lds_bytes, ctx.stream, m, c, A,
+    hipLaunchKernelGGL(k_jacobi_svd<1>, dim3(1), dim3(threads), lds_request(lds_bytes), ctx.stream, m, c, A,
                        transA ? 1 : 0, lda, work.d(), U, s, V, 40, G);
   else
     hipLaunchKernelGGL(k_jacobi_svd<0>, dim3(1), dim3(threads), 0, ctx.stream, m, c, A, transA ? 1 : 0, lda,
@@ -1196,12 +1208,11 @@ __global__ void k_trunc_rank(const double* __restrict__ s, int c, double eps_rel
 
 int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* norm_out) {
   // delta >= 0: absolute threshold; delta < 0: relative eps = -delta.
-  double* h = ctx.host(3);
-  DBuf o(ctx.alloc, 3 * sizeof(double));
+  double* hd = ctx.host_device(3);
+  double* h = ctx.host_scratch;
   hipLaunchKernelGGL(k_trunc_rank, dim3(1), dim3(64), 0, ctx.stream, s, c,
-                     delta < 0 ? -delta : 0.0, delta < 0 ? -1.0 : delta, o.d());
+                     delta < 0 ? -delta : 0.0, delta < 0 ? -1.0 : delta, hd);
   TTIGA_HIP(hipGetLastError());
-  TTIGA_HIP(hipMemcpyAsync(h, o.d(), 3 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
   ctx.sync();
   if (norm_out) {
     norm_out[0] = h[1];
@@ -1223,9 +1234,19 @@ void fill(Context& ctx, double* p, size_t n, double v) {
   TTIGA_HIP(hipGetLastError());
 }
 
+// A copy kernel rather than hipMemcpyAsync: one plain dispatch, no runtime memory-object
+// lookups on the host (which serialise concurrent lanes), and the destination may be the
+// device address of host staging memory.
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
 void copy(Context& ctx, double* dst, const double* src, size_t n) {
   if (!n || dst == src) return;
-  TTIGA_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+  const int blocks = (int)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, ctx.stream, dst, src, n);
+  TTIGA_HIP(hipGetLastError());
 }
 
 __global__ void k_sumsq_partial(const double* __restrict__ x, size_t n, double* __restrict__ part) {

@@ -174,8 +174,10 @@ struct Context {
   PlanCache* plans = &own_plans;
   // rocBLAS handle (created on first use by gemm, bound to this context's stream)
   void* blas = nullptr;
-  // pinned host staging for small readbacks (ranks, scalars)
+  // pinned, coherent host staging for small readbacks (ranks, scalars); kernels write
+  // results straight to host_dev (its device address), so a readback needs no copy
   double* host_scratch = nullptr;
+  double* host_dev = nullptr;
   size_t host_scratch_doubles = 0;
   // sketch seeds; reset at the start of every assembly and solve, so a problem's
   // results do not depend on what ran before it on the context
@@ -188,7 +190,15 @@ struct Context {
   struct ::ttiga_ctx* owner = nullptr;
   ~Context();
   double* host(size_t n);
-  void sync() { TTIGA_HIP(hipStreamSynchronize(stream)); }
+  // host(n) and the device address of the same memory
+  double* host_device(size_t n) {
+    host(n);
+    return host_dev;
+  }
+  // waits for the stream; with TTIGA_BLOCKING_SYNC=1 the host thread sleeps on a
+  // blocking-sync event instead of polling (measurement switch for many lanes)
+  void sync();
+  hipEvent_t sync_event = nullptr;
 };
 
 // TT tensor with d = 3 cores in paper order [r_k][n_k][r_{k+1}] (FP64, device).

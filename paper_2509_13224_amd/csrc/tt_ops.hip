@@ -361,12 +361,10 @@ void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev) {
 }
 
 double tt_dot_sync(Context& ctx, const TT& x, const TT& y) {
-  DBuf o(ctx.alloc, sizeof(double));
-  tt_dot_dev(ctx, x, y, o.d());
-  double* h = ctx.host(1);
-  TTIGA_HIP(hipMemcpyAsync(h, o.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  double* hd = ctx.host_device(1);
+  tt_dot_dev(ctx, x, y, hd);
   ctx.sync();
-  return h[0];
+  return ctx.host_scratch[0];
 }
 
 // Truncated SVD of B (r x M, row-major): B ~= U_s diag(S_s) Vt_s with orthonormal U_s
