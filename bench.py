@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--single-only", action="store_true",
                     help="only the single-solve phase (value = its solve rate): the run whose kernel "
                          "averages a rocprofv3 trace can be compared with the roofline line")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the timed batched FP64 steps (value = their solve rate, accuracy not "
+                         "gated): the run whose rocprofv3 trace shows the lanes side by side")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="only copy this many GiB device-to-device three times (scale of the HBM "
                          "byte counters) and exit")
@@ -238,6 +241,25 @@ def main():
     plain = [W.c2_problem(n=args.n, seed=s) for s in seeds]
     mixed = [W.c2_problem(n=args.n, seed=s, precision=PREC_FP32) for s in seeds]
     refs_pr = [W.c2_problem(n=args.n, seed=s, eps=eps / 10, tol=tol / 10) for s in seeds]
+
+    if args.batched_only:
+        log("batched FP64 steps only")
+        for _ in range(args.warmup):
+            ctx.solve_batch(plain, lanes=args.lanes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.solve_batch(plain, lanes=args.lanes)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        print(json.dumps({
+            "metric": "solves/s (batched FP64 steps only, accuracy not gated)",
+            "value": args.batch * args.steps / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{args.batch} C2 problems (annulus degree 3, n={args.n}/dir, TT eps {eps}) "
+                                   f"per step on {args.lanes} lanes"}}), flush=True)
+        return
 
     # 1. plain FP64 single solve: latency, roofline of the dominant kernel class
     log("single FP64 solve")

@@ -622,10 +622,6 @@ __global__ void k_homogeneous(long count, const double* __restrict__ xyz, const 
 
 // ------------------------------------------------------------------ launchers
 static int blocks_for(long total, int per = 256) { return (int)((total + per - 1) / per); }
-static int grid_for(long total) {
-  return (int)std::max<long>(1, std::min<long>((total + 255) / 256, 16384));
-}
-
 void launch_basis_tables(Context& ctx, int n, int p, int g, const double* knots, double* xi,
                          double* w, double* B, double* D) {
   const int Q = (n - p) * g;
@@ -648,7 +644,9 @@ void launch_detj_min(Context& ctx, const GeoDev& geo, const int* Q, double* min_
   const long rows = (long)Q[0] * Q[1];
   const long total = rows * Q[2];
   ProfScope prof(ctx, "geometry_detj", (32.0 * (geo.pg[2] + 1) + 40.0) * total, 0.0);
-  const int blocks = (int)std::min<long>((rows + 3) / 4, 8192);
+  // two blocks per compute unit: the kernel loops over rows for its whole duration, so a
+  // larger grid would hold every wave slot while the kernels of other streams wait
+  const int blocks = (int)std::min<long>((rows + 3) / 4, 512);
   const int iters = (int)((rows + 4L * blocks - 1) / (4L * blocks));
   DBuf part(ctx.alloc, sizeof(double) * blocks);
   hipLaunchKernelGGL(k_detj_rows, dim3(blocks), dim3(256), sizeof(double) * 4 * 12 * geo.m[2], ctx.stream, geo,

@@ -150,8 +150,7 @@ static void gemm_hand(Context& ctx, int split_scale, bool ta, bool tb, int M, in
   TTIGA_HIP(hipGetLastError());
   if (splits > 1) {
     const long total = (long)batch * M * N;
-    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_splitk_reduce, dim3(blocks), dim3(256), 0, ctx.stream, M, N, splits,
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(total)), dim3(256), 0, ctx.stream, M, N, splits,
                        batch, alpha, part.d(), beta, C, ldc, sC);
     TTIGA_HIP(hipGetLastError());
   }
@@ -1229,8 +1228,7 @@ __global__ void k_fill(double* p, size_t n, double v) {
 
 void fill(Context& ctx, double* p, size_t n, double v) {
   if (!n) return;
-  const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, ctx.stream, p, n, v);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for((long)n)), dim3(256), 0, ctx.stream, p, n, v);
   TTIGA_HIP(hipGetLastError());
 }
 
@@ -1244,8 +1242,7 @@ __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src,
 
 void copy(Context& ctx, double* dst, const double* src, size_t n) {
   if (!n || dst == src) return;
-  const int blocks = (int)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, ctx.stream, dst, src, n);
+  hipLaunchKernelGGL(k_copy, dim3(grid_for((long)n)), dim3(256), 0, ctx.stream, dst, src, n);
   TTIGA_HIP(hipGetLastError());
 }
 

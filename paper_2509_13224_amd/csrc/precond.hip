@@ -26,10 +26,6 @@
 
 namespace ttiga {
 
-static int grid_for(long total) {
-  return (int)std::max<long>(1, std::min<long>((total + 255) / 256, 16384));
-}
-
 __global__ void k_band_to_dense(int n, int p, const double* __restrict__ M, double* __restrict__ D) {
   const long total = (long)n * n;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;

@@ -207,10 +207,6 @@ __global__ void k_gaussian(double* __restrict__ O, long n, uint64_t seed) {
   }
 }
 
-static int grid_for(long total) {
-  return (int)std::max<long>(1, std::min<long>((total + 255) / 256, 16384));
-}
-
 // --------------------------------------------------------------- host ops
 void tt_copy(Context& ctx, const TT& src, TT& dst) {
   if (src.zero()) { dst.set_zero(src.n); return; }
@@ -731,9 +727,8 @@ int column_basis(Context& ctx, const double* C, int m, int L, double delta, DBuf
 
 __global__ void k_gather_rows(const double* __restrict__ A, int k, const int* __restrict__ rows, int nr,
                               double* __restrict__ out) {
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= (long)nr * k) return;
-  out[e] = A[(long)rows[e / k] * k + e % k];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)nr * k; e += (long)gridDim.x * blockDim.x)
+    out[e] = A[(long)rows[e / k] * k + e % k];
 }
 
 void scale_cols_inv(Context& ctx, const double* A, int m, int cols, const double* S, double* out) {
@@ -756,16 +751,16 @@ __global__ void k_tt_eval(int r1, int r2, int n1, int n2, const double* __restri
                           const double* __restrict__ G1, const double* __restrict__ G2, long count,
                           const int* __restrict__ i0, const int* __restrict__ i1, const int* __restrict__ i2,
                           double* __restrict__ out) {
-  const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (q >= count) return;
-  const double* g0 = G0 + (long)i0[q] * r1;
-  double v = 0.0;
-  for (int b = 0; b < r2; ++b) {
-    double t = 0.0;
-    for (int a = 0; a < r1; ++a) t += g0[a] * G1[((long)a * n1 + i1[q]) * r2 + b];
-    v += t * G2[(long)b * n2 + i2[q]];
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < count; q += (long)gridDim.x * blockDim.x) {
+    const double* g0 = G0 + (long)i0[q] * r1;
+    double v = 0.0;
+    for (int b = 0; b < r2; ++b) {
+      double t = 0.0;
+      for (int a = 0; a < r1; ++a) t += g0[a] * G1[((long)a * n1 + i1[q]) * r2 + b];
+      v += t * G2[(long)b * n2 + i2[q]];
+    }
+    out[q] = v;
   }
-  out[q] = v;
 }
 
 void tt_eval_points(Context& ctx, const TT& x, long count, const int* i0, const int* i1, const int* i2,
