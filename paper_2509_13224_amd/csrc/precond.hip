@@ -84,6 +84,11 @@ __global__ void k_exp_hadamard(int k, int R, int n, int ra, int rb, const double
   }
 }
 
+__global__ void k_square(double* __restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= x[i];
+}
+
 static std::shared_ptr<EigenBasis> eigenbasis(Problem& P, int d) {
   Context& ctx = *P.ctx;
   const int p = P.p, band = 2 * p + 1;
@@ -133,6 +138,12 @@ static std::shared_ptr<EigenBasis> eigenbasis(Problem& P, int d) {
   gemm(ctx, false, false, m, m, m, 1.0, Ad.d(), m, 0, Rmi.d(), m, 0, 0.0, T1.d(), m, 0);
   gemm(ctx, true, false, m, m, m, 1.0, Rmi.d(), m, 0, T1.d(), m, 0, 0.0, S.d(), m, 0);
   DBuf U(ctx.alloc, sizeof(double) * m * m), W(ctx.alloc, sizeof(double) * m * m);
+  // with the Dirichlet cut S is positive definite: S = L L^T (pivoted Cholesky, full rank)
+  // and the left singular vectors of L are the eigenvectors of S, sigma^2 its eigenvalues
+  // (Jacobi on L converges in about a third of the sweeps of Jacobi on S); a singular S
+  // keeps the Jacobi SVD of S itself, whose null vectors the fast diagonalisation needs
+  DBuf Lc(ctx.alloc, sizeof(double) * m * m);
+  const int k = pivoted_cholesky(ctx, S.d(), m, Lc.d(), 2.220446049250313e-16);
   e->lam = DBuf(ctx.plan_alloc, sizeof(double) * m);
   e->V = DBuf(ctx.plan_alloc, sizeof(double) * m * m);
   if (ctx.plan_stream && ctx.plan_stream != ctx.stream) {
@@ -144,8 +155,15 @@ static std::shared_ptr<EigenBasis> eigenbasis(Problem& P, int d) {
     TTIGA_HIP(hipStreamWaitEvent(ctx.stream, ev, 0));
     TTIGA_HIP(hipEventDestroy(ev));
   }
-  svd_small(ctx, S.d(), false, m, m, m, U.d(), e->lam.d(), W.d());
-  gemm(ctx, false, false, m, m, m, 1.0, Rmi.d(), m, 0, W.d(), m, 0, 0.0, e->V.d(), m, 0);
+  if (k == m) {
+    svd_small(ctx, Lc.d(), false, m, m, m, U.d(), e->lam.d(), nullptr, "jacobi_eig");
+    hipLaunchKernelGGL(k_square, dim3((m + 255) / 256), dim3(256), 0, ctx.stream, e->lam.d(), m);
+    TTIGA_HIP(hipGetLastError());
+    gemm(ctx, false, false, m, m, m, 1.0, Rmi.d(), m, 0, U.d(), m, 0, 0.0, e->V.d(), m, 0);
+  } else {
+    svd_small(ctx, S.d(), false, m, m, m, U.d(), e->lam.d(), W.d());
+    gemm(ctx, false, false, m, m, m, 1.0, Rmi.d(), m, 0, W.d(), m, 0, 0.0, e->V.d(), m, 0);
+  }
   double* h = ctx.host(2);
   TTIGA_HIP(hipMemcpyAsync(h, e->lam.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
   TTIGA_HIP(hipMemcpyAsync(h + 1, e->lam.d() + (m - 1), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
