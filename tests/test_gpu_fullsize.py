@@ -215,3 +215,88 @@ def test_fullsize_manufactured_solve(ctx):
     allowed = 10 * (pr.options.tt_eps + pr.options.rel_res_tol) * rms_u
     say("fullsize manufactured: RMS error", rms_err, "max", np.abs(uh - ue).max(), "allowed RMS", allowed)
     assert rms_err <= allowed
+
+
+@pytest.fixture(scope="module")
+def c3_assembled():
+    """The complex-geometry configuration at its full size: bumpy degree-3 NURBS cube (8^3 net,
+    Gaussian bumps, weights U[0.8, 1.2]), n = 512 per direction (1.3e8 DOF, 2036 Gauss points
+    per direction), TT eps 1e-6."""
+    from paper_2509_13224_amd import ttiga
+    say("fullsize C3 assembly")
+    c = ttiga.Context(workspace_bytes=64 << 30)
+    pr = W.c3_problem()
+    h = c.problem_create(pr, precond=1)
+    st = h.assemble()
+    say("fullsize C3 copy cores", st["compression_path"], st["rank_K"], st["min_detJ"])
+    out = (pr, st, h.tt(ttiga.WHICH_K), h.tt(ttiga.WHICH_F), [h.tt(ttiga.WHICH_FACTOR0 + f) for f in range(7)])
+    h.close()
+    return out
+
+
+def _factor_values(fac, idx):
+    got = np.zeros((7, len(idx[0])))
+    for f in range(7):
+        if fac[f] is None:
+            continue
+        for q in range(len(idx[0])):
+            v = np.ones((1,))
+            for d in range(3):
+                v = v @ fac[f][d][:, idx[d][q], :]
+            got[f, q] = v[0]
+    return got
+
+
+def test_c3_detj_and_factors(c3_assembled):
+    """min det J over all 8.4e9 Gauss points is positive and no larger than det J at any of 512
+    sampled points (oracle); the factor TTs at those points within 10 eps of their threshold
+    scale spread over the grid (RMS per point), as the compression guarantees."""
+    pr, st, _, _, fac = c3_assembled
+    nodes = [g[0] for g in geometry.gauss_grid(pr)]
+    rng = np.random.default_rng(13)
+    idx = [rng.integers(0, len(nodes[d]), size=512) for d in range(3)]
+    pts = np.stack([nodes[d][idx[d]] for d in range(3)], axis=1)
+    ref, detj = geometry.sample_factors_points(pr, pts)
+    assert 0.0 < st["min_detJ"] <= detj.min() * (1 + 1e-12)
+    got = _factor_values(fac, idx)
+    npts = float(np.prod([len(x) for x in nodes]))
+    norms = [ott.norm(fac[f]) if fac[f] is not None else 0.0 for f in range(7)]
+    scale = [max(norms[:6])] * 6 + [norms[6]]
+    for f in range(7):
+        rms = np.sqrt(np.mean((got[f] - ref[f]) ** 2))
+        allowed = 10 * pr.options.tt_eps * scale[f] / np.sqrt(npts)
+        say("fullsize C3 factor", f, "RMS diff", rms, "allowed", allowed)
+        assert rms <= allowed
+
+
+def test_c3_entries_within_bounds(c3_assembled):
+    """Sampled entries of K^TT and F^TT against their definition.  K_ab is linear in the six
+    metric factors and the sum of the nine terms is rounded at eps: |dK_ab| <= sum_ij
+    ||w d_i phi_a d_j phi_b||_2 * 10 eps max ||R|| + eps ||K^TT||; F as for the annulus."""
+    pr, st, K, F, fac = c3_assembled
+    p, n = pr.disc.degree, pr.disc.n_basis[0]
+    tabs = _tables(pr)
+    eps = pr.options.tt_eps
+    rnorm = max(ott.norm(fac[f]) for f in range(6) if fac[f] is not None)
+    fj_norm = ott.norm(fac[6])
+    k_norm = ott.norm([c.reshape(c.shape[0], -1, c.shape[-1]) for c in K])
+    worst_k = worst_f = 0.0
+    for a, b in _pairs(n, p, 12, 2025091303):
+        sub, vals = [], []
+        for d in range(3):
+            nodes, wts, B, D = tabs[d]
+            q = np.nonzero(((B[:, a[d]] != 0) | (D[:, a[d]] != 0)) & ((B[:, b[d]] != 0) | (D[:, b[d]] != 0)))[0]
+            sub.append((nodes[q], wts[q]))
+            vals.append((wts[q], B[q, a[d]], D[q, a[d]], B[q, b[d]], D[q, b[d]]))
+        w = np.einsum("i,j,k->ijk", vals[0][0], vals[1][0], vals[2][0])
+        g = [[np.einsum("i,j,k->ijk", *[vals[d][1 + 2 * s] if d != i else vals[d][2 + 2 * s] for d in range(3)])
+              for i in range(3)] for s in range(2)]
+        cs = sum(np.sqrt(np.sum((w * g[0][i] * g[1][j]) ** 2)) for i in range(3) for j in range(3))
+        rk, rf, csf = _reference_entries(pr, tabs, a, b)
+        dk = abs(_tt_matrix_entry(K, a, b, p) - rk)
+        df = abs(_tt_vector_entry(F, a) - rf)
+        bound_k = 10 * eps * rnorm * cs + eps * k_norm
+        bound_f = 10 * eps * fj_norm * csf
+        worst_k, worst_f = max(worst_k, dk / bound_k), max(worst_f, df / bound_f)
+        assert dk <= bound_k and df <= bound_f, (a, b, dk, bound_k, df, bound_f)
+    say("fullsize C3 entries: worst |dK| / bound", worst_k, "worst |dF| / bound", worst_f)
