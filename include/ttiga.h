@@ -257,6 +257,18 @@ int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view
 int ttiga_tt_matvec_lowp(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, int dtype,
                          ttiga_tt** out);
 
+/* Rounded product y = round(alpha K x + beta z, eps) without forming the product cores
+ * (the TT solve's residual and operator products when K x would be large, e.g. the
+ * complex-geometry configuration): a randomised rounding whose Gaussian TT sketch, of
+ * width sketch_rank + 10 widened by 12 while the rounded rank saturates it, is contracted
+ * through the K and x cores one at a time, followed by the deterministic rounding
+ * (Oseledets 2011) of the small sketched train at relative eps.  z may be NULL (then beta
+ * is ignored); its mode sizes must equal x's.  The sketch is drawn from the context's
+ * counter exactly as the rounding of an explicit train draws it.  Result in a library-owned
+ * TT (*out, free with ttiga_tt_free); E_ARG on size mismatches. */
+int ttiga_tt_matvec_round(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, double alpha,
+                          const ttiga_tt_view* z, double beta, double eps, int sketch_rank, ttiga_tt** out);
+
 /* Standalone TT-rounding (Oseledets 2011, used after each summation of
  * Section 4.2.1): y = round(x, eps) with per-unfolding threshold
  * eps * ||x||_F / sqrt(2). */

@@ -498,6 +498,42 @@ int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view
   });
 }
 
+int ttiga_tt_matvec_round(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, double alpha,
+                          const ttiga_tt_view* z, double beta, double eps, int sketch_rank, ttiga_tt** out) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && K && x && out, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(K->p >= 0 && K->p <= 16, TTIGA_E_ARG, "bad band half-width");
+    TTIGA_CHECK(eps > 0.0 && eps < 1.0, TTIGA_E_ARG, "eps must lie in (0, 1)");
+    TTIGA_CHECK(sketch_rank >= 1, TTIGA_E_ARG, "sketch_rank must be positive");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    ttiga_tt_view kv{};
+    const int band = 2 * K->p + 1;
+    for (int k = 0; k < 3; ++k) {
+      TTIGA_CHECK(K->n[k] == x->n[k], TTIGA_E_ARG, "matvec: mode sizes differ");
+      if (z) TTIGA_CHECK(z->n[k] == x->n[k], TTIGA_E_ARG, "z: mode sizes differ");
+      kv.n[k] = K->n[k] * band;
+      kv.core[k] = K->core[k];
+    }
+    for (int k = 0; k < 4; ++k) kv.r[k] = K->r[k];
+    TT Kt, xt, zt;
+    tt_from_view(c, kv, Kt);
+    tt_from_view(c, *x, xt);
+    if (z) tt_from_view(c, *z, zt);
+    auto* res = new ttiga_tt{&c, TT()};
+    try {
+      int hint = sketch_rank;
+      tt_matvec_round(c, Kt, K->p, xt, alpha, z ? &zt : nullptr, beta, eps, 0, hint, res->t);
+      c.sync();
+    } catch (...) {
+      delete res;
+      throw;
+    }
+    *out = res;
+    ctx_retain(&c);
+  });
+}
+
 int ttiga_tt_matvec_lowp(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, int dtype,
                          ttiga_tt** out) {
   return guard([&] {

@@ -278,6 +278,16 @@ void tt_round(Context& ctx, TT& x, double eps_rel, double delta_abs, int max_ran
 // hint + 10 (randomised TT-rounding) and then truncates deterministically; hint
 // is updated to the resulting rank.
 void tt_round_auto(Context& ctx, TT& x, double eps_rel, int max_rank, int& hint);
+// out[0..n) = standard normal numbers from the context's sketch counter (advanced by one).
+void gaussian_fill(Context& ctx, double* out, long n);
+// Randomised rounding of y = alpha K x + beta z (K banded with half-bandwidth p, z optional)
+// at relative eps without forming the product cores (sketch width hint + 10, widened by 12
+// while the rounded rank saturates it; hint receives the rank).  The sketch is drawn as
+// tt_round_auto draws it for an explicit train.
+void tt_matvec_round(Context& ctx, const TT& K, int p, const TT& x, double alpha, const TT* z, double beta,
+                     double eps_rel, int max_rank, int& hint, TT& out);
+// Bytes of the explicit product cores of K x.
+size_t matvec_product_bytes(const TT& K, const TT& x);
 // out core d of x multiplied along mode d by op(Mat) (n x n row-major).
 void tt_mode_product(Context& ctx, TT& x, int d, const double* Mat, bool trans);
 void tt_axpby(Context& ctx, double alpha, const TT& x, double beta, const TT& y, TT& out);

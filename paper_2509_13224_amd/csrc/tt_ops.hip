@@ -196,6 +196,14 @@ __device__ inline uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+__global__ void k_gaussian(double* __restrict__ O, long n, uint64_t seed);
+
+void gaussian_fill(Context& ctx, double* out, long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gaussian, dim3(grid_for(n)), dim3(256), 0, ctx.stream, out, n, ++ctx.rng_counter);
+  TTIGA_HIP(hipGetLastError());
+}
+
 __global__ void k_gaussian(double* __restrict__ O, long n, uint64_t seed) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
        e += (long)gridDim.x * blockDim.x) {
@@ -782,11 +790,8 @@ void tt_eval_points(Context& ctx, const TT& x, long count, const int* i0, const 
 static void tt_sketch_project(Context& ctx, const TT& x, int l1, int l2, TT& y) {
   const int n0 = x.n[0], n1 = x.n[1], n2 = x.n[2], R1 = x.r[1], R2 = x.r[2];
   DBuf O2(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2), O3(ctx.alloc, sizeof(double) * (size_t)l2 * n2);
-  hipLaunchKernelGGL(k_gaussian, dim3(grid_for((long)l1 * n1 * l2)), dim3(256), 0, ctx.stream, O2.d(),
-                     (long)l1 * n1 * l2, ++ctx.rng_counter);
-  hipLaunchKernelGGL(k_gaussian, dim3(grid_for((long)l2 * n2)), dim3(256), 0, ctx.stream, O3.d(),
-                     (long)l2 * n2, ++ctx.rng_counter);
-  TTIGA_HIP(hipGetLastError());
+  gaussian_fill(ctx, O2.d(), (long)l1 * n1 * l2);
+  gaussian_fill(ctx, O3.d(), (long)l2 * n2);
   DBuf W3(ctx.alloc, sizeof(double) * (size_t)R2 * l2);
   gemm(ctx, false, true, R2, l2, n2, 1.0, x.c[2].d(), n2, 0, O3.d(), n2, 0, 0.0, W3.d(), l2, 0);
   DBuf T(ctx.alloc, sizeof(double) * (size_t)R1 * n1 * l2);

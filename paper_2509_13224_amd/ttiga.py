@@ -32,7 +32,7 @@ EXPORTED = (
     "ttiga_version", "ttiga_create", "ttiga_destroy", "ttiga_set_workspace", "ttiga_last_error",
     "ttiga_validate", "ttiga_problem_create", "ttiga_problem_destroy", "ttiga_assemble", "ttiga_solve",
     "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
-    "ttiga_sample_factors", "ttiga_tt_matvec", "ttiga_tt_round", "ttiga_tt_dot",
+    "ttiga_sample_factors", "ttiga_tt_matvec", "ttiga_tt_matvec_round", "ttiga_tt_round", "ttiga_tt_dot",
     "ttiga_tt_compress", "ttiga_tt_matvec_lowp", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free", "ttiga_profile",
     "ttiga_profile_read", "ttiga_tt_view_of", "ttiga_footprint", "ttiga_solve_batch",
     "ttiga_server_create", "ttiga_server_submit", "ttiga_server_poll", "ttiga_server_solution",
@@ -165,6 +165,9 @@ def load(path=LIB_PATH):
         "ttiga_tt_matvec_lowp": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView), ctypes.c_int,
                                                 ctypes.POINTER(vp)]),
         "ttiga_tt_round": (ctypes.c_int, [vp, ctypes.POINTER(TTView), ctypes.c_double, ctypes.POINTER(vp)]),
+        "ttiga_tt_matvec_round": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView), ctypes.c_double,
+                                                 ctypes.POINTER(TTView), ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                 ctypes.POINTER(vp)]),
         "ttiga_tt_dot": (ctypes.c_int, [vp, ctypes.POINTER(TTView), ctypes.POINTER(TTView), c_dbl_p]),
         "ttiga_tt_compress": (ctypes.c_int, [vp, vp, c_int_p, ctypes.c_double, ctypes.POINTER(vp)]),
         "ttiga_tt_info": (ctypes.c_int, [vp, c_int_p, c_int_p]),
@@ -333,6 +336,25 @@ class Context:
                                                            ctypes.byref(h)))
         else:
             _check(self.lib, self.lib.ttiga_tt_matvec(self.h, ctypes.byref(kv), ctypes.byref(xv), ctypes.byref(h)))
+        return self._take(h)
+
+    def tt_matvec_round(self, K_cores_dev, p, x_cores_dev, eps, alpha=1.0, z_cores_dev=None, beta=0.0,
+                        sketch_rank=8):
+        """round(alpha K x + beta z, eps) without forming K x (ttiga_tt_matvec_round)."""
+        kv = TTMView()
+        kv.p = p
+        rK = [1, K_cores_dev[0].shape[-1], K_cores_dev[1].shape[-1], 1]
+        for k in range(3):
+            kv.n[k] = K_cores_dev[k].shape[1]
+            kv.core[k] = K_cores_dev[k].data_ptr()
+        for k in range(4):
+            kv.r[k] = rK[k]
+        xv = self._view(x_cores_dev)
+        zp = ctypes.byref(self._view(z_cores_dev)) if z_cores_dev is not None else None
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.ttiga_tt_matvec_round(self.h, ctypes.byref(kv), ctypes.byref(xv), ctypes.c_double(alpha),
+                                                        zp, ctypes.c_double(beta), ctypes.c_double(eps),
+                                                        ctypes.c_int(sketch_rank), ctypes.byref(h)))
         return self._take(h)
 
     def tt_round(self, cores_dev, eps):

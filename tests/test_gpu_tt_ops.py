@@ -125,3 +125,32 @@ def test_compress_rank_deficient_geometry_factor(ctx):
         cores = ctx.tt_compress(torch.from_numpy(np.ascontiguousarray(fj)).cuda(), delta)
         assert np.linalg.norm(tt.full(cores) - fj) <= 1.5 * eps * np.linalg.norm(fj)
         assert tt.ranks(cores) == tt.ranks(tt.tt_svd(fj, delta=delta))
+
+
+@pytest.mark.parametrize("sketch_rank", [64, 4])
+@pytest.mark.parametrize("shape,rK,rx,rz,p,alpha,beta", [
+    ((13, 9, 11), (3, 2), (4, 5), None, 2, 1.0, 0.0),
+    ((17, 16, 15), (5, 4), (7, 6), (3, 4), 3, -1.0, 1.0),  # the residual form b - K x
+    ((40, 33, 70), (6, 5), (9, 8), (4, 3), 3, 2.0, -0.5),  # several tiles and ragged tails
+])
+def test_matvec_round_matches_oracle(ctx, shape, rK, rx, rz, p, alpha, beta, sketch_rank):
+    """round(alpha K x + beta z, eps) without the product cores, against the oracle's exact
+    alpha K x + beta z.  The random trains have no rank decay, so the rounded rank is the
+    product rank: a sketch of width 64 + 10 covers it at once, one of width 4 + 10 has to be
+    widened until it does; either way only the eps-rounding separates the result from the
+    exact vector (<= eps ||y|| per the rounding bound; 10 eps allowed)."""
+    say("matvec_round", shape, rK, rx, rz, p, alpha, beta, sketch_rank)
+    rng = np.random.default_rng(sum(shape) + 7 * p + sketch_rank)
+    K = rand_banded(shape, rK, p, rng)
+    x = rand_tt(shape, rx, rng)
+    z = rand_tt(shape, rz, rng) if rz else None
+    eps = 1e-10
+    y = ctx.tt_matvec_round(to_dev(K), p, to_dev(x), eps, alpha=alpha,
+                            z_cores_dev=to_dev(z) if z is not None else None, beta=beta, sketch_rank=sketch_rank)
+    ref = alpha * (tt.mat_full(banded_to_dense_cores(K, p)) @ tt.full(x).ravel())
+    if z is not None:
+        ref = ref + beta * tt.full(z).ravel()
+    got = tt.full(y).ravel()
+    assert np.linalg.norm(got - ref) <= 10 * eps * np.linalg.norm(ref)
+    full_rank = [1, rK[0] * rx[0] + (rz[0] if rz else 0), rK[1] * rx[1] + (rz[1] if rz else 0), 1]
+    assert all(a <= b for a, b in zip(tt.ranks(y), full_rank))
