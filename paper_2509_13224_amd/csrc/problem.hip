@@ -684,9 +684,18 @@ void Problem::solve(ttiga_solve_stats* st) {
 
 using Matvec = std::function<void(const TT&, TT&)>;
 
-// ||b - K x|| / ||b||, with the residual train b - K x rounded at eps_x (replaces r).
+// Products K x whose explicit cores (ranks rK rx) would exceed this many bytes are rounded
+// as they are formed (tt_matvec_round) instead of being stored and rounded afterwards.
+static constexpr size_t kFusedProductBytes = size_t(1) << 30;
+
+// ||b - K x|| / ||b||, with the residual train b - K x rounded at eps_x (replaces r).  With
+// Kf given and a large product the residual train is formed already rounded.
 static double true_residual(Context& c, const Matvec& mv, const TT& b, const TT& x, double nb,
-                            double eps_x, int max_rank, TT& r, int& hint) {
+                            double eps_x, int max_rank, TT& r, int& hint, const TT* Kf = nullptr, int p = 0) {
+  if (Kf && matvec_product_bytes(*Kf, x) > kFusedProductBytes) {
+    tt_matvec_round(c, *Kf, p, x, -1.0, &b, 1.0, eps_x, max_rank, hint, r);
+    return std::sqrt(std::max(tt_dot_sync(c, r, r), 0.0)) / nb;
+  }
   TT Kx, tr;
   mv(x, Kx);
   tt_axpby(c, 1.0, b, -1.0, Kx, tr);
@@ -806,13 +815,21 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
   pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
   tt_copy(c, z, pdir);
   double rho = tt_dot_sync(c, r, z);
+  // a product too large to store is rounded as it is formed, with the FP64 operator (also
+  // inside a mixed-precision refinement, whose low-precision product forms the cores)
+  const TT* Kf = &KII;
   PcgRun o;
   while (o.it < max_iter) {
     ++o.it;
     TT q;
-    mv(pdir, q);
-    seen(q);
-    tt_round_auto(c, q, eps, opts.max_rank, hq);
+    if (Kf && matvec_product_bytes(*Kf, pdir) > kFusedProductBytes) {
+      tt_matvec_round(c, *Kf, p, pdir, 1.0, nullptr, 0.0, eps, opts.max_rank, hq, q);
+      seen(q);
+    } else {
+      mv(pdir, q);
+      seen(q);
+      tt_round_auto(c, q, eps, opts.max_rank, hq);
+    }
     const double alpha = rho / tt_dot_sync(c, pdir, q);
     TT xn, rn;
     tt_axpby(c, 1.0, x, alpha, pdir, xn);
@@ -825,7 +842,7 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
     r = std::move(rn);
     bool replaced = false;
     if (o.it % 10 == 0) {
-      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr);
+      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr, Kf, p);
       replaced = true;
     }
     pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
@@ -837,7 +854,7 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
     };
     o.pres = err_est();
     if (o.pres <= tol && !replaced) {
-      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr);
+      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr, Kf, p);
       pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
       rho_new = tt_dot_sync(c, r, z);
       o.pres = err_est();
@@ -863,7 +880,7 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
   }
   if (!o.conv) {
     TT tmp;
-    o.true_res = true_residual(c, mv, b, x, nb, eps_x, 0, tmp, hr);
+    o.true_res = true_residual(c, mv, b, x, nb, eps_x, 0, tmp, hr, Kf, p);
   }
   return o;
 }

@@ -221,15 +221,23 @@ def test_fullsize_manufactured_solve(ctx):
 def c3_assembled():
     """The complex-geometry configuration at its full size: bumpy degree-3 NURBS cube (8^3 net,
     Gaussian bumps, weights U[0.8, 1.2]), n = 512 per direction (1.3e8 DOF, 2036 Gauss points
-    per direction), TT eps 1e-6."""
+    per direction), TT eps 1e-6; assembled, then solved in FP64 (preconditioned TT-CG whose
+    operator products are rounded as they are formed)."""
     from paper_2509_13224_amd import ttiga
+    from workloads.problem import PREC_FP64
     say("fullsize C3 assembly")
-    c = ttiga.Context(workspace_bytes=64 << 30)
+    c = ttiga.Context(workspace_bytes=120 << 30)
     pr = W.c3_problem()
+    pr.options.precision = PREC_FP64
     h = c.problem_create(pr, precond=1)
     st = h.assemble()
     say("fullsize C3 copy cores", st["compression_path"], st["rank_K"], st["min_detJ"])
-    out = (pr, st, h.tt(ttiga.WHICH_K), h.tt(ttiga.WHICH_F), [h.tt(ttiga.WHICH_FACTOR0 + f) for f in range(7)])
+    out = dict(pr=pr, st=st, K=h.tt(ttiga.WHICH_K), F=h.tt(ttiga.WHICH_F),
+               fac=[h.tt(ttiga.WHICH_FACTOR0 + f) for f in range(7)], rhs=h.tt(ttiga.WHICH_RHS))
+    say("fullsize C3 solve (about 40 s)")
+    out["solve"] = h.solve()
+    out["u"] = h.solution()
+    say("fullsize C3 solved", out["solve"]["iterations"], out["solve"]["rank_u"], out["solve"]["rel_res"])
     h.close()
     return out
 
@@ -251,7 +259,7 @@ def test_c3_detj_and_factors(c3_assembled):
     """min det J over all 8.4e9 Gauss points is positive and no larger than det J at any of 512
     sampled points (oracle); the factor TTs at those points within 10 eps of their threshold
     scale spread over the grid (RMS per point), as the compression guarantees."""
-    pr, st, _, _, fac = c3_assembled
+    pr, st, fac = c3_assembled["pr"], c3_assembled["st"], c3_assembled["fac"]
     nodes = [g[0] for g in geometry.gauss_grid(pr)]
     rng = np.random.default_rng(13)
     idx = [rng.integers(0, len(nodes[d]), size=512) for d in range(3)]
@@ -273,7 +281,7 @@ def test_c3_entries_within_bounds(c3_assembled):
     """Sampled entries of K^TT and F^TT against their definition.  K_ab is linear in the six
     metric factors and the sum of the nine terms is rounded at eps: |dK_ab| <= sum_ij
     ||w d_i phi_a d_j phi_b||_2 * 10 eps max ||R|| + eps ||K^TT||; F as for the annulus."""
-    pr, st, K, F, fac = c3_assembled
+    pr, K, F, fac = c3_assembled["pr"], c3_assembled["K"], c3_assembled["F"], c3_assembled["fac"]
     p, n = pr.disc.degree, pr.disc.n_basis[0]
     tabs = _tables(pr)
     eps = pr.options.tt_eps
@@ -300,3 +308,63 @@ def test_c3_entries_within_bounds(c3_assembled):
         worst_k, worst_f = max(worst_k, dk / bound_k), max(worst_f, df / bound_f)
         assert dk <= bound_k and df <= bound_f, (a, b, dk, bound_k, df, bound_f)
     say("fullsize C3 entries: worst |dK| / bound", worst_k, "worst |dF| / bound", worst_f)
+
+
+def test_c3_solution_residual_entries(c3_assembled):
+    """The full-size complex-geometry solve against the oracle's discrete system: at sampled
+    interior rows a the oracle forms r_a = F_a - sum_b K_ab u_b from the definition (the 7^3
+    neighbouring entries of row a as Gauss sums over the support of a) and the GPU solution's
+    coefficients u_b.  Every entry of a vector is bounded by its 2-norm, so |r_a| may not exceed
+    the solver's reported ||F_I - K_II u|| (times 2) plus what separates the exact entries from
+    the eps-accurate K^TT and F^TT (10 eps of the row's absolute sum)."""
+    pr, st, sol, u = c3_assembled["pr"], c3_assembled["st"], c3_assembled["solve"], c3_assembled["u"]
+    p, n = pr.disc.degree, pr.disc.n_basis[0]
+    eps = pr.options.tt_eps
+    assert sol["status"] == 0 and sol["rel_pres"] <= pr.options.rel_res_tol
+    tabs = _tables(pr)
+    from oracle import tt_iga
+    sl = tt_iga.interior_slices(pr)
+    lo = [s.start for s in sl]
+    rhs_norm = ott.norm(c3_assembled["rhs"])
+    res_norm = sol["rel_res"] * rhs_norm
+    rng = np.random.default_rng(17)
+    worst = 0.0
+    for _ in range(4):
+        a = tuple(int(rng.integers(s.start + p, s.stop - p)) for s in sl)
+        sub, Ba, Da = [], [], []
+        nb = [np.arange(a[d] - p, a[d] + p + 1) for d in range(3)]
+        Bb, Db = [], []
+        for d in range(3):
+            nodes, wts, B, D = tabs[d]
+            q = np.nonzero(B[:, a[d]] != 0)[0]
+            sub.append((nodes[q], wts[q]))
+            Ba.append(B[q, a[d]])
+            Da.append(D[q, a[d]])
+            Bb.append(B[np.ix_(q, nb[d])])
+            Db.append(D[np.ix_(q, nb[d])])
+        fac, _ = geometry.sample_factors_grid(pr, grid=sub)
+        R = np.zeros((3, 3) + fac.shape[1:])
+        for idx, (i, j) in enumerate(geometry.R_PAIRS):
+            R[i, j] = fac[idx]
+            R[j, i] = fac[idx]
+        w = np.einsum("i,j,k->ijk", sub[0][1], sub[1][1], sub[2][1])
+        ga = [np.einsum("i,j,k->ijk", *[Da[d] if d == i else Ba[d] for d in range(3)]) for i in range(3)]
+        Krow = np.zeros((2 * p + 1,) * 3)
+        for i in range(3):
+            for j in range(3):
+                g = w * ga[i] * R[i, j]
+                mats = [Db[d] if d == j else Bb[d] for d in range(3)]
+                Krow += np.einsum("xyz,xa,yb,zc->abc", g, *mats)
+        F_a = np.sum(np.einsum("i,j,k->ijk", *[sub[d][1] * Ba[d] for d in range(3)]) * fac[6])
+        ub = np.zeros((2 * p + 1,) * 3)
+        for i0, b0 in enumerate(nb[0]):
+            for i1, b1 in enumerate(nb[1]):
+                for i2, b2 in enumerate(nb[2]):
+                    v = u[0][:, b0 - lo[0], :] @ u[1][:, b1 - lo[1], :] @ u[2][:, b2 - lo[2], :]
+                    ub[i0, i1, i2] = v[0, 0]
+        r_a = F_a - np.sum(Krow * ub)
+        bound = 2 * res_norm + 10 * eps * (abs(F_a) + np.sum(np.abs(Krow * ub)))
+        worst = max(worst, abs(r_a) / bound)
+        say("fullsize C3 residual row", a, "r_a", r_a, "bound", bound)
+        assert abs(r_a) <= bound
+    say("fullsize C3 residual entries: worst |r_a| / bound", worst)

@@ -57,7 +57,8 @@ def c3_problem(n=512, p=3, eps=1e-6, tol=1e-7, geom_seed=C3_GEOM_SEED,
         disc=Discretization(degree=p, n_basis=(n, n, n), n_gauss=p + 1),
         source=fourier_source(geo, source_seed),
         dirichlet=_all_zero(),
-        options=Options(tt_eps=eps, rel_res_tol=tol, max_iter=400, precision=precision),
+        # the products of the solve reach ranks near 270 before rounding settles them
+        options=Options(tt_eps=eps, rel_res_tol=tol, max_iter=400, max_rank=1024, precision=precision),
     )
 
 
