@@ -551,6 +551,166 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
   }
 }
 
+// col[q][i] -= sum_k v[k][i] X[4 k + q] for q < NQ and the rows i = i0, i0 + 64, ... < nr of
+// one lane: the update of a panel of four reflectors in compact WY form.
+template <int NQ>
+__device__ inline void update_panel(double* const* col, const double* X, const double* const* v, int i0, int nr) {
+  for (int i = i0; i < nr; i += 64) {
+    double vv[4], y[NQ];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) vv[k] = v[k][i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) y[q] = col[q][i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = y[q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s -= vv[k] * X[4 * k + q];
+      col[q][i] = s;
+    }
+  }
+}
+
+__device__ inline void update_panel_n(int nq, double* const* col, const double* X, const double* const* v, int i0,
+                                      int nr) {
+  switch (nq) {
+    case 1: update_panel<1>(col, X, v, i0, nr); break;
+    case 2: update_panel<2>(col, X, v, i0, nr); break;
+    case 3: update_panel<3>(col, X, v, i0, nr); break;
+    default: update_panel<4>(col, X, v, i0, nr); break;
+  }
+}
+
+// The same product as k_hh_apply with the reflectors taken four at a time in compact WY form
+// (Schreiber and Van Loan): H_j0 ... H_j0+3 = I - V_p T_p V_p^T with T_p upper triangular,
+// T_mm = tau_m and T[0:m, m] = -tau_m T[0:m, 0:m] (V_p^T V_p)[0:m, m].  A panel costs each
+// batch of four owned columns one round of 4 x 4 dot products (rows from the panel's first diagonal on: the
+// reflectors vanish above their diagonal), one reduction, a 4 x 4 triangular product and one
+// fused update, instead of four dependent reflector steps.  The panel factors are formed
+// first, one wave per panel, into Tg (16 doubles per panel, per block), then copied into the
+// LDS that held tau (so c <= 256), where the update reads them entry by entry.  Panel columns
+// past c alias the panel's first column with tau 0, which T turns into zero updates.
+template <bool kLds, bool kVLds>
+__global__ __launch_bounds__(1024) void k_hh_apply_wy(int m, int c, int nb, int ldw,
+                                                      const double* __restrict__ V,
+                                                      const double* __restrict__ tau,
+                                                      const double* __restrict__ Qtop,
+                                                      double* __restrict__ Qout,
+                                                      double* __restrict__ gwork,
+                                                      double* __restrict__ Tg) {
+  extern __shared__ double smem[];
+  __shared__ double s_tau[1024];
+  const int blk = blockIdx.x;
+  const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
+  const int nr = (int)(r1 - r0);
+  const int tid = threadIdx.x, lane = tid & 63, nwaves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* Y = kLds ? smem : gwork + (long)blk * ldw * c;
+  const double* Vg = V + r0 * c;
+  double* Vs = smem + (long)ldw * c;
+  if (kVLds)
+    for (long e = tid; e < (long)nr * c; e += blockDim.x) Vs[e] = Vg[e];
+  const double* Vb = kVLds ? Vs : Vg;
+  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
+    const int k = e / nr, i = e % nr;
+    double v = 0.0;
+    if (i < c) v = Qtop ? Qtop[((long)blk * c + i) * c + k] : (i == k ? 1.0 : 0.0);
+    Y[(long)k * ldw + i] = v;
+  }
+  for (int j = tid; j < c; j += blockDim.x) s_tau[j] = tau[(long)blk * c + j];
+  __syncthreads();
+  const int np = (c + 3) / 4;
+  double* Tb = Tg + (long)blk * np * 16;
+  // panel factors
+  for (int P = wave; P < np; P += nwaves) {
+    const int j0 = 4 * P, bp = min(4, c - j0);
+    const double* v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = Vb + (long)(j0 + (k < bp ? k : 0)) * nr;
+    double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+    for (int i = j0 + lane; i < nr; i += 64) {
+      const double x0 = v[0][i], x1 = v[1][i], x2 = v[2][i], x3 = v[3][i];
+      g[0] += x0 * x1;
+      g[1] += x0 * x2;
+      g[2] += x0 * x3;
+      g[3] += x1 * x2;
+      g[4] += x1 * x3;
+      g[5] += x2 * x3;
+    }
+    wave_sum8(g);
+    if (lane == 0) {
+      double tp[4], G[4][4] = {{0}}, T[4][4] = {{0}};
+      for (int k = 0; k < 4; ++k) tp[k] = k < bp ? s_tau[j0 + k] : 0.0;
+      G[0][1] = g[0];
+      G[0][2] = g[1];
+      G[0][3] = g[2];
+      G[1][2] = g[3];
+      G[1][3] = g[4];
+      G[2][3] = g[5];
+      for (int mm = 0; mm < 4; ++mm) {
+        T[mm][mm] = tp[mm];
+        for (int k = 0; k < mm; ++k) {
+          double s = 0.0;
+          for (int l = k; l < mm; ++l) s += T[k][l] * G[l][mm];
+          T[k][mm] = -tp[mm] * s;
+        }
+      }
+      for (int e = 0; e < 16; ++e) Tb[(long)P * 16 + e] = T[e / 4][e % 4];
+    }
+  }
+  __syncthreads();
+  double* Ts = s_tau;  // tau is no longer needed: the panel factors take its place
+  for (int e = tid; e < np * 16; e += blockDim.x) Ts[e] = Tb[e];
+  __syncthreads();
+  // panels from the last to the first on each wave's owned columns, four at a time (sixteen
+  // accumulators per lane keep the kernel within the registers of a 1024-thread block)
+  for (int kb = wave; kb < c; kb += 4 * nwaves) {
+    const int nq = min(4, (c - kb + nwaves - 1) / nwaves);
+    double* col[4];  // columns past c alias the batch's first (read, never written)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) col[q] = Y + (long)(kb + (q < nq ? q : 0) * nwaves) * ldw;
+    for (int P = np - 1; P >= 0; --P) {
+      const int j0 = 4 * P, bp = min(4, c - j0);
+      const double* v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = Vb + (long)(j0 + (k < bp ? k : 0)) * nr;
+      double w[16];  // w[4 k + q] = v_k . col_q
+#pragma unroll
+      for (int e = 0; e < 16; ++e) w[e] = 0.0;
+      for (int i = j0 + lane; i < nr; i += 64) {
+        double vv[4], x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) vv[k] = v[k][i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = col[q][i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[4 * k + q] += vv[k] * x[q];
+      }
+      wave_sum8(w);
+      wave_sum8(w + 8);
+      // X = T W in place (T upper triangular: row k uses rows k.. of W)
+      const double* T = Ts + P * 16;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double s = 0.0;
+#pragma unroll
+          for (int l = k; l < 4; ++l) s += T[k * 4 + l] * w[4 * l + q];
+          w[4 * k + q] = s;
+        }
+      update_panel_n(nq, col, w, v, j0 + lane, nr);
+    }
+  }
+  __syncthreads();
+  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
+    const int i = e / c, k = e % c;
+    Qout[(r0 + i) * c + k] = Y[(long)k * ldw + i];
+  }
+}
+
 template <int kMode>
 __global__ void k_jacobi_svd(int m, int c, const double* __restrict__ A, int transA, long lda,
                              double* __restrict__ gwork, double* __restrict__ U, double* __restrict__ S,
@@ -584,6 +744,10 @@ static int lds_doubles() {
           hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
           hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply_wy<true, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply_wy<true, false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
           hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_svd<2>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kJacobiStatic) ==
@@ -669,7 +833,12 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     ld = c;
     mm = last.nb * c;
   }
-  // thin Q, top-down
+  // thin Q, top-down: reflectors four at a time in compact WY form (TTIGA_TSQR_APPLY=reflector
+  // selects the one-reflector-at-a-time kernel, for measurements)
+  static const bool per_reflector = [] {
+    const char* e = std::getenv("TTIGA_TSQR_APPLY");
+    return e && std::strcmp(e, "reflector") == 0;
+  }();
   DBuf qprev;
   for (int l = (int)lv.size() - 1; l >= 0; --l) {
     Level& L = lv[l];
@@ -678,15 +847,28 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     const size_t shm = L.lds ? (L.v_lds ? 2 : 1) * sizeof(double) * (size_t)L.ldw * c : 0;
     ProfScope prof(ctx, "tsqr_apply", 4.0 * c * c * (double)L.m - 2.0 * c * c * c * L.nb,
                    8.0 * (2.0 * L.m * c + (double)L.nb * c * c), c);
-    if (L.v_lds)
-      hipLaunchKernelGGL((k_hh_apply<true, true>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, L.m, c,
-                         L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
-    else if (L.lds)
-      hipLaunchKernelGGL((k_hh_apply<true, false>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, L.m, c,
-                         L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
-    else
-      hipLaunchKernelGGL((k_hh_apply<false, false>), dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, L.m, c,
-                         L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, L.work.d());
+    if (per_reflector || c > 256) {
+      if (L.v_lds)
+        hipLaunchKernelGGL((k_hh_apply<true, true>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream,
+                           L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
+      else if (L.lds)
+        hipLaunchKernelGGL((k_hh_apply<true, false>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream,
+                           L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
+      else
+        hipLaunchKernelGGL((k_hh_apply<false, false>), dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, L.m, c,
+                           L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, L.work.d());
+    } else {
+      DBuf Tg(ctx.alloc, sizeof(double) * (size_t)L.nb * ((c + 3) / 4) * 16);
+      if (L.v_lds)
+        hipLaunchKernelGGL((k_hh_apply_wy<true, true>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm),
+                           ctx.stream, L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr, Tg.d());
+      else if (L.lds)
+        hipLaunchKernelGGL((k_hh_apply_wy<true, false>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm),
+                           ctx.stream, L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr, Tg.d());
+      else
+        hipLaunchKernelGGL((k_hh_apply_wy<false, false>), dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, L.m, c,
+                           L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, L.work.d(), Tg.d());
+    }
     TTIGA_HIP(hipGetLastError());
     qprev = std::move(qout);
   }
