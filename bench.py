@@ -54,9 +54,9 @@ KERNEL_BOUND = {
 SERVE_SEED = 2025_0913_05
 # HBM bytes per dispatch of a kernel class measured by rocprofv3 --pmc on `bench.py
 # --single-only` (FETCH_SIZE scaled by the 1 GiB copy calibration, WRITE_SIZE), in KiB;
-# profiles/tsqr_apply_annulus_n256.md has the commands.  Valid only for the kernel code
+# profiles/tsqr_factor_annulus_n256.md has the commands.  Valid only for the kernel code
 # it was taken on.
-MEASURED_TRAFFIC_KIB = {"tsqr_apply": (1956.9, 2940.4)}
+MEASURED_TRAFFIC_KIB = {"tsqr_factor": (1706.7, 2786.9)}
 
 
 def roofline_entry(name, st):
