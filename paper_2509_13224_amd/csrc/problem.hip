@@ -736,9 +736,14 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
   while (it < opts.max_iter) {
     ++it;
     TT q;
-    tt_matvec_banded(c, KII, p, pdir, q);
-    seen(q);
-    tt_round_auto(c, q, eps, opts.max_rank, hq);
+    if (matvec_product_bytes(KII, pdir) > kFusedProductBytes) {
+      tt_matvec_round(c, KII, p, pdir, 1.0, nullptr, 0.0, eps, opts.max_rank, hq, q);
+      seen(q);
+    } else {
+      tt_matvec_banded(c, KII, p, pdir, q);
+      seen(q);
+      tt_round_auto(c, q, eps, opts.max_rank, hq);
+    }
     const double alpha = rho / tt_dot_sync(c, pdir, q);
     TT xn, rn;
     tt_axpby(c, 1.0, u, alpha, pdir, xn);
@@ -749,7 +754,7 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
     r = std::move(rn);
     const double est = std::sqrt(std::max(tt_dot_sync(c, r, r), 0.0)) / nb;
     if (it % 10 == 0 || est <= tol) {
-      true_res = true_residual(c, mv, rhs, u, nb, eps_x, opts.max_rank, r, hr);
+      true_res = true_residual(c, mv, rhs, u, nb, eps_x, opts.max_rank, r, hr, &KII, p);
       if (true_res <= tol) {
         conv = true;
         break;
@@ -766,7 +771,7 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
   }
   if (!conv) {
     TT tmp;
-    true_res = true_residual(c, mv, rhs, u, nb, eps_x, 0, tmp, hr);
+    true_res = true_residual(c, mv, rhs, u, nb, eps_x, 0, tmp, hr, &KII, p);
   }
   s.iterations = it;
   s.rel_res = true_res;
@@ -938,7 +943,7 @@ void Problem::solve_mixed(ttiga_solve_stats& s) {
     tt_axpby(c, 1.0, u, 1.0, d, un);
     tt_round_auto(c, un, eps_x, opts.max_rank, hx);
     u = std::move(un);
-    true_res = true_residual(c, mv, rhs, u, nb, eps_r, opts.max_rank, r, hr);
+    true_res = true_residual(c, mv, rhs, u, nb, eps_r, opts.max_rank, r, hr, &KII, p);
     TT z;
     pc.apply(c, r, z, 1e-2, opts.max_rank, hz);
     const double zz = tt_dot_sync(c, z, z), uu = tt_dot_sync(c, u, u);

@@ -11,6 +11,8 @@
 // The sketch matrices are drawn exactly as the rounding of an explicit train draws them, so
 // both give the same result up to the order of the floating-point sums.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 
 #include "runtime.hpp"
 
@@ -127,6 +129,16 @@ void permute4(Context& ctx, const double* in, long d0, long d1, long d2, long d3
   TTIGA_HIP(hipGetLastError());
 }
 
+// Rows of the middle mode contracted together: the band products run over blocks of i so
+// that their intermediates (bytes_per_row each row) stay within a fixed budget, 4 GiB unless
+// TTIGA_MATVEC_BLOCK_BYTES sets another, however large the ranks are.
+int middle_block(size_t bytes_per_row, int n1, int p) {
+  size_t budget = size_t(4) << 30;
+  if (const char* e = std::getenv("TTIGA_MATVEC_BLOCK_BYTES")) budget = std::max<size_t>(1, std::strtoull(e, nullptr, 10));
+  const long rows = (long)(budget / std::max<size_t>(bytes_per_row, 1)) - 2 * p;
+  return (int)std::max<long>(1, std::min<long>(n1, rows));
+}
+
 // The sketched train (Q1, Q2, C3) of y = alpha K x + beta z for sketch widths (l1, l2).
 void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double alpha, const TT* z, double beta,
                            int l1, int l2, TT& y) {
@@ -154,28 +166,34 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
   {
     DBuf W3p(ctx.alloc, sizeof(double) * (size_t)rK2 * rx2 * l2);
     permute4(ctx, W3.d(), 1, rK2, rx2, l2, 0, 2, 1, 3, W3p.d());  // [b'][a'][l2]
-    const size_t usz = (size_t)rx1 * n1 * rK2 * l2;
+    // over blocks [i0, i1) of the middle mode, which read rows j in [i0 - p, i1 + p) of x_1
+    const int ib = middle_block(sizeof(double) * 2 * ((size_t)rx1 * rK2 * l2 + (size_t)rK1 * rx1 * l2), n1, p);
+    const size_t usz = (size_t)rx1 * std::min(n1, ib + 2 * p) * rK2 * l2, tsz = (size_t)ib * rK1 * rx1 * l2;
     DBuf U(ctx.alloc, sizeof(double) * usz), Up(ctx.alloc, sizeof(double) * usz);
-    gemm(ctx, false, false, rx1 * n1, rK2 * l2, rx2, 1.0, x1, rx2, 0, W3p.d(), (long)rK2 * l2, 0, 0.0, U.d(),
-         (long)rK2 * l2, 0);
-    permute4(ctx, U.d(), rx1, n1, rK2, l2, 1, 2, 0, 3, Up.d());  // [j][a'][b][l2]
-    U = DBuf();
-    const size_t tsz = (size_t)n1 * rK1 * rx1 * l2;
-    DBuf Tt(ctx.alloc, sizeof(double) * tsz);
-    fill(ctx, Tt.d(), tsz, 0.0);
-    for (int t = 0; t < band; ++t) {
-      const int ilo = std::max(0, p - t), ihi = std::min(n1, n1 + p - t);
-      if (ihi <= ilo) continue;
-      gemm(ctx, false, false, rK1, rx1 * l2, rK2, 1.0, K1 + ((long)ilo * band + t) * rK2, (long)n1 * band * rK2,
-           (long)band * rK2, Up.d() + (long)(ilo + t - p) * rK2 * rx1 * l2, (long)rx1 * l2,
-           (long)rK2 * rx1 * l2, 1.0, Tt.d() + (long)ilo * rK1 * rx1 * l2, (long)rx1 * l2,
-           (long)rK1 * rx1 * l2, ihi - ilo);
+    DBuf Tt(ctx.alloc, sizeof(double) * tsz), T(ctx.alloc, sizeof(double) * tsz);
+    for (int i0 = 0; i0 < n1; i0 += ib) {
+      const int i1 = std::min(n1, i0 + ib), ic = i1 - i0;
+      const int j0 = std::max(0, i0 - p), jc = std::min(n1, i1 + p) - j0;
+      if (jc == n1)
+        gemm(ctx, false, false, rx1 * n1, rK2 * l2, rx2, 1.0, x1, rx2, 0, W3p.d(), (long)rK2 * l2, 0, 0.0, U.d(),
+             (long)rK2 * l2, 0);
+      else  // one product per row b of x_1, over its rows j0..j0+jc
+        gemm(ctx, false, false, jc, rK2 * l2, rx2, 1.0, x1 + (long)j0 * rx2, rx2, (long)n1 * rx2, W3p.d(),
+             (long)rK2 * l2, 0, 0.0, U.d(), (long)rK2 * l2, (long)jc * rK2 * l2, rx1);
+      permute4(ctx, U.d(), rx1, jc, rK2, l2, 1, 2, 0, 3, Up.d());  // [j][a'][b][l2]
+      fill(ctx, Tt.d(), (size_t)ic * rK1 * rx1 * l2, 0.0);
+      for (int t = 0; t < band; ++t) {
+        const int ilo = std::max(i0, p - t), ihi = std::min(i1, n1 + p - t);
+        if (ihi <= ilo) continue;
+        gemm(ctx, false, false, rK1, rx1 * l2, rK2, 1.0, K1 + ((long)ilo * band + t) * rK2, (long)n1 * band * rK2,
+             (long)band * rK2, Up.d() + (long)(ilo + t - p - j0) * rK2 * rx1 * l2, (long)rx1 * l2,
+             (long)rK2 * rx1 * l2, 1.0, Tt.d() + (long)(ilo - i0) * rK1 * rx1 * l2, (long)rx1 * l2,
+             (long)rK1 * rx1 * l2, ihi - ilo);
+      }
+      permute4(ctx, Tt.d(), ic, rK1, rx1, l2, 1, 2, 0, 3, T.d());  // [a][b][i][l2]
+      gemm(ctx, false, true, rK1 * rx1, l1, ic * l2, 1.0, T.d(), (long)ic * l2, 0, O2.d() + (long)i0 * l2,
+           (long)n1 * l2, 0, i0 == 0 ? 0.0 : 1.0, W2.d(), l1, 0);
     }
-    Up = DBuf();
-    DBuf T(ctx.alloc, sizeof(double) * tsz);
-    permute4(ctx, Tt.d(), n1, rK1, rx1, l2, 1, 2, 0, 3, T.d());  // [a][b][i][l2]
-    gemm(ctx, false, true, rK1 * rx1, l1, n1 * l2, 1.0, T.d(), (long)n1 * l2, 0, O2.d(), (long)n1 * l2, 0, 0.0,
-         W2.d(), l1, 0);
   }
   DBuf W3z, W2z;
   if (hz) {
@@ -212,52 +230,65 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
       gemm(ctx, true, false, l1, rz1, n0, beta, Q1.d(), l1, 0, z->c[0].d(), rz1, 0, 0.0, M1z.d(), rz1, 0);
     }
   }
-  // middle core: Z2 = M1 y_1 ((l1 i1) x (a' b')), Y2 = Z2 W3, Q2 its basis, M2 = Q2^T Z2
-  const size_t zsz = (size_t)l1 * n1 * rK2 * rx2;
-  DBuf Z2(ctx.alloc, sizeof(double) * zsz);
-  {
-    const size_t esz = (size_t)l1 * rK1 * n1 * rx2;
-    DBuf E(ctx.alloc, sizeof(double) * esz), Ep(ctx.alloc, sizeof(double) * esz);
-    gemm(ctx, false, false, l1 * rK1, n1 * rx2, rx1, 1.0, M1.d(), rx1, 0, x1, (long)n1 * rx2, 0, 0.0, E.d(),
-         (long)n1 * rx2, 0);
-    permute4(ctx, E.d(), l1, rK1, n1, rx2, 2, 1, 0, 3, Ep.d());  // [j][a][l1][b']
-    E = DBuf();
-    DBuf Zt(ctx.alloc, sizeof(double) * zsz);
-    fill(ctx, Zt.d(), zsz, 0.0);
+  // middle core: Z2 = M1 y_1 (rows (i, l1), columns (a', b')), Y2 = Z2 W3, Q2 its basis,
+  // M2 = Q2^T Z2.  Z2 is formed over blocks of i; when it takes more than one block it is
+  // formed twice (once for Y2, once for M2) instead of being stored whole.
+  const int zb = middle_block(sizeof(double) * 2 * ((size_t)l1 * rK1 * rx2 + (size_t)l1 * rK2 * rx2), n1, p);
+  const size_t esz = (size_t)l1 * rK1 * std::min(n1, zb + 2 * p) * rx2, zsz = (size_t)zb * l1 * rK2 * rx2;
+  DBuf E(ctx.alloc, sizeof(double) * esz), Ep(ctx.alloc, sizeof(double) * esz);
+  DBuf Zt(ctx.alloc, sizeof(double) * zsz), Zc(ctx.alloc, sizeof(double) * zsz);
+  auto z2_block = [&](int i0, int i1) {  // Zc = rows i0..i1 of Z2, [i][l1][a'][b']
+    const int ic = i1 - i0, j0 = std::max(0, i0 - p), jc = std::min(n1, i1 + p) - j0;
+    gemm(ctx, false, false, l1 * rK1, jc * rx2, rx1, 1.0, M1.d(), rx1, 0, x1 + (long)j0 * rx2, (long)n1 * rx2, 0,
+         0.0, E.d(), (long)jc * rx2, 0);
+    permute4(ctx, E.d(), l1, rK1, jc, rx2, 2, 1, 0, 3, Ep.d());  // [j][a][l1][b']
+    fill(ctx, Zt.d(), (size_t)ic * rK2 * l1 * rx2, 0.0);
     for (int t = 0; t < band; ++t) {
-      const int ilo = std::max(0, p - t), ihi = std::min(n1, n1 + p - t);
+      const int ilo = std::max(i0, p - t), ihi = std::min(i1, n1 + p - t);
       if (ihi <= ilo) continue;
       gemm(ctx, true, false, rK2, l1 * rx2, rK1, 1.0, K1 + ((long)ilo * band + t) * rK2, (long)n1 * band * rK2,
-           (long)band * rK2, Ep.d() + (long)(ilo + t - p) * rK1 * l1 * rx2, (long)l1 * rx2,
-           (long)rK1 * l1 * rx2, 1.0, Zt.d() + (long)ilo * rK2 * l1 * rx2, (long)l1 * rx2,
+           (long)band * rK2, Ep.d() + (long)(ilo + t - p - j0) * rK1 * l1 * rx2, (long)l1 * rx2,
+           (long)rK1 * l1 * rx2, 1.0, Zt.d() + (long)(ilo - i0) * rK2 * l1 * rx2, (long)l1 * rx2,
            (long)rK2 * l1 * rx2, ihi - ilo);
     }
-    Ep = DBuf();
-    permute4(ctx, Zt.d(), n1, rK2, l1, rx2, 2, 0, 1, 3, Z2.d());  // [l1][i][a'][b']
-  }
+    permute4(ctx, Zt.d(), ic, rK2, l1, rx2, 0, 2, 1, 3, Zc.d());  // [i][l1][a'][b']
+  };
   DBuf Z2z;
-  if (hz) {
-    Z2z = DBuf(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * rz2);
-    gemm(ctx, false, false, l1, n1 * rz2, rz1, 1.0, M1z.d(), rz1, 0, z->c[1].d(), (long)n1 * rz2, 0, 0.0,
-         Z2z.d(), (long)n1 * rz2, 0);
+  if (hz) {  // [i][l1][c'] = M1z z_1
+    Z2z = DBuf(ctx.alloc, sizeof(double) * (size_t)n1 * l1 * rz2);
+    gemm(ctx, false, false, l1, rz2, rz1, 1.0, M1z.d(), rz1, 0, z->c[1].d(), (long)n1 * rz2, rz2, 0.0, Z2z.d(),
+         rz2, (long)l1 * rz2, n1);
   }
   DBuf Q2(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2);
   DBuf M2(ctx.alloc, sizeof(double) * (size_t)l2 * rK2 * rx2), M2z;
   {
-    DBuf Y2(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2), Rq(ctx.alloc, sizeof(double) * (size_t)l2 * l2);
-    gemm(ctx, false, false, l1 * n1, l2, rK2 * rx2, 1.0, Z2.d(), (long)rK2 * rx2, 0, W3.d(), l2, 0, 0.0, Y2.d(),
-         l2, 0);
+    DBuf Y2(ctx.alloc, sizeof(double) * (size_t)n1 * l1 * l2), Rq(ctx.alloc, sizeof(double) * (size_t)l2 * l2);
+    for (int i0 = 0; i0 < n1; i0 += zb) {
+      const int i1 = std::min(n1, i0 + zb);
+      z2_block(i0, i1);
+      gemm(ctx, false, false, (i1 - i0) * l1, l2, rK2 * rx2, 1.0, Zc.d(), (long)rK2 * rx2, 0, W3.d(), l2, 0, 0.0,
+           Y2.d() + (long)i0 * l1 * l2, l2, 0);
+    }
     if (hz)
-      gemm(ctx, false, false, l1 * n1, l2, rz2, 1.0, Z2z.d(), rz2, 0, W3z.d(), l2, 0, 1.0, Y2.d(), l2, 0);
-    qr_tall(ctx, Y2.d(), false, l1 * n1, l2, l2, Q2.d(), Rq.d());
-    gemm(ctx, true, false, l2, rK2 * rx2, l1 * n1, 1.0, Q2.d(), l2, 0, Z2.d(), (long)rK2 * rx2, 0, 0.0, M2.d(),
-         (long)rK2 * rx2, 0);
+      gemm(ctx, false, false, n1 * l1, l2, rz2, 1.0, Z2z.d(), rz2, 0, W3z.d(), l2, 0, 1.0, Y2.d(), l2, 0);
+    DBuf Qi(ctx.alloc, sizeof(double) * (size_t)n1 * l1 * l2);
+    qr_tall(ctx, Y2.d(), false, n1 * l1, l2, l2, Qi.d(), Rq.d());
+    for (int i0 = 0; i0 < n1; i0 += zb) {
+      const int i1 = std::min(n1, i0 + zb);
+      if (zb < n1) z2_block(i0, i1);
+      gemm(ctx, true, false, l2, rK2 * rx2, (i1 - i0) * l1, 1.0, Qi.d() + (long)i0 * l1 * l2, l2, 0, Zc.d(),
+           (long)rK2 * rx2, 0, i0 == 0 ? 0.0 : 1.0, M2.d(), (long)rK2 * rx2, 0);
+    }
     if (hz) {
       M2z = DBuf(ctx.alloc, sizeof(double) * (size_t)l2 * rz2);
-      gemm(ctx, true, false, l2, rz2, l1 * n1, 1.0, Q2.d(), l2, 0, Z2z.d(), rz2, 0, 0.0, M2z.d(), rz2, 0);
+      gemm(ctx, true, false, l2, rz2, n1 * l1, 1.0, Qi.d(), l2, 0, Z2z.d(), rz2, 0, 0.0, M2z.d(), rz2, 0);
     }
+    permute4(ctx, Qi.d(), 1, n1, l1, l2, 0, 2, 1, 3, Q2.d());  // [l1][i][l2]
   }
-  Z2 = DBuf();
+  E = DBuf();
+  Ep = DBuf();
+  Zt = DBuf();
+  Zc = DBuf();
   // last core: C3 = M2 y_2 (l2 x n2)
   DBuf C3(ctx.alloc, sizeof(double) * (size_t)l2 * n2);
   {
@@ -317,6 +348,9 @@ void tt_matvec_round(Context& ctx, const TT& K, int p, const TT& x, double alpha
       l += 12;
       continue;
     }
+    if (const char* e = std::getenv("TTIGA_TRACE_ROUND"); e && e[0] == '1')
+      std::fprintf(stderr, "[matvec_round] K (%d,%d) x (%d,%d) l (%d,%d) eps %.1e -> (%d,%d)\n", K.r[1], K.r[2],
+                   x.r[1], x.r[2], l1, l2, eps_rel, y.r[1], y.r[2]);
     hint = std::max(y.r[1], y.r[2]);
     out = std::move(y);
     return;

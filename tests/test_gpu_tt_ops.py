@@ -127,19 +127,25 @@ def test_compress_rank_deficient_geometry_factor(ctx):
         assert tt.ranks(cores) == tt.ranks(tt.tt_svd(fj, delta=delta))
 
 
+@pytest.mark.parametrize("block_bytes", [None, 1_000_000])
 @pytest.mark.parametrize("sketch_rank", [64, 4])
 @pytest.mark.parametrize("shape,rK,rx,rz,p,alpha,beta", [
     ((13, 9, 11), (3, 2), (4, 5), None, 2, 1.0, 0.0),
     ((17, 16, 15), (5, 4), (7, 6), (3, 4), 3, -1.0, 1.0),  # the residual form b - K x
     ((40, 33, 70), (6, 5), (9, 8), (4, 3), 3, 2.0, -0.5),  # several tiles and ragged tails
 ])
-def test_matvec_round_matches_oracle(ctx, shape, rK, rx, rz, p, alpha, beta, sketch_rank):
+def test_matvec_round_matches_oracle(ctx, monkeypatch, shape, rK, rx, rz, p, alpha, beta, sketch_rank,
+                                    block_bytes):
     """round(alpha K x + beta z, eps) without the product cores, against the oracle's exact
     alpha K x + beta z.  The random trains have no rank decay, so the rounded rank is the
     product rank: a sketch of width 64 + 10 covers it at once, one of width 4 + 10 has to be
     widened until it does; either way only the eps-rounding separates the result from the
-    exact vector (<= eps ||y|| per the rounding bound; 10 eps allowed)."""
-    say("matvec_round", shape, rK, rx, rz, p, alpha, beta, sketch_rank)
+    exact vector (<= eps ||y|| per the rounding bound; 10 eps allowed).  A 1 MB block budget
+    splits the middle-mode contractions into blocks of a few rows of i with a ragged last
+    block (and forms the middle sketch twice), which must not change the result."""
+    say("matvec_round", shape, rK, rx, rz, p, alpha, beta, sketch_rank, block_bytes)
+    if block_bytes is not None:
+        monkeypatch.setenv("TTIGA_MATVEC_BLOCK_BYTES", str(block_bytes))
     rng = np.random.default_rng(sum(shape) + 7 * p + sketch_rank)
     K = rand_banded(shape, rK, p, rng)
     x = rand_tt(shape, rx, rng)
