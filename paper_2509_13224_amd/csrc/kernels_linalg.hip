@@ -388,9 +388,57 @@ __device__ inline void update_batch_n(int nq, double* const* col, const double* 
   }
 }
 
+// d[q] += v[i] col[q][i] for q < NQ over the rows i = i0, i0 + 64, ... < nr of one lane; only
+// the batch's real columns are read (a batch of a few columns would otherwise stream the
+// aliased ones through LDS as well)
+template <int NQ>
+__device__ inline void dot_batch(double* const* col, const double* v, int i0, int nr, double* d) {
+  for (int i = i0; i < nr; i += 64) {
+    const double x = v[i];
+    double y[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) y[q] = col[q][i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) d[q] += x * y[q];
+  }
+}
+
+__device__ inline void dot_batch_n(int nq, double* const* col, const double* v, int i0, int nr, double* d) {
+  switch (nq) {
+    case 1: dot_batch<1>(col, v, i0, nr, d); break;
+    case 2: dot_batch<2>(col, v, i0, nr, d); break;
+    case 3: dot_batch<3>(col, v, i0, nr, d); break;
+    case 4: dot_batch<4>(col, v, i0, nr, d); break;
+    case 5: dot_batch<5>(col, v, i0, nr, d); break;
+    case 6: dot_batch<6>(col, v, i0, nr, d); break;
+    case 7: dot_batch<7>(col, v, i0, nr, d); break;
+    default: dot_batch<8>(col, v, i0, nr, d); break;
+  }
+}
+
 // Column k of the block belongs to wave k % nwaves for the whole factorisation,
 // so a reflector needs one barrier: the owner of column j forms v_j and tau_j,
 // then every wave applies H_j to the columns it owns.
+// (outer, inner) = (e / n_inner, e % n_inner) for e = e0, e0 + step, ...: one division at the
+// start instead of a (64-bit) division per element of a flattened copy loop
+struct FlatWalk {
+  int outer, inner, d_out, d_in, n_in;
+  __device__ FlatWalk(int e0, int step, int n_inner) : n_in(n_inner) {
+    outer = e0 / n_inner;
+    inner = e0 - outer * n_inner;
+    d_out = step / n_inner;
+    d_in = step - d_out * n_inner;
+  }
+  __device__ void next() {
+    inner += d_in;
+    outer += d_out;
+    if (inner >= n_in) {
+      inner -= n_in;
+      ++outer;
+    }
+  }
+};
+
 template <bool kLds>
 __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* __restrict__ A,
                                                     long lda, int trans, int nb, int ldw,
@@ -407,13 +455,12 @@ __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform within the wave
   // the storage is a template choice so LDS accesses compile to ds_* instructions
   double* W = kLds ? smem : gwork + (long)blk * ldw * c;
-  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
-    int i, j;
-    double v;
-    if (trans) { i = e % nr; j = e / nr; v = A[(long)j * lda + r0 + i]; }
-    else { i = e / c; j = e % c; v = A[(r0 + i) * lda + j]; }
-    W[(long)j * ldw + i] = v;
-  }
+  if (trans)
+    for (FlatWalk w(tid, blockDim.x, nr); w.outer < c; w.next())
+      W[(long)w.outer * ldw + w.inner] = A[(long)w.outer * lda + r0 + w.inner];
+  else
+    for (FlatWalk w(tid, blockDim.x, c); w.outer < nr; w.next())
+      W[(long)w.inner * ldw + w.outer] = A[(r0 + w.outer) * lda + w.inner];
   __syncthreads();
   for (int j = 0; j < c; ++j) {
     double* wj = W + (long)j * ldw;
@@ -450,15 +497,7 @@ __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* 
       double d[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) d[q] = 0.0;
-      for (int i = j + 1 + lane; i < nr; i += 64) {
-        // all eight loads issued before the products, so their latencies overlap
-        const double v = wj[i];
-        double x[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = col[q][i];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) d[q] += v * x[q];
-      }
+      dot_batch_n(nq, col, wj, j + 1 + lane, nr, d);
       wave_sum8(d);
       double f[8];
 #pragma unroll
@@ -470,14 +509,14 @@ __global__ __launch_bounds__(1024) void k_hh_factor(int m, int c, const double* 
   }
   __syncthreads();
   for (int j = tid; j < c; j += blockDim.x) tau[(long)blk * c + j] = s_tau[j];
-  for (long e = tid; e < (long)c * c; e += blockDim.x) {
-    const int j = e / c, k = e % c;
-    Rout[(long)blk * c * c + e] = (k >= j) ? W[(long)k * ldw + j] : 0.0;
+  for (FlatWalk w(tid, blockDim.x, c); w.outer < c; w.next()) {
+    const int j = w.outer, k = w.inner;
+    Rout[(long)blk * c * c + (long)j * c + k] = (k >= j) ? W[(long)k * ldw + j] : 0.0;
   }
   double* Vb = V + r0 * c;
-  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
-    const int j = e / nr, i = e % nr;
-    Vb[e] = (i > j) ? W[(long)j * ldw + i] : (i == j ? 1.0 : 0.0);
+  for (FlatWalk w(tid, blockDim.x, nr); w.outer < c; w.next()) {
+    const int j = w.outer, i = w.inner;
+    Vb[(long)j * nr + i] = (i > j) ? W[(long)j * ldw + i] : (i == j ? 1.0 : 0.0);
   }
 }
 
@@ -505,8 +544,8 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
   if (kVLds)
     for (long e = tid; e < (long)nr * c; e += blockDim.x) Vs[e] = Vg[e];
   const double* Vb = kVLds ? Vs : Vg;
-  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
-    const int k = e / nr, i = e % nr;
+  for (FlatWalk w(tid, blockDim.x, nr); w.outer < c; w.next()) {
+    const int k = w.outer, i = w.inner;
     double v = 0.0;
     if (i < c) v = Qtop ? Qtop[((long)blk * c + i) * c + k] : (i == k ? 1.0 : 0.0);
     Y[(long)k * ldw + i] = v;
@@ -527,14 +566,7 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
       double d[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) d[q] = 0.0;
-      for (int i = j + 1 + lane; i < nr; i += 64) {
-        const double v = vj[i];
-        double x[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = col[q][i];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) d[q] += v * x[q];
-      }
+      dot_batch_n(nq, col, vj, j + 1 + lane, nr, d);
       wave_sum8(d);
       double f[8];
 #pragma unroll
@@ -545,10 +577,8 @@ __global__ __launch_bounds__(1024) void k_hh_apply(int m, int c, int nb, int ldw
     }
   }
   __syncthreads();
-  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
-    const int i = e / c, k = e % c;
-    Qout[(r0 + i) * c + k] = Y[(long)k * ldw + i];
-  }
+  for (FlatWalk w(tid, blockDim.x, c); w.outer < nr; w.next())
+    Qout[(r0 + w.outer) * c + w.inner] = Y[(long)w.inner * ldw + w.outer];
 }
 
 // col[q][i] -= sum_k v[k][i] X[4 k + q] for q < NQ and the rows i = i0, i0 + 64, ... < nr of
@@ -568,6 +598,32 @@ __device__ inline void update_panel(double* const* col, const double* X, const d
       for (int k = 0; k < 4; ++k) s -= vv[k] * X[4 * k + q];
       col[q][i] = s;
     }
+  }
+}
+
+// w[4 k + q] += v[k][i] col[q][i] for q < NQ over the rows i = i0, i0 + 64, ... < nr of one
+// lane: the 4 x NQ dot products of a panel with a batch of owned columns
+template <int NQ>
+__device__ inline void panel_dots(double* const* col, const double* const* v, int i0, int nr, double* w) {
+  for (int i = i0; i < nr; i += 64) {
+    double vv[4], x[NQ];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) vv[k] = v[k][i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) x[q] = col[q][i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) w[4 * k + q] += vv[k] * x[q];
+  }
+}
+
+__device__ inline void panel_dots_n(int nq, double* const* col, const double* const* v, int i0, int nr, double* w) {
+  switch (nq) {
+    case 1: panel_dots<1>(col, v, i0, nr, w); break;
+    case 2: panel_dots<2>(col, v, i0, nr, w); break;
+    case 3: panel_dots<3>(col, v, i0, nr, w); break;
+    default: panel_dots<4>(col, v, i0, nr, w); break;
   }
 }
 
@@ -611,8 +667,8 @@ __global__ __launch_bounds__(1024) void k_hh_apply_wy(int m, int c, int nb, int 
   if (kVLds)
     for (long e = tid; e < (long)nr * c; e += blockDim.x) Vs[e] = Vg[e];
   const double* Vb = kVLds ? Vs : Vg;
-  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
-    const int k = e / nr, i = e % nr;
+  for (FlatWalk w(tid, blockDim.x, nr); w.outer < c; w.next()) {
+    const int k = w.outer, i = w.inner;
     double v = 0.0;
     if (i < c) v = Qtop ? Qtop[((long)blk * c + i) * c + k] : (i == k ? 1.0 : 0.0);
     Y[(long)k * ldw + i] = v;
@@ -677,17 +733,7 @@ __global__ __launch_bounds__(1024) void k_hh_apply_wy(int m, int c, int nb, int 
       double w[16];  // w[4 k + q] = v_k . col_q
 #pragma unroll
       for (int e = 0; e < 16; ++e) w[e] = 0.0;
-      for (int i = j0 + lane; i < nr; i += 64) {
-        double vv[4], x[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) vv[k] = v[k][i];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = col[q][i];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) w[4 * k + q] += vv[k] * x[q];
-      }
+      panel_dots_n(nq, col, v, j0 + lane, nr, w);
       wave_sum8(w);
       wave_sum8(w + 8);
       // X = T W in place (T upper triangular: row k uses rows k.. of W)
@@ -705,9 +751,225 @@ __global__ __launch_bounds__(1024) void k_hh_apply_wy(int m, int c, int nb, int 
     }
   }
   __syncthreads();
-  for (long e = tid; e < (long)nr * c; e += blockDim.x) {
-    const int i = e / c, k = e % c;
-    Qout[(r0 + i) * c + k] = Y[(long)k * ldw + i];
+  for (FlatWalk w(tid, blockDim.x, c); w.outer < nr; w.next())
+    Qout[(r0 + w.outer) * c + w.inner] = Y[(long)w.inner * ldw + w.outer];
+}
+
+// Orders the LDS accesses of one wave: stores issued before it are complete and visible
+// to every lane of the wave (and to the compiler's alias analysis) before later loads.
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// v_k[i] of a panel's reflectors k = 0..3 as stored in W (below the diagonal, the diagonal
+// holding R): 0 above row j0 + k, 1 on it, the stored entry below
+__device__ inline void panel_rows(const double* const* v, int j0, int i, double* vv) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) vv[k] = v[k][i];
+  if (i < j0 + 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) vv[k] = i > j0 + k ? vv[k] : (i == j0 + k ? 1.0 : 0.0);
+  }
+}
+
+// w[4 k + q] += v_k[i] col[q][i] over rows i = i0, i0 + 64, ... < nr (i0 >= j0)
+template <int NQ>
+__device__ inline void panel_dots_tri(double* const* col, const double* const* v, int j0, int i0, int nr,
+                                      double* w) {
+  for (int i = i0; i < nr; i += 64) {
+    double vv[4], x[NQ];
+    panel_rows(v, j0, i, vv);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) x[q] = col[q][i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) w[4 * k + q] += vv[k] * x[q];
+  }
+}
+
+// col[q][i] -= sum_k v_k[i] X[4 k + q] over the same rows
+template <int NQ>
+__device__ inline void panel_update_tri(double* const* col, const double* X, const double* const* v, int j0,
+                                        int i0, int nr) {
+  for (int i = i0; i < nr; i += 64) {
+    double vv[4], y[NQ];
+    panel_rows(v, j0, i, vv);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) y[q] = col[q][i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = y[q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s -= vv[k] * X[4 * k + q];
+      col[q][i] = s;
+    }
+  }
+}
+
+template <int NQ>
+__device__ inline void panel_apply_tri(double* const* col, const double* T, const double* const* v, int j0,
+                                       int i0, int nr) {
+  double w[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) w[e] = 0.0;
+  panel_dots_tri<NQ>(col, v, j0, i0, nr, w);
+  wave_sum8(w);
+  wave_sum8(w + 8);
+  // X = T^T W in place, rows from the last (T^T is lower triangular: row k uses rows 0..k)
+#pragma unroll
+  for (int k = 3; k >= 0; --k)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l <= k; ++l) s += T[l * 4 + k] * w[4 * l + q];
+      w[4 * k + q] = s;
+    }
+  panel_update_tri<NQ>(col, w, v, j0, i0, nr);
+}
+
+// The Householder QR of each block that k_hh_factor computes (same reflectors, tau, R and V
+// layout), blocked by panels of four columns.  Wave 0 factors the panel's columns one after
+// another, each reflector applied at once to the panel's remaining columns, with only
+// wave-level ordering between the steps, and forms the panel's compact WY factor T
+// (H_j0 ... H_j0+3 = I - V T V^T, Schreiber and Van Loan).  After one barrier every wave
+// applies H_j0+3 ... H_j0 = I - V T^T V^T to its owned trailing columns, four at a time.
+// Two workgroup barriers per four columns instead of one per column: the column-at-a-time
+// kernel is bound by the latency of its dependent steps, not by arithmetic or bandwidth.
+template <bool kLds>
+__global__ __launch_bounds__(1024) void k_hh_factor_wy(int m, int c, const double* __restrict__ A, long lda,
+                                                       int trans, int nb, int ldw, double* __restrict__ V,
+                                                       double* __restrict__ tau, double* __restrict__ Rout,
+                                                       double* __restrict__ gwork) {
+  extern __shared__ double smem[];
+  __shared__ double s_tau[1024];
+  __shared__ double s_T[16];
+  const int blk = blockIdx.x;
+  const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
+  const int nr = (int)(r1 - r0);
+  const int tid = threadIdx.x, lane = tid & 63, nwaves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* W = kLds ? smem : gwork + (long)blk * ldw * c;
+  if (trans)
+    for (FlatWalk w(tid, blockDim.x, nr); w.outer < c; w.next())
+      W[(long)w.outer * ldw + w.inner] = A[(long)w.outer * lda + r0 + w.inner];
+  else
+    for (FlatWalk w(tid, blockDim.x, c); w.outer < nr; w.next())
+      W[(long)w.inner * ldw + w.outer] = A[(r0 + w.outer) * lda + w.inner];
+  __syncthreads();
+  for (int j0 = 0; j0 < c; j0 += 4) {
+    const int bp = min(4, c - j0), kt = j0 + bp;  // kt: first trailing column
+    if (wave == 0) {
+      for (int j = j0; j < kt; ++j) {
+        double* wj = W + (long)j * ldw;
+        double ss = 0.0;
+        for (int i = j + 1 + lane; i < nr; i += 64) ss += wj[i] * wj[i];
+        ss = wave_sum(ss);
+        const double alpha = wj[j];
+        double t = 0.0, sc = 0.0, beta = alpha;
+        if (ss != 0.0) {
+          beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+          t = (beta - alpha) / beta;
+          sc = 1.0 / (alpha - beta);
+        }
+        if (t != 0.0)
+          for (int i = j + 1 + lane; i < nr; i += 64) wj[i] *= sc;
+        if (lane == 0) {
+          wj[j] = beta;
+          s_tau[j] = t;
+        }
+        wave_lds_fence();
+        const int nq = kt - 1 - j;  // panel columns right of j
+        if (t != 0.0 && nq > 0) {
+          double* col[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) col[q] = W + (long)(j + 1 + (q < nq ? q : 0)) * ldw;
+          double d[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) d[q] = 0.0;
+          dot_batch_n(nq, col, wj, j + 1 + lane, nr, d);
+          wave_sum8(d);
+          double f[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) f[q] = t * (d[q] + col[q][j]);
+          if (lane == 0)
+            for (int q = 0; q < nq; ++q) col[q][j] -= f[q];
+          update_batch_n(nq, col, f, wj, j + 1 + lane, nr);
+          wave_lds_fence();
+        }
+      }
+      if (kt < c) {  // T of the panel (bp == 4 whenever trailing columns remain)
+        const double* v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = W + (long)(j0 + k) * ldw;
+        double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+        for (int i = j0 + lane; i < nr; i += 64) {
+          double x[4];
+          panel_rows(v, j0, i, x);
+          g[0] += x[0] * x[1];
+          g[1] += x[0] * x[2];
+          g[2] += x[0] * x[3];
+          g[3] += x[1] * x[2];
+          g[4] += x[1] * x[3];
+          g[5] += x[2] * x[3];
+        }
+        wave_sum8(g);
+        if (lane == 0) {
+          double G[4][4] = {{0}}, T[4][4] = {{0}};
+          G[0][1] = g[0];
+          G[0][2] = g[1];
+          G[0][3] = g[2];
+          G[1][2] = g[3];
+          G[1][3] = g[4];
+          G[2][3] = g[5];
+          for (int mm = 0; mm < 4; ++mm) {
+            const double tm = s_tau[j0 + mm];
+            T[mm][mm] = tm;
+            for (int k = 0; k < mm; ++k) {
+              double acc = 0.0;
+              for (int l = k; l < mm; ++l) acc += T[k][l] * G[l][mm];
+              T[k][mm] = -tm * acc;
+            }
+          }
+          for (int e = 0; e < 16; ++e) s_T[e] = T[e / 4][e % 4];
+        }
+      }
+    }
+    __syncthreads();
+    if (kt < c) {
+      double T[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) T[e] = s_T[e];
+      const double* v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = W + (long)(j0 + k) * ldw;
+      for (int kb = kt + wave; kb < c; kb += 4 * nwaves) {
+        const int nq = min(4, (c - kb + nwaves - 1) / nwaves);
+        double* col[4];  // columns past c alias the batch's first (read, never written)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) col[q] = W + (long)(kb + (q < nq ? q : 0) * nwaves) * ldw;
+        switch (nq) {
+          case 1: panel_apply_tri<1>(col, T, v, j0, j0 + lane, nr); break;
+          case 2: panel_apply_tri<2>(col, T, v, j0, j0 + lane, nr); break;
+          case 3: panel_apply_tri<3>(col, T, v, j0, j0 + lane, nr); break;
+          default: panel_apply_tri<4>(col, T, v, j0, j0 + lane, nr); break;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = tid; j < c; j += blockDim.x) tau[(long)blk * c + j] = s_tau[j];
+  for (FlatWalk w(tid, blockDim.x, c); w.outer < c; w.next()) {
+    const int j = w.outer, k = w.inner;
+    Rout[(long)blk * c * c + (long)j * c + k] = (k >= j) ? W[(long)k * ldw + j] : 0.0;
+  }
+  double* Vb = V + r0 * c;
+  for (FlatWalk w(tid, blockDim.x, nr); w.outer < c; w.next()) {
+    const int j = w.outer, i = w.inner;
+    Vb[(long)j * nr + i] = (i > j) ? W[(long)j * ldw + i] : (i == j ? 1.0 : 0.0);
   }
 }
 
@@ -740,6 +1002,8 @@ static int lds_doubles() {
     if (bytes > 65536) {
       const bool ok =
           hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_factor<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
+          hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_factor_wy<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
           hipFuncSetAttribute(reinterpret_cast<const void*>(k_hh_apply<true, true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kTsqrStatic) == hipSuccess &&
@@ -800,6 +1064,12 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
   // LDS holds the work columns (each tree level costs a launch of c dependent steps, so
   // fewer, taller blocks win); the apply step keeps the reflectors in LDS only when
   // both fit and otherwise streams them from L2
+  // panels of four columns (TTIGA_TSQR_FACTOR=column selects the column-at-a-time kernel, for
+  // measurements)
+  static const bool per_column = [] {
+    const char* e = std::getenv("TTIGA_TSQR_FACTOR");
+    return e && std::strcmp(e, "column") == 0;
+  }();
   const int rows_work = kLdsDoubles / c;
   const int rows_target = rows_work >= 2 * c ? rows_work : 4 * c;
   while (true) {
@@ -818,11 +1088,17 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
     ProfScope prof(ctx, "tsqr_factor", 2.0 * mm * c * c - L.nb * (2.0 / 3.0) * c * c * c,
                    8.0 * (2.0 * mm * c + (double)L.nb * c * c), c);
-    if (L.lds)
+    if (per_column && L.lds)
       hipLaunchKernelGGL(k_hh_factor<true>, dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, mm, c, in, ld,
                          tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, nullptr);
-    else
+    else if (per_column)
       hipLaunchKernelGGL(k_hh_factor<false>, dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, mm, c, in, ld,
+                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, L.work.d());
+    else if (L.lds)
+      hipLaunchKernelGGL(k_hh_factor_wy<true>, dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, mm, c,
+                         in, ld, tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, nullptr);
+    else
+      hipLaunchKernelGGL(k_hh_factor_wy<false>, dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, mm, c, in, ld,
                          tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, L.work.d());
     TTIGA_HIP(hipGetLastError());
     lv.push_back(std::move(L));
@@ -1081,12 +1357,15 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
   __shared__ int s_rot;
   __shared__ int s_perm[1024];
   __shared__ double s_sig[1024];
-  for (long e = tid; e < (long)m * c; e += nt) {
-    const int i = e % m, j = e / m;
-    Ucol[e] = transA ? A[(long)j * lda + i] : A[(long)i * lda + j];
-  }
+  if (transA)
+    for (FlatWalk w(tid, nt, m); w.outer < c; w.next())
+      Ucol[(long)w.outer * m + w.inner] = A[(long)w.outer * lda + w.inner];
+  else
+    for (FlatWalk w(tid, nt, c); w.outer < m; w.next())
+      Ucol[(long)w.inner * m + w.outer] = A[(long)w.outer * lda + w.inner];
   if (want_v)
-    for (long e = tid; e < (long)c * c; e += nt) Vcol[e] = ((e / c) == (e % c)) ? 1.0 : 0.0;
+    for (FlatWalk w(tid, nt, c); w.outer < c; w.next())
+      Vcol[(long)w.outer * c + w.inner] = w.outer == w.inner ? 1.0 : 0.0;
   __shared__ double s_f2[16];
   {
     double f = 0.0;
@@ -1235,17 +1514,16 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
   }
   __syncthreads();
   for (int j = tid; j < c; j += nt) S[j] = s_sig[s_perm[j]];
-  for (long e = tid; e < (long)m * c; e += nt) {
-    const int i = e / c, jj = e % c;
+  for (FlatWalk w(tid, nt, c); w.outer < m; w.next()) {
+    const int i = w.outer, jj = w.inner;
+    const long e = (long)i * c + jj;
     const int j = s_perm[jj];
     const double sg = s_sig[j];
     U[e] = (sg > 0.0) ? Ucol[(long)j * m + i] / sg : 0.0;
   }
   if (want_v)
-    for (long e = tid; e < (long)c * c; e += nt) {
-      const int i = e / c, jj = e % c;
-      V[e] = Vcol[(long)s_perm[jj] * c + i];
-    }
+    for (FlatWalk w(tid, nt, c); w.outer < c; w.next())
+      V[(long)w.outer * c + w.inner] = Vcol[(long)s_perm[w.inner] * c + w.outer];
 }
 
 // Interpolation rows of an n x k matrix Q with orthonormal columns: column-pivoted
