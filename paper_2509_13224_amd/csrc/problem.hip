@@ -852,18 +852,21 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
     }
     pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
     seen(z);
-    double rho_new = tt_dot_sync(c, r, z);
-    auto err_est = [&]() {
-      const double zz = tt_dot_sync(c, z, z), xx = tt_dot_sync(c, x, x);
-      return std::sqrt(std::max(zz, 0.0) / std::max(xx, 1e-300));
+    // r.z, z.z, x.x and r_old.z (the Polak-Ribiere term) with one synchronisation
+    double dd[4];
+    auto dots = [&]() {
+      const TT* xs[4] = {&r, &z, &x, &r_old};
+      const TT* ys[4] = {&z, &z, &x, &z};
+      tt_dots_sync(c, xs, ys, 4, dd);
+      o.pres = std::sqrt(std::max(dd[1], 0.0) / std::max(dd[2], 1e-300));
     };
-    o.pres = err_est();
+    dots();
     if (o.pres <= tol && !replaced) {
       o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr, Kf, p);
       pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
-      rho_new = tt_dot_sync(c, r, z);
-      o.pres = err_est();
+      dots();
     }
+    const double rho_new = dd[0];
     if (o.pres <= tol) {
       o.conv = true;
       break;
@@ -876,7 +879,7 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
     } else if (o.it - best_it >= 15) {
       break;
     }
-    const double beta = std::max(0.0, (rho_new - tt_dot_sync(c, r_old, z)) / rho);
+    const double beta = std::max(0.0, (rho_new - dd[3]) / rho);
     rho = rho_new;
     TT pn;
     tt_axpby(c, 1.0, z, beta, pdir, pn);
@@ -946,8 +949,10 @@ void Problem::solve_mixed(ttiga_solve_stats& s) {
     true_res = true_residual(c, mv, rhs, u, nb, eps_r, opts.max_rank, r, hr, &KII, p);
     TT z;
     pc.apply(c, r, z, 1e-2, opts.max_rank, hz);
-    const double zz = tt_dot_sync(c, z, z), uu = tt_dot_sync(c, u, u);
-    est = std::sqrt(std::max(zz, 0.0) / std::max(uu, 1e-300));
+    double dd[2];
+    const TT* xs[2] = {&z, &u};
+    tt_dots_sync(c, xs, xs, 2, dd);
+    est = std::sqrt(std::max(dd[0], 0.0) / std::max(dd[1], 1e-300));
     if (est <= tol) {
       conv = true;
       break;

@@ -294,6 +294,8 @@ void tt_axpby(Context& ctx, double alpha, const TT& x, double beta, const TT& y,
 void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* beta, const TT& y,
                   TT& out);
 double tt_dot_sync(Context& ctx, const TT& x, const TT& y);
+// out[i] = x_i . y_i for count pairs (count <= 8) with one host synchronisation
+void tt_dots_sync(Context& ctx, const TT* const* x, const TT* const* y, int count, double* out);
 void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev);
 void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y);
 // FP64 cores -> FP32 or BF16 cores (round to nearest even, BF16 through FP32).

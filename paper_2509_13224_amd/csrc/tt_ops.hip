@@ -189,6 +189,18 @@ __global__ void k_scale_rows(const double* __restrict__ V, int rows, long M, con
     O[e] = s[e / M] * V[e];
 }
 
+// O = diag(1 / s) V: the reciprocal of each row's s, then the product (as k_reciprocal followed
+// by k_scale_rows, in one launch)
+__global__ void k_scale_rows_inv(const double* __restrict__ V, int rows, long M, const double* __restrict__ s,
+                                 double* __restrict__ O) {
+  const long total = (long)rows * M;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const double r = 1.0 / s[e / M];
+    O[e] = r * V[e];
+  }
+}
+
 // Standard normal numbers from a counter-based hash (SplitMix64 finaliser + Box-Muller).
 __device__ inline uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
@@ -346,22 +358,27 @@ void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* 
 
 void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev) {
   if (x.zero() || y.zero()) { fill(ctx, out_dev, 1, 0.0); return; }
-  // L_k (rx_k x ry_k); L_0 = [1].
-  DBuf L(ctx.alloc, sizeof(double));
-  fill(ctx, L.d(), 1, 1.0);
-  for (int k = 0; k < 3; ++k) {
+  // L_k (rx_k x ry_k); L_0 = [1], so L_1 = x_0^T y_0 directly; the last (1 x 1) product is
+  // written straight to out_dev
+  DBuf L(ctx.alloc, sizeof(double) * (size_t)x.r[1] * y.r[1]);
+  gemm(ctx, true, false, x.r[1], y.r[1], x.n[0], 1.0, x.c[0].d(), x.r[1], 0, y.c[0].d(), y.r[1], 0, 0.0, L.d(),
+       y.r[1], 0);
+  for (int k = 1; k < 3; ++k) {
     const int rx0 = x.r[k], rx1 = x.r[k + 1], ry0 = y.r[k], ry1 = y.r[k + 1], n = x.n[k];
     // T[b][i][a'] = sum_a L[a][b] x[a][i][a']   : (ry0 x rx0)^T-view * (rx0 x n rx1)
     DBuf T(ctx.alloc, sizeof(double) * (size_t)ry0 * n * rx1);
     gemm(ctx, true, false, ry0, n * rx1, rx0, 1.0, L.d(), ry0, 0, x.c[k].d(), (long)n * rx1, 0, 0.0,
          T.d(), (long)n * rx1, 0);
     // L'[a'][b'] = sum_{b,i} T[(b i)][a'] y[(b i)][b']
-    DBuf Ln(ctx.alloc, sizeof(double) * (size_t)rx1 * ry1);
-    gemm(ctx, true, false, rx1, ry1, ry0 * n, 1.0, T.d(), rx1, 0, y.c[k].d(), ry1, 0, 0.0, Ln.d(),
-         ry1, 0);
-    L = std::move(Ln);
+    DBuf Ln;
+    double* dst = out_dev;
+    if (k < 2) {
+      Ln = DBuf(ctx.alloc, sizeof(double) * (size_t)rx1 * ry1);
+      dst = Ln.d();
+    }
+    gemm(ctx, true, false, rx1, ry1, ry0 * n, 1.0, T.d(), rx1, 0, y.c[k].d(), ry1, 0, 0.0, dst, ry1, 0);
+    if (k < 2) L = std::move(Ln);
   }
-  copy(ctx, out_dev, L.d(), 1);
 }
 
 double tt_dot_sync(Context& ctx, const TT& x, const TT& y) {
@@ -369,6 +386,14 @@ double tt_dot_sync(Context& ctx, const TT& x, const TT& y) {
   tt_dot_dev(ctx, x, y, hd);
   ctx.sync();
   return ctx.host_scratch[0];
+}
+
+void tt_dots_sync(Context& ctx, const TT* const* x, const TT* const* y, int count, double* out) {
+  TTIGA_CHECK(count > 0 && count <= 8, TTIGA_E_ARG, "tt_dots_sync: 1..8 pairs");
+  double* hd = ctx.host_device(count);
+  for (int i = 0; i < count; ++i) tt_dot_dev(ctx, *x[i], *y[i], hd + i);
+  ctx.sync();
+  for (int i = 0; i < count; ++i) out[i] = ctx.host_scratch[i];
 }
 
 // Truncated SVD of B (r x M, row-major): B ~= U_s diag(S_s) Vt_s with orthonormal U_s
@@ -411,12 +436,11 @@ static TruncSVD truncated_svd_gram(Context& ctx, const double* B, int r, long M,
   o.U = DBuf(ctx.alloc, sizeof(double) * r * o.s);
   hipLaunchKernelGGL(k_copy_cols, dim3(grid_for((long)r * o.s)), dim3(256), 0, ctx.stream, V.d(), r, k, o.s,
                      o.U.d());
-  DBuf W(ctx.alloc, sizeof(double) * o.s * M), inv(ctx.alloc, sizeof(double) * o.s);
+  DBuf W(ctx.alloc, sizeof(double) * o.s * M);
   gemm(ctx, true, false, o.s, (int)M, r, 1.0, V.d(), k, 0, B, M, 0, 0.0, W.d(), M, 0);
-  hipLaunchKernelGGL(k_reciprocal, dim3((o.s + 255) / 256), dim3(256), 0, ctx.stream, o.S.d(), o.s, inv.d());
   o.Vt = DBuf(ctx.alloc, sizeof(double) * o.s * M);
-  hipLaunchKernelGGL(k_scale_rows, dim3(grid_for((long)o.s * M)), dim3(256), 0, ctx.stream, W.d(), o.s, M,
-                     inv.d(), o.Vt.d());
+  hipLaunchKernelGGL(k_scale_rows_inv, dim3(grid_for((long)o.s * M)), dim3(256), 0, ctx.stream, W.d(), o.s, M,
+                     o.S.d(), o.Vt.d());
   TTIGA_HIP(hipGetLastError());
   return o;
 }
