@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--family", type=int, default=64, help="requests of the batched family (0: skip)")
     ap.add_argument("--serve", type=int, default=48, help="requests per serving rate (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slabs", type=int, default=8)
+    ap.add_argument("--cpu-slabs", type=int, default=24)
     ap.add_argument("--workspace-gib", type=float, default=200.0)
     ap.add_argument("--single-only", action="store_true",
                     help="only the single-solve phase (value = its solve rate): the run whose kernel "
