@@ -179,7 +179,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed batches")
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256, help="basis functions per direction")
     ap.add_argument("--batch", type=int, default=16, help="problems per step")
     ap.add_argument("--lanes", type=int, default=16, help="concurrent executor lanes")
