@@ -18,9 +18,10 @@ descriptions (a few KB each) are host inputs; everything else happens on the dev
 Beside it the JSON line reports: the single-solve latency of the plain FP64 path with
 the roofline of its dominant kernel class (HIP events around every launch of that
 class, on the library's stream) and the TT-matvec rate; the mixed-precision (FP32
-operator, FP64 refinement) batch; the batched family (mixed sizes and geometries,
-FP32) with its throughput; Poisson-arrival serving of the same family with p50/p99
-latency; and, on request, the oracle's CPU rate on a bounded sample.
+operator, FP64 refinement) batch; the batched family (256 requests of mixed sizes and
+geometries, FP32) with its throughput; Poisson-arrival serving of requests drawn the same
+way with sizes up to n = 512, at 0.25x to 2x the family's throughput, with p50/p99 latency;
+and the oracle's CPU rate on a bounded sample.
 """
 import argparse
 import json
@@ -52,6 +53,14 @@ KERNEL_BOUND = {
     "assemble_cores": "alu",
 }
 SERVE_SEED = 2025_0913_05
+SERVE_SIZES = (32, 64, 128, 256, 512)
+# arrival rates as fractions of the measured batched-family throughput, a geometric sweep
+SERVE_RATES = (0.25, 0.5, 1.0, 2.0)
+# the n = 512 FP32 refinements reach ranks of about 360 in their corrections
+SERVE_MAX_RANK = 1024
+# tolerance of the family's assembly (eps / 100; its references: eps / 1000): on twisted boxes a
+# compressed operator that drops a singular value near eps = 1e-6 moves the solution by up to 1e-3
+ASSEMBLY_EPS = 1e-8
 # HBM bytes per dispatch of a kernel class measured by rocprofv3 --pmc on `bench.py
 # --single-only` (FETCH_SIZE scaled by the 1 GiB copy calibration, WRITE_SIZE), in KiB;
 # profiles/tsqr_factor_annulus_n256.md has the commands.  Valid only for the kernel code
@@ -183,8 +192,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="basis functions per direction")
     ap.add_argument("--batch", type=int, default=16, help="problems per step")
     ap.add_argument("--lanes", type=int, default=16, help="concurrent executor lanes")
-    ap.add_argument("--family", type=int, default=64, help="requests of the batched family (0: skip)")
-    ap.add_argument("--serve", type=int, default=48, help="requests per serving rate (0: skip)")
+    ap.add_argument("--family", type=int, default=256, help="requests of the batched family (0: skip)")
+    ap.add_argument("--serve", type=int, default=32, help="requests per serving rate (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=24)
     ap.add_argument("--workspace-gib", type=float, default=200.0)
@@ -373,8 +382,9 @@ def main():
     # 4. batched family (mixed sizes/geometries, FP32 mixed) and 5. serving of it
     if args.family > 0:
         log("batched family")
-        fam = W.c4_requests(count=args.family, precision=PREC_FP32)
-        fam_ref_pr = W.c4_requests(count=args.family, precision=PREC_FP64, eps=1e-7, tol=1e-8)
+        fam = W.c4_requests(count=args.family, precision=PREC_FP32, assembly_eps=ASSEMBLY_EPS)
+        fam_ref_pr = W.c4_requests(count=args.family, precision=PREC_FP64, eps=1e-7, tol=1e-8,
+                                   assembly_eps=ASSEMBLY_EPS / 10)
         t0 = time.perf_counter()
         fam_out = ctx.solve_batch(fam, lanes=args.lanes)
         fam_s = time.perf_counter() - t0
@@ -386,21 +396,31 @@ def main():
         out["batched_family"] = {"requests": args.family, "solves_per_s": sat, "passed": fam_ok,
                                  "rel_err_max": max(fam_err), "seconds": fam_s,
                                  "workload": "n in {32,64,128,256}, p in {2,3}, annulus sector or twisted box, "
-                                             "seeded Fourier source, FP32 mixed, seeds 10000+b"}
+                                             "seeded Fourier source, FP32 mixed, seeds 10000+b, "
+                                             f"TT eps 1e-6, assembly at {ASSEMBLY_EPS:g}"}
         if args.serve > 0:
-            sreqs = fam[:args.serve]
+            # the served requests: sizes n in {32..512}, otherwise drawn as the batched family
+            sreqs = W.c4_requests(count=args.serve, sizes=SERVE_SIZES, precision=PREC_FP32,
+                                  assembly_eps=ASSEMBLY_EPS, max_rank=SERVE_MAX_RANK)
+            log("serving references")
+            srefs = [u for _, u in ctx.solve_batch(
+                W.c4_requests(count=args.serve, sizes=SERVE_SIZES, precision=PREC_FP64, eps=1e-7, tol=1e-8,
+                              assembly_eps=ASSEMBLY_EPS / 10, max_rank=SERVE_MAX_RANK),
+                lanes=args.lanes)]
             lines = []
-            for frac in (0.5, 1.0):
+            for frac in SERVE_RATES:
                 log("serving at", frac, "x saturation")
                 res, sols, secs = serve(ctx, sreqs, frac * sat, args.lanes, SERVE_SEED)
                 serr = [tt_rel_diff(u, ur) if (u is not None and ur is not None) else float("inf")
-                        for u, ur in zip(sols, fam_refs[:args.serve])]
+                        for u, ur in zip(sols, srefs)]
                 lat_ms = [r["latency_ms"] for r in res]
                 lines.append({"rate_per_s": frac * sat, "solves_per_s": sum(e <= 1e-6 for e in serr) / secs,
                               "p50_ms": percentile(lat_ms, 50), "p99_ms": percentile(lat_ms, 99),
                               "mean_queue_ms": sum(r["queue_ms"] for r in res) / len(res),
                               "rel_err_max": max(serr)})
-            out["serving"] = {"requests": len(sreqs), "arrival": f"Poisson, seed {SERVE_SEED}", "rates": lines}
+            out["serving"] = {"requests": len(sreqs), "arrival": f"Poisson, seed {SERVE_SEED}",
+                              "workload": "n in {32,64,128,256,512}, otherwise as the batched family",
+                              "rates": lines}
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_slabs)

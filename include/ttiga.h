@@ -136,6 +136,12 @@ typedef struct {
                          column fibers, pivoted interpolation slices), verified on random
                          grid points, with TT-SVD as the fallback; TTIGA_COMPRESS_SVD (1):
                          TT-SVD of the whole (or streamed) Gauss-grid samples only */
+  double assembly_eps; /* 0: tt_eps; > 0: relative tolerance of the assembly alone (factor
+                         compression, the TT-rounded sums K and F, the lifted right-hand
+                         side), independent of the solve's roundings.  The solution of a
+                         non-separable geometry can move by far more than tt_eps when the
+                         compressed operator drops a small singular value, so callers that
+                         need the solution to about tt_eps set this well below it. */
 } ttiga_options;
 
 #define TTIGA_COMPRESS_AUTO 0

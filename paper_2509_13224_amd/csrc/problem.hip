@@ -134,6 +134,7 @@ Problem::Problem(Context* c, const ttiga_geometry* geo, const ttiga_discretizati
   // options
   opts = *opt;
   TTIGA_CHECK(opts.tt_eps > 0.0 && opts.tt_eps < 1.0, TTIGA_E_ARG, "tt_eps must be in (0, 1)");
+  TTIGA_CHECK(opts.assembly_eps >= 0.0 && opts.assembly_eps < 1.0, TTIGA_E_ARG, "assembly_eps must be in [0, 1)");
   TTIGA_CHECK(opts.rel_res_tol > 0.0, TTIGA_E_ARG, "rel_res_tol must be positive");
   TTIGA_CHECK(opts.max_iter > 0, TTIGA_E_ARG, "max_iter must be positive");
   TTIGA_CHECK(opts.precision == TTIGA_FP64 || opts.precision == TTIGA_FP32 || opts.precision == TTIGA_BF16,
@@ -260,7 +261,7 @@ bool Problem::compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, tti
   Context& c = *ctx;
   const int n0 = Q[0], n1 = Q[1], n2 = Q[2];
   const long M = (long)n1 * n2;
-  const double eps = opts.tt_eps;
+  const double eps = assembly_eps();
   uint64_t rs = c.rng_counter;
   auto rnd = [&](int hi) { return (int)(splitmix(rs) % (uint64_t)hi); };
   static const bool trace = [] {
@@ -447,7 +448,7 @@ void Problem::assemble(ttiga_assembly_stats* st) {
   const GeoDev gd = geo_dev(gtab_span, gtab_B, gtab_D);
   const SourceDev sd = source_dev();
   DBuf st8(c.alloc, sizeof(double) * 8);
-  const double eps = opts.tt_eps;
+  const double eps = assembly_eps();
   double t1 = 0.0;
   // norms, det J check and the compression thresholds from the 8 gathered statistics
   auto thresholds = [&](std::vector<double>& delta) {
@@ -614,7 +615,7 @@ void Problem::reduce_boundary() {
       launch_slice_vec(c, n[d], lo[d], ni[d], Kug.r[d], Kug.r[d + 1], Kug.c[d].d(), KugI.c[d].d());
     TT sum;
     tt_axpby(c, 1.0, FI, -1.0, KugI, sum);
-    tt_round(c, sum, opts.tt_eps * 1e-2, -1.0, opts.max_rank);
+    tt_round(c, sum, assembly_eps() * 1e-2, -1.0, opts.max_rank);
     rhs = std::move(sum);
   } else {
     rhs = std::move(FI);

@@ -58,6 +58,8 @@ struct Problem {
   size_t footprint_estimate() const;
 
  private:
+  // relative tolerance of the assembly (factor compression, rounded K and F)
+  double assembly_eps() const { return opts.assembly_eps > 0.0 ? opts.assembly_eps : opts.tt_eps; }
   bool compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, ttiga_assembly_stats& s);
   void solve_cg(ttiga_solve_stats& s);
   void solve_pcg(ttiga_solve_stats& s);

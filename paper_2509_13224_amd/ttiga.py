@@ -65,7 +65,8 @@ class Options(ctypes.Structure):
     _fields_ = [("tt_eps", ctypes.c_double), ("rel_res_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("max_rank", ctypes.c_int),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int),
-                ("sample_chunk_bytes", ctypes.c_size_t), ("compression", ctypes.c_int)]
+                ("sample_chunk_bytes", ctypes.c_size_t), ("compression", ctypes.c_int),
+                ("assembly_eps", ctypes.c_double)]
 
 
 class AssemblyStats(ctypes.Structure):
@@ -421,6 +422,7 @@ def describe(pr, precond=0):
     o.precond = precond
     o.sample_chunk_bytes = int(getattr(pr.options, "sample_chunk_bytes", 0))
     o.compression = int(getattr(pr.options, "compression", 0))
+    o.assembly_eps = float(getattr(pr.options, "assembly_eps", 0.0))
     return (g, disc, src, bc, o), keep
 
 

@@ -76,8 +76,9 @@ def small_problem(geometry, n, p, source, dirichlet=None, eps=1e-10, tol=1e-10, 
 
 
 def c4_requests(count=256, sizes=(32, 64, 128, 256), degrees=(2, 3), precision=PREC_FP32,
-                eps=1e-6, tol=1e-7):
-    """Request b draws n, p and a geometry (annulus sector or twisted box) from seed 10000+b."""
+                eps=1e-6, tol=1e-7, assembly_eps=0.0, max_rank=256):
+    """Request b draws n, p and a geometry (annulus sector or twisted box) from seed 10000+b.
+    assembly_eps (0: eps) is the tolerance of the assembly alone."""
     out = []
     for b in range(count):
         rng = np.random.default_rng(C4_SEED_BASE + b)
@@ -100,6 +101,7 @@ def c4_requests(count=256, sizes=(32, 64, 128, 256), degrees=(2, 3), precision=P
             disc=Discretization(degree=p, n_basis=(n, n, n), n_gauss=p + 1),
             source=src,
             dirichlet=_all_zero(),
-            options=Options(tt_eps=eps, rel_res_tol=tol, max_iter=400, precision=precision),
+            options=Options(tt_eps=eps, rel_res_tol=tol, max_iter=400, precision=precision,
+                            assembly_eps=assembly_eps, max_rank=max_rank),
         ))
     return out

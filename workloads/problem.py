@@ -93,6 +93,7 @@ class Options:
     refine: int = 1
     sample_chunk_bytes: int = 0  # 0: automatic; > 0: stream the Gauss-grid sampling in chunks
     compression: int = 0  # 0: cross approximation where it pays, verified, TT-SVD fallback; 1: TT-SVD only
+    assembly_eps: float = 0.0  # 0: tt_eps; > 0: tolerance of the assembly alone
 
 
 @dataclass
