@@ -223,3 +223,22 @@ def test_cross_compression(ctx, geo_name):
     say("cross", geo_name, "compare K, F")
     assert _tt_rel_dist(h.tt(ttiga.WHICH_K), h2.tt(ttiga.WHICH_K)) <= 20 * eps
     assert _tt_rel_dist(h.tt(ttiga.WHICH_F), h2.tt(ttiga.WHICH_F)) <= 20 * eps
+
+
+def test_assembly_eps_sets_operator_accuracy(ctx):
+    """assembly_eps governs the assembled K alone: a twisted box assembled at tt_eps = 1e-3 but
+    assembly_eps = 1e-10 matches the sparse oracle's K to 10 * 1e-10, while the same problem
+    assembled at tt_eps is further off."""
+    say("assembly_eps twisted_p3_n9")
+    geo = W.twisted_box(1.2)
+    errs = {}
+    for asm in (0.0, 1e-10):
+        pr = W.small_problem(geo, 9, 3, W.fourier_source(geo, 5), eps=1e-3)
+        pr.options.assembly_eps = asm
+        h = ctx.problem_create(pr)
+        h.assemble()
+        Kd = sparse_iga.assemble(pr)[0].toarray()
+        KT = banded_to_dense_cores(h.tt(0), pr.disc.degree)
+        errs[asm] = np.linalg.norm(tt.mat_full(KT) - Kd) / np.linalg.norm(Kd)
+    assert errs[1e-10] <= 1e-9
+    assert errs[0.0] > errs[1e-10]
