@@ -212,7 +212,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the TT-IGA solve here is a "
-              "single-device hot path; see DESIGN.md for how it would shard", file=sys.stderr)
+              "single-device hot path; independent solves would shard by request, one process per "
+              "GPU, with no communication", file=sys.stderr)
         sys.exit(2)
     # one hardware queue per lane plus the context's and torch's streams (HIP's default is 4,
     # and an environment may preset it; two streams on one queue serialise), raised before
