@@ -73,6 +73,22 @@ def test_round_error_bound_and_ranks(ctx, eps):
     assert tt.ranks(y) == tt.ranks(yo)
 
 
+def test_round_large_ranks_multilevel_tsqr(ctx):
+    """Ranks (40, 110) on a 40 x 60 x 120 grid: the 2400 x 110 unfolding takes the TSQR factor
+    in global memory (c > 96), a tree of three levels and a last panel of two columns; the
+    doubled train (ranks (80, 220)) rounds back to (40, 110) and equals 2x."""
+    say("round large ranks")
+    rng = np.random.default_rng(17)
+    x = rand_tt((40, 60, 120), (40, 110), rng)
+    X = tt.full(x)
+    y = ctx.tt_round(to_dev(x), 1e-12)
+    assert tt.ranks(y) == [1, 40, 110, 1]
+    assert np.linalg.norm(tt.full(y) - X) <= 1e-11 * np.linalg.norm(X)
+    z = ctx.tt_round(to_dev(tt.add(x, x)), 1e-12)
+    assert tt.ranks(z) == [1, 40, 110, 1]
+    assert np.linalg.norm(tt.full(z) - 2 * X) <= 1e-11 * np.linalg.norm(X)
+
+
 def test_round_wide_unfoldings(ctx):
     """Ranks above the mode sizes (wide unfoldings) reduce to the true ranks."""
     say("round wide")
