@@ -131,3 +131,29 @@ def test_validate_mixed_precision_rules():
         assert code == ttiga.TTIGA_E_ARG and "precond" in msg
     for pr in W.c4_requests(4):  # the batched family is FP32 by default
         assert ttiga.validate(pr, precond=1)[0] == ttiga.TTIGA_OK
+
+
+def test_validate_assembly_eps_range():
+    """assembly_eps: 0 (use tt_eps) or a tolerance in (0, 1); anything else is E_ARG."""
+    pr = W.c2_problem(n=64)
+    for ok in (0.0, 1e-9):
+        pr.options.assembly_eps = ok
+        assert ttiga.validate(pr)[0] == ttiga.TTIGA_OK
+    for bad in (-1e-9, 1.0, 2.0):
+        pr.options.assembly_eps = bad
+        code, msg = ttiga.validate(pr)
+        assert code == ttiga.TTIGA_E_ARG and "assembly_eps" in msg
+
+
+def test_c4_requests_follow_the_recipe():
+    """Request b is drawn from seed 10000 + b: n from the size set, p in {2, 3}, annulus sector or
+    twisted box about half each; the draws repeat, and the options reach every request."""
+    a, b = W.c4_requests(64), W.c4_requests(64)
+    assert [r.name for r in a] == [r.name for r in b]
+    assert {r.disc.n_basis[0] for r in a} == {32, 64, 128, 256}
+    assert {r.disc.degree for r in a} == {2, 3}
+    share = sum("annulus" in r.name for r in a) / len(a)
+    assert 0.3 < share < 0.7
+    s = W.c4_requests(32, sizes=(32, 64, 128, 256, 512), assembly_eps=1e-9, max_rank=1024)
+    assert any(r.disc.n_basis[0] == 512 for r in s)
+    assert all(r.options.assembly_eps == 1e-9 and r.options.max_rank == 1024 for r in s)
