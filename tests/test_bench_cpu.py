@@ -56,3 +56,15 @@ def test_cpu_baseline_reports_the_contract_fields():
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "solves/s"
     assert out["value"] > 0 and out["seconds_sampled"] > 0
     assert "1 of" in out["sample"]
+
+
+def test_roofline_entry_arithmetic():
+    """achieved = algorithmic work / time, frac = achieved / peak, the unit by the class's bound."""
+    st = {"total_ms": 2.0, "launches": 4, "flops": 4.0e9, "bytes": 8.0e9}
+    alu = bench.roofline_entry("tsqr_factor", st)
+    assert alu["bound"] == "alu" and alu["unit"] == "TFLOP/s"
+    assert abs(alu["achieved"] - 2.0) < 1e-12 and abs(alu["frac"] - 2.0 / 78.6) < 1e-12
+    assert abs(alu["avg_launch_us"] - 500.0) < 1e-9 and alu["algorithmic_per_launch"] == 1.0e9
+    hbm = bench.roofline_entry("tt_matvec_banded", st)
+    assert hbm["bound"] == "hbm" and hbm["unit"] == "GB/s"
+    assert abs(hbm["achieved"] - 4000.0) < 1e-9 and abs(hbm["frac"] - 0.5) < 1e-12
