@@ -18,7 +18,9 @@ Modules, each following the passage of the paper named in its header:
 * ``tt_iga``     - TT assembly of K and F and the TT solve (Sections 4.2-4.3)
 * ``errors``     - relative L2 error (eq. L2norm)
 
-Parity unpinned: nothing in this package; every function is pinned by a
+Parity unpinned: nothing in this package.  Every function is pinned by a
 ``-m "not gpu"`` test against closed forms, identities, library routines or
-brute force (see the test files named ``test_oracle_*``).
+brute force (the test files named ``test_oracle_*``): the error measures by
+integrals with closed forms on the annulus and the identity cube, the
+condition estimate by the extreme eigenvalues of the dense K_II.
 """

@@ -75,14 +75,3 @@ def greville(knots, p):
         return 0.5 * (knots[:-1] + knots[1:])[:n]
     return np.array([knots[i + 1:i + p + 1].mean() for i in range(n)])
 
-
-def check_open_knots(knots, p):
-    """Validate a knot vector of degree p: non-decreasing, end multiplicity p+1 on [0, 1] ends."""
-    knots = np.asarray(knots, dtype=np.float64)
-    if len(knots) < 2 * (p + 1):
-        return False
-    if np.any(np.diff(knots) < 0):
-        return False
-    if np.any(knots[:p + 1] != knots[0]) or np.any(knots[-(p + 1):] != knots[-1]):
-        return False
-    return knots[0] < knots[-1]

@@ -20,15 +20,18 @@ def _error_grid(problem, extra=3):
     return out
 
 
+def _volume_weights(grid, J):
+    """Quadrature weight of each grid point in physical space: w0 w1 w2 det J."""
+    return np.einsum("i,j,k->ijk", grid[0][2], grid[1][2], grid[2][2]) * np.linalg.det(J)
+
+
 def _fields(problem, u_coeff, exact):
     p = problem.disc.degree
     grid = _error_grid(problem)
     B = [bspline.basis(kn, p, nodes) for kn, nodes, _ in grid]
     uh = np.einsum("abc,ia,jb,kc->ijk", u_coeff, B[0], B[1], B[2], optimize=True)
     x, J = nurbs.solid_map_grid(problem.geometry, grid[0][1], grid[1][1], grid[2][1])
-    detJ = np.linalg.det(J)
-    W = np.einsum("i,j,k->ijk", grid[0][2], grid[1][2], grid[2][2]) * detJ
-    return uh, exact(x), W
+    return uh, exact(x), _volume_weights(grid, J)
 
 
 def rel_l2(problem, u_coeff, exact):

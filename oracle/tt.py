@@ -199,10 +199,6 @@ def mat_round(a, eps=None, delta=None):
     return tt_as_mat(round_(mat_as_tt(a), eps=eps, delta=delta), shapes)
 
 
-def mat_transpose(a):
-    return [M.transpose(0, 2, 1, 3) for M in a]
-
-
 def matvec(mcores, x):
     """y = K x in TT: cores y_k[(b, a), i, (b', a')] = sum_j M_k[b, i, j, b'] x_k[a, j, a']."""
     if mcores is None or x is None:

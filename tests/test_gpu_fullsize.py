@@ -181,7 +181,7 @@ def test_fullsize_factor_samples(assembled):
 
 def test_fullsize_manufactured_solve(ctx):
     """The C2 discretisation (annulus, degree 3, n = 256, TT eps 1e-6, tol 1e-7) with the
-    manufactured forcing of u = sin(pi r) sin(2 theta) sin(pi z) (Sec. 5.2), solved through the
+    manufactured forcing of u = sin(pi r) sin(2 theta) sin(pi z) (a closed form chosen for this test: it vanishes on the six faces of the quarter annulus; its forcing is -Laplace u), solved through the
     executor beside three C2 Fourier problems as in the bench's steps: the TT solution at 300
     random points of the solid against u itself.  At this mesh the discretisation error
     (O(h^4), about 1e-9) is far below the tolerances, so what is measured is the TT solve,
