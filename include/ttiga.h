@@ -220,14 +220,25 @@ int ttiga_problem_destroy(ttiga_problem* prob);
  * boundary reduction.  K and F stay on the device, owned by the problem. */
 int ttiga_assemble(ttiga_problem* prob, ttiga_assembly_stats* stats);
 
-/* TT solve of K_II u_I = F_I - K_IB u_B.  On E_NOTCONV the solution and stats are valid. */
+/* TT solve of the reduced system K_II u_I = F_I - K_IB u_B (Section 4.3) with the
+ * assembled TT operator and right-hand side; the paper solves it in TT format with
+ * AMEn (Section 4.1.2), this library by truncated TT-CG (precond = 0) or flexible
+ * preconditioned TT-CG (precond = 1), optionally inside FP64 iterative refinement
+ * (precision FP32/BF16).  The solution TT stays on the device, owned by the problem.
+ * Errors: E_STATE before ttiga_assemble; E_RANKCAP when a rounded TT needs more than
+ * max_rank; E_NOTCONV when the tolerance is not met in max_iter iterations (the
+ * solution and stats are still valid); E_HIP / E_OOM on device failures. */
 int ttiga_solve(ttiga_problem* prob, ttiga_solve_stats* stats);
 
-/* Ranks and mode sizes of the interior solution TT. */
+/* Ranks and mode sizes of the interior solution TT u_I (Section 4.1.1 format: ranks
+ * r_0 = 1, r_1, r_2, r_3 = 1, modes n_d - (number of Dirichlet faces in direction d)),
+ * so that a caller can size the buffer of ttiga_get_solution.  E_STATE before a solve. */
 int ttiga_solution_ranks(const ttiga_problem* prob, int ranks[4], int n[3]);
 
-/* Copy the interior solution cores, concatenated in paper order, to host
- * memory `dst` holding `count` doubles (E_ARG if too small). */
+/* The solution TT of Section 4.1.2 (the output of the solve): copies the interior
+ * cores, concatenated in paper order [r0][n1][r1] | [r1][n2][r2] | [r2][n3][r3],
+ * row-major FP64, into caller-owned host memory `dst` holding `count` doubles.
+ * E_ARG if dst is null or count is below the total; E_STATE before a solve. */
 int ttiga_get_solution(const ttiga_problem* prob, double* dst, size_t count);
 
 /* Which TT of an assembled problem a query refers to. */
@@ -255,6 +266,22 @@ int ttiga_sample_factors(ttiga_problem* prob, const double* pts, size_t count, d
 /* Standalone banded TT-matvec y = K x on caller device data: y is written to a
  * library-owned TT (ranks r_K * r_x), returned in *out (free with ttiga_tt_free). */
 int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view* x, ttiga_tt** out);
+
+/* Dense FP64 product C[b] = alpha op(A[b]) op(B[b]) + beta C[b] on the context stream:
+ * the kernel behind the core contractions of this library (TT-matrix x TT-vector,
+ * Section 4.1.1; the QR/SVD products of TT-rounding), exposed for parity tests and tile
+ * tuning.  Row-major device operands: op(A) is M x K (A stored M x K with leading
+ * dimension lda, or K x M when ta != 0), op(B) is K x N (B stored K x N with ldb, or
+ * N x K when tb != 0), C is M x N with ldc; batch >= 1 products at element strides sA,
+ * sB, sC.  plan: NULL for the library's shape rule, else {bm, bn, splits} with (bm, bn)
+ * one of (64, 64), (128, 64), (64, 128) and 1 <= splits <= K (the contraction cut into
+ * that many chunks of a multiple of 32, partials summed in chunk order).  Synchronises
+ * the stream.  E_ARG on null pointers, M, N, K or batch < 1, a leading dimension shorter
+ * than a row, or a plan outside that set; the partial-tile workspace of a split product
+ * comes from the context's allocator (E_OOM). */
+int ttiga_gemm_f64(ttiga_ctx* ctx, int ta, int tb, int M, int N, int K, double alpha, const double* A,
+                   long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+                   long sC, int batch, const int* plan);
 
 /* The same product with the operator cores rounded to dtype (TTIGA_FP32 or TTIGA_BF16,
  * round to nearest even; BF16 through FP32), the vector cores to FP32, FP32 products

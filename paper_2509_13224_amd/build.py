@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libttiga.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_linalg.hip", "tt_ops.hip", "tt_matvec_round.hip", "kernels_iga.hip", "precond.hip", "problem.hip", "engine.hip", "capi.hip"]
+SOURCES = ["gemm_f64.hip", "kernels_linalg.hip", "tt_ops.hip", "tt_matvec_round.hip", "kernels_iga.hip", "precond.hip", "problem.hip", "engine.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -42,8 +42,7 @@ def build(verbose=False):
                 print(err, file=sys.stderr)
     objs = [o for o, _ in results]
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lrocblas",
-           "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -150,7 +150,6 @@ void DeviceAllocator::release(void* p) {
 }
 
 Context::~Context() {
-  release_blas(blas);
   if (sync_event) (void)hipEventDestroy(sync_event);
   if (host_scratch) (void)hipHostFree(host_scratch);
 }
@@ -465,6 +464,36 @@ int ttiga_sample_factors(ttiga_problem* prob, const double* pts, size_t count, d
     TTIGA_CHECK(prob != nullptr, TTIGA_E_ARG, "null problem");
     TTIGA_HIP(hipSetDevice(prob->impl->ctx->device));
     prob->impl->sample_points(pts, count, out, det_out);
+  });
+}
+
+int ttiga_gemm_f64(ttiga_ctx* ctx, int ta, int tb, int M, int N, int K, double alpha, const double* A,
+                   long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+                   long sC, int batch, const int* plan) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && A && B && C, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(M >= 1 && N >= 1 && K >= 1 && batch >= 1, TTIGA_E_ARG, "gemm: sizes must be positive");
+    TTIGA_CHECK(lda >= (ta ? M : K) && ldb >= (tb ? K : N) && ldc >= N, TTIGA_E_ARG,
+                "gemm: leading dimension shorter than a row");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    GemmPlan g = gemm_plan(M, N, K, batch);
+    if (plan) {
+      const bool tile_ok = (plan[0] == 64 && plan[1] == 64) || (plan[0] == 128 && plan[1] == 64) ||
+                           (plan[0] == 64 && plan[1] == 128);
+      TTIGA_CHECK(tile_ok && plan[2] >= 1 && plan[2] <= K, TTIGA_E_ARG, "gemm: unknown plan");
+      g.bm = plan[0];
+      g.bn = plan[1];
+      int kchunk = (K + plan[2] - 1) / plan[2];
+      kchunk = (kchunk + 31) / 32 * 32;
+      g.kchunk = kchunk;
+      g.splits = (K + kchunk - 1) / kchunk;
+    }
+    DBuf part;
+    if (g.splits > 1) part = DBuf(c.alloc, sizeof(double) * gemm_part_doubles(g, M, N, batch));
+    gemm_planned(c, g, ta != 0, tb != 0, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
+                 part.d());
+    c.sync();
   });
 }
 

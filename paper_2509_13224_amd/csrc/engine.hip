@@ -74,7 +74,9 @@ Job* Engine::pick_locked() {
     queue_.erase(it);
     return j;
   };
-  if (queue_.front()->footprint <= free_bytes) return take(queue_.begin());
+  // with nothing running the head always starts: only resident solutions can hold the
+  // pool then, and waiting would wait for a release that may never come
+  if (queue_.front()->footprint <= free_bytes || running_ == 0) return take(queue_.begin());
   if (queue_.front()->bypassed >= kMaxBypass) return nullptr;
   for (auto it = queue_.begin() + 1; it != queue_.end(); ++it) {
     if ((*it)->footprint <= free_bytes) {
@@ -126,7 +128,9 @@ void Engine::worker(int index) {
     run(*j, lane, index);
     {
       std::lock_guard<std::mutex> lk(mu_);
+      // the arena is back in the pool; the resident solution stays charged until release
       reserved_ -= j->footprint;
+      reserved_ += j->resident_bytes;
       running_ -= 1;
       j->state = 2;
     }
@@ -144,13 +148,18 @@ void Engine::run(Job& j, Lane& lane, int index) {
   int code = TTIGA_OK;
   std::string msg;
   {
-    // the arena: wait for running problems to hand memory back when the pool is too
-    // fragmented; run on spills alone only when nothing else is running
+    // the arena: when the pool is too fragmented, wait for a running problem that is not
+    // itself waiting to hand memory back (a finished problem or a released solution wakes
+    // the waiters); with no such problem, run on spills from the pool (E_OOM if they fail)
     DBuf chunk;
     {
       std::unique_lock<std::mutex> lk(mu_);
       void* p = nullptr;
-      while (!(p = pool_.try_alloc(j.footprint)) && running_ > 1) cv_done_.wait(lk);
+      while (!(p = pool_.try_alloc(j.footprint)) && running_ - arena_waiters_ > 1) {
+        arena_waiters_ += 1;
+        cv_done_.wait(lk);
+        arena_waiters_ -= 1;
+      }
       if (p) {
         chunk.a = &pool_;
         chunk.p = p;
@@ -187,6 +196,7 @@ void Engine::run(Job& j, Lane& lane, int index) {
         const size_t bytes = sizeof(double) * u.core_elems(k);
         if (!bytes) continue;
         s.c[k] = DBuf(&pool_, bytes);
+        j.resident_bytes += bytes;
         TTIGA_HIP(hipMemcpyAsync(s.c[k].p, u.c[k].p, bytes, hipMemcpyDeviceToDevice, c.stream));
       }
       c.sync();
@@ -201,7 +211,10 @@ void Engine::run(Job& j, Lane& lane, int index) {
       msg = e.what();
     }
     (void)hipStreamSynchronize(c.stream);
-    if (code != TTIGA_OK && code != TTIGA_E_NOTCONV) j.solution.set_zero(j.solution.n);
+    if (code != TTIGA_OK && code != TTIGA_E_NOTCONV) {
+      j.solution.set_zero(j.solution.n);
+      j.resident_bytes = 0;
+    }
     r.assembly.status = P.assembled ? TTIGA_OK : code;
     r.peak_bytes = arena.high_water();
     j.prob.reset();  // its buffers go back to the arena (the stream has drained)
@@ -256,16 +269,26 @@ const TT& Engine::solution(unsigned long long ticket) {
 
 void Engine::release(unsigned long long ticket) {
   std::unique_ptr<Job> dead;
+  size_t dead_bytes = 0;
   {
     std::lock_guard<std::mutex> lk(mu_);
     auto it = jobs_.find(ticket);
     TTIGA_CHECK(it != jobs_.end(), TTIGA_E_ARG, "unknown ticket");
     TTIGA_CHECK(it->second->state == 2, TTIGA_E_STATE, "request still pending");
+    dead_bytes = it->second->resident_bytes;
     dead = std::move(it->second);
     jobs_.erase(it);
   }
   // copies of the solution on the root stream are complete before its memory is reused
   root_->sync();
+  dead.reset();
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    reserved_ -= std::min(reserved_, dead_bytes);
+  }
+  // the solution's memory is back in the pool: waiting arenas and queued problems retry
+  cv_done_.notify_all();
+  cv_work_.notify_all();
 }
 
 void Engine::wait_all() {

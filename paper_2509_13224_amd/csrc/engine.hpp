@@ -19,6 +19,7 @@ struct Job {
   int bypassed = 0;  // later problems that started while this one waited at the head
   ttiga_result res{};
   TT solution;  // in the pool, resident until the job is released
+  size_t resident_bytes = 0;  // the solution's bytes, charged to admission until release
   double t_submit = 0.0, t_start = 0.0;
 };
 
@@ -60,9 +61,12 @@ class Engine {
   std::mutex mu_;
   std::condition_variable cv_work_, cv_done_;
   std::deque<Job*> queue_;
+  // reserved_: footprints of running problems plus the bytes of resident solutions
   size_t budget_ = 0, reserved_ = 0;
   unsigned long long next_ticket_ = 1;
-  int max_queue_ = 0, running_ = 0;
+  // running_: problems started and not finished; arena_waiters_: those of them blocked
+  // until memory comes back to the pool
+  int max_queue_ = 0, running_ = 0, arena_waiters_ = 0;
   bool stop_ = false;
 };
 

@@ -1,0 +1,260 @@
+// FP64 GEMM for the TT contractions and TT-rounding products on gfx950.
+//
+// C[b] = alpha op(A[b]) op(B[b]) + beta C[b] with row-major operands.  One kernel,
+// v_mfma_f64_16x16x4 on tiles of BM x BN (64x64, 128x64 or 64x128) per workgroup of four
+// 64-wide waves (2 x 2, each owning a (BM/2) x (BN/2) sub-tile), the contraction staged
+// through LDS 32 at a time.  The next K step's global loads are issued before the current
+// step's MFMAs, so a workgroup keeps one step of loads in flight while it computes (the
+// products here are mostly short contractions over a few hundred, where one exposed
+// global round trip per step would dominate).  LDS layouts follow the global layout of
+// each operand (row-major A is staged m-major, transposed A k-major, and the same for B),
+// so the staging writes and the MFMA operand reads both hit distinct banks.
+//
+// Which tile and how many K splits a product takes is a pure function of its shape
+// (gemm_plan): the same product runs the same code, with the same summation order, in
+// every problem, process and mix.  K splits write partial tiles that a second kernel adds
+// in a fixed order; there are no atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "runtime.hpp"
+
+namespace ttiga {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kGK = 32;  // contraction step staged in LDS
+
+// LDS row lengths: an m-major (n-major) tile has rows of kGK + 2 doubles; a k-major tile rows
+// of BM + 16 (BN + 16).  Both make the 16-lane groups of an MFMA operand read (and a staging
+// write) fall on distinct banks.
+template <bool KMajor, int BX>
+struct TileLds {
+  static constexpr int kRows = KMajor ? kGK : BX;
+  static constexpr int kLd = KMajor ? BX + 16 : kGK + 2;
+  static constexpr int kElems = kRows * kLd;
+  // element (x, k) of the tile, x along M (or N)
+  __device__ static int at(int x, int k) { return KMajor ? k * kLd + x : x * kLd + k; }
+};
+
+template <bool TA, bool TB, int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double alpha,
+                                                  const double* __restrict__ A, long lda, long sA,
+                                                  const double* __restrict__ B, long ldb, long sB,
+                                                  double beta, double* __restrict__ C, long ldc,
+                                                  long sC, int splits, int kchunk,
+                                                  double* __restrict__ Cpart) {
+  // A is staged k-major when it is stored transposed (K x M), m-major otherwise; B k-major
+  // when stored K x N, n-major when transposed
+  using LA = TileLds<TA, BM>;
+  using LB = TileLds<!TB, BN>;
+  constexpr int kLoadA = BM * kGK / 256;
+  constexpr int kLoadB = BN * kGK / 256;
+  constexpr int MI = BM / 32, NI = BN / 32;  // 16 x 16 blocks per wave
+  __shared__ double As[LA::kElems];
+  __shared__ double Bs[LB::kElems];
+
+  const int bz = blockIdx.z;
+  const int batch = bz / splits, split = bz % splits;
+  A += batch * sA;
+  B += batch * sB;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+
+  // (x, k) of the e-th element a thread stages: consecutive threads along the operand's
+  // contiguous global index
+  auto a_xk = [&](int e, int& x, int& k) {
+    if (TA) { x = e % BM; k = e / BM; } else { k = e % kGK; x = e / kGK; }
+  };
+  auto b_xk = [&](int e, int& x, int& k) {
+    if (TB) { k = e % kGK; x = e / kGK; } else { x = e % BN; k = e / BN; }
+  };
+  double ra[kLoadA], rb[kLoadB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < kLoadA; ++i) {
+      int x, k;
+      a_xk(tid + 256 * i, x, k);
+      const int gm = m0 + x, gk = k0 + k;
+      ra[i] = (gm < M && gk < kend) ? (TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk]) : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kLoadB; ++i) {
+      int x, k;
+      b_xk(tid + 256 * i, x, k);
+      const int gn = n0 + x, gk = k0 + k;
+      rb[i] = (gn < N && gk < kend) ? (TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn]) : 0.0;
+    }
+  };
+
+  d4_t acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kGK) {
+    __syncthreads();  // the previous step's operand reads are done
+#pragma unroll
+    for (int i = 0; i < kLoadA; ++i) {
+      int x, k;
+      a_xk(tid + 256 * i, x, k);
+      As[LA::at(x, k)] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kLoadB; ++i) {
+      int x, k;
+      b_xk(tid + 256 * i, x, k);
+      Bs[LB::at(x, k)] = rb[i];
+    }
+    __syncthreads();
+    if (k0 + kGK < kend) load(k0 + kGK);  // in flight during this step's MFMAs
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4) {
+      // operand layout of the 16x16x4 f64 MFMA: lane holds row (lane & 15) of A and column
+      // (lane & 15) of B at contraction index lane >> 4
+      const int kr = kk + (lane >> 4);
+      double a[MI], b[NI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) a[i] = As[LA::at(wm + 16 * i + (lane & 15), kr)];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) b[j] = Bs[LB::at(wn + 16 * j + (lane & 15), kr)];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // D layout of the 16x16x4 f64 MFMA: lane holds column (lane & 15) of rows (lane >> 4) + 4 v
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + 16 * i + (lane >> 4) + 4 * v;
+        const int col = n0 + wn + 16 * j + (lane & 15);
+        if (row < M && col < N) {
+          const double s = acc[i][j][v];
+          if (splits == 1) {
+            double* c = C + batch * sC + (long)row * ldc + col;
+            *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
+          } else {
+            Cpart[((long)bz * M + row) * N + col] = s;
+          }
+        }
+      }
+}
+
+// C = alpha * (sum of the K-split partial tiles, in split order) + beta C
+__global__ void k_splitk_reduce(int M, int N, int splits, int batches, double alpha,
+                                const double* __restrict__ Cpart, double beta, double* C, long ldc,
+                                long sC) {
+  const long total = (long)batches * M * N;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e / ((long)M * N);
+    const long rc = e % ((long)M * N);
+    const int row = rc / N, col = rc % N;
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += Cpart[((long)(b * splits + k) * M + row) * N + col];
+    double* c = C + b * sC + (long)row * ldc + col;
+    *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
+  }
+}
+
+GemmPlan gemm_plan(int M, int N, int K, int batch) {
+  GemmPlan g;
+  // a 128-wide tile where the other dimension is long and this one fits in 65..128: the
+  // long operand is then streamed once instead of twice
+  if (M > 64 && M <= 128 && N > 128) g.bm = 128;
+  else if (N > 64 && N <= 128 && M > 128) g.bn = 128;
+  const long tiles = (long)((M + g.bm - 1) / g.bm) * ((N + g.bn - 1) / g.bn) * batch;
+  // long contractions on grids that cannot fill the device are split (partials summed by a
+  // second kernel in split order); at most 256 rows of K per split, about 512 workgroups
+  if (tiles < 256 && K >= 512) {
+    long s = std::min<long>((K + 255) / 256, std::max<long>(1, 512 / tiles));
+    int kchunk = (int)((K + s - 1) / s);
+    kchunk = (kchunk + kGK - 1) / kGK * kGK;
+    g.splits = (K + kchunk - 1) / kchunk;
+    g.kchunk = kchunk;
+  } else {
+    g.splits = 1;
+    g.kchunk = K;
+  }
+  return g;
+}
+
+template <int BM, int BN>
+static void launch_tile(Context& ctx, const GemmPlan& g, bool ta, bool tb, int M, int N, int K,
+                        double alpha, const double* A, long lda, long sA, const double* B, long ldb,
+                        long sB, double beta, double* C, long ldc, long sC, int batch, double* part) {
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch * g.splits);
+  dim3 block(256);
+#define TTIGA_GEMM_LAUNCH(TA, TB)                                                                   \
+  hipLaunchKernelGGL((k_gemm_f64<TA, TB, BM, BN>), grid, block, 0, ctx.stream, M, N, K, alpha, A, lda, \
+                     sA, B, ldb, sB, beta, C, ldc, sC, g.splits, g.kchunk, part)
+  if (!ta && !tb) TTIGA_GEMM_LAUNCH(false, false);
+  else if (ta && !tb) TTIGA_GEMM_LAUNCH(true, false);
+  else if (!ta && tb) TTIGA_GEMM_LAUNCH(false, true);
+  else TTIGA_GEMM_LAUNCH(true, true);
+#undef TTIGA_GEMM_LAUNCH
+  TTIGA_HIP(hipGetLastError());
+}
+
+void gemm_planned(Context& ctx, const GemmPlan& g, bool ta, bool tb, int M, int N, int K, double alpha,
+                  const double* A, long lda, long sA, const double* B, long ldb, long sB, double beta,
+                  double* C, long ldc, long sC, int batch, double* part) {
+  TTIGA_CHECK(batch <= 65535 / std::max(1, g.splits), TTIGA_E_ARG, "gemm: batch too large");
+  TTIGA_CHECK((M + g.bm - 1) / g.bm <= 65535, TTIGA_E_ARG, "gemm: M too large for the grid");
+  ProfScope prof(ctx, "gemm_f64", 2.0 * M * N * (double)K * batch,
+                 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N));
+  if (g.bm == 128) launch_tile<128, 64>(ctx, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
+  else if (g.bn == 128) launch_tile<64, 128>(ctx, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
+  else launch_tile<64, 64>(ctx, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
+  if (g.splits > 1) {
+    const long total = (long)batch * M * N;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(total)), dim3(256), 0, ctx.stream, M, N, g.splits,
+                       batch, alpha, part, beta, C, ldc, sC);
+    TTIGA_HIP(hipGetLastError());
+  }
+}
+
+size_t gemm_part_doubles(const GemmPlan& g, int M, int N, int batch) {
+  return g.splits > 1 ? (size_t)batch * g.splits * M * N : 0;
+}
+
+__global__ void k_scale_matrix(int M, int N, double beta, double* C, long ldc, long sC, int batch) {
+  const long total = (long)batch * M * N;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e / ((long)M * N);
+    const long rc = e % ((long)M * N);
+    double* c = C + b * sC + (rc / N) * ldc + rc % N;
+    *c = (beta == 0.0) ? 0.0 : beta * (*c);
+  }
+}
+
+void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+          long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+          long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0) {  // C = beta C
+    hipLaunchKernelGGL(k_scale_matrix, dim3(grid_for((long)batch * M * N)), dim3(256), 0, ctx.stream, M, N,
+                       beta, C, ldc, sC, batch);
+    TTIGA_HIP(hipGetLastError());
+    return;
+  }
+  const GemmPlan g = gemm_plan(M, N, K, batch);
+  DBuf part;
+  if (g.splits > 1) part = DBuf(ctx.alloc, sizeof(double) * gemm_part_doubles(g, M, N, batch));
+  gemm_planned(ctx, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part.d());
+}
+
+}  // namespace ttiga

@@ -1,21 +1,17 @@
 // Dense FP64 linear algebra for TT contractions and TT-rounding on gfx950.
 //
-//  * gemm: 64x64 workgroup tiles of v_mfma_f64_16x16x4 (four 64-wide waves,
-//    each owning a 32x32 sub-tile), K staged through LDS 16 at a time, split-K
-//    with a deterministic second-stage reduction for the tall-skinny Gram
-//    products (A^T A with a long contraction) that dominate rounding.
 //  * qr_tall: Householder QR as a tree over row blocks (TSQR), each block
 //    factored in LDS by one workgroup; exact orthogonality also for the
 //    rank-deficient unfoldings that TT sums produce.
 //  * svd_small: one-sided (Hestenes) Jacobi in a single workgroup, round-robin
 //    pair ordering so every wave rotates a disjoint column pair each round.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -24,267 +20,6 @@
 #include "runtime.hpp"
 
 namespace ttiga {
-
-typedef double d4_t __attribute__((ext_vector_type(4)));
-
-constexpr int GT = 64;  // workgroup tile edge
-constexpr int GK = 16;  // K step staged in LDS
-
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double alpha,
-                                                  const double* __restrict__ A, long lda, long sA,
-                                                  const double* __restrict__ B, long ldb, long sB,
-                                                  double beta, double* __restrict__ C, long ldc,
-                                                  long sC, int splits, int kchunk,
-                                                  double* __restrict__ Cpart) {
-  const int bz = blockIdx.z;
-  const int batch = bz / splits, split = bz % splits;
-  A += batch * sA;
-  B += batch * sB;
-  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  const int kbeg = split * kchunk;
-  const int kend = min(K, kbeg + kchunk);
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  d4_t acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-
-  for (int k0 = kbeg; k0 < kend; k0 += GK) {
-    for (int e = tid; e < GT * GK; e += 256) {
-      int mm, kk;
-      if (TA) { kk = e / GT; mm = e % GT; } else { mm = e / GK; kk = e % GK; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < M && gk < kend) v = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
-      As[kk][mm] = v;
-    }
-    for (int e = tid; e < GT * GK; e += 256) {
-      int nn, kk;
-      if (TB) { nn = e / GK; kk = e % GK; } else { kk = e / GT; nn = e % GT; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < N && gk < kend) v = TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      const double a0 = As[kr][wm + (lane & 15)];
-      const double a1 = As[kr][wm + 16 + (lane & 15)];
-      const double b0 = Bs[kr][wn + (lane & 15)];
-      const double b1 = Bs[kr][wn + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  // D layout of the 16x16x4 f64 MFMA: lane holds column (lane & 15) of rows (lane >> 4) + 4 v.
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm + 16 * i + (lane >> 4) + 4 * v;
-        const int col = n0 + wn + 16 * j + (lane & 15);
-        if (row < M && col < N) {
-          const double a = acc[i][j][v];
-          if (splits == 1) {
-            double* c = C + batch * sC + (long)row * ldc + col;
-            *c = (beta == 0.0) ? alpha * a : alpha * a + beta * (*c);
-          } else {
-            Cpart[((long)bz * M + row) * N + col] = a;
-          }
-        }
-      }
-}
-
-__global__ void k_splitk_reduce(int M, int N, int splits, int batches, double alpha,
-                                const double* __restrict__ Cpart, double beta, double* C, long ldc,
-                                long sC) {
-  const long total = (long)batches * M * N;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    const int b = e / ((long)M * N);
-    const long rc = e % ((long)M * N);
-    const int row = rc / N, col = rc % N;
-    double s = 0.0;
-    for (int k = 0; k < splits; ++k) s += Cpart[((long)(b * splits + k) * M + row) * N + col];
-    double* c = C + b * sC + (long)row * ldc + col;
-    *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
-  }
-}
-
-// The hand-written kernel; split_scale multiplies the number of K splits chosen for
-// grids of fewer than 256 tiles.
-static void gemm_hand(Context& ctx, int split_scale, bool ta, bool tb, int M, int N, int K, double alpha,
-                      const double* A, long lda, long sA, const double* B, long ldb, long sB, double beta,
-                      double* C, long ldc, long sC, int batch) {
-  const int tm = (M + GT - 1) / GT, tn = (N + GT - 1) / GT;
-  const long tiles = (long)tm * tn * batch;
-  int splits = 1;
-  if (tiles < 256 && K > 256) {
-    splits = (int)std::min<long>((K + 255) / 256, std::max<long>(1, 512 / tiles));
-    splits = (int)std::min<long>((long)splits * split_scale, (K + GK - 1) / GK);
-  }
-  int kchunk = (K + splits - 1) / splits;
-  kchunk = (kchunk + GK - 1) / GK * GK;
-  splits = (K + kchunk - 1) / kchunk;
-  DBuf part;
-  if (splits > 1) part = DBuf(ctx.alloc, sizeof(double) * (size_t)batch * splits * M * N);
-  ProfScope prof(ctx, "gemm_f64", 2.0 * M * N * (double)K * batch,
-                 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N));
-  dim3 grid(tn, tm, batch * splits);
-  dim3 block(256);
-#define TTIGA_GEMM_LAUNCH(TA, TB)                                                                 \
-  hipLaunchKernelGGL((k_gemm_f64<TA, TB>), grid, block, 0, ctx.stream, M, N, K, alpha, A, lda, sA, \
-                     B, ldb, sB, beta, C, ldc, sC, splits, kchunk, part.d())
-  if (!ta && !tb) TTIGA_GEMM_LAUNCH(false, false);
-  else if (ta && !tb) TTIGA_GEMM_LAUNCH(true, false);
-  else if (!ta && tb) TTIGA_GEMM_LAUNCH(false, true);
-  else TTIGA_GEMM_LAUNCH(true, true);
-#undef TTIGA_GEMM_LAUNCH
-  TTIGA_HIP(hipGetLastError());
-  if (splits > 1) {
-    const long total = (long)batch * M * N;
-    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(total)), dim3(256), 0, ctx.stream, M, N, splits,
-                       batch, alpha, part.d(), beta, C, ldc, sC);
-    TTIGA_HIP(hipGetLastError());
-  }
-}
-
-// rocBLAS handle of a context, created on first use, bound to the context's stream, with
-// atomics disabled so that reductions keep a fixed order.
-static rocblas_handle blas_handle(Context& ctx) {
-  if (!ctx.blas) {
-    rocblas_handle h = nullptr;
-    TTIGA_CHECK(rocblas_create_handle(&h) == rocblas_status_success, TTIGA_E_HIP, "rocblas_create_handle failed");
-    rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
-    ctx.blas = h;
-  }
-  rocblas_handle h = static_cast<rocblas_handle>(ctx.blas);
-  TTIGA_CHECK(rocblas_set_stream(h, ctx.stream) == rocblas_status_success, TTIGA_E_HIP, "rocblas_set_stream failed");
-  return h;
-}
-
-void release_blas(void* handle) {
-  if (handle) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
-}
-
-// rocBLAS dgemm on the row-major operands: a row-major X is the column-major X^T, so
-// C^T = op(B)^T op(A)^T is one column-major product with the operands swapped.
-static void gemm_blas(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
-                      long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
-                      long sC, int batch) {
-  rocblas_handle h = blas_handle(ctx);
-  ProfScope prof(ctx, "gemm_f64_blas", 2.0 * M * N * (double)K * batch,
-                 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N));
-  const rocblas_operation opB = tb ? rocblas_operation_transpose : rocblas_operation_none;
-  const rocblas_operation opA = ta ? rocblas_operation_transpose : rocblas_operation_none;
-  rocblas_status st;
-  if (batch == 1)
-    st = rocblas_dgemm(h, opB, opA, N, M, K, &alpha, B, (int)ldb, A, (int)lda, &beta, C, (int)ldc);
-  else
-    st = rocblas_dgemm_strided_batched(h, opB, opA, N, M, K, &alpha, B, (int)ldb, sB, A, (int)lda, sA, &beta, C,
-                                       (int)ldc, sC, batch);
-  TTIGA_CHECK(st == rocblas_status_success, TTIGA_E_HIP, std::string("rocblas_dgemm: ") + rocblas_status_to_string(st));
-}
-
-// Autotuner: GEMM shapes fall into buckets (transposes, ceil log2 of M, N, K, batched);
-// the first call of a bucket with beta = 0 times every implementation on its own operands
-// (one untimed and one timed run each, HIP events on the context stream) and the fastest
-// serves the bucket from then on (and recomputes this call's result if it did not run
-// last).  The table is process-wide and filled under a lock, so every problem, alone or
-// among others, uses the same implementation for the same shape.  TTIGA_GEMM=hand or
-// =blas pins the choice.
-namespace {
-enum GemmImpl { kGemmHand = 0, kGemmHandDeep = 1, kGemmBlas = 2, kGemmImpls = 3 };
-struct GemmTuner {
-  std::mutex mu;
-  std::map<std::array<int, 6>, int> choice;
-};
-GemmTuner& gemm_tuner() {
-  static GemmTuner t;
-  return t;
-}
-int ceil_log2(long v) {
-  int b = 0;
-  while ((1L << b) < v) ++b;
-  return b;
-}
-int pinned_impl() {
-  static const int v = [] {
-    const char* e = std::getenv("TTIGA_GEMM");
-    if (e && std::strcmp(e, "hand") == 0) return (int)kGemmHand;
-    if (e && std::strcmp(e, "blas") == 0) return (int)kGemmBlas;
-    return -1;
-  }();
-  return v;
-}
-}  // namespace
-
-void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
-          long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
-          long sC, int batch) {
-  if (M <= 0 || N <= 0 || batch <= 0) return;
-  if (K <= 0) {
-    // C = beta * C
-    if (beta == 0.0) {
-      for (int b = 0; b < batch; ++b)
-        TTIGA_HIP(hipMemset2DAsync(C + b * sC, ldc * sizeof(double), 0, N * sizeof(double), M,
-                                   ctx.stream));
-      return;
-    }
-    throw Error(TTIGA_E_ARG, "gemm with K=0 and beta!=0 unsupported");
-  }
-  auto run = [&](int impl) {
-    if (impl == kGemmBlas)
-      gemm_blas(ctx, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
-    else
-      gemm_hand(ctx, impl == kGemmHandDeep ? 4 : 1, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc,
-                sC, batch);
-  };
-  if (pinned_impl() >= 0) return run(pinned_impl());
-  const std::array<int, 6> key = {(ta ? 1 : 0) + (tb ? 2 : 0), ceil_log2(M), ceil_log2(N), ceil_log2(K),
-                                  batch > 1 ? 1 : 0, 0};
-  GemmTuner& T = gemm_tuner();
-  std::unique_lock<std::mutex> lk(T.mu);
-  auto it = T.choice.find(key);
-  if (it != T.choice.end()) {
-    const int impl = it->second;
-    lk.unlock();
-    return run(impl);
-  }
-  if (beta != 0.0) {
-    lk.unlock();
-    return run(kGemmHand);
-  }
-  hipEvent_t e0, e1;
-  TTIGA_HIP(hipEventCreate(&e0));
-  TTIGA_HIP(hipEventCreate(&e1));
-  float best_ms = 0.f;
-  int best = kGemmHand;
-  for (int impl = 0; impl < kGemmImpls; ++impl) {
-    run(impl);
-    TTIGA_HIP(hipEventRecord(e0, ctx.stream));
-    run(impl);
-    TTIGA_HIP(hipEventRecord(e1, ctx.stream));
-    TTIGA_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    TTIGA_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (impl == 0 || ms < best_ms) {
-      best_ms = ms;
-      best = impl;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (best != kGemmImpls - 1) run(best);
-  T.choice[key] = best;
-}
 
 // ------------------------------------------------------- Householder TSQR
 // Householder QR of a tall m x c matrix as a tree (TSQR): the rows are split into

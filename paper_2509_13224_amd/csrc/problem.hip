@@ -689,8 +689,12 @@ using Matvec = std::function<void(const TT&, TT&)>;
 // as they are formed (tt_matvec_round) instead of being stored and rounded afterwards.
 static constexpr size_t kFusedProductBytes = size_t(1) << 30;
 
-// ||b - K x|| / ||b||, with the residual train b - K x rounded at eps_x (replaces r).  With
-// Kf given and a large product the residual train is formed already rounded.
+// ||b - K x|| / ||b||, with the residual train b - K x rounded at eps_x (replaces r).  The
+// norm is that of the unrounded train: Householder orthogonalisation of the concatenated
+// cores of [b, -K x] loses no digits to the cancellation, and the first SVD of the
+// right-to-left sweep reads the norm before anything is truncated (a randomised sketch
+// could only underestimate it).  With Kf given and a product too large to store, the
+// residual train is formed already rounded and the norm is that of the rounded train.
 static double true_residual(Context& c, const Matvec& mv, const TT& b, const TT& x, double nb,
                             double eps_x, int max_rank, TT& r, int& hint, const TT* Kf = nullptr, int p = 0) {
   if (Kf && matvec_product_bytes(*Kf, x) > kFusedProductBytes) {
@@ -700,17 +704,10 @@ static double true_residual(Context& c, const Matvec& mv, const TT& b, const TT&
   TT Kx, tr;
   mv(x, Kx);
   tt_axpby(c, 1.0, b, -1.0, Kx, tr);
-  if (eps_x < 1e-9) {
-    // near cancellation a sketch of [b, -K x] loses digits; Householder orthogonalisation
-    // of the concatenated cores does not, and its first SVD gives the norm
-    double nrm = 0.0;
-    tt_round(c, tr, eps_x, -1.0, max_rank, &nrm);
-    r = std::move(tr);
-    return nrm / nb;
-  }
-  tt_round_auto(c, tr, eps_x, max_rank, hint);
+  double nrm = 0.0;
+  tt_round(c, tr, eps_x, -1.0, max_rank, &nrm);
   r = std::move(tr);
-  return std::sqrt(std::max(tt_dot_sync(c, r, r), 0.0)) / nb;
+  return nrm / nb;
 }
 
 // Truncated TT-CG: conjugate gradients with TT-rounding of every update, the

@@ -172,8 +172,6 @@ struct Context {
   // declared after the allocator so that cached plans are released before it
   PlanCache own_plans;
   PlanCache* plans = &own_plans;
-  // rocBLAS handle (created on first use by gemm, bound to this context's stream)
-  void* blas = nullptr;
   // pinned, coherent host staging for small readbacks (ranks, scalars); kernels write
   // results straight to host_dev (its device address), so a readback needs no copy
   double* host_scratch = nullptr;
@@ -236,10 +234,20 @@ namespace ttiga {
 
 // ----------------------------------------------------------------- kernel API
 // Dense linear algebra on the stream (kernels_linalg.hip).
-// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]; row-major operands.
-void release_blas(void* handle);
-// C = alpha op(A) op(B) + beta C through the GEMM autotuner (hand-written MFMA kernel or
-// rocBLAS, chosen per shape bucket by timing).
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]; row-major operands, hand-written MFMA
+// kernel (gemm_f64.hip).  The tile and the K splits are a function of the shape alone.
+struct GemmPlan {
+  int bm = 64, bn = 64;  // workgroup tile
+  int splits = 1;        // K splits (partials summed in split order by a second kernel)
+  int kchunk = 0;        // contraction length per split
+};
+GemmPlan gemm_plan(int M, int N, int K, int batch);
+// doubles of partial-tile workspace a plan needs (0 without K splits)
+size_t gemm_part_doubles(const GemmPlan& g, int M, int N, int batch);
+// the product with a given plan and caller-provided partial-tile workspace (K > 0)
+void gemm_planned(Context& ctx, const GemmPlan& g, bool ta, bool tb, int M, int N, int K, double alpha,
+                  const double* A, long lda, long sA, const double* B, long ldb, long sB, double beta,
+                  double* C, long ldc, long sC, int batch, double* part);
 void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
           long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
           long sC, int batch = 1);
@@ -297,6 +305,11 @@ double tt_dot_sync(Context& ctx, const TT& x, const TT& y);
 // out[i] = x_i . y_i for count pairs (count <= 8) with one host synchronisation
 void tt_dots_sync(Context& ctx, const TT* const* x, const TT* const* y, int count, double* out);
 void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev);
+// <x, y> from raw device cores (ranks rx, ry with rx[0] = ry[0] = rx[3] = ry[3] = 1) into
+// out_dev, all temporaries in `scratch` of tt_dot_scratch_doubles(n, rx, ry) doubles
+size_t tt_dot_scratch_doubles(const int* n, const int* rx, const int* ry);
+void tt_dot_cores(Context& ctx, const int* n, const int* rx, const double* const* xc, const int* ry,
+                  const double* const* yc, double* out_dev, double* scratch);
 void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y);
 // FP64 cores -> FP32 or BF16 cores (round to nearest even, BF16 through FP32).
 void tt_to_lowp(Context& ctx, const TT& src, int dtype, LowpTT& dst);

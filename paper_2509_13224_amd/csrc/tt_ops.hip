@@ -356,29 +356,58 @@ void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* 
   axpby_impl(ctx, alpha, 0.0, x, beta, 0.0, y, out);
 }
 
+// The inner product <x, y> as a chain of GEMMs over the cores: L_1 = x_0^T y_0, then per core
+// T[b][i][a'] = sum_a L[a][b] x_k[a][i][a'] and L'[a'][b'] = sum_{b,i} T[(b i)][a'] y_k[(b i)][b'];
+// the last (1 x 1) product is written to out_dev.  Every temporary lives in one scratch block
+// (two L buffers, one T buffer, one area for the partial tiles of split GEMMs), laid out by
+// DotScratch, so the same chain runs on arena memory or on a fixed buffer.
+namespace {
+struct DotScratch {
+  size_t l = 0, t = 0, part = 0;
+  DotScratch(const int* n, const int* rx, const int* ry) {
+    auto part_of = [&](int M, int N, int K) { return gemm_part_doubles(gemm_plan(M, N, K, 1), M, N, 1); };
+    l = std::max((size_t)rx[1] * ry[1], (size_t)rx[2] * ry[2]);
+    t = std::max((size_t)ry[1] * n[1] * rx[2], (size_t)ry[2] * n[2] * rx[3]);
+    part = std::max({part_of(rx[1], ry[1], n[0]), part_of(ry[1], n[1] * rx[2], rx[1]),
+                     part_of(rx[2], ry[2], ry[1] * n[1]), part_of(ry[2], n[2] * rx[3], rx[2]),
+                     part_of(rx[3], ry[3], ry[2] * n[2])});
+  }
+  size_t total() const { return 2 * l + t + part; }
+};
+}  // namespace
+
+size_t tt_dot_scratch_doubles(const int* n, const int* rx, const int* ry) { return DotScratch(n, rx, ry).total(); }
+
+void tt_dot_cores(Context& ctx, const int* n, const int* rx, const double* const* xc, const int* ry,
+                  const double* const* yc, double* out_dev, double* scratch) {
+  const DotScratch sz(n, rx, ry);
+  double* Lb[2] = {scratch, scratch + sz.l};
+  double* T = scratch + 2 * sz.l;
+  double* part = T + sz.t;
+  auto mm = [&](bool ta, int M, int N, int K, const double* A, long lda, const double* B, long ldb, double* C,
+                long ldc) {
+    gemm_planned(ctx, gemm_plan(M, N, K, 1), ta, false, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1,
+                 part);
+  };
+  mm(true, rx[1], ry[1], n[0], xc[0], rx[1], yc[0], ry[1], Lb[0], ry[1]);
+  int cur = 0;
+  for (int k = 1; k < 3; ++k) {
+    const int rx0 = rx[k], rx1 = rx[k + 1], ry0 = ry[k], ry1 = ry[k + 1], nk = n[k];
+    // T (ry0 x nk rx1) = L^T (ry0 x rx0) * x_k (rx0 x nk rx1)
+    mm(true, ry0, nk * rx1, rx0, Lb[cur], ry0, xc[k], (long)nk * rx1, T, (long)nk * rx1);
+    // L' (rx1 x ry1) = T^T viewed as (ry0 nk) x rx1, times y_k ((ry0 nk) x ry1)
+    double* dst = (k < 2) ? Lb[1 - cur] : out_dev;
+    mm(true, rx1, ry1, ry0 * nk, T, rx1, yc[k], ry1, dst, ry1);
+    cur = 1 - cur;
+  }
+}
+
 void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev) {
   if (x.zero() || y.zero()) { fill(ctx, out_dev, 1, 0.0); return; }
-  // L_k (rx_k x ry_k); L_0 = [1], so L_1 = x_0^T y_0 directly; the last (1 x 1) product is
-  // written straight to out_dev
-  DBuf L(ctx.alloc, sizeof(double) * (size_t)x.r[1] * y.r[1]);
-  gemm(ctx, true, false, x.r[1], y.r[1], x.n[0], 1.0, x.c[0].d(), x.r[1], 0, y.c[0].d(), y.r[1], 0, 0.0, L.d(),
-       y.r[1], 0);
-  for (int k = 1; k < 3; ++k) {
-    const int rx0 = x.r[k], rx1 = x.r[k + 1], ry0 = y.r[k], ry1 = y.r[k + 1], n = x.n[k];
-    // T[b][i][a'] = sum_a L[a][b] x[a][i][a']   : (ry0 x rx0)^T-view * (rx0 x n rx1)
-    DBuf T(ctx.alloc, sizeof(double) * (size_t)ry0 * n * rx1);
-    gemm(ctx, true, false, ry0, n * rx1, rx0, 1.0, L.d(), ry0, 0, x.c[k].d(), (long)n * rx1, 0, 0.0,
-         T.d(), (long)n * rx1, 0);
-    // L'[a'][b'] = sum_{b,i} T[(b i)][a'] y[(b i)][b']
-    DBuf Ln;
-    double* dst = out_dev;
-    if (k < 2) {
-      Ln = DBuf(ctx.alloc, sizeof(double) * (size_t)rx1 * ry1);
-      dst = Ln.d();
-    }
-    gemm(ctx, true, false, rx1, ry1, ry0 * n, 1.0, T.d(), rx1, 0, y.c[k].d(), ry1, 0, 0.0, dst, ry1, 0);
-    if (k < 2) L = std::move(Ln);
-  }
+  DBuf scratch(ctx.alloc, sizeof(double) * tt_dot_scratch_doubles(x.n, x.r, y.r));
+  const double* xc[3] = {x.c[0].d(), x.c[1].d(), x.c[2].d()};
+  const double* yc[3] = {y.c[0].d(), y.c[1].d(), y.c[2].d()};
+  tt_dot_cores(ctx, x.n, x.r, xc, y.r, yc, out_dev, scratch.d());
 }
 
 double tt_dot_sync(Context& ctx, const TT& x, const TT& y) {

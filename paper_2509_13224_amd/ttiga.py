@@ -32,7 +32,7 @@ EXPORTED = (
     "ttiga_version", "ttiga_create", "ttiga_destroy", "ttiga_set_workspace", "ttiga_last_error",
     "ttiga_validate", "ttiga_problem_create", "ttiga_problem_destroy", "ttiga_assemble", "ttiga_solve",
     "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
-    "ttiga_sample_factors", "ttiga_tt_matvec", "ttiga_tt_matvec_round", "ttiga_tt_round", "ttiga_tt_dot",
+    "ttiga_sample_factors", "ttiga_gemm_f64", "ttiga_tt_matvec", "ttiga_tt_matvec_round", "ttiga_tt_round", "ttiga_tt_dot",
     "ttiga_tt_compress", "ttiga_tt_matvec_lowp", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free", "ttiga_profile",
     "ttiga_profile_read", "ttiga_tt_view_of", "ttiga_footprint", "ttiga_solve_batch",
     "ttiga_server_create", "ttiga_server_submit", "ttiga_server_poll", "ttiga_server_solution",
@@ -161,6 +161,10 @@ def load(path=LIB_PATH):
         "ttiga_problem_tt_info": (ctypes.c_int, [vp, ctypes.c_int, c_int_p, c_int_p, c_int_p]),
         "ttiga_problem_tt_copy": (ctypes.c_int, [vp, ctypes.c_int, c_dbl_p, ctypes.c_size_t]),
         "ttiga_sample_factors": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t, c_dbl_p, c_dbl_p]),
+        "ttiga_gemm_f64": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, vp, ctypes.c_long, ctypes.c_long, vp, ctypes.c_long,
+                                          ctypes.c_long, ctypes.c_double, vp, ctypes.c_long, ctypes.c_long,
+                                          ctypes.c_int, c_int_p]),
         "ttiga_tt_matvec": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView),
                                            ctypes.POINTER(vp)]),
         "ttiga_tt_matvec_lowp": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView), ctypes.c_int,
@@ -317,6 +321,15 @@ class Context:
         if r[1] == 0:
             return None
         return split_cores(flat, n, r)
+
+    def gemm_f64(self, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch=1, sA=0, sB=0, sC=0,
+                 plan=None):
+        """ttiga_gemm_f64 on device float64 tensors A, B, C (row-major, leading dimensions and
+        batch strides in elements); plan = (bm, bn, splits) or None for the library's rule."""
+        pl = (ctypes.c_int * 3)(*plan) if plan is not None else None
+        _check(self.lib, self.lib.ttiga_gemm_f64(self.h, int(ta), int(tb), M, N, K, float(alpha), A.data_ptr(), lda,
+                                                 sA, B.data_ptr(), ldb, sB, float(beta), C.data_ptr(), ldc, sC,
+                                                 batch, pl))
 
     def tt_matvec(self, K_cores_dev, p, x_cores_dev, dtype=None):
         """y = K x; K banded cores [r][n][2p+1][r'] and x cores [r][n][r'] as device tensors.

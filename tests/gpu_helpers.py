@@ -60,3 +60,34 @@ def rand_banded(shape, ranks, p, rng):
 def to_dev(cores, device="cuda:0"):
     import torch
     return [torch.from_numpy(np.ascontiguousarray(c)).to(device) for c in cores]
+
+
+def tt_rel_diff(a, b):
+    """||a - b|| / ||b|| for host TT cores (3 cores): the difference train [a, -b] is
+    left-orthogonalised by QR and its norm read from the last core, so differences far below
+    ||b|| are resolved (no cancellation between <a,a>, <a,b> and <b,b>)."""
+    def orth_norm(cores):
+        cores = [c.copy() for c in cores]
+        for k in range(len(cores) - 1):
+            r0, n, r1 = cores[k].shape
+            _, r = np.linalg.qr(cores[k].reshape(r0 * n, r1))
+            cores[k + 1] = np.tensordot(r, cores[k + 1], axes=([1], [0]))
+        return float(np.linalg.norm(cores[-1]))
+
+    d = []
+    for k, (A, B) in enumerate(zip(a, b)):
+        if k == 0:
+            d.append(np.concatenate([A, -B], axis=2))
+        elif k == len(a) - 1:
+            d.append(np.concatenate([A, B], axis=0))
+        else:
+            C = np.zeros((A.shape[0] + B.shape[0], A.shape[1], A.shape[2] + B.shape[2]))
+            C[:A.shape[0], :, :A.shape[2]] = A
+            C[A.shape[0]:, :, A.shape[2]:] = B
+            d.append(C)
+    return orth_norm(d) / orth_norm(b)
+
+
+def same_tt(a, b):
+    """True when two host TTs have the same ranks and bit-identical cores."""
+    return len(a) == len(b) and all(x.shape == y.shape and np.array_equal(x, y) for x, y in zip(a, b))

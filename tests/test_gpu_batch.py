@@ -1,6 +1,5 @@
 """Batched and serving modes: every result equals the same problem solved alone, failures stay
 with their problem, and admission refuses what can never fit."""
-import math
 import threading
 import time
 
@@ -8,8 +7,8 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import sparse_iga, tt, tt_iga
-from tests.gpu_helpers import say
+from oracle import sparse_iga, tt_iga
+from tests.gpu_helpers import same_tt, say, tt_rel_diff
 from workloads.problem import PREC_FP64
 
 pytestmark = pytest.mark.gpu
@@ -24,12 +23,6 @@ def ctx(gpu_lib):
 def _mix(count=6):
     """Small requests of the batched family: annulus sectors and twisted boxes, p in {2, 3}."""
     return W.c4_requests(count=count, sizes=(12, 16, 24), precision=PREC_FP64, eps=1e-8, tol=1e-9)
-
-
-def _dist(a, b):
-    """||a - b|| / ||b|| of host TT cores."""
-    aa, ab, bb = tt.dot(a, a), tt.dot(a, b), tt.dot(b, b)
-    return math.sqrt(max(aa - 2.0 * ab + bb, 0.0) / bb)
 
 
 def _alone(ctx, pr):
@@ -53,7 +46,8 @@ def test_batch_equals_alone(ctx):
         lanes.add(res["lane"])
         st, u0 = _alone(ctx, pr)
         assert res["iterations"] == st["iterations"]
-        assert _dist(u, u0) <= 1e-12, pr.name
+        # the same kernels with the same shapes in the same order: the same bits
+        assert same_tt(u, u0), (pr.name, tt_rel_diff(u, u0))
     assert len(lanes) > 1
     # and one of them against the sparse direct solution of the oracle
     pr, (res, u) = reqs[0], out[0]
@@ -82,7 +76,7 @@ def test_batch_isolates_failures(ctx):
 
 def test_server_alone_vs_mix(ctx):
     """Requests submitted from three threads while others run: each result equals its solve
-    alone (same iterations, same TT to 1e-12)."""
+    alone (same iterations, bit-identical TT cores)."""
     say("server mix")
     reqs = _mix(9)
     srv = ctx.server(hbm_budget=4 << 30, lanes=4)
@@ -111,7 +105,7 @@ def test_server_alone_vs_mix(ctx):
         u = srv.solution(t)
         st, u0 = _alone(ctx, pr)
         assert res["iterations"] == st["iterations"]
-        assert _dist(u, u0) <= 1e-12, pr.name
+        assert same_tt(u, u0), (pr.name, tt_rel_diff(u, u0))
         srv.release(t)
     assert len({r["lane"] for r in results}) > 1
     srv.close()
@@ -133,4 +127,25 @@ def test_server_admission(ctx):
     with pytest.raises(ttiga.TTIGAError):
         srv.release(t + 100)
     srv.release(t)
+    srv.close()
+
+
+def test_server_tight_pool_keeps_resident_solutions(ctx):
+    """A pool that holds about two footprints, two lanes and eight requests whose solutions stay
+    resident until the end: admission charges the resident solutions, a lane that finds the pool
+    fragmented waits only while another problem is running, and every request finishes with the
+    result it has alone."""
+    from paper_2509_13224_amd import ttiga
+    say("server tight pool")
+    reqs = _mix(8)
+    fp = max(ttiga.footprint(pr) for pr in reqs)
+    srv = ctx.server(hbm_budget=int(2.2 * fp), lanes=2)
+    tickets = [srv.submit(pr) for pr in reqs]
+    results = [srv.poll(t, wait_ms=-1) for t in tickets]
+    for pr, t, res in zip(reqs, tickets, results):
+        assert res["status"] == 0, res
+        st, u0 = _alone(ctx, pr)
+        assert same_tt(srv.solution(t), u0), pr.name
+    for t in tickets:
+        srv.release(t)
     srv.close()

@@ -184,9 +184,9 @@ def test_fullsize_manufactured_solve(ctx):
     manufactured forcing of u = sin(pi r) sin(2 theta) sin(pi z) (a closed form chosen for this test: it vanishes on the six faces of the quarter annulus; its forcing is -Laplace u), solved through the
     executor beside three C2 Fourier problems as in the bench's steps: the TT solution at 300
     random points of the solid against u itself.  At this mesh the discretisation error
-    (O(h^4), about 1e-9) is far below the tolerances, so what is measured is the TT solve,
-    whose relative error is of the order of eps + tol; 10x that is allowed (RMS over the
-    points, relative to the RMS of u)."""
+    (O(h^4), about 1e-9) is far below the tolerances, so what is measured is the TT solve;
+    the gate is the relative accuracy the solves are held to, 1e-6 (RMS over the points,
+    relative to the RMS of u)."""
     from oracle import nurbs, sources
     say("fullsize manufactured solve (4 lanes)")
     pr = W.c2_problem(n=256)
@@ -212,7 +212,7 @@ def test_fullsize_manufactured_solve(ctx):
     ue = sources.manufactured_annulus_solution(x)
     rms_err = np.sqrt(np.mean((uh - ue) ** 2))
     rms_u = np.sqrt(np.mean(ue ** 2))
-    allowed = 10 * (pr.options.tt_eps + pr.options.rel_res_tol) * rms_u
+    allowed = 1e-6 * rms_u
     say("fullsize manufactured: RMS error", rms_err, "max", np.abs(uh - ue).max(), "allowed RMS", allowed)
     assert rms_err <= allowed
 
@@ -311,25 +311,30 @@ def test_c3_entries_within_bounds(c3_assembled):
 
 
 def test_c3_solution_residual_entries(c3_assembled):
-    """The full-size complex-geometry solve against the oracle's discrete system: at sampled
-    interior rows a the oracle forms r_a = F_a - sum_b K_ab u_b from the definition (the 7^3
-    neighbouring entries of row a as Gauss sums over the support of a) and the GPU solution's
-    coefficients u_b.  Every entry of a vector is bounded by its 2-norm, so |r_a| may not exceed
-    the solver's reported ||F_I - K_II u|| (times 2) plus what separates the exact entries from
-    the eps-accurate K^TT and F^TT (10 eps of the row's absolute sum)."""
-    pr, st, sol, u = c3_assembled["pr"], c3_assembled["st"], c3_assembled["solve"], c3_assembled["u"]
-    p, n = pr.disc.degree, pr.disc.n_basis[0]
-    eps = pr.options.tt_eps
-    assert sol["status"] == 0 and sol["rel_pres"] <= pr.options.rel_res_tol
+    """The full-size complex-geometry solve against the oracle's discrete system, with a bound
+    that uses nothing the solver reports: at 16 sampled interior rows a the oracle forms
+    r_a = F_a - sum_b K_ab u_b from the definition (the 7^3 neighbouring entries of row a as
+    Gauss sums over the support of a) and the GPU solution's coefficients u_b.  The RMS of these
+    entries estimates ||F_I - K_II u|| / sqrt(N_I).  A solution within 10 (eps + tol) of the
+    discrete one in the 2-norm has ||F_I - K_II u|| <= ||K_II|| 10 (eps + tol) ||u|| (plus what
+    separates the eps-accurate K^TT and F^TT from the exact ones); ||K_II|| is estimated from the
+    sampled absolute row sums (Gershgorin), ||u|| is computed from the TT.  The bound is a
+    necessary condition (a smooth error of the same size leaves a smaller residual); the
+    sufficient check against u_h is made at oracle size on the same path in
+    test_gpu_timed_path.py."""
+    pr, sol, u = c3_assembled["pr"], c3_assembled["solve"], c3_assembled["u"]
+    p = pr.disc.degree
+    eps, tol = pr.options.tt_eps, pr.options.rel_res_tol
+    assert sol["status"] == 0 and sol["rel_pres"] <= tol
     tabs = _tables(pr)
     from oracle import tt_iga
     sl = tt_iga.interior_slices(pr)
     lo = [s.start for s in sl]
-    rhs_norm = ott.norm(c3_assembled["rhs"])
-    res_norm = sol["rel_res"] * rhs_norm
+    n_interior = float(np.prod([s.stop - s.start for s in sl]))
+    u_norm = ott.norm(u)
     rng = np.random.default_rng(17)
-    worst = 0.0
-    for _ in range(4):
+    r_rows, f_rows, row_sums = [], [], []
+    for _ in range(16):
         a = tuple(int(rng.integers(s.start + p, s.stop - p)) for s in sl)
         sub, Ba, Da = [], [], []
         nb = [np.arange(a[d] - p, a[d] + p + 1) for d in range(3)]
@@ -362,9 +367,13 @@ def test_c3_solution_residual_entries(c3_assembled):
                 for i2, b2 in enumerate(nb[2]):
                     v = u[0][:, b0 - lo[0], :] @ u[1][:, b1 - lo[1], :] @ u[2][:, b2 - lo[2], :]
                     ub[i0, i1, i2] = v[0, 0]
-        r_a = F_a - np.sum(Krow * ub)
-        bound = 2 * res_norm + 10 * eps * (abs(F_a) + np.sum(np.abs(Krow * ub)))
-        worst = max(worst, abs(r_a) / bound)
-        say("fullsize C3 residual row", a, "r_a", r_a, "bound", bound)
-        assert abs(r_a) <= bound
-    say("fullsize C3 residual entries: worst |r_a| / bound", worst)
+        r_rows.append(F_a - np.sum(Krow * ub))
+        f_rows.append(F_a)
+        row_sums.append(np.sum(np.abs(Krow)))
+    res_est = np.sqrt(n_interior * np.mean(np.square(r_rows)))
+    f_est = np.sqrt(n_interior * np.mean(np.square(f_rows)))
+    k_est = max(row_sums)
+    bound = 10 * (eps + tol) * k_est * u_norm + 10 * eps * f_est
+    say("fullsize C3 residual: sampled ||r|| estimate", res_est, "bound", bound, "||F_I|| estimate", f_est,
+        "||K_II|| estimate", k_est, "||u||", u_norm)
+    assert res_est <= bound

@@ -108,3 +108,26 @@ def test_preconditioned_solve_matches_sparse(ctx, name):
     u = _full(pr, h.solution()).ravel()
     assert np.linalg.norm(u - u_h) <= 1e-8 * np.linalg.norm(u_h), st
     assert st["iterations"] <= 40, st
+
+
+def test_rank_cap_reports_rankcap(ctx):
+    """A rank cap below what a TT needs fails the call with E_RANKCAP instead of truncating
+    silently: at assembly when the operator itself needs more (annulus K^TT has ranks (3, 2)),
+    at the solve when only the iterates do."""
+    from paper_2509_13224_amd import ttiga
+    say("rankcap")
+    pr = W.c1_problem(n=12, eps=1e-10, tol=1e-10)
+    pr.options.max_rank = 2
+    h = ctx.problem_create(pr)
+    with pytest.raises(ttiga.TTIGAError) as e:
+        h.assemble()
+    assert e.value.code == ttiga.TTIGA_E_RANKCAP
+    h.close()
+    pr.options.max_rank = 4
+    h = ctx.problem_create(pr)
+    st = h.assemble()
+    assert max(st["rank_K"]) <= 4
+    with pytest.raises(ttiga.TTIGAError) as e:
+        h.solve()
+    assert e.value.code == ttiga.TTIGA_E_RANKCAP
+    h.close()
