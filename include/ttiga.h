@@ -310,6 +310,18 @@ int ttiga_tt_round(ttiga_ctx* ctx, const ttiga_tt_view* x, double eps, ttiga_tt*
 /* Standalone TT inner product <x, y> (left-to-right contraction), result to host. */
 int ttiga_tt_dot(ttiga_ctx* ctx, const ttiga_tt_view* x, const ttiga_tt_view* y, double* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): ttiga_tt_dot with its temporaries in a fixed 64 MiB
+ * device array per GPU (held until the process ends) instead of the workspace, so the call
+ * allocates nothing, does not synchronise, and writes <x, y> to the caller's device double
+ * out_dev on the context stream (the same bits as ttiga_tt_dot).  Views as for ttiga_tt_dot
+ * (caller-owned device cores).  E_ARG when the contraction needs more scratch than 64 MiB
+ * (e.g. ranks above 128 at mode sizes of 256; the message gives the need), on null or
+ * mismatched views; E_STATE while profiling (ttiga_profile) is on.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race, so a caller serialises them. */
+int ttiga_tt_dot_noalloc(ttiga_ctx* ctx, const ttiga_tt_view* x, const ttiga_tt_view* y, double* out_dev);
+
 /* TT-SVD of a dense device tensor A[n0][n1][n2] with absolute per-unfolding
  * threshold delta (randomised range finder above 64 points per mode). */
 int ttiga_tt_compress(ttiga_ctx* ctx, const double* A, const int n[3], double delta, ttiga_tt** out);

@@ -334,6 +334,8 @@ int ttiga_create(int device, void* hip_stream, ttiga_ctx** out) {
     c->impl.owner = c;
     c->impl.device = device;
     c->impl.stream = static_cast<hipStream_t>(hip_stream);
+    // the device address of the allocation-free entry point's scratch, once per device
+    (void)noalloc_scratch(device);
     *out = c;
   });
 }
@@ -627,6 +629,15 @@ int ttiga_tt_dot(ttiga_ctx* ctx, const ttiga_tt_view* x, const ttiga_tt_view* y,
     tt_from_view(c, *x, xt);
     tt_from_view(c, *y, yt);
     *out = tt_dot_sync(c, xt, yt);
+  });
+}
+
+int ttiga_tt_dot_noalloc(ttiga_ctx* ctx, const ttiga_tt_view* x, const ttiga_tt_view* y, double* out_dev) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && x && y && out_dev, TTIGA_E_ARG, "null argument");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    tt_dot_noalloc(c, *x, *y, out_dev);
   });
 }
 

@@ -308,6 +308,12 @@ void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev);
 // <x, y> from raw device cores (ranks rx, ry with rx[0] = ry[0] = rx[3] = ry[3] = 1) into
 // out_dev, all temporaries in `scratch` of tt_dot_scratch_doubles(n, rx, ry) doubles
 size_t tt_dot_scratch_doubles(const int* n, const int* rx, const int* ry);
+// the allocation-free variant (noalloc.hip): the same chain with its temporaries in a fixed
+// per-device array; noalloc_scratch looks the array's address up (once per device, with
+// that device current)
+double* noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
+void tt_dot_noalloc(Context& ctx, const ttiga_tt_view& x, const ttiga_tt_view& y, double* out_dev);
 void tt_dot_cores(Context& ctx, const int* n, const int* rx, const double* const* xc, const int* ry,
                   const double* const* yc, double* out_dev, double* scratch);
 void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y);

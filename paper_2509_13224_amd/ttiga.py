@@ -33,6 +33,7 @@ EXPORTED = (
     "ttiga_validate", "ttiga_problem_create", "ttiga_problem_destroy", "ttiga_assemble", "ttiga_solve",
     "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
     "ttiga_sample_factors", "ttiga_gemm_f64", "ttiga_tt_matvec", "ttiga_tt_matvec_round", "ttiga_tt_round", "ttiga_tt_dot",
+    "ttiga_tt_dot_noalloc",
     "ttiga_tt_compress", "ttiga_tt_matvec_lowp", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free", "ttiga_profile",
     "ttiga_profile_read", "ttiga_tt_view_of", "ttiga_footprint", "ttiga_solve_batch",
     "ttiga_server_create", "ttiga_server_submit", "ttiga_server_poll", "ttiga_server_solution",
@@ -174,6 +175,7 @@ def load(path=LIB_PATH):
                                                  ctypes.POINTER(TTView), ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                                  ctypes.POINTER(vp)]),
         "ttiga_tt_dot": (ctypes.c_int, [vp, ctypes.POINTER(TTView), ctypes.POINTER(TTView), c_dbl_p]),
+        "ttiga_tt_dot_noalloc": (ctypes.c_int, [vp, ctypes.POINTER(TTView), ctypes.POINTER(TTView), vp]),
         "ttiga_tt_compress": (ctypes.c_int, [vp, vp, c_int_p, ctypes.c_double, ctypes.POINTER(vp)]),
         "ttiga_tt_info": (ctypes.c_int, [vp, c_int_p, c_int_p]),
         "ttiga_tt_copy": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t]),
@@ -382,6 +384,13 @@ class Context:
         out = ctypes.c_double()
         _check(self.lib, self.lib.ttiga_tt_dot(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(out)))
         return out.value
+
+    def tt_dot_noalloc(self, x_dev, y_dev, out_dev):
+        """ttiga_tt_dot_noalloc: <x, y> written to the device float64 tensor out_dev (one
+        element) on the context stream, without allocating; the caller synchronises."""
+        a, b = self._view(x_dev), self._view(y_dev)
+        _check(self.lib, self.lib.ttiga_tt_dot_noalloc(self.h, ctypes.byref(a), ctypes.byref(b),
+                                                       ctypes.c_void_p(out_dev.data_ptr())))
 
     def tt_compress(self, A_dev, delta):
         n = (ctypes.c_int * 3)(*A_dev.shape)
