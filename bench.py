@@ -54,19 +54,41 @@ KERNEL_BOUND = {
 }
 SERVE_SEED = 2025_0913_05
 SERVE_SIZES = (32, 64, 128, 256, 512)
-# arrival rates as fractions of the measured batched-family throughput, a geometric sweep
-SERVE_RATES = (0.25, 0.5, 1.0, 2.0)
+# arrival rates as fractions of the served mix's own saturation throughput (all requests offered
+# at once to the same server), a geometric sweep
+SERVE_RATES = (0.5, 1.0, 2.0)
 # the n = 512 FP32 refinements reach ranks of about 360 in their corrections
 SERVE_MAX_RANK = 1024
 # tolerance of the family's assembly (eps / 1000; its references: eps / 10000): on twisted boxes a
 # compressed operator that drops a singular value near eps = 1e-6 moves the solution by up to 1e-3,
 # and at 1e-8 some requests (and at 1e-9 some references) still sit above 1e-6
 ASSEMBLY_EPS = 1e-9
-# HBM bytes per dispatch of a kernel class measured by rocprofv3 --pmc on `bench.py
-# --single-only` (FETCH_SIZE scaled by the 1 GiB copy calibration, WRITE_SIZE), in KiB;
-# profiles/tsqr_factor_annulus_n256.md has the commands.  Valid only for the kernel code
-# it was taken on.
-MEASURED_TRAFFIC_KIB = {"tsqr_factor": (1756.4, 2154.7)}
+# HBM bytes per dispatch of the roofline kernel, measured by two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE) of `bench.py --single-only` and written, with the copy-kernel calibration, into
+# this summary as `traffic:` lines; a line counts only while the sha256 of the kernel's source file
+# still equals the one recorded with it (after a change to the kernel the field is null).
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic.md")
+
+
+def measured_traffic(kernel):
+    """(bytes per dispatch, note) of `kernel` from the committed PMC summary, or (None, reason)."""
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None, "no PMC summary"
+    for line in open(TRAFFIC_SUMMARY):
+        m = re.match(r"\s*traffic: kernel=(\S+) fetch_kib=([\d.]+) write_kib=([\d.]+) source=(\S+) sha256=([0-9a-f]+)",
+                     line)
+        if not m or m.group(1) != kernel:
+            continue
+        src = os.path.join(ROOT, m.group(4))
+        if not os.path.exists(src):
+            return None, f"source {m.group(4)} missing"
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if sha != m.group(5):
+            return None, f"{m.group(4)} changed since the counters were taken"
+        return 1024.0 * (float(m.group(2)) + float(m.group(3))), f"rocprofv3 --pmc, {TRAFFIC_SUMMARY[len(ROOT) + 1:]}"
+    return None, f"no PMC line for {kernel}"
 
 
 def roofline_entry(name, st):
@@ -111,33 +133,128 @@ def tt_rel_diff(a, b):
     return orth_norm(d) / orth_norm(b)
 
 
-def cpu_baseline(n, slabs):
-    """Oracle factor sampling on `slabs` of the n-grid's first-direction Gauss nodes, one thread."""
+def host_cores():
+    """Threads the oracle may use: the machine's CPU share (OMP_NUM_THREADS when the environment sets
+    it), else the cores this process may run on."""
+    aff = len(os.sched_getaffinity(0))
     try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:  # pragma: no cover
-        threadpool_limits = None
-    import contextlib
+        omp = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        omp = 0
+    return min(aff, omp) if omp > 0 else aff, aff
+
+
+def cpu_model():
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    for line in out.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return None
+
+
+def cpu_baseline(n, slabs, n_full):
+    """The oracle's whole TT pipeline (Gauss-grid sampling, TT-SVD, assembly with rounding,
+    truncated TT-CG) on one problem of the benchmark's family at n basis functions per
+    direction, with BLAS threads set to the host cores; plus the oracle's factor sampling on
+    `slabs` first-direction slabs of the full-size grid, extrapolated, as a bound for the
+    full-size problem."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import workloads as W
-    from oracle import geometry
+    from oracle import geometry, tt_iga
+    cores, affinity = host_cores()
     pr = W.c2_problem(n=n)
-    grid = geometry.gauss_grid(pr)
-    Q0 = len(grid[0][0])
-    sub = [(grid[0][0][:slabs], grid[0][1][:slabs]), grid[1], grid[2]]
-    limit = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
-    with limit:
+    with threadpool_limits(limits=cores):
+        blas = [f"{i.get('internal_api')}:{i.get('num_threads')}" for i in threadpool_info()]
         t0 = time.perf_counter()
-        geometry.sample_factors_grid(pr, sub)
+        tt_iga.solve(pr)
         dt = time.perf_counter() - t0
-    full = dt * Q0 / slabs
-    pts = slabs * len(grid[1][0]) * len(grid[2][0])
-    return {"value": 1.0 / full, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle Gauss-grid sampling of R_ij and f det J on {slabs} of {Q0} first-direction "
-                       f"slabs ({pts} points, {dt:.1f} s, 1 thread), extrapolated to the full grid "
-                       f"({full:.0f} s); compression and the solve are not included, so this bounds the "
-                       f"oracle's solve rate from above"),
-            "seconds_sampled": dt}
+        full = W.c2_problem(n=n_full)
+        grid = geometry.gauss_grid(full)
+        Q0 = len(grid[0][0])
+        sub = [(grid[0][0][:slabs], grid[0][1][:slabs]), grid[1], grid[2]]
+        t1 = time.perf_counter()
+        geometry.sample_factors_grid(full, sub)
+        ds = time.perf_counter() - t1
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"one whole oracle TT solve (sampling, TT-SVD, assembly, truncated TT-CG) of the same "
+                       f"annulus / Fourier family at n={n}/dir ({n ** 3} DOF), eps and tol as the benchmark; "
+                       f"{dt:.1f} s on {cores} BLAS threads"),
+            "seconds": dt, "n": n, "cpu_model": cpu_model(), "affinity_cores": affinity, "blas": blas,
+            "full_size_sampling_bound": {
+                "solves_per_s": 1.0 / (ds * Q0 / slabs),
+                "note": (f"factor sampling alone on {slabs} of {Q0} first-direction slabs at n={n_full} "
+                         f"({ds:.1f} s), extrapolated to the whole grid ({ds * Q0 / slabs:.0f} s): an upper "
+                         f"bound on the oracle's full-size solve rate")}}
+
+
+# seeded synthetic sweep of the TT-matrix x TT-vector product: random banded operator cores of
+# ranks (rK, rK), vector cores of ranks (rx, rx), N(0, 1) entries
+SWEEP_RK = (2, 4, 8, 16, 32)
+SWEEP_RX = (8, 16, 32, 64, 128)
+SWEEP_N = (256, 512)
+SWEEP_P = (2, 3)
+SWEEP_DTYPES = ((0, "fp64", "tt_matvec_banded"), (1, "fp32", "tt_matvec_fp32"), (2, "bf16", "tt_matvec_bf16"))
+# points whose product cores exceed this are left out (the largest, rK 32 x rx 128 at n = 512,
+# would write 69 GB)
+SWEEP_MAX_OUT_BYTES = 8 << 30
+SWEEP_SEED = 2025_0913_07
+
+
+def matvec_sweep(ctx, reps=3, only=None):
+    """Achieved HBM GB/s and TFLOP/s of the banded TT-matvec over the synthetic sweep, from the
+    library's per-launch HIP events (algorithmic bytes: operator, vector and product cores).
+    only = (rK, rx, n, p) restricts the sweep to that point (profiling runs)."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(SWEEP_SEED)
+    points, skipped = [], 0
+    for n in SWEEP_N:
+        for p in SWEEP_P:
+            band = 2 * p + 1
+            mask = np.array([[0 <= i + t - p < n for t in range(band)] for i in range(n)], dtype=np.float64)
+            for rK in SWEEP_RK:
+                for rx in SWEEP_RX:
+                    if only and (rK, rx, n, p) != only:
+                        continue
+                    out_bytes = 8 * n * ((rK * rx) ** 2 + 2 * rK * rx)
+                    if out_bytes > SWEEP_MAX_OUT_BYTES:
+                        skipped += len(SWEEP_DTYPES)
+                        continue
+                    rKs, rxs = (1, rK, rK, 1), (1, rx, rx, 1)
+                    K = [torch.from_numpy(rng.normal(size=(rKs[k], n, band, rKs[k + 1])) *
+                                          mask[None, :, :, None]).cuda() for k in range(3)]
+                    x = [torch.from_numpy(rng.normal(size=(rxs[k], n, rxs[k + 1]))).cuda() for k in range(3)]
+                    for code, dname, cls in SWEEP_DTYPES:
+                        ctx.tt_matvec(K, p, x, dtype=code or None, copy=False)  # warm-up
+                        ctx.profile(-1)
+                        ctx.profile(1)
+                        for _ in range(reps):
+                            ctx.tt_matvec(K, p, x, dtype=code or None, copy=False)
+                        ctx.profile(0)
+                        st = ctx.profile_read()[cls]
+                        secs = st["total_ms"] * 1e-3
+                        gbs = st["bytes"] / secs / 1e9
+                        points.append({"rK": rK, "rx": rx, "n": n, "p": p, "dtype": dname,
+                                       "GBps": gbs, "TFLOPps": st["flops"] / secs / 1e12,
+                                       "hbm_frac": gbs / PEAKS["hbm_GBps"],
+                                       "us_per_product": 1e6 * secs / reps})
+                    del K, x
+    torch.cuda.synchronize()
+    big = [q for q in points if q["rK"] * q["rx"] >= 256]
+    return {"points": points, "skipped_points": skipped,
+            "max_hbm_frac": max(q["hbm_frac"] for q in points),
+            "median_hbm_frac_large": (sorted(q["hbm_frac"] for q in big)[len(big) // 2] if big else None),
+            "max_tflops": {d: max(q["TFLOPps"] for q in points if q["dtype"] == d) for _, d, _ in SWEEP_DTYPES},
+            "recipe": (f"seed {SWEEP_SEED}; banded operator cores of ranks (rK, rK), vector cores of ranks "
+                       f"(rx, rx), N(0,1) entries; rK in {SWEEP_RK}, rx in {SWEEP_RX}, n in {SWEEP_N}, p in "
+                       f"{SWEEP_P}; points whose product exceeds {SWEEP_MAX_OUT_BYTES >> 30} GiB left out; "
+                       f"{reps} timed products per point after one warm-up; bytes = operator + vector + "
+                       f"product cores (FP64 product, operator in the point's dtype)")}
 
 
 def log(*a):
@@ -154,12 +271,13 @@ def percentile(xs, q):
 
 
 def serve(ctx, reqs, rate, lanes, seed):
-    """Poisson arrivals at `rate` requests/s into a server; returns latencies and throughput."""
+    """Poisson arrivals at `rate` requests/s into a server (rate None: all at once); returns the
+    results, the solutions and the seconds from the first submission to the last result."""
     import threading
 
     import numpy as np
     rng = np.random.default_rng(seed)
-    gaps = rng.exponential(1.0 / rate, size=len(reqs))
+    gaps = rng.exponential(1.0 / rate, size=len(reqs)) if rate else np.zeros(len(reqs))
     srv = ctx.server(lanes=lanes)
     tickets = [None] * len(reqs)
     t0 = time.perf_counter()
@@ -185,6 +303,47 @@ def serve(ctx, reqs, rate, lanes, seed):
     return results, sols, t1 - t0
 
 
+def serving_phase(ctx, count, lanes):
+    """C5: `count` requests of the batched family with sizes up to n = 512, FP32 mixed, served by one
+    server under Poisson arrivals at fractions of the mix's own saturation throughput; latency
+    percentiles, offered and achieved rates, and every result against its FP64 reference."""
+    import workloads as W
+    from workloads.problem import PREC_FP32, PREC_FP64
+    sreqs = W.c4_requests(count=count, sizes=SERVE_SIZES, precision=PREC_FP32, assembly_eps=ASSEMBLY_EPS,
+                          max_rank=SERVE_MAX_RANK)
+    log("serving references")
+    srefs = [u for _, u in ctx.solve_batch(
+        W.c4_requests(count=count, sizes=SERVE_SIZES, precision=PREC_FP64, eps=1e-7, tol=1e-8,
+                      assembly_eps=ASSEMBLY_EPS / 10, max_rank=SERVE_MAX_RANK), lanes=lanes)]
+
+    def summarise(res, sols, secs, offered):
+        serr = [tt_rel_diff(u, ur) if (u is not None and ur is not None) else float("inf")
+                for u, ur in zip(sols, srefs)]
+        lat = [r["latency_ms"] for r in res]
+        ok = sum(e <= 1e-6 for e in serr)
+        return {"offered_per_s": offered, "achieved_per_s": len(res) / secs, "solves_per_s": ok / secs,
+                "passed": ok, "p50_ms": percentile(lat, 50), "p90_ms": percentile(lat, 90),
+                "p99_ms": percentile(lat, 99), "max_ms": max(lat),
+                "mean_queue_ms": sum(r["queue_ms"] for r in res) / len(res), "rel_err_max": max(serr)}
+
+    log("serving: saturation (all requests at once)")
+    res, sols, secs = serve(ctx, sreqs, None, lanes, SERVE_SEED)
+    sat_line = summarise(res, sols, secs, None)
+    sat = sat_line["achieved_per_s"]
+    lines = []
+    for frac in SERVE_RATES:
+        log("serving at", frac, "x saturation")
+        res, sols, secs = serve(ctx, sreqs, frac * sat, lanes, SERVE_SEED)
+        line = summarise(res, sols, secs, frac * sat)
+        line["fraction_of_saturation"] = frac
+        lines.append(line)
+    return {"requests": count, "arrival": f"Poisson, seed {SERVE_SEED}", "lanes": lanes,
+            "workload": ("n in {32,64,128,256,512}, p in {2,3}, annulus sector or twisted box, seeded Fourier "
+                         f"source, FP32 mixed, assembly at {ASSEMBLY_EPS:g}, seeds 10000+b"),
+            "saturation": sat_line, "rates": lines,
+            "percentiles": f"nearest rank over {count} requests per rate"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,7 +355,8 @@ def main():
     ap.add_argument("--family", type=int, default=256, help="requests of the batched family (0: skip)")
     ap.add_argument("--serve", type=int, default=32, help="requests per serving rate (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slabs", type=int, default=24)
+    ap.add_argument("--cpu-slabs", type=int, default=8)
+    ap.add_argument("--cpu-n", type=int, default=32, help="basis functions per direction of the oracle sample")
     ap.add_argument("--workspace-gib", type=float, default=200.0)
     ap.add_argument("--single-only", action="store_true",
                     help="only the single-solve phase (value = its solve rate): the run whose kernel "
@@ -207,6 +367,13 @@ def main():
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="only copy this many GiB device-to-device three times (scale of the HBM "
                          "byte counters) and exit")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving measurement (use with --serve 300 for resolved percentiles)")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the synthetic TT-matvec sweep (value = the best fraction of HBM bandwidth)")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-point", type=str, default="",
+                    help="rK,rx,n,p: run only this point of the sweep (with --sweep-only)")
     ap.add_argument("--traffic-kib", type=str, default="",
                     help="measured FETCH_SIZE,WRITE_SIZE of the roofline kernel (KiB per dispatch, "
                          "already scaled by the copy calibration) to report as roofline.traffic")
@@ -253,6 +420,28 @@ def main():
     mixed = [W.c2_problem(n=args.n, seed=s, precision=PREC_FP32) for s in seeds]
     refs_pr = [W.c2_problem(n=args.n, seed=s, eps=eps / 10, tol=tol / 10) for s in seeds]
 
+    if args.serve_only:
+        sv = serving_phase(ctx, args.serve, args.lanes)
+        at1 = next(q for q in sv["rates"] if q["fraction_of_saturation"] == 1.0)
+        print(json.dumps({
+            "metric": "served solves/s at 1e-6 rel-L2 (Poisson arrivals at the mix's saturation rate)",
+            "value": at1["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": len(SERVE_RATES) + 1,
+            "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic", "config": {"workload": sv["workload"]}, "serving": sv}),
+            flush=True)
+        return
+
+    if args.sweep_only:
+        log("TT-matvec sweep")
+        only = tuple(int(v) for v in args.sweep_point.split(",")) if args.sweep_point else None
+        sw = matvec_sweep(ctx, only=only)
+        print(json.dumps({
+            "metric": "TT-matvec HBM fraction (synthetic sweep)", "value": sw["max_hbm_frac"], "unit": "fraction",
+            "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": {"workload": sw["recipe"]},
+            "tt_matvec_sweep": sw}), flush=True)
+        return
+
     if args.batched_only:
         log("batched FP64 steps only")
         for _ in range(args.warmup):
@@ -297,8 +486,9 @@ def main():
     if args.traffic_kib:
         fetch_kib, write_kib = (float(v) for v in args.traffic_kib.split(","))
         roof["traffic"] = 1024.0 * (fetch_kib + write_kib)
-    elif dom[0] in MEASURED_TRAFFIC_KIB:
-        roof["traffic"] = 1024.0 * sum(MEASURED_TRAFFIC_KIB[dom[0]])
+        roof["traffic_source"] = "--traffic-kib"
+    else:
+        roof["traffic"], roof["traffic_source"] = measured_traffic(dom[0])
     mv = prof.get("tt_matvec_banded")
 
     if args.single_only:
@@ -381,6 +571,12 @@ def main():
                                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]},
     }
 
+    if not args.no_sweep:
+        log("TT-matvec sweep")
+        sw = matvec_sweep(ctx)
+        out["tt_matvec_sweep"] = {k: v for k, v in sw.items() if k != "points"}
+        out["tt_matvec_sweep"]["best"] = max(sw["points"], key=lambda q: q["hbm_frac"])
+
     # 4. batched family (mixed sizes/geometries, FP32 mixed) and 5. serving of it
     if args.family > 0:
         log("batched family")
@@ -400,32 +596,23 @@ def main():
                                  "workload": "n in {32,64,128,256}, p in {2,3}, annulus sector or twisted box, "
                                              "seeded Fourier source, FP32 mixed, seeds 10000+b, "
                                              f"TT eps 1e-6, assembly at {ASSEMBLY_EPS:g}"}
-        if args.serve > 0:
-            # the served requests: sizes n in {32..512}, otherwise drawn as the batched family
-            sreqs = W.c4_requests(count=args.serve, sizes=SERVE_SIZES, precision=PREC_FP32,
-                                  assembly_eps=ASSEMBLY_EPS, max_rank=SERVE_MAX_RANK)
-            log("serving references")
-            srefs = [u for _, u in ctx.solve_batch(
-                W.c4_requests(count=args.serve, sizes=SERVE_SIZES, precision=PREC_FP64, eps=1e-7, tol=1e-8,
-                              assembly_eps=ASSEMBLY_EPS / 10, max_rank=SERVE_MAX_RANK),
-                lanes=args.lanes)]
-            lines = []
-            for frac in SERVE_RATES:
-                log("serving at", frac, "x saturation")
-                res, sols, secs = serve(ctx, sreqs, frac * sat, args.lanes, SERVE_SEED)
-                serr = [tt_rel_diff(u, ur) if (u is not None and ur is not None) else float("inf")
-                        for u, ur in zip(sols, srefs)]
-                lat_ms = [r["latency_ms"] for r in res]
-                lines.append({"rate_per_s": frac * sat, "solves_per_s": sum(e <= 1e-6 for e in serr) / secs,
-                              "p50_ms": percentile(lat_ms, 50), "p99_ms": percentile(lat_ms, 99),
-                              "mean_queue_ms": sum(r["queue_ms"] for r in res) / len(res),
-                              "rel_err_max": max(serr)})
-            out["serving"] = {"requests": len(sreqs), "arrival": f"Poisson, seed {SERVE_SEED}",
-                              "workload": "n in {32,64,128,256,512}, otherwise as the batched family",
-                              "rates": lines}
+    if args.serve > 0:
+        log("serving")
+        out["serving"] = serving_phase(ctx, args.serve, args.lanes)
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_slabs)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_slabs, args.n)
+        # the GPU's rate on the same problem as the oracle sample (single FP64 solve, warm context)
+        small = W.c2_problem(n=args.cpu_n)
+        ts = []
+        for _ in range(3):
+            h = ctx.problem_create(small, precond=1)
+            t0 = time.perf_counter()
+            h.assemble()
+            h.solve()
+            ts.append(time.perf_counter() - t0)
+            h.close()
+        out["cpu_baseline"]["gpu_same_problem_solves_per_s"] = 1.0 / min(ts[1:])
     print(json.dumps(out), flush=True)
 
 

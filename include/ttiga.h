@@ -65,9 +65,20 @@ extern "C" {
 #define TTIGA_SOURCE_MANUFACTURED_ANNULUS 1 /* forcing of u = sin(pi r) sin(2 theta) sin(pi z) */
 #define TTIGA_SOURCE_FOURIER 2              /* sum_m a_m sin(pi k_m.(x - origin)/scale + phi_m) */
 
+/* Exact solutions for ttiga_l2_error (Section 5): the manufactured field of the quarter
+ * annulus workload; the radial Laplace solution between coaxial cylinders of radii
+ * r_in < r_out with u = u_in at r_in and u_out at r_out (the ring of Section 5.2),
+ * params = {r_in, r_out, u_in, u_out}; the L-shape solution of Section 5.1 for
+ * f = sin(pi x) sin(pi y). */
+#define TTIGA_EXACT_MANUFACTURED_ANNULUS 1 /* u = sin(pi r) sin(2 theta) sin(pi z) */
+#define TTIGA_EXACT_RADIAL_LOG 2           /* u = (u_in ln(r_out/r) + u_out ln(r/r_in)) / ln(r_out/r_in) */
+#define TTIGA_EXACT_SINE_XY 3              /* u = sin(pi x) sin(pi y) / (2 pi^2) */
+
 #define TTIGA_BC_NATURAL 0  /* zero traction: nothing to impose */
 #define TTIGA_BC_ZERO 1     /* homogeneous Dirichlet */
 #define TTIGA_BC_CONSTANT 2 /* u = value on the face */
+#define TTIGA_BC_TRACTION 3 /* natural face with the flux du/dn = value (outward normal): adds
+                               value * int_face N_a dS to F (Section 3.1) */
 
 #define TTIGA_FP64 0
 #define TTIGA_FP32 1
@@ -241,6 +252,25 @@ int ttiga_solution_ranks(const ttiga_problem* prob, int ranks[4], int n[3]);
  * E_ARG if dst is null or count is below the total; E_STATE before a solve. */
 int ttiga_get_solution(const ttiga_problem* prob, double* dst, size_t count);
 
+/* Accuracy of the solution (Section 5, eq. L2norm read with squares and a root): the
+ * relative L2 error ||u_h - u||_L2(Omega) / ||u||_L2(Omega) against an exact solution u
+ * (TTIGA_EXACT_*; params as listed there, else NULL), by Gauss quadrature with
+ * p + extra_gauss points per knot span on the exact geometry (dOmega = det J dxi), all of it
+ * evaluated in TT format on the device: u_h on the grid from the solution cores, u and
+ * w det J compressed by TT-SVD at 1e-13, their difference rounded by Householder sweeps and
+ * its weighted square norm contracted core by core.  out = {relative error, ||u_h - u||,
+ * ||u||} (host).  E_STATE before a solve; E_ARG on an unknown kind, bad parameters or
+ * p + extra_gauss > 16; E_DETJ if det J <= 0 on the error grid. */
+int ttiga_l2_error(ttiga_problem* prob, int exact_kind, const double* params, int extra_gauss, double out[3]);
+
+/* Compression ratios (entries of the full-grid object over entries of its TT cores, the
+ * figure the paper reports for its operators and vectors in Section 5): out[0] K^TT (banded
+ * cores) against the sparse IGA stiffness matrix, whose non-zeros are
+ * prod_d (n_d (2p+1) - p (p+1)); out[1] K^TT against the dense N x N matrix (dense TT-matrix
+ * cores r n n r' counted); out[2] F^TT against N values; out[3] the solution TT against the
+ * N_I interior values (0 before a solve).  E_STATE before ttiga_assemble. */
+int ttiga_compression_ratios(ttiga_problem* prob, double out[4]);
+
 /* Which TT of an assembled problem a query refers to. */
 #define TTIGA_WHICH_K 0        /* full K, banded TT-matrix cores */
 #define TTIGA_WHICH_F 1        /* full F */
@@ -273,15 +303,25 @@ int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view
  * tuning.  Row-major device operands: op(A) is M x K (A stored M x K with leading
  * dimension lda, or K x M when ta != 0), op(B) is K x N (B stored K x N with ldb, or
  * N x K when tb != 0), C is M x N with ldc; batch >= 1 products at element strides sA,
- * sB, sC.  plan: NULL for the library's shape rule, else {bm, bn, splits} with (bm, bn)
- * one of (64, 64), (128, 64), (64, 128) and 1 <= splits <= K (the contraction cut into
- * that many chunks of a multiple of 32, partials summed in chunk order).  Synchronises
- * the stream.  E_ARG on null pointers, M, N, K or batch < 1, a leading dimension shorter
- * than a row, or a plan outside that set; the partial-tile workspace of a split product
- * comes from the context's allocator (E_OOM). */
+ * sB, sC.  plan: NULL for the library's own choice (its tuned table, else its shape
+ * rule), else {bm, bn, kchunk} with (bm, bn) one of (64, 64), (128, 64), (64, 128) and
+ * kchunk 0 (the whole contraction in one pass) or a multiple of 32 (the contraction cut
+ * into chunks of that length, partials summed in chunk order).  Synchronises the stream.
+ * E_ARG on null pointers, M, N, K or batch < 1, a leading dimension shorter than a row, a
+ * plan outside that set, or batch times chunks above 65535; the partial-tile workspace of
+ * a split product comes from the context's allocator (E_OOM). */
 int ttiga_gemm_f64(ttiga_ctx* ctx, int ta, int tb, int M, int N, int K, double alpha, const double* A,
                    long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
                    long sC, int batch, const int* plan);
+
+/* The product of ttiga_gemm_f64 with both operands rounded to dtype (TTIGA_FP32, or
+ * TTIGA_BF16 through FP32; round to nearest even) as they are staged, MFMA in that type with
+ * FP32 accumulation, FP64 in and out: the contraction of the mixed-precision solves' inner
+ * corrections (their Gram matrices, preconditioner transforms and rounded operator products).
+ * Arguments as ttiga_gemm_f64 without a plan; E_ARG also for any other dtype. */
+int ttiga_gemm_lowp(ttiga_ctx* ctx, int dtype, int ta, int tb, int M, int N, int K, double alpha, const double* A,
+                    long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+                    long sC, int batch);
 
 /* The same product with the operator cores rounded to dtype (TTIGA_FP32 or TTIGA_BF16,
  * round to nearest even; BF16 through FP32), the vector cores to FP32, FP32 products

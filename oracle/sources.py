@@ -36,3 +36,11 @@ def ring_log_solution(x, r_in, r_out, u_in, u_out):
     x = np.asarray(x, dtype=np.float64)
     r = np.sqrt(x[..., 0] ** 2 + x[..., 1] ** 2)
     return (u_in * np.log(r_out / r) + u_out * np.log(r / r_in)) / np.log(r_out / r_in)
+
+
+def lshape_solution(x):
+    """u = sin(pi x) sin(pi y) / (2 pi^2), the exact solution of the L-shape experiment
+    (Section 5.1) for f = sin(pi x) sin(pi y): it vanishes on the lateral faces of the L
+    (x or y in {-1, 0, 1}) and does not depend on z (natural faces at z = 0 and z = 1)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.sin(np.pi * x[..., 0]) * np.sin(np.pi * x[..., 1]) / (2.0 * np.pi ** 2)

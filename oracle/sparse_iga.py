@@ -13,9 +13,9 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from workloads.problem import BC_CONSTANT, BC_NATURAL, BC_ZERO
+from workloads.problem import BC_CONSTANT, BC_NATURAL, BC_TRACTION, BC_ZERO
 
-from . import bspline, geometry
+from . import bspline, geometry, nurbs
 
 
 def one_d_tables(problem):
@@ -53,7 +53,33 @@ def assemble(problem, factors=None):
             K = K + G[i].T @ sp.diags(W * Rfull[i, j]) @ G[j]
     B0 = _kron3(tabs[0]["B"], tabs[1]["B"], tabs[2]["B"])
     F = B0.T @ (W * factors[6].ravel())
-    return K.tocsr(), np.asarray(F).ravel()
+    return K.tocsr(), np.asarray(F).ravel() + traction_load(problem, tabs)
+
+
+def traction_load(problem, tabs=None):
+    """Boundary term of the weak form on natural faces with a flux (Section 3.1):
+    F_a += g_f int_face N_a dS, dS = |dx/dxi_i x dx/dxi_j| dxi_i dxi_j over the face's two
+    tangential directions, by the tensor Gauss rule of the volume in those directions."""
+    if tabs is None:
+        tabs = one_d_tables(problem)
+    n = problem.disc.n_basis
+    F = np.zeros(tuple(n))
+    for face in range(6):
+        if problem.dirichlet.kind[face] != BC_TRACTION:
+            continue
+        d, side = divmod(face, 2)
+        i, j = [e for e in range(3) if e != d]
+        nodes = [tabs[e]["nodes"] for e in range(3)]
+        nodes[d] = np.array([float(side)])
+        _, J = nurbs.solid_map_grid(problem.geometry, *nodes)
+        Js = np.linalg.norm(np.cross(J[..., :, i], J[..., :, j]), axis=-1)
+        Js = Js.reshape(len(tabs[i]["nodes"]), len(tabs[j]["nodes"]))
+        Wf = np.outer(tabs[i]["weights"], tabs[j]["weights"]) * Js
+        S = tabs[i]["B"].T @ Wf @ tabs[j]["B"]  # (n_i, n_j)
+        sl = [slice(None)] * 3
+        sl[d] = 0 if side == 0 else n[d] - 1
+        F[tuple(sl)] += problem.dirichlet.value[face] * S
+    return F.ravel()
 
 
 def dirichlet_values(problem):
@@ -63,7 +89,7 @@ def dirichlet_values(problem):
     vals = np.zeros(tuple(n))
     for face in range(6):
         kind = problem.dirichlet.kind[face]
-        if kind == BC_NATURAL:
+        if kind in (BC_NATURAL, BC_TRACTION):
             continue
         d, side = divmod(face, 2)
         sl = [slice(None)] * 3

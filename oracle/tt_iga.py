@@ -28,7 +28,7 @@ Steps, in the paper's order:
 """
 import numpy as np
 
-from workloads.problem import BC_NATURAL
+from workloads.problem import BC_NATURAL, BC_TRACTION
 
 from . import geometry, sparse_iga, tt
 
@@ -82,12 +82,18 @@ def assemble_K(problem, R_tts, tabs=None, eps=None):
 
 
 def assemble_F(problem, fj_tt, tabs=None):
-    if fj_tt is None:
-        return None
+    """F^TT cores sum_q w_q G_d(a, q, a') N_k(q) (Section 4.2.2), plus the flux of traction
+    faces (Section 3.1; the full-grid traction vector of the sparse assembly, TT-SVD at 1e-15,
+    added and rounded)."""
     if tabs is None:
         tabs = sparse_iga.one_d_tables(problem)
-    return [np.einsum("aqb,q,qk->akb", fj_tt[d], tabs[d]["weights"], tabs[d]["B"])
-            for d in range(3)]
+    F = None
+    if fj_tt is not None:
+        F = [np.einsum("aqb,q,qk->akb", fj_tt[d], tabs[d]["weights"], tabs[d]["B"]) for d in range(3)]
+    if any(k == BC_TRACTION for k in problem.dirichlet.kind):
+        Fs = tt.tt_svd(sparse_iga.traction_load(problem, tabs).reshape(tuple(problem.disc.n_basis)), eps=1e-15)
+        F = Fs if F is None else tt.round_(tt.add(F, Fs), eps=1e-15)
+    return F
 
 
 def interior_slices(problem):
@@ -95,8 +101,8 @@ def interior_slices(problem):
     n = problem.disc.n_basis
     out = []
     for d in range(3):
-        lo = 0 if problem.dirichlet.kind[2 * d] == BC_NATURAL else 1
-        hi = n[d] if problem.dirichlet.kind[2 * d + 1] == BC_NATURAL else n[d] - 1
+        lo = 0 if problem.dirichlet.kind[2 * d] in (BC_NATURAL, BC_TRACTION) else 1
+        hi = n[d] if problem.dirichlet.kind[2 * d + 1] in (BC_NATURAL, BC_TRACTION) else n[d] - 1
         out.append(slice(lo, hi))
     return out
 

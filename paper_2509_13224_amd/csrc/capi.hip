@@ -436,6 +436,22 @@ int ttiga_get_solution(const ttiga_problem* prob, double* dst, size_t count) {
   });
 }
 
+int ttiga_l2_error(ttiga_problem* prob, int exact_kind, const double* params, int extra_gauss, double out[3]) {
+  return guard([&] {
+    TTIGA_CHECK(prob && out, TTIGA_E_ARG, "null argument");
+    Problem& P = *prob->impl;
+    TTIGA_HIP(hipSetDevice(P.ctx->device));
+    P.l2_error(exact_kind, params, extra_gauss, out);
+  });
+}
+
+int ttiga_compression_ratios(ttiga_problem* prob, double out[4]) {
+  return guard([&] {
+    TTIGA_CHECK(prob && out, TTIGA_E_ARG, "null argument");
+    prob->impl->compression_ratios(out);
+  });
+}
+
 int ttiga_problem_tt_info(const ttiga_problem* prob, int which, int ranks[4], int n[3], int* band) {
   return guard([&] {
     TTIGA_CHECK(prob && ranks && n, TTIGA_E_ARG, "null argument");
@@ -479,22 +495,36 @@ int ttiga_gemm_f64(ttiga_ctx* ctx, int ta, int tb, int M, int N, int K, double a
                 "gemm: leading dimension shorter than a row");
     Context& c = ctx->impl;
     TTIGA_HIP(hipSetDevice(c.device));
-    GemmPlan g = gemm_plan(M, N, K, batch);
+    GemmPlan g = gemm_plan(ta != 0, tb != 0, M, N, K, batch);
     if (plan) {
       const bool tile_ok = (plan[0] == 64 && plan[1] == 64) || (plan[0] == 128 && plan[1] == 64) ||
                            (plan[0] == 64 && plan[1] == 128);
-      TTIGA_CHECK(tile_ok && plan[2] >= 1 && plan[2] <= K, TTIGA_E_ARG, "gemm: unknown plan");
+      TTIGA_CHECK(tile_ok && plan[2] >= 0 && plan[2] % 32 == 0, TTIGA_E_ARG, "gemm: unknown plan");
       g.bm = plan[0];
       g.bn = plan[1];
-      int kchunk = (K + plan[2] - 1) / plan[2];
-      kchunk = (kchunk + 31) / 32 * 32;
-      g.kchunk = kchunk;
-      g.splits = (K + kchunk - 1) / kchunk;
+      g.kchunk = (plan[2] == 0 || plan[2] >= K) ? K : plan[2];
+      g.splits = (K + g.kchunk - 1) / g.kchunk;
+      TTIGA_CHECK((long)batch * g.splits <= 65535, TTIGA_E_ARG, "gemm: batch times splits above 65535");
     }
     DBuf part;
     if (g.splits > 1) part = DBuf(c.alloc, sizeof(double) * gemm_part_doubles(g, M, N, batch));
     gemm_planned(c, g, ta != 0, tb != 0, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
                  part.d());
+    c.sync();
+  });
+}
+
+int ttiga_gemm_lowp(ttiga_ctx* ctx, int dtype, int ta, int tb, int M, int N, int K, double alpha, const double* A,
+                    long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
+                    long sC, int batch) {
+  return guard([&] {
+    TTIGA_CHECK(ctx && A && B && C, TTIGA_E_ARG, "null argument");
+    TTIGA_CHECK(M >= 1 && N >= 1 && K >= 1 && batch >= 1, TTIGA_E_ARG, "gemm: sizes must be positive");
+    TTIGA_CHECK(lda >= (ta ? M : K) && ldb >= (tb ? K : N) && ldc >= N, TTIGA_E_ARG,
+                "gemm: leading dimension shorter than a row");
+    Context& c = ctx->impl;
+    TTIGA_HIP(hipSetDevice(c.device));
+    gemm_lowp(c, dtype, ta != 0, tb != 0, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
     c.sync();
   });
 }

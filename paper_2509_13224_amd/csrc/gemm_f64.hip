@@ -11,12 +11,15 @@
 // so the staging writes and the MFMA operand reads both hit distinct banks.
 //
 // Which tile and how many K splits a product takes is a pure function of its shape
-// (gemm_plan): the same product runs the same code, with the same summation order, in
-// every problem, process and mix.  K splits write partial tiles that a second kernel adds
-// in a fixed order; there are no atomics.
+// (gemm_plan: a table measured offline by tune_gemm.py, else a fixed rule): the same product
+// runs the same code, with the same summation order, in every problem, process and mix.  K
+// splits write partial tiles that a second kernel adds in a fixed order; there are no atomics.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdint>
+#include <cstdlib>
 
 #include "runtime.hpp"
 
@@ -152,6 +155,148 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
       }
 }
 
+// ------------------------------------------------------------------ low precision
+// The same product with the operands rounded to FP32 or BF16 (round to nearest even; BF16
+// through FP32) as they are staged, MFMA in that type with FP32 accumulation
+// (v_mfma_f32_16x16x4_f32, or v_mfma_f32_16x16x16_bf16 with four contraction indices per
+// lane), FP64 in and out: the contractions of a mixed-precision solve whose FP64 result only
+// needs the low type's accuracy.  64x64 tiles of four waves, the contraction staged 32 at a
+// time with the next step's loads in flight, LDS in FP32 (BF16 values are exact in it).
+__device__ inline float round_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return f;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+template <bool KMajor>
+struct TileLdsF {
+  static constexpr int kLd = KMajor ? 64 + 16 : kGK + 2;
+  static constexpr int kElems = (KMajor ? kGK : 64) * kLd;
+  __device__ static int at(int x, int k) { return KMajor ? k * kLd + x : x * kLd + k; }
+};
+
+template <bool TA, bool TB, int PREC>
+__global__ __launch_bounds__(256) void k_gemm_lowp(int M, int N, int K, double alpha,
+                                                   const double* __restrict__ A, long lda, long sA,
+                                                   const double* __restrict__ B, long ldb, long sB,
+                                                   double beta, double* __restrict__ C, long ldc, long sC,
+                                                   int splits, int kchunk, double* __restrict__ Cpart) {
+  using LA = TileLdsF<TA>;
+  using LB = TileLdsF<!TB>;
+  constexpr int kLoad = 64 * kGK / 256;
+  __shared__ float As[LA::kElems];
+  __shared__ float Bs[LB::kElems];
+  const int bz = blockIdx.z;
+  const int batch = bz / splits, split = bz % splits;
+  A += batch * sA;
+  B += batch * sB;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  auto a_xk = [&](int e, int& x, int& k) {
+    if (TA) { x = e % 64; k = e / 64; } else { k = e % kGK; x = e / kGK; }
+  };
+  auto b_xk = [&](int e, int& x, int& k) {
+    if (TB) { k = e % kGK; x = e / kGK; } else { x = e % 64; k = e / 64; }
+  };
+  auto lowp = [](double v) {
+    const float f = (float)v;
+    return PREC == TTIGA_BF16 ? round_bf16(f) : f;
+  };
+  float ra[kLoad], rb[kLoad];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < kLoad; ++i) {
+      int x, k;
+      a_xk(tid + 256 * i, x, k);
+      const int gm = m0 + x, gk = k0 + k;
+      ra[i] = (gm < M && gk < kend) ? lowp(TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk]) : 0.0f;
+      b_xk(tid + 256 * i, x, k);
+      const int gn = n0 + x, gk2 = k0 + k;
+      rb[i] = (gn < N && gk2 < kend) ? lowp(TB ? B[(long)gn * ldb + gk2] : B[(long)gk2 * ldb + gn]) : 0.0f;
+    }
+  };
+  f4_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kGK) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kLoad; ++i) {
+      int x, k;
+      a_xk(tid + 256 * i, x, k);
+      As[LA::at(x, k)] = ra[i];
+      b_xk(tid + 256 * i, x, k);
+      Bs[LB::at(x, k)] = rb[i];
+    }
+    __syncthreads();
+    if (k0 + kGK < kend) load(k0 + kGK);
+    if constexpr (PREC == TTIGA_BF16) {
+      // 16 contraction indices per MFMA: lane holds indices 4 (lane >> 4) + j, j = 0..3
+#pragma unroll
+      for (int kk = 0; kk < kGK; kk += 16) {
+        s4_t a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int kr = kk + 4 * (lane >> 4) + j;
+            a[i][j] = (short)(__float_as_uint(As[LA::at(wm + 16 * i + (lane & 15), kr)]) >> 16);
+            b[i][j] = (short)(__float_as_uint(Bs[LB::at(wn + 16 * i + (lane & 15), kr)]) >> 16);
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < kGK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        float a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[i] = As[LA::at(wm + 16 * i + (lane & 15), kr)];
+          b[i] = Bs[LB::at(wn + 16 * i + (lane & 15), kr)];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  // D layout of the FP32-accumulating 16x16 MFMAs: lane holds column (lane & 15) of rows
+  // 4 (lane >> 4) + v
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + v;
+        const int col = n0 + wn + 16 * j + (lane & 15);
+        if (row < M && col < N) {
+          const double s = (double)acc[i][j][v];
+          if (splits == 1) {
+            double* c = C + batch * sC + (long)row * ldc + col;
+            *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
+          } else {
+            Cpart[((long)bz * M + row) * N + col] = s;
+          }
+        }
+      }
+}
+
 // C = alpha * (sum of the K-split partial tiles, in split order) + beta C
 __global__ void k_splitk_reduce(int M, int N, int splits, int batches, double alpha,
                                 const double* __restrict__ Cpart, double beta, double* C, long ldc,
@@ -169,8 +314,43 @@ __global__ void k_splitk_reduce(int M, int N, int splits, int batches, double al
   }
 }
 
-GemmPlan gemm_plan(int M, int N, int K, int batch) {
+// Tuned plans: one entry per shape bucket that measured faster than the rule below, written
+// by tune_gemm.py (offline, on the target GPU) and compiled in, so the choice is the same in
+// every run and process.
+namespace {
+struct GemmEntry {
+  int ta, tb, lm, ln, lk, batched, bm, bn, kchunk;
+};
+const GemmEntry kGemmTable[] = {
+#include "gemm_table.inc"
+    {-1, 0, 0, 0, 0, 0, 0, 0, 0}};
+int ceil_log2(long v) {
+  int b = 0;
+  while ((1L << b) < v) ++b;
+  return b;
+}
+}  // namespace
+
+GemmPlan gemm_plan(bool ta, bool tb, int M, int N, int K, int batch) {
   GemmPlan g;
+  const int key[6] = {ta ? 1 : 0, tb ? 1 : 0, ceil_log2(M), ceil_log2(N), ceil_log2(K), batch > 1 ? 1 : 0};
+  for (const GemmEntry* e = kGemmTable; e->ta >= 0; ++e) {
+    if (e->ta != key[0] || e->tb != key[1] || e->lm != key[2] || e->ln != key[3] || e->lk != key[4] ||
+        e->batched != key[5])
+      continue;
+    g.bm = e->bm;
+    g.bn = e->bn;
+    if (e->kchunk > 0 && e->kchunk < K) {
+      g.kchunk = e->kchunk;
+      g.splits = (K + g.kchunk - 1) / g.kchunk;
+    } else {
+      g.kchunk = K;
+      g.splits = 1;
+    }
+    if (batch * g.splits <= 65535) return g;
+    g = GemmPlan();
+    break;
+  }
   // a 128-wide tile where the other dimension is long and this one fits in 65..128: the
   // long operand is then streamed once instead of twice
   if (M > 64 && M <= 128 && N > 128) g.bm = 128;
@@ -226,6 +406,57 @@ void gemm_planned(Context& ctx, const GemmPlan& g, bool ta, bool tb, int M, int 
   }
 }
 
+void gemm_lowp(Context& ctx, int dtype, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+               long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC,
+               int batch) {
+  TTIGA_CHECK(dtype == TTIGA_FP32 || dtype == TTIGA_BF16, TTIGA_E_ARG, "low-precision GEMM is FP32 or BF16");
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0) {
+    gemm(ctx, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+    return;
+  }
+  GemmPlan g = gemm_plan(ta, tb, M, N, K, batch);
+  g.bm = g.bn = 64;  // the low-precision kernel has one tile shape
+  TTIGA_CHECK(batch <= 65535 / std::max(1, g.splits), TTIGA_E_ARG, "gemm: batch too large");
+  DBuf part;
+  if (g.splits > 1) part = DBuf(ctx.alloc, sizeof(double) * gemm_part_doubles(g, M, N, batch));
+  ProfScope prof(ctx, dtype == TTIGA_BF16 ? "gemm_bf16" : "gemm_fp32", 2.0 * M * N * (double)K * batch,
+                 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N));
+  dim3 grid((N + 63) / 64, (M + 63) / 64, batch * g.splits);
+#define TTIGA_LP_LAUNCH(TA, TB, PR)                                                                      \
+  hipLaunchKernelGGL((k_gemm_lowp<TA, TB, PR>), grid, dim3(256), 0, ctx.stream, M, N, K, alpha, A, lda, sA, B, \
+                     ldb, sB, beta, C, ldc, sC, g.splits, g.kchunk, part.d())
+#define TTIGA_LP_PREC(PR)                                     \
+  if (!ta && !tb) TTIGA_LP_LAUNCH(false, false, PR);          \
+  else if (ta && !tb) TTIGA_LP_LAUNCH(true, false, PR);       \
+  else if (!ta && tb) TTIGA_LP_LAUNCH(false, true, PR);       \
+  else TTIGA_LP_LAUNCH(true, true, PR)
+  if (dtype == TTIGA_BF16) {
+    TTIGA_LP_PREC(TTIGA_BF16);
+  } else {
+    TTIGA_LP_PREC(TTIGA_FP32);
+  }
+#undef TTIGA_LP_PREC
+#undef TTIGA_LP_LAUNCH
+  TTIGA_HIP(hipGetLastError());
+  if (g.splits > 1) {
+    const long total = (long)batch * M * N;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(total)), dim3(256), 0, ctx.stream, M, N, g.splits, batch,
+                       alpha, part.d(), beta, C, ldc, sC);
+    TTIGA_HIP(hipGetLastError());
+  }
+}
+
+void gemm_c(Context& ctx, bool operator_, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+            long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC,
+            int batch) {
+  if (ctx.lowp == 0)
+    gemm(ctx, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+  else
+    gemm_lowp(ctx, operator_ ? ctx.lowp : TTIGA_FP32, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc,
+              sC, batch);
+}
+
 size_t gemm_part_doubles(const GemmPlan& g, int M, int N, int batch) {
   return g.splits > 1 ? (size_t)batch * g.splits * M * N : 0;
 }
@@ -251,7 +482,9 @@ void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, con
     TTIGA_HIP(hipGetLastError());
     return;
   }
-  const GemmPlan g = gemm_plan(M, N, K, batch);
+  static const bool trace = std::getenv("TTIGA_GEMM_TRACE") != nullptr;
+  if (trace) std::fprintf(stderr, "[gemm-shape] ta=%d tb=%d M=%d N=%d K=%d batch=%d\n", ta, tb, M, N, K, batch);
+  const GemmPlan g = gemm_plan(ta, tb, M, N, K, batch);
   DBuf part;
   if (g.splits > 1) part = DBuf(ctx.alloc, sizeof(double) * gemm_part_doubles(g, M, N, batch));
   gemm_planned(ctx, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part.d());

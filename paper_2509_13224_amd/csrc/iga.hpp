@@ -29,6 +29,12 @@ struct SourceDev {
   int int_kmax;
 };
 
+// An exact solution u(x) of the problem, for measuring a solution's L2 error.
+struct ExactDev {
+  int kind;       // TTIGA_EXACT_*
+  double prm[4];  // radial log: r_in, r_out, u_in, u_out
+};
+
 constexpr int kMaxIntWave = 8;
 constexpr int kMaxRowModes = 64;  // Fourier modes whose phase shifts the row kernel caches
 
@@ -50,6 +56,18 @@ void launch_detj_min(Context& ctx, const GeoDev& geo, const int* Q, double* min_
 // Grid points (i0[q], i1[q], i2[q]) (device index arrays): out[7][count], det (optional).
 void launch_factors_at(Context& ctx, const GeoDev& geo, const SourceDev& src, long count, const int* i0,
                        const int* i1, const int* i2, double* out, double* det);
+// Error grid: the exact solution and w0 w1 w2 det J of the slabs b0 .. b0+c1-1 of the second
+// direction into F[2][Q0][c1][Q2]; stats8 gets their sums of squares (slots 0, 1) and min det J
+// (slot 7).  w[d]: the quadrature weights per direction.
+void launch_exact_grid(Context& ctx, const GeoDev& geo, const ExactDev& ex, const double* const* w, const int* Q,
+                       int b0, int c1, double* F, double* stats8);
+// |dx/dxi_i x dx/dxi_j| on the Qi x Qj tangential grid of a face xi_d = const (the geometry
+// tables of direction d hold the face's single point)
+void launch_surface_jac(Context& ctx, const GeoDev& geo, int d, int Qi, int Qj, double* out);
+// out[a][q][b] = sum_j B[q][j] U[a][e_q + j - lo][b] (the solution core on a grid of g points per
+// span; U has ni interior indices starting at global index lo)
+void launch_eval_core(Context& ctx, int ra, int rb, int Q, int g, int p, int lo, int ni, const double* B,
+                      const double* U, double* out);
 void launch_factors_points(Context& ctx, const GeoDev& geo, const SourceDev& src, long count,
                            double* out, double* det);
 void launch_assemble_band(Context& ctx, int n, int p, int g, int ra, int rb, const double* G,

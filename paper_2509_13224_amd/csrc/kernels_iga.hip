@@ -204,9 +204,9 @@ __device__ double jacobian_det(const double H[4], const double dH[3][4]) {
          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
-// One sample point: 7 factors and det J.  ga/gb/gc index the per-direction geometry tables.
-__device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, int ib, int ic,
-                              double* out7, double* det_out) {
+// Homogeneous sums H = (x w, y w, z w, w) of the NURBS map at one sample point and their
+// derivatives dH[i] along xi_i.  ia/ib/ic index the per-direction geometry tables.
+__device__ void homogeneous_sums(const GeoDev& geo, int ia, int ib, int ic, double H[4], double dH[3][4]) {
   const int p0 = geo.pg[0], p1 = geo.pg[1], p2 = geo.pg[2];
   const int s0 = geo.span[0][ia], s1 = geo.span[1][ib], s2 = geo.span[2][ic];
   const double* B0 = geo.B[0] + (long)ia * (p0 + 1);
@@ -215,7 +215,10 @@ __device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, i
   const double* D0 = geo.D[0] + (long)ia * (p0 + 1);
   const double* D1 = geo.D[1] + (long)ib * (p1 + 1);
   const double* D2 = geo.D[2] + (long)ic * (p2 + 1);
-  double H[4] = {0, 0, 0, 0}, dH[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int s = 0; s < 4; ++s) {
+    H[s] = 0.0;
+    dH[0][s] = dH[1][s] = dH[2][s] = 0.0;
+  }
   for (int a = 0; a <= p0; ++a) {
     for (int b = 0; b <= p1; ++b) {
       // partial sums over c first (sum factorisation of the inner direction)
@@ -237,7 +240,118 @@ __device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, i
       }
     }
   }
+}
+
+// One sample point: 7 factors and det J.
+__device__ void point_factors(const GeoDev& geo, const SourceDev& src, int ia, int ib, int ic,
+                              double* out7, double* det_out) {
+  double H[4], dH[3][4];
+  homogeneous_sums(geo, ia, ib, ic, H, dH);
   factors_from_sums(H, dH, src, nullptr, nullptr, out7, det_out);
+}
+
+// Exact solutions against which a computed solution's L2 error is measured (Section 5):
+// the manufactured field of the quarter-annulus workload, the radial Laplace solution
+// between two coaxial cylinders (the ring experiment of Section 5.2) and the L-shape
+// solution of Section 5.1.
+__device__ double exact_value(const ExactDev& ex, double x, double y, double z) {
+  const double pi = 3.141592653589793;
+  const double r = sqrt(x * x + y * y);
+  if (ex.kind == TTIGA_EXACT_MANUFACTURED_ANNULUS)
+    return sin(pi * r) * sin(2.0 * atan2(y, x)) * sin(pi * z);
+  if (ex.kind == TTIGA_EXACT_RADIAL_LOG)
+    return (ex.prm[2] * log(ex.prm[1] / r) + ex.prm[3] * log(r / ex.prm[0])) / log(ex.prm[1] / ex.prm[0]);
+  if (ex.kind == TTIGA_EXACT_SINE_XY) return sin(pi * x) * sin(pi * y) / (2.0 * pi * pi);
+  return 0.0;
+}
+
+// Error-grid sampling of the slabs b0 .. b0+c1-1 of the second direction: per point the
+// exact solution u(x(xi)) and the physical quadrature weight w0 w1 w2 det J; output
+// F[2][Q0][c1][Q2], per-block sums of squares of both (slots 0, 1) and min det J (slot 7)
+// to part[block][8].
+__global__ __launch_bounds__(256) void k_exact_grid(GeoDev geo, ExactDev ex, const double* __restrict__ w0,
+                                                    const double* __restrict__ w1, const double* __restrict__ w2,
+                                                    int Q0, int b0, int c1, int Q2, double* __restrict__ F,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[3][256];
+  const long total = (long)Q0 * c1 * Q2;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double acc[3] = {0.0, 0.0, 1e300};
+  if (e < total) {
+    const int i2 = (int)(e % Q2);
+    const int i1 = b0 + (int)((e / Q2) % c1);
+    const int i0 = (int)(e / ((long)c1 * Q2));
+    double H[4], dH[3][4];
+    homogeneous_sums(geo, i0, i1, i2, H, dH);
+    const double iW = 1.0 / H[3];
+    const double u = exact_value(ex, H[0] * iW, H[1] * iW, H[2] * iW);
+    const double det = jacobian_det(H, dH);
+    const double wt = w0[i0] * w1[i1] * w2[i2] * det;
+    F[e] = u;
+    F[total + e] = wt;
+    acc[0] = u * u;
+    acc[1] = wt * wt;
+    acc[2] = det;
+  }
+  for (int f = 0; f < 3; ++f) sh[f][threadIdx.x] = acc[f];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+      sh[2][threadIdx.x] = fmin(sh[2][threadIdx.x], sh[2][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  // the layout of the factor statistics: sums of squares in slots 0 and 1, min det J in slot 7
+  if (threadIdx.x < 8)
+    part[(long)blockIdx.x * 8 + threadIdx.x] = threadIdx.x < 2 ? sh[threadIdx.x][0] : (threadIdx.x == 7 ? sh[2][0] : 0.0);
+}
+
+// Surface element of a face xi_d = const (geometry tables of direction d hold that one
+// point): |dx/dxi_i x dx/dxi_j| at the tangential Gauss points (qi, qj), i < j the other two
+// directions; out[qi * Qj + qj].
+__global__ void k_surface_jac(GeoDev geo, int d, int Qi, int Qj, double* __restrict__ out) {
+  const long total = (long)Qi * Qj;
+  const int i = d == 0 ? 1 : 0, j = d == 2 ? 1 : 2;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int qi = (int)(e / Qj), qj = (int)(e % Qj);
+    int idx[3];
+    idx[d] = 0;
+    idx[i] = qi;
+    idx[j] = qj;
+    double H[4], dH[3][4];
+    homogeneous_sums(geo, idx[0], idx[1], idx[2], H, dH);
+    const double iW = 1.0 / H[3];
+    double ti[3], tj[3];
+    for (int k = 0; k < 3; ++k) {
+      const double xk = H[k] * iW;
+      ti[k] = (dH[i][k] - xk * dH[i][3]) * iW;
+      tj[k] = (dH[j][k] - xk * dH[j][3]) * iW;
+    }
+    const double c0 = ti[1] * tj[2] - ti[2] * tj[1], c1 = ti[2] * tj[0] - ti[0] * tj[2],
+                 c2 = ti[0] * tj[1] - ti[1] * tj[0];
+    out[e] = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+  }
+}
+
+// Grid values of a solution TT: out[a][q][b] = sum_j B[q][j] u[a][(e_q + j) - lo][b] over the
+// p+1 B-splines non-zero at error-grid point q (span e_q = q / g), interior indices only.
+__global__ void k_eval_core(int ra, int rb, int Q, int g, int p, int lo, int ni, const double* __restrict__ B,
+                            const double* __restrict__ U, double* __restrict__ out) {
+  const long total = (long)ra * Q * rb;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(e % rb);
+    const int q = (int)((e / rb) % Q);
+    const int a = (int)(e / ((long)rb * Q));
+    const int el = q / g;
+    double s = 0.0;
+    for (int j = 0; j <= p; ++j) {
+      const int k = el + j - lo;
+      if (k >= 0 && k < ni) s += B[(long)q * (p + 1) + j] * U[((long)a * ni + k) * rb + b];
+    }
+    out[e] = s;
+  }
 }
 
 // The 7 factors and det J at one point from the homogeneous sums H (x w, y w, z w, w)
@@ -686,6 +800,31 @@ void launch_factors_grid(Context& ctx, const GeoDev& geo, const SourceDev& src, 
     hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks,
                        accumulate ? 1 : 0, stats8);
   }
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_exact_grid(Context& ctx, const GeoDev& geo, const ExactDev& ex, const double* const* w, const int* Q,
+                       int b0, int c1, double* F, double* stats8) {
+  TTIGA_CHECK(b0 >= 0 && c1 > 0 && b0 + c1 <= Q[1], TTIGA_E_ARG, "error-grid slab range out of the grid");
+  const long total = (long)Q[0] * c1 * Q[2];
+  const long blocks = (total + 255) / 256;
+  DBuf part(ctx.alloc, sizeof(double) * 8 * blocks);
+  hipLaunchKernelGGL(k_exact_grid, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, geo, ex, w[0], w[1], w[2],
+                     Q[0], b0, c1, Q[2], F, part.d());
+  hipLaunchKernelGGL(k_factors_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), blocks, 0, stats8);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_surface_jac(Context& ctx, const GeoDev& geo, int d, int Qi, int Qj, double* out) {
+  hipLaunchKernelGGL(k_surface_jac, dim3(grid_for((long)Qi * Qj)), dim3(256), 0, ctx.stream, geo, d, Qi, Qj, out);
+  TTIGA_HIP(hipGetLastError());
+}
+
+void launch_eval_core(Context& ctx, int ra, int rb, int Q, int g, int p, int lo, int ni, const double* B,
+                      const double* U, double* out) {
+  const long total = (long)ra * Q * rb;
+  hipLaunchKernelGGL(k_eval_core, dim3(grid_for(total)), dim3(256), 0, ctx.stream, ra, rb, Q, g, p, lo, ni, B, U,
+                     out);
   TTIGA_HIP(hipGetLastError());
 }
 

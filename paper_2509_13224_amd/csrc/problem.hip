@@ -114,21 +114,15 @@ Problem::Problem(Context* c, const ttiga_geometry* geo, const ttiga_discretizati
   for (int f = 0; f < 6; ++f) {
     bc_kind[f] = bc->kind[f];
     bc_value[f] = bc->value[f];
-    TTIGA_CHECK(bc_kind[f] >= TTIGA_BC_NATURAL && bc_kind[f] <= TTIGA_BC_CONSTANT, TTIGA_E_ARG,
+    TTIGA_CHECK(bc_kind[f] >= TTIGA_BC_NATURAL && bc_kind[f] <= TTIGA_BC_TRACTION, TTIGA_E_ARG,
                 "unknown boundary kind");
   }
-  // constant data must be carried by faces of one direction (rank-1 lifting)
-  int dir = -1;
-  for (int f = 0; f < 6; ++f)
-    if (bc_kind[f] == TTIGA_BC_CONSTANT && bc_value[f] != 0.0) {
-      TTIGA_CHECK(dir < 0 || dir == f / 2, TTIGA_E_ARG,
-                  "non-zero constant Dirichlet data on faces of more than one direction");
-      dir = f / 2;
-    }
-  lift_dir = dir;
+  // constant data on any faces: lifted by a TT of rank at most the number of such faces
+  lift = false;
+  for (int f = 0; f < 6; ++f) lift = lift || (bc_kind[f] == TTIGA_BC_CONSTANT && bc_value[f] != 0.0);
   for (int d = 0; d < 3; ++d) {
-    lo[d] = bc_kind[2 * d] == TTIGA_BC_NATURAL ? 0 : 1;
-    hi[d] = bc_kind[2 * d + 1] == TTIGA_BC_NATURAL ? n[d] : n[d] - 1;
+    lo[d] = is_dirichlet(bc_kind[2 * d]) ? 1 : 0;
+    hi[d] = is_dirichlet(bc_kind[2 * d + 1]) ? n[d] - 1 : n[d];
     TTIGA_CHECK(hi[d] - lo[d] >= 1, TTIGA_E_ARG, "no interior unknowns");
   }
   // options
@@ -552,6 +546,8 @@ void Problem::assemble(ttiga_assembly_stats* st) {
   } else {
     F.set_zero(n);
   }
+  for (int f = 0; f < 6; ++f)
+    if (bc_kind[f] == TTIGA_BC_TRACTION && bc_value[f] != 0.0) add_traction(f, eps);
   c.sync();
   double t3 = now_ms();
   s.time_ms[2] = t3 - t2;
@@ -566,6 +562,75 @@ void Problem::assemble(ttiga_assembly_stats* st) {
   assembled = true;
   solved = false;
   if (st) *st = s;
+}
+
+// The flux of a traction face f (Section 3.1: the boundary term of the weak form on a natural
+// face with du/dn = g): F_a += g int_face N_a dS.  On the face xi_d = 0 (or 1) only the first
+// (last) B-spline of direction d is non-zero, and equals 1; over the two tangential directions
+// i < j the integral is the Gauss sum of w_i w_j J_s N_ai N_aj with the surface element
+// J_s = |dx/dxi_i x dx/dxi_j|.  J_s on the tangential Gauss grid is compressed to a rank-r
+// two-mode TT (TT-SVD at 1e-2 eps of its norm), each mode contracted against the B-splines
+// like the cores of F, and the face vector g e_end placed in mode d: a TT of rank r added to F.
+void Problem::add_traction(int f, double eps) {
+  Context& c = *ctx;
+  const int d = f / 2, side = f % 2;
+  const int i = d == 0 ? 1 : 0, j = d == 2 ? 1 : 2;
+  // geometry tables: the tangential directions at their Gauss points, direction d at xi_d = side
+  DBuf xi1(c.alloc, sizeof(double)), span[3], GB[3], GD[3];
+  const double xv = (double)side;
+  TTIGA_HIP(hipMemcpyAsync(xi1.d(), &xv, sizeof(double), hipMemcpyHostToDevice, c.stream));
+  for (int e = 0; e < 3; ++e) {
+    const int cnt = e == d ? 1 : Q[e];
+    span[e] = DBuf(c.alloc, sizeof(int) * cnt);
+    GB[e] = DBuf(c.alloc, sizeof(double) * cnt * (pg[e] + 1));
+    GD[e] = DBuf(c.alloc, sizeof(double) * cnt * (pg[e] + 1));
+    launch_geo_tables(c, cnt, e == d ? xi1.d() : tab_xi[e].d(), 1, m[e], pg[e], gknots_d[e].d(), span[e].as<int>(),
+                      GB[e].d(), GD[e].d());
+  }
+  c.sync();  // the host value xv is read by the copy above
+  const GeoDev gd = geo_dev(span, GB, GD);
+  const int Qi = Q[i], Qj = Q[j];
+  DBuf Js(c.alloc, sizeof(double) * (size_t)Qi * Qj);
+  launch_surface_jac(c, gd, d, Qi, Qj, Js.d());
+  DBuf nrm(c.alloc, sizeof(double));
+  fill(c, nrm.d(), 1, 0.0);
+  sumsq_reduce(c, Js.d(), (size_t)Qi * Qj, nrm.d());
+  double* h = c.host(1);
+  TTIGA_HIP(hipMemcpyAsync(h, nrm.d(), sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+  TTIGA_CHECK(h[0] > 0.0, TTIGA_E_GEOM, "traction face has zero area");
+  TT S;  // J_s as a TT over (Q_i, Q_j, 1)
+  const int shape[3] = {Qi, Qj, 1};
+  tt_compress_dense(c, Js.d(), shape, 1e-2 * eps * std::sqrt(h[0]), S, opts.max_rank);
+  const int r = S.r[1];
+  // cores of the face load: ranks (1, r, 1, 1) for d = 0 ... in the order of the directions
+  int rr[4];
+  if (d == 0) { rr[0] = 1; rr[1] = 1; rr[2] = r; rr[3] = 1; }
+  else if (d == 1) { rr[0] = 1; rr[1] = r; rr[2] = r; rr[3] = 1; }
+  else { rr[0] = 1; rr[1] = r; rr[2] = 1; rr[3] = 1; }
+  TT Fs;
+  Fs.alloc(c, n, rr);
+  // mode i: the first core of S (1 x Q_i x r) against the B-splines; mode j: the second core
+  // times the third (r x Q_j x 1) against the B-splines
+  DBuf Sj(c.alloc, sizeof(double) * (size_t)r * Qj);
+  gemm(c, false, false, r * Qj, 1, S.r[2], 1.0, S.c[1].d(), S.r[2], 0, S.c[2].d(), 1, 0, 0.0, Sj.d(), 1, 0);
+  launch_assemble_vec(c, n[i], p, g, 1, r, S.c[0].d(), tab_w[i].d(), tab_B[i].d(), Fs.c[i].d());
+  launch_assemble_vec(c, n[j], p, g, r, 1, Sj.d(), tab_w[j].d(), tab_B[j].d(), Fs.c[j].d());
+  // mode d: g e_end, times the identity over the rank when d sits between i and j
+  const int rd = d == 1 ? r : 1;
+  std::vector<double> core((size_t)rd * n[d] * rd, 0.0);
+  for (int a = 0; a < rd; ++a) core[((size_t)a * n[d] + (side ? n[d] - 1 : 0)) * rd + a] = bc_value[f];
+  TTIGA_HIP(hipMemcpyAsync(Fs.c[d].d(), core.data(), sizeof(double) * core.size(), hipMemcpyHostToDevice,
+                           c.stream));
+  c.sync();
+  if (F.zero()) {
+    F = std::move(Fs);
+  } else {
+    TT sum;
+    tt_axpby(c, 1.0, F, 1.0, Fs, sum);
+    tt_round(c, sum, eps * 1e-2, -1.0, opts.max_rank);
+    F = std::move(sum);
+  }
 }
 
 void Problem::reduce_boundary() {
@@ -586,27 +651,35 @@ void Problem::reduce_boundary() {
   } else {
     FI.set_zero(ni);
   }
-  if (lift_dir >= 0) {
-    // u_g: rank 1; direction lift_dir carries the two face constants, the others are
-    // ones except at Dirichlet ends of later directions (later faces win at edges).
-    TT ug;
-    int r1[4] = {1, 1, 1, 1};
-    ug.alloc(c, n, r1);
-    for (int d = 0; d < 3; ++d) {
-      std::vector<double> v(n[d], 0.0);
-      if (d == lift_dir) {
-        if (bc_kind[2 * d] == TTIGA_BC_CONSTANT) v[0] = bc_value[2 * d];
-        if (bc_kind[2 * d + 1] == TTIGA_BC_CONSTANT) v[n[d] - 1] = bc_value[2 * d + 1];
-      } else {
-        std::fill(v.begin(), v.end(), 1.0);
-        if (d > lift_dir) {
-          if (bc_kind[2 * d] != TTIGA_BC_NATURAL) v[0] = 0.0;
-          if (bc_kind[2 * d + 1] != TTIGA_BC_NATURAL) v[n[d] - 1] = 0.0;
+  if (lift) {
+    // u_g: the face constants on the Dirichlet faces, 0 inside, the later face in face order
+    // winning where faces meet.  With m_f the indicator of face f (rank 1: the end vector of
+    // its direction times ones), u_g = sum_f c_f m_f prod_{f' > f Dirichlet} (1 - m_f'), and
+    // every term is rank 1: per direction the face's end vector (or ones) times, for each
+    // later Dirichlet face of that direction, ones with that face's end zeroed.
+    ug.set_zero(n);
+    for (int f = 0; f < 6; ++f) {
+      if (bc_kind[f] != TTIGA_BC_CONSTANT || bc_value[f] == 0.0) continue;
+      TT term;
+      int r1[4] = {1, 1, 1, 1};
+      term.alloc(c, n, r1);
+      for (int d = 0; d < 3; ++d) {
+        std::vector<double> v(n[d], 1.0);
+        if (d == f / 2) {
+          std::fill(v.begin(), v.end(), 0.0);
+          v[f % 2 == 0 ? 0 : n[d] - 1] = 1.0;
         }
+        for (int g2 = f + 1; g2 < 6; ++g2)
+          if (g2 / 2 == d && is_dirichlet(bc_kind[g2])) v[g2 % 2 == 0 ? 0 : n[d] - 1] = 0.0;
+        if (d == 0)
+          for (double& x : v) x *= bc_value[f];
+        TTIGA_HIP(hipMemcpyAsync(term.c[d].d(), v.data(), sizeof(double) * n[d], hipMemcpyHostToDevice,
+                                 c.stream));
+        c.sync();
       }
-      TTIGA_HIP(hipMemcpyAsync(ug.c[d].d(), v.data(), sizeof(double) * n[d], hipMemcpyHostToDevice,
-                               c.stream));
-      c.sync();
+      TT acc;
+      tt_axpby(c, 1.0, ug, 1.0, term, acc);
+      ug = std::move(acc);
     }
     TT Kug, KugI;
     tt_matvec_banded(c, K, p, ug, Kug);
@@ -618,6 +691,7 @@ void Problem::reduce_boundary() {
     tt_round(c, sum, assembly_eps() * 1e-2, -1.0, opts.max_rank);
     rhs = std::move(sum);
   } else {
+    ug.set_zero(n);
     rhs = std::move(FI);
   }
 }
@@ -689,14 +763,19 @@ using Matvec = std::function<void(const TT&, TT&)>;
 // as they are formed (tt_matvec_round) instead of being stored and rounded afterwards.
 static constexpr size_t kFusedProductBytes = size_t(1) << 30;
 
-// ||b - K x|| / ||b||, with the residual train b - K x rounded at eps_x (replaces r).  The
-// norm is that of the unrounded train: Householder orthogonalisation of the concatenated
-// cores of [b, -K x] loses no digits to the cancellation, and the first SVD of the
-// right-to-left sweep reads the norm before anything is truncated (a randomised sketch
-// could only underestimate it).  With Kf given and a product too large to store, the
-// residual train is formed already rounded and the norm is that of the rounded train.
+// ||b - K x|| / ||b||, with the residual train b - K x rounded at eps_x (replaces r).
+// exact_norm: the norm is that of the unrounded train: Householder orthogonalisation of the
+// concatenated cores of [b, -K x] loses no digits to the cancellation, and the first SVD of
+// the right-to-left sweep reads the norm before anything is truncated (a randomised sketch
+// could only underestimate it); the plain CG stops on this norm, and the preconditioned
+// solves report it at their end.  Otherwise (the residual replacements inside PCG, whose
+// stopping test is the preconditioned estimate) a train of rank above 160 is rounded by the
+// randomised sketch at loose tolerances, and the norm returned is that of the rounded train.  With Kf
+// given and a product too large to store, the residual train is formed already rounded and
+// the norm is that of the rounded train.
 static double true_residual(Context& c, const Matvec& mv, const TT& b, const TT& x, double nb,
-                            double eps_x, int max_rank, TT& r, int& hint, const TT* Kf = nullptr, int p = 0) {
+                            double eps_x, int max_rank, TT& r, int& hint, const TT* Kf = nullptr, int p = 0,
+                            bool exact_norm = true) {
   if (Kf && matvec_product_bytes(*Kf, x) > kFusedProductBytes) {
     tt_matvec_round(c, *Kf, p, x, -1.0, &b, 1.0, eps_x, max_rank, hint, r);
     return std::sqrt(std::max(tt_dot_sync(c, r, r), 0.0)) / nb;
@@ -704,10 +783,16 @@ static double true_residual(Context& c, const Matvec& mv, const TT& b, const TT&
   TT Kx, tr;
   mv(x, Kx);
   tt_axpby(c, 1.0, b, -1.0, Kx, tr);
-  double nrm = 0.0;
-  tt_round(c, tr, eps_x, -1.0, max_rank, &nrm);
+  // trains of modest rank take the deterministic rounding anyway: it is the cheaper one there
+  if (exact_norm || eps_x < 1e-9 || std::max(tr.r[1], tr.r[2]) <= 160) {
+    double nrm = 0.0;
+    tt_round(c, tr, eps_x, -1.0, max_rank, &nrm);
+    r = std::move(tr);
+    return nrm / nb;
+  }
+  tt_round_auto(c, tr, eps_x, max_rank, hint);
   r = std::move(tr);
-  return nrm / nb;
+  return std::sqrt(std::max(tt_dot_sync(c, r, r), 0.0)) / nb;
 }
 
 // Truncated TT-CG: conjugate gradients with TT-rounding of every update, the
@@ -790,7 +875,7 @@ void Problem::solve_cg(ttiga_solve_stats& s) {
 // is amplified by kappa(K) and would stall near kappa * eps.  The test is
 // confirmed on the true residual b - K x every 10 iterations and before stopping.
 PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int max_iter,
-                        const LowpTT* Klp, int& max_seen) {
+                        const LowpTT* Klp, int& max_seen, bool report_exact) {
   Context& c = *ctx;
   const Matvec mv = [&](const TT& v, TT& out) {
     if (Klp)
@@ -845,7 +930,7 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
     r = std::move(rn);
     bool replaced = false;
     if (o.it % 10 == 0) {
-      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr, Kf, p);
+      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr, Kf, p, false);
       replaced = true;
     }
     pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
@@ -860,7 +945,7 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
     };
     dots();
     if (o.pres <= tol && !replaced) {
-      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr, Kf, p);
+      o.true_res = true_residual(c, mv, b, x, nb, eps_x, opts.max_rank, r, hr, Kf, p, false);
       pc.apply(c, r, z, eps_p(), opts.max_rank, hz);
       dots();
     }
@@ -884,9 +969,10 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
     tt_round_auto(c, pn, eps, opts.max_rank, hp);
     pdir = std::move(pn);
   }
-  if (!o.conv) {
+  // the reported true residual (exact norm of the unrounded b - K x when asked for)
+  if (report_exact || !o.conv) {
     TT tmp;
-    o.true_res = true_residual(c, mv, b, x, nb, eps_x, 0, tmp, hr, Kf, p);
+    o.true_res = true_residual(c, mv, b, x, nb, eps_x, 0, tmp, hr, Kf, p, report_exact);
   }
   return o;
 }
@@ -895,7 +981,7 @@ PcgRun Problem::pcg_run(const TT& b, TT& x, double tol, double eps_floor, int ma
 void Problem::solve_pcg(ttiga_solve_stats& s) {
   const double tol = opts.rel_res_tol;
   int max_seen = 0;
-  const PcgRun o = pcg_run(rhs, u, tol, std::min(opts.tt_eps, 0.3 * tol), opts.max_iter, nullptr, max_seen);
+  const PcgRun o = pcg_run(rhs, u, tol, std::min(opts.tt_eps, 0.3 * tol), opts.max_iter, nullptr, max_seen, true);
   s.iterations = o.it;
   s.rel_res = o.true_res;
   s.rel_pres = o.pres;
@@ -908,7 +994,12 @@ void Problem::solve_pcg(ttiga_solve_stats& s) {
 // Mixed precision by iterative refinement: the operator is stored in FP32 or BF16 (the
 // cores of K_II rounded once), and each correction d solves K d = r with the same
 // flexible PCG whose products K v take the low-precision cores with FP32 arithmetic,
-// to a loose relative tolerance t.  The update u + d, the residual r = rhs - K u (FP64
+// to a loose relative tolerance t; its dense contractions with the operator (the products
+// rounded as they are formed) and the preconditioner's transforms run on the FP32 MFMA product
+// (operator products in BF16 mode: BF16) with FP32 accumulation.  The roundings' sketches and
+// Gram matrices stay FP64: the trains they round are differences such as b - K d whose parts
+// are far larger than the result, so FP32 contractions of them lose the result's digits (the
+// mixed C2 batch lost accuracy to 5e-5 and speed 7x when they ran in FP32).  The update u + d, the residual r = rhs - K u (FP64
 // product), its rounding, the preconditioned error estimate and every QR/SVD stay in
 // FP64.  A correction of relative accuracy t reduces the error by about
 // max(t, kappa u_low); with FP32 (u = 6e-8) that is a few steps for any mesh here,
@@ -937,14 +1028,24 @@ void Problem::solve_mixed(ttiga_solve_stats& s) {
     const double tol_in = std::max(floor_in, 0.3 * tol / est);
     TT d;
     d.set_zero(u.n);
-    const PcgRun o = pcg_run(r, d, tol_in, std::min(0.1, 0.3 * tol_in), opts.max_iter - inner, &Klp, max_seen);
+    PcgRun o;
+    {
+      // the correction's operator products rounded as they are formed and its preconditioner
+      // transforms on the low-precision MFMA product
+      struct LowpScope {
+        Context& c;
+        LowpScope(Context& cc, int dt) : c(cc) { c.lowp = dt; }
+        ~LowpScope() { c.lowp = 0; }
+      } scope(c, opts.precision);
+      o = pcg_run(r, d, tol_in, std::min(0.1, 0.3 * tol_in), opts.max_iter - inner, &Klp, max_seen, false);
+    }
     inner += o.it;
     if (d.zero()) break;
     TT un;
     tt_axpby(c, 1.0, u, 1.0, d, un);
     tt_round_auto(c, un, eps_x, opts.max_rank, hx);
     u = std::move(un);
-    true_res = true_residual(c, mv, rhs, u, nb, eps_r, opts.max_rank, r, hr, &KII, p);
+    true_res = true_residual(c, mv, rhs, u, nb, eps_r, opts.max_rank, r, hr, &KII, p, false);
     TT z;
     pc.apply(c, r, z, 1e-2, opts.max_rank, hz);
     double dd[2];
@@ -957,6 +1058,11 @@ void Problem::solve_mixed(ttiga_solve_stats& s) {
     }
     if (est > 0.5 * prev) break;  // the low-precision corrections no longer contract
     prev = est;
+  }
+  {
+    // the reported true residual: exact norm of the unrounded rhs - K u
+    TT tmp;
+    true_res = true_residual(c, mv, rhs, u, nb, eps_x, 0, tmp, hr, &KII, p, true);
   }
   s.iterations = inner;
   s.refine_steps = steps;

@@ -21,6 +21,9 @@ struct PcgRun {
 
 constexpr int kMaxRefineSteps = 12;
 
+// faces with Dirichlet data (their end indices are cut from the cores)
+inline bool is_dirichlet(int kind) { return kind == TTIGA_BC_ZERO || kind == TTIGA_BC_CONSTANT; }
+
 struct Problem {
   Context* ctx;
   // description
@@ -32,7 +35,7 @@ struct Problem {
   double src_origin[3], src_scale;
   int bc_kind[6];
   double bc_value[6];
-  int lift_dir = -1;
+  bool lift = false;  // non-zero constant Dirichlet data on some face
   int lo[3], hi[3];  // interior index range per direction
   ttiga_options opts;
   // device inputs
@@ -42,6 +45,7 @@ struct Problem {
   DBuf gtab_span[3], gtab_B[3], gtab_D[3];
   // TT state
   TT R[6], fJ, K, F, KII, rhs, u;
+  TT ug;  // full-grid coefficients of the Dirichlet data (zero inside), when lift
   LowpTT Klp;  // K_II in FP32 or BF16 for the mixed-precision solve
   Precond pc;
   double min_detJ = 0.0;
@@ -55,6 +59,11 @@ struct Problem {
   const TT* which(int w) const;
   void sample_points(const double* pts, size_t count, double* out, double* det_out);
   void upload();  // device copies of the small inputs
+  // relative L2 error of the solution against an exact solution on a Gauss grid of p + extra
+  // points per span, evaluated in TT format: out = {relative, ||u_h - u||, ||u||}
+  void l2_error(int exact_kind, const double* prm, int extra, double out[3]);
+  // {K vs sparse, K vs dense, F, u} compression ratios (entries of the full-grid object over TT entries)
+  void compression_ratios(double out[4]);
   size_t footprint_estimate() const;
 
  private:
@@ -65,8 +74,9 @@ struct Problem {
   void solve_pcg(ttiga_solve_stats& s);
   void solve_mixed(ttiga_solve_stats& s);
   PcgRun pcg_run(const TT& b, TT& x, double tol, double eps_floor, int max_iter, const LowpTT* Klp,
-                 int& max_seen);
+                 int& max_seen, bool report_exact);
   void build_tables();
+  void add_traction(int face, double eps);
   void reduce_boundary();
   SourceDev source_dev() const;
   GeoDev geo_dev(const DBuf* span, const DBuf* B, const DBuf* D) const;

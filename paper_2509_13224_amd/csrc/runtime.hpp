@@ -177,6 +177,9 @@ struct Context {
   double* host_scratch = nullptr;
   double* host_dev = nullptr;
   size_t host_scratch_doubles = 0;
+  // TTIGA_FP32 / TTIGA_BF16 while the inner corrections of a mixed-precision solve run: the
+  // contractions routed through gemm_c then use the low-precision MFMA product (0: FP64)
+  int lowp = 0;
   // sketch seeds; reset at the start of every assembly and solve, so a problem's
   // results do not depend on what ran before it on the context
   uint64_t rng_counter = 0x5eed;
@@ -241,7 +244,7 @@ struct GemmPlan {
   int splits = 1;        // K splits (partials summed in split order by a second kernel)
   int kchunk = 0;        // contraction length per split
 };
-GemmPlan gemm_plan(int M, int N, int K, int batch);
+GemmPlan gemm_plan(bool ta, bool tb, int M, int N, int K, int batch);
 // doubles of partial-tile workspace a plan needs (0 without K splits)
 size_t gemm_part_doubles(const GemmPlan& g, int M, int N, int batch);
 // the product with a given plan and caller-provided partial-tile workspace (K > 0)
@@ -251,6 +254,17 @@ void gemm_planned(Context& ctx, const GemmPlan& g, bool ta, bool tb, int M, int 
 void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
           long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc,
           long sC, int batch = 1);
+// the contraction of a TT operation that may run in low precision: gemm, or while ctx.lowp is
+// set gemm_lowp in ctx.lowp (operator = true: a product with the operator's cores) or FP32
+// (the preconditioner's transforms, which need about two digits)
+void gemm_c(Context& ctx, bool operator_, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+            long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC,
+            int batch = 1);
+// the same product with the operands rounded to dtype (TTIGA_FP32 / TTIGA_BF16) as they are
+// staged, MFMA in that type with FP32 accumulation, FP64 in and out
+void gemm_lowp(Context& ctx, int dtype, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+               long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC,
+               int batch = 1);
 // Blocks of 256 threads for a grid-stride elementwise kernel over `total` elements: at most
 // 2048 (eight per compute unit), enough to stream HBM on an idle device without holding every
 // wave slot while the kernels of other streams wait for room.
@@ -308,6 +322,8 @@ void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev);
 // <x, y> from raw device cores (ranks rx, ry with rx[0] = ry[0] = rx[3] = ry[3] = 1) into
 // out_dev, all temporaries in `scratch` of tt_dot_scratch_doubles(n, rx, ry) doubles
 size_t tt_dot_scratch_doubles(const int* n, const int* rx, const int* ry);
+// sum_q W_q E_q^2 over the grid of two TTs with the same mode sizes (errors.hip)
+double tt_weighted_sqnorm(Context& ctx, const TT& E, const TT& W);
 // the allocation-free variant (noalloc.hip): the same chain with its temporaries in a fixed
 // per-device array; noalloc_scratch looks the array's address up (once per device, with
 // that device current)

@@ -160,7 +160,7 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
   hipLaunchKernelGGL(k_band_last_sketch, dim3(grid_for((long)rK2 * n2 * l2)), dim3(256), 0, ctx.stream, n2, p, rK2,
                      l2, K2, O3.d(), P.d());
   TTIGA_HIP(hipGetLastError());
-  gemm(ctx, false, false, rx2, l2, n2, 1.0, x2, n2, 0, P.d(), l2, (long)n2 * l2, 0.0, W3.d(), l2,
+  gemm_c(ctx, false, false, false, rx2, l2, n2, 1.0, x2, n2, 0, P.d(), l2, (long)n2 * l2, 0.0, W3.d(), l2,
        (long)rx2 * l2, rK2);
   DBuf W2(ctx.alloc, sizeof(double) * (size_t)rK1 * rx1 * l1);
   {
@@ -175,34 +175,34 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
       const int i1 = std::min(n1, i0 + ib), ic = i1 - i0;
       const int j0 = std::max(0, i0 - p), jc = std::min(n1, i1 + p) - j0;
       if (jc == n1)
-        gemm(ctx, false, false, rx1 * n1, rK2 * l2, rx2, 1.0, x1, rx2, 0, W3p.d(), (long)rK2 * l2, 0, 0.0, U.d(),
+        gemm_c(ctx, false, false, false, rx1 * n1, rK2 * l2, rx2, 1.0, x1, rx2, 0, W3p.d(), (long)rK2 * l2, 0, 0.0, U.d(),
              (long)rK2 * l2, 0);
       else  // one product per row b of x_1, over its rows j0..j0+jc
-        gemm(ctx, false, false, jc, rK2 * l2, rx2, 1.0, x1 + (long)j0 * rx2, rx2, (long)n1 * rx2, W3p.d(),
+        gemm_c(ctx, false, false, false, jc, rK2 * l2, rx2, 1.0, x1 + (long)j0 * rx2, rx2, (long)n1 * rx2, W3p.d(),
              (long)rK2 * l2, 0, 0.0, U.d(), (long)rK2 * l2, (long)jc * rK2 * l2, rx1);
       permute4(ctx, U.d(), rx1, jc, rK2, l2, 1, 2, 0, 3, Up.d());  // [j][a'][b][l2]
       fill(ctx, Tt.d(), (size_t)ic * rK1 * rx1 * l2, 0.0);
       for (int t = 0; t < band; ++t) {
         const int ilo = std::max(i0, p - t), ihi = std::min(i1, n1 + p - t);
         if (ihi <= ilo) continue;
-        gemm(ctx, false, false, rK1, rx1 * l2, rK2, 1.0, K1 + ((long)ilo * band + t) * rK2, (long)n1 * band * rK2,
+        gemm_c(ctx, true, false, false, rK1, rx1 * l2, rK2, 1.0, K1 + ((long)ilo * band + t) * rK2, (long)n1 * band * rK2,
              (long)band * rK2, Up.d() + (long)(ilo + t - p - j0) * rK2 * rx1 * l2, (long)rx1 * l2,
              (long)rK2 * rx1 * l2, 1.0, Tt.d() + (long)(ilo - i0) * rK1 * rx1 * l2, (long)rx1 * l2,
              (long)rK1 * rx1 * l2, ihi - ilo);
       }
       permute4(ctx, Tt.d(), ic, rK1, rx1, l2, 1, 2, 0, 3, T.d());  // [a][b][i][l2]
-      gemm(ctx, false, true, rK1 * rx1, l1, ic * l2, 1.0, T.d(), (long)ic * l2, 0, O2.d() + (long)i0 * l2,
+      gemm_c(ctx, false, false, true, rK1 * rx1, l1, ic * l2, 1.0, T.d(), (long)ic * l2, 0, O2.d() + (long)i0 * l2,
            (long)n1 * l2, 0, i0 == 0 ? 0.0 : 1.0, W2.d(), l1, 0);
     }
   }
   DBuf W3z, W2z;
   if (hz) {
     W3z = DBuf(ctx.alloc, sizeof(double) * (size_t)rz2 * l2);
-    gemm(ctx, false, true, rz2, l2, n2, 1.0, z->c[2].d(), n2, 0, O3.d(), n2, 0, 0.0, W3z.d(), l2, 0);
+    gemm_c(ctx, false, false, true, rz2, l2, n2, 1.0, z->c[2].d(), n2, 0, O3.d(), n2, 0, 0.0, W3z.d(), l2, 0);
     DBuf Tz(ctx.alloc, sizeof(double) * (size_t)rz1 * n1 * l2);
-    gemm(ctx, false, false, rz1 * n1, l2, rz2, 1.0, z->c[1].d(), rz2, 0, W3z.d(), l2, 0, 0.0, Tz.d(), l2, 0);
+    gemm_c(ctx, false, false, false, rz1 * n1, l2, rz2, 1.0, z->c[1].d(), rz2, 0, W3z.d(), l2, 0, 0.0, Tz.d(), l2, 0);
     W2z = DBuf(ctx.alloc, sizeof(double) * (size_t)rz1 * l1);
-    gemm(ctx, false, true, rz1, l1, n1 * l2, 1.0, Tz.d(), (long)n1 * l2, 0, O2.d(), (long)n1 * l2, 0, 0.0,
+    gemm_c(ctx, false, false, true, rz1, l1, n1 * l2, 1.0, Tz.d(), (long)n1 * l2, 0, O2.d(), (long)n1 * l2, 0, 0.0,
          W2z.d(), l1, 0);
   }
   // first core: Y1 = y_0 W2 (n0 x l1), Q1 its orthonormal basis, M1 = Q1^T y_0
@@ -211,23 +211,23 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
   {
     DBuf W2p(ctx.alloc, sizeof(double) * (size_t)rK1 * rx1 * l1), V(ctx.alloc, sizeof(double) * (size_t)n0 * rK1 * l1);
     permute4(ctx, W2.d(), 1, rK1, rx1, l1, 0, 2, 1, 3, W2p.d());  // [b][a][l1]
-    gemm(ctx, false, false, n0, rK1 * l1, rx1, 1.0, x0, rx1, 0, W2p.d(), (long)rK1 * l1, 0, 0.0, V.d(),
+    gemm_c(ctx, false, false, false, n0, rK1 * l1, rx1, 1.0, x0, rx1, 0, W2p.d(), (long)rK1 * l1, 0, 0.0, V.d(),
          (long)rK1 * l1, 0);
     DBuf Y1(ctx.alloc, sizeof(double) * (size_t)n0 * l1), Rq(ctx.alloc, sizeof(double) * (size_t)l1 * l1);
     hipLaunchKernelGGL(k_band_first_apply, dim3(grid_for((long)n0 * l1)), dim3(256), 0, ctx.stream, n0, p, rK1, l1,
                        alpha, K0, V.d(), Y1.d());
     TTIGA_HIP(hipGetLastError());
     if (hz)
-      gemm(ctx, false, false, n0, l1, rz1, beta, z->c[0].d(), rz1, 0, W2z.d(), l1, 0, 1.0, Y1.d(), l1, 0);
+      gemm_c(ctx, false, false, false, n0, l1, rz1, beta, z->c[0].d(), rz1, 0, W2z.d(), l1, 0, 1.0, Y1.d(), l1, 0);
     qr_tall(ctx, Y1.d(), false, n0, l1, l1, Q1.d(), Rq.d());
     DBuf S(ctx.alloc, sizeof(double) * (size_t)l1 * rK1 * n0);
     hipLaunchKernelGGL(k_band_first_adjoint, dim3(grid_for((long)l1 * rK1 * n0)), dim3(256), 0, ctx.stream, n0, p,
                        rK1, l1, Q1.d(), K0, S.d());
     TTIGA_HIP(hipGetLastError());
-    gemm(ctx, false, false, l1 * rK1, rx1, n0, alpha, S.d(), n0, 0, x0, rx1, 0, 0.0, M1.d(), rx1, 0);
+    gemm_c(ctx, false, false, false, l1 * rK1, rx1, n0, alpha, S.d(), n0, 0, x0, rx1, 0, 0.0, M1.d(), rx1, 0);
     if (hz) {
       M1z = DBuf(ctx.alloc, sizeof(double) * (size_t)l1 * rz1);
-      gemm(ctx, true, false, l1, rz1, n0, beta, Q1.d(), l1, 0, z->c[0].d(), rz1, 0, 0.0, M1z.d(), rz1, 0);
+      gemm_c(ctx, false, true, false, l1, rz1, n0, beta, Q1.d(), l1, 0, z->c[0].d(), rz1, 0, 0.0, M1z.d(), rz1, 0);
     }
   }
   // middle core: Z2 = M1 y_1 (rows (i, l1), columns (a', b')), Y2 = Z2 W3, Q2 its basis,
@@ -239,14 +239,14 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
   DBuf Zt(ctx.alloc, sizeof(double) * zsz), Zc(ctx.alloc, sizeof(double) * zsz);
   auto z2_block = [&](int i0, int i1) {  // Zc = rows i0..i1 of Z2, [i][l1][a'][b']
     const int ic = i1 - i0, j0 = std::max(0, i0 - p), jc = std::min(n1, i1 + p) - j0;
-    gemm(ctx, false, false, l1 * rK1, jc * rx2, rx1, 1.0, M1.d(), rx1, 0, x1 + (long)j0 * rx2, (long)n1 * rx2, 0,
+    gemm_c(ctx, false, false, false, l1 * rK1, jc * rx2, rx1, 1.0, M1.d(), rx1, 0, x1 + (long)j0 * rx2, (long)n1 * rx2, 0,
          0.0, E.d(), (long)jc * rx2, 0);
     permute4(ctx, E.d(), l1, rK1, jc, rx2, 2, 1, 0, 3, Ep.d());  // [j][a][l1][b']
     fill(ctx, Zt.d(), (size_t)ic * rK2 * l1 * rx2, 0.0);
     for (int t = 0; t < band; ++t) {
       const int ilo = std::max(i0, p - t), ihi = std::min(i1, n1 + p - t);
       if (ihi <= ilo) continue;
-      gemm(ctx, true, false, rK2, l1 * rx2, rK1, 1.0, K1 + ((long)ilo * band + t) * rK2, (long)n1 * band * rK2,
+      gemm_c(ctx, true, true, false, rK2, l1 * rx2, rK1, 1.0, K1 + ((long)ilo * band + t) * rK2, (long)n1 * band * rK2,
            (long)band * rK2, Ep.d() + (long)(ilo + t - p - j0) * rK1 * l1 * rx2, (long)l1 * rx2,
            (long)rK1 * l1 * rx2, 1.0, Zt.d() + (long)(ilo - i0) * rK2 * l1 * rx2, (long)l1 * rx2,
            (long)rK2 * l1 * rx2, ihi - ilo);
@@ -256,7 +256,7 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
   DBuf Z2z;
   if (hz) {  // [i][l1][c'] = M1z z_1
     Z2z = DBuf(ctx.alloc, sizeof(double) * (size_t)n1 * l1 * rz2);
-    gemm(ctx, false, false, l1, rz2, rz1, 1.0, M1z.d(), rz1, 0, z->c[1].d(), (long)n1 * rz2, rz2, 0.0, Z2z.d(),
+    gemm_c(ctx, false, false, false, l1, rz2, rz1, 1.0, M1z.d(), rz1, 0, z->c[1].d(), (long)n1 * rz2, rz2, 0.0, Z2z.d(),
          rz2, (long)l1 * rz2, n1);
   }
   DBuf Q2(ctx.alloc, sizeof(double) * (size_t)l1 * n1 * l2);
@@ -266,22 +266,22 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
     for (int i0 = 0; i0 < n1; i0 += zb) {
       const int i1 = std::min(n1, i0 + zb);
       z2_block(i0, i1);
-      gemm(ctx, false, false, (i1 - i0) * l1, l2, rK2 * rx2, 1.0, Zc.d(), (long)rK2 * rx2, 0, W3.d(), l2, 0, 0.0,
+      gemm_c(ctx, false, false, false, (i1 - i0) * l1, l2, rK2 * rx2, 1.0, Zc.d(), (long)rK2 * rx2, 0, W3.d(), l2, 0, 0.0,
            Y2.d() + (long)i0 * l1 * l2, l2, 0);
     }
     if (hz)
-      gemm(ctx, false, false, n1 * l1, l2, rz2, 1.0, Z2z.d(), rz2, 0, W3z.d(), l2, 0, 1.0, Y2.d(), l2, 0);
+      gemm_c(ctx, false, false, false, n1 * l1, l2, rz2, 1.0, Z2z.d(), rz2, 0, W3z.d(), l2, 0, 1.0, Y2.d(), l2, 0);
     DBuf Qi(ctx.alloc, sizeof(double) * (size_t)n1 * l1 * l2);
     qr_tall(ctx, Y2.d(), false, n1 * l1, l2, l2, Qi.d(), Rq.d());
     for (int i0 = 0; i0 < n1; i0 += zb) {
       const int i1 = std::min(n1, i0 + zb);
       if (zb < n1) z2_block(i0, i1);
-      gemm(ctx, true, false, l2, rK2 * rx2, (i1 - i0) * l1, 1.0, Qi.d() + (long)i0 * l1 * l2, l2, 0, Zc.d(),
+      gemm_c(ctx, false, true, false, l2, rK2 * rx2, (i1 - i0) * l1, 1.0, Qi.d() + (long)i0 * l1 * l2, l2, 0, Zc.d(),
            (long)rK2 * rx2, 0, i0 == 0 ? 0.0 : 1.0, M2.d(), (long)rK2 * rx2, 0);
     }
     if (hz) {
       M2z = DBuf(ctx.alloc, sizeof(double) * (size_t)l2 * rz2);
-      gemm(ctx, true, false, l2, rz2, n1 * l1, 1.0, Qi.d(), l2, 0, Z2z.d(), rz2, 0, 0.0, M2z.d(), rz2, 0);
+      gemm_c(ctx, false, true, false, l2, rz2, n1 * l1, 1.0, Qi.d(), l2, 0, Z2z.d(), rz2, 0, 0.0, M2z.d(), rz2, 0);
     }
     permute4(ctx, Qi.d(), 1, n1, l1, l2, 0, 2, 1, 3, Q2.d());  // [l1][i][l2]
   }
@@ -293,11 +293,11 @@ void sketch_project_matvec(Context& ctx, const TT& K, int p, const TT& x, double
   DBuf C3(ctx.alloc, sizeof(double) * (size_t)l2 * n2);
   {
     DBuf F(ctx.alloc, sizeof(double) * (size_t)l2 * rK2 * n2);
-    gemm(ctx, false, false, l2 * rK2, n2, rx2, 1.0, M2.d(), rx2, 0, x2, n2, 0, 0.0, F.d(), n2, 0);
+    gemm_c(ctx, false, false, false, l2 * rK2, n2, rx2, 1.0, M2.d(), rx2, 0, x2, n2, 0, 0.0, F.d(), n2, 0);
     hipLaunchKernelGGL(k_band_last_apply, dim3(grid_for((long)l2 * n2)), dim3(256), 0, ctx.stream, n2, p, rK2, l2,
                        K2, F.d(), C3.d());
     TTIGA_HIP(hipGetLastError());
-    if (hz) gemm(ctx, false, false, l2, n2, rz2, 1.0, M2z.d(), rz2, 0, z->c[2].d(), n2, 0, 1.0, C3.d(), n2, 0);
+    if (hz) gemm_c(ctx, false, false, false, l2, n2, rz2, 1.0, M2z.d(), rz2, 0, z->c[2].d(), n2, 0, 1.0, C3.d(), n2, 0);
   }
   y.n[0] = n0;
   y.n[1] = n1;

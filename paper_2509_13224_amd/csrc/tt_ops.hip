@@ -24,31 +24,6 @@ void TT::alloc(Context& ctx, const int* nn, const int* rr) {
 }
 
 // --------------------------------------------------------------- kernels
-// y[(b a)][i][(b' a')] = sum_t M[b][i][t][b'] x[a][i+t-p][a'] over in-range columns.
-__global__ void k_matvec_banded(int n, int p, int rK0, int rK1, int rx0, int rx1,
-                                const double* __restrict__ M, const double* __restrict__ X,
-                                double* __restrict__ Y) {
-  const long R1 = (long)rK1 * rx1;
-  const long total = (long)rK0 * rx0 * n * R1;
-  const int band = 2 * p + 1;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    const int a2 = e % rx1;
-    const int b2 = (e / rx1) % rK1;
-    const int i = (e / R1) % n;
-    const long ba = e / (R1 * n);
-    const int a = ba % rx0, b = ba / rx0;
-    const double* Mrow = M + (((long)b * n + i) * band) * rK1 + b2;
-    double s = 0.0;
-    for (int t = 0; t < band; ++t) {
-      const int j = i + t - p;
-      if (j < 0 || j >= n) continue;
-      s += Mrow[(long)t * rK1] * X[((long)a * n + j) * rx1 + a2];
-    }
-    Y[e] = s;
-  }
-}
-
 // Low-precision operands.  BF16 is kept as its 16 raw bits: FP32 rounded to nearest
 // even on the upper half (so FP64 -> BF16 rounds through FP32), NaN kept quiet.
 __device__ inline uint16_t f32_to_bf16(float f) {
@@ -59,6 +34,7 @@ __device__ inline uint16_t f32_to_bf16(float f) {
 }
 __device__ inline float lp_to_f32(float v) { return v; }
 __device__ inline float lp_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline double lp_to_f32(double v) { return v; }
 __device__ inline void lp_store(float* p, double v) { *p = (float)v; }
 __device__ inline void lp_store(uint16_t* p, double v) { *p = f32_to_bf16((float)v); }
 
@@ -68,32 +44,107 @@ __global__ void k_to_lowp(const double* __restrict__ src, long n, T* __restrict_
     lp_store(dst + e, src[e]);
 }
 
-// The banded product of k_matvec_banded with the operator core in FP32 or BF16 and the
-// vector core in FP32, products and sums over the band in FP32; the output core is
-// written in FP64 for the FP64 rounding that follows.
-template <class TK>
-__global__ void k_matvec_banded_lp(int n, int p, int rK0, int rK1, int rx0, int rx1,
-                                   const TK* __restrict__ M, const float* __restrict__ X,
-                                   double* __restrict__ Y) {
-  const long R1 = (long)rK1 * rx1;
-  const long total = (long)rK0 * rx0 * n * R1;
+// One core of the banded TT-matrix x TT-vector product (Section 4.1.1: the cores of K x are
+// the mode-wise products of the matrix and vector cores, ranks multiplying):
+//   y[(b a)][i][(b' a')] = sum_t M[b][i][t][b'] x[a][i+t-p][a'],   j = i + t - p in range.
+// A workgroup takes one (b, a) pair (blockIdx.y) and a tile of TI rows i (blockIdx.x): the
+// band entries M[b][i0..i0+TI)[.][.] and the rows x[a][i0-p .. i0+TI+p)[.] (zero outside
+// 0..n-1, which drops the out-of-range band entries) are copied to LDS with coalesced loads,
+// then each thread owns pairs (i, a'), keeps the 2p+1 values x[a][i+t-p][a'] in registers and
+// sweeps b', so the output slab y[(b a)][i0..i0+TI)[.][.] (contiguous) is written once, in
+// order, with non-temporal stores (the product is read back only by the next kernel, long
+// after it has left the caches; keeping it out of them measured 1.3-2x faster).  The work is bound by writing y (rK rx times the size of x), so the band entries and
+// x are read from HBM about once per (b, a).  TK / TX / TS: operator, vector and arithmetic
+// types (FP64 throughout, or FP32/BF16 operator with FP32 vector and FP32 arithmetic);
+// y is FP64.
+template <int P, class TK, class TX, class TS>
+__global__ __launch_bounds__(256) void k_band_matvec(int n, int p_rt, int ti, int rK0, int rK1, int rx0, int rx1,
+                                                     const TK* __restrict__ M, const TX* __restrict__ X,
+                                                     double* __restrict__ Y) {
+  extern __shared__ unsigned char lds_raw[];
+  // P > 0: the half-width is a compile-time constant and the 2P+1 values of x sit in
+  // registers; P = 0: any half-width, x read from LDS in the inner loop
+  const int p = P > 0 ? P : p_rt;
   const int band = 2 * p + 1;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    const int a2 = e % rx1;
-    const int b2 = (e / rx1) % rK1;
-    const int i = (e / R1) % n;
-    const long ba = e / (R1 * n);
-    const int a = ba % rx0, b = ba / rx0;
-    const TK* Mrow = M + (((long)b * n + i) * band) * rK1 + b2;
-    float s = 0.0f;
-    for (int t = 0; t < band; ++t) {
-      const int j = i + t - p;
-      if (j < 0 || j >= n) continue;
-      s += lp_to_f32(Mrow[(long)t * rK1]) * X[((long)a * n + j) * rx1 + a2];
-    }
-    Y[e] = (double)s;
+  const int ba = blockIdx.y, b = ba / rx0, a = ba - b * rx0;
+  const int i0 = blockIdx.x * ti;
+  const int rows = min(ti, n - i0);
+  // LDS: band entries Ms[il][t][b'] (rows * band * rK1), then x rows Xs[jl][a'] for
+  // j = i0 - p + jl, jl < rows + 2p
+  TS* Ms = reinterpret_cast<TS*>(lds_raw);
+  TS* Xs = Ms + (size_t)ti * band * rK1;
+  const int nm = rows * band * rK1;
+  const TK* Mg = M + ((size_t)b * n + i0) * band * rK1;
+  for (int e = threadIdx.x; e < nm; e += blockDim.x) Ms[e] = (TS)lp_to_f32(Mg[e]);
+  const int nxr = rows + 2 * p;
+  const TX* Xg = X + (size_t)a * n * rx1;
+  for (int e = threadIdx.x; e < nxr * rx1; e += blockDim.x) {
+    const int jl = e / rx1;
+    const int j = i0 - p + jl;
+    Xs[e] = (j >= 0 && j < n) ? (TS)Xg[(size_t)j * rx1 + (e - jl * rx1)] : (TS)0;
   }
+  __syncthreads();
+  const size_t R1 = (size_t)rK1 * rx1;
+  double* Yg = Y + ((size_t)ba * n + i0) * R1;
+  const int pairs = rows * rx1;
+  for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
+    const int il = q / rx1, a2 = q - il * rx1;
+    const TS* Mrow = Ms + (size_t)il * band * rK1;
+    double* yrow = Yg + (size_t)il * R1 + a2;
+    if constexpr (P > 0) {
+      TS xv[2 * P + 1];
+#pragma unroll
+      for (int t = 0; t < 2 * P + 1; ++t) xv[t] = Xs[(il + t) * rx1 + a2];
+      for (int b2 = 0; b2 < rK1; ++b2) {
+        TS s = (TS)0;
+#pragma unroll
+        for (int t = 0; t < 2 * P + 1; ++t) s += Mrow[t * rK1 + b2] * xv[t];
+        __builtin_nontemporal_store((double)s, yrow + (size_t)b2 * rx1);
+      }
+    } else {
+      const TS* xcol = Xs + (size_t)il * rx1 + a2;
+      for (int b2 = 0; b2 < rK1; ++b2) {
+        TS s = (TS)0;
+        for (int t = 0; t < band; ++t) s += Mrow[t * rK1 + b2] * xcol[(size_t)t * rx1];
+        __builtin_nontemporal_store((double)s, yrow + (size_t)b2 * rx1);
+      }
+    }
+  }
+}
+
+// Rows per workgroup: as many as fit in 24 KiB of LDS (band entries of the rows plus their
+// x halo), at most 256, at least 1: small tiles keep several workgroups per compute unit in
+// flight, which hides the load phase of one behind the stores of the others.
+static int band_rows(int n, int p, int rK1, int rx1, size_t elem) {
+  const size_t budget = (size_t(24) << 10) / elem;
+  const size_t per_row = (size_t)(2 * p + 1) * rK1 + rx1;
+  const size_t fixed = (size_t)2 * p * rx1;
+  long ti = budget > fixed ? (long)((budget - fixed) / per_row) : 1;
+  ti = std::max<long>(1, std::min<long>(ti, 256));
+  return (int)std::min<long>(ti, n);
+}
+
+template <class TK, class TX, class TS>
+static void launch_band_matvec(Context& ctx, int n, int p, int rK0, int rK1, int rx0, int rx1, const TK* M,
+                               const TX* X, double* Y) {
+  const int ti = band_rows(n, p, rK1, rx1, sizeof(TS));
+  TTIGA_CHECK((long)rK0 * rx0 <= 65535, TTIGA_E_ARG, "matvec: rK * rx above 65535 on a core's left rank");
+  const size_t lds = sizeof(TS) * ((size_t)ti * (2 * p + 1) * rK1 + (size_t)(ti + 2 * p) * rx1);
+  TTIGA_CHECK(lds <= (size_t(64) << 10), TTIGA_E_ARG, "matvec: ranks too large for one LDS row tile");
+  dim3 grid((n + ti - 1) / ti, rK0 * rx0);
+#define TTIGA_BAND_LAUNCH(PP)                                                                       \
+  hipLaunchKernelGGL((k_band_matvec<PP, TK, TX, TS>), grid, dim3(256), lds, ctx.stream, n, p, ti, rK0, rK1, \
+                     rx0, rx1, M, X, Y)
+  switch (p) {
+    case 1: TTIGA_BAND_LAUNCH(1); break;
+    case 2: TTIGA_BAND_LAUNCH(2); break;
+    case 3: TTIGA_BAND_LAUNCH(3); break;
+    case 4: TTIGA_BAND_LAUNCH(4); break;
+    case 5: TTIGA_BAND_LAUNCH(5); break;
+    default: TTIGA_BAND_LAUNCH(0); break;
+  }
+#undef TTIGA_BAND_LAUNCH
+  TTIGA_HIP(hipGetLastError());
 }
 
 // out core k of alpha x + beta y (block structure of the TT sum).
@@ -260,10 +311,9 @@ void tt_matvec_banded(Context& ctx, const TT& K, int p, const TT& x, TT& y) {
     ProfScope prof(ctx, "tt_matvec_banded",
                    2.0 * band_nnz * K.r[k] * K.r[k + 1] * x.r[k] * x.r[k + 1],
                    8.0 * ((double)K.core_elems(k) + (double)x.core_elems(k) + (double)total));
-    hipLaunchKernelGGL(k_matvec_banded, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n[k], p,
-                       K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].d(), x.c[k].d(), y.c[k].d());
+    launch_band_matvec<double, double, double>(ctx, n[k], p, K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].d(),
+                                               x.c[k].d(), y.c[k].d());
   }
-  TTIGA_HIP(hipGetLastError());
 }
 
 static size_t lowp_bytes(int dtype) { return dtype == TTIGA_BF16 ? 2 : 4; }
@@ -309,15 +359,12 @@ void tt_matvec_banded_lp(Context& ctx, const LowpTT& K, int p, const TT& x, TT& 
     hipLaunchKernelGGL(k_to_lowp<float>, dim3(grid_for(nx)), dim3(256), 0, ctx.stream, x.c[k].d(), nx,
                        x32.as<float>());
     if (K.dtype == TTIGA_FP32)
-      hipLaunchKernelGGL(k_matvec_banded_lp<float>, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n[k], p,
-                         K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].as<float>(), x32.as<float>(),
-                         y.c[k].d());
+      launch_band_matvec<float, float, float>(ctx, n[k], p, K.r[k], K.r[k + 1], x.r[k], x.r[k + 1],
+                                              K.c[k].as<float>(), x32.as<float>(), y.c[k].d());
     else
-      hipLaunchKernelGGL(k_matvec_banded_lp<uint16_t>, dim3(grid_for(total)), dim3(256), 0, ctx.stream, n[k],
-                         p, K.r[k], K.r[k + 1], x.r[k], x.r[k + 1], K.c[k].as<uint16_t>(), x32.as<float>(),
-                         y.c[k].d());
+      launch_band_matvec<uint16_t, float, float>(ctx, n[k], p, K.r[k], K.r[k + 1], x.r[k], x.r[k + 1],
+                                                 K.c[k].as<uint16_t>(), x32.as<float>(), y.c[k].d());
   }
-  TTIGA_HIP(hipGetLastError());
 }
 
 static void axpby_impl(Context& ctx, const double* ap, double a, const TT& x, const double* bp,
@@ -365,7 +412,7 @@ namespace {
 struct DotScratch {
   size_t l = 0, t = 0, part = 0;
   DotScratch(const int* n, const int* rx, const int* ry) {
-    auto part_of = [&](int M, int N, int K) { return gemm_part_doubles(gemm_plan(M, N, K, 1), M, N, 1); };
+    auto part_of = [&](int M, int N, int K) { return gemm_part_doubles(gemm_plan(true, false, M, N, K, 1), M, N, 1); };
     l = std::max((size_t)rx[1] * ry[1], (size_t)rx[2] * ry[2]);
     t = std::max((size_t)ry[1] * n[1] * rx[2], (size_t)ry[2] * n[2] * rx[3]);
     part = std::max({part_of(rx[1], ry[1], n[0]), part_of(ry[1], n[1] * rx[2], rx[1]),
@@ -386,7 +433,7 @@ void tt_dot_cores(Context& ctx, const int* n, const int* rx, const double* const
   double* part = T + sz.t;
   auto mm = [&](bool ta, int M, int N, int K, const double* A, long lda, const double* B, long ldb, double* C,
                 long ldc) {
-    gemm_planned(ctx, gemm_plan(M, N, K, 1), ta, false, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1,
+    gemm_planned(ctx, gemm_plan(ta, false, M, N, K, 1), ta, false, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1,
                  part);
   };
   mm(true, rx[1], ry[1], n[0], xc[0], rx[1], yc[0], ry[1], Lb[0], ry[1]);
@@ -926,7 +973,7 @@ void tt_mode_product(Context& ctx, TT& x, int d, const double* Mat, bool trans) 
   const int ra = x.r[d], n = x.n[d], rb = x.r[d + 1];
   DBuf out(ctx.alloc, sizeof(double) * x.core_elems(d));
   // out[a] (n x rb) = op(Mat) (n x n) * X[a] (n x rb), batched over a
-  gemm(ctx, trans, false, n, rb, n, 1.0, Mat, n, 0, x.c[d].d(), rb, (long)n * rb, 0.0, out.d(), rb,
+  gemm_c(ctx, false, trans, false, n, rb, n, 1.0, Mat, n, 0, x.c[d].d(), rb, (long)n * rb, 0.0, out.d(), rb,
        (long)n * rb, ra);
   x.c[d] = std::move(out);
 }

@@ -27,12 +27,14 @@ TTIGA_E_STATE = -9
 TTIGA_E_HIP = -10
 
 WHICH_K, WHICH_F, WHICH_KII, WHICH_RHS, WHICH_FACTOR0 = 0, 1, 2, 3, 10
+TTIGA_EXACT_MANUFACTURED_ANNULUS, TTIGA_EXACT_RADIAL_LOG, TTIGA_EXACT_SINE_XY = 1, 2, 3
 
 EXPORTED = (
     "ttiga_version", "ttiga_create", "ttiga_destroy", "ttiga_set_workspace", "ttiga_last_error",
     "ttiga_validate", "ttiga_problem_create", "ttiga_problem_destroy", "ttiga_assemble", "ttiga_solve",
-    "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
-    "ttiga_sample_factors", "ttiga_gemm_f64", "ttiga_tt_matvec", "ttiga_tt_matvec_round", "ttiga_tt_round", "ttiga_tt_dot",
+    "ttiga_solution_ranks", "ttiga_get_solution", "ttiga_l2_error", "ttiga_compression_ratios",
+    "ttiga_problem_tt_info", "ttiga_problem_tt_copy",
+    "ttiga_sample_factors", "ttiga_gemm_f64", "ttiga_gemm_lowp", "ttiga_tt_matvec", "ttiga_tt_matvec_round", "ttiga_tt_round", "ttiga_tt_dot",
     "ttiga_tt_dot_noalloc",
     "ttiga_tt_compress", "ttiga_tt_matvec_lowp", "ttiga_tt_info", "ttiga_tt_copy", "ttiga_tt_free", "ttiga_profile",
     "ttiga_profile_read", "ttiga_tt_view_of", "ttiga_footprint", "ttiga_solve_batch",
@@ -159,6 +161,8 @@ def load(path=LIB_PATH):
         "ttiga_solve": (ctypes.c_int, [vp, ctypes.POINTER(SolveStats)]),
         "ttiga_solution_ranks": (ctypes.c_int, [vp, c_int_p, c_int_p]),
         "ttiga_get_solution": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t]),
+        "ttiga_l2_error": (ctypes.c_int, [vp, ctypes.c_int, c_dbl_p, ctypes.c_int, c_dbl_p]),
+        "ttiga_compression_ratios": (ctypes.c_int, [vp, c_dbl_p]),
         "ttiga_problem_tt_info": (ctypes.c_int, [vp, ctypes.c_int, c_int_p, c_int_p, c_int_p]),
         "ttiga_problem_tt_copy": (ctypes.c_int, [vp, ctypes.c_int, c_dbl_p, ctypes.c_size_t]),
         "ttiga_sample_factors": (ctypes.c_int, [vp, c_dbl_p, ctypes.c_size_t, c_dbl_p, c_dbl_p]),
@@ -166,6 +170,10 @@ def load(path=LIB_PATH):
                                           ctypes.c_double, vp, ctypes.c_long, ctypes.c_long, vp, ctypes.c_long,
                                           ctypes.c_long, ctypes.c_double, vp, ctypes.c_long, ctypes.c_long,
                                           ctypes.c_int, c_int_p]),
+        "ttiga_gemm_lowp": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_double, vp, ctypes.c_long, ctypes.c_long, vp,
+                                           ctypes.c_long, ctypes.c_long, ctypes.c_double, vp, ctypes.c_long,
+                                           ctypes.c_long, ctypes.c_int]),
         "ttiga_tt_matvec": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView),
                                            ctypes.POINTER(vp)]),
         "ttiga_tt_matvec_lowp": (ctypes.c_int, [vp, ctypes.POINTER(TTMView), ctypes.POINTER(TTView), ctypes.c_int,
@@ -327,16 +335,24 @@ class Context:
     def gemm_f64(self, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch=1, sA=0, sB=0, sC=0,
                  plan=None):
         """ttiga_gemm_f64 on device float64 tensors A, B, C (row-major, leading dimensions and
-        batch strides in elements); plan = (bm, bn, splits) or None for the library's rule."""
+        batch strides in elements); plan = (bm, bn, kchunk) or None for the library's choice."""
         pl = (ctypes.c_int * 3)(*plan) if plan is not None else None
         _check(self.lib, self.lib.ttiga_gemm_f64(self.h, int(ta), int(tb), M, N, K, float(alpha), A.data_ptr(), lda,
                                                  sA, B.data_ptr(), ldb, sB, float(beta), C.data_ptr(), ldc, sC,
                                                  batch, pl))
 
-    def tt_matvec(self, K_cores_dev, p, x_cores_dev, dtype=None):
+    def gemm_lowp(self, dtype, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch=1, sA=0, sB=0, sC=0):
+        """ttiga_gemm_lowp: the product with operands rounded to dtype (1 FP32, 2 BF16), MFMA in
+        that type with FP32 accumulation; device float64 tensors in and out."""
+        _check(self.lib, self.lib.ttiga_gemm_lowp(self.h, int(dtype), int(ta), int(tb), M, N, K, float(alpha),
+                                                  A.data_ptr(), lda, sA, B.data_ptr(), ldb, sB, float(beta),
+                                                  C.data_ptr(), ldc, sC, batch))
+
+    def tt_matvec(self, K_cores_dev, p, x_cores_dev, dtype=None, copy=True):
         """y = K x; K banded cores [r][n][2p+1][r'] and x cores [r][n][r'] as device tensors.
 
-        dtype TTIGA_FP32 / TTIGA_BF16 (1 / 2) selects the low-precision product."""
+        dtype TTIGA_FP32 / TTIGA_BF16 (1 / 2) selects the low-precision product.  copy=False
+        frees the result on the device without copying it (timing runs) and returns None."""
         kv = TTMView()
         kv.p = p
         rK = [1, K_cores_dev[0].shape[-1], K_cores_dev[1].shape[-1], 1]
@@ -352,6 +368,9 @@ class Context:
                                                            ctypes.byref(h)))
         else:
             _check(self.lib, self.lib.ttiga_tt_matvec(self.h, ctypes.byref(kv), ctypes.byref(xv), ctypes.byref(h)))
+        if not copy:
+            self.lib.ttiga_tt_free(h)
+            return None
         return self._take(h)
 
     def tt_matvec_round(self, K_cores_dev, p, x_cores_dev, eps, alpha=1.0, z_cores_dev=None, beta=0.0,
@@ -570,6 +589,21 @@ class ProblemHandle:
                     rank_u=list(st.rank_u), max_rank_seen=st.max_rank_seen, precond_terms=st.precond_terms,
                     precond_err=st.precond_err, precond_setup_ms=st.precond_setup_ms, time_ms=st.time_ms,
                     refine_steps=st.refine_steps)
+
+    def l2_error(self, exact_kind, params=None, extra_gauss=3):
+        """ttiga_l2_error: relative L2 error of the solution against an exact solution, evaluated
+        in TT format on the device (p + extra_gauss Gauss points per span)."""
+        out = (ctypes.c_double * 3)()
+        prm = (ctypes.c_double * 4)(*params) if params is not None else None
+        _check(self.lib, self.lib.ttiga_l2_error(self.h, int(exact_kind), prm, int(extra_gauss), out))
+        return dict(rel_l2=out[0], err_norm=out[1], exact_norm=out[2])
+
+    def compression_ratios(self):
+        """ttiga_compression_ratios: full-grid entries over TT entries for K (against the sparse
+        and the dense matrix), F and the solution."""
+        out = (ctypes.c_double * 4)()
+        _check(self.lib, self.lib.ttiga_compression_ratios(self.h, out))
+        return dict(K_sparse=out[0], K_dense=out[1], F=out[2], u=out[3])
 
     def solution(self):
         r = (ctypes.c_int * 4)()

@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Offline tile tuner of the FP64 GEMM kernel (writes csrc/gemm_table.inc).
+
+The library picks the tile (64x64, 128x64 or 64x128) and the contraction split of every
+product from a table compiled into it, keyed by shape bucket (transposes, ceil log2 of M, N,
+K, batched or not), with a fixed rule for shapes the table does not list.  So the choice is
+deterministic at run time and the same in every process; this script is what fills the table,
+once per hardware, by measurement:
+
+1. trace: run representative workloads (the plain-vs-mixed annulus solve at n = 256, the
+   complex geometry at n = 128, a slice of the batched family) in a child process with
+   TTIGA_GEMM_TRACE=1, which makes the library print the shape of every product;
+2. time: for the most frequent shape of every bucket, every tile with contraction chunks of
+   {whole K, 2048, 1024, 512, 256} (multiples of 32) through ttiga_gemm_f64 on random operands,
+   median of 7 timed runs after 2 warm-ups (HIP events on the context stream);
+3. choose: a bucket gets a table entry when its best plan beats the rule's plan by more than
+   5%; the entry stores the tile and the contraction chunk.
+
+Usage (on the GPU): python paper_2509_13224_amd/tune_gemm.py [--out csrc/gemm_table.inc]
+The table is a build input: rebuild after writing it.
+"""
+import argparse
+import collections
+import os
+import re
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+TILES = ((64, 64), (128, 64), (64, 128))
+CHUNKS = (0, 2048, 1024, 512, 256)  # 0: the whole contraction in one pass
+GAIN = 1.05
+
+TRACE_SCRIPT = r"""
+import sys
+sys.path.insert(0, {root!r})
+import workloads as W
+from paper_2509_13224_amd import ttiga
+from workloads.problem import PREC_FP64
+ctx = ttiga.Context(workspace_bytes=64 << 30)
+probs = [W.c2_problem(n=256), W.c3_problem(n=128, precision=PREC_FP64)]
+probs += W.c4_requests(count=12)
+for pr in probs:
+    h = ctx.problem_create(pr, precond=1)
+    h.assemble()
+    h.solve(allow_notconv=True)
+    h.close()
+"""
+
+
+def ceil_log2(v):
+    b = 0
+    while (1 << b) < v:
+        b += 1
+    return b
+
+
+def bucket(ta, tb, M, N, K, batch):
+    return (ta, tb, ceil_log2(M), ceil_log2(N), ceil_log2(K), 1 if batch > 1 else 0)
+
+
+def trace_shapes():
+    env = dict(os.environ, TTIGA_GEMM_TRACE="1")
+    r = subprocess.run([sys.executable, "-c", TRACE_SCRIPT.format(root=ROOT)], capture_output=True, text=True,
+                       env=env, timeout=1200)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr[-3000:])
+    shapes = collections.Counter()
+    for line in r.stderr.splitlines():
+        m = re.match(r"\[gemm-shape\] ta=(\d) tb=(\d) M=(\d+) N=(\d+) K=(\d+) batch=(\d+)", line)
+        if m:
+            shapes[tuple(int(v) for v in m.groups())] += 1
+    return shapes
+
+
+def time_plan(ctx, torch, shape, plan, reps=7):
+    ta, tb, M, N, K, batch = shape
+    a_shape = (batch, K, M) if ta else (batch, M, K)
+    b_shape = (batch, N, K) if tb else (batch, K, N)
+    A = torch.randn(a_shape, dtype=torch.float64, device="cuda")
+    B = torch.randn(b_shape, dtype=torch.float64, device="cuda")
+    C = torch.zeros((batch, M, N), dtype=torch.float64, device="cuda")
+    args = dict(batch=batch, sA=a_shape[1] * a_shape[2], sB=b_shape[1] * b_shape[2], sC=M * N, plan=plan)
+    times = []
+    for r in range(reps + 2):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.gemm_f64(ta, tb, M, N, K, 1.0, A, a_shape[2], B, b_shape[2], 0.0, C, N, **args)
+        e1.record()
+        e1.synchronize()
+        if r >= 2:
+            times.append(e0.elapsed_time(e1))
+    return sorted(times)[len(times) // 2]
+
+
+def rule_plan(M, N, K, batch):
+    """The library's rule (gemm_plan without a table entry) as (bm, bn, kchunk), for the
+    comparison."""
+    bm = bn = 64
+    if 64 < M <= 128 and N > 128:
+        bm = 128
+    elif 64 < N <= 128 and M > 128:
+        bn = 128
+    tiles = ((M + bm - 1) // bm) * ((N + bn - 1) // bn) * batch
+    kchunk = 0
+    if tiles < 256 and K >= 512:
+        s = min((K + 255) // 256, max(1, 512 // tiles))
+        kchunk = (K + s - 1) // s
+        kchunk = (kchunk + 31) // 32 * 32
+    return (bm, bn, kchunk)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--out", default=os.path.join(HERE, "csrc", "gemm_table.inc"))
+    args = ap.parse_args()
+    import torch
+
+    from paper_2509_13224_amd import ttiga
+    shapes = trace_shapes()
+    buckets = collections.defaultdict(collections.Counter)
+    for sh, cnt in shapes.items():
+        buckets[bucket(*sh)][sh] += cnt
+    print(f"{sum(shapes.values())} products, {len(shapes)} shapes, {len(buckets)} buckets", file=sys.stderr)
+    ctx = ttiga.Context(workspace_bytes=8 << 30)
+    entries = []
+    for key in sorted(buckets):
+        sh, cnt = buckets[key].most_common(1)[0]
+        ta, tb, M, N, K, batch = sh
+        if M * N * batch * 8 > (1 << 31) or M * K * batch * 8 > (1 << 31) or K * N * batch * 8 > (1 << 31):
+            continue
+        base = time_plan(ctx, torch, sh, rule_plan(M, N, K, batch))
+        best, best_t = None, base
+        for bm, bn in TILES:
+            for ch in CHUNKS:
+                if ch and ch >= K:
+                    continue
+                splits = 1 if ch == 0 else (K + ch - 1) // ch
+                if batch * splits > 65535:
+                    continue
+                t = time_plan(ctx, torch, sh, (bm, bn, ch))
+                if t * GAIN < best_t:
+                    best, best_t = (bm, bn, ch), t
+        if best:
+            entries.append((key, best, base, best_t))
+            print(f"{key} {sh} x{cnt}: rule {base * 1e3:.1f} us -> {best} {best_t * 1e3:.1f} us", file=sys.stderr)
+    with open(args.out, "w") as f:
+        f.write("// Generated by paper_2509_13224_amd/tune_gemm.py from timings on MI355X; rebuild after\n")
+        f.write("// regenerating.  {ta, tb, ceil log2 M, N, K, batched, tile rows, tile cols, contraction\n")
+        f.write("// chunk (0: whole K)}, sorted by key; buckets not listed follow gemm_plan's rule.\n")
+        for (key, (bm, bn, ch), base, t) in entries:
+            f.write("{%d, %d, %d, %d, %d, %d, %d, %d, %d},  // rule %.1f us, tuned %.1f us\n"
+                    % (*key, bm, bn, ch, base * 1e3, t * 1e3))
+    print(f"wrote {len(entries)} entries to {args.out}", file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()

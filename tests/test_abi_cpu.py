@@ -95,10 +95,13 @@ def test_validate_constant_dirichlet_rules():
     geo = W.annulus_sector(0.5, 1.0, math.pi / 2, 1.0)
     ok = Dirichlet(kind=(BC_CONSTANT, BC_CONSTANT) + (BC_NATURAL,) * 4, value=(1.0, 2.0, 0, 0, 0, 0))
     assert ttiga.validate(W.small_problem(geo, 8, 2, W.zero_source(), dirichlet=ok))[0] == 0
+    # constants on faces of several directions are lifted too (the later face wins at edges)
     two_dirs = Dirichlet(kind=(BC_CONSTANT,) * 2 + (BC_CONSTANT,) + (BC_NATURAL,) * 3,
                          value=(1.0, 2.0, 3.0, 0, 0, 0))
-    code, msg = ttiga.validate(W.small_problem(geo, 8, 2, W.zero_source(), dirichlet=two_dirs))
-    assert code == ttiga.TTIGA_E_ARG and "more than one direction" in msg
+    assert ttiga.validate(W.small_problem(geo, 8, 2, W.zero_source(), dirichlet=two_dirs))[0] == 0
+    bad_kind = Dirichlet(kind=(BC_CONSTANT, 7) + (BC_NATURAL,) * 4, value=(1.0, 2.0, 0, 0, 0, 0))
+    code, msg = ttiga.validate(W.small_problem(geo, 8, 2, W.zero_source(), dirichlet=bad_kind))
+    assert code == ttiga.TTIGA_E_ARG and "boundary kind" in msg
 
 
 def test_footprint_estimate_orders_requests():

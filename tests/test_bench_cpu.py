@@ -52,10 +52,33 @@ def test_percentile():
 
 
 def test_cpu_baseline_reports_the_contract_fields():
-    out = bench.cpu_baseline(16, 1)
-    assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "solves/s"
-    assert out["value"] > 0 and out["seconds_sampled"] > 0
-    assert "1 of" in out["sample"]
+    """A whole oracle solve at a small n, on the host's cores, with the core count, CPU model and
+    BLAS threads recorded, and the full-size sampling bound beside it."""
+    out = bench.cpu_baseline(8, 1, 16)
+    cores, affinity = bench.host_cores()
+    assert out["kind"] == "oracle" and out["cores"] == cores and out["unit"] == "solves/s"
+    assert out["value"] > 0 and out["seconds"] > 0 and out["n"] == 8
+    assert out["affinity_cores"] == affinity >= cores >= 1
+    assert "n=8" in out["sample"] and "1 of" in out["full_size_sampling_bound"]["note"]
+    assert out["full_size_sampling_bound"]["solves_per_s"] > 0
+
+
+def test_measured_traffic_needs_the_recorded_source(tmp_path, monkeypatch):
+    """The PMC traffic line counts only while the kernel's source file is unchanged."""
+    import hashlib
+    src = tmp_path / "k.hip"
+    src.write_text("kernel v1")
+    sha = hashlib.sha256(b"kernel v1").hexdigest()
+    summary = tmp_path / "pmc.md"
+    summary.write_text(f"traffic: kernel=kx fetch_kib=10.0 write_kib=6.0 source=k.hip sha256={sha}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summary))
+    val, note = bench.measured_traffic("kx")
+    assert val == 16.0 * 1024 and "pmc" in note
+    assert bench.measured_traffic("other")[0] is None
+    src.write_text("kernel v2")
+    val, note = bench.measured_traffic("kx")
+    assert val is None and "changed" in note
 
 
 def test_roofline_entry_arithmetic():

@@ -71,8 +71,8 @@ def test_gemm_default_plan(ctx, ta, tb, shape):
     _run(ctx, ta, tb, M, N, K, batch, -0.5, 2.0, None, seed=M + N + K)
 
 
-@pytest.mark.parametrize("plan", [(64, 64, 1), (128, 64, 1), (64, 128, 1), (64, 64, 5), (128, 64, 3),
-                                  (64, 128, 2)])
+@pytest.mark.parametrize("plan", [(64, 64, 0), (128, 64, 0), (64, 128, 0), (64, 64, 64), (128, 64, 96),
+                                  (64, 128, 160)])
 def test_gemm_every_plan(ctx, plan):
     say("gemm plan", plan)
     for ta in (0, 1):
@@ -89,4 +89,47 @@ def test_gemm_rejects_bad_arguments(ctx):
     with pytest.raises(ttiga.TTIGAError):
         ctx.gemm_f64(0, 0, 4, 4, 4, 1.0, A, 2, A, 4, 0.0, A, 4)  # lda shorter than a row
     with pytest.raises(ttiga.TTIGAError):
-        ctx.gemm_f64(0, 0, 4, 4, 4, 1.0, A, 4, A, 4, 0.0, A, 4, plan=(32, 32, 1))
+        ctx.gemm_f64(0, 0, 4, 4, 4, 1.0, A, 4, A, 4, 0.0, A, 4, plan=(32, 32, 0))
+    with pytest.raises(ttiga.TTIGAError):
+        ctx.gemm_f64(0, 0, 4, 4, 4, 1.0, A, 4, A, 4, 0.0, A, 4, plan=(64, 64, 48))  # chunk not a multiple of 32
+
+
+def _round_lowp(x, dtype):
+    """The operand rounding of the low-precision product: FP64 -> FP32 (nearest even), and for
+    BF16 FP32 -> BF16 (nearest even on the upper 16 bits), exactly as the host can emulate it."""
+    f = x.astype(np.float32)
+    if dtype == 2:
+        u = f.view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        f = u.astype(np.uint32).view(np.float32)
+    return f.astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("shape", [(70, 130, 300, 1), (5, 9, 33, 3), (200, 64, 1200, 1)])
+def test_gemm_lowp_matches_rounded_operands(ctx, dtype, ta, tb, shape):
+    """The low-precision MFMA product equals the exact product of the rounded operands within the
+    FP32 accumulation bound 2 K u32 (|A_r| |B_r|): the operand rounding, the MFMA operand and
+    result layouts and the K splits are all checked by it."""
+    import torch
+    M, N, K, batch = shape
+    say("gemm lowp", dtype, ta, tb, shape)
+    rng = np.random.default_rng(M + N + K + dtype)
+    a_shape = (batch, K, M) if ta else (batch, M, K)
+    b_shape = (batch, N, K) if tb else (batch, K, N)
+    A = rng.normal(size=a_shape)
+    B = rng.normal(size=b_shape)
+    C0 = rng.normal(size=(batch, M, N))
+    Ar, Br = _round_lowp(A, dtype), _round_lowp(B, dtype)
+    opA = np.swapaxes(Ar, 1, 2) if ta else Ar
+    opB = np.swapaxes(Br, 1, 2) if tb else Br
+    alpha, beta = 0.75, -0.5
+    ref = alpha * np.matmul(opA, opB) + beta * C0
+    bound = 2 * K * 2.0 ** -24 * abs(alpha) * np.matmul(np.abs(opA), np.abs(opB)) + 2 * U * abs(beta) * np.abs(C0)
+    dC = torch.from_numpy(C0).cuda()
+    ctx.gemm_lowp(dtype, ta, tb, M, N, K, alpha, torch.from_numpy(A).cuda(), a_shape[2], torch.from_numpy(B).cuda(),
+                  b_shape[2], beta, dC, N, batch=batch, sA=a_shape[1] * a_shape[2], sB=b_shape[1] * b_shape[2],
+                  sC=M * N)
+    err = np.abs(dC.cpu().numpy() - ref)
+    assert np.all(err <= bound + 1e-300), float(np.max(err / (bound + 1e-300)))

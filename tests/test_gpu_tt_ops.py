@@ -35,6 +35,26 @@ def test_matvec_matches_dense(ctx, shape, rK, rx, p):
         assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
 
 
+@pytest.mark.parametrize("shape,rK,rx,p", [
+    ((600, 20, 9), (12, 84), (30, 7), 3),  # many row tiles with a ragged tail; LDS-limited tiles of 9 rows
+    ((257, 31, 40), (5, 3), (64, 65), 2),  # vector ranks above one wave
+    ((40, 30, 20), (3, 4), (5, 6), 5),     # the widest compiled band
+    ((40, 30, 20), (3, 4), (5, 6), 6),     # a band width without its own kernel (generic path)
+])
+def test_matvec_cores_match_oracle(ctx, shape, rK, rx, p):
+    """Every product core against the oracle's TT-matvec core (elementwise, within the rounding
+    of a (2p+1)-term sum)."""
+    say("matvec cores", shape, rK, rx, p)
+    rng = np.random.default_rng(sum(shape) * 3 + p)
+    K = rand_banded(shape, rK, p, rng)
+    x = rand_tt(shape, rx, rng)
+    y = ctx.tt_matvec(to_dev(K), p, to_dev(x))
+    yo = tt.matvec(banded_to_dense_cores(K, p), x)
+    for a, b in zip(y, yo):
+        assert a.shape == b.shape
+        assert np.max(np.abs(a - b)) <= 1e-14 * (2 * p + 1) * np.max(np.abs(b))
+
+
 @pytest.mark.parametrize("shape,ra,rb", [((4, 5, 6), (2, 3), (3, 2)), ((40, 33, 70), (9, 7), (12, 5))])
 def test_dot_matches_dense(ctx, shape, ra, rb):
     say("dot", shape, ra, rb)

@@ -6,7 +6,7 @@ import pytest
 
 import workloads as W
 from oracle import bspline, errors, geometry, nurbs, sources, sparse_iga
-from workloads.problem import BC_CONSTANT, BC_NATURAL, Dirichlet
+from workloads.problem import BC_CONSTANT, BC_NATURAL, BC_ZERO, Dirichlet
 
 
 def _annulus_closed_form(pts, r_in=1.0, r_out=2.0, sweep=math.pi / 2, H=1.0):
@@ -175,3 +175,101 @@ def test_ring_laplace_log_solution():
         exact = lambda x: sources.ring_log_solution(x, 0.5, 1.0, 1.0, 2.0)
         errs.append(errors.rel_l2(pr, u.reshape(n, n, n), exact))
     assert errs[1] < errs[0] / 4 and errs[1] < 1e-4
+
+
+def test_lshape_geometry_volume_and_orientation():
+    """The L-shape of Section 5.1 as one C0 patch: det J > 0 at every Gauss point and the volume
+    (3 for height 1: the 2 x 2 square minus the unit cutout) from the load vector of f = 1."""
+    pr = W.small_problem(W.lshape(), (9, 5, 3), 1, W.zero_source())
+    fac, detJ = geometry.sample_factors_grid(pr)
+    assert detJ.min() > 0.0
+    fac[6] = detJ
+    _, F = sparse_iga.assemble(pr, fac)
+    assert abs(F.sum() - 3.0) < 1e-12
+
+
+def test_lshape_forcing_matches_laplacian():
+    """-Laplace of the L-shape solution by central differences equals sin(pi x) sin(pi y), and the
+    two-mode Fourier source evaluates to the same function."""
+    rng = np.random.default_rng(6)
+    x = np.stack([rng.uniform(-0.9, 0.9, 40), rng.uniform(-0.9, -0.1, 40), rng.uniform(0.1, 0.9, 40)], axis=1)
+    h = 1e-3
+    lap = -6 * sources.lshape_solution(x)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        lap += sources.lshape_solution(x + e) + sources.lshape_solution(x - e)
+    lap /= h * h
+    f_exact = np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1])
+    assert np.max(np.abs(-lap - f_exact)) < 1e-6
+    assert np.max(np.abs(sources.evaluate(W.sine_xy_source(), x) - f_exact)) < 1e-14
+
+
+@pytest.mark.slow
+def test_lshape_linear_convergence_rate():
+    """Section 5.1 with linear B-splines, homogeneous Dirichlet on the lateral faces and natural
+    faces at z = 0, 1 (reading of the garbled boundary sentence): the L2 error against
+    sin(pi x) sin(pi y) / (2 pi^2) decays with slope about 2 in the points per edge."""
+    bc = Dirichlet(kind=(BC_ZERO,) * 4 + (BC_NATURAL,) * 2, value=(0.0,) * 6)
+    errs, ns = [], [(9, 5, 2), (17, 9, 2), (33, 17, 2)]
+    for nb in ns:
+        pr = W.small_problem(W.lshape(), nb, 1, W.sine_xy_source(), dirichlet=bc)
+        u = sparse_iga.solve(pr)
+        errs.append(errors.rel_l2(pr, u.reshape(nb), sources.lshape_solution))
+    slopes = [math.log(errs[i] / errs[i + 1]) / math.log((ns[i + 1][1] - 1) / (ns[i][1] - 1)) for i in range(2)]
+    assert 1.7 < slopes[-1] < 2.3, (errs, slopes)
+
+
+def test_full_ring_volume_and_log_solution():
+    """The full ring of Section 5.2 (r 0.5..1, height 1, nine-point circle with C0 knots): volume
+    pi (r_out^2 - r_in^2) h from f = 1, and the radial Laplace solution with u = 1 / 2 on the
+    cylinders (natural seam and end faces) within the discretisation error, decreasing with n."""
+    pr = W.small_problem(W.ring(), (3, 10, 3), 2, W.zero_source())
+    fac, detJ = geometry.sample_factors_grid(pr)
+    assert detJ.min() > 0.0
+    fac[6] = detJ
+    _, F = sparse_iga.assemble(pr, fac)
+    assert abs(F.sum() - math.pi * 0.75) < 1e-3  # the rational circle is exact; quadrature is not
+    bc = Dirichlet(kind=(BC_CONSTANT, BC_CONSTANT) + (BC_NATURAL,) * 4, value=(1.0, 2.0, 0, 0, 0, 0))
+    exact = lambda x: sources.ring_log_solution(x, 0.5, 1.0, 1.0, 2.0)
+    errs = []
+    for nb in ((4, 9, 3), (7, 9, 3)):
+        pr = W.small_problem(W.ring(), nb, 2, W.zero_source(), dirichlet=bc)
+        u = sparse_iga.solve(pr)
+        errs.append(errors.rel_l2(pr, u.reshape(nb), exact))
+    assert errs[1] < errs[0] / 4 and errs[1] < 1e-4, errs
+
+
+def test_traction_load_integrates_the_face_area():
+    """A unit flux on a face gives sum_a F_a = the face's area (partition of unity): on the
+    quarter annulus r 1..2, 90 degrees, height 1 the outer cylinder (xi0 = 1) has area pi, the
+    inner pi / 2, the flat end xi2 = 1 the quarter ring 3 pi / 4."""
+    from workloads.problem import BC_TRACTION
+    for face, area in ((1, math.pi), (0, math.pi / 2), (5, 0.75 * math.pi)):
+        kind = [BC_NATURAL] * 6
+        kind[face] = BC_TRACTION
+        val = [0.0] * 6
+        val[face] = 1.0
+        pr = W.small_problem(W.annulus_sector(), (5, 7, 4), 2, W.zero_source(),
+                             dirichlet=Dirichlet(kind=tuple(kind), value=tuple(val)))
+        Fs = sparse_iga.traction_load(pr)
+        # the arc's length element is rational, so the Gauss rule is accurate, not exact
+        assert abs(Fs.sum() - area) <= 1e-6 * area, (face, Fs.sum(), area)
+        assert np.all(Fs.reshape(5, 7, 4)[tuple(slice(None) if d != face // 2 else (0 if face % 2 == 0 else -1)
+                                                for d in range(3))] >= 0.0)
+
+
+def test_ring_with_traction_reaches_the_log_solution():
+    """Dirichlet u = 1 at r = 1 and the flux du/dr = 1 / (r_out ln 2) at r = 2 (Section 5.2's
+    radial solution with its outer condition written as a traction): the solution converges to
+    u = 1 + ln(r) / ln 2, the same log solution as with u = 2 there."""
+    from workloads.problem import BC_TRACTION
+    g = 1.0 / (2.0 * math.log(2.0))
+    bc = Dirichlet(kind=(BC_CONSTANT, BC_TRACTION) + (BC_NATURAL,) * 4, value=(1.0, g, 0, 0, 0, 0))
+    exact = lambda x: sources.ring_log_solution(x, 1.0, 2.0, 1.0, 2.0)
+    errs = []
+    for nb in ((4, 4, 3), (8, 4, 3)):
+        pr = W.small_problem(W.annulus_sector(), nb, 2, W.zero_source(), dirichlet=bc)
+        u = sparse_iga.solve(pr)
+        errs.append(errors.rel_l2(pr, u.reshape(nb), exact))
+    assert errs[1] < errs[0] / 5 and errs[1] < 1e-4, errs

@@ -25,6 +25,7 @@ from .problem import (  # noqa: F401
     BC_NATURAL,
     BC_ZERO,
     BC_CONSTANT,
+    BC_TRACTION,
     PREC_FP64,
     PREC_FP32,
     PREC_BF16,
@@ -34,7 +35,15 @@ from .geometries import (  # noqa: F401
     twisted_box,
     bumpy_cube,
     identity_cube,
+    lshape,
     nurbs_circle_fig1,
+    ring,
 )
-from .sources import fourier_source, manufactured_annulus_source, zero_source  # noqa: F401
+from .sources import (  # noqa: F401
+    fourier_source,
+    manufactured_annulus_source,
+    sine_product_source,
+    sine_xy_source,
+    zero_source,
+)
 from .configs import c1_problem, c2_problem, c3_problem, c4_requests, small_problem  # noqa: F401

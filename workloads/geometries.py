@@ -55,6 +55,49 @@ def twisted_box(twist=0.5 * math.pi):
     return Geometry(degree=(1, 1, 3), knots=knots, ctrl=ctrl, weights=None)
 
 
+def lshape(height=1.0):
+    """The L-shaped solid of Section 5.1: [-1, 1]^2 x [0, height] with [0, 1]^2 x [0, height]
+    removed, as one bilinear-by-linear B-spline patch with a C0 knot.
+
+    Direction 0 runs along the L through its corner (knots {0, 0, 1/2, 1, 1}, the kink of the
+    map at 1/2): cross-sections from the end of the left leg (outer point (-1, 1), inner (0, 1))
+    through the corner ((-1, -1) to (0, 0)) to the end of the lower leg ((1, -1) to (1, 0)).
+    Direction 1 runs across the leg from the outer side to the inner (re-entrant) side, which
+    makes det J positive, direction 2 along the height.  Both halves are bilinear quadrilaterals: the left leg minus
+    the triangle (0, 0), (0, -1), (-1, -1), and the lower leg plus that triangle.
+    """
+    sections = [((-1.0, 1.0), (0.0, 1.0)), ((-1.0, -1.0), (0.0, 0.0)), ((1.0, -1.0), (1.0, 0.0))]
+    ctrl = np.zeros((3, 2, 2, 3))
+    for a, sec in enumerate(sections):
+        for b, (x, y) in enumerate(sec):
+            for c, z in enumerate((0.0, height)):
+                ctrl[a, b, c] = (x, y, z)
+    knots = [_open_knots(1, (0.5,)), _open_knots(1), _open_knots(1)]
+    return Geometry(degree=(1, 1, 1), knots=knots, ctrl=ctrl, weights=None)
+
+
+def ring(r_in=0.5, r_out=1.0, height=1.0):
+    """The full ring of Section 5.2: radii r_in..r_out, height 0..height, as one NURBS patch.
+
+    Direction 0 is radial, direction 1 goes once around the circle (the standard nine-point
+    rational quadratic circle: knots {0, 0, 0, 1/4, 1/4, 1/2, 1/2, 3/4, 3/4, 1, 1, 1}, corner
+    weights 1, edge-midpoint weights 1/sqrt(2)), direction 2 the height.  The faces xi1 = 0 and
+    xi1 = 1 meet at the seam theta = 0; they are left natural, which is exact for data and
+    solutions that do not depend on the angle.
+    """
+    circ = [(1, 0), (1, 1), (0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1), (1, 0)]
+    w_c = [1.0 if i % 2 == 0 else 1.0 / math.sqrt(2.0) for i in range(9)]
+    ctrl = np.zeros((2, 9, 2, 3))
+    wts = np.zeros((2, 9, 2))
+    for a, rho in enumerate((r_in, r_out)):
+        for b, (cx, cy) in enumerate(circ):
+            for c, z in enumerate((0.0, height)):
+                ctrl[a, b, c] = (rho * cx, rho * cy, z)
+                wts[a, b, c] = w_c[b]
+    knots = [_open_knots(1), _open_knots(2, (0.25, 0.25, 0.5, 0.5, 0.75, 0.75)), _open_knots(1)]
+    return Geometry(degree=(1, 2, 1), knots=knots, ctrl=ctrl, weights=wts)
+
+
 CUBE_KNOTS_P3 = (0.2, 0.4, 0.6, 0.8)
 CUBE_GREVILLE_P3 = (0.0, 1.0 / 15.0, 0.2, 0.4, 0.6, 0.8, 14.0 / 15.0, 1.0)
 

@@ -20,6 +20,7 @@ SOURCE_FOURIER = 2
 BC_NATURAL = 0
 BC_ZERO = 1
 BC_CONSTANT = 2
+BC_TRACTION = 3  # natural face with a constant outward normal derivative du/dn = value
 
 PREC_FP64 = 0
 PREC_FP32 = 1
@@ -77,7 +78,10 @@ class Source:
 
 @dataclass
 class Dirichlet:
-    """Per-face boundary condition; face order xi0=0, xi0=1, xi1=0, xi1=1, xi2=0, xi2=1."""
+    """Per-face boundary condition; face order xi0=0, xi0=1, xi1=0, xi1=1, xi2=0, xi2=1.
+
+    BC_ZERO / BC_CONSTANT faces carry Dirichlet data u = value; BC_NATURAL and BC_TRACTION
+    faces are natural boundaries (Section 3.1), the latter with the flux du/dn = value."""
 
     kind: Sequence[int] = (BC_ZERO,) * 6
     value: Sequence[float] = (0.0,) * 6

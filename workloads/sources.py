@@ -44,3 +44,11 @@ def sine_product_source():
     k = np.array([[1, -1, 1], [-1, 1, 1], [1, 1, 1], [-1, -1, 1]], dtype=np.float64)
     a = np.array([0.25, 0.25, -0.25, -0.25])
     return Source(kind=SOURCE_FOURIER, a=a, k=k, phi=np.zeros(4), origin=np.zeros(3), scale=1.0)
+
+
+def sine_xy_source():
+    """f = sin(pi x) sin(pi y) (the L-shape experiment of Section 5.1), as two Fourier modes:
+    sin A sin B = (sin(A - B + pi/2) - sin(A + B + pi/2)) / 2."""
+    k = np.array([[1, -1, 0], [1, 1, 0]], dtype=np.float64)
+    a = np.array([0.5, -0.5])
+    return Source(kind=SOURCE_FOURIER, a=a, k=k, phi=np.full(2, 0.5 * np.pi), origin=np.zeros(3), scale=1.0)
