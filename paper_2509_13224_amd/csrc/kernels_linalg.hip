@@ -1265,10 +1265,13 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
 // Gram-Schmidt on the rows of Q (QR with column pivoting of Q^T): step l takes the row
 // with the largest residual norm and removes its direction from every row, so the k rows
 // chosen span the column space as well as any greedy choice can (the selection of
-// Q-DEIM).  One workgroup; W (n x k) is a global work copy; norms live in LDS.
+// Q-DEIM).  One workgroup; W (n x k) is a global work copy; the norms live in LDS, or in
+// global memory (nrm_g) when n does not fit there.
 __global__ __launch_bounds__(1024) void k_pivot_rows(int n, int k, const double* __restrict__ Q,
-                                                     double* __restrict__ W, int* __restrict__ rows) {
-  extern __shared__ double nrm[];  // n residual norms (negative once chosen)
+                                                     double* __restrict__ W, int* __restrict__ rows,
+                                                     double* __restrict__ nrm_g) {
+  extern __shared__ double nrm_lds[];
+  double* nrm = nrm_g ? nrm_g : nrm_lds;  // n residual norms (negative once chosen)
   __shared__ double s_v[256];
   __shared__ double s_best[32];
   __shared__ int s_bi[32];
@@ -1325,10 +1328,13 @@ __global__ __launch_bounds__(1024) void k_pivot_rows(int n, int k, const double*
 }
 
 void pivot_rows(Context& ctx, const double* Q, int n, int k, int* rows) {
-  TTIGA_CHECK(n > 0 && k > 0 && k <= 256 && k <= n && n <= 6144, TTIGA_E_ARG, "pivot_rows: bad shape");
+  TTIGA_CHECK(n > 0 && k > 0 && k <= 256 && k <= n, TTIGA_E_ARG, "pivot_rows: bad shape");
   DBuf W(ctx.alloc, sizeof(double) * (size_t)n * k);
+  const bool lds = n <= 6144;
+  DBuf G(ctx.alloc, lds ? 0 : sizeof(double) * (size_t)n);
   ProfScope prof(ctx, "pivot_rows", 4.0 * n * (double)k * k, 16.0 * n * (double)k * k);
-  hipLaunchKernelGGL(k_pivot_rows, dim3(1), dim3(1024), sizeof(double) * n, ctx.stream, n, k, Q, W.d(), rows);
+  hipLaunchKernelGGL(k_pivot_rows, dim3(1), dim3(1024), lds ? sizeof(double) * n : 0, ctx.stream, n, k, Q, W.d(), rows,
+                     lds ? nullptr : G.d());
   TTIGA_HIP(hipGetLastError());
 }
 

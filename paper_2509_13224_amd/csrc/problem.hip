@@ -237,6 +237,180 @@ static uint64_t splitmix(uint64_t& state) {
   return z ^ (z >> 31);
 }
 
+// Second level of the cross approximation: with the first-mode bases U_t (Q0 x k_t), the
+// interpolation rows I and P_t^+ = U_t[I, :]^+, the coefficient tensor X_t = P_t^+ A_t[I, :, :]
+// (k_t x Q1 x Q2) is approximated in the same way along its last mode instead of being formed:
+//  a. L2 random third-direction indices j: the fibres X_t[:, :, j] from the samples A[I, :, j]
+//     (|I| Q1 L2 points), their column basis V_t ((k_t Q1) x k2_t, truncated at 0.1 eps of the
+//     largest metric sample scale), L2 doubling while a rank comes within 8 of it;
+//  b. interpolation rows R_t of V_t (pivoted Gram-Schmidt on its rows, as for U_t); the rows
+//     (a, i1) need the samples A[I, i1, :] for the distinct i1 of all R_t plus 8 random ones
+//     (|I| |S| Q2 points), giving X_t[R_t, :];
+//  c. X_t ~= V_t D_t with D_t = V_t[R_t, :]^+ X_t[R_t, :] (k2_t x Q2); the TT of the factor is
+//     (U_t, V_t as k_t x Q1 x k2_t, D_t), rounded at eps of its scale like the TT-SVD path.
+// Declines (the caller samples the whole slices) when a basis saturates its largest sample,
+// when V_t[R_t, :] is ill-conditioned or when the grid is too small for it to pay.
+bool Problem::cross_second_level(const GeoDev& gd, const SourceDev& sd, TT* fac, ttiga_assembly_stats& s,
+                                 const std::vector<DBuf>& U, const std::vector<int>& k, const std::vector<int>& I,
+                                 const DBuf& Id, const std::vector<DBuf>& Pinv, double* scale, uint64_t& rs) {
+  Context& c = *ctx;
+  const int n1 = Q[1], n2 = Q[2];
+  const int nI = (int)I.size();
+  const double eps = assembly_eps();
+  auto rnd = [&](int hi) { return (int)(splitmix(rs) % (uint64_t)hi); };
+  const int cap = std::min(n2 / 2, 256);
+  if (cap < 32 || n1 < 8) return false;
+  int L2 = std::min(cap, 48);
+  std::vector<DBuf> V(7);
+  std::vector<int> k2(7, 0);
+  while (true) {
+    // a. the fibres A[i0, i1, j] for i0 in I, all i1, the L2 chosen j
+    std::vector<int> J(L2);
+    for (int q = 0; q < L2; ++q) J[q] = rnd(n2);
+    const long cnt = (long)nI * n1 * L2;
+    std::vector<int> h0(cnt), h1(cnt), h2(cnt);
+    for (int a = 0; a < nI; ++a)
+      for (int i1 = 0; i1 < n1; ++i1)
+        for (int q = 0; q < L2; ++q) {
+          const long e = ((long)a * n1 + i1) * L2 + q;
+          h0[e] = I[a];
+          h1[e] = i1;
+          h2[e] = J[q];
+        }
+    DBuf idx(c.alloc, sizeof(int) * 3 * cnt), Af(c.alloc, sizeof(double) * 7 * cnt);
+    int* di = idx.as<int>();
+    TTIGA_HIP(hipMemcpyAsync(di, h0.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(di + cnt, h1.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(di + 2 * cnt, h2.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+    launch_factors_at(c, gd, sd, cnt, di, di + cnt, di + 2 * cnt, Af.d(), nullptr);
+    s.samples += cnt;
+    // C_t = P_t^+ A_t[I, :, J]: (k_t) x (Q1 L2), read as (k_t Q1) x L2
+    std::vector<DBuf> C(7);
+    DBuf csq(c.alloc, sizeof(double) * 7);
+    fill(c, csq.d(), 7, 0.0);
+    for (int t = 0; t < 7; ++t) {
+      if (!k[t]) continue;
+      C[t] = DBuf(c.alloc, sizeof(double) * (size_t)k[t] * n1 * L2);
+      gemm(c, false, false, k[t], n1 * L2, nI, 1.0, Pinv[t].d(), nI, 0, Af.d() + (size_t)t * cnt, (long)n1 * L2, 0,
+           0.0, C[t].d(), (long)n1 * L2, 0);
+      sumsq_reduce(c, C[t].d(), (size_t)k[t] * n1 * L2, csq.d() + t);
+    }
+    double* hc = c.host(7);
+    TTIGA_HIP(hipMemcpyAsync(hc, csq.d(), 7 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();  // the host index arrays go out of scope
+    double cmax = 0.0;
+    for (int t = 0; t < 6; ++t) cmax = std::max(cmax, std::sqrt(std::max(hc[t], 0.0)));
+    bool saturated = false;
+    for (int t = 0; t < 7; ++t) {
+      const double cs = t < 6 ? cmax : std::sqrt(std::max(hc[6], 0.0));
+      k2[t] = (k[t] && cs > 0.0 && (long)k[t] * n1 >= L2) ? column_basis(c, C[t].d(), k[t] * n1, L2, 0.1 * eps * cs, V[t])
+                                                         : 0;
+      if (k[t] && (long)k[t] * n1 < L2) return false;
+      if (k2[t] > L2 - 8) saturated = true;
+    }
+    if (!saturated) break;
+    if (L2 == cap) return false;
+    L2 = std::min(cap, 2 * L2);
+  }
+  // b. interpolation rows (a, i1) of each V_t; the distinct i1 of all of them plus 8 random
+  std::vector<std::vector<int>> R(7);
+  std::vector<char> pick(n1, 0);
+  for (int t = 0; t < 7; ++t) {
+    if (!k2[t]) continue;
+    DBuf rows(c.alloc, sizeof(int) * k2[t]);
+    pivot_rows(c, V[t].d(), k[t] * n1, k2[t], rows.as<int>());
+    R[t].resize(k2[t]);
+    TTIGA_HIP(hipMemcpyAsync(R[t].data(), rows.d(), sizeof(int) * k2[t], hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    for (int r : R[t]) pick[r % n1] = 1;
+  }
+  for (int e = 0; e < 8; ++e) pick[rnd(n1)] = 1;
+  std::vector<int> S, pos(n1, -1);
+  for (int i1 = 0; i1 < n1; ++i1)
+    if (pick[i1]) {
+      pos[i1] = (int)S.size();
+      S.push_back(i1);
+    }
+  const int nS = (int)S.size();
+  if (2 * nS > n1) return false;
+  // the samples A[i0, i1, :] for i0 in I, i1 in S; E_t = P_t^+ A_t[I, S, :] (k_t x |S| Q2)
+  const long cnt = (long)nI * nS * n2;
+  std::vector<int> h0(cnt), h1(cnt), h2(cnt);
+  for (int a = 0; a < nI; ++a)
+    for (int q = 0; q < nS; ++q)
+      for (int i2 = 0; i2 < n2; ++i2) {
+        const long e = ((long)a * nS + q) * n2 + i2;
+        h0[e] = I[a];
+        h1[e] = S[q];
+        h2[e] = i2;
+      }
+  DBuf idx(c.alloc, sizeof(int) * 3 * cnt), As(c.alloc, sizeof(double) * 7 * cnt);
+  int* di = idx.as<int>();
+  TTIGA_HIP(hipMemcpyAsync(di, h0.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+  TTIGA_HIP(hipMemcpyAsync(di + cnt, h1.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+  TTIGA_HIP(hipMemcpyAsync(di + 2 * cnt, h2.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
+  launch_factors_at(c, gd, sd, cnt, di, di + cnt, di + 2 * cnt, As.d(), nullptr);
+  s.samples += cnt;
+  c.sync();  // the host index arrays go out of scope
+  // c. D_t = V_t[R_t, :]^+ X_t[R_t, :] and the TT (U_t, V_t, D_t)
+  double nrm[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int t = 0; t < 7; ++t) {
+    if (!k2[t]) {
+      fac[t].set_zero(Q);
+      continue;
+    }
+    const int kt = k[t], k2t = k2[t];
+    DBuf E(c.alloc, sizeof(double) * (size_t)kt * nS * n2);
+    gemm(c, false, false, kt, nS * n2, nI, 1.0, Pinv[t].d(), nI, 0, As.d() + (size_t)t * cnt, (long)nS * n2, 0, 0.0,
+         E.d(), (long)nS * n2, 0);
+    // rows of X_t at R_t: row (a, i1) of X_t is row a * |S| + pos(i1) of E viewed as (k_t |S|) x Q2
+    std::vector<int> er(k2t), vr(k2t);
+    for (int q = 0; q < k2t; ++q) {
+      const int a = R[t][q] / n1, i1 = R[t][q] % n1;
+      er[q] = a * nS + pos[i1];
+      vr[q] = R[t][q];
+    }
+    DBuf erd(c.alloc, sizeof(int) * k2t), vrd(c.alloc, sizeof(int) * k2t);
+    TTIGA_HIP(hipMemcpyAsync(erd.d(), er.data(), sizeof(int) * k2t, hipMemcpyHostToDevice, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(vrd.d(), vr.data(), sizeof(int) * k2t, hipMemcpyHostToDevice, c.stream));
+    DBuf XR(c.alloc, sizeof(double) * (size_t)k2t * n2), VR(c.alloc, sizeof(double) * (size_t)k2t * k2t);
+    gather_rows(c, E.d(), n2, erd.as<int>(), k2t, XR.d());
+    gather_rows(c, V[t].d(), k2t, vrd.as<int>(), k2t, VR.d());
+    DBuf Uv(c.alloc, sizeof(double) * k2t * k2t), Sv(c.alloc, sizeof(double) * k2t), Wv(c.alloc, sizeof(double) * k2t * k2t);
+    svd_small(c, VR.d(), false, k2t, k2t, k2t, Uv.d(), Sv.d(), Wv.d());
+    double* h = c.host(2);
+    TTIGA_HIP(hipMemcpyAsync(h, Sv.d(), sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(h + 1, Sv.d() + (k2t - 1), sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();  // er, vr go out of scope
+    if (!(h[1] > 1e-8 * h[0])) return false;
+    // VR^+ = W S^-1 Uv^T; D = VR^+ XR
+    DBuf WS(c.alloc, sizeof(double) * k2t * k2t), VRp(c.alloc, sizeof(double) * k2t * k2t);
+    scale_cols_inv(c, Wv.d(), k2t, k2t, Sv.d(), WS.d());
+    gemm(c, false, true, k2t, k2t, k2t, 1.0, WS.d(), k2t, 0, Uv.d(), k2t, 0, 0.0, VRp.d(), k2t, 0);
+    TT tt;
+    const int rr[4] = {1, kt, k2t, 1};
+    tt.alloc(c, Q, rr);
+    copy(c, tt.c[0].d(), U[t].d(), (size_t)Q[0] * kt);
+    copy(c, tt.c[1].d(), V[t].d(), (size_t)kt * n1 * k2t);
+    gemm(c, false, false, k2t, n2, k2t, 1.0, VRp.d(), k2t, 0, XR.d(), n2, 0, 0.0, tt.c[2].d(), n2, 0);
+    nrm[t] = std::sqrt(std::max(tt_dot_sync(c, tt, tt), 0.0));
+    fac[t] = std::move(tt);
+  }
+  double rmax = 0.0;
+  for (int t = 0; t < 6; ++t) rmax = std::max(rmax, nrm[t]);
+  s.max_R_norm = rmax;
+  for (int t = 0; t < 7; ++t) scale[t] = t < 6 ? rmax : nrm[6];
+  for (int t = 0; t < 7; ++t) {
+    if (fac[t].zero()) continue;
+    if (scale[t] == 0.0) {
+      fac[t].set_zero(Q);
+      continue;
+    }
+    tt_round(c, fac[t], 0.0, eps * scale[t] / std::sqrt(2.0), opts.max_rank);
+  }
+  return true;
+}
+
 // Cross approximation of the first unfolding A_(0) (Q0 x Q1 Q2) of the seven factors, the
 // sampled-entries alternative to full-grid TT-SVD (the role TT-cross plays in the paper):
 //  1. L random columns (fibres along the first direction, shared by the factors); per
@@ -353,9 +527,16 @@ bool Problem::compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, tti
     scale_cols_inv(c, Vp.d(), kt, kt, Sp.d(), VS.d());
     Pinv[t] = DBuf(c.alloc, sizeof(double) * kt * nI);
     gemm(c, false, true, kt, nI, kt, 1.0, VS.d(), kt, 0, Up.d(), kt, 0, 0.0, Pinv[t].d(), nI, 0);
-    X[t] = DBuf(c.alloc, sizeof(double) * (size_t)kt * M);
   }
-  // 3. the slices, in second-direction chunks of at most 2 GiB
+  double scale[7];
+  // 3. the coefficients X_t = P_t^+ A_t[I, :] (k_t x Q1 Q2): by a second cross approximation of X_t
+  // viewed as (k_t Q1) x Q2 when it succeeds (samples of O(Q r^2)), else from the whole slices
+  // A_t[I, :, :] (|I| Q1 Q2 samples)
+  if (cross_second_level(gd, sd, fac, s, U, k, I, Id, Pinv, scale, rs)) {
+    if (trace) std::fprintf(stderr, "[cross] second level accepted\n");
+  } else {
+  for (int t = 0; t < 7; ++t)
+    if (k[t]) X[t] = DBuf(c.alloc, sizeof(double) * (size_t)k[t] * M);
   {
     const size_t slab = sizeof(double) * 7 * (size_t)nI * n2;
     const int chunk = (int)std::max<size_t>(1, std::min<size_t>(n1, (size_t(2) << 30) / slab));
@@ -383,7 +564,7 @@ bool Problem::compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, tti
   for (int t = 0; t < 7; ++t) nrm[t] = std::sqrt(std::max(h[t], 0.0));
   for (int t = 0; t < 6; ++t) rmax = std::max(rmax, nrm[t]);
   s.max_R_norm = rmax;
-  const double scale[7] = {rmax, rmax, rmax, rmax, rmax, rmax, nrm[6]};
+  for (int t = 0; t < 7; ++t) scale[t] = t < 6 ? rmax : nrm[6];
   for (int t = 0; t < 7; ++t) {
     if (k[t] == 0 || nrm[t] == 0.0) {
       fac[t].set_zero(Q);
@@ -392,6 +573,7 @@ bool Problem::compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, tti
     tt_from_first_unfolding(c, U[t].d(), k[t], X[t].d(), Q, eps * scale[t] / std::sqrt(2.0), 0, fac[t],
                             opts.max_rank);
   }
+  }  // whole slices
   // 5. probe check on random grid points
   const int P = 2048;
   std::vector<int> p0(P), p1(P), p2(P);
@@ -737,6 +919,12 @@ void Problem::solve(ttiga_solve_stats* st) {
     s.iterations = 0;
     s.rel_res = 0.0;
     s.status = TTIGA_OK;
+  } else if (opts.solver == TTIGA_SOLVER_AMEN) {
+    TTIGA_CHECK(opts.precision == TTIGA_FP64, TTIGA_E_ARG, "the AMEn solve runs in FP64 only");
+    const double ts = now_ms();
+    if (!pc.ready) pc.setup(*this);
+    s.precond_setup_ms = now_ms() - ts;
+    solve_amen(s);
   } else if (opts.precond) {
     const double ts = now_ms();
     if (!pc.ready) pc.setup(*this);
@@ -754,10 +942,10 @@ void Problem::solve(ttiga_solve_stats* st) {
   solved = true;
   last_solve = s;
   if (st) *st = s;
-  if (s.status != TTIGA_OK) throw Error(s.status, "TT-CG did not reach rel_res_tol within max_iter");
+  if (s.status != TTIGA_OK)
+    throw Error(s.status, opts.solver == TTIGA_SOLVER_AMEN ? "AMEn did not reach rel_res_tol within its sweeps"
+                                                           : "TT-CG did not reach rel_res_tol within max_iter");
 }
-
-using Matvec = std::function<void(const TT&, TT&)>;
 
 // Products K x whose explicit cores (ranks rK rx) would exceed this many bytes are rounded
 // as they are formed (tt_matvec_round) instead of being stored and rounded afterwards.
@@ -773,9 +961,8 @@ static constexpr size_t kFusedProductBytes = size_t(1) << 30;
 // randomised sketch at loose tolerances, and the norm returned is that of the rounded train.  With Kf
 // given and a product too large to store, the residual train is formed already rounded and
 // the norm is that of the rounded train.
-static double true_residual(Context& c, const Matvec& mv, const TT& b, const TT& x, double nb,
-                            double eps_x, int max_rank, TT& r, int& hint, const TT* Kf = nullptr, int p = 0,
-                            bool exact_norm = true) {
+double true_residual(Context& c, const Matvec& mv, const TT& b, const TT& x, double nb, double eps_x, int max_rank,
+                     TT& r, int& hint, const TT* Kf, int p, bool exact_norm) {
   if (Kf && matvec_product_bytes(*Kf, x) > kFusedProductBytes) {
     tt_matvec_round(c, *Kf, p, x, -1.0, &b, 1.0, eps_x, max_rank, hint, r);
     return std::sqrt(std::max(tt_dot_sync(c, r, r), 0.0)) / nb;

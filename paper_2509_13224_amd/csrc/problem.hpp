@@ -1,6 +1,7 @@
 // One TT-IGA problem: validated host copy of the description plus its device state.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "iga.hpp"
@@ -20,6 +21,12 @@ struct PcgRun {
 };
 
 constexpr int kMaxRefineSteps = 12;
+
+using Matvec = std::function<void(const TT&, TT&)>;
+
+// ||b - K x|| / ||b|| with the residual train b - K x rounded at eps_x into r (problem.hip)
+double true_residual(Context& c, const Matvec& mv, const TT& b, const TT& x, double nb, double eps_x, int max_rank,
+                     TT& r, int& hint, const TT* Kf = nullptr, int p = 0, bool exact_norm = true);
 
 // faces with Dirichlet data (their end indices are cut from the cores)
 inline bool is_dirichlet(int kind) { return kind == TTIGA_BC_ZERO || kind == TTIGA_BC_CONSTANT; }
@@ -70,9 +77,13 @@ struct Problem {
   // relative tolerance of the assembly (factor compression, rounded K and F)
   double assembly_eps() const { return opts.assembly_eps > 0.0 ? opts.assembly_eps : opts.tt_eps; }
   bool compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, ttiga_assembly_stats& s);
+  bool cross_second_level(const GeoDev& gd, const SourceDev& sd, TT* fac, ttiga_assembly_stats& s,
+                          const std::vector<DBuf>& U, const std::vector<int>& k, const std::vector<int>& I,
+                          const DBuf& Id, const std::vector<DBuf>& Pinv, double* scale, uint64_t& rs);
   void solve_cg(ttiga_solve_stats& s);
   void solve_pcg(ttiga_solve_stats& s);
   void solve_mixed(ttiga_solve_stats& s);
+  void solve_amen(ttiga_solve_stats& s);
   PcgRun pcg_run(const TT& b, TT& x, double tol, double eps_floor, int max_iter, const LowpTT* Klp,
                  int& max_seen, bool report_exact);
   void build_tables();
