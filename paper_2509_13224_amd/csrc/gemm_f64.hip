@@ -351,14 +351,12 @@ GemmPlan gemm_plan(bool ta, bool tb, int M, int N, int K, int batch) {
     g = GemmPlan();
     break;
   }
-  // a 128-wide tile where the other dimension is long and this one fits in 65..128: the
-  // long operand is then streamed once instead of twice
-  if (M > 64 && M <= 128 && N > 128) g.bm = 128;
-  else if (N > 64 && N <= 128 && M > 128) g.bn = 128;
+  // otherwise 64 x 64 tiles (measured: the 128-wide tiles win only on a few shapes, which the
+  // table lists, and lose on most, where they halve the workgroups of a grid that cannot fill
+  // the device); long contractions on such grids are split (partials summed by a second kernel
+  // in split order), at most 256 rows of K per split, about 512 workgroups
   const long tiles = (long)((M + g.bm - 1) / g.bm) * ((N + g.bn - 1) / g.bn) * batch;
-  // long contractions on grids that cannot fill the device are split (partials summed by a
-  // second kernel in split order); at most 256 rows of K per split, about 512 workgroups
-  if (tiles < 256 && K >= 512) {
+  if (tiles < 256 && K >= 320) {
     long s = std::min<long>((K + 255) / 256, std::max<long>(1, 512 / tiles));
     int kchunk = (int)((K + s - 1) / s);
     kchunk = (kchunk + kGK - 1) / kGK * kGK;

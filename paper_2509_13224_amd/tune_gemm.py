@@ -11,10 +11,12 @@ once per hardware, by measurement:
    complex geometry at n = 128, a slice of the batched family) in a child process with
    TTIGA_GEMM_TRACE=1, which makes the library print the shape of every product;
 2. time: for the most frequent shape of every bucket, every tile with contraction chunks of
-   {whole K, 2048, 1024, 512, 256} (multiples of 32) through ttiga_gemm_f64 on random operands,
-   median of 7 timed runs after 2 warm-ups (HIP events on the context stream);
-3. choose: a bucket gets a table entry when its best plan beats the rule's plan by more than
-   5%; the entry stores the tile and the contraction chunk.
+   {whole K, 2048, 1024, 512, 256} (multiples of 32) through ttiga_gemm_f64 on random operands:
+   10 back-to-back launches between two HIP events on the context stream, median of 5 such
+   runs after a warm-up (single launches of 20 us products are too noisy to rank plans);
+3. choose: a bucket gets a table entry when its best plan differs from the rule's plan and
+   still beats it by more than 5% when the two are timed again, alternately, three times each;
+   the entry stores the tile and the contraction chunk.
 
 Usage (on the GPU): python paper_2509_13224_amd/tune_gemm.py [--out csrc/gemm_table.inc]
 The table is a build input: rebuild after writing it.
@@ -76,7 +78,7 @@ def trace_shapes():
     return shapes
 
 
-def time_plan(ctx, torch, shape, plan, reps=7):
+def time_plan(ctx, torch, shape, plan, reps=5, inner=10):
     ta, tb, M, N, K, batch = shape
     a_shape = (batch, K, M) if ta else (batch, M, K)
     b_shape = (batch, N, K) if tb else (batch, K, N)
@@ -85,28 +87,34 @@ def time_plan(ctx, torch, shape, plan, reps=7):
     C = torch.zeros((batch, M, N), dtype=torch.float64, device="cuda")
     args = dict(batch=batch, sA=a_shape[1] * a_shape[2], sB=b_shape[1] * b_shape[2], sC=M * N, plan=plan)
     times = []
-    for r in range(reps + 2):
+    for r in range(reps + 1):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        ctx.gemm_f64(ta, tb, M, N, K, 1.0, A, a_shape[2], B, b_shape[2], 0.0, C, N, **args)
+        for _ in range(inner):
+            ctx.gemm_f64(ta, tb, M, N, K, 1.0, A, a_shape[2], B, b_shape[2], 0.0, C, N, **args)
         e1.record()
         e1.synchronize()
-        if r >= 2:
-            times.append(e0.elapsed_time(e1))
+        if r >= 1:
+            times.append(e0.elapsed_time(e1) / inner)
     return sorted(times)[len(times) // 2]
+
+
+def confirmed_gain(ctx, torch, shape, rule, best, rounds=3):
+    """rule time / best time, each the sum of `rounds` alternate measurements."""
+    tr = tb = 0.0
+    for _ in range(rounds):
+        tr += time_plan(ctx, torch, shape, rule)
+        tb += time_plan(ctx, torch, shape, best)
+    return tr / tb
 
 
 def rule_plan(M, N, K, batch):
     """The library's rule (gemm_plan without a table entry) as (bm, bn, kchunk), for the
     comparison."""
     bm = bn = 64
-    if 64 < M <= 128 and N > 128:
-        bm = 128
-    elif 64 < N <= 128 and M > 128:
-        bn = 128
     tiles = ((M + bm - 1) // bm) * ((N + bn - 1) // bn) * batch
     kchunk = 0
-    if tiles < 256 and K >= 512:
+    if tiles < 256 and K >= 320:
         s = min((K + 255) // 256, max(1, 512 // tiles))
         kchunk = (K + s - 1) // s
         kchunk = (kchunk + 31) // 32 * 32
@@ -132,7 +140,8 @@ def main():
         ta, tb, M, N, K, batch = sh
         if M * N * batch * 8 > (1 << 31) or M * K * batch * 8 > (1 << 31) or K * N * batch * 8 > (1 << 31):
             continue
-        base = time_plan(ctx, torch, sh, rule_plan(M, N, K, batch))
+        rule = rule_plan(M, N, K, batch)
+        base = time_plan(ctx, torch, sh, rule)
         best, best_t = None, base
         for bm, bn in TILES:
             for ch in CHUNKS:
@@ -144,7 +153,11 @@ def main():
                 t = time_plan(ctx, torch, sh, (bm, bn, ch))
                 if t * GAIN < best_t:
                     best, best_t = (bm, bn, ch), t
-        if best:
+        if best and best != rule:
+            gain = confirmed_gain(ctx, torch, sh, rule, best)
+            if gain < GAIN:
+                print(f"{key} {sh}: {best} not confirmed ({gain:.3f})", file=sys.stderr)
+                continue
             entries.append((key, best, base, best_t))
             print(f"{key} {sh} x{cnt}: rule {base * 1e3:.1f} us -> {best} {best_t * 1e3:.1f} us", file=sys.stderr)
     with open(args.out, "w") as f:
