@@ -2,9 +2,9 @@
 """Throughput of TT-IGA solves on one MI355X.
 
 One solve is the whole hot path for one problem: TT assembly (basis tables, geometry
-factors on the Gauss grid streamed through the TT-SVD, TT cores of K and F, summation
-with rounding, boundary reduction), the preconditioned TT-CG solve, and the solution
-cores resident on the device.  The workload is the plain-vs-mixed annulus case:
+factors on the Gauss grid compressed by cross approximation, TT cores of K and F, summation
+with rounding, boundary reduction), the TT solve (the paper's AMEn by default, `--solver cg`
+for the preconditioned TT-CG), and the solution cores resident on the device.  The workload is the plain-vs-mixed annulus case:
 quarter annulus (radii 1..2, 90 degrees) extruded over z in [0, 1], degree-3 B-splines
 with 256 basis functions per direction (16.7M DOF), f from 8 seeded Fourier modes, TT
 tolerance 1e-6.
@@ -12,10 +12,12 @@ tolerance 1e-6.
 One timed step is a batch of --batch such problems (Fourier seeds seed0 + b) run on
 --lanes concurrent lanes of the library's executor (FP64 path); `value` is solves per
 second over the timed steps, counting only solves within 1e-6 (relative, coefficient
-2-norm) of an FP64 reference solve of the same problem at eps/10, tol/10.  Problem
+2-norm) of an FP64 reference solve of the same problem at eps/10, tol/10 by the other method
+(preconditioned TT-CG references for AMEn solves).  Problem
 descriptions (a few KB each) are host inputs; everything else happens on the device.
 
-Beside it the JSON line reports: the single-solve latency of the plain FP64 path with
+Beside it the JSON line reports: the same batches and single solve with the other solver
+(`solver_comparison`); the single-solve latency of the plain FP64 path with
 the roofline of its dominant kernel class (HIP events around every launch of that
 class, on the library's stream) and the TT-matvec rate; the mixed-precision (FP32
 operator, FP64 refinement) batch; the batched family (256 requests of mixed sizes and
@@ -358,6 +360,8 @@ def main():
     ap.add_argument("--cpu-slabs", type=int, default=8)
     ap.add_argument("--cpu-n", type=int, default=32, help="basis functions per direction of the oracle sample")
     ap.add_argument("--workspace-gib", type=float, default=200.0)
+    ap.add_argument("--solver", choices=("amen", "cg"), default="amen",
+                    help="TT solve of the timed problems: the paper's AMEn, or preconditioned TT-CG")
     ap.add_argument("--single-only", action="store_true",
                     help="only the single-solve phase (value = its solve rate): the run whose kernel "
                          "averages a rocprofv3 trace can be compared with the roofline line")
@@ -413,12 +417,22 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = ttiga.Context(device=0, workspace_bytes=int(args.workspace_gib * 2**30))
-    base = W.c2_problem(n=args.n)
+    solver = ttiga.TTIGA_SOLVER_AMEN if args.solver == "amen" else ttiga.TTIGA_SOLVER_CG
+    other = ttiga.TTIGA_SOLVER_CG if solver == ttiga.TTIGA_SOLVER_AMEN else ttiga.TTIGA_SOLVER_AMEN
+    solver_name = {ttiga.TTIGA_SOLVER_AMEN: "amen", ttiga.TTIGA_SOLVER_CG: "tt-cg (preconditioned)"}
+
+    def with_solver(pr, which):
+        pr.options.solver = which
+        return pr
+
+    base = with_solver(W.c2_problem(n=args.n), solver)
     eps, tol = base.options.tt_eps, base.options.rel_res_tol
     seeds = [W.configs.C2_SEED + b for b in range(args.batch)]
-    plain = [W.c2_problem(n=args.n, seed=s) for s in seeds]
+    plain = [with_solver(W.c2_problem(n=args.n, seed=s), solver) for s in seeds]
+    plain_other = [with_solver(W.c2_problem(n=args.n, seed=s), other) for s in seeds]
     mixed = [W.c2_problem(n=args.n, seed=s, precision=PREC_FP32) for s in seeds]
-    refs_pr = [W.c2_problem(n=args.n, seed=s, eps=eps / 10, tol=tol / 10) for s in seeds]
+    # references by the other method at eps/10, tol/10 (TT-CG for AMEn solves)
+    refs_pr = [with_solver(W.c2_problem(n=args.n, seed=s, eps=eps / 10, tol=tol / 10), other) for s in seeds]
 
     if args.serve_only:
         sv = serving_phase(ctx, args.serve, args.lanes)
@@ -520,6 +534,23 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
+    # the same steps with the other solver, for the comparison
+    log(f"batched FP64 steps, {solver_name[other]}")
+    ctx.solve_batch(plain_other, lanes=args.lanes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs_other = [ctx.solve_batch(plain_other, lanes=args.lanes) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed_other = time.perf_counter() - t0
+    lat_other = []
+    for _ in range(2):
+        h = ctx.problem_create(plain_other[0], precond=1)
+        t0 = time.perf_counter()
+        h.assemble()
+        st_other = h.solve()
+        lat_other.append(time.perf_counter() - t0)
+        h.close()
+
     # 3. mixed precision batch (FP32 operator inside FP64 refinement)
     log("mixed FP32 batch")
     t0 = time.perf_counter()
@@ -534,6 +565,10 @@ def main():
     passed = sum(e <= 1e-6 for run in errs for e in run)
     mixed_err = [tt_rel_diff(u, refs[b]) if u is not None else float("inf") for b, (_, u) in enumerate(mixed_out)]
     single_err = tt_rel_diff(u1, refs[0])
+    # the other solver's solves against the same references (by their own method, at eps/10)
+    errs_other = [[tt_rel_diff(u, refs[b]) if u is not None else float("inf") for b, (_, u) in enumerate(run)]
+                  for run in runs_other]
+    passed_other = sum(e <= 1e-6 for run in errs_other for e in run)
 
     out = {
         "metric": "solves/s at 1e-6 rel-L2 (plain vs batched/mixed); TT-matvec TFLOP/s; p99 lat",
@@ -550,18 +585,29 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded Fourier sources, exact NURBS annulus)",
         "config": {"workload": (f"quarter annulus r 1..2, 90 deg, z 0..1; degree 3, n={args.n}/dir "
-                                f"({args.n ** 3} DOF); f = 8 seeded Fourier modes; TT eps {eps}; FP64 with "
-                                f"separable preconditioner; step = {args.batch} such problems "
+                                f"({args.n ** 3} DOF); f = 8 seeded Fourier modes; TT eps {eps}; FP64, "
+                                f"{solver_name[solver]} solve; step = {args.batch} such problems "
                                 f"(seeds {seeds[0]}..{seeds[-1]}) on {args.lanes} executor lanes"),
-                   "precision": "fp64", "tt_eps": eps, "rel_err_tol": tol, "batch": args.batch,
-                   "lanes": args.lanes},
+                   "precision": "fp64", "solver": args.solver, "tt_eps": eps, "rel_err_tol": tol,
+                   "batch": args.batch, "lanes": args.lanes},
         "roofline": roof,
         "accuracy": {"rel_err_vs_ref_max": max(max(r) for r in errs), "passed": passed,
                      "solves": args.batch * args.steps,
-                     "reference": f"FP64 solve of the same problem at eps {eps / 10:g}, tol {tol / 10:g}"},
+                     "reference": (f"FP64 {solver_name[other]} solve of the same problem at eps {eps / 10:g}, "
+                                   f"tol {tol / 10:g}")},
+        "solver_comparison": {
+            solver_name[solver]: {"batched_solves_per_s": passed / elapsed,
+                                  "single_latency_ms": 1e3 * sum(lat) / len(lat)},
+            solver_name[other]: {"batched_solves_per_s": passed_other / elapsed_other,
+                                 "batched_passed": passed_other,
+                                 "rel_err_vs_ref_max": max(max(r) for r in errs_other),
+                                 "single_latency_ms": 1e3 * sum(lat_other) / len(lat_other),
+                                 "iterations": st_other["iterations"], "rank_u": st_other["rank_u"],
+                                 "note": "accuracy against the references of its own method at eps/10"}},
         "plain_single": {"solves_per_s": 1.0 / (sum(lat) / len(lat)), "latency_ms": 1e3 * sum(lat) / len(lat),
-                         "rel_err": single_err, "iterations": st1["iterations"], "rank_u": st1["rank_u"],
-                         "max_rank_seen": st1["max_rank_seen"]},
+                         "rel_err": single_err, "iterations": st1["iterations"],
+                         "local_iterations": st1.get("local_iterations"), "rank_u": st1["rank_u"],
+                         "max_rank_seen": st1["max_rank_seen"], "solver": args.solver},
         "mixed_fp32": {"solves_per_s": sum(e <= 1e-6 for e in mixed_err) / mixed_s,
                        "rel_err_vs_ref_max": max(mixed_err),
                        "refine_steps": [r["refine_steps"] for r, _ in mixed_out],
@@ -603,7 +649,7 @@ def main():
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_slabs, args.n)
         # the GPU's rate on the same problem as the oracle sample (single FP64 solve, warm context)
-        small = W.c2_problem(n=args.cpu_n)
+        small = with_solver(W.c2_problem(n=args.cpu_n), solver)
         ts = []
         for _ in range(3):
             h = ctx.problem_create(small, precond=1)

@@ -16,7 +16,8 @@
  * sampled at Gauss points, compressed to TT with tolerance eps and contracted
  * against 1-D B-spline matrices; the nine K_ij are summed with TT-rounding
  * after each addition.  Boundary conditions (Section 4.3) reduce the system to
- * the interior unknowns.  The TT solve is a preconditioned truncated TT-CG.
+ * the interior unknowns.  The TT solve is the paper's AMEn (Section 4.1.2) or a
+ * preconditioned truncated TT-CG (options.solver).
  *
  * Conventions
  *   - Flattened multi-index: (i0 * n1 + i1) * n2 + i2 (first direction slowest),
@@ -153,7 +154,16 @@ typedef struct {
                          non-separable geometry can move by far more than tt_eps when the
                          compressed operator drops a small singular value, so callers that
                          need the solution to about tt_eps set this well below it. */
+  int solver;         /* TTIGA_SOLVER_CG (0): truncated TT-CG, preconditioned when precond = 1;
+                         TTIGA_SOLVER_AMEN (1): the AMEn solve of Section 4.1.2 (alternating
+                         local solves of one core, enrichment by the residual), FP64 only, with
+                         local systems preconditioned by the projection of the separable
+                         preconditioner whatever precond says; it stops on the same test as the
+                         preconditioned TT-CG, ||P^-1 (F_I - K_II u)|| <= tol ||u|| */
 } ttiga_options;
+
+#define TTIGA_SOLVER_CG 0
+#define TTIGA_SOLVER_AMEN 1
 
 #define TTIGA_COMPRESS_AUTO 0
 #define TTIGA_COMPRESS_SVD 1
@@ -184,6 +194,7 @@ typedef struct {
   double precond_setup_ms; /* preconditioner set-up time within time_ms */
   double time_ms;
   int refine_steps;  /* mixed precision: FP64 refinement steps (iterations counts the inner ones) */
+  int local_iterations; /* AMEn: CG iterations of all local solves (iterations counts half-sweeps) */
 } ttiga_solve_stats;
 
 /* Plain views of caller-owned device TT data (used by the standalone ops). */
@@ -232,13 +243,15 @@ int ttiga_problem_destroy(ttiga_problem* prob);
 int ttiga_assemble(ttiga_problem* prob, ttiga_assembly_stats* stats);
 
 /* TT solve of the reduced system K_II u_I = F_I - K_IB u_B (Section 4.3) with the
- * assembled TT operator and right-hand side; the paper solves it in TT format with
- * AMEn (Section 4.1.2), this library by truncated TT-CG (precond = 0) or flexible
+ * assembled TT operator and right-hand side.  options.solver = TTIGA_SOLVER_AMEN runs the
+ * paper's solver (Section 4.1.2: AMEn, alternating local solves of one core with residual
+ * enrichment; FP64); TTIGA_SOLVER_CG runs truncated TT-CG (precond = 0) or flexible
  * preconditioned TT-CG (precond = 1), optionally inside FP64 iterative refinement
  * (precision FP32/BF16).  The solution TT stays on the device, owned by the problem.
- * Errors: E_STATE before ttiga_assemble; E_RANKCAP when a rounded TT needs more than
- * max_rank; E_NOTCONV when the tolerance is not met in max_iter iterations (the
- * solution and stats are still valid); E_HIP / E_OOM on device failures. */
+ * Errors: E_STATE before ttiga_assemble; E_ARG for AMEn with a precision other than FP64;
+ * E_RANKCAP when a rounded TT needs more than max_rank; E_NOTCONV when the tolerance is
+ * not met in max_iter iterations (AMEn: half-sweeps, at most 60) (the solution and stats
+ * are still valid); E_HIP / E_OOM on device failures. */
 int ttiga_solve(ttiga_problem* prob, ttiga_solve_stats* stats);
 
 /* Ranks and mode sizes of the interior solution TT u_I (Section 4.1.1 format: ranks

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libttiga.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["gemm_f64.hip", "kernels_linalg.hip", "tt_ops.hip", "tt_matvec_round.hip", "kernels_iga.hip", "precond.hip", "problem.hip", "engine.hip", "errors.hip", "noalloc.hip", "capi.hip"]
+SOURCES = ["gemm_f64.hip", "kernels_linalg.hip", "tt_ops.hip", "tt_matvec_round.hip", "kernels_iga.hip", "precond.hip", "problem.hip", "engine.hip", "errors.hip", "noalloc.hip", "amen.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,761 @@
+// AMEn solve of the reduced system K_II u = rhs (Section 4.1.2: the alternating minimal
+// energy method, which updates one TT core at a time by a local system and enriches the core
+// with a low-rank approximation of the residual so that the ranks adapt).
+//
+// For the three cores of this library a sweep solves core k of u with the other two fixed:
+// with u's cores left of k left-orthonormal and right of k right-orthonormal, the Galerkin
+// projection of K onto that subspace is the local operator
+//   A_k = Phi_L (x) K_k (x) Phi_R     (size r_{k-1} n_k r_k, SPD),
+// whose frames Phi_L, Phi_R contract K's cores with u's on each side, and the right-hand side
+// projects the same way.  After the local solve the core is truncated (SVD) and enriched with
+// kick columns taken from the projected residual; a second train z of small rank keeps the
+// residual's projection basis and is updated by the same local projections (the residual
+// approximation of AMEn).  The core then moves on to the next one.  Sweeps alternate
+// direction; the right-to-left half runs as a left-to-right half over the reversed trains
+// (cores in reverse order, rank indices swapped), so only one direction is coded.
+//
+// Local solver: preconditioned CG.  The preconditioner is the Galerkin projection of the
+// separable operator P = sum_d c_d (a_d in mode d, m_d elsewhere) of the TT-CG path onto the
+// same subspace: its frames have two terms per side (the part with one stiffness factor and
+// the pure mass part), each pair is diagonalised by a generalised eigenproblem, and mode k by
+// the 1-D eigenbasis, so P_k^-1 is three small transforms, a diagonal scaling and their
+// transposes.  A projection keeps the spectral bounds of P^-1 K, so the local iteration counts
+// are those of the global preconditioned CG.
+//
+// Stopping: the core updates are measured as ||P_k^-1 (b_k - A_k x_old)|| / ||x_new|| (the
+// preconditioned local residual, an error estimate like the TT-CG stopping test); when a whole
+// sweep stays below tol the global test ||P^-1 (rhs - K u)|| <= tol ||u|| (the TT-CG path's) is
+// evaluated, and sweeps continue while it fails.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "problem.hpp"
+
+namespace ttiga {
+
+namespace {
+
+constexpr int kKick = 6;  // rank of the residual train z and of the enrichment per step
+
+// out = in with axes reordered: output axis a is input axis perm[a] (input dims d0, d1, d2)
+__global__ void k_permute3(int d0, int d1, int d2, int p0, int p1, int p2, const double* __restrict__ in,
+                           double* __restrict__ out) {
+  const int dims[3] = {d0, d1, d2};
+  const int o1n = dims[p1], o2n = dims[p2];
+  const long total = (long)d0 * d1 * d2;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int o2 = (int)(e % o2n);
+    const long t = e / o2n;
+    const int o1 = (int)(t % o1n);
+    const int o0 = (int)(t / o1n);
+    int idx[3];
+    idx[p0] = o0;
+    idx[p1] = o1;
+    idx[p2] = o2;
+    out[e] = in[((long)idx[0] * d1 + idx[1]) * d2 + idx[2]];
+  }
+}
+
+// Core of the separable preconditioner in banded TT form, [n][2p+1][ra0][ra1]: first core
+// (c a, m), middle core ((m, 0), (c a, m)), last core (m; c a).
+__global__ void k_pcore(long nb, int pos, const double* __restrict__ m, const double* __restrict__ a, double cc,
+                        double* __restrict__ out) {
+  const int ra0 = pos == 0 ? 1 : 2, ra1 = pos == 2 ? 1 : 2;
+  const long total = nb * ra0 * ra1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int ab = (int)(e % (ra0 * ra1));
+    const long it = e / (ra0 * ra1);
+    const int al = ab / ra1, be = ab % ra1;
+    double v = 0.0;
+    if (pos == 0)
+      v = be == 0 ? cc * a[it] : m[it];
+    else if (pos == 2)
+      v = al == 0 ? m[it] : cc * a[it];
+    else if (al == be)
+      v = m[it];
+    else if (al == 1 && be == 0)
+      v = cc * a[it];
+    out[e] = v;
+  }
+}
+
+struct DotArgs {
+  const double* x[4];
+  const double* y[4];
+  int nv;
+};
+
+constexpr int kDotBlocks = 512;
+
+// part[b][v] = block b's share of x_v . y_v (fixed grid: the sums do not depend on timing)
+template <int NV>
+__global__ void __launch_bounds__(256) k_dots_partial(long n, DotArgs a, double* __restrict__ part) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256L)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] += a.x[v][e] * a.y[v][e];
+  __shared__ double sh[4][256];
+  for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = s[v];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_dots_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[4][256];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += 256)
+    for (int v = 0; v < 4; ++v) s[v] += part[b * 4 + v];
+  for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = s[v];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// x += a p, r -= a q
+__global__ void k_cg_update(long n, double a, double* __restrict__ x, const double* __restrict__ p,
+                            double* __restrict__ r, const double* __restrict__ q) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    x[e] += a * p[e];
+    r[e] -= a * q[e];
+  }
+}
+
+// p = z + b p
+__global__ void k_xpby(long n, const double* __restrict__ z, double b, double* __restrict__ p) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    p[e] = z[e] + b * p[e];
+}
+
+// y = a - y
+__global__ void k_rsub(long n, const double* __restrict__ a, double* __restrict__ y) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    y[e] = a[e] - y[e];
+}
+
+// t[a][i][b] /= mu[a] + c lam[i] + nu[b] (the transformed projected preconditioner), with a
+// floor relative to the largest diagonal entry
+__global__ void k_diag_scale(int r0, int n, int r1, const double* __restrict__ mu, double cc,
+                             const double* __restrict__ lam, const double* __restrict__ nu, double floor_,
+                             double* __restrict__ t) {
+  const long total = (long)r0 * n * r1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(e % r1);
+    const long q = e / r1;
+    const int i = (int)(q % n);
+    const int a = (int)(q / n);
+    const double d = mu[a] + cc * lam[i] + nu[b];
+    t[e] /= fmax(d, floor_);
+  }
+}
+
+// out (m x (c1 + c2)) = [A | first c2 columns of B] (row strides lda, ldb)
+__global__ void k_concat_cols(long m, int c1, int c2, const double* __restrict__ A, int lda,
+                              const double* __restrict__ B, int ldb, double* __restrict__ out) {
+  const int w = c1 + c2;
+  const long total = m * w;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e % w);
+    const long i = e / w;
+    out[e] = j < c1 ? A[i * lda + j] : B[i * ldb + (j - c1)];
+  }
+}
+
+// out[j][b] = s[j] V[b][j] (the factor S V^T of a truncated SVD, first k columns of V)
+__global__ void k_svt(int k, int c, const double* __restrict__ s, const double* __restrict__ V,
+                      double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * c) return;
+  const int j = e / c, b = e % c;
+  out[e] = s[j] * V[(long)b * c + j];
+}
+
+// G = (G + G^T) / 2 for an r x r matrix, in place (upper triangle read, both written)
+__global__ void k_symmetrize(int r, double* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * r) return;
+  const int i = e / r, j = e % r;
+  if (i < j) {
+    const double v = 0.5 * (G[(long)i * r + j] + G[(long)j * r + i]);
+    G[(long)i * r + j] = v;
+    G[(long)j * r + i] = v;
+  }
+}
+
+void permute3(Context& c, const double* in, int d0, int d1, int d2, int p0, int p1, int p2, double* out) {
+  const long total = (long)d0 * d1 * d2;
+  if (!total) return;
+  hipLaunchKernelGGL(k_permute3, dim3(grid_for(total)), dim3(256), 0, c.stream, d0, d1, d2, p0, p1, p2, in, out);
+  TTIGA_HIP(hipGetLastError());
+}
+
+// A frame [ry][ra][rx] (right-hand-side frames: [ry][s][1]).
+struct Frame {
+  DBuf d;
+  int ry = 0, ra = 0, rx = 0;
+};
+
+struct FrameSet {
+  Frame L[4], R[4];  // L[k]: cores 0..k-1; R[k]: cores k..2
+  void reverse() {
+    for (int j = 0; j < 4; ++j) std::swap(L[j], R[3 - j]);
+  }
+};
+
+// a banded TT-matrix core in the layout of the local contraction: [n][2p+1][ra0][ra1]
+struct BandCore {
+  DBuf perm;
+  int ra0 = 0, n = 0, ra1 = 0;
+};
+
+struct Orientation {
+  BandCore A[3], P[3];
+  DBuf B[3];
+  int s[4];
+  const double* V[3];
+  const double* lam[3];
+  double cc[3];
+};
+
+}  // namespace
+
+class Amen {
+ public:
+  Amen(Problem& pr) : P(pr), c(*pr.ctx), p(pr.p), band(2 * pr.p + 1) {}
+  void run(ttiga_solve_stats& s);
+
+ private:
+  Problem& P;
+  Context& c;
+  int p, band;
+  Orientation O[2];
+  int o = 0;
+  TT x, z;
+  FrameSet fk, fp, fz, gb, gz;
+  long local_its = 0;
+  int max_seen = 0;
+
+  void setup();
+  void one(Frame& f);
+  void reverse();
+  // T2 [n][ry][rx1][ra1] = sum_{a', alpha, t} F[c][alpha][a'] A[alpha][i][t][beta] X[a'][i+t-p][b']
+  void contract(const Frame& F, const BandCore& A, const double* X, int rx1, DBuf& T2);
+  void apply_local(const Frame& FL, const BandCore& A, const Frame& FR, const double* X, double* Y);
+  void frame_next(const Frame& F, const BandCore& A, const double* Y, int ry1, const double* X, int rx1,
+                  Frame& out);
+  void rhs_local(const Frame& GL, const double* B, int s0, int n, int s1, const Frame& GR, double* Y);
+  void rhs_frame_next(const Frame& G, const double* B, int s0, int n, int s1, const double* Y, int ry1,
+                      Frame& out);
+  void pencil(const double* GA, const double* GM, int r, DBuf& W, DBuf& ev);
+  double solve_core(int k, double tol_loc);
+  void step(int k, double eps_x, bool solve_mode);
+  void frames_at(int k);
+  void dots(long n, int nv, const double* const* xs, const double* const* ys, double* out);
+};
+
+void Amen::one(Frame& f) {
+  f.d = DBuf(c.alloc, sizeof(double));
+  fill(c, f.d.d(), 1, 1.0);
+  f.ry = f.ra = f.rx = 1;
+}
+
+void Amen::dots(long n, int nv, const double* const* xs, const double* const* ys, double* out) {
+  DotArgs a{};
+  a.nv = nv;
+  for (int v = 0; v < 4; ++v) {
+    a.x[v] = v < nv ? xs[v] : xs[0];
+    a.y[v] = v < nv ? ys[v] : ys[0];
+  }
+  DBuf part(c.alloc, sizeof(double) * 4 * kDotBlocks);
+  double* hd = c.host_device(4);
+  if (nv == 1)
+    hipLaunchKernelGGL(k_dots_partial<1>, dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, part.d());
+  else if (nv == 2)
+    hipLaunchKernelGGL(k_dots_partial<2>, dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, part.d());
+  else if (nv == 3)
+    hipLaunchKernelGGL(k_dots_partial<3>, dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, part.d());
+  else
+    hipLaunchKernelGGL(k_dots_partial<4>, dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, part.d());
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, c.stream, kDotBlocks, part.d(), hd);
+  TTIGA_HIP(hipGetLastError());
+  c.sync();
+  for (int v = 0; v < nv; ++v) out[v] = c.host_scratch[v];
+}
+
+void Amen::contract(const Frame& F, const BandCore& A, const double* X, int rx1, DBuf& T2) {
+  const int ry = F.ry, ra0 = F.ra, rx0 = F.rx, n = A.n, ra1 = A.ra1;
+  TTIGA_CHECK(A.ra0 == ra0, TTIGA_E_ARG, "AMEn frame and operator ranks differ");
+  DBuf Fp(c.alloc, sizeof(double) * ry * ra0 * rx0);
+  permute3(c, F.d.d(), ry, ra0, rx0, 1, 0, 2, Fp.d());  // [ra0][ry][rx0]
+  const long slab = (long)ra0 * ry * rx1;
+  DBuf T1(c.alloc, sizeof(double) * slab * (n + 2 * p));
+  fill(c, T1.d(), (size_t)slab * p, 0.0);
+  fill(c, T1.d() + slab * (n + p), (size_t)slab * p, 0.0);
+  // T1[j + p][alpha][c][b'] = sum_a' F[c][alpha][a'] X[a'][j][b']  (batched over j)
+  gemm(c, false, false, ra0 * ry, rx1, rx0, 1.0, Fp.d(), rx0, 0, X, (long)n * rx1, rx1, 0.0, T1.d() + slab * p, rx1,
+       slab, n);
+  // T2[i][(c, b')][beta] = sum_{(t, alpha)} T1[i + t][alpha][(c, b')] A[i][t][alpha][beta]
+  T2 = DBuf(c.alloc, sizeof(double) * (size_t)n * ry * rx1 * ra1);
+  gemm(c, true, false, ry * rx1, ra1, band * ra0, 1.0, T1.d(), (long)ry * rx1, slab, A.perm.d(), ra1,
+       (long)band * ra0 * ra1, 0.0, T2.d(), ra1, (long)ry * rx1 * ra1, n);
+}
+
+void Amen::apply_local(const Frame& FL, const BandCore& A, const Frame& FR, const double* X, double* Y) {
+  const int ry0 = FL.ry, ra1 = FR.ra, rx1 = FR.rx, ry1 = FR.ry, n = A.n;
+  TTIGA_CHECK(A.ra1 == ra1, TTIGA_E_ARG, "AMEn frame and operator ranks differ");
+  DBuf T2;
+  contract(FL, A, X, rx1, T2);
+  DBuf FRp(c.alloc, sizeof(double) * ry1 * ra1 * rx1);
+  permute3(c, FR.d.d(), ry1, ra1, rx1, 2, 1, 0, FRp.d());  // [rx1][ra1][ry1]
+  // Y[c][i][d] = sum_{(b', beta)} T2[i][c][(b', beta)] FRp[(b', beta)][d]  (batched over c)
+  gemm(c, false, false, n, ry1, rx1 * ra1, 1.0, T2.d(), (long)ry0 * rx1 * ra1, (long)rx1 * ra1, FRp.d(), ry1, 0, 0.0,
+       Y, ry1, (long)n * ry1, ry0);
+}
+
+void Amen::frame_next(const Frame& F, const BandCore& A, const double* Y, int ry1, const double* X, int rx1,
+                      Frame& out) {
+  const int ry0 = F.ry, n = A.n, ra1 = A.ra1;
+  DBuf T2;
+  contract(F, A, X, rx1, T2);
+  DBuf Yp(c.alloc, sizeof(double) * (size_t)ry0 * n * ry1), Fq(c.alloc, sizeof(double) * ry1 * rx1 * ra1);
+  permute3(c, Y, ry0, n, ry1, 1, 0, 2, Yp.d());  // [n][ry0][ry1]
+  // Fq[d][(b', beta)] = sum_{(i, c)} Y[c][i][d] T2[i][c][(b', beta)]
+  gemm(c, true, false, ry1, rx1 * ra1, n * ry0, 1.0, Yp.d(), ry1, 0, T2.d(), (long)rx1 * ra1, 0, 0.0, Fq.d(),
+       (long)rx1 * ra1, 0);
+  out.d = DBuf(c.alloc, sizeof(double) * ry1 * ra1 * rx1);
+  permute3(c, Fq.d(), ry1, rx1, ra1, 0, 2, 1, out.d.d());
+  out.ry = ry1;
+  out.ra = ra1;
+  out.rx = rx1;
+}
+
+void Amen::rhs_local(const Frame& GL, const double* B, int s0, int n, int s1, const Frame& GR, double* Y) {
+  const int ry0 = GL.ry, ry1 = GR.ry;
+  DBuf T(c.alloc, sizeof(double) * (size_t)ry0 * n * s1);
+  gemm(c, false, false, ry0, n * s1, s0, 1.0, GL.d.d(), s0, 0, B, (long)n * s1, 0, 0.0, T.d(), (long)n * s1, 0);
+  gemm(c, false, true, ry0 * n, ry1, s1, 1.0, T.d(), s1, 0, GR.d.d(), s1, 0, 0.0, Y, ry1, 0);
+}
+
+void Amen::rhs_frame_next(const Frame& G, const double* B, int s0, int n, int s1, const double* Y, int ry1,
+                          Frame& out) {
+  const int ry0 = G.ry;
+  DBuf T(c.alloc, sizeof(double) * (size_t)ry0 * n * s1);
+  gemm(c, false, false, ry0, n * s1, s0, 1.0, G.d.d(), s0, 0, B, (long)n * s1, 0, 0.0, T.d(), (long)n * s1, 0);
+  out.d = DBuf(c.alloc, sizeof(double) * ry1 * s1);
+  gemm(c, true, false, ry1, s1, ry0 * n, 1.0, Y, ry1, 0, T.d(), s1, 0, 0.0, out.d.d(), s1, 0);
+  out.ry = ry1;
+  out.ra = s1;
+  out.rx = 1;
+}
+
+// W (r x r) and ev with W^T GM W = I, W^T GA W = diag(ev) (GM positive definite)
+void Amen::pencil(const double* GA, const double* GM, int r, DBuf& W, DBuf& ev) {
+  DBuf A(c.alloc, sizeof(double) * r * r), M(c.alloc, sizeof(double) * r * r);
+  copy(c, A.d(), GA, (size_t)r * r);
+  copy(c, M.d(), GM, (size_t)r * r);
+  const int blocks = (r * r + 255) / 256;
+  hipLaunchKernelGGL(k_symmetrize, dim3(blocks), dim3(256), 0, c.stream, r, A.d());
+  hipLaunchKernelGGL(k_symmetrize, dim3(blocks), dim3(256), 0, c.stream, r, M.d());
+  TTIGA_HIP(hipGetLastError());
+  DBuf Rc(c.alloc, sizeof(double) * r * r), Ri(c.alloc, sizeof(double) * r * r);
+  TTIGA_CHECK(cholesky_inverse(c, M.d(), r, Rc.d(), Ri.d()), TTIGA_E_NOTCONV,
+              "AMEn: projected mass frame is not positive definite");
+  DBuf T(c.alloc, sizeof(double) * r * r), S(c.alloc, sizeof(double) * r * r), U(c.alloc, sizeof(double) * r * r);
+  gemm(c, false, false, r, r, r, 1.0, A.d(), r, 0, Ri.d(), r, 0, 0.0, T.d(), r, 0);
+  gemm(c, true, false, r, r, r, 1.0, Ri.d(), r, 0, T.d(), r, 0, 0.0, S.d(), r, 0);
+  hipLaunchKernelGGL(k_symmetrize, dim3(blocks), dim3(256), 0, c.stream, r, S.d());
+  TTIGA_HIP(hipGetLastError());
+  ev = DBuf(c.alloc, sizeof(double) * r);
+  svd_small(c, S.d(), false, r, r, r, U.d(), ev.d(), nullptr, "amen_pencil");
+  W = DBuf(c.alloc, sizeof(double) * r * r);
+  gemm(c, false, false, r, r, r, 1.0, Ri.d(), r, 0, U.d(), r, 0, 0.0, W.d(), r, 0);
+}
+
+void Amen::setup() {
+  const TT& K = P.KII;
+  const TT& b = P.rhs;
+  int ni[3];
+  for (int d = 0; d < 3; ++d) ni[d] = P.hi[d] - P.lo[d];
+  // 1-D interior mass and stiffness matrices (banded [n][2p+1]) of every direction
+  DBuf mi[3], ai[3];
+  for (int d = 0; d < 3; ++d) {
+    const int n = P.n[d], m = ni[d];
+    DBuf ones(c.alloc, sizeof(double) * P.Q[d]);
+    fill(c, ones.d(), P.Q[d], 1.0);
+    DBuf mb(c.alloc, sizeof(double) * n * band), ab(c.alloc, sizeof(double) * n * band);
+    launch_assemble_band(c, n, p, P.g, 1, 1, ones.d(), P.tab_w[d].d(), P.tab_B[d].d(), P.tab_B[d].d(), mb.d());
+    launch_assemble_band(c, n, p, P.g, 1, 1, ones.d(), P.tab_w[d].d(), P.tab_D[d].d(), P.tab_D[d].d(), ab.d());
+    mi[d] = DBuf(c.alloc, sizeof(double) * m * band);
+    ai[d] = DBuf(c.alloc, sizeof(double) * m * band);
+    launch_slice_band(c, n, p, P.lo[d], m, 1, 1, mb.d(), mi[d].d());
+    launch_slice_band(c, n, p, P.lo[d], m, 1, 1, ab.d(), ai[d].d());
+    c.sync();  // `ones`, mb, ab are released at the end of the iteration
+  }
+  for (int oo = 0; oo < 2; ++oo) {
+    Orientation& Q = O[oo];
+    for (int k = 0; k < 3; ++k) {
+      const int src = oo == 0 ? k : 2 - k;  // original core (and direction) at position k
+      const int R0 = K.r[src], R1 = K.r[src + 1], n = K.n[src] / band;
+      BandCore& A = Q.A[k];
+      A.n = n;
+      A.ra0 = oo == 0 ? R0 : R1;
+      A.ra1 = oo == 0 ? R1 : R0;
+      A.perm = DBuf(c.alloc, sizeof(double) * (size_t)R0 * n * band * R1);
+      // [alpha][(i t)][beta] -> [(i t)][alpha][beta], reversed: [(i t)][beta][alpha]
+      if (oo == 0)
+        permute3(c, K.c[src].d(), R0, n * band, R1, 1, 0, 2, A.perm.d());
+      else
+        permute3(c, K.c[src].d(), R0, n * band, R1, 1, 2, 0, A.perm.d());
+      BandCore& Pc = Q.P[k];
+      Pc.n = n;
+      Pc.ra0 = k == 0 ? 1 : 2;
+      Pc.ra1 = k == 2 ? 1 : 2;
+      Pc.perm = DBuf(c.alloc, sizeof(double) * (size_t)n * band * Pc.ra0 * Pc.ra1);
+      const long nb = (long)n * band;
+      hipLaunchKernelGGL(k_pcore, dim3(grid_for(nb * 4)), dim3(256), 0, c.stream, nb, k, mi[src].d(), ai[src].d(),
+                         P.pc.c[src], Pc.perm.d());
+      TTIGA_HIP(hipGetLastError());
+      const int s0 = b.r[src], s1 = b.r[src + 1];
+      Q.B[k] = DBuf(c.alloc, sizeof(double) * (size_t)s0 * n * s1);
+      if (oo == 0)
+        copy(c, Q.B[k].d(), b.c[src].d(), (size_t)s0 * n * s1);
+      else
+        permute3(c, b.c[src].d(), s0, n, s1, 2, 1, 0, Q.B[k].d());
+      Q.V[k] = P.pc.eb[src]->V.d();
+      Q.lam[k] = P.pc.eb[src]->lam.d();
+      Q.cc[k] = P.pc.c[src];
+    }
+    for (int k = 0; k < 4; ++k) Q.s[k] = oo == 0 ? b.r[k] : b.r[3 - k];
+  }
+  c.sync();
+}
+
+// reverse the trains (cores in reverse order, rank indices swapped) and the frames
+void Amen::reverse() {
+  for (TT* t : {&x, &z}) {
+    TT r;
+    const int rr[4] = {t->r[3], t->r[2], t->r[1], t->r[0]};
+    const int nn[3] = {t->n[2], t->n[1], t->n[0]};
+    r.alloc(c, nn, rr);
+    for (int k = 0; k < 3; ++k) permute3(c, t->c[2 - k].d(), t->r[2 - k], t->n[2 - k], t->r[3 - k], 2, 1, 0, r.c[k].d());
+    *t = std::move(r);
+  }
+  for (FrameSet* f : {&fk, &fp, &fz, &gb, &gz}) f->reverse();
+  o ^= 1;
+}
+
+// left frames at bond k + 1 from cores k of x and z
+void Amen::frames_at(int k) {
+  const Orientation& Q = O[o];
+  const int rx1 = x.r[k + 1], rz1 = z.r[k + 1], n = x.n[k];
+  frame_next(fk.L[k], Q.A[k], x.c[k].d(), rx1, x.c[k].d(), rx1, fk.L[k + 1]);
+  frame_next(fp.L[k], Q.P[k], x.c[k].d(), rx1, x.c[k].d(), rx1, fp.L[k + 1]);
+  frame_next(fz.L[k], Q.A[k], z.c[k].d(), rz1, x.c[k].d(), rx1, fz.L[k + 1]);
+  rhs_frame_next(gb.L[k], Q.B[k].d(), Q.s[k], n, Q.s[k + 1], x.c[k].d(), rx1, gb.L[k + 1]);
+  rhs_frame_next(gz.L[k], Q.B[k].d(), Q.s[k], n, Q.s[k + 1], z.c[k].d(), rz1, gz.L[k + 1]);
+}
+
+// Local preconditioned CG on core k; returns the preconditioned local residual of the core it
+// started from, relative to the solved core's norm.
+double Amen::solve_core(int k, double tol_loc) {
+  const Orientation& Q = O[o];
+  const int r0 = x.r[k], n = x.n[k], r1 = x.r[k + 1];
+  const long N = (long)r0 * n * r1;
+  const Frame &FL = fk.L[k], &FR = fk.R[k + 1];
+  // the projected preconditioner: pencils of the two frame terms on each side
+  DBuf WL, mu, WR, nu;
+  // every frame is formed as a left frame (in one orientation or the other) of the separable
+  // operator's canonical cores, so term 0 of a frame is the part with one stiffness factor and
+  // term 1 the pure mass part, on either side
+  if (k > 0) {
+    const Frame& G = fp.L[k];  // [r0][2][r0]
+    DBuf Gp(c.alloc, sizeof(double) * 2 * r0 * r0);
+    permute3(c, G.d.d(), r0, 2, r0, 1, 0, 2, Gp.d());
+    pencil(Gp.d(), Gp.d() + (size_t)r0 * r0, r0, WL, mu);
+  } else {
+    WL = DBuf(c.alloc, sizeof(double));
+    mu = DBuf(c.alloc, sizeof(double));
+    fill(c, WL.d(), 1, 1.0);
+    fill(c, mu.d(), 1, 0.0);
+  }
+  if (k < 2) {
+    const Frame& H = fp.R[k + 1];  // [r1][2][r1]
+    DBuf Hp(c.alloc, sizeof(double) * 2 * r1 * r1);
+    permute3(c, H.d.d(), r1, 2, r1, 1, 0, 2, Hp.d());
+    pencil(Hp.d(), Hp.d() + (size_t)r1 * r1, r1, WR, nu);
+  } else {
+    WR = DBuf(c.alloc, sizeof(double));
+    nu = DBuf(c.alloc, sizeof(double));
+    fill(c, WR.d(), 1, 1.0);
+    fill(c, nu.d(), 1, 0.0);
+  }
+  double hl[2];
+  {
+    double* h = c.host(2);
+    TTIGA_HIP(hipMemcpyAsync(h, Q.lam[k], sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    hl[0] = h[0];  // largest 1-D eigenvalue (descending order)
+  }
+  const double dfloor = 1e-14 * std::max(Q.cc[k] * hl[0], 1e-300);
+  DBuf t1(c.alloc, sizeof(double) * N), t2(c.alloc, sizeof(double) * N);
+  const double* V = Q.V[k];
+  auto prec = [&](const double* r, double* zz) {
+    gemm(c, true, false, r0, n * r1, r0, 1.0, WL.d(), r0, 0, r, (long)n * r1, 0, 0.0, t1.d(), (long)n * r1, 0);
+    gemm(c, true, false, n, r1, n, 1.0, V, n, 0, t1.d(), r1, (long)n * r1, 0.0, t2.d(), r1, (long)n * r1, r0);
+    gemm(c, false, false, r0 * n, r1, r1, 1.0, t2.d(), r1, 0, WR.d(), r1, 0, 0.0, t1.d(), r1, 0);
+    hipLaunchKernelGGL(k_diag_scale, dim3(grid_for(N)), dim3(256), 0, c.stream, r0, n, r1, mu.d(), Q.cc[k], Q.lam[k],
+                       nu.d(), dfloor, t1.d());
+    TTIGA_HIP(hipGetLastError());
+    gemm(c, false, true, r0 * n, r1, r1, 1.0, t1.d(), r1, 0, WR.d(), r1, 0, 0.0, t2.d(), r1, 0);
+    gemm(c, false, false, n, r1, n, 1.0, V, n, 0, t2.d(), r1, (long)n * r1, 0.0, t1.d(), r1, (long)n * r1, r0);
+    gemm(c, false, false, r0, n * r1, r0, 1.0, WL.d(), r0, 0, t1.d(), (long)n * r1, 0, 0.0, zz, (long)n * r1, 0);
+  };
+  DBuf bl(c.alloc, sizeof(double) * N), r(c.alloc, sizeof(double) * N), zz(c.alloc, sizeof(double) * N),
+      pd(c.alloc, sizeof(double) * N), q(c.alloc, sizeof(double) * N);
+  double* xk = x.c[k].d();
+  rhs_local(gb.L[k], Q.B[k].d(), Q.s[k], n, Q.s[k + 1], gb.R[k + 1], bl.d());
+  apply_local(FL, Q.A[k], FR, xk, r.d());
+  hipLaunchKernelGGL(k_rsub, dim3(grid_for(N)), dim3(256), 0, c.stream, N, bl.d(), r.d());
+  TTIGA_HIP(hipGetLastError());
+  prec(r.d(), zz.d());
+  copy(c, pd.d(), zz.d(), N);
+  double dd[4];
+  auto three = [&]() {  // r.z, z.z, x.x with one synchronisation
+    const double* xs[3] = {r.d(), zz.d(), xk};
+    const double* ys[3] = {zz.d(), zz.d(), xk};
+    dots(N, 3, xs, ys, dd);
+  };
+  three();
+  double rz = dd[0];
+  const double z0 = std::sqrt(std::max(dd[1], 0.0));
+  double zn = z0, xn = std::sqrt(std::max(dd[2], 0.0));
+  const int max_it = 400;
+  for (int it = 0; it < max_it; ++it) {
+    if (zn <= tol_loc * xn || !(rz > 0.0)) break;
+    apply_local(FL, Q.A[k], FR, pd.d(), q.d());
+    {
+      const double* xs[1] = {pd.d()};
+      const double* ys[1] = {q.d()};
+      dots(N, 1, xs, ys, dd);
+    }
+    if (!(dd[0] > 0.0)) break;
+    const double alpha = rz / dd[0];
+    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(N)), dim3(256), 0, c.stream, N, alpha, xk, pd.d(), r.d(), q.d());
+    TTIGA_HIP(hipGetLastError());
+    prec(r.d(), zz.d());
+    three();
+    const double beta = dd[0] / rz;
+    rz = dd[0];
+    zn = std::sqrt(std::max(dd[1], 0.0));
+    xn = std::sqrt(std::max(dd[2], 0.0));
+    hipLaunchKernelGGL(k_xpby, dim3(grid_for(N)), dim3(256), 0, c.stream, N, zz.d(), beta, pd.d());
+    TTIGA_HIP(hipGetLastError());
+    ++local_its;
+  }
+  c.sync();
+  return z0 / std::max(xn, 1e-300);
+}
+
+// Core k (k < 2) moves to the right: truncated SVD of its unfolding, update of z's core k,
+// enrichment with the residual projected on z's right interface, x_{k+1} takes the
+// coefficients, frames at bond k + 1.  With solve_mode false (start-up) the core is only
+// orthogonalised.
+void Amen::step(int k, double eps_x, bool solve_mode) {
+  const Orientation& Q = O[o];
+  const int r0 = x.r[k], n = x.n[k], r1 = x.r[k + 1];
+  const int m = r0 * n;
+  const int nxt = x.n[k + 1] * x.r[k + 2];
+  TTIGA_CHECK(m >= r1, TTIGA_E_ARG, "AMEn: rank exceeds its unfolding");
+  DBuf Qx(c.alloc, sizeof(double) * (size_t)m * r1), Rx(c.alloc, sizeof(double) * r1 * r1);
+  qr_tall(c, x.c[k].d(), false, m, r1, r1, Qx.d(), Rx.d());
+  if (!solve_mode) {
+    // x_k = Q, x_{k+1} = R x_{k+1}; z likewise
+    DBuf nx(c.alloc, sizeof(double) * (size_t)r1 * nxt);
+    gemm(c, false, false, r1, nxt, r1, 1.0, Rx.d(), r1, 0, x.c[k + 1].d(), nxt, 0, 0.0, nx.d(), nxt, 0);
+    x.c[k] = std::move(Qx);
+    x.c[k + 1] = std::move(nx);
+    const int zr0 = z.r[k], zr1 = z.r[k + 1], zm = zr0 * z.n[k], znx = z.n[k + 1] * z.r[k + 2];
+    DBuf Qz(c.alloc, sizeof(double) * (size_t)zm * zr1), Rz(c.alloc, sizeof(double) * zr1 * zr1);
+    qr_tall(c, z.c[k].d(), false, zm, zr1, zr1, Qz.d(), Rz.d());
+    DBuf nz(c.alloc, sizeof(double) * (size_t)zr1 * znx);
+    gemm(c, false, false, zr1, znx, zr1, 1.0, Rz.d(), zr1, 0, z.c[k + 1].d(), znx, 0, 0.0, nz.d(), znx, 0);
+    z.c[k] = std::move(Qz);
+    z.c[k + 1] = std::move(nz);
+    frames_at(k);
+    return;
+  }
+  // truncated SVD: X = Q Ur S Vr^T, rank rt at eps_x ||X|| / sqrt(3)
+  DBuf Ur(c.alloc, sizeof(double) * r1 * r1), S(c.alloc, sizeof(double) * r1), Vr(c.alloc, sizeof(double) * r1 * r1);
+  svd_small(c, Rx.d(), false, r1, r1, r1, Ur.d(), S.d(), Vr.d());
+  int rt = trunc_rank_sync(c, S.d(), r1, -eps_x * std::sqrt(2.0 / 3.0), nullptr);
+  rt = std::max(1, rt);
+  DBuf U(c.alloc, sizeof(double) * (size_t)m * rt), SVt(c.alloc, sizeof(double) * rt * r1),
+      xt(c.alloc, sizeof(double) * (size_t)m * r1);
+  gemm(c, false, false, m, rt, r1, 1.0, Qx.d(), r1, 0, Ur.d(), r1, 0, 0.0, U.d(), rt, 0);
+  hipLaunchKernelGGL(k_svt, dim3((rt * r1 + 255) / 256), dim3(256), 0, c.stream, rt, r1, S.d(), Vr.d(), SVt.d());
+  TTIGA_HIP(hipGetLastError());
+  gemm(c, false, false, m, r1, rt, 1.0, U.d(), rt, 0, SVt.d(), r1, 0, 0.0, xt.d(), r1, 0);
+  // z_k: the residual projected on z's interfaces, orthonormalised
+  const int zr0 = z.r[k], zr1 = z.r[k + 1], zm = zr0 * n;
+  {
+    DBuf zr(c.alloc, sizeof(double) * (size_t)zm * zr1), t(c.alloc, sizeof(double) * (size_t)zm * zr1);
+    rhs_local(gz.L[k], Q.B[k].d(), Q.s[k], n, Q.s[k + 1], gz.R[k + 1], zr.d());
+    apply_local(fz.L[k], Q.A[k], fz.R[k + 1], xt.d(), t.d());
+    hipLaunchKernelGGL(k_rsub, dim3(grid_for((long)zm * zr1)), dim3(256), 0, c.stream, (long)zm * zr1, zr.d(), t.d());
+    TTIGA_HIP(hipGetLastError());
+    DBuf Qz(c.alloc, sizeof(double) * (size_t)zm * zr1), Rz(c.alloc, sizeof(double) * zr1 * zr1);
+    qr_tall(c, t.d(), false, zm, zr1, zr1, Qz.d(), Rz.d());
+    z.c[k] = std::move(Qz);
+  }
+  // enrichment: the residual with x's left interface and z's right interface
+  int kick = std::min(zr1, std::min(m, nxt) - rt);
+  if (P.opts.max_rank > 0) kick = std::min(kick, P.opts.max_rank - rt);
+  kick = std::max(kick, 0);
+  const int rn = rt + kick;
+  DBuf Q2(c.alloc, sizeof(double) * (size_t)m * rn);
+  if (kick > 0) {
+    DBuf e(c.alloc, sizeof(double) * (size_t)m * zr1), t(c.alloc, sizeof(double) * (size_t)m * zr1);
+    rhs_local(gb.L[k], Q.B[k].d(), Q.s[k], n, Q.s[k + 1], gz.R[k + 1], e.d());
+    apply_local(fk.L[k], Q.A[k], fz.R[k + 1], xt.d(), t.d());
+    hipLaunchKernelGGL(k_rsub, dim3(grid_for((long)m * zr1)), dim3(256), 0, c.stream, (long)m * zr1, e.d(), t.d());
+    TTIGA_HIP(hipGetLastError());
+    // the first `kick` residual columns join the basis
+    DBuf Ue(c.alloc, sizeof(double) * (size_t)m * rn), R2(c.alloc, sizeof(double) * rn * rn);
+    hipLaunchKernelGGL(k_concat_cols, dim3(grid_for((long)m * rn)), dim3(256), 0, c.stream, (long)m, rt, kick, U.d(),
+                       rt, t.d(), zr1, Ue.d());
+    TTIGA_HIP(hipGetLastError());
+    qr_tall(c, Ue.d(), false, m, rn, rn, Q2.d(), R2.d());
+  } else {
+    copy(c, Q2.d(), U.d(), (size_t)m * rt);
+  }
+  TTIGA_CHECK(P.opts.max_rank <= 0 || rt <= P.opts.max_rank, TTIGA_E_RANKCAP,
+              "AMEn: TT rank " + std::to_string(rt) + " exceeds max_rank");
+  // x_{k+1} <- (Q2^T xt) x_{k+1}
+  DBuf C(c.alloc, sizeof(double) * rn * r1), nx(c.alloc, sizeof(double) * (size_t)rn * nxt);
+  gemm(c, true, false, rn, r1, m, 1.0, Q2.d(), rn, 0, xt.d(), r1, 0, 0.0, C.d(), r1, 0);
+  gemm(c, false, false, rn, nxt, r1, 1.0, C.d(), r1, 0, x.c[k + 1].d(), nxt, 0, 0.0, nx.d(), nxt, 0);
+  x.c[k] = std::move(Q2);
+  x.c[k + 1] = std::move(nx);
+  x.r[k + 1] = rn;
+  max_seen = std::max(max_seen, rn);
+  frames_at(k);
+}
+
+// the iterate in the original core order
+static void unreversed(Context& c, const TT& x, bool reversed, TT& u) {
+  if (!reversed) {
+    tt_copy(c, x, u);
+    return;
+  }
+  const int rr[4] = {x.r[3], x.r[2], x.r[1], x.r[0]};
+  const int nn[3] = {x.n[2], x.n[1], x.n[0]};
+  u.alloc(c, nn, rr);
+  for (int k = 0; k < 3; ++k) permute3(c, x.c[2 - k].d(), x.r[2 - k], x.n[2 - k], x.r[3 - k], 2, 1, 0, u.c[k].d());
+}
+
+void Amen::run(ttiga_solve_stats& s) {
+  Problem& pr = P;
+  const double tol = pr.opts.rel_res_tol;
+  const double eps_x = std::min(pr.opts.tt_eps, 0.3 * tol);
+  if (!pr.pc.ready) pr.pc.setup(pr);
+  setup();
+  // initial guess P^-1 rhs (two digits), residual train z Gaussian of rank kKick
+  int hint = 8;
+  pr.pc.apply(c, pr.rhs, x, 1e-2, pr.opts.max_rank, hint);
+  {
+    const int rz[4] = {1, kKick, kKick, 1};
+    z.alloc(c, x.n, rz);
+    for (int k = 0; k < 3; ++k) gaussian_fill(c, z.c[k].d(), (long)z.core_elems(k));
+  }
+  for (FrameSet* f : {&fk, &fp, &fz, &gb, &gz}) {
+    one(f->L[0]);
+    one(f->R[3]);
+  }
+  // right-orthogonal start: orthogonalise the reversed trains left to right
+  reverse();
+  step(0, eps_x, false);
+  step(1, eps_x, false);
+  reverse();
+  const Matvec mv = [&](const TT& v, TT& out) { tt_matvec_banded(c, pr.KII, pr.p, v, out); };
+  const double nb = std::sqrt(std::max(tt_dot_sync(c, pr.rhs, pr.rhs), 0.0));
+  const int max_half = std::max(2, std::min(pr.opts.max_iter, 60));
+  double prev = 1.0, pres = 1.0, res = 1.0;
+  int half = 0;
+  bool conv = false;
+  const double tol_loc = 0.3 * tol;
+  static const bool trace = [] {
+    const char* e = std::getenv("TTIGA_TRACE_AMEN");
+    return e && e[0] == '1';
+  }();
+  while (half < max_half) {
+    double dmax = 0.0;
+    for (int k = 0; k < 2; ++k) {
+      dmax = std::max(dmax, solve_core(k, tol_loc));
+      step(k, eps_x, true);
+    }
+    reverse();
+    ++half;
+    if (trace)
+      std::fprintf(stderr, "[amen] half %d max local update %.3e ranks %d %d local its %ld\n", half, dmax, x.r[1],
+                   x.r[2], local_its);
+    if (half >= 2 && std::max(prev, dmax) <= tol) {
+      // the global test of the TT-CG path on the rounded iterate
+      TT u;
+      unreversed(c, x, o == 1, u);
+      tt_round(c, u, eps_x, -1.0, pr.opts.max_rank);
+      TT r, zr;
+      int hr = 8, hz = 8;
+      res = true_residual(c, mv, pr.rhs, u, nb, eps_x, pr.opts.max_rank, r, hr, &pr.KII, pr.p);
+      pr.pc.apply(c, r, zr, 1e-2, pr.opts.max_rank, hz);
+      const double zz = tt_dot_sync(c, zr, zr), uu = tt_dot_sync(c, u, u);
+      pres = std::sqrt(std::max(zz, 0.0) / std::max(uu, 1e-300));
+      if (trace) std::fprintf(stderr, "[amen] global check: residual %.3e, P^-1 r / u %.3e\n", res, pres);
+      if (pres <= tol) {
+        pr.u = std::move(u);
+        conv = true;
+        break;
+      }
+    }
+    prev = dmax;
+  }
+  if (!conv) {
+    TT u;
+    unreversed(c, x, o == 1, u);
+    tt_round(c, u, eps_x, -1.0, pr.opts.max_rank);
+    pr.u = std::move(u);
+  }
+  // the reported residual: exact norm of the unrounded rhs - K u
+  {
+    TT tmp;
+    int hr = 8;
+    res = true_residual(c, mv, pr.rhs, pr.u, nb, eps_x, 0, tmp, hr, &pr.KII, pr.p);
+  }
+  s.iterations = half;
+  s.local_iterations = (int)std::min<long>(local_its, 2147483647L);
+  s.rel_res = res;
+  s.rel_pres = pres;
+  s.max_rank_seen = max_seen;
+  s.precond_terms = pr.pc.R;
+  s.precond_err = pr.pc.approx_err;
+  s.status = conv ? TTIGA_OK : TTIGA_E_NOTCONV;
+}
+
+void Problem::solve_amen(ttiga_solve_stats& s) {
+  Amen a(*this);
+  a.run(s);
+}
+
+}  // namespace ttiga

@@ -23,6 +23,8 @@ TTIGA_E_OOM = -5
 TTIGA_E_ADMISSION = -6
 TTIGA_E_NOTCONV = -7
 TTIGA_E_RANKCAP = -8
+TTIGA_SOLVER_CG = 0
+TTIGA_SOLVER_AMEN = 1
 TTIGA_E_STATE = -9
 TTIGA_E_HIP = -10
 
@@ -69,7 +71,7 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("max_rank", ctypes.c_int),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int),
                 ("sample_chunk_bytes", ctypes.c_size_t), ("compression", ctypes.c_int),
-                ("assembly_eps", ctypes.c_double)]
+                ("assembly_eps", ctypes.c_double), ("solver", ctypes.c_int)]
 
 
 class AssemblyStats(ctypes.Structure):
@@ -85,7 +87,7 @@ class SolveStats(ctypes.Structure):
                 ("rel_pres", ctypes.c_double), ("rank_u", ctypes.c_int * 4), ("max_rank_seen", ctypes.c_int),
                 ("precond_terms", ctypes.c_int), ("precond_err", ctypes.c_double),
                 ("precond_setup_ms", ctypes.c_double), ("time_ms", ctypes.c_double),
-                ("refine_steps", ctypes.c_int)]
+                ("refine_steps", ctypes.c_int), ("local_iterations", ctypes.c_int)]
 
 
 class TTView(ctypes.Structure):
@@ -120,7 +122,8 @@ def _result_dict(r):
     return dict(status=r.status, lane=r.lane, rank_u=list(r.rank_u), n=list(r.n),
                 iterations=r.solve.iterations, rel_res=r.solve.rel_res, rel_pres=r.solve.rel_pres,
                 max_rank_seen=r.solve.max_rank_seen, rank_K=list(r.assembly.rank_K),
-                refine_steps=r.solve.refine_steps, assembly_ms=list(r.assembly.time_ms),
+                refine_steps=r.solve.refine_steps, local_iterations=r.solve.local_iterations,
+                assembly_ms=list(r.assembly.time_ms),
                 compression_path=r.assembly.compression_path, solve_ms=r.solve.time_ms,
                 precond_setup_ms=r.solve.precond_setup_ms, queue_ms=r.queue_ms, run_ms=r.run_ms, latency_ms=r.latency_ms,
                 footprint_bytes=r.footprint_bytes, peak_bytes=r.peak_bytes, error=r.error.decode())
@@ -464,6 +467,7 @@ def describe(pr, precond=0):
     o.sample_chunk_bytes = int(getattr(pr.options, "sample_chunk_bytes", 0))
     o.compression = int(getattr(pr.options, "compression", 0))
     o.assembly_eps = float(getattr(pr.options, "assembly_eps", 0.0))
+    o.solver = int(getattr(pr.options, "solver", TTIGA_SOLVER_CG))
     return (g, disc, src, bc, o), keep
 
 
@@ -588,7 +592,7 @@ class ProblemHandle:
         return dict(status=code, iterations=st.iterations, rel_res=st.rel_res, rel_pres=st.rel_pres,
                     rank_u=list(st.rank_u), max_rank_seen=st.max_rank_seen, precond_terms=st.precond_terms,
                     precond_err=st.precond_err, precond_setup_ms=st.precond_setup_ms, time_ms=st.time_ms,
-                    refine_steps=st.refine_steps)
+                    refine_steps=st.refine_steps, local_iterations=st.local_iterations)
 
     def l2_error(self, exact_kind, params=None, extra_gauss=3):
         """ttiga_l2_error: relative L2 error of the solution against an exact solution, evaluated

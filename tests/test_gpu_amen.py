@@ -1,0 +1,129 @@
+"""The AMEn solve (Section 4.1.2) against the oracle's sparse direct solution u_h of
+K_II u_I = F_I - K_IB u_B (Section 4.3; K and F by eqs. Kfinal and ffinal), and against the
+preconditioned TT-CG solution of the same assembled system.
+
+AMEn stops on the preconditioned TT-CG path's test, ||P^-1 (F_I - K_II u)|| <= tol ||u||, an
+estimate of the relative error of u, so the gates are error gates: a few tol at tight
+tolerances, the 1e-6 of the timed workloads on the path those take (cross approximation,
+executor) at the shrunk size the oracle can solve.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sparse_iga, tt_iga
+from tests.gpu_helpers import say, tt_rel_diff
+from workloads.problem import PREC_FP32, Discretization
+
+pytestmark = pytest.mark.gpu
+
+AMEN = 1
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    from paper_2509_13224_amd import ttiga
+    return ttiga.Context(workspace_bytes=16 << 30)
+
+
+def _solve(ctx, pr):
+    pr.options.solver = AMEN
+    h = ctx.problem_create(pr, precond=1)
+    h.assemble()
+    st = h.solve()
+    cores = h.solution()
+    h.close()
+    return st, cores
+
+
+@pytest.mark.parametrize("case", ["twisted_p3_n10", "annulus_p2_n12", "bumpy_p2_n9"])
+def test_amen_matches_sparse(ctx, case):
+    """Tight tolerances (eps 1e-12, tol 1e-11): the AMEn solution within 1e-9 of u_h."""
+    geo = {"twisted_p3_n10": W.twisted_box(1.0), "annulus_p2_n12": W.annulus_sector(1.0, 2.0, np.pi / 2, 1.0),
+           "bumpy_p2_n9": W.bumpy_cube()}[case]
+    n, p = {"twisted_p3_n10": (10, 3), "annulus_p2_n12": (12, 2), "bumpy_p2_n9": (9, 2)}[case]
+    pr = W.small_problem(geo, n, p, W.fourier_source(geo, 21), eps=1e-12, tol=1e-11)
+    say("amen vs sparse", case)
+    u_h = sparse_iga.solve(pr)
+    st, cores = _solve(ctx, pr)
+    u = tt_iga.full_solution(pr, cores).ravel()
+    err = np.linalg.norm(u - u_h) / np.linalg.norm(u_h)
+    say("amen", case, "half-sweeps", st["iterations"], "local its", st["local_iterations"], "ranks", st["rank_u"],
+        "err", err)
+    assert st["status"] == 0 and st["rel_pres"] <= 1e-11, st
+    assert err <= 1e-9, (err, st)
+
+
+def test_amen_timed_path_matches_sparse(ctx):
+    """The annulus workload of the timed solves (degree 3, 8-mode Fourier source, eps 1e-6,
+    tol 1e-7) with 36 x 12 x 12 basis functions, so that the factors are compressed by cross
+    approximation as at full size, solved by AMEn through the executor beside TT-CG solves of
+    the same problems: every AMEn solution within 1e-6 of u_h."""
+    probs, amen = [], []
+    for seed in (W.configs.C2_SEED, W.configs.C2_SEED + 1):
+        for solver in (0, AMEN):
+            pr = W.c2_problem(seed=seed)
+            pr.disc = Discretization(degree=pr.disc.degree, n_basis=(36, 12, 12), n_gauss=pr.disc.n_gauss)
+            pr.options.solver = solver
+            probs.append(pr)
+            amen.append(solver == AMEN)
+    say("amen timed path batch of", len(probs))
+    out = ctx.solve_batch(probs, lanes=4)
+    for pr, is_amen, (res, cores) in zip(probs, amen, out):
+        assert res["status"] == 0, res
+        u_h = sparse_iga.solve(pr)
+        u = tt_iga.full_solution(pr, cores).ravel()
+        err = np.linalg.norm(u - u_h) / np.linalg.norm(u_h)
+        say("solver", "amen" if is_amen else "tt-cg", "path", res["compression_path"], "err", err)
+        assert res["compression_path"] == 2
+        assert err <= 1e-6, (err, res)
+
+
+def test_amen_fullsize_matches_tt_cg(ctx):
+    """The full-size annulus workload (degree 3, n = 256 per direction, 16.5M unknowns): the AMEn
+    solution and the preconditioned TT-CG solution of the same assembled system agree to 1e-6
+    (relative 2-norm of the difference of the two TTs), and AMEn reports the true residual of
+    what it returns."""
+    say("amen fullsize")
+    pr = W.c2_problem(n=256)
+    h = ctx.problem_create(pr, precond=1)
+    h.assemble()
+    st_cg = h.solve()
+    cg = h.solution()
+    h.close()
+    st_am, am = _solve(ctx, W.c2_problem(n=256))
+    d = tt_rel_diff(am, cg)
+    say("amen fullsize: tt-cg", st_cg["time_ms"], "ms, amen", st_am["time_ms"], "ms, ranks", st_am["rank_u"],
+        "rel diff", d)
+    assert st_am["status"] == 0 and st_am["rel_pres"] <= pr.options.rel_res_tol
+    assert d <= 1e-6
+
+
+def test_amen_rejects_low_precision(ctx):
+    from paper_2509_13224_amd import ttiga
+    geo = W.twisted_box(1.0)
+    pr = W.small_problem(geo, 8, 2, W.fourier_source(geo, 3), eps=1e-8, tol=1e-8)
+    pr.options.precision = PREC_FP32
+    pr.options.solver = AMEN
+    h = ctx.problem_create(pr, precond=1)
+    h.assemble()
+    with pytest.raises(ttiga.TTIGAError) as e:
+        h.solve()
+    assert e.value.code == ttiga.TTIGA_E_ARG
+
+
+def test_amen_rank_cap(ctx):
+    """A rank cap below the solution's ranks (8-mode Fourier source) fails the AMEn solve with
+    E_RANKCAP, as in TT-CG; the annulus operator itself has ranks (3, 2), within the cap of 4."""
+    from paper_2509_13224_amd import ttiga
+    say("amen rankcap")
+    pr = W.c2_problem(n=16)
+    pr.options.max_rank = 4
+    pr.options.solver = AMEN
+    h = ctx.problem_create(pr, precond=1)
+    st = h.assemble()
+    assert max(st["rank_K"]) <= 4
+    with pytest.raises(ttiga.TTIGAError) as e:
+        h.solve()
+    assert e.value.code == ttiga.TTIGA_E_RANKCAP
+    h.close()

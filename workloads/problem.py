@@ -98,6 +98,7 @@ class Options:
     sample_chunk_bytes: int = 0  # 0: automatic; > 0: stream the Gauss-grid sampling in chunks
     compression: int = 0  # 0: cross approximation where it pays, verified, TT-SVD fallback; 1: TT-SVD only
     assembly_eps: float = 0.0  # 0: tt_eps; > 0: tolerance of the assembly alone
+    solver: int = 0  # 0: TT-CG (preconditioned per precond); 1: AMEn
 
 
 @dataclass
