@@ -296,7 +296,11 @@ def serve(ctx, reqs, rate, lanes, seed):
     th = threading.Thread(target=producer)
     th.start()
     th.join()
-    results = [srv.poll(t, wait_ms=-1) for t in tickets]
+    results = []
+    for i, t in enumerate(tickets):
+        results.append(srv.poll(t, wait_ms=-1))
+        if (i + 1) % 50 == 0 and i + 1 < len(tickets):
+            log(f"  {i + 1} of {len(tickets)} requests done")
     t1 = time.perf_counter()
     sols = [srv.solution(t) if r["status"] in (0, -7) else None for t, r in zip(tickets, results)]
     for t in tickets:
@@ -314,9 +318,12 @@ def serving_phase(ctx, count, lanes):
     sreqs = W.c4_requests(count=count, sizes=SERVE_SIZES, precision=PREC_FP32, assembly_eps=ASSEMBLY_EPS,
                           max_rank=SERVE_MAX_RANK)
     log("serving references")
-    srefs = [u for _, u in ctx.solve_batch(
-        W.c4_requests(count=count, sizes=SERVE_SIZES, precision=PREC_FP64, eps=1e-7, tol=1e-8,
-                      assembly_eps=ASSEMBLY_EPS / 10, max_rank=SERVE_MAX_RANK), lanes=lanes)]
+    ref_pr = W.c4_requests(count=count, sizes=SERVE_SIZES, precision=PREC_FP64, eps=1e-7, tol=1e-8,
+                           assembly_eps=ASSEMBLY_EPS / 10, max_rank=SERVE_MAX_RANK)
+    srefs = []
+    for b in range(0, count, 50):
+        srefs += [u for _, u in ctx.solve_batch(ref_pr[b:b + 50], lanes=lanes)]
+        log(f"  references: {len(srefs)} of {count}")
 
     def summarise(res, sols, secs, offered):
         serr = [tt_rel_diff(u, ur) if (u is not None and ur is not None) else float("inf")
