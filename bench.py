@@ -309,14 +309,17 @@ def serve(ctx, reqs, rate, lanes, seed):
     return results, sols, t1 - t0
 
 
-def serving_phase(ctx, count, lanes):
-    """C5: `count` requests of the batched family with sizes up to n = 512, FP32 mixed, served by one
-    server under Poisson arrivals at fractions of the mix's own saturation throughput; latency
-    percentiles, offered and achieved rates, and every result against its FP64 reference."""
+def serving_phase(ctx, count, lanes, solver=1):
+    """C5: `count` requests of the batched family with sizes up to n = 512 (FP64 AMEn solves, or with
+    solver 0 FP32 mixed TT-CG), served by one server under Poisson arrivals at fractions of the
+    mix's own saturation throughput; latency percentiles, offered and achieved rates, and every
+    result against its FP64 TT-CG reference."""
     import workloads as W
     from workloads.problem import PREC_FP32, PREC_FP64
-    sreqs = W.c4_requests(count=count, sizes=SERVE_SIZES, precision=PREC_FP32, assembly_eps=ASSEMBLY_EPS,
-                          max_rank=SERVE_MAX_RANK)
+    sreqs = W.c4_requests(count=count, sizes=SERVE_SIZES, precision=PREC_FP64 if solver else PREC_FP32,
+                          assembly_eps=ASSEMBLY_EPS, max_rank=SERVE_MAX_RANK)
+    for pr in sreqs:
+        pr.options.solver = solver
     log("serving references")
     ref_pr = W.c4_requests(count=count, sizes=SERVE_SIZES, precision=PREC_FP64, eps=1e-7, tol=1e-8,
                            assembly_eps=ASSEMBLY_EPS / 10, max_rank=SERVE_MAX_RANK)
@@ -348,7 +351,8 @@ def serving_phase(ctx, count, lanes):
         lines.append(line)
     return {"requests": count, "arrival": f"Poisson, seed {SERVE_SEED}", "lanes": lanes,
             "workload": ("n in {32,64,128,256,512}, p in {2,3}, annulus sector or twisted box, seeded Fourier "
-                         f"source, FP32 mixed, assembly at {ASSEMBLY_EPS:g}, seeds 10000+b"),
+                         f"source, {'FP64 AMEn' if solver else 'FP32 mixed TT-CG'}, assembly at {ASSEMBLY_EPS:g}, "
+                         "seeds 10000+b"),
             "saturation": sat_line, "rates": lines,
             "percentiles": f"nearest rank over {count} requests per rate"}
 
@@ -383,6 +387,7 @@ def main():
     ap.add_argument("--sweep-only", action="store_true",
                     help="only the synthetic TT-matvec sweep (value = the best fraction of HBM bandwidth)")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the complex-geometry AMEn solve")
     ap.add_argument("--sweep-point", type=str, default="",
                     help="rK,rx,n,p: run only this point of the sweep (with --sweep-only)")
     ap.add_argument("--traffic-kib", type=str, default="",
@@ -442,13 +447,14 @@ def main():
     refs_pr = [with_solver(W.c2_problem(n=args.n, seed=s, eps=eps / 10, tol=tol / 10), other) for s in seeds]
 
     if args.serve_only:
-        sv = serving_phase(ctx, args.serve, args.lanes)
+        sv = serving_phase(ctx, args.serve, args.lanes, solver)
         at1 = next(q for q in sv["rates"] if q["fraction_of_saturation"] == 1.0)
         print(json.dumps({
             "metric": "served solves/s at 1e-6 rel-L2 (Poisson arrivals at the mix's saturation rate)",
             "value": at1["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": len(SERVE_RATES) + 1,
             "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32+f64", "data": "synthetic", "config": {"workload": sv["workload"]}, "serving": sv}),
+            "dtype": "f64" if solver else "f32+f64", "data": "synthetic", "config": {"workload": sv["workload"]},
+            "serving": sv}),
             flush=True)
         return
 
@@ -624,6 +630,54 @@ def main():
                                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]},
     }
 
+    # the plain FP64 parity configuration (annulus, degree 2, n = 16, eps = tol = 1e-10): latency of
+    # one assembly + solve with each solver, warm context
+    log("C1 latency")
+    c1 = {}
+    for which in (solver, other):
+        pr = with_solver(W.configs.c1_problem(), which)
+        ts, st = [], None
+        for _ in range(4):
+            h = ctx.problem_create(pr, precond=1)
+            t0 = time.perf_counter()
+            h.assemble()
+            st = h.solve()
+            ts.append(1e3 * (time.perf_counter() - t0))
+            h.close()
+        c1[solver_name[which]] = {"latency_ms": sum(ts[1:]) / 3, "min_ms": min(ts[1:]), "iterations": st["iterations"],
+                                  "rel_res": st["rel_res"], "rank_u": st["rank_u"]}
+    out["c1_latency"] = {"workload": "annulus degree 2, n=16/dir, manufactured source, eps = tol = 1e-10, FP64; "
+                                     "assembly + solve, mean of 3 after one warm-up", **c1}
+
+    # the complex-geometry configuration (bumpy cube, degree 3, n = 512, 1.3e8 DOF, FP64) solved by
+    # AMEn once, with the rate of its GEMMs (the local products contract the operator rank 84)
+    if not args.no_c3:
+        log("C3 AMEn solve")
+        pr = with_solver(W.c3_problem(n=512, precision=PREC_FP64), ttiga.TTIGA_SOLVER_AMEN)
+        h = ctx.problem_create(pr, precond=1)
+        t0 = time.perf_counter()
+        ast = h.assemble()
+        t1 = time.perf_counter()
+        ctx.profile(-1)
+        ctx.profile(1)
+        st3 = h.solve(allow_notconv=True)
+        t2 = time.perf_counter()
+        ctx.profile(0)
+        p3 = ctx.profile_read()
+        h.close()
+        g3 = p3.get("gemm_f64")
+        out["c3_amen"] = {
+            "workload": "bumpy cube (seeded NURBS), degree 3, n=512/dir (1.3e8 DOF), 8-mode Fourier source, "
+                        "TT eps 1e-6, tol 1e-7, FP64, AMEn (one solve; the preconditioner plan is built in it)",
+            "assembly_ms": 1e3 * (t1 - t0), "solve_ms": 1e3 * (t2 - t1), "status": st3["status"],
+            "half_sweeps": st3["iterations"], "local_iterations": st3["local_iterations"], "rank_u": st3["rank_u"],
+            "rank_K": ast["rank_K"], "rel_pres": st3["rel_pres"], "rel_res": st3["rel_res"],
+            "gemm_f64": ({"tflops": g3["flops"] / (g3["total_ms"] * 1e-3) / 1e12,
+                          "frac_fp64_peak": g3["flops"] / (g3["total_ms"] * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
+                          "ms": g3["total_ms"], "launches": g3["launches"]} if g3 else None),
+            "kernels": {k: {"ms": v["total_ms"], "launches": v["launches"]}
+                        for k, v in sorted(p3.items(), key=lambda kv: -kv[1]["total_ms"])[:6]}}
+
     if not args.no_sweep:
         log("TT-matvec sweep")
         sw = matvec_sweep(ctx)
@@ -651,7 +705,7 @@ def main():
                                              f"TT eps 1e-6, assembly at {ASSEMBLY_EPS:g}"}
     if args.serve > 0:
         log("serving")
-        out["serving"] = serving_phase(ctx, args.serve, args.lanes)
+        out["serving"] = serving_phase(ctx, args.serve, args.lanes, solver)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_slabs, args.n)

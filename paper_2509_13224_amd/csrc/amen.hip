@@ -23,9 +23,10 @@
 // are those of the global preconditioned CG.
 //
 // Stopping: the core updates are measured as ||P_k^-1 (b_k - A_k x_old)|| / ||x_new|| (the
-// preconditioned local residual, an error estimate like the TT-CG stopping test); when a whole
-// sweep stays below tol the global test ||P^-1 (rhs - K u)|| <= tol ||u|| (the TT-CG path's) is
-// evaluated, and sweeps continue while it fails.
+// preconditioned local residual, an error estimate like the TT-CG stopping test); when those of
+// a half-sweep stay below tol (after the first full sweep) the global test
+// ||P^-1 (rhs - K u)|| <= tol ||u|| (the TT-CG path's) is evaluated, and sweeps continue while
+// it fails.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -92,14 +93,24 @@ struct DotArgs {
 
 constexpr int kDotBlocks = 512;
 
-// part[b][v] = block b's share of x_v . y_v (fixed grid: the sums do not depend on timing)
-template <int NV>
-__global__ void __launch_bounds__(256) k_dots_partial(long n, DotArgs a, double* __restrict__ part) {
+// out[v] = x_v . y_v for v < NV in one launch: each block writes its share to part[b][v]; the
+// block that finishes last (a counter, reset by it for the next call) adds the shares in block
+// order, so the sums do not depend on timing.
+// post-processing by the last block: none (out = the sums), the start of a local CG (scal[0] =
+// r.z, out = the sums), its step length (scal[2] = r.z / p.q) or its direction update
+// (scal[3] = r.z new / r.z old, scal[0] = r.z new, out = the sums); scal lives on the device,
+// out in host-mapped memory
+enum DotPost { kPostNone = 0, kPostInit = 1, kPostAlpha = 2, kPostBeta = 3 };
+
+template <int NV, int POST>
+__global__ void __launch_bounds__(256) k_dots(long n, DotArgs a, double* __restrict__ part, unsigned* counter,
+                                              double* __restrict__ out, double* __restrict__ scal) {
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256L)
 #pragma unroll
     for (int v = 0; v < NV; ++v) s[v] += a.x[v][e] * a.y[v][e];
   __shared__ double sh[4][256];
+  __shared__ bool last;
   for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = s[v];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -108,36 +119,59 @@ __global__ void __launch_bounds__(256) k_dots_partial(long n, DotArgs a, double*
     __syncthreads();
   }
   if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
-}
-
-__global__ void __launch_bounds__(256) k_dots_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
-  __shared__ double sh[4][256];
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nb; b += 256)
-    for (int v = 0; v < 4; ++v) s[v] += part[b * 4 + v];
-  for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = s[v];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* vp = part;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += 256)
+    for (int v = 0; v < 4; ++v) t[v] += vp[b * 4 + v];
+  for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = t[v];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
       for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x == 0) {
+    const double s0 = sh[0][0];
+    if (POST == kPostAlpha) {
+      scal[2] = (s0 > 0.0 && scal[0] > 0.0) ? scal[0] / s0 : 0.0;
+    } else {
+      if (POST == kPostInit) scal[0] = s0;
+      if (POST == kPostBeta) {
+        scal[3] = scal[0] > 0.0 ? s0 / scal[0] : 0.0;
+        scal[0] = s0;
+      }
+      for (int v = 0; v < 4; ++v) out[v] = sh[v][0];
+    }
+    *counter = 0u;
+  }
 }
 
-// x += a p, r -= a q
-__global__ void k_cg_update(long n, double a, double* __restrict__ x, const double* __restrict__ p,
-                            double* __restrict__ r, const double* __restrict__ q) {
+// x += a p, r -= a q with a = *alpha (device)
+__global__ void k_cg_update_dev(long n, const double* __restrict__ alpha, double* __restrict__ x,
+                                const double* __restrict__ p, double* __restrict__ r, const double* __restrict__ q) {
+  const double a = *alpha;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     x[e] += a * p[e];
     r[e] -= a * q[e];
   }
 }
 
-// p = z + b p
-__global__ void k_xpby(long n, const double* __restrict__ z, double b, double* __restrict__ p) {
+// p = z + b p with b = *beta (device)
+__global__ void k_xpby_dev(long n, const double* __restrict__ z, const double* __restrict__ beta,
+                           double* __restrict__ p) {
+  const double b = *beta;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
     p[e] = z[e] + b * p[e];
+}
+
+__global__ void k_zero_counter(unsigned* counter) {
+  if (threadIdx.x == 0) *counter = 0u;
 }
 
 // y = a - y
@@ -206,6 +240,10 @@ void permute3(Context& c, const double* in, int d0, int d1, int d2, int p0, int 
 struct Frame {
   DBuf d;
   int ry = 0, ra = 0, rx = 0;
+  // for frames of the separable preconditioner: the pencil of its two terms (W, eigenvalues),
+  // once formed; a frame is used on the left of one core and later, after the trains are
+  // reversed, on the right of the same core, so each pencil serves two local solves
+  DBuf W, ev;
 };
 
 struct FrameSet {
@@ -227,10 +265,56 @@ struct Orientation {
   int s[4];
   const double* V[3];
   const double* lam[3];
+  double lam_max[3];
   double cc[3];
 };
 
 }  // namespace
+
+// A product C = op(A) op(B) whose plan and split workspace are fixed in advance, so that running
+// it allocates nothing (a stream under graph capture must not).
+struct FixedGemm {
+  GemmPlan g;
+  bool ta = false, tb = false;
+  int M = 0, N = 0, K = 0, batch = 1;
+  DBuf part;
+  void plan(Context& c, bool ta_, bool tb_, int M_, int N_, int K_, int batch_ = 1) {
+    ta = ta_;
+    tb = tb_;
+    M = M_;
+    N = N_;
+    K = K_;
+    batch = batch_;
+    g = gemm_plan(ta, tb, M, N, K, batch);
+    if (g.splits > 1) part = DBuf(c.alloc, sizeof(double) * gemm_part_doubles(g, M, N, batch));
+  }
+  void run(Context& c, const double* A, long lda, long sA, const double* B, long ldb, long sB, double* C, long ldc,
+           long sC) const {
+    gemm_planned(c, g, ta, tb, M, N, K, 1.0, A, lda, sA, B, ldb, sB, 0.0, C, ldc, sC, batch, part.d());
+  }
+};
+
+// The local product y = (Phi_L (x) K_k (x) Phi_R) x of one core, with the frame layouts, the
+// work buffers (T1 with its zero padding, T2) and the three products prepared once for the many
+// products of a local solve.
+struct LocalOp {
+  int p = 0, band = 0, n = 0, ry0 = 0, ra0 = 0, rx0 = 0, ry1 = 0, ra1 = 0, rx1 = 0;
+  long slab = 0;
+  DBuf Fp, FRp, T1, T2;
+  const double* Kp = nullptr;
+  FixedGemm g1, g2, g3;
+};
+
+// The projected preconditioner P_k^-1 = (W_L (x) V_k (x) W_R) D^-1 (W_L (x) V_k (x) W_R)^T of one
+// core, prepared once per local solve.
+struct PrecOp {
+  int r0 = 0, n = 0, r1 = 0;
+  long N = 0;
+  const double *WL = nullptr, *mu = nullptr, *WR = nullptr, *nu = nullptr, *V = nullptr, *lam = nullptr;
+  double cc = 0.0, dfloor = 0.0;
+  DBuf t1, t2;
+  FixedGemm a1, a2, a3, b1, b2, b3;
+};
 
 class Amen {
  public:
@@ -263,36 +347,29 @@ class Amen {
   double solve_core(int k, double tol_loc);
   void step(int k, double eps_x, bool solve_mode);
   void frames_at(int k);
-  void dots(long n, int nv, const double* const* xs, const double* const* ys, double* out);
+  void local_op(const Frame& FL, const BandCore& A, const Frame& FR, LocalOp& op);
+  void local_apply(const LocalOp& op, const double* X, double* Y);
+  void prec_op(int k, PrecOp& pp);
+  void prec_apply(const PrecOp& pp, const double* r, double* z);
+  template <int NV, int POST>
+  void dots_dev(long n, const double* const* xs, const double* const* ys);
+  double* hmap = nullptr;      // host-mapped results of the local CG dots (host address)
+  double* hmap_dev = nullptr;  // its device address
+  DBuf scal;                   // device scalars of the local CG: r.z, -, alpha, beta
+ public:
+  ~Amen() {
+    if (hmap) (void)hipHostFree(hmap);
+  }
+ private:
+  void pencil_of(Frame& F, int r);
+  DBuf dot_part;  // partial sums of the dots and their counter
+  DBuf unit;
 };
 
 void Amen::one(Frame& f) {
   f.d = DBuf(c.alloc, sizeof(double));
   fill(c, f.d.d(), 1, 1.0);
   f.ry = f.ra = f.rx = 1;
-}
-
-void Amen::dots(long n, int nv, const double* const* xs, const double* const* ys, double* out) {
-  DotArgs a{};
-  a.nv = nv;
-  for (int v = 0; v < 4; ++v) {
-    a.x[v] = v < nv ? xs[v] : xs[0];
-    a.y[v] = v < nv ? ys[v] : ys[0];
-  }
-  DBuf part(c.alloc, sizeof(double) * 4 * kDotBlocks);
-  double* hd = c.host_device(4);
-  if (nv == 1)
-    hipLaunchKernelGGL(k_dots_partial<1>, dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, part.d());
-  else if (nv == 2)
-    hipLaunchKernelGGL(k_dots_partial<2>, dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, part.d());
-  else if (nv == 3)
-    hipLaunchKernelGGL(k_dots_partial<3>, dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, part.d());
-  else
-    hipLaunchKernelGGL(k_dots_partial<4>, dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, part.d());
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, c.stream, kDotBlocks, part.d(), hd);
-  TTIGA_HIP(hipGetLastError());
-  c.sync();
-  for (int v = 0; v < nv; ++v) out[v] = c.host_scratch[v];
 }
 
 void Amen::contract(const Frame& F, const BandCore& A, const double* X, int rx1, DBuf& T2) {
@@ -311,6 +388,101 @@ void Amen::contract(const Frame& F, const BandCore& A, const double* X, int rx1,
   T2 = DBuf(c.alloc, sizeof(double) * (size_t)n * ry * rx1 * ra1);
   gemm(c, true, false, ry * rx1, ra1, band * ra0, 1.0, T1.d(), (long)ry * rx1, slab, A.perm.d(), ra1,
        (long)band * ra0 * ra1, 0.0, T2.d(), ra1, (long)ry * rx1 * ra1, n);
+}
+
+void Amen::local_op(const Frame& FL, const BandCore& A, const Frame& FR, LocalOp& op) {
+  TTIGA_CHECK(A.ra0 == FL.ra && A.ra1 == FR.ra, TTIGA_E_ARG, "AMEn frame and operator ranks differ");
+  op.p = p;
+  op.band = band;
+  op.n = A.n;
+  op.ry0 = FL.ry;
+  op.ra0 = FL.ra;
+  op.rx0 = FL.rx;
+  op.ry1 = FR.ry;
+  op.ra1 = FR.ra;
+  op.rx1 = FR.rx;
+  op.Kp = A.perm.d();
+  op.Fp = DBuf(c.alloc, sizeof(double) * op.ry0 * op.ra0 * op.rx0);
+  permute3(c, FL.d.d(), op.ry0, op.ra0, op.rx0, 1, 0, 2, op.Fp.d());  // [ra0][ry0][rx0]
+  op.FRp = DBuf(c.alloc, sizeof(double) * op.ry1 * op.ra1 * op.rx1);
+  permute3(c, FR.d.d(), op.ry1, op.ra1, op.rx1, 2, 1, 0, op.FRp.d());  // [rx1][ra1][ry1]
+  op.slab = (long)op.ra0 * op.ry0 * op.rx1;
+  op.T1 = DBuf(c.alloc, sizeof(double) * op.slab * (op.n + 2 * p));
+  fill(c, op.T1.d(), (size_t)op.slab * p, 0.0);
+  fill(c, op.T1.d() + op.slab * (op.n + p), (size_t)op.slab * p, 0.0);
+  op.T2 = DBuf(c.alloc, sizeof(double) * (size_t)op.n * op.ry0 * op.rx1 * op.ra1);
+  op.g1.plan(c, false, false, op.ra0 * op.ry0, op.rx1, op.rx0, op.n);
+  op.g2.plan(c, true, false, op.ry0 * op.rx1, op.ra1, op.band * op.ra0, op.n);
+  op.g3.plan(c, false, false, op.n, op.ry1, op.rx1 * op.ra1, op.ry0);
+}
+
+// the three GEMMs of contract() and apply_local() on prepared layouts
+void Amen::local_apply(const LocalOp& op, const double* X, double* Y) {
+  const int n = op.n;
+  op.g1.run(c, op.Fp.d(), op.rx0, 0, X, (long)n * op.rx1, op.rx1, op.T1.d() + op.slab * op.p, op.rx1, op.slab);
+  op.g2.run(c, op.T1.d(), (long)op.ry0 * op.rx1, op.slab, op.Kp, op.ra1, (long)op.band * op.ra0 * op.ra1, op.T2.d(),
+            op.ra1, (long)op.ry0 * op.rx1 * op.ra1);
+  op.g3.run(c, op.T2.d(), (long)op.ry0 * op.rx1 * op.ra1, (long)op.rx1 * op.ra1, op.FRp.d(), op.ry1, 0, Y, op.ry1,
+            (long)n * op.ry1);
+}
+
+void Amen::prec_op(int k, PrecOp& pp) {
+  const Orientation& Q = O[o];
+  const int r0 = x.r[k], n = x.n[k], r1 = x.r[k + 1];
+  pp.r0 = r0;
+  pp.n = n;
+  pp.r1 = r1;
+  pp.N = (long)r0 * n * r1;
+  // every frame is formed as a left frame (in one orientation or the other) of the separable
+  // operator's canonical cores, so term 0 of a frame is the part with one stiffness factor and
+  // term 1 the pure mass part, on either side; the frames at the ends are the scalar 1 (W = 1,
+  // eigenvalue 0)
+  if (k > 0) pencil_of(fp.L[k], r0);
+  if (k < 2) pencil_of(fp.R[k + 1], r1);
+  pp.WL = k > 0 ? fp.L[k].W.d() : unit.d();
+  pp.mu = k > 0 ? fp.L[k].ev.d() : unit.d() + 1;
+  pp.WR = k < 2 ? fp.R[k + 1].W.d() : unit.d();
+  pp.nu = k < 2 ? fp.R[k + 1].ev.d() : unit.d() + 1;
+  pp.V = Q.V[k];
+  pp.lam = Q.lam[k];
+  pp.cc = Q.cc[k];
+  pp.dfloor = 1e-14 * std::max(Q.cc[k] * Q.lam_max[k], 1e-300);
+  pp.t1 = DBuf(c.alloc, sizeof(double) * pp.N);
+  pp.t2 = DBuf(c.alloc, sizeof(double) * pp.N);
+  pp.a1.plan(c, true, false, r0, n * r1, r0);
+  pp.a2.plan(c, true, false, n, r1, n, r0);
+  pp.a3.plan(c, false, false, r0 * n, r1, r1);
+  pp.b1.plan(c, false, true, r0 * n, r1, r1);
+  pp.b2.plan(c, false, false, n, r1, n, r0);
+  pp.b3.plan(c, false, false, r0, n * r1, r0);
+}
+
+void Amen::prec_apply(const PrecOp& pp, const double* r, double* z) {
+  const int r0 = pp.r0, n = pp.n, r1 = pp.r1;
+  double *t1 = pp.t1.d(), *t2 = pp.t2.d();
+  pp.a1.run(c, pp.WL, r0, 0, r, (long)n * r1, 0, t1, (long)n * r1, 0);
+  pp.a2.run(c, pp.V, n, 0, t1, r1, (long)n * r1, t2, r1, (long)n * r1);
+  pp.a3.run(c, t2, r1, 0, pp.WR, r1, 0, t1, r1, 0);
+  hipLaunchKernelGGL(k_diag_scale, dim3(grid_for(pp.N)), dim3(256), 0, c.stream, r0, n, r1, pp.mu, pp.cc, pp.lam,
+                     pp.nu, pp.dfloor, t1);
+  TTIGA_HIP(hipGetLastError());
+  pp.b1.run(c, t1, r1, 0, pp.WR, r1, 0, t2, r1, 0);
+  pp.b2.run(c, pp.V, n, 0, t2, r1, (long)n * r1, t1, r1, (long)n * r1);
+  pp.b3.run(c, pp.WL, r0, 0, t1, (long)n * r1, 0, z, (long)n * r1, 0);
+}
+
+template <int NV, int POST>
+void Amen::dots_dev(long n, const double* const* xs, const double* const* ys) {
+  DotArgs a{};
+  a.nv = NV;
+  for (int v = 0; v < 4; ++v) {
+    a.x[v] = v < NV ? xs[v] : xs[0];
+    a.y[v] = v < NV ? ys[v] : ys[0];
+  }
+  unsigned* cnt = dot_part.as<unsigned>() + 8 * kDotBlocks;
+  hipLaunchKernelGGL((k_dots<NV, POST>), dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, dot_part.d(), cnt, hmap_dev,
+                     scal.d());
+  TTIGA_HIP(hipGetLastError());
 }
 
 void Amen::apply_local(const Frame& FL, const BandCore& A, const Frame& FR, const double* X, double* Y) {
@@ -337,6 +509,8 @@ void Amen::frame_next(const Frame& F, const BandCore& A, const double* Y, int ry
        (long)rx1 * ra1, 0);
   out.d = DBuf(c.alloc, sizeof(double) * ry1 * ra1 * rx1);
   permute3(c, Fq.d(), ry1, rx1, ra1, 0, 2, 1, out.d.d());
+  out.W.reset();
+  out.ev.reset();
   out.ry = ry1;
   out.ra = ra1;
   out.rx = rx1;
@@ -384,7 +558,28 @@ void Amen::pencil(const double* GA, const double* GM, int r, DBuf& W, DBuf& ev) 
   gemm(c, false, false, r, r, r, 1.0, Ri.d(), r, 0, U.d(), r, 0, 0.0, W.d(), r, 0);
 }
 
+// the pencil of a preconditioner frame [r][2][r] (term 0: one stiffness factor, term 1: mass
+// only), formed once per frame
+void Amen::pencil_of(Frame& F, int r) {
+  if (F.W.d()) return;
+  DBuf Gp(c.alloc, sizeof(double) * 2 * r * r);
+  permute3(c, F.d.d(), r, 2, r, 1, 0, 2, Gp.d());
+  pencil(Gp.d(), Gp.d() + (size_t)r * r, r, F.W, F.ev);
+}
+
 void Amen::setup() {
+  unit = DBuf(c.alloc, 2 * sizeof(double));  // {1, 0}: W and eigenvalue of a scalar end frame
+  fill(c, unit.d(), 1, 1.0);
+  fill(c, unit.d() + 1, 1, 0.0);
+  dot_part = DBuf(c.alloc, sizeof(double) * 4 * kDotBlocks + 64);
+  scal = DBuf(c.alloc, sizeof(double) * 8);
+  fill(c, scal.d(), 8, 0.0);
+  if (!hmap) {
+    TTIGA_HIP(hipHostMalloc(reinterpret_cast<void**>(&hmap), sizeof(double) * 8, hipHostMallocCoherent));
+    TTIGA_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&hmap_dev), hmap, 0));
+  }
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, c.stream, dot_part.as<unsigned>() + 8 * kDotBlocks);
+  TTIGA_HIP(hipGetLastError());
   const TT& K = P.KII;
   const TT& b = P.rhs;
   int ni[3];
@@ -436,6 +631,7 @@ void Amen::setup() {
         permute3(c, b.c[src].d(), s0, n, s1, 2, 1, 0, Q.B[k].d());
       Q.V[k] = P.pc.eb[src]->V.d();
       Q.lam[k] = P.pc.eb[src]->lam.d();
+      Q.lam_max[k] = P.pc.eb[src]->lam_max;
       Q.cc[k] = P.pc.c[src];
     }
     for (int k = 0; k < 4; ++k) Q.s[k] = oo == 0 ? b.r[k] : b.r[3 - k];
@@ -469,103 +665,93 @@ void Amen::frames_at(int k) {
 }
 
 // Local preconditioned CG on core k; returns the preconditioned local residual of the core it
-// started from, relative to the solved core's norm.
+// started from, relative to the solved core's norm.  The step length and the direction update
+// are computed on the device (by the last block of the dot products), so a CG iteration is a
+// fixed sequence of 14 launches without host round trips; kGraphIters iterations are captured
+// once per local solve as a HIP graph and replayed, with the convergence test (read from
+// host-mapped memory) after each replay.  With profiling on (per-launch timing), on the legacy
+// default stream or with TTIGA_AMEN_GRAPH=0 the same launches are issued directly, in the same
+// order, so the results are the same bits either way.
+constexpr int kGraphIters = 2;
+
 double Amen::solve_core(int k, double tol_loc) {
   const Orientation& Q = O[o];
   const int r0 = x.r[k], n = x.n[k], r1 = x.r[k + 1];
   const long N = (long)r0 * n * r1;
-  const Frame &FL = fk.L[k], &FR = fk.R[k + 1];
-  // the projected preconditioner: pencils of the two frame terms on each side
-  DBuf WL, mu, WR, nu;
-  // every frame is formed as a left frame (in one orientation or the other) of the separable
-  // operator's canonical cores, so term 0 of a frame is the part with one stiffness factor and
-  // term 1 the pure mass part, on either side
-  if (k > 0) {
-    const Frame& G = fp.L[k];  // [r0][2][r0]
-    DBuf Gp(c.alloc, sizeof(double) * 2 * r0 * r0);
-    permute3(c, G.d.d(), r0, 2, r0, 1, 0, 2, Gp.d());
-    pencil(Gp.d(), Gp.d() + (size_t)r0 * r0, r0, WL, mu);
-  } else {
-    WL = DBuf(c.alloc, sizeof(double));
-    mu = DBuf(c.alloc, sizeof(double));
-    fill(c, WL.d(), 1, 1.0);
-    fill(c, mu.d(), 1, 0.0);
-  }
-  if (k < 2) {
-    const Frame& H = fp.R[k + 1];  // [r1][2][r1]
-    DBuf Hp(c.alloc, sizeof(double) * 2 * r1 * r1);
-    permute3(c, H.d.d(), r1, 2, r1, 1, 0, 2, Hp.d());
-    pencil(Hp.d(), Hp.d() + (size_t)r1 * r1, r1, WR, nu);
-  } else {
-    WR = DBuf(c.alloc, sizeof(double));
-    nu = DBuf(c.alloc, sizeof(double));
-    fill(c, WR.d(), 1, 1.0);
-    fill(c, nu.d(), 1, 0.0);
-  }
-  double hl[2];
-  {
-    double* h = c.host(2);
-    TTIGA_HIP(hipMemcpyAsync(h, Q.lam[k], sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    c.sync();
-    hl[0] = h[0];  // largest 1-D eigenvalue (descending order)
-  }
-  const double dfloor = 1e-14 * std::max(Q.cc[k] * hl[0], 1e-300);
-  DBuf t1(c.alloc, sizeof(double) * N), t2(c.alloc, sizeof(double) * N);
-  const double* V = Q.V[k];
-  auto prec = [&](const double* r, double* zz) {
-    gemm(c, true, false, r0, n * r1, r0, 1.0, WL.d(), r0, 0, r, (long)n * r1, 0, 0.0, t1.d(), (long)n * r1, 0);
-    gemm(c, true, false, n, r1, n, 1.0, V, n, 0, t1.d(), r1, (long)n * r1, 0.0, t2.d(), r1, (long)n * r1, r0);
-    gemm(c, false, false, r0 * n, r1, r1, 1.0, t2.d(), r1, 0, WR.d(), r1, 0, 0.0, t1.d(), r1, 0);
-    hipLaunchKernelGGL(k_diag_scale, dim3(grid_for(N)), dim3(256), 0, c.stream, r0, n, r1, mu.d(), Q.cc[k], Q.lam[k],
-                       nu.d(), dfloor, t1.d());
-    TTIGA_HIP(hipGetLastError());
-    gemm(c, false, true, r0 * n, r1, r1, 1.0, t1.d(), r1, 0, WR.d(), r1, 0, 0.0, t2.d(), r1, 0);
-    gemm(c, false, false, n, r1, n, 1.0, V, n, 0, t2.d(), r1, (long)n * r1, 0.0, t1.d(), r1, (long)n * r1, r0);
-    gemm(c, false, false, r0, n * r1, r0, 1.0, WL.d(), r0, 0, t1.d(), (long)n * r1, 0, 0.0, zz, (long)n * r1, 0);
-  };
+  PrecOp pp;
+  prec_op(k, pp);
+  LocalOp op;
+  local_op(fk.L[k], Q.A[k], fk.R[k + 1], op);
   DBuf bl(c.alloc, sizeof(double) * N), r(c.alloc, sizeof(double) * N), zz(c.alloc, sizeof(double) * N),
       pd(c.alloc, sizeof(double) * N), q(c.alloc, sizeof(double) * N);
   double* xk = x.c[k].d();
   rhs_local(gb.L[k], Q.B[k].d(), Q.s[k], n, Q.s[k + 1], gb.R[k + 1], bl.d());
-  apply_local(FL, Q.A[k], FR, xk, r.d());
+  local_apply(op, xk, r.d());
   hipLaunchKernelGGL(k_rsub, dim3(grid_for(N)), dim3(256), 0, c.stream, N, bl.d(), r.d());
   TTIGA_HIP(hipGetLastError());
-  prec(r.d(), zz.d());
+  prec_apply(pp, r.d(), zz.d());
   copy(c, pd.d(), zz.d(), N);
-  double dd[4];
-  auto three = [&]() {  // r.z, z.z, x.x with one synchronisation
-    const double* xs[3] = {r.d(), zz.d(), xk};
-    const double* ys[3] = {zz.d(), zz.d(), xk};
-    dots(N, 3, xs, ys, dd);
-  };
-  three();
-  double rz = dd[0];
-  const double z0 = std::sqrt(std::max(dd[1], 0.0));
-  double zn = z0, xn = std::sqrt(std::max(dd[2], 0.0));
-  const int max_it = 400;
-  for (int it = 0; it < max_it; ++it) {
-    if (zn <= tol_loc * xn || !(rz > 0.0)) break;
-    apply_local(FL, Q.A[k], FR, pd.d(), q.d());
-    {
-      const double* xs[1] = {pd.d()};
-      const double* ys[1] = {q.d()};
-      dots(N, 1, xs, ys, dd);
-    }
-    if (!(dd[0] > 0.0)) break;
-    const double alpha = rz / dd[0];
-    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(N)), dim3(256), 0, c.stream, N, alpha, xk, pd.d(), r.d(), q.d());
-    TTIGA_HIP(hipGetLastError());
-    prec(r.d(), zz.d());
-    three();
-    const double beta = dd[0] / rz;
-    rz = dd[0];
-    zn = std::sqrt(std::max(dd[1], 0.0));
-    xn = std::sqrt(std::max(dd[2], 0.0));
-    hipLaunchKernelGGL(k_xpby, dim3(grid_for(N)), dim3(256), 0, c.stream, N, zz.d(), beta, pd.d());
-    TTIGA_HIP(hipGetLastError());
-    ++local_its;
-  }
+  const double* xs3[3] = {r.d(), zz.d(), xk};
+  const double* ys3[3] = {zz.d(), zz.d(), xk};
+  dots_dev<3, kPostInit>(N, xs3, ys3);
   c.sync();
+  const double z0 = std::sqrt(std::max(hmap[1], 0.0));
+  double rz = hmap[0], zn = z0, xn = std::sqrt(std::max(hmap[2], 0.0));
+  auto iterations = [&]() {
+    const double* xp[1] = {pd.d()};
+    const double* yq[1] = {q.d()};
+    for (int g = 0; g < kGraphIters; ++g) {
+      local_apply(op, pd.d(), q.d());
+      dots_dev<1, kPostAlpha>(N, xp, yq);
+      hipLaunchKernelGGL(k_cg_update_dev, dim3(grid_for(N)), dim3(256), 0, c.stream, N, scal.d() + 2, xk, pd.d(),
+                         r.d(), q.d());
+      prec_apply(pp, r.d(), zz.d());
+      dots_dev<3, kPostBeta>(N, xs3, ys3);
+      hipLaunchKernelGGL(k_xpby_dev, dim3(grid_for(N)), dim3(256), 0, c.stream, N, zz.d(), scal.d() + 3, pd.d());
+    }
+    TTIGA_HIP(hipGetLastError());
+  };
+  static const bool graphs = [] {
+    const char* e = std::getenv("TTIGA_AMEN_GRAPH");
+    return !(e && e[0] == '0');
+  }();
+  struct GraphHold {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~GraphHold() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } gh;
+  // (the legacy default stream cannot be captured: there the launches go out directly)
+  const bool use_graph = graphs && !c.prof.on && c.stream != nullptr;
+  const int max_it = 400;
+  for (int it = 0; it < max_it; it += kGraphIters) {
+    if (zn <= tol_loc * xn || !(rz > 0.0)) break;
+    if (!use_graph) {
+      iterations();
+    } else {
+      if (!gh.x) {
+        TTIGA_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+        try {
+          iterations();
+        } catch (...) {
+          hipGraph_t g0 = nullptr;
+          (void)hipStreamEndCapture(c.stream, &g0);
+          if (g0) (void)hipGraphDestroy(g0);
+          throw;
+        }
+        TTIGA_HIP(hipStreamEndCapture(c.stream, &gh.g));
+        TTIGA_HIP(hipGraphInstantiate(&gh.x, gh.g, nullptr, nullptr, 0));
+      }
+      TTIGA_HIP(hipGraphLaunch(gh.x, c.stream));
+    }
+    c.sync();
+    local_its += kGraphIters;
+    rz = hmap[0];
+    zn = std::sqrt(std::max(hmap[1], 0.0));
+    xn = std::sqrt(std::max(hmap[2], 0.0));
+  }
   return z0 / std::max(xn, 1e-300);
 }
 
@@ -692,7 +878,7 @@ void Amen::run(ttiga_solve_stats& s) {
   const Matvec mv = [&](const TT& v, TT& out) { tt_matvec_banded(c, pr.KII, pr.p, v, out); };
   const double nb = std::sqrt(std::max(tt_dot_sync(c, pr.rhs, pr.rhs), 0.0));
   const int max_half = std::max(2, std::min(pr.opts.max_iter, 60));
-  double prev = 1.0, pres = 1.0, res = 1.0;
+  double pres = 1.0, res = 1.0;
   int half = 0;
   bool conv = false;
   const double tol_loc = 0.3 * tol;
@@ -711,14 +897,17 @@ void Amen::run(ttiga_solve_stats& s) {
     if (trace)
       std::fprintf(stderr, "[amen] half %d max local update %.3e ranks %d %d local its %ld\n", half, dmax, x.r[1],
                    x.r[2], local_its);
-    if (half >= 2 && std::max(prev, dmax) <= tol) {
+    // the global test once a half-sweep's updates are below tol (after the first full sweep)
+    if (half >= 2 && dmax <= tol) {
       // the global test of the TT-CG path on the rounded iterate
       TT u;
       unreversed(c, x, o == 1, u);
       tt_round(c, u, eps_x, -1.0, pr.opts.max_rank);
       TT r, zr;
       int hr = 8, hz = 8;
-      res = true_residual(c, mv, pr.rhs, u, nb, eps_x, pr.opts.max_rank, r, hr, &pr.KII, pr.p);
+      // r only feeds a norm and the two-digit preconditioner, so it is rounded at 1e-2 of itself
+      // (its norm is still read before the truncation where the product is stored)
+      res = true_residual(c, mv, pr.rhs, u, nb, 1e-2, pr.opts.max_rank, r, hr, &pr.KII, pr.p);
       pr.pc.apply(c, r, zr, 1e-2, pr.opts.max_rank, hz);
       const double zz = tt_dot_sync(c, zr, zr), uu = tt_dot_sync(c, u, u);
       pres = std::sqrt(std::max(zz, 0.0) / std::max(uu, 1e-300));
@@ -729,7 +918,6 @@ void Amen::run(ttiga_solve_stats& s) {
         break;
       }
     }
-    prev = dmax;
   }
   if (!conv) {
     TT u;
@@ -737,8 +925,8 @@ void Amen::run(ttiga_solve_stats& s) {
     tt_round(c, u, eps_x, -1.0, pr.opts.max_rank);
     pr.u = std::move(u);
   }
-  // the reported residual: exact norm of the unrounded rhs - K u
-  {
+  // the reported residual: exact norm of the unrounded rhs - K u (the global test's when it passed)
+  if (!conv) {
     TT tmp;
     int hr = 8;
     res = true_residual(c, mv, pr.rhs, pr.u, nb, eps_x, 0, tmp, hr, &pr.KII, pr.p);

@@ -186,7 +186,7 @@ void Profiler::flush() {
     float ms = 0.f;
     TTIGA_HIP(hipEventElapsedTime(&ms, p.a, p.b));
     KernelStat& k = stats[p.name];
-    k.launches += 1;
+    k.launches += p.count;
     k.ms += ms;
     k.flops += p.flops;
     k.bytes += p.bytes;
@@ -218,7 +218,7 @@ Profiler::~Profiler() {
   for (auto e : pool) (void)hipEventDestroy(e);
 }
 
-ProfScope::ProfScope(Context& c, const char* name, double flops, double bytes, int size)
+ProfScope::ProfScope(Context& c, const char* name, double flops, double bytes, int size, bool per_kernel)
     : c_(&c), name_(name), flops_(flops), bytes_(bytes) {
   if (!c.prof.on) return;
   if (c.prof.detail && size >= 0) {
@@ -231,11 +231,30 @@ ProfScope::ProfScope(Context& c, const char* name, double flops, double bytes, i
       }
     name_ += "_c" + std::to_string(b);
   }
+  if (per_kernel) {
+    per_kernel_ = true;
+    return;
+  }
   a_ = c.prof.get();
   TTIGA_HIP(hipEventRecord(a_, c.stream));
 }
 
+void ProfScope::kernel_events(hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
+  if (!per_kernel_) return;
+  *start = c_->prof.get();
+  *stop = c_->prof.get();
+  kev_.emplace_back(*start, *stop);
+}
+
 ProfScope::~ProfScope() {
+  if (per_kernel_) {
+    for (size_t i = 0; i < kev_.size(); ++i)
+      c_->prof.pending.push_back({name_, kev_[i].first, kev_[i].second, i == 0 ? flops_ : 0.0, i == 0 ? bytes_ : 0.0,
+                                  i == 0 ? 1 : 0});
+    if (c_->prof.pending.size() > 4096) c_->prof.flush();
+    return;
+  }
   if (!a_) return;
   hipEvent_t b = c_->prof.get();
   if (hipEventRecord(b, c_->stream) != hipSuccess) {
@@ -244,7 +263,7 @@ ProfScope::~ProfScope() {
     c_->prof.pool.push_back(a_);
     return;
   }
-  c_->prof.pending.push_back({name_, a_, b, flops_, bytes_});
+  c_->prof.pending.push_back({name_, a_, b, flops_, bytes_, 1});
   if (c_->prof.pending.size() > 4096) c_->prof.flush();
 }
 

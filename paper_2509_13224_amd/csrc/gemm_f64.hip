@@ -14,6 +14,7 @@
 // (gemm_plan: a table measured offline by tune_gemm.py, else a fixed rule): the same product
 // runs the same code, with the same summation order, in every problem, process and mix.  K
 // splits write partial tiles that a second kernel adds in a fixed order; there are no atomics.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -370,14 +371,23 @@ GemmPlan gemm_plan(bool ta, bool tb, int M, int N, int K, int batch) {
 }
 
 template <int BM, int BN>
-static void launch_tile(Context& ctx, const GemmPlan& g, bool ta, bool tb, int M, int N, int K,
+static void launch_tile(Context& ctx, ProfScope& prof, const GemmPlan& g, bool ta, bool tb, int M, int N, int K,
                         double alpha, const double* A, long lda, long sA, const double* B, long ldb,
                         long sB, double beta, double* C, long ldc, long sC, int batch, double* part) {
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch * g.splits);
   dim3 block(256);
-#define TTIGA_GEMM_LAUNCH(TA, TB)                                                                   \
-  hipLaunchKernelGGL((k_gemm_f64<TA, TB, BM, BN>), grid, block, 0, ctx.stream, M, N, K, alpha, A, lda, \
-                     sA, B, ldb, sB, beta, C, ldc, sC, g.splits, g.kchunk, part)
+  hipEvent_t e0, e1;
+  prof.kernel_events(&e0, &e1);
+  // the plain launch unless timed (a stream under graph capture is never timed)
+#define TTIGA_GEMM_LAUNCH(TA, TB)                                                                               \
+  do {                                                                                                          \
+    if (e0)                                                                                                     \
+      hipExtLaunchKernelGGL((k_gemm_f64<TA, TB, BM, BN>), grid, block, 0, ctx.stream, e0, e1, 0, M, N, K, alpha, \
+                            A, lda, sA, B, ldb, sB, beta, C, ldc, sC, g.splits, g.kchunk, part);                  \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_gemm_f64<TA, TB, BM, BN>), grid, block, 0, ctx.stream, M, N, K, alpha, A, lda, sA, B, \
+                         ldb, sB, beta, C, ldc, sC, g.splits, g.kchunk, part);                                     \
+  } while (0)
   if (!ta && !tb) TTIGA_GEMM_LAUNCH(false, false);
   else if (ta && !tb) TTIGA_GEMM_LAUNCH(true, false);
   else if (!ta && tb) TTIGA_GEMM_LAUNCH(false, true);
@@ -391,15 +401,22 @@ void gemm_planned(Context& ctx, const GemmPlan& g, bool ta, bool tb, int M, int 
                   double* C, long ldc, long sC, int batch, double* part) {
   TTIGA_CHECK(batch <= 65535 / std::max(1, g.splits), TTIGA_E_ARG, "gemm: batch too large");
   TTIGA_CHECK((M + g.bm - 1) / g.bm <= 65535, TTIGA_E_ARG, "gemm: M too large for the grid");
+  // timed per kernel: most products here take a few microseconds
   ProfScope prof(ctx, "gemm_f64", 2.0 * M * N * (double)K * batch,
-                 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N));
-  if (g.bm == 128) launch_tile<128, 64>(ctx, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
-  else if (g.bn == 128) launch_tile<64, 128>(ctx, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
-  else launch_tile<64, 64>(ctx, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
+                 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N), -1, true);
+  if (g.bm == 128) launch_tile<128, 64>(ctx, prof, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
+  else if (g.bn == 128) launch_tile<64, 128>(ctx, prof, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
+  else launch_tile<64, 64>(ctx, prof, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
   if (g.splits > 1) {
     const long total = (long)batch * M * N;
-    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(total)), dim3(256), 0, ctx.stream, M, N, g.splits,
-                       batch, alpha, part, beta, C, ldc, sC);
+    hipEvent_t e0, e1;
+    prof.kernel_events(&e0, &e1);
+    if (e0)
+      hipExtLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(total)), dim3(256), 0, ctx.stream, e0, e1, 0, M, N,
+                            g.splits, batch, alpha, (const double*)part, beta, C, ldc, sC);
+    else
+      hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(total)), dim3(256), 0, ctx.stream, M, N, g.splits, batch,
+                         alpha, (const double*)part, beta, C, ldc, sC);
     TTIGA_HIP(hipGetLastError());
   }
 }

@@ -887,11 +887,18 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
 
 // ------------------------------------------------------------------ Cholesky
 // One workgroup: upper Cholesky factor R of an SPD matrix G (c x c, row-major),
-// R^T R = G, and its inverse Rinv (upper).  Used for the 1-D mass matrices of
-// the preconditioner (a few hundred rows).
+// R^T R = G, and its inverse Rinv (upper).  Used for the 1-D mass matrices of the
+// preconditioner (a few hundred rows: the work arrays in global memory) and for the small
+// frame matrices of the AMEn local preconditioner (kLds: R and Rinv built in LDS, c <= 56,
+// then copied out; every step is a barrier, so LDS instead of global memory is most of the
+// cost of a small factorisation).
+template <bool kLds>
 __global__ __launch_bounds__(256) void k_chol_inv(int c, const double* __restrict__ G,
-                                                  double* __restrict__ R, double* __restrict__ Rinv,
+                                                  double* __restrict__ Rg, double* __restrict__ Rinvg,
                                                   double* __restrict__ status) {
+  extern __shared__ double sm[];
+  double* R = kLds ? sm : Rg;
+  double* Rinv = kLds ? sm + (long)c * c : Rinvg;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (long e = tid; e < (long)c * c; e += nt) {
     const int i = e / c, k = e % c;
@@ -924,12 +931,23 @@ __global__ __launch_bounds__(256) void k_chol_inv(int c, const double* __restric
       Rinv[(long)i * c + j] = -acc / R[(long)i * c + i];
     }
   }
+  if (kLds) {
+    __syncthreads();
+    for (long e = tid; e < (long)c * c; e += nt) {
+      Rg[e] = R[e];
+      Rinvg[e] = Rinv[e];
+    }
+  }
 }
 
 bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* Rinv) {
   DBuf st(ctx.alloc, sizeof(double));
   fill(ctx, st.d(), 1, 0.0);
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, ctx.stream, c, G, R, Rinv, st.d());
+  if (c <= 56)
+    hipLaunchKernelGGL(k_chol_inv<true>, dim3(1), dim3(256), 2 * sizeof(double) * c * c, ctx.stream, c, G, R, Rinv,
+                       st.d());
+  else
+    hipLaunchKernelGGL(k_chol_inv<false>, dim3(1), dim3(256), 0, ctx.stream, c, G, R, Rinv, st.d());
   TTIGA_HIP(hipGetLastError());
   double* h = ctx.host(1);
   TTIGA_HIP(hipMemcpyAsync(h, st.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
@@ -1265,13 +1283,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double*
 // Gram-Schmidt on the rows of Q (QR with column pivoting of Q^T): step l takes the row
 // with the largest residual norm and removes its direction from every row, so the k rows
 // chosen span the column space as well as any greedy choice can (the selection of
-// Q-DEIM).  One workgroup; W (n x k) is a global work copy; the norms live in LDS, or in
-// global memory (nrm_g) when n does not fit there.
+// Q-DEIM).  One workgroup; W (n x k) is a global work copy; norms live in LDS.
 __global__ __launch_bounds__(1024) void k_pivot_rows(int n, int k, const double* __restrict__ Q,
-                                                     double* __restrict__ W, int* __restrict__ rows,
-                                                     double* __restrict__ nrm_g) {
-  extern __shared__ double nrm_lds[];
-  double* nrm = nrm_g ? nrm_g : nrm_lds;  // n residual norms (negative once chosen)
+                                                     double* __restrict__ W, int* __restrict__ rows) {
+  extern __shared__ double nrm[];  // n residual norms (negative once chosen)
   __shared__ double s_v[256];
   __shared__ double s_best[32];
   __shared__ int s_bi[32];
@@ -1327,14 +1342,103 @@ __global__ __launch_bounds__(1024) void k_pivot_rows(int n, int k, const double*
   }
 }
 
+// The same selection for long bases (n > 6144 rows), spread over the device: one step is a
+// launch that finds each block's largest residual norm, a one-block launch that takes the
+// largest of those (ties: smallest index), records it and normalises its row into v, and a
+// launch that removes v from every remaining row.  Each row is updated with the arithmetic of
+// k_pivot_rows, so both pick the same rows.
+__global__ void __launch_bounds__(256) k_piv_init(int n, int k, const double* __restrict__ Q, double* __restrict__ W,
+                                                  double* __restrict__ nrm) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    double ss = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double w = Q[(long)i * k + j];
+      W[(long)i * k + j] = w;
+      ss += w * w;
+    }
+    nrm[i] = ss;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_piv_partial(int n, const double* __restrict__ nrm, double* __restrict__ pbest,
+                                                     int* __restrict__ pidx) {
+  __shared__ double s_b[4];
+  __shared__ int s_i[4];
+  double best = -1.0;
+  int bi = n;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    if (nrm[i] > best) { best = nrm[i]; bi = i; }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  if ((threadIdx.x & 63) == 0) { s_b[threadIdx.x >> 6] = best; s_i[threadIdx.x >> 6] = bi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (s_b[w] > best || (s_b[w] == best && s_i[w] < bi)) { best = s_b[w]; bi = s_i[w]; }
+    pbest[blockIdx.x] = best;
+    pidx[blockIdx.x] = bi;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_piv_select(int nb, const double* __restrict__ pbest,
+                                                    const int* __restrict__ pidx, int k, const double* __restrict__ W,
+                                                    double* __restrict__ v, double* __restrict__ nrm,
+                                                    int* __restrict__ rows, int l) {
+  __shared__ int s_p;
+  if (threadIdx.x == 0) {
+    double b = -1.0;
+    int p = 0x7fffffff;
+    for (int q = 0; q < nb; ++q)
+      if (pbest[q] > b || (pbest[q] == b && pidx[q] < p)) { b = pbest[q]; p = pidx[q]; }
+    s_p = p;
+    rows[l] = p;
+  }
+  __syncthreads();
+  const int p = s_p;
+  const double np_ = sqrt(fmax(nrm[p], 0.0));
+  for (int j = threadIdx.x; j < k; j += 256) v[j] = np_ > 0.0 ? W[(long)p * k + j] / np_ : 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) nrm[p] = -1.0;
+}
+
+__global__ void __launch_bounds__(256) k_piv_update(int n, int k, const double* __restrict__ v, double* __restrict__ W,
+                                                    double* __restrict__ nrm) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    if (nrm[i] < 0.0) continue;
+    double cf = 0.0;
+    for (int j = 0; j < k; ++j) cf += W[(long)i * k + j] * v[j];
+    double ss = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double w = W[(long)i * k + j] - cf * v[j];
+      W[(long)i * k + j] = w;
+      ss += w * w;
+    }
+    nrm[i] = ss;
+  }
+}
+
 void pivot_rows(Context& ctx, const double* Q, int n, int k, int* rows) {
   TTIGA_CHECK(n > 0 && k > 0 && k <= 256 && k <= n, TTIGA_E_ARG, "pivot_rows: bad shape");
   DBuf W(ctx.alloc, sizeof(double) * (size_t)n * k);
-  const bool lds = n <= 6144;
-  DBuf G(ctx.alloc, lds ? 0 : sizeof(double) * (size_t)n);
   ProfScope prof(ctx, "pivot_rows", 4.0 * n * (double)k * k, 16.0 * n * (double)k * k);
-  hipLaunchKernelGGL(k_pivot_rows, dim3(1), dim3(1024), lds ? sizeof(double) * n : 0, ctx.stream, n, k, Q, W.d(), rows,
-                     lds ? nullptr : G.d());
+  if (n <= 6144) {
+    hipLaunchKernelGGL(k_pivot_rows, dim3(1), dim3(1024), sizeof(double) * n, ctx.stream, n, k, Q, W.d(), rows);
+    TTIGA_HIP(hipGetLastError());
+    return;
+  }
+  const int nb = std::min(1024, (n + 255) / 256);
+  DBuf nrm(ctx.alloc, sizeof(double) * (size_t)n), v(ctx.alloc, sizeof(double) * k),
+      pbest(ctx.alloc, sizeof(double) * nb), pidx(ctx.alloc, sizeof(int) * nb);
+  hipLaunchKernelGGL(k_piv_init, dim3(nb), dim3(256), 0, ctx.stream, n, k, Q, W.d(), nrm.d());
+  for (int l = 0; l < k; ++l) {
+    hipLaunchKernelGGL(k_piv_partial, dim3(nb), dim3(256), 0, ctx.stream, n, nrm.d(), pbest.d(), pidx.as<int>());
+    hipLaunchKernelGGL(k_piv_select, dim3(1), dim3(256), 0, ctx.stream, nb, pbest.d(), pidx.as<int>(), k, W.d(),
+                       v.d(), nrm.d(), rows, l);
+    hipLaunchKernelGGL(k_piv_update, dim3(nb), dim3(256), 0, ctx.stream, n, k, v.d(), W.d(), nrm.d());
+  }
   TTIGA_HIP(hipGetLastError());
 }
 

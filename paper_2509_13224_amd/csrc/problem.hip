@@ -237,19 +237,51 @@ static uint64_t splitmix(uint64_t& state) {
   return z ^ (z >> 31);
 }
 
+// idx0[e], idx1[e], idx2[e] for e = (x a1 + y) a2 + z: the grid points of the product of three
+// index lists (a null list: 0 .. a-1)
+__global__ void k_product_indices(int a0, int a1, int a2, const int* __restrict__ L0, const int* __restrict__ L1,
+                                  const int* __restrict__ L2, int* __restrict__ i0, int* __restrict__ i1,
+                                  int* __restrict__ i2) {
+  const long total = (long)a0 * a1 * a2;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int z = (int)(e % a2);
+    const long t = e / a2;
+    const int y = (int)(t % a1), x = (int)(t / a1);
+    i0[e] = L0 ? L0[x] : x;
+    i1[e] = L1 ? L1[y] : y;
+    i2[e] = L2 ? L2[z] : z;
+  }
+}
+
+// The seven factors at the product of three index lists (device lists, null: the whole range),
+// into out[7][a0 a1 a2].
+static void sample_product(Context& c, const GeoDev& gd, const SourceDev& sd, const int* L0, int a0, const int* L1,
+                           int a1, const int* L2, int a2, double* out) {
+  const long cnt = (long)a0 * a1 * a2;
+  DBuf idx(c.alloc, sizeof(int) * 3 * cnt);
+  int* di = idx.as<int>();
+  hipLaunchKernelGGL(k_product_indices, dim3(grid_for(cnt)), dim3(256), 0, c.stream, a0, a1, a2, L0, L1, L2, di,
+                     di + cnt, di + 2 * cnt);
+  TTIGA_HIP(hipGetLastError());
+  launch_factors_at(c, gd, sd, cnt, di, di + cnt, di + 2 * cnt, out, nullptr);
+}
+
 // Second level of the cross approximation: with the first-mode bases U_t (Q0 x k_t), the
 // interpolation rows I and P_t^+ = U_t[I, :]^+, the coefficient tensor X_t = P_t^+ A_t[I, :, :]
 // (k_t x Q1 x Q2) is approximated in the same way along its last mode instead of being formed:
 //  a. L2 random third-direction indices j: the fibres X_t[:, :, j] from the samples A[I, :, j]
 //     (|I| Q1 L2 points), their column basis V_t ((k_t Q1) x k2_t, truncated at 0.1 eps of the
-//     largest metric sample scale), L2 doubling while a rank comes within 8 of it;
+//     largest metric sample scale), L2 doubling while a rank comes within 12 of it;
 //  b. interpolation rows R_t of V_t (pivoted Gram-Schmidt on its rows, as for U_t); the rows
 //     (a, i1) need the samples A[I, i1, :] for the distinct i1 of all R_t plus 8 random ones
 //     (|I| |S| Q2 points), giving X_t[R_t, :];
-//  c. X_t ~= V_t D_t with D_t = V_t[R_t, :]^+ X_t[R_t, :] (k2_t x Q2); the TT of the factor is
-//     (U_t, V_t as k_t x Q1 x k2_t, D_t), rounded at eps of its scale like the TT-SVD path.
-// Declines (the caller samples the whole slices) when a basis saturates its largest sample,
-// when V_t[R_t, :] is ill-conditioned or when the grid is too small for it to pay.
+//  c. X_t ~= V_t D_t with D_t the least-squares solution over all the sampled rows (a, i1),
+//     i1 in S, of X_t (k_t |S| rows: the pivots and the rest of their slices, an oversampling
+//     that keeps the interpolation well conditioned); the TT of the factor is (U_t, V_t as
+//     k_t x Q1 x k2_t, D_t), rounded at eps of its scale like the TT-SVD path.
+// Declines (the caller samples the whole slices) when a basis comes within 12 of its largest
+// sample, when the sampled rows of V_t are ill-conditioned or when the grid is too small for it
+// to pay; the caller also takes the slices when the result fails the probe check.
 bool Problem::cross_second_level(const GeoDev& gd, const SourceDev& sd, TT* fac, ttiga_assembly_stats& s,
                                  const std::vector<DBuf>& U, const std::vector<int>& k, const std::vector<int>& I,
                                  const DBuf& Id, const std::vector<DBuf>& Pinv, double* scale, uint64_t& rs) {
@@ -268,21 +300,9 @@ bool Problem::cross_second_level(const GeoDev& gd, const SourceDev& sd, TT* fac,
     std::vector<int> J(L2);
     for (int q = 0; q < L2; ++q) J[q] = rnd(n2);
     const long cnt = (long)nI * n1 * L2;
-    std::vector<int> h0(cnt), h1(cnt), h2(cnt);
-    for (int a = 0; a < nI; ++a)
-      for (int i1 = 0; i1 < n1; ++i1)
-        for (int q = 0; q < L2; ++q) {
-          const long e = ((long)a * n1 + i1) * L2 + q;
-          h0[e] = I[a];
-          h1[e] = i1;
-          h2[e] = J[q];
-        }
-    DBuf idx(c.alloc, sizeof(int) * 3 * cnt), Af(c.alloc, sizeof(double) * 7 * cnt);
-    int* di = idx.as<int>();
-    TTIGA_HIP(hipMemcpyAsync(di, h0.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
-    TTIGA_HIP(hipMemcpyAsync(di + cnt, h1.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
-    TTIGA_HIP(hipMemcpyAsync(di + 2 * cnt, h2.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
-    launch_factors_at(c, gd, sd, cnt, di, di + cnt, di + 2 * cnt, Af.d(), nullptr);
+    DBuf Jd(c.alloc, sizeof(int) * L2), Af(c.alloc, sizeof(double) * 7 * cnt);
+    TTIGA_HIP(hipMemcpyAsync(Jd.d(), J.data(), sizeof(int) * L2, hipMemcpyHostToDevice, c.stream));
+    sample_product(c, gd, sd, Id.as<int>(), nI, nullptr, n1, Jd.as<int>(), L2, Af.d());
     s.samples += cnt;
     // C_t = P_t^+ A_t[I, :, J]: (k_t) x (Q1 L2), read as (k_t Q1) x L2
     std::vector<DBuf> C(7);
@@ -297,7 +317,7 @@ bool Problem::cross_second_level(const GeoDev& gd, const SourceDev& sd, TT* fac,
     }
     double* hc = c.host(7);
     TTIGA_HIP(hipMemcpyAsync(hc, csq.d(), 7 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    c.sync();  // the host index arrays go out of scope
+    c.sync();  // J goes out of scope
     double cmax = 0.0;
     for (int t = 0; t < 6; ++t) cmax = std::max(cmax, std::sqrt(std::max(hc[t], 0.0)));
     bool saturated = false;
@@ -306,7 +326,7 @@ bool Problem::cross_second_level(const GeoDev& gd, const SourceDev& sd, TT* fac,
       k2[t] = (k[t] && cs > 0.0 && (long)k[t] * n1 >= L2) ? column_basis(c, C[t].d(), k[t] * n1, L2, 0.1 * eps * cs, V[t])
                                                          : 0;
       if (k[t] && (long)k[t] * n1 < L2) return false;
-      if (k2[t] > L2 - 8) saturated = true;
+      if (k2[t] > L2 - 12) saturated = true;
     }
     if (!saturated) break;
     if (L2 == cap) return false;
@@ -325,74 +345,60 @@ bool Problem::cross_second_level(const GeoDev& gd, const SourceDev& sd, TT* fac,
     for (int r : R[t]) pick[r % n1] = 1;
   }
   for (int e = 0; e < 8; ++e) pick[rnd(n1)] = 1;
-  std::vector<int> S, pos(n1, -1);
+  std::vector<int> S;
   for (int i1 = 0; i1 < n1; ++i1)
-    if (pick[i1]) {
-      pos[i1] = (int)S.size();
-      S.push_back(i1);
-    }
+    if (pick[i1]) S.push_back(i1);
   const int nS = (int)S.size();
   if (2 * nS > n1) return false;
   // the samples A[i0, i1, :] for i0 in I, i1 in S; E_t = P_t^+ A_t[I, S, :] (k_t x |S| Q2)
   const long cnt = (long)nI * nS * n2;
-  std::vector<int> h0(cnt), h1(cnt), h2(cnt);
-  for (int a = 0; a < nI; ++a)
-    for (int q = 0; q < nS; ++q)
-      for (int i2 = 0; i2 < n2; ++i2) {
-        const long e = ((long)a * nS + q) * n2 + i2;
-        h0[e] = I[a];
-        h1[e] = S[q];
-        h2[e] = i2;
-      }
-  DBuf idx(c.alloc, sizeof(int) * 3 * cnt), As(c.alloc, sizeof(double) * 7 * cnt);
-  int* di = idx.as<int>();
-  TTIGA_HIP(hipMemcpyAsync(di, h0.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
-  TTIGA_HIP(hipMemcpyAsync(di + cnt, h1.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
-  TTIGA_HIP(hipMemcpyAsync(di + 2 * cnt, h2.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, c.stream));
-  launch_factors_at(c, gd, sd, cnt, di, di + cnt, di + 2 * cnt, As.d(), nullptr);
+  DBuf Sd(c.alloc, sizeof(int) * nS), As(c.alloc, sizeof(double) * 7 * cnt);
+  TTIGA_HIP(hipMemcpyAsync(Sd.d(), S.data(), sizeof(int) * nS, hipMemcpyHostToDevice, c.stream));
+  sample_product(c, gd, sd, Id.as<int>(), nI, Sd.as<int>(), nS, nullptr, n2, As.d());
   s.samples += cnt;
-  c.sync();  // the host index arrays go out of scope
-  // c. D_t = V_t[R_t, :]^+ X_t[R_t, :] and the TT (U_t, V_t, D_t)
+  c.sync();  // S may go out of scope
+  // c. D_t = V_t[S_t, :]^+ X_t[S_t, :], least squares over every sampled row (a, i1 in S) of X_t
+  // (k_t |S| rows, the pivots R_t among them), and the TT (U_t, V_t, D_t)
   double nrm[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int t = 0; t < 7; ++t) {
     if (!k2[t]) {
       fac[t].set_zero(Q);
       continue;
     }
-    const int kt = k[t], k2t = k2[t];
-    DBuf E(c.alloc, sizeof(double) * (size_t)kt * nS * n2);
+    const int kt = k[t], k2t = k2[t], ms = kt * nS;
+    if (ms < k2t) return false;
+    // E = P_t^+ A_t[I, S, :]: k_t x |S| Q2, read as (k_t |S|) x Q2 with row a |S| + q
+    DBuf E(c.alloc, sizeof(double) * (size_t)ms * n2);
     gemm(c, false, false, kt, nS * n2, nI, 1.0, Pinv[t].d(), nI, 0, As.d() + (size_t)t * cnt, (long)nS * n2, 0, 0.0,
          E.d(), (long)nS * n2, 0);
-    // rows of X_t at R_t: row (a, i1) of X_t is row a * |S| + pos(i1) of E viewed as (k_t |S|) x Q2
-    std::vector<int> er(k2t), vr(k2t);
-    for (int q = 0; q < k2t; ++q) {
-      const int a = R[t][q] / n1, i1 = R[t][q] % n1;
-      er[q] = a * nS + pos[i1];
-      vr[q] = R[t][q];
-    }
-    DBuf erd(c.alloc, sizeof(int) * k2t), vrd(c.alloc, sizeof(int) * k2t);
-    TTIGA_HIP(hipMemcpyAsync(erd.d(), er.data(), sizeof(int) * k2t, hipMemcpyHostToDevice, c.stream));
-    TTIGA_HIP(hipMemcpyAsync(vrd.d(), vr.data(), sizeof(int) * k2t, hipMemcpyHostToDevice, c.stream));
-    DBuf XR(c.alloc, sizeof(double) * (size_t)k2t * n2), VR(c.alloc, sizeof(double) * (size_t)k2t * k2t);
-    gather_rows(c, E.d(), n2, erd.as<int>(), k2t, XR.d());
-    gather_rows(c, V[t].d(), k2t, vrd.as<int>(), k2t, VR.d());
-    DBuf Uv(c.alloc, sizeof(double) * k2t * k2t), Sv(c.alloc, sizeof(double) * k2t), Wv(c.alloc, sizeof(double) * k2t * k2t);
-    svd_small(c, VR.d(), false, k2t, k2t, k2t, Uv.d(), Sv.d(), Wv.d());
+    // the same rows of V_t: row a Q1 + S[q]
+    std::vector<int> vr(ms);
+    for (int a = 0; a < kt; ++a)
+      for (int q = 0; q < nS; ++q) vr[(size_t)a * nS + q] = a * n1 + S[q];
+    DBuf vrd(c.alloc, sizeof(int) * ms), VS(c.alloc, sizeof(double) * (size_t)ms * k2t);
+    TTIGA_HIP(hipMemcpyAsync(vrd.d(), vr.data(), sizeof(int) * ms, hipMemcpyHostToDevice, c.stream));
+    gather_rows(c, V[t].d(), k2t, vrd.as<int>(), ms, VS.d());
+    // V_S = Qv Rv, Rv = Ur diag(sv) Wr^T: D = Wr diag(1/sv) Ur^T Qv^T E
+    DBuf Qv(c.alloc, sizeof(double) * (size_t)ms * k2t), Rv(c.alloc, sizeof(double) * k2t * k2t),
+        Ur(c.alloc, sizeof(double) * k2t * k2t), Sv(c.alloc, sizeof(double) * k2t), Wr(c.alloc, sizeof(double) * k2t * k2t);
+    qr_tall(c, VS.d(), false, ms, k2t, k2t, Qv.d(), Rv.d());
+    svd_small(c, Rv.d(), false, k2t, k2t, k2t, Ur.d(), Sv.d(), Wr.d());
     double* h = c.host(2);
     TTIGA_HIP(hipMemcpyAsync(h, Sv.d(), sizeof(double), hipMemcpyDeviceToHost, c.stream));
     TTIGA_HIP(hipMemcpyAsync(h + 1, Sv.d() + (k2t - 1), sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    c.sync();  // er, vr go out of scope
+    c.sync();  // vr goes out of scope
     if (!(h[1] > 1e-8 * h[0])) return false;
-    // VR^+ = W S^-1 Uv^T; D = VR^+ XR
-    DBuf WS(c.alloc, sizeof(double) * k2t * k2t), VRp(c.alloc, sizeof(double) * k2t * k2t);
-    scale_cols_inv(c, Wv.d(), k2t, k2t, Sv.d(), WS.d());
-    gemm(c, false, true, k2t, k2t, k2t, 1.0, WS.d(), k2t, 0, Uv.d(), k2t, 0, 0.0, VRp.d(), k2t, 0);
+    DBuf T1(c.alloc, sizeof(double) * (size_t)k2t * n2), T2(c.alloc, sizeof(double) * (size_t)k2t * n2),
+        WS(c.alloc, sizeof(double) * k2t * k2t);
+    gemm(c, true, false, k2t, n2, ms, 1.0, Qv.d(), k2t, 0, E.d(), n2, 0, 0.0, T1.d(), n2, 0);
+    gemm(c, true, false, k2t, n2, k2t, 1.0, Ur.d(), k2t, 0, T1.d(), n2, 0, 0.0, T2.d(), n2, 0);
+    scale_cols_inv(c, Wr.d(), k2t, k2t, Sv.d(), WS.d());
     TT tt;
     const int rr[4] = {1, kt, k2t, 1};
     tt.alloc(c, Q, rr);
     copy(c, tt.c[0].d(), U[t].d(), (size_t)Q[0] * kt);
     copy(c, tt.c[1].d(), V[t].d(), (size_t)kt * n1 * k2t);
-    gemm(c, false, false, k2t, n2, k2t, 1.0, VRp.d(), k2t, 0, XR.d(), n2, 0, 0.0, tt.c[2].d(), n2, 0);
+    gemm(c, false, false, k2t, n2, k2t, 1.0, WS.d(), k2t, 0, T2.d(), n2, 0, 0.0, tt.c[2].d(), n2, 0);
     nrm[t] = std::sqrt(std::max(tt_dot_sync(c, tt, tt), 0.0));
     fac[t] = std::move(tt);
   }
@@ -418,8 +424,10 @@ bool Problem::cross_second_level(const GeoDev& gd, const SourceDev& sd, TT* fac,
 //     a basis within 8 of L means the columns may miss directions: L doubles;
 //  2. interpolation rows: the pivoted rows of each U (column-pivoted QR of U^T), their
 //     union I plus 8 random rows;
-//  3. the slices A[I, :, :] only (|I| of Q0), streamed in second-direction chunks, give
-//     X = U[I, :]^+ A[I, :], so that A_(0) ~= U X (interpolation through the rows I);
+//  3. X = U[I, :]^+ A[I, :], so that A_(0) ~= U X (interpolation through the rows I): by a
+//     second level of the same construction along the last mode (cross_second_level), or
+//     from the slices A[I, :, :] only (|I| of Q0), streamed in second-direction chunks, when
+//     the second level declines or its result fails the probe check of step 5;
 //  4. ||A||_F ~= ||X||_F sets the thresholds; U, X continue as in TT-SVD (truncated SVD
 //     of X, dense factorisation of the rest);
 //  5. 2048 random grid points compare the TTs with directly sampled values: a factor
@@ -529,83 +537,96 @@ bool Problem::compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, tti
     gemm(c, false, true, kt, nI, kt, 1.0, VS.d(), kt, 0, Up.d(), kt, 0, 0.0, Pinv[t].d(), nI, 0);
   }
   double scale[7];
-  // 3. the coefficients X_t = P_t^+ A_t[I, :] (k_t x Q1 Q2): by a second cross approximation of X_t
-  // viewed as (k_t Q1) x Q2 when it succeeds (samples of O(Q r^2)), else from the whole slices
-  // A_t[I, :, :] (|I| Q1 Q2 samples)
-  if (cross_second_level(gd, sd, fac, s, U, k, I, Id, Pinv, scale, rs)) {
-    if (trace) std::fprintf(stderr, "[cross] second level accepted\n");
-  } else {
-  for (int t = 0; t < 7; ++t)
-    if (k[t]) X[t] = DBuf(c.alloc, sizeof(double) * (size_t)k[t] * M);
-  {
-    const size_t slab = sizeof(double) * 7 * (size_t)nI * n2;
-    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(n1, (size_t(2) << 30) / slab));
-    DBuf buf(c.alloc, slab * chunk), st(c.alloc, sizeof(double) * 8);
-    for (int b = 0; b < n1; b += chunk) {
-      const int cn = std::min(chunk, n1 - b);
-      const long w = (long)cn * n2;
-      launch_factors_grid(c, gd, sd, Q, b, cn, buf.d(), st.d(), false, Id.as<int>(), nI);
-      for (int t = 0; t < 7; ++t)
-        if (k[t])
-          gemm(c, false, false, k[t], (int)w, nI, 1.0, Pinv[t].d(), nI, 0, buf.d() + (size_t)t * nI * w, w, 0,
-               0.0, X[t].d() + (size_t)b * n2, M, 0);
+  // the whole-slice path of step 3
+  auto slices = [&]() {
+    for (int t = 0; t < 7; ++t)
+      if (k[t]) X[t] = DBuf(c.alloc, sizeof(double) * (size_t)k[t] * M);
+    {
+      const size_t slab = sizeof(double) * 7 * (size_t)nI * n2;
+      const int chunk = (int)std::max<size_t>(1, std::min<size_t>(n1, (size_t(2) << 30) / slab));
+      DBuf buf(c.alloc, slab * chunk), st(c.alloc, sizeof(double) * 8);
+      for (int b = 0; b < n1; b += chunk) {
+        const int cn = std::min(chunk, n1 - b);
+        const long w = (long)cn * n2;
+        launch_factors_grid(c, gd, sd, Q, b, cn, buf.d(), st.d(), false, Id.as<int>(), nI);
+        for (int t = 0; t < 7; ++t)
+          if (k[t])
+            gemm(c, false, false, k[t], (int)w, nI, 1.0, Pinv[t].d(), nI, 0, buf.d() + (size_t)t * nI * w, w, 0,
+                 0.0, X[t].d() + (size_t)b * n2, M, 0);
+      }
+      s.samples += (long long)nI * M;
     }
-    s.samples += (long long)nI * M;
-  }
-  // 4. thresholds from ||X|| and the TT-SVD tail
-  DBuf ssq(c.alloc, sizeof(double) * 7);
-  fill(c, ssq.d(), 7, 0.0);
-  for (int t = 0; t < 7; ++t)
-    if (k[t]) sumsq_reduce(c, X[t].d(), (size_t)k[t] * M, ssq.d() + t);
-  double* h = c.host(7);
-  TTIGA_HIP(hipMemcpyAsync(h, ssq.d(), 7 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-  c.sync();
-  double nrm[7], rmax = 0.0;
-  for (int t = 0; t < 7; ++t) nrm[t] = std::sqrt(std::max(h[t], 0.0));
-  for (int t = 0; t < 6; ++t) rmax = std::max(rmax, nrm[t]);
-  s.max_R_norm = rmax;
-  for (int t = 0; t < 7; ++t) scale[t] = t < 6 ? rmax : nrm[6];
-  for (int t = 0; t < 7; ++t) {
-    if (k[t] == 0 || nrm[t] == 0.0) {
-      fac[t].set_zero(Q);
-      continue;
+    // 4. thresholds from ||X|| and the TT-SVD tail
+    DBuf ssq(c.alloc, sizeof(double) * 7);
+    fill(c, ssq.d(), 7, 0.0);
+    for (int t = 0; t < 7; ++t)
+      if (k[t]) sumsq_reduce(c, X[t].d(), (size_t)k[t] * M, ssq.d() + t);
+    double* h = c.host(7);
+    TTIGA_HIP(hipMemcpyAsync(h, ssq.d(), 7 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    double nrm[7], rmax = 0.0;
+    for (int t = 0; t < 7; ++t) nrm[t] = std::sqrt(std::max(h[t], 0.0));
+    for (int t = 0; t < 6; ++t) rmax = std::max(rmax, nrm[t]);
+    s.max_R_norm = rmax;
+    for (int t = 0; t < 7; ++t) scale[t] = t < 6 ? rmax : nrm[6];
+    for (int t = 0; t < 7; ++t) {
+      if (k[t] == 0 || nrm[t] == 0.0) {
+        fac[t].set_zero(Q);
+        continue;
+      }
+      tt_from_first_unfolding(c, U[t].d(), k[t], X[t].d(), Q, eps * scale[t] / std::sqrt(2.0), 0, fac[t],
+                              opts.max_rank);
     }
-    tt_from_first_unfolding(c, U[t].d(), k[t], X[t].d(), Q, eps * scale[t] / std::sqrt(2.0), 0, fac[t],
-                            opts.max_rank);
-  }
-  }  // whole slices
-  // 5. probe check on random grid points
-  const int P = 2048;
-  std::vector<int> p0(P), p1(P), p2(P);
-  for (int q = 0; q < P; ++q) {
-    p0[q] = rnd(n0);
-    p1[q] = rnd(n1);
-    p2[q] = rnd(n2);
-  }
-  DBuf pid(c.alloc, sizeof(int) * 3 * P), ref(c.alloc, sizeof(double) * 7 * P), got(c.alloc, sizeof(double) * 7 * P);
-  int* dp = pid.as<int>();
-  TTIGA_HIP(hipMemcpyAsync(dp, p0.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
-  TTIGA_HIP(hipMemcpyAsync(dp + P, p1.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
-  TTIGA_HIP(hipMemcpyAsync(dp + 2 * P, p2.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
-  launch_factors_at(c, gd, sd, P, dp, dp + P, dp + 2 * P, ref.d(), nullptr);
-  for (int t = 0; t < 7; ++t) tt_eval_points(c, fac[t], P, dp, dp + P, dp + 2 * P, got.d() + (size_t)t * P);
-  std::vector<double> hr((size_t)7 * P), hg((size_t)7 * P);
-  TTIGA_HIP(hipMemcpyAsync(hr.data(), ref.d(), sizeof(double) * 7 * P, hipMemcpyDeviceToHost, c.stream));
-  TTIGA_HIP(hipMemcpyAsync(hg.data(), got.d(), sizeof(double) * 7 * P, hipMemcpyDeviceToHost, c.stream));
-  c.sync();
-  s.samples += P;
-  const double npts = (double)n0 * M;
-  for (int t = 0; t < 7; ++t) {
-    double e2 = 0.0;
+    for (int t = 0; t < 7; ++t) X[t].reset();
+  };
+  // 5. probe check on random grid points: every factor's RMS error per point within 10 eps of its
+  // threshold scale spread over the grid
+  auto probe = [&]() {
+    const int P = 2048;
+    std::vector<int> p0(P), p1(P), p2(P);
     for (int q = 0; q < P; ++q) {
-      const double d = hg[(size_t)t * P + q] - hr[(size_t)t * P + q];
-      e2 += d * d;
+      p0[q] = rnd(n0);
+      p1[q] = rnd(n1);
+      p2[q] = rnd(n2);
     }
-    // RMS error per point against the threshold scale spread over the grid
-    const double rms = std::sqrt(e2 / P), allowed = 10.0 * eps * scale[t] / std::sqrt(npts);
-    if (trace) std::fprintf(stderr, "[cross] factor %d probe rms %.3e allowed %.3e\n", t, rms, allowed);
-    if (!(rms <= allowed) && !(scale[t] == 0.0 && e2 == 0.0)) return reject("probe error above 10 eps");
+    DBuf pid(c.alloc, sizeof(int) * 3 * P), ref(c.alloc, sizeof(double) * 7 * P), got(c.alloc, sizeof(double) * 7 * P);
+    int* dp = pid.as<int>();
+    TTIGA_HIP(hipMemcpyAsync(dp, p0.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(dp + P, p1.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(dp + 2 * P, p2.data(), sizeof(int) * P, hipMemcpyHostToDevice, c.stream));
+    launch_factors_at(c, gd, sd, P, dp, dp + P, dp + 2 * P, ref.d(), nullptr);
+    for (int t = 0; t < 7; ++t) tt_eval_points(c, fac[t], P, dp, dp + P, dp + 2 * P, got.d() + (size_t)t * P);
+    std::vector<double> hr((size_t)7 * P), hg((size_t)7 * P);
+    TTIGA_HIP(hipMemcpyAsync(hr.data(), ref.d(), sizeof(double) * 7 * P, hipMemcpyDeviceToHost, c.stream));
+    TTIGA_HIP(hipMemcpyAsync(hg.data(), got.d(), sizeof(double) * 7 * P, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    s.samples += P;
+    const double npts = (double)n0 * M;
+    bool ok = true;
+    for (int t = 0; t < 7; ++t) {
+      double e2 = 0.0;
+      for (int q = 0; q < P; ++q) {
+        const double d = hg[(size_t)t * P + q] - hr[(size_t)t * P + q];
+        e2 += d * d;
+      }
+      const double rms = std::sqrt(e2 / P), allowed = 10.0 * eps * scale[t] / std::sqrt(npts);
+      if (trace) std::fprintf(stderr, "[cross] factor %d probe rms %.3e allowed %.3e\n", t, rms, allowed);
+      if (!(rms <= allowed) && !(scale[t] == 0.0 && e2 == 0.0)) ok = false;
+    }
+    return ok;
+  };
+  // 3. the coefficients X_t = P_t^+ A_t[I, :] (k_t x Q1 Q2): by a second cross approximation of X_t
+  // viewed as (k_t Q1) x Q2 when it succeeds (samples of O(Q r^2)) and passes the probe check,
+  // else from the whole slices A_t[I, :, :] (|I| Q1 Q2 samples)
+  if (cross_second_level(gd, sd, fac, s, U, k, I, Id, Pinv, scale, rs)) {
+    if (probe()) {
+      if (trace) std::fprintf(stderr, "[cross] second level accepted\n");
+      return true;
+    }
+    if (trace) std::fprintf(stderr, "[cross] second level failed its probe check: whole slices\n");
   }
+  slices();
+  if (!probe()) return reject("probe error above 10 eps");
   return true;
 }
 

@@ -118,6 +118,7 @@ struct Profiler {
     std::string name;
     hipEvent_t a, b;
     double flops, bytes;
+    int count;  // launches this entry stands for (0: a further kernel of the same call)
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
@@ -132,15 +133,23 @@ struct Context;
 // Records events around the launches issued while it lives (when profiling is on).
 class ProfScope {
  public:
-  // size >= 0 is bucketed into the name when detailed profiling is on
-  ProfScope(Context& c, const char* name, double flops, double bytes, int size = -1);
+  // size >= 0 is bucketed into the name when detailed profiling is on.  per_kernel: the time is
+  // that of the kernels launched with the events of kernel_events (hipExtLaunchKernelGGL stamps
+  // them at each kernel's own start and end) instead of the span between two stream markers,
+  // which for kernels of a few microseconds also holds the host's launch latency whenever the
+  // stream had run dry before the launch.
+  ProfScope(Context& c, const char* name, double flops, double bytes, int size = -1, bool per_kernel = false);
   ~ProfScope();
+  // start and stop events for one kernel of a per-kernel scope (both null when profiling is off)
+  void kernel_events(hipEvent_t* start, hipEvent_t* stop);
 
  private:
   Context* c_;
   std::string name_;
   double flops_, bytes_;
   hipEvent_t a_ = nullptr;
+  bool per_kernel_ = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> kev_;
 };
 
 // Discretisation-level plans reused across problems (the 1-D eigenbases of the

@@ -128,3 +128,23 @@ def test_amen_rank_cap(ctx):
         h.solve()
     assert e.value.code == ttiga.TTIGA_E_RANKCAP
     h.close()
+
+
+def test_amen_graph_replay_equals_direct_launches(ctx):
+    """The executor's lanes run every local CG of AMEn as replays of a captured HIP graph (two
+    iterations per replay, convergence read between replays); a solve on the context's default
+    stream issues the same launches directly.  Both must give the same TT cores bit for bit, here
+    for three problems solved side by side, so that the replays interleave with other lanes' work
+    and with host synchronisations."""
+    say("amen graph replay vs direct")
+    probs = []
+    for s in range(3):
+        pr = W.c2_problem(n=48, seed=W.configs.C2_SEED + 40 + s)
+        pr.options.solver = AMEN
+        probs.append(pr)
+    out = ctx.solve_batch(probs, lanes=3)
+    for pr, (res, cores) in zip(probs, out):
+        assert res["status"] == 0, res
+        st, direct = _solve(ctx, pr)
+        assert st["iterations"] == res["iterations"]
+        assert all(np.array_equal(a, b) for a, b in zip(cores, direct)), pr.name
