@@ -357,6 +357,41 @@ def serving_phase(ctx, count, lanes, solver=1):
             "percentiles": f"nearest rank over {count} requests per rate"}
 
 
+
+def c3_amen_phase(ctx):
+    """The complex-geometry configuration (bumpy cube, degree 3, n = 512, 1.3e8 DOF, FP64) solved by
+    AMEn once, with the rate of its GEMMs (the local products contract the operator rank 84)."""
+    import workloads as W
+    from paper_2509_13224_amd import ttiga
+    from workloads.problem import PREC_FP64
+    pr = W.c3_problem(n=512, precision=PREC_FP64)
+    pr.options.solver = ttiga.TTIGA_SOLVER_AMEN
+    h = ctx.problem_create(pr, precond=1)
+    t0 = time.perf_counter()
+    ast = h.assemble()
+    t1 = time.perf_counter()
+    ctx.profile(-1)
+    ctx.profile(1)
+    st3 = h.solve(allow_notconv=True)
+    t2 = time.perf_counter()
+    ctx.profile(0)
+    p3 = ctx.profile_read()
+    h.close()
+    g3 = p3.get("gemm_f64")
+    return {
+        "workload": "bumpy cube (seeded NURBS), degree 3, n=512/dir (1.3e8 DOF), 8-mode Fourier source, "
+                    "TT eps 1e-6, tol 1e-7, FP64, AMEn (one solve; the preconditioner plan is built in it)",
+        "assembly_ms": 1e3 * (t1 - t0), "solve_ms": 1e3 * (t2 - t1), "status": st3["status"],
+        "half_sweeps": st3["iterations"], "local_iterations": st3["local_iterations"], "rank_u": st3["rank_u"],
+        "rank_K": ast["rank_K"], "compression_path": ast["compression_path"], "samples": ast["samples"],
+        "rel_pres": st3["rel_pres"], "rel_res": st3["rel_res"],
+        "gemm_f64": ({"tflops": g3["flops"] / (g3["total_ms"] * 1e-3) / 1e12,
+                      "frac_fp64_peak": g3["flops"] / (g3["total_ms"] * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
+                      "ms": g3["total_ms"], "launches": g3["launches"],
+                      "avg_launch_us": 1e3 * g3["total_ms"] / max(g3["launches"], 1)} if g3 else None),
+        "kernels": {k: {"ms": v["total_ms"], "launches": v["launches"]}
+                    for k, v in sorted(p3.items(), key=lambda kv: -kv[1]["total_ms"])[:6]}}
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,6 +423,7 @@ def main():
                     help="only the synthetic TT-matvec sweep (value = the best fraction of HBM bandwidth)")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the complex-geometry AMEn solve")
+    ap.add_argument("--c3-only", action="store_true", help="only the complex-geometry AMEn solve (profiling)")
     ap.add_argument("--sweep-point", type=str, default="",
                     help="rK,rx,n,p: run only this point of the sweep (with --sweep-only)")
     ap.add_argument("--traffic-kib", type=str, default="",
@@ -456,6 +492,16 @@ def main():
             "dtype": "f64" if solver else "f32+f64", "data": "synthetic", "config": {"workload": sv["workload"]},
             "serving": sv}),
             flush=True)
+        return
+
+    if args.c3_only:
+        log("C3 AMEn solve")
+        c3 = c3_amen_phase(ctx)
+        print(json.dumps({
+            "metric": "complex-geometry AMEn solve time", "value": c3["solve_ms"], "unit": "ms", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": c3["solve_ms"], "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": {"workload": c3["workload"]},
+            "c3_amen": c3}), flush=True)
         return
 
     if args.sweep_only:
@@ -649,34 +695,9 @@ def main():
     out["c1_latency"] = {"workload": "annulus degree 2, n=16/dir, manufactured source, eps = tol = 1e-10, FP64; "
                                      "assembly + solve, mean of 3 after one warm-up", **c1}
 
-    # the complex-geometry configuration (bumpy cube, degree 3, n = 512, 1.3e8 DOF, FP64) solved by
-    # AMEn once, with the rate of its GEMMs (the local products contract the operator rank 84)
     if not args.no_c3:
         log("C3 AMEn solve")
-        pr = with_solver(W.c3_problem(n=512, precision=PREC_FP64), ttiga.TTIGA_SOLVER_AMEN)
-        h = ctx.problem_create(pr, precond=1)
-        t0 = time.perf_counter()
-        ast = h.assemble()
-        t1 = time.perf_counter()
-        ctx.profile(-1)
-        ctx.profile(1)
-        st3 = h.solve(allow_notconv=True)
-        t2 = time.perf_counter()
-        ctx.profile(0)
-        p3 = ctx.profile_read()
-        h.close()
-        g3 = p3.get("gemm_f64")
-        out["c3_amen"] = {
-            "workload": "bumpy cube (seeded NURBS), degree 3, n=512/dir (1.3e8 DOF), 8-mode Fourier source, "
-                        "TT eps 1e-6, tol 1e-7, FP64, AMEn (one solve; the preconditioner plan is built in it)",
-            "assembly_ms": 1e3 * (t1 - t0), "solve_ms": 1e3 * (t2 - t1), "status": st3["status"],
-            "half_sweeps": st3["iterations"], "local_iterations": st3["local_iterations"], "rank_u": st3["rank_u"],
-            "rank_K": ast["rank_K"], "rel_pres": st3["rel_pres"], "rel_res": st3["rel_res"],
-            "gemm_f64": ({"tflops": g3["flops"] / (g3["total_ms"] * 1e-3) / 1e12,
-                          "frac_fp64_peak": g3["flops"] / (g3["total_ms"] * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
-                          "ms": g3["total_ms"], "launches": g3["launches"]} if g3 else None),
-            "kernels": {k: {"ms": v["total_ms"], "launches": v["launches"]}
-                        for k, v in sorted(p3.items(), key=lambda kv: -kv[1]["total_ms"])[:6]}}
+        out["c3_amen"] = c3_amen_phase(ctx)
 
     if not args.no_sweep:
         log("TT-matvec sweep")
