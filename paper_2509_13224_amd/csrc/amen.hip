@@ -41,7 +41,16 @@ namespace ttiga {
 
 namespace {
 
-constexpr int kKick = 6;  // rank of the residual train z and of the enrichment per step
+// rank of the residual train z and of the enrichment per step (TTIGA_AMEN_KICK overrides it
+// for measurements)
+static int kick_rank() {
+  static const int k = [] {
+    const char* e = std::getenv("TTIGA_AMEN_KICK");
+    const int v = e ? std::atoi(e) : 0;
+    return (v >= 1 && v <= 32) ? v : 12;
+  }();
+  return k;
+}
 
 // out = in with axes reordered: output axis a is input axis perm[a] (input dims d0, d1, d2)
 __global__ void k_permute3(int d0, int d1, int d2, int p0, int p1, int p2, const double* __restrict__ in,
@@ -858,11 +867,14 @@ void Amen::run(ttiga_solve_stats& s) {
   const double eps_x = std::min(pr.opts.tt_eps, 0.3 * tol);
   if (!pr.pc.ready) pr.pc.setup(pr);
   setup();
-  // initial guess P^-1 rhs (two digits), residual train z Gaussian of rank kKick
+  // initial guess P^-1 rhs (two digits), residual train z Gaussian of rank kick_rank()
   int hint = 8;
   pr.pc.apply(c, pr.rhs, x, 1e-2, pr.opts.max_rank, hint);
   {
-    const int rz[4] = {1, kKick, kKick, 1};
+    // the residual train's ranks within its unfolding sizes (small modes)
+    const int kk = kick_rank();
+    const int rz[4] = {1, std::min(kk, std::min(x.n[0], x.n[1] * x.n[2])),
+                       std::min(kk, std::min(x.n[0] * x.n[1], x.n[2])), 1};
     z.alloc(c, x.n, rz);
     for (int k = 0; k < 3; ++k) gaussian_fill(c, z.c[k].d(), (long)z.core_elems(k));
   }

@@ -607,6 +607,112 @@ __global__ __launch_bounds__(256) void k_detj_rows(GeoDev geo, int b0, int c1, i
   if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
+// The same minimum for geometry degree P2 in the third direction: each lane takes a contiguous
+// run of points along the row, so neighbouring points share their knot span, and keeps the
+// staged sums of that span in registers, reloading them from LDS only when the span changes
+// (the generic kernel reads 12 (p_g2 + 1) LDS values per point).  The arithmetic, and so the
+// minimum, is the generic kernel's.
+template <int P2>
+__global__ __launch_bounds__(256) void k_detj_rows_reg(GeoDev geo, int b0, int c1, int Q2, long rows, int iters,
+                                                       double* __restrict__ part) {
+  extern __shared__ double T[];  // [4 waves][3][m2][4]
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p0 = geo.pg[0], p1 = geo.pg[1];
+  const int m1 = geo.m[1], m2 = geo.m[2];
+  const int tsz = 12 * m2;
+  double* Tw = T + w * tsz;
+  const int run = (Q2 + 63) / 64;
+  const int i2a = lane * run, i2b = min(Q2, i2a + run);
+  double mn = 1e300;
+  for (int it = 0; it < iters; ++it) {
+    const long row = ((long)it * gridDim.x + blockIdx.x) * 4 + w;
+    const bool live = row < rows;
+    if (live) {
+      const int i0 = (int)(row / c1), i1 = b0 + (int)(row % c1);
+      const int s0 = geo.span[0][i0], s1 = geo.span[1][i1];
+      const double* B0 = geo.B[0] + (long)i0 * (p0 + 1);
+      const double* D0 = geo.D[0] + (long)i0 * (p0 + 1);
+      const double* B1 = geo.B[1] + (long)i1 * (p1 + 1);
+      const double* D1 = geo.D[1] + (long)i1 * (p1 + 1);
+      for (int e = lane; e < tsz; e += 64) {
+        const int v = e / (m2 * 4), c = (e / 4) % m2, sc = e % 4;
+        double acc = 0.0;
+        for (int a = 0; a <= p0; ++a) {
+          const double wa = (v == 1) ? D0[a] : B0[a];
+          for (int b = 0; b <= p1; ++b) {
+            const double wb = (v == 2) ? D1[b] : B1[b];
+            acc += wa * wb * geo.Pw[(((long)(s0 - p0 + a) * m1 + (s1 - p1 + b)) * m2 + c) * 4 + sc];
+          }
+        }
+        Tw[e] = acc;
+      }
+    }
+    __syncthreads();
+    if (live && i2a < i2b) {
+      double t0[P2 + 1][4], t1[P2 + 1][4], t2[P2 + 1][4];
+      int cur = -1;
+      // the next point's span and basis values are loaded one point ahead, so that their
+      // latency overlaps the current point's arithmetic (two waves per SIMD hide little)
+      int s2n = geo.span[2][i2a];
+      double bn[P2 + 1], dn[P2 + 1];
+#pragma unroll
+      for (int c = 0; c <= P2; ++c) {
+        bn[c] = geo.B[2][(long)i2a * (P2 + 1) + c];
+        dn[c] = geo.D[2][(long)i2a * (P2 + 1) + c];
+      }
+      for (int i2 = i2a; i2 < i2b; ++i2) {
+        const int s2 = s2n;
+        double b2v[P2 + 1], d2v[P2 + 1];
+#pragma unroll
+        for (int c = 0; c <= P2; ++c) {
+          b2v[c] = bn[c];
+          d2v[c] = dn[c];
+        }
+        if (i2 + 1 < i2b) {
+          s2n = geo.span[2][i2 + 1];
+#pragma unroll
+          for (int c = 0; c <= P2; ++c) {
+            bn[c] = geo.B[2][(long)(i2 + 1) * (P2 + 1) + c];
+            dn[c] = geo.D[2][(long)(i2 + 1) * (P2 + 1) + c];
+          }
+        }
+        if (s2 != cur) {
+          cur = s2;
+#pragma unroll
+          for (int c = 0; c <= P2; ++c) {
+            const int cc = s2 - P2 + c;
+#pragma unroll
+            for (int sc = 0; sc < 4; ++sc) {
+              t0[c][sc] = Tw[(0 * m2 + cc) * 4 + sc];
+              t1[c][sc] = Tw[(1 * m2 + cc) * 4 + sc];
+              t2[c][sc] = Tw[(2 * m2 + cc) * 4 + sc];
+            }
+          }
+        }
+        double H[4] = {0, 0, 0, 0}, dH[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+        for (int c = 0; c <= P2; ++c) {
+          const double b2 = b2v[c], d2 = d2v[c];
+#pragma unroll
+          for (int sc = 0; sc < 4; ++sc) {
+            H[sc] += b2 * t0[c][sc];
+            dH[0][sc] += b2 * t1[c][sc];
+            dH[1][sc] += b2 * t2[c][sc];
+            dH[2][sc] += d2 * t0[c][sc];
+          }
+        }
+        mn = fmin(mn, jacobian_det(H, dH));
+      }
+    }
+    __syncthreads();
+  }
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+  if (lane == 0) red[w] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
 __global__ void k_min_reduce(const double* __restrict__ part, long count, double* __restrict__ out) {
   __shared__ double sh[256];
   double v = 1e300;
@@ -763,8 +869,19 @@ void launch_detj_min(Context& ctx, const GeoDev& geo, const int* Q, double* min_
   const int blocks = (int)std::min<long>((rows + 3) / 4, 512);
   const int iters = (int)((rows + 4L * blocks - 1) / (4L * blocks));
   DBuf part(ctx.alloc, sizeof(double) * blocks);
-  hipLaunchKernelGGL(k_detj_rows, dim3(blocks), dim3(256), sizeof(double) * 4 * 12 * geo.m[2], ctx.stream, geo,
-                     0, Q[1], Q[2], rows, iters, part.d());
+  const size_t lds = sizeof(double) * 4 * 12 * geo.m[2];
+  if (geo.pg[2] == 1)
+    hipLaunchKernelGGL(k_detj_rows_reg<1>, dim3(blocks), dim3(256), lds, ctx.stream, geo, 0, Q[1], Q[2], rows, iters,
+                       part.d());
+  else if (geo.pg[2] == 2)
+    hipLaunchKernelGGL(k_detj_rows_reg<2>, dim3(blocks), dim3(256), lds, ctx.stream, geo, 0, Q[1], Q[2], rows, iters,
+                       part.d());
+  else if (geo.pg[2] == 3)
+    hipLaunchKernelGGL(k_detj_rows_reg<3>, dim3(blocks), dim3(256), lds, ctx.stream, geo, 0, Q[1], Q[2], rows, iters,
+                       part.d());
+  else
+    hipLaunchKernelGGL(k_detj_rows, dim3(blocks), dim3(256), lds, ctx.stream, geo, 0, Q[1], Q[2], rows, iters,
+                       part.d());
   hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(256), 0, ctx.stream, part.d(), (long)blocks, min_out);
   TTIGA_HIP(hipGetLastError());
 }

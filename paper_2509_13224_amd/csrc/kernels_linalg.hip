@@ -1455,12 +1455,195 @@ static int jacobi_group(int m) {
   return m <= 16 ? 8 : 16;
 }
 
+__global__ void k_copy_scalar(const double* __restrict__ src, double* __restrict__ dst) { dst[0] = src[0]; }
+
+// ---- one-sided Jacobi over the whole device, for matrices whose columns do not fit in LDS
+// (c > 135: the 1-D eigenbases of long directions, wide R factors).  The columns of W = op(A)
+// and of V live in global memory, column-major; one round of the circle ordering (c - 1 rounds
+// of c / 2 disjoint pairs per sweep) is one launch with a workgroup per pair, which forms the
+// pair's three inner products by a block reduction, rotates both columns of W and of V, and
+// folds |w_i . w_j| / (|w_i| |w_j|) into the sweep's maximum, rotating when that exceeds u m (the
+// tolerance of the single-workgroup kernel).  After each sweep one host read of that maximum ends
+// the iteration once a sweep made no rotation (or after 40 sweeps).  A ranking kernel then writes
+// s = |w_j| in descending order (ties by index), U = w_j / s_j and V in that order.
+__global__ void k_jr_load(int m, int c, int cp, const double* __restrict__ A, int transA, long lda,
+                          double* __restrict__ W, double* __restrict__ V) {
+  const long total = (long)cp * m;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / m), i = (int)(e % m);
+    W[e] = j < c ? (transA ? A[(long)j * lda + i] : A[(long)i * lda + j]) : 0.0;
+  }
+  if (V)
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)cp * cp; e += (long)gridDim.x * blockDim.x)
+      V[e] = (e / cp == e % cp) ? 1.0 : 0.0;
+}
+
+// ||W||_F^2 into f2[0] (one workgroup): pairs whose norm product lies below 1e-30 of it are left
+// alone, as in the single-workgroup kernel
+__global__ void k_jr_frob(long total, const double* __restrict__ W, double* __restrict__ f2) {
+  __shared__ double sh[256];
+  double v = 0.0;
+  for (long e = threadIdx.x; e < total; e += 256) v += W[e] * W[e];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) f2[0] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_jr_round(int m, int cp, int r, double* __restrict__ W,
+                                                  double* __restrict__ V, const double* __restrict__ f2,
+                                                  unsigned long long* __restrict__ mx) {
+  __shared__ double sh[3][256];
+  __shared__ double cs_sn[2];
+  const int pair = blockIdx.x;
+  int i, j;
+  if (pair == 0) {
+    i = r;
+    j = cp - 1;
+  } else {
+    i = (r + pair) % (cp - 1);
+    j = (r - pair + cp - 1) % (cp - 1);
+  }
+  if (i > j) {
+    const int t = i;
+    i = j;
+    j = t;
+  }
+  double* wi = W + (long)i * m;
+  double* wj = W + (long)j * m;
+  double a = 0.0, b = 0.0, g = 0.0;
+  for (int e = threadIdx.x; e < m; e += 256) {
+    const double x = wi[e], y = wj[e];
+    a += x * x;
+    b += y * y;
+    g += x * y;
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = g;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a = sh[0][0];
+    b = sh[1][0];
+    g = sh[2][0];
+    double cs = 1.0, sn = 0.0, meas = 0.0;
+    const double pq = sqrt(a) * sqrt(b);
+    if (g != 0.0 && pq > 1e-30 * f2[0]) meas = fabs(g) / pq;
+    // rotate only above the tolerance of the single-workgroup kernel, u m
+    if (meas > 2.220446049250313e-16 * m) {
+      const double zeta = (b - a) / (2.0 * g);
+      const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      cs = 1.0 / sqrt(1.0 + t * t);
+      sn = cs * t;
+    }
+    cs_sn[0] = cs;
+    cs_sn[1] = sn;
+    // non-negative doubles order as their bit patterns: the sweep's largest measure
+    atomicMax(mx, (unsigned long long)__double_as_longlong(meas));
+  }
+  __syncthreads();
+  const double cs = cs_sn[0], sn = cs_sn[1];
+  if (sn == 0.0) return;
+  for (int e = threadIdx.x; e < m; e += 256) {
+    const double x = wi[e], y = wj[e];
+    wi[e] = cs * x - sn * y;
+    wj[e] = sn * x + cs * y;
+  }
+  if (V) {
+    double* vi = V + (long)i * cp;
+    double* vj = V + (long)j * cp;
+    for (int e = threadIdx.x; e < cp; e += 256) {
+      const double x = vi[e], y = vj[e];
+      vi[e] = cs * x - sn * y;
+      vj[e] = sn * x + cs * y;
+    }
+  }
+}
+
+__global__ void k_jr_norms(int m, int c, const double* __restrict__ W, double* __restrict__ nrm) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  double v = 0.0;
+  for (int e = threadIdx.x; e < m; e += 256) v += W[(long)j * m + e] * W[(long)j * m + e];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nrm[j] = sqrt(sh[0]);
+}
+
+// position of column j in descending order of the norms (ties: smaller index first), then
+// s, U (m x c row-major) and V (c x c row-major) in that order
+__global__ void k_jr_store(int m, int c, int cp, const double* __restrict__ W, const double* __restrict__ Vw,
+                           const double* __restrict__ nrm, double* __restrict__ U, double* __restrict__ s,
+                           double* __restrict__ V) {
+  const int j = blockIdx.x;
+  __shared__ int s_rank;
+  if (threadIdx.x == 0) {
+    int rk = 0;
+    const double x = nrm[j];
+    for (int k = 0; k < c; ++k) rk += (nrm[k] > x || (nrm[k] == x && k < j)) ? 1 : 0;
+    s_rank = rk;
+    s[rk] = x;
+  }
+  __syncthreads();
+  const int rk = s_rank;
+  const double x = nrm[j];
+  const double inv = x > 0.0 ? 1.0 / x : 0.0;
+  for (int e = threadIdx.x; e < m; e += blockDim.x) U[(long)e * c + rk] = W[(long)j * m + e] * inv;
+  if (V)
+    for (int e = threadIdx.x; e < c; e += blockDim.x) V[(long)e * c + rk] = Vw[(long)j * cp + e];
+}
+
+static void svd_rounds(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U, double* s,
+                       double* V) {
+  const int cp = c + (c & 1);  // an even count of columns (a zero column pads an odd one)
+  const int pairs = cp / 2;
+  DBuf W(ctx.alloc, sizeof(double) * (size_t)cp * m), Vw(ctx.alloc, V ? sizeof(double) * (size_t)cp * cp : 0),
+      mx(ctx.alloc, sizeof(double)), f2(ctx.alloc, sizeof(double)), nrm(ctx.alloc, sizeof(double) * cp);
+  hipLaunchKernelGGL(k_jr_load, dim3(grid_for((long)cp * m)), dim3(256), 0, ctx.stream, m, c, cp, A, transA ? 1 : 0,
+                     lda, W.d(), V ? Vw.d() : nullptr);
+  hipLaunchKernelGGL(k_jr_frob, dim3(1), dim3(256), 0, ctx.stream, (long)cp * m, W.d(), f2.d());
+  double* h = ctx.host_device(1);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    fill(ctx, mx.d(), 1, 0.0);
+    for (int r = 0; r < cp - 1; ++r) {
+      hipLaunchKernelGGL(k_jr_round, dim3(pairs), dim3(256), 0, ctx.stream, m, cp, r, W.d(), V ? Vw.d() : nullptr,
+                         f2.d(), reinterpret_cast<unsigned long long*>(mx.d()));
+    }
+    TTIGA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, ctx.stream, mx.d(), h);
+    ctx.sync();
+    if (!(ctx.host_scratch[0] > 2.220446049250313e-16 * m)) break;  // a sweep without rotations
+  }
+  hipLaunchKernelGGL(k_jr_norms, dim3(c), dim3(256), 0, ctx.stream, m, c, W.d(), nrm.d());
+  hipLaunchKernelGGL(k_jr_store, dim3(c), dim3(256), 0, ctx.stream, m, c, cp, W.d(), V ? Vw.d() : nullptr, nrm.d(),
+                     U, s, V);
+  TTIGA_HIP(hipGetLastError());
+}
+
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V, const char* prof_name) {
   TTIGA_CHECK(c > 0 && m >= c && c <= 1024, TTIGA_E_ARG, "svd_small needs 0 < c <= m, c <= 1024");
   const long uc = (long)m * c, vc = V ? (long)c * c : 0;
   const long cap = lds_doubles();
   const int mode = (uc + vc <= cap) ? 2 : (uc <= cap ? 1 : 0);
+  if (mode == 0 && c > 135) {
+    ProfScope prof(ctx, prof_name, 8.0 * 0.5 * c * (c - 1.0) * (12.0 * m + (V ? 6.0 * c : 0.0)),
+                   8.0 * (2.0 * m * c + (V ? 2.0 * c * c : 0.0) + c), c);
+    svd_rounds(ctx, A, transA, m, c, lda, U, s, V);
+    return;
+  }
   DBuf work;
   const long gneed = mode == 2 ? 0 : (mode == 1 ? vc : uc + vc);
   if (gneed > 0) work = DBuf(ctx.alloc, sizeof(double) * gneed);
