@@ -38,7 +38,8 @@ PEAKS = {  # MI355X published peaks
     "hbm_GBps": 8000.0,
     "fp64_tflops": 78.6,
 }
-# bound of each kernel class: memory traffic or FP64 arithmetic
+# bound of each kernel class: memory traffic or FP64 arithmetic (a contraction class whose
+# arithmetic intensity lies below the ridge is held to the HBM roof instead: roofline_entry)
 KERNEL_BOUND = {
     "gemm_f64": "mfma",
     "tt_matvec_banded": "hbm",
@@ -67,8 +68,9 @@ SERVE_MAX_RANK = 1024
 ASSEMBLY_EPS = 1e-9
 # HBM bytes per dispatch of the roofline kernel, measured by two rocprofv3 --pmc runs (FETCH_SIZE,
 # then WRITE_SIZE) of `bench.py --single-only` and written, with the copy-kernel calibration, into
-# this summary as `traffic:` lines; a line counts only while the sha256 of the kernel's source file
-# still equals the one recorded with it (after a change to the kernel the field is null).
+# this summary as `traffic:` lines; a line counts only while the sha256 of the kernel's source files
+# (the kernel and, for the GEMM, its plan table) still equals the one recorded with it (after a
+# change to either the field is null).
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic.md")
 
 
@@ -83,19 +85,30 @@ def measured_traffic(kernel):
                      line)
         if not m or m.group(1) != kernel:
             continue
-        src = os.path.join(ROOT, m.group(4))
-        if not os.path.exists(src):
-            return None, f"source {m.group(4)} missing"
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if sha != m.group(5):
+        # source: one file, or several joined by '+' (hashed in that order, concatenated)
+        h = hashlib.sha256()
+        for rel in m.group(4).split("+"):
+            src = os.path.join(ROOT, rel)
+            if not os.path.exists(src):
+                return None, f"source {rel} missing"
+            h.update(open(src, "rb").read())
+        if h.hexdigest() != m.group(5):
             return None, f"{m.group(4)} changed since the counters were taken"
         return 1024.0 * (float(m.group(2)) + float(m.group(3))), f"rocprofv3 --pmc, {TRAFFIC_SUMMARY[len(ROOT) + 1:]}"
     return None, f"no PMC line for {kernel}"
 
 
 def roofline_entry(name, st):
+    """Roofline of a kernel class from its measured time and algorithmic flops and bytes.  A
+    contraction class is held to the roof its arithmetic intensity meets: the FP64 MFMA peak at
+    or above the ridge (peak flops / peak bandwidth, 9.8 flop/byte), HBM bandwidth below it (the
+    short-contraction products of the small TT ranks move more bytes than MFMA time)."""
     bound = KERNEL_BOUND.get(name, "alu")
     secs = st["total_ms"] * 1e-3
+    ridge = PEAKS["fp64_tflops"] * 1e12 / (PEAKS["hbm_GBps"] * 1e9)
+    intensity = st["flops"] / st["bytes"] if st["bytes"] > 0 else None
+    if bound == "mfma" and intensity is not None and intensity < ridge:
+        bound = "hbm"
     if bound == "hbm":
         achieved = st["bytes"] / secs / 1e9
         peak, unit = PEAKS["hbm_GBps"], "GB/s"
@@ -105,7 +118,9 @@ def roofline_entry(name, st):
     return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": None, "launches": st["launches"],
             "avg_launch_us": 1e3 * st["total_ms"] / max(st["launches"], 1),
-            "algorithmic_per_launch": (st["bytes"] if bound == "hbm" else st["flops"]) / max(st["launches"], 1)}
+            "algorithmic_per_launch": (st["bytes"] if bound == "hbm" else st["flops"]) / max(st["launches"], 1),
+            "arithmetic_intensity": intensity, "ridge": ridge,
+            "achieved_tflops": st["flops"] / secs / 1e12, "achieved_GBps": st["bytes"] / secs / 1e9}
 
 
 def tt_rel_diff(a, b):

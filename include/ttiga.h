@@ -317,7 +317,8 @@ int ttiga_tt_matvec(ttiga_ctx* ctx, const ttiga_ttm_view* K, const ttiga_tt_view
  * dimension lda, or K x M when ta != 0), op(B) is K x N (B stored K x N with ldb, or
  * N x K when tb != 0), C is M x N with ldc; batch >= 1 products at element strides sA,
  * sB, sC.  plan: NULL for the library's own choice (its tuned table, else its shape
- * rule), else {bm, bn, kchunk} with (bm, bn) one of (64, 64), (128, 64), (64, 128) and
+ * rule), else {bm, bn, kchunk} with (bm, bn) one of (64, 64), (128, 64), (64, 128), (64, 16),
+ * (16, 64) and
  * kchunk 0 (the whole contraction in one pass) or a multiple of 32 (the contraction cut
  * into chunks of that length, partials summed in chunk order).  Synchronises the stream.
  * E_ARG on null pointers, M, N, K or batch < 1, a leading dimension shorter than a row, a

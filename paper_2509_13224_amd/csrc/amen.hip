@@ -362,14 +362,11 @@ class Amen {
   void prec_apply(const PrecOp& pp, const double* r, double* z);
   template <int NV, int POST>
   void dots_dev(long n, const double* const* xs, const double* const* ys);
-  double* hmap = nullptr;      // host-mapped results of the local CG dots (host address)
-  double* hmap_dev = nullptr;  // its device address
-  DBuf scal;                   // device scalars of the local CG: r.z, -, alpha, beta
- public:
-  ~Amen() {
-    if (hmap) (void)hipHostFree(hmap);
-  }
- private:
+  // host-mapped results of the local CG dots: the context's fixed small host array (host
+  // address and device address)
+  double* hmap = nullptr;
+  double* hmap_dev = nullptr;
+  DBuf scal;  // device scalars of the local CG: r.z, -, alpha, beta
   void pencil_of(Frame& F, int r);
   DBuf dot_part;  // partial sums of the dots and their counter
   DBuf unit;
@@ -583,10 +580,7 @@ void Amen::setup() {
   dot_part = DBuf(c.alloc, sizeof(double) * 4 * kDotBlocks + 64);
   scal = DBuf(c.alloc, sizeof(double) * 8);
   fill(c, scal.d(), 8, 0.0);
-  if (!hmap) {
-    TTIGA_HIP(hipHostMalloc(reinterpret_cast<void**>(&hmap), sizeof(double) * 8, hipHostMallocCoherent));
-    TTIGA_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&hmap_dev), hmap, 0));
-  }
+  hmap = c.small(&hmap_dev);
   hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, c.stream, dot_part.as<unsigned>() + 8 * kDotBlocks);
   TTIGA_HIP(hipGetLastError());
   const TT& K = P.KII;

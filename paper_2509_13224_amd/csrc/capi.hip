@@ -151,7 +151,28 @@ void DeviceAllocator::release(void* p) {
 
 Context::~Context() {
   if (sync_event) (void)hipEventDestroy(sync_event);
-  if (host_scratch) (void)hipHostFree(host_scratch);
+  if (!borrowed) {
+    if (host_scratch) (void)hipHostFree(host_scratch);
+    if (host_small) (void)hipHostFree(host_small);
+  }
+  for (LaneRes& r : lane_cache) {
+    if (r.stream) {
+      (void)hipStreamSynchronize(r.stream);
+      (void)hipStreamDestroy(r.stream);
+    }
+    if (r.host) (void)hipHostFree(r.host);
+    if (r.small) (void)hipHostFree(r.small);
+  }
+}
+
+double* Context::small(double** dev) {
+  if (!host_small) {
+    TTIGA_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_small), sizeof(double) * kHostSmall,
+                            hipHostMallocCoherent));
+    TTIGA_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&host_small_dev), host_small, 0));
+  }
+  *dev = host_small_dev;
+  return host_small;
 }
 
 void Context::sync() {
@@ -517,7 +538,8 @@ int ttiga_gemm_f64(ttiga_ctx* ctx, int ta, int tb, int M, int N, int K, double a
     GemmPlan g = gemm_plan(ta != 0, tb != 0, M, N, K, batch);
     if (plan) {
       const bool tile_ok = (plan[0] == 64 && plan[1] == 64) || (plan[0] == 128 && plan[1] == 64) ||
-                           (plan[0] == 64 && plan[1] == 128);
+                           (plan[0] == 64 && plan[1] == 128) || (plan[0] == 64 && plan[1] == 16) ||
+                           (plan[0] == 16 && plan[1] == 64);
       TTIGA_CHECK(tile_ok && plan[2] >= 0 && plan[2] % 32 == 0, TTIGA_E_ARG, "gemm: unknown plan");
       g.bm = plan[0];
       g.bn = plan[1];

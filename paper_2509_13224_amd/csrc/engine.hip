@@ -39,7 +39,28 @@ Engine::Engine(Context* root, size_t budget, int lanes, int max_queue) : root_(r
   for (int i = 0; i < lanes; ++i) {
     auto ln = std::make_unique<Lane>();
     ln->ctx.device = root->device;
-    TTIGA_HIP(hipStreamCreateWithFlags(&ln->ctx.stream, hipStreamNonBlocking));
+    ln->ctx.borrowed = true;
+    Context::LaneRes r;
+    {
+      std::lock_guard<std::mutex> lk(root->lane_mu);
+      if (!root->lane_cache.empty()) {
+        r = root->lane_cache.back();
+        root->lane_cache.pop_back();
+      }
+    }
+    if (!r.stream) {
+      const hipError_t e = hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        give_back();
+        TTIGA_HIP(e);
+      }
+    }
+    ln->ctx.stream = r.stream;
+    ln->ctx.host_scratch = r.host;
+    ln->ctx.host_dev = r.host_dev;
+    ln->ctx.host_scratch_doubles = r.host_doubles;
+    ln->ctx.host_small = r.small;
+    ln->ctx.host_small_dev = r.small_dev;
     lanes_.push_back(std::move(ln));
   }
   for (int i = 0; i < lanes; ++i) threads_.emplace_back([this, i] { worker(i); });
@@ -52,13 +73,24 @@ Engine::~Engine() {
   }
   cv_work_.notify_all();
   for (auto& t : threads_) t.join();
+  give_back();
+}
+
+// the lanes' streams and host arrays back to the root context (after their work has drained)
+void Engine::give_back() {
   for (auto& ln : lanes_) {
-    if (ln->ctx.stream) {
-      (void)hipStreamSynchronize(ln->ctx.stream);
-      (void)hipStreamDestroy(ln->ctx.stream);
-      ln->ctx.stream = nullptr;
+    Context& c = ln->ctx;
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    Context::LaneRes r{c.stream, c.host_scratch, c.host_dev, c.host_scratch_doubles, c.host_small, c.host_small_dev};
+    c.stream = nullptr;
+    c.host_scratch = c.host_dev = c.host_small = c.host_small_dev = nullptr;
+    c.host_scratch_doubles = 0;
+    if (r.stream || r.host || r.small) {
+      std::lock_guard<std::mutex> lk(root_->lane_mu);
+      root_->lane_cache.push_back(r);
     }
   }
+  lanes_.clear();
 }
 
 Job* Engine::find_locked(unsigned long long ticket) {

@@ -48,6 +48,7 @@ class Engine {
     Context ctx;  // stream, host scratch and profiler of the lane; arena set per job
   };
   void worker(int lane);
+  void give_back();
   void run(Job& j, Lane& lane, int index);
   Job* pick_locked();
   Job* find_locked(unsigned long long ticket);

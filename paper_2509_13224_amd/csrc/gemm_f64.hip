@@ -1,8 +1,9 @@
 // FP64 GEMM for the TT contractions and TT-rounding products on gfx950.
 //
 // C[b] = alpha op(A[b]) op(B[b]) + beta C[b] with row-major operands.  One kernel,
-// v_mfma_f64_16x16x4 on tiles of BM x BN (64x64, 128x64 or 64x128) per workgroup of four
-// 64-wide waves (2 x 2, each owning a (BM/2) x (BN/2) sub-tile), the contraction staged
+// v_mfma_f64_16x16x4 on tiles of BM x BN (64x64, 128x64, 64x128, or the skinny 64x16 and
+// 16x64) per workgroup of four 64-wide waves (2 x 2 on the square and wide tiles, 4 x 1 or
+// 1 x 4 on the skinny ones, each wave owning a sub-tile of 16 x 16 blocks), the contraction staged
 // through LDS 32 at a time.  The next K step's global loads are issued before the current
 // step's MFMAs, so a workgroup keeps one step of loads in flight while it computes (the
 // products here are mostly short contractions over a few hundred, where one exposed
@@ -18,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstdint>
 #include <cstdlib>
@@ -55,7 +57,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
   using LB = TileLds<!TB, BN>;
   constexpr int kLoadA = BM * kGK / 256;
   constexpr int kLoadB = BN * kGK / 256;
-  constexpr int MI = BM / 32, NI = BN / 32;  // 16 x 16 blocks per wave
+  // four waves: 2 x 2 on the square and wide tiles, stacked along the long side of the
+  // skinny ones (64 x 16: four along M; 16 x 64: four along N), each owning MI x NI blocks
+  // of 16 x 16
+  constexpr int WN = BN == 16 ? 1 : (BM == 16 ? 4 : 2);
+  constexpr int WM = 4 / WN;
+  constexpr int MI = BM / (16 * WM), NI = BN / (16 * WN);
+  static_assert(MI >= 1 && NI >= 1 && MI * 16 * WM == BM && NI * 16 * WN == BN, "tile shape");
   __shared__ double As[LA::kElems];
   __shared__ double Bs[LB::kElems];
 
@@ -67,7 +75,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, double al
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int wm = (wave / WN) * (BM / WM), wn = (wave % WN) * (BN / WN);
 
   // (x, k) of the e-th element a thread stages: consecutive threads along the operand's
   // contiguous global index
@@ -334,11 +342,14 @@ int ceil_log2(long v) {
 
 GemmPlan gemm_plan(bool ta, bool tb, int M, int N, int K, int batch) {
   GemmPlan g;
-  const int key[6] = {ta ? 1 : 0, tb ? 1 : 0, ceil_log2(M), ceil_log2(N), ceil_log2(K), batch > 1 ? 1 : 0};
-  for (const GemmEntry* e = kGemmTable; e->ta >= 0; ++e) {
-    if (e->ta != key[0] || e->tb != key[1] || e->lm != key[2] || e->ln != key[3] || e->lk != key[4] ||
-        e->batched != key[5])
-      continue;
+  const std::array<int, 6> key = {ta ? 1 : 0, tb ? 1 : 0, ceil_log2(M), ceil_log2(N), ceil_log2(K), batch > 1 ? 1 : 0};
+  // the table is sorted by key (the tuner writes it so): binary search
+  auto key_of = [](const GemmEntry& e) { return std::array<int, 6>{e.ta, e.tb, e.lm, e.ln, e.lk, e.batched}; };
+  constexpr size_t kEntries = sizeof(kGemmTable) / sizeof(kGemmTable[0]) - 1;
+  const GemmEntry* hit = std::lower_bound(kGemmTable, kGemmTable + kEntries, key,
+                                          [&](const GemmEntry& e, const std::array<int, 6>& k) { return key_of(e) < k; });
+  if (hit != kGemmTable + kEntries && key_of(*hit) == key) {
+    const GemmEntry* e = hit;
     g.bm = e->bm;
     g.bn = e->bn;
     if (e->kchunk > 0 && e->kchunk < K) {
@@ -350,12 +361,26 @@ GemmPlan gemm_plan(bool ta, bool tb, int M, int N, int K, int batch) {
     }
     if (batch * g.splits <= 65535) return g;
     g = GemmPlan();
-    break;
   }
-  // otherwise 64 x 64 tiles (measured: the 128-wide tiles win only on a few shapes, which the
-  // table lists, and lose on most, where they halve the workgroups of a grid that cannot fill
-  // the device); long contractions on such grids are split (partials summed by a second kernel
-  // in split order), at most 256 rows of K per split, about 512 workgroups
+  // otherwise a skinny 64 x 16 (16 x 64) tile when N (M) is at most 16, where a square tile
+  // would spend almost all of its MFMA work on padding, or when 64 x 64 tiles would give fewer
+  // than 512 workgroups (four times as many workgroups, each with a quarter of the MFMA work
+  // per contraction step: on such grids the products are bound by latency, not by MFMA
+  // throughput); else 64 x 64 (measured: the 128-wide tiles win only on a few shapes, which
+  // the table lists).  Long contractions on grids below 256 workgroups are split (partials
+  // summed by a second kernel in split order), at most 256 rows of K per split, about 512
+  // workgroups.
+  const long square_tiles = (long)((M + 63) / 64) * ((N + 63) / 64) * batch;
+  if (N <= 16 && (M > 16 || M >= N)) {
+    g.bm = 64;
+    g.bn = 16;
+  } else if (M <= 16) {
+    g.bm = 16;
+    g.bn = 64;
+  } else if (square_tiles < 512) {
+    g.bm = M >= N ? 64 : 16;
+    g.bn = M >= N ? 16 : 64;
+  }
   const long tiles = (long)((M + g.bm - 1) / g.bm) * ((N + g.bn - 1) / g.bn) * batch;
   if (tiles < 256 && K >= 320) {
     long s = std::min<long>((K + 255) / 256, std::max<long>(1, 512 / tiles));
@@ -400,12 +425,17 @@ void gemm_planned(Context& ctx, const GemmPlan& g, bool ta, bool tb, int M, int 
                   const double* A, long lda, long sA, const double* B, long ldb, long sB, double beta,
                   double* C, long ldc, long sC, int batch, double* part) {
   TTIGA_CHECK(batch <= 65535 / std::max(1, g.splits), TTIGA_E_ARG, "gemm: batch too large");
+  // TTIGA_GEMM_TRACE=1 prints the shape of every product (the input of the offline tile tuner)
+  static const bool trace = std::getenv("TTIGA_GEMM_TRACE") != nullptr;
+  if (trace) std::fprintf(stderr, "[gemm-shape] ta=%d tb=%d M=%d N=%d K=%d batch=%d\n", ta, tb, M, N, K, batch);
   TTIGA_CHECK((M + g.bm - 1) / g.bm <= 65535, TTIGA_E_ARG, "gemm: M too large for the grid");
   // timed per kernel: most products here take a few microseconds
   ProfScope prof(ctx, "gemm_f64", 2.0 * M * N * (double)K * batch,
                  8.0 * batch * ((double)M * K + (double)K * N + (double)M * N), -1, true);
   if (g.bm == 128) launch_tile<128, 64>(ctx, prof, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
   else if (g.bn == 128) launch_tile<64, 128>(ctx, prof, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
+  else if (g.bn == 16) launch_tile<64, 16>(ctx, prof, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
+  else if (g.bm == 16) launch_tile<16, 64>(ctx, prof, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
   else launch_tile<64, 64>(ctx, prof, g, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, part);
   if (g.splits > 1) {
     const long total = (long)batch * M * N;
@@ -433,6 +463,9 @@ void gemm_lowp(Context& ctx, int dtype, bool ta, bool tb, int M, int N, int K, d
   GemmPlan g = gemm_plan(ta, tb, M, N, K, batch);
   g.bm = g.bn = 64;  // the low-precision kernel has one tile shape
   TTIGA_CHECK(batch <= 65535 / std::max(1, g.splits), TTIGA_E_ARG, "gemm: batch too large");
+  // TTIGA_GEMM_TRACE=1 prints the shape of every product (the input of the offline tile tuner)
+  static const bool trace = std::getenv("TTIGA_GEMM_TRACE") != nullptr;
+  if (trace) std::fprintf(stderr, "[gemm-shape] ta=%d tb=%d M=%d N=%d K=%d batch=%d\n", ta, tb, M, N, K, batch);
   DBuf part;
   if (g.splits > 1) part = DBuf(ctx.alloc, sizeof(double) * gemm_part_doubles(g, M, N, batch));
   ProfScope prof(ctx, dtype == TTIGA_BF16 ? "gemm_bf16" : "gemm_fp32", 2.0 * M * N * (double)K * batch,
@@ -497,8 +530,6 @@ void gemm(Context& ctx, bool ta, bool tb, int M, int N, int K, double alpha, con
     TTIGA_HIP(hipGetLastError());
     return;
   }
-  static const bool trace = std::getenv("TTIGA_GEMM_TRACE") != nullptr;
-  if (trace) std::fprintf(stderr, "[gemm-shape] ta=%d tb=%d M=%d N=%d K=%d batch=%d\n", ta, tb, M, N, K, batch);
   const GemmPlan g = gemm_plan(ta, tb, M, N, K, batch);
   DBuf part;
   if (g.splits > 1) part = DBuf(ctx.alloc, sizeof(double) * gemm_part_doubles(g, M, N, batch));

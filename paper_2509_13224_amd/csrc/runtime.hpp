@@ -186,6 +186,28 @@ struct Context {
   double* host_scratch = nullptr;
   double* host_dev = nullptr;
   size_t host_scratch_doubles = 0;
+  // a second, fixed host-mapped array of kHostSmall doubles that never moves (host_scratch
+  // is reallocated when a larger readback needs it): the AMEn local CG's dot results, whose
+  // device address its captured graphs hold
+  static constexpr int kHostSmall = 64;
+  double* host_small = nullptr;
+  double* host_small_dev = nullptr;
+  double* small(double** dev);
+  // executor lanes take their stream and pinned host memory from here and give them back
+  // when the executor ends, so that a batch does not pay for creating streams (milliseconds
+  // each) or for freeing pinned memory, which waits for the whole device to go idle
+  struct LaneRes {
+    hipStream_t stream = nullptr;
+    double* host = nullptr;
+    double* host_dev = nullptr;
+    size_t host_doubles = 0;
+    double* small = nullptr;
+    double* small_dev = nullptr;
+  };
+  std::mutex lane_mu;
+  std::vector<LaneRes> lane_cache;
+  // set on an executor lane's context: its stream and host arrays belong to lane_cache
+  bool borrowed = false;
   // TTIGA_FP32 / TTIGA_BF16 while the inner corrections of a mixed-precision solve run: the
   // contractions routed through gemm_c then use the low-precision MFMA product (0: FP64)
   int lowp = 0;

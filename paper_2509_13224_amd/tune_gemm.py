@@ -1,19 +1,20 @@
 #!/usr/bin/env python3
 """Offline tile tuner of the FP64 GEMM kernel (writes csrc/gemm_table.inc).
 
-The library picks the tile (64x64, 128x64 or 64x128) and the contraction split of every
+The library picks the tile (64x64, 128x64, 64x128, 64x16 or 16x64) and the contraction split of every
 product from a table compiled into it, keyed by shape bucket (transposes, ceil log2 of M, N,
 K, batched or not), with a fixed rule for shapes the table does not list.  So the choice is
 deterministic at run time and the same in every process; this script is what fills the table,
 once per hardware, by measurement:
 
-1. trace: run representative workloads (the plain-vs-mixed annulus solve at n = 256, the
-   complex geometry at n = 128, a slice of the batched family) in a child process with
-   TTIGA_GEMM_TRACE=1, which makes the library print the shape of every product;
+1. trace: run representative workloads (the annulus at n = 256, the complex geometry at
+   n = 128 and a slice of the serving mix, each by preconditioned TT-CG and by AMEn) in a child
+   process with TTIGA_GEMM_TRACE=1, which makes the library print the shape of every product;
 2. time: for the most frequent shape of every bucket, every tile with contraction chunks of
-   {whole K, 2048, 1024, 512, 256} (multiples of 32) through ttiga_gemm_f64 on random operands:
-   10 back-to-back launches between two HIP events on the context stream, median of 5 such
-   runs after a warm-up (single launches of 20 us products are too noisy to rank plans);
+   {whole K, 2048, 1024, 512, 256, 128, 64} (multiples of 32) through ttiga_gemm_f64 on random
+   operands: the mean kernel time of 10 products from the library's per-kernel events (so the
+   host round trip of each synchronous call is not counted), median of 3 such runs after a
+   warm-up;
 3. choose: a bucket gets a table entry when its best plan differs from the rule's plan and
    still beats it by more than 5% when the two are timed again, alternately, three times each;
    the entry stores the tile and the contraction chunk.
@@ -32,8 +33,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 sys.path.insert(0, ROOT)
 
-TILES = ((64, 64), (128, 64), (64, 128))
-CHUNKS = (0, 2048, 1024, 512, 256)  # 0: the whole contraction in one pass
+TILES = ((64, 64), (128, 64), (64, 128), (64, 16), (16, 64))
+CHUNKS = (0, 2048, 1024, 512, 256, 128, 64)  # 0: the whole contraction in one pass
 GAIN = 1.05
 
 TRACE_SCRIPT = r"""
@@ -43,8 +44,13 @@ import workloads as W
 from paper_2509_13224_amd import ttiga
 from workloads.problem import PREC_FP64
 ctx = ttiga.Context(workspace_bytes=64 << 30)
-probs = [W.c2_problem(n=256), W.c3_problem(n=128, precision=PREC_FP64)]
-probs += W.c4_requests(count=12)
+probs = []
+for solver in (0, 1):  # preconditioned TT-CG, AMEn
+    batch = [W.c2_problem(n=256), W.c3_problem(n=128, precision=PREC_FP64)] + W.c4_requests(count=12,
+                                                                                          precision=PREC_FP64)
+    for pr in batch:
+        pr.options.solver = solver
+    probs += batch
 for pr in probs:
     h = ctx.problem_create(pr, precond=1)
     h.assemble()
@@ -78,7 +84,10 @@ def trace_shapes():
     return shapes
 
 
-def time_plan(ctx, torch, shape, plan, reps=5, inner=10):
+def time_plan(ctx, torch, shape, plan, reps=3, inner=10):
+    """Median over `reps` runs of the mean kernel time (ms) of `inner` products: the library's
+    own per-kernel events (taken at each kernel's start and end, split-K reduction included), so
+    the host round trip of the synchronous entry point between products is not counted."""
     ta, tb, M, N, K, batch = shape
     a_shape = (batch, K, M) if ta else (batch, M, K)
     b_shape = (batch, N, K) if tb else (batch, K, N)
@@ -88,14 +97,14 @@ def time_plan(ctx, torch, shape, plan, reps=5, inner=10):
     args = dict(batch=batch, sA=a_shape[1] * a_shape[2], sB=b_shape[1] * b_shape[2], sC=M * N, plan=plan)
     times = []
     for r in range(reps + 1):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        ctx.profile(-1)
+        ctx.profile(1)
         for _ in range(inner):
             ctx.gemm_f64(ta, tb, M, N, K, 1.0, A, a_shape[2], B, b_shape[2], 0.0, C, N, **args)
-        e1.record()
-        e1.synchronize()
+        ctx.profile(0)
+        st = ctx.profile_read()["gemm_f64"]
         if r >= 1:
-            times.append(e0.elapsed_time(e1) / inner)
+            times.append(st["total_ms"] / inner)
     return sorted(times)[len(times) // 2]
 
 
@@ -112,6 +121,13 @@ def rule_plan(M, N, K, batch):
     """The library's rule (gemm_plan without a table entry) as (bm, bn, kchunk), for the
     comparison."""
     bm = bn = 64
+    square_tiles = ((M + 63) // 64) * ((N + 63) // 64) * batch
+    if N <= 16 and (M > 16 or M >= N):
+        bn = 16
+    elif M <= 16:
+        bm = 16
+    elif square_tiles < 512:
+        bm, bn = (64, 16) if M >= N else (16, 64)
     tiles = ((M + bm - 1) // bm) * ((N + bn - 1) // bn) * batch
     kchunk = 0
     if tiles < 256 and K >= 320:
@@ -135,8 +151,9 @@ def main():
     print(f"{sum(shapes.values())} products, {len(shapes)} shapes, {len(buckets)} buckets", file=sys.stderr)
     ctx = ttiga.Context(workspace_bytes=8 << 30)
     entries = []
-    for key in sorted(buckets):
+    for bi, key in enumerate(sorted(buckets)):
         sh, cnt = buckets[key].most_common(1)[0]
+        print(f"bucket {bi + 1}/{len(buckets)} {key} {sh} x{cnt}", file=sys.stderr, flush=True)
         ta, tb, M, N, K, batch = sh
         if M * N * batch * 8 > (1 << 31) or M * K * batch * 8 > (1 << 31) or K * N * batch * 8 > (1 << 31):
             continue

@@ -26,6 +26,11 @@ SHAPES = [
     (254, 67, 254, 7),
     (40, 30, 3000, 1),
     (130, 140, 100, 3),
+    # skinny tiles (N or M at most 16): the preconditioner's 1-D transforms, dot-like products
+    (254, 3, 254, 15),
+    (5, 300, 700, 2),
+    (16, 16, 1012, 1),
+    (1, 2286, 1, 1),
 ]
 
 
@@ -72,7 +77,7 @@ def test_gemm_default_plan(ctx, ta, tb, shape):
 
 
 @pytest.mark.parametrize("plan", [(64, 64, 0), (128, 64, 0), (64, 128, 0), (64, 64, 64), (128, 64, 96),
-                                  (64, 128, 160)])
+                                  (64, 128, 160), (64, 16, 0), (16, 64, 0), (64, 16, 64), (16, 64, 96)])
 def test_gemm_every_plan(ctx, plan):
     say("gemm plan", plan)
     for ta in (0, 1):
