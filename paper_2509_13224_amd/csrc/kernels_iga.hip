@@ -713,6 +713,135 @@ __global__ __launch_bounds__(256) void k_detj_rows_reg(GeoDev geo, int b0, int c
   if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
+// The same minimum for geometries of degree 1 in the third direction, one grid row per lane.
+// On a knot span [k_s, k_s+1] of that direction every homogeneous sum is linear in the local
+// coordinate t = N_s(xi2) (the second basis value of the span): H(t) = A + B t, the in-plane
+// derivatives C + D t and E + F t, and the derivative along xi2 a constant G.  The quotient
+// rule gives J = M / w^2 with M_ki = w dH_i,k - H_k dH_i,w (quadratic in t for i = 0, 1, linear
+// for i = 2), so det J = det M(t) / w(t)^6 with det M a polynomial of degree 5.  Each lane
+// builds the six coefficients of its row's span once (the staged sums of the span's two
+// control planes, as in the row kernels) and then evaluates each point by Horner's rule and
+// one division (none when the weight is constant along the span, as in extrusions): about 8
+// to 20 instructions a point instead of the 100 of the direct formula, four points at a time.
+// All lanes of a wave walk the same points of their rows in step, so the span and table loads
+// are uniform (scalar).  Agreement with the direct formula: a few units of roundoff relative to the product
+// of the Jacobian's column norms.
+__device__ inline void poly_mul(const double* a, int na, const double* b, int nb, double* out) {
+  for (int i = 0; i < na + nb - 1; ++i) out[i] = 0.0;
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j) out[i + j] += a[i] * b[j];
+}
+
+__global__ __launch_bounds__(256) void k_detj_lin(GeoDev geo, int Q1, int Q2, long rows, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int p0 = geo.pg[0], p1 = geo.pg[1];
+  const int m1 = geo.m[1], m2 = geo.m[2];
+  double mn = 1e300;
+  for (long row = blockIdx.x * 256L + threadIdx.x; row < rows; row += (long)gridDim.x * 256L) {
+    const int i0 = (int)(row / Q1), i1 = (int)(row % Q1);
+    const int s0 = geo.span[0][i0], s1 = geo.span[1][i1];
+    const double* B0 = geo.B[0] + (long)i0 * (p0 + 1);
+    const double* D0 = geo.D[0] + (long)i0 * (p0 + 1);
+    const double* B1 = geo.B[1] + (long)i1 * (p1 + 1);
+    const double* D1 = geo.D[1] + (long)i1 * (p1 + 1);
+    int cur = -1;
+    double cf[6] = {0, 0, 0, 0, 0, 0}, a3 = 1.0, b3 = 0.0, inv6 = 1.0;
+    for (int i2 = 0; i2 < Q2;) {
+      const int s2 = geo.span[2][i2];
+      if (s2 != cur) {
+        cur = s2;
+        // T[e][v][sc]: control plane s2 - 1 + e summed over the first two directions (v = 0
+        // value, 1 and 2 the derivatives along xi0 and xi1)
+        double T[2][3][4];
+        for (int e = 0; e < 2; ++e)
+          for (int v = 0; v < 3; ++v)
+            for (int sc = 0; sc < 4; ++sc) T[e][v][sc] = 0.0;
+        for (int a = 0; a <= p0; ++a)
+          for (int b = 0; b <= p1; ++b) {
+            const double wv = B0[a] * B1[b], w0 = D0[a] * B1[b], w1 = B0[a] * D1[b];
+            for (int e = 0; e < 2; ++e) {
+              const double* P = geo.Pw + (((long)(s0 - p0 + a) * m1 + (s1 - p1 + b)) * m2 + (s2 - 1 + e)) * 4;
+              for (int sc = 0; sc < 4; ++sc) {
+                T[e][0][sc] += wv * P[sc];
+                T[e][1][sc] += w0 * P[sc];
+                T[e][2][sc] += w1 * P[sc];
+              }
+            }
+          }
+        const double d20 = geo.D[2][(long)i2 * 2], d21 = geo.D[2][(long)i2 * 2 + 1];
+        double A[4], Bc[4], C[4], D[4], E[4], F[4], G[4];
+        for (int sc = 0; sc < 4; ++sc) {
+          A[sc] = T[0][0][sc];
+          Bc[sc] = T[1][0][sc] - T[0][0][sc];
+          C[sc] = T[0][1][sc];
+          D[sc] = T[1][1][sc] - T[0][1][sc];
+          E[sc] = T[0][2][sc];
+          F[sc] = T[1][2][sc] - T[0][2][sc];
+          G[sc] = d20 * T[0][0][sc] + d21 * T[1][0][sc];
+        }
+        // M[k][i] coefficients in t (quadratic for i = 0, 1; linear for i = 2)
+        double M[3][3][3];
+        for (int k = 0; k < 3; ++k) {
+          M[k][0][0] = A[3] * C[k] - A[k] * C[3];
+          M[k][0][1] = (A[3] * D[k] + Bc[3] * C[k]) - (A[k] * D[3] + Bc[k] * C[3]);
+          M[k][0][2] = Bc[3] * D[k] - Bc[k] * D[3];
+          M[k][1][0] = A[3] * E[k] - A[k] * E[3];
+          M[k][1][1] = (A[3] * F[k] + Bc[3] * E[k]) - (A[k] * F[3] + Bc[k] * E[3]);
+          M[k][1][2] = Bc[3] * F[k] - Bc[k] * F[3];
+          M[k][2][0] = A[3] * G[k] - A[k] * G[3];
+          M[k][2][1] = Bc[3] * G[k] - Bc[k] * G[3];
+          M[k][2][2] = 0.0;
+        }
+        // cofactor expansion along the first row, as polynomials in t: minors of degree 3, 3
+        // and 4, the determinant of degree 5
+        double x[5], y[5], mn0[4], mn1[4], mn2[5];
+        poly_mul(M[1][1], 3, M[2][2], 2, x);
+        poly_mul(M[1][2], 2, M[2][1], 3, y);
+        for (int i = 0; i < 4; ++i) mn0[i] = x[i] - y[i];
+        poly_mul(M[1][0], 3, M[2][2], 2, x);
+        poly_mul(M[1][2], 2, M[2][0], 3, y);
+        for (int i = 0; i < 4; ++i) mn1[i] = x[i] - y[i];
+        poly_mul(M[1][0], 3, M[2][1], 3, x);
+        poly_mul(M[1][1], 3, M[2][0], 3, y);
+        for (int i = 0; i < 5; ++i) mn2[i] = x[i] - y[i];
+        double u0[6], u1[6], u2[6];
+        poly_mul(M[0][0], 3, mn0, 4, u0);
+        poly_mul(M[0][1], 3, mn1, 4, u1);
+        poly_mul(M[0][2], 2, mn2, 5, u2);
+        for (int i = 0; i < 6; ++i) cf[i] = u0[i] - u1[i] + u2[i];
+        a3 = A[3];
+        b3 = Bc[3];
+        // a weight constant along the span (extrusions): one division per span
+        const double a2 = a3 * a3;
+        inv6 = 1.0 / (a2 * a2 * a2);
+      }
+      auto value = [&](double t) {
+        double sdet = cf[5];
+#pragma unroll
+        for (int i = 4; i >= 0; --i) sdet = sdet * t + cf[i];
+        if (b3 == 0.0) return sdet * inv6;
+        const double w = a3 + b3 * t;
+        const double w2 = w * w;
+        return sdet / (w2 * w2 * w2);
+      };
+      // four points at a time while they stay on this span (the spans do not decrease)
+      if (i2 + 3 < Q2 && geo.span[2][i2 + 3] == s2) {
+        const double* tb = geo.B[2] + (long)i2 * 2 + 1;
+        const double v0 = value(tb[0]), v1 = value(tb[2]), v2 = value(tb[4]), v3 = value(tb[6]);
+        mn = fmin(mn, fmin(fmin(v0, v1), fmin(v2, v3)));
+        i2 += 4;
+      } else {
+        mn = fmin(mn, value(geo.B[2][(long)i2 * 2 + 1]));
+        i2 += 1;
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
 __global__ void k_min_reduce(const double* __restrict__ part, long count, double* __restrict__ out) {
   __shared__ double sh[256];
   double v = 1e300;
@@ -863,16 +992,19 @@ void launch_detj_min(Context& ctx, const GeoDev& geo, const int* Q, double* min_
   TTIGA_CHECK(detj_rows_fit(geo), TTIGA_E_ARG, "geometry net too large for the det J rows kernel");
   const long rows = (long)Q[0] * Q[1];
   const long total = rows * Q[2];
-  ProfScope prof(ctx, "geometry_detj", (32.0 * (geo.pg[2] + 1) + 40.0) * total, 0.0);
+  // degree 1 along xi2: a rational function per row and span, about 20 flop a point (the
+  // direct formula: 32 (p_g2 + 1) + 40)
+  const bool lin = geo.pg[2] == 1;
+  ProfScope prof(ctx, "geometry_detj", (lin ? 20.0 : 32.0 * (geo.pg[2] + 1) + 40.0) * total, 0.0);
   // two blocks per compute unit: the kernel loops over rows for its whole duration, so a
-  // larger grid would hold every wave slot while the kernels of other streams wait
-  const int blocks = (int)std::min<long>((rows + 3) / 4, 512);
+  // larger grid would hold every wave slot while the kernels of other streams wait (the
+  // degree-1 kernel: one row per lane, 256 rows per block and pass)
+  const int blocks = (int)std::min<long>(lin ? (rows + 255) / 256 : (rows + 3) / 4, 512);
   const int iters = (int)((rows + 4L * blocks - 1) / (4L * blocks));
   DBuf part(ctx.alloc, sizeof(double) * blocks);
   const size_t lds = sizeof(double) * 4 * 12 * geo.m[2];
-  if (geo.pg[2] == 1)
-    hipLaunchKernelGGL(k_detj_rows_reg<1>, dim3(blocks), dim3(256), lds, ctx.stream, geo, 0, Q[1], Q[2], rows, iters,
-                       part.d());
+  if (lin)
+    hipLaunchKernelGGL(k_detj_lin, dim3(blocks), dim3(256), 0, ctx.stream, geo, Q[1], Q[2], rows, part.d());
   else if (geo.pg[2] == 2)
     hipLaunchKernelGGL(k_detj_rows_reg<2>, dim3(blocks), dim3(256), lds, ctx.stream, geo, 0, Q[1], Q[2], rows, iters,
                        part.d());

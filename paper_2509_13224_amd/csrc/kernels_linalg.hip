@@ -784,6 +784,9 @@ static int qr_threads(int c) { return 64 * std::min(16, std::max(1, c)); }
 void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
              double* R) {
   TTIGA_CHECK(m >= c && c > 0, TTIGA_E_ARG, "qr_tall needs m >= c > 0");
+  // TTIGA_QR_TRACE=1 prints the shape of every factorisation (for measurements)
+  static const bool trace = std::getenv("TTIGA_QR_TRACE") != nullptr;
+  if (trace) std::fprintf(stderr, "[qr-shape] m=%d c=%d\n", m, c);
   const int kLdsDoubles = lds_doubles();
   struct Level {
     int m, nb, ldw;
@@ -1635,6 +1638,8 @@ static void svd_rounds(Context& ctx, const double* A, bool transA, int m, int c,
 void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* U,
                double* s, double* V, const char* prof_name) {
   TTIGA_CHECK(c > 0 && m >= c && c <= 1024, TTIGA_E_ARG, "svd_small needs 0 < c <= m, c <= 1024");
+  static const bool trace = std::getenv("TTIGA_QR_TRACE") != nullptr;
+  if (trace) std::fprintf(stderr, "[svd-shape] m=%d c=%d v=%d\n", m, c, V ? 1 : 0);
   const long uc = (long)m * c, vc = V ? (long)c * c : 0;
   const long cap = lds_doubles();
   const int mode = (uc + vc <= cap) ? 2 : (uc <= cap ? 1 : 0);

@@ -232,6 +232,44 @@ def test_cross_compression(ctx, geo_name):
     assert _tt_rel_dist(h.tt(ttiga.WHICH_F), h2.tt(ttiga.WHICH_F)) <= 20 * eps
 
 
+def _warped_column():
+    """Degree (1, 1, 1) with three knot spans along xi2 (interior knots 1/3, 2/3), a mildly
+    perturbed unit column and weights in [0.8, 1.2] that vary along xi2 (seeded)."""
+    from workloads.geometries import _open_knots
+    from workloads.problem import Geometry
+    rng = np.random.default_rng(7)
+    zc = (0.0, 0.3, 0.7, 1.0)
+    ctrl = np.zeros((2, 2, 4, 3))
+    wts = np.zeros((2, 2, 4))
+    for a in range(2):
+        for b in range(2):
+            for c in range(4):
+                ctrl[a, b, c] = (a + 0.05 * rng.standard_normal(), b + 0.05 * rng.standard_normal(),
+                                 zc[c] + 0.03 * rng.standard_normal())
+                wts[a, b, c] = 0.8 + 0.4 * rng.random()
+    return Geometry(degree=(1, 1, 1), knots=[_open_knots(1), _open_knots(1), _open_knots(1, (1 / 3, 2 / 3))],
+                    ctrl=ctrl, weights=wts)
+
+
+@pytest.mark.parametrize("geo_name", ["warped_column", "ring"])
+def test_detj_pass_degree1_matches_oracle(ctx, geo_name):
+    """Geometries of degree 1 along xi2 take the rational det J pass (per row and knot span a
+    degree-5 polynomial over w^6, evaluated four points at a time): weights varying along xi2
+    over three spans (a division per point, spans changing inside the rows) and the ring
+    (weights constant along xi2: one division per span), 114 Gauss points per direction (not
+    a multiple of four).  The reported minimum lies within 1e-12 of the largest |det J| of the
+    oracle's grid."""
+    say("det J degree 1", geo_name)
+    geo = _warped_column() if geo_name == "warped_column" else W.ring()
+    pr = W.small_problem(geo, 40, 2, W.fourier_source(geo, 5))
+    h = ctx.problem_create(pr)
+    st = h.assemble()
+    _, detj = geometry.sample_factors_grid(pr)
+    assert detj.shape == (114, 114, 114)
+    say("det J degree 1", geo_name, st["min_detJ"], detj.min())
+    assert abs(st["min_detJ"] - detj.min()) <= 1e-12 * np.abs(detj).max()
+
+
 def test_assembly_eps_sets_operator_accuracy(ctx):
     """assembly_eps governs the assembled K alone: a twisted box assembled at tt_eps = 1e-3 but
     assembly_eps = 1e-10 matches the sparse oracle's K to 10 * 1e-10, while the same problem
