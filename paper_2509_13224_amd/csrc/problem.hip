@@ -146,12 +146,16 @@ void Problem::upload() {
   TTIGA_HIP(hipMemcpyAsync(w.d(), weights.data(), sizeof(double) * nctrl, hipMemcpyHostToDevice, c.stream));
   Pw = DBuf(c.alloc, sizeof(double) * 4 * nctrl);
   launch_homogeneous(c, (long)nctrl, xyz.d(), w.d(), Pw.d());
+  // host sources of the asynchronous copies below: they must outlive the copies, so they live
+  // until the stream has drained at the end of this function
+  std::vector<double> knots_h[3], modes_h;
   for (int d = 0; d < 3; ++d) {
     gknots_d[d] = DBuf(c.alloc, sizeof(double) * gknots[d].size());
     TTIGA_HIP(hipMemcpyAsync(gknots_d[d].d(), gknots[d].data(), sizeof(double) * gknots[d].size(),
                              hipMemcpyHostToDevice, c.stream));
     // open uniform solution knots: p+1 zeros, e/E for e = 1..E-1, p+1 ones
-    std::vector<double> kn(n[d] + p + 1);
+    std::vector<double>& kn = knots_h[d];
+    kn.resize(n[d] + p + 1);
     for (int i = 0; i < (int)kn.size(); ++i) {
       const int e = std::min(std::max(i - p, 0), E[d]);
       kn[i] = (e == E[d]) ? 1.0 : (double)e / E[d];
@@ -163,13 +167,14 @@ void Problem::upload() {
   const int nm = (int)src_a.size();
   if (nm > 0) {
     modes_d = DBuf(c.alloc, sizeof(double) * 5 * nm);
-    std::vector<double> h(5 * nm);
+    std::vector<double>& h = modes_h;
+    h.resize(5 * nm);
     std::memcpy(h.data(), src_a.data(), sizeof(double) * nm);
     std::memcpy(h.data() + nm, src_k.data(), sizeof(double) * 3 * nm);
     std::memcpy(h.data() + 4 * nm, src_phi.data(), sizeof(double) * nm);
     TTIGA_HIP(hipMemcpyAsync(modes_d.d(), h.data(), sizeof(double) * 5 * nm, hipMemcpyHostToDevice, c.stream));
   }
-  c.sync();  // host vectors above go out of scope
+  c.sync();  // the host vectors above go out of scope after this
 }
 
 SourceDev Problem::source_dev() const {
