@@ -102,6 +102,12 @@ struct DotArgs {
 
 constexpr int kDotBlocks = 512;
 
+// Blocks for the local solver's vector kernels over n elements: eight or more elements per
+// thread.  The local vectors hold a few hundred thousand entries; a thread per entry would
+// launch a thousand short workgroups per kernel, which hold wave slots mostly while waiting for
+// memory, and with many lanes those slots are what the other lanes' kernels wait for.
+static int local_grid(long n, int cap) { return (int)std::max<long>(1, std::min<long>((n + 2047) / 2048, cap)); }
+
 // out[v] = x_v . y_v for v < NV in one launch: each block writes its share to part[b][v]; the
 // block that finishes last (a counter, reset by it for the next call) adds the shares in block
 // order, so the sums do not depend on timing.
@@ -469,7 +475,7 @@ void Amen::prec_apply(const PrecOp& pp, const double* r, double* z) {
   pp.a1.run(c, pp.WL, r0, 0, r, (long)n * r1, 0, t1, (long)n * r1, 0);
   pp.a2.run(c, pp.V, n, 0, t1, r1, (long)n * r1, t2, r1, (long)n * r1);
   pp.a3.run(c, t2, r1, 0, pp.WR, r1, 0, t1, r1, 0);
-  hipLaunchKernelGGL(k_diag_scale, dim3(grid_for(pp.N)), dim3(256), 0, c.stream, r0, n, r1, pp.mu, pp.cc, pp.lam,
+  hipLaunchKernelGGL(k_diag_scale, dim3(local_grid(pp.N, 2048)), dim3(256), 0, c.stream, r0, n, r1, pp.mu, pp.cc, pp.lam,
                      pp.nu, pp.dfloor, t1);
   TTIGA_HIP(hipGetLastError());
   pp.b1.run(c, t1, r1, 0, pp.WR, r1, 0, t2, r1, 0);
@@ -486,7 +492,7 @@ void Amen::dots_dev(long n, const double* const* xs, const double* const* ys) {
     a.y[v] = v < NV ? ys[v] : ys[0];
   }
   unsigned* cnt = dot_part.as<unsigned>() + 8 * kDotBlocks;
-  hipLaunchKernelGGL((k_dots<NV, POST>), dim3(kDotBlocks), dim3(256), 0, c.stream, n, a, dot_part.d(), cnt, hmap_dev,
+  hipLaunchKernelGGL((k_dots<NV, POST>), dim3(local_grid(n, kDotBlocks)), dim3(256), 0, c.stream, n, a, dot_part.d(), cnt, hmap_dev,
                      scal.d());
   TTIGA_HIP(hipGetLastError());
 }
@@ -706,11 +712,11 @@ double Amen::solve_core(int k, double tol_loc) {
     for (int g = 0; g < kGraphIters; ++g) {
       local_apply(op, pd.d(), q.d());
       dots_dev<1, kPostAlpha>(N, xp, yq);
-      hipLaunchKernelGGL(k_cg_update_dev, dim3(grid_for(N)), dim3(256), 0, c.stream, N, scal.d() + 2, xk, pd.d(),
+      hipLaunchKernelGGL(k_cg_update_dev, dim3(local_grid(N, 2048)), dim3(256), 0, c.stream, N, scal.d() + 2, xk, pd.d(),
                          r.d(), q.d());
       prec_apply(pp, r.d(), zz.d());
       dots_dev<3, kPostBeta>(N, xs3, ys3);
-      hipLaunchKernelGGL(k_xpby_dev, dim3(grid_for(N)), dim3(256), 0, c.stream, N, zz.d(), scal.d() + 3, pd.d());
+      hipLaunchKernelGGL(k_xpby_dev, dim3(local_grid(N, 2048)), dim3(256), 0, c.stream, N, zz.d(), scal.d() + 3, pd.d());
     }
     TTIGA_HIP(hipGetLastError());
   };
