@@ -296,10 +296,11 @@ void gemm_c(Context& ctx, bool operator_, bool ta, bool tb, int M, int N, int K,
 void gemm_lowp(Context& ctx, int dtype, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
                long lda, long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC,
                int batch = 1);
-// Blocks of 256 threads for a grid-stride elementwise kernel over `total` elements: at most
-// 2048 (eight per compute unit), enough to stream HBM on an idle device without holding every
-// wave slot while the kernels of other streams wait for room.
-inline int grid_for(long total) { return (int)std::max<long>(1, std::min<long>((total + 255) / 256, 2048)); }
+// Blocks of 256 threads for a grid-stride elementwise kernel over `total` elements: four or
+// more elements per thread and at most 2048 blocks (eight per compute unit), enough to stream
+// HBM on an idle device without holding every wave slot while the kernels of other streams
+// wait for room (short workgroups of one element per thread mostly wait for memory).
+inline int grid_for(long total) { return (int)std::max<long>(1, std::min<long>((total + 1023) / 1024, 2048)); }
 // Q (m x c, row-major, orthonormal columns) and R (c x c, upper) with op(A) = Q R (Householder TSQR).
 void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
              double* R);
