@@ -47,7 +47,7 @@ static int kick_rank() {
   static const int k = [] {
     const char* e = std::getenv("TTIGA_AMEN_KICK");
     const int v = e ? std::atoi(e) : 0;
-    return (v >= 1 && v <= 32) ? v : 12;
+    return (v >= 1 && v <= 32) ? v : 16;
   }();
   return k;
 }
