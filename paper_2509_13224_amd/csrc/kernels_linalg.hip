@@ -381,6 +381,11 @@ __device__ inline void update_panel_n(int nq, double* const* col, const double* 
 // first, one wave per panel, into Tg (16 doubles per panel, per block), then copied into the
 // LDS that held tau (so c <= 256), where the update reads them entry by entry.  Panel columns
 // past c alias the panel's first column with tau 0, which T turns into zero updates.
+// Per-problem strides of a batched TSQR (blockIdx.y selects the problem; all zero for one).
+struct QrStrides {
+  long in = 0, v = 0, tau = 0, r = 0, work = 0, qtop = 0, qout = 0, tg = 0;
+};
+
 template <bool kLds, bool kVLds>
 __global__ __launch_bounds__(1024) void k_hh_apply_wy(int m, int c, int nb, int ldw,
                                                       const double* __restrict__ V,
@@ -388,10 +393,19 @@ __global__ __launch_bounds__(1024) void k_hh_apply_wy(int m, int c, int nb, int 
                                                       const double* __restrict__ Qtop,
                                                       double* __restrict__ Qout,
                                                       double* __restrict__ gwork,
-                                                      double* __restrict__ Tg) {
+                                                      double* __restrict__ Tg, QrStrides bs) {
   extern __shared__ double smem[];
   __shared__ double s_tau[1024];
   const int blk = blockIdx.x;
+  {
+    const long b = blockIdx.y;
+    V += b * bs.v;
+    tau += b * bs.tau;
+    if (Qtop) Qtop += b * bs.qtop;
+    Qout += b * bs.qout;
+    if (gwork) gwork += b * bs.work;
+    Tg += b * bs.tg;
+  }
   const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
   const int nr = (int)(r1 - r0);
   const int tid = threadIdx.x, lane = tid & 63, nwaves = blockDim.x >> 6;
@@ -578,11 +592,19 @@ template <bool kLds>
 __global__ __launch_bounds__(1024) void k_hh_factor_wy(int m, int c, const double* __restrict__ A, long lda,
                                                        int trans, int nb, int ldw, double* __restrict__ V,
                                                        double* __restrict__ tau, double* __restrict__ Rout,
-                                                       double* __restrict__ gwork) {
+                                                       double* __restrict__ gwork, QrStrides bs) {
   extern __shared__ double smem[];
   __shared__ double s_tau[1024];
   __shared__ double s_T[16];
   const int blk = blockIdx.x;
+  {
+    const long b = blockIdx.y;
+    A += b * bs.in;
+    V += b * bs.v;
+    tau += b * bs.tau;
+    Rout += b * bs.r;
+    if (gwork) gwork += b * bs.work;
+  }
   const long r0 = (long)m * blk / nb, r1 = (long)m * (blk + 1) / nb;
   const int nr = (int)(r1 - r0);
   const int tid = threadIdx.x, lane = tid & 63, nwaves = blockDim.x >> 6;
@@ -708,10 +730,15 @@ __global__ __launch_bounds__(1024) void k_hh_factor_wy(int m, int c, const doubl
   }
 }
 
+// Per-problem strides of a batched Jacobi SVD (blockIdx.x selects the problem; LDS mode only).
+struct SvdStrides {
+  long a = 0, u = 0, s = 0, v = 0;
+};
+
 template <int kMode>
 __global__ void k_jacobi_svd(int m, int c, const double* __restrict__ A, int transA, long lda,
                              double* __restrict__ gwork, double* __restrict__ U, double* __restrict__ S,
-                             double* __restrict__ V, int max_sweeps, int G);
+                             double* __restrict__ V, int max_sweeps, int G, SvdStrides bs);
 
 template <bool kLds>
 __global__ void k_pchol(int r, const double* __restrict__ G, double tau_rel, double* __restrict__ L,
@@ -783,10 +810,16 @@ static int qr_threads(int c) { return 64 * std::min(16, std::max(1, c)); }
 
 void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
              double* R) {
+  qr_tall_batched(ctx, 1, A, 0, transA, m, c, lda, Q, 0, R, 0);
+}
+
+void qr_tall_batched(Context& ctx, int batch, const double* A, long sA, bool transA, int m, int c, long lda,
+                     double* Q, long sQ, double* R, long sR) {
   TTIGA_CHECK(m >= c && c > 0, TTIGA_E_ARG, "qr_tall needs m >= c > 0");
+  TTIGA_CHECK(batch >= 1 && batch <= 65535, TTIGA_E_ARG, "qr_tall: batch out of range");
   // TTIGA_QR_TRACE=1 prints the shape of every factorisation (for measurements)
   static const bool trace = std::getenv("TTIGA_QR_TRACE") != nullptr;
-  if (trace) std::fprintf(stderr, "[qr-shape] m=%d c=%d\n", m, c);
+  if (trace) std::fprintf(stderr, "[qr-shape] m=%d c=%d batch=%d\n", m, c, batch);
   const int kLdsDoubles = lds_doubles();
   struct Level {
     int m, nb, ldw;
@@ -795,21 +828,24 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
   };
   std::vector<Level> lv;
   const double* in = A;
+  long s_in = sA;
   bool tr = transA;
   long ld = lda;
   int mm = m;
   // blocks of at least 2c rows so every level at least halves the rows, as tall as the
   // LDS holds the work columns (each tree level costs a launch of c dependent steps, so
   // fewer, taller blocks win); the apply step keeps the reflectors in LDS only when
-  // both fit and otherwise streams them from L2
+  // both fit and otherwise streams them from L2.  A batch of problems of one shape runs
+  // every level as one launch (grid.y = problem).
   // panels of four columns (TTIGA_TSQR_FACTOR=column selects the column-at-a-time kernel, for
-  // measurements)
+  // measurements; single problems only)
   static const bool per_column = [] {
     const char* e = std::getenv("TTIGA_TSQR_FACTOR");
     return e && std::strcmp(e, "column") == 0;
   }();
   const int rows_work = kLdsDoubles / c;
   const int rows_target = rows_work >= 2 * c ? rows_work : 4 * c;
+  const size_t bt = (size_t)batch;
   while (true) {
     Level L;
     L.m = mm;
@@ -817,74 +853,94 @@ void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda,
     L.ldw = (mm + L.nb - 1) / L.nb;
     L.lds = (long)L.ldw * c <= kLdsDoubles;
     L.v_lds = 2L * L.ldw * c <= kLdsDoubles;
-    L.V = DBuf(ctx.alloc, sizeof(double) * (size_t)mm * c);
-    L.tau = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * c);
+    L.V = DBuf(ctx.alloc, sizeof(double) * bt * mm * c);
+    L.tau = DBuf(ctx.alloc, sizeof(double) * bt * L.nb * c);
     // the root of the tree writes its R straight to the caller's buffer
-    if (L.nb > 1) L.R = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * c * c);
+    if (L.nb > 1) L.R = DBuf(ctx.alloc, sizeof(double) * bt * L.nb * c * c);
     double* Rout = L.nb > 1 ? L.R.d() : R;
-    if (!L.lds) L.work = DBuf(ctx.alloc, sizeof(double) * (size_t)L.nb * L.ldw * c);
+    if (!L.lds) L.work = DBuf(ctx.alloc, sizeof(double) * bt * L.nb * L.ldw * c);
+    QrStrides bs;
+    bs.in = s_in;
+    bs.v = (long)mm * c;
+    bs.tau = (long)L.nb * c;
+    bs.r = L.nb > 1 ? (long)L.nb * c * c : sR;
+    bs.work = (long)L.nb * L.ldw * c;
     const size_t shm = L.lds ? sizeof(double) * (size_t)L.ldw * c : 0;
-    ProfScope prof(ctx, "tsqr_factor", 2.0 * mm * c * c - L.nb * (2.0 / 3.0) * c * c * c,
-                   8.0 * (2.0 * mm * c + (double)L.nb * c * c), c);
-    if (per_column && L.lds)
-      hipLaunchKernelGGL(k_hh_factor<true>, dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, mm, c, in, ld,
+    ProfScope prof(ctx, "tsqr_factor", batch * (2.0 * mm * c * c - L.nb * (2.0 / 3.0) * c * c * c),
+                   batch * 8.0 * (2.0 * mm * c + (double)L.nb * c * c), c);
+    const dim3 grid(L.nb, batch);
+    if (per_column && batch == 1 && L.lds)
+      hipLaunchKernelGGL(k_hh_factor<true>, grid, dim3(qr_threads(c)), lds_request(shm), ctx.stream, mm, c, in, ld,
                          tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, nullptr);
-    else if (per_column)
-      hipLaunchKernelGGL(k_hh_factor<false>, dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, mm, c, in, ld,
-                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, L.work.d());
+    else if (per_column && batch == 1)
+      hipLaunchKernelGGL(k_hh_factor<false>, grid, dim3(qr_threads(c)), 0, ctx.stream, mm, c, in, ld, tr ? 1 : 0,
+                         L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, L.work.d());
     else if (L.lds)
-      hipLaunchKernelGGL(k_hh_factor_wy<true>, dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream, mm, c,
-                         in, ld, tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, nullptr);
+      hipLaunchKernelGGL(k_hh_factor_wy<true>, grid, dim3(qr_threads(c)), lds_request(shm), ctx.stream, mm, c, in,
+                         ld, tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, nullptr, bs);
     else
-      hipLaunchKernelGGL(k_hh_factor_wy<false>, dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, mm, c, in, ld,
-                         tr ? 1 : 0, L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, L.work.d());
+      hipLaunchKernelGGL(k_hh_factor_wy<false>, grid, dim3(qr_threads(c)), 0, ctx.stream, mm, c, in, ld, tr ? 1 : 0,
+                         L.nb, L.ldw, L.V.d(), L.tau.d(), Rout, L.work.d(), bs);
     TTIGA_HIP(hipGetLastError());
     lv.push_back(std::move(L));
     const Level& last = lv.back();
     if (last.nb == 1) break;
     in = last.R.d();
+    s_in = (long)last.nb * c * c;
     tr = false;
     ld = c;
     mm = last.nb * c;
   }
   // thin Q, top-down: reflectors four at a time in compact WY form (TTIGA_TSQR_APPLY=reflector
-  // selects the one-reflector-at-a-time kernel, for measurements)
+  // selects the one-reflector-at-a-time kernel, for measurements; single problems only)
   static const bool per_reflector = [] {
     const char* e = std::getenv("TTIGA_TSQR_APPLY");
     return e && std::strcmp(e, "reflector") == 0;
   }();
+  TTIGA_CHECK(batch == 1 || c <= 256, TTIGA_E_ARG, "qr_tall: batched factorisations need c <= 256");
   DBuf qprev;
+  long s_qprev = 0;
   for (int l = (int)lv.size() - 1; l >= 0; --l) {
     Level& L = lv[l];
     DBuf qout;
-    double* dst = (l == 0) ? Q : (qout = DBuf(ctx.alloc, sizeof(double) * (size_t)L.m * c), qout.d());
+    double* dst = (l == 0) ? Q : (qout = DBuf(ctx.alloc, sizeof(double) * bt * L.m * c), qout.d());
     const size_t shm = L.lds ? (L.v_lds ? 2 : 1) * sizeof(double) * (size_t)L.ldw * c : 0;
-    ProfScope prof(ctx, "tsqr_apply", 4.0 * c * c * (double)L.m - 2.0 * c * c * c * L.nb,
-                   8.0 * (2.0 * L.m * c + (double)L.nb * c * c), c);
-    if (per_reflector || c > 256) {
+    ProfScope prof(ctx, "tsqr_apply", batch * (4.0 * c * c * (double)L.m - 2.0 * c * c * c * L.nb),
+                   batch * 8.0 * (2.0 * L.m * c + (double)L.nb * c * c), c);
+    const dim3 grid(L.nb, batch);
+    if ((per_reflector || c > 256) && batch == 1) {
       if (L.v_lds)
-        hipLaunchKernelGGL((k_hh_apply<true, true>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream,
-                           L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
+        hipLaunchKernelGGL((k_hh_apply<true, true>), grid, dim3(qr_threads(c)), lds_request(shm), ctx.stream, L.m, c,
+                           L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
       else if (L.lds)
-        hipLaunchKernelGGL((k_hh_apply<true, false>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm), ctx.stream,
-                           L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
+        hipLaunchKernelGGL((k_hh_apply<true, false>), grid, dim3(qr_threads(c)), lds_request(shm), ctx.stream, L.m,
+                           c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr);
       else
-        hipLaunchKernelGGL((k_hh_apply<false, false>), dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, L.m, c,
-                           L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, L.work.d());
+        hipLaunchKernelGGL((k_hh_apply<false, false>), grid, dim3(qr_threads(c)), 0, ctx.stream, L.m, c, L.nb,
+                           L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, L.work.d());
     } else {
-      DBuf Tg(ctx.alloc, sizeof(double) * (size_t)L.nb * ((c + 3) / 4) * 16);
+      const long tg = (long)L.nb * ((c + 3) / 4) * 16;
+      DBuf Tg(ctx.alloc, sizeof(double) * bt * tg);
+      QrStrides bs;
+      bs.v = (long)L.m * c;
+      bs.tau = (long)L.nb * c;
+      bs.qtop = s_qprev;
+      bs.qout = l == 0 ? sQ : (long)L.m * c;
+      bs.work = (long)L.nb * L.ldw * c;
+      bs.tg = tg;
       if (L.v_lds)
-        hipLaunchKernelGGL((k_hh_apply_wy<true, true>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm),
-                           ctx.stream, L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr, Tg.d());
+        hipLaunchKernelGGL((k_hh_apply_wy<true, true>), grid, dim3(qr_threads(c)), lds_request(shm), ctx.stream, L.m,
+                           c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr, Tg.d(), bs);
       else if (L.lds)
-        hipLaunchKernelGGL((k_hh_apply_wy<true, false>), dim3(L.nb), dim3(qr_threads(c)), lds_request(shm),
-                           ctx.stream, L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr, Tg.d());
+        hipLaunchKernelGGL((k_hh_apply_wy<true, false>), grid, dim3(qr_threads(c)), lds_request(shm), ctx.stream,
+                           L.m, c, L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, nullptr, Tg.d(), bs);
       else
-        hipLaunchKernelGGL((k_hh_apply_wy<false, false>), dim3(L.nb), dim3(qr_threads(c)), 0, ctx.stream, L.m, c,
-                           L.nb, L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, L.work.d(), Tg.d());
+        hipLaunchKernelGGL((k_hh_apply_wy<false, false>), grid, dim3(qr_threads(c)), 0, ctx.stream, L.m, c, L.nb,
+                           L.ldw, L.V.d(), L.tau.d(), qprev.d(), dst, L.work.d(), Tg.d(), bs);
     }
     TTIGA_HIP(hipGetLastError());
     qprev = std::move(qout);
+    s_qprev = (long)L.m * c;
   }
 }
 
@@ -1103,8 +1159,16 @@ template <int kMode>
 __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int c, const double* __restrict__ A,
                                                      int transA, long lda, double* __restrict__ gwork,
                                                      double* __restrict__ U, double* __restrict__ S,
-                                                     double* __restrict__ V, int max_sweeps, int G) {
+                                                     double* __restrict__ V, int max_sweeps, int G,
+                                                     SvdStrides bs) {
   extern __shared__ double smem[];
+  {
+    const long b = blockIdx.x;
+    A += b * bs.a;
+    U += b * bs.u;
+    S += b * bs.s;
+    if (V) V += b * bs.v;
+  }
   double* Ucol = kMode >= 1 ? smem : gwork;
   double* Vcol = kMode == 2 ? smem + (long)m * c : (kMode == 1 ? gwork : gwork + (long)m * c);
   const bool want_v = V != nullptr;
@@ -1663,20 +1727,50 @@ void svd_small(Context& ctx, const double* A, bool transA, int m, int c, long ld
   const size_t lds_bytes = sizeof(double) * (mode == 2 ? uc + vc : (mode == 1 ? uc : 0));
   if (mode == 2)
     hipLaunchKernelGGL(k_jacobi_svd<2>, dim3(1), dim3(threads), lds_request(lds_bytes), ctx.stream, m, c, A,
-                       transA ? 1 : 0, lda, nullptr, U, s, V, 40, G);
+                       transA ? 1 : 0, lda, nullptr, U, s, V, 40, G, SvdStrides());
   else if (mode == 1)
     hipLaunchKernelGGL(k_jacobi_svd<1>, dim3(1), dim3(threads), lds_request(lds_bytes), ctx.stream, m, c, A,
-                       transA ? 1 : 0, lda, work.d(), U, s, V, 40, G);
+                       transA ? 1 : 0, lda, work.d(), U, s, V, 40, G, SvdStrides());
   else
     hipLaunchKernelGGL(k_jacobi_svd<0>, dim3(1), dim3(threads), 0, ctx.stream, m, c, A, transA ? 1 : 0, lda,
-                       work.d(), U, s, V, 40, G);
+                       work.d(), U, s, V, 40, G, SvdStrides());
+  TTIGA_HIP(hipGetLastError());
+}
+
+void svd_small_batched(Context& ctx, int batch, const double* A, long sA, bool transA, int m, int c, long lda,
+                       double* U, long sU, double* s, long sS, double* V, long sV, const char* prof_name) {
+  TTIGA_CHECK(c > 0 && m >= c && c <= 1024 && batch >= 1 && batch <= 65535, TTIGA_E_ARG,
+              "svd_small_batched: bad shape");
+  const long uc = (long)m * c, vc = V ? (long)c * c : 0;
+  if (batch == 1 || uc + vc > lds_doubles()) {
+    // one problem, or columns that do not fit in LDS: one launch per problem
+    for (int b = 0; b < batch; ++b)
+      svd_small(ctx, A + b * sA, transA, m, c, lda, U + b * sU, s + b * sS, V ? V + b * sV : nullptr, prof_name);
+    return;
+  }
+  const int pairs = (c + 1) / 2;
+  const int G = jacobi_group(m);
+  const int threads = 64 * std::min(16, std::max(1, (pairs * G + 63) / 64));
+  const double per_rot = 12.0 * m + (V ? 6.0 * c : 0.0);
+  ProfScope prof(ctx, prof_name, batch * 8.0 * 0.5 * c * (c - 1.0) * per_rot,
+                 batch * 8.0 * (2.0 * m * c + (V ? 2.0 * c * c : 0.0) + c), c);
+  SvdStrides bs;
+  bs.a = sA;
+  bs.u = sU;
+  bs.s = sS;
+  bs.v = sV;
+  hipLaunchKernelGGL(k_jacobi_svd<2>, dim3(batch), dim3(threads), lds_request(sizeof(double) * (uc + vc)), ctx.stream,
+                     m, c, A, transA ? 1 : 0, lda, nullptr, U, s, V, 40, G, bs);
   TTIGA_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------ small utilities
 __global__ void k_trunc_rank(const double* __restrict__ s, int c, double eps_rel, double delta_abs,
-                             double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+                             double* __restrict__ out, long ss) {
+  // one problem per block: problem b reads s + b ss and writes out[3 b .. 3 b + 2]
+  if (threadIdx.x != 0) return;
+  s += blockIdx.x * ss;
+  out += 3L * blockIdx.x;
   double tot = 0.0;
   for (int i = 0; i < c; ++i) tot += s[i] * s[i];
   const double nrm = sqrt(tot);
@@ -1703,7 +1797,7 @@ int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* 
   double* hd = ctx.host_device(3);
   double* h = ctx.host_scratch;
   hipLaunchKernelGGL(k_trunc_rank, dim3(1), dim3(64), 0, ctx.stream, s, c,
-                     delta < 0 ? -delta : 0.0, delta < 0 ? -1.0 : delta, hd);
+                     delta < 0 ? -delta : 0.0, delta < 0 ? -1.0 : delta, hd, 0L);
   TTIGA_HIP(hipGetLastError());
   ctx.sync();
   if (norm_out) {
@@ -1711,6 +1805,22 @@ int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* 
     norm_out[1] = h[2];
   }
   return (int)h[0];
+}
+
+void trunc_ranks_sync(Context& ctx, int batch, const double* s, long ss, int c, const double* delta, int* ranks,
+                      double* norms) {
+  double* hd = ctx.host_device(3 * (size_t)batch);
+  double* h = ctx.host_scratch;
+  // one launch per problem (the thresholds differ), one host round trip for all
+  for (int b = 0; b < batch; ++b)
+    hipLaunchKernelGGL(k_trunc_rank, dim3(1), dim3(64), 0, ctx.stream, s + b * ss, c,
+                       delta[b] < 0 ? -delta[b] : 0.0, delta[b] < 0 ? -1.0 : delta[b], hd + 3L * b, 0L);
+  TTIGA_HIP(hipGetLastError());
+  ctx.sync();
+  for (int b = 0; b < batch; ++b) {
+    ranks[b] = (int)h[3 * b];
+    if (norms) norms[b] = h[3 * b + 1];
+  }
 }
 
 __global__ void k_fill(double* p, size_t n, double v) {

@@ -490,10 +490,23 @@ bool Problem::compress_cross(const GeoDev& gd, const SourceDev& sd, TT* fac, tti
     for (int t = 0; t < 6; ++t) cmax = std::max(cmax, std::sqrt(std::max(hc[t], 0.0)));
     const double cscale[7] = {cmax, cmax, cmax, cmax, cmax, cmax, std::sqrt(std::max(hc[6], 0.0))};
     bool saturated = false;
-    for (int t = 0; t < 7; ++t) {
-      k[t] = cscale[t] > 0.0 ? column_basis(c, Cf.d() + (size_t)t * cnt, n0, L, 0.1 * eps * cscale[t], U[t]) : 0;
-      if (k[t] > L - 8) saturated = true;
+    if (n0 > L) {
+      // the seven bases in batched factorisations (the same bits as one at a time)
+      double dl[7];
+      for (int t = 0; t < 7; ++t) dl[t] = 0.1 * eps * cscale[t];
+      int kb[7];
+      DBuf Ub[7];
+      column_basis_batched(c, 7, Cf.d(), cnt, n0, L, dl, kb, Ub);
+      for (int t = 0; t < 7; ++t) {
+        k[t] = cscale[t] > 0.0 ? kb[t] : 0;
+        if (k[t] > 0) U[t] = std::move(Ub[t]);
+      }
+    } else {
+      for (int t = 0; t < 7; ++t)
+        k[t] = cscale[t] > 0.0 ? column_basis(c, Cf.d() + (size_t)t * cnt, n0, L, 0.1 * eps * cscale[t], U[t]) : 0;
     }
+    for (int t = 0; t < 7; ++t)
+      if (k[t] > L - 8) saturated = true;
     if (trace)
       std::fprintf(stderr, "[cross] L %d column ranks %d %d %d %d %d %d %d\n", L, k[0], k[1], k[2], k[3], k[4], k[5],
                    k[6]);

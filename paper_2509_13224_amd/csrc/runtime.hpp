@@ -304,6 +304,10 @@ inline int grid_for(long total) { return (int)std::max<long>(1, std::min<long>((
 // Q (m x c, row-major, orthonormal columns) and R (c x c, upper) with op(A) = Q R (Householder TSQR).
 void qr_tall(Context& ctx, const double* A, bool transA, int m, int c, long lda, double* Q,
              double* R);
+// qr_tall of `batch` problems of one shape in the same launches: problem b reads A + b sA and
+// writes Q + b sQ, R + b sR (c <= 256).
+void qr_tall_batched(Context& ctx, int batch, const double* A, long sA, bool transA, int m, int c, long lda,
+                     double* Q, long sQ, double* R, long sR);
 // One-sided Jacobi SVD of op(A) (m x c, m >= c): U (m x c), s (c, descending), V (c x c);
 // V may be null when the right vectors are not needed.  prof_name labels the launch in
 // the profile.
@@ -320,6 +324,14 @@ bool cholesky_inverse(Context& ctx, const double* G, int c, double* R, double* R
 int pivoted_cholesky(Context& ctx, const double* G, int r, double* L, double tau_rel);
 // Smallest r with ||s[r:]|| <= delta (delta < 0: -delta * ||s|| / sqrt(2) relative).
 int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* norm_out);
+// truncation ranks of `batch` singular value lists (s + b ss, thresholds as trunc_rank_sync's
+// delta, one per list) with one host round trip; norms (optional) receives each list's norm
+void trunc_ranks_sync(Context& ctx, int batch, const double* s, long ss, int c, const double* delta, int* ranks,
+                      double* norms);
+// svd_small of `batch` problems of one shape (problem b: A + b sA, U + b sU, s + b sS, V + b sV):
+// one launch when a problem's columns fit in LDS, else one launch per problem
+void svd_small_batched(Context& ctx, int batch, const double* A, long sA, bool transA, int m, int c, long lda,
+                       double* U, long sU, double* s, long sS, double* V, long sV, const char* prof_name = "jacobi_svd");
 void fill(Context& ctx, double* p, size_t n, double v);
 void copy(Context& ctx, double* dst, const double* src, size_t n);
 void sumsq_reduce(Context& ctx, const double* x, size_t n, double* out_dev);
@@ -389,6 +401,10 @@ bool tt_from_first_unfolding(Context& ctx, const double* Qb, int L, const double
 // Orthonormal basis U (m x k) of the columns of C (m x L, m >= L) from its truncated SVD
 // with tail delta (Frobenius; delta < 0: relative to ||C||); returns k (0: C is below it).
 int column_basis(Context& ctx, const double* C, int m, int L, double delta, DBuf& U);
+// column_basis of `count` m x L matrices C + t stride (m > L) at thresholds delta[t]: ranks into
+// k[t], bases into U[t] (left empty at rank 0), with the factorisations batched
+void column_basis_batched(Context& ctx, int count, const double* C, long stride, int m, int L, const double* delta,
+                          int* k, DBuf* U);
 // out[i][j] = A[i][j] / S[j] for an m x cols row-major A.
 void scale_cols_inv(Context& ctx, const double* A, int m, int cols, const double* S, double* out);
 // out (nr x k) = rows `rows` (device) of A (n x k), row-major.

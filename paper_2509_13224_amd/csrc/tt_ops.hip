@@ -833,6 +833,28 @@ int column_basis(Context& ctx, const double* C, int m, int L, double delta, DBuf
   return t.s;
 }
 
+void column_basis_batched(Context& ctx, int count, const double* C, long stride, int m, int L, const double* delta,
+                          int* k, DBuf* U) {
+  TTIGA_CHECK(m > L && L > 0 && count >= 1, TTIGA_E_ARG, "column_basis_batched needs m > L > 0");
+  // the tall route of truncated_svd for every matrix at once: C_t = Q_t T_t (one TSQR launch per
+  // tree level), Jacobi on the rows of T_t (one launch), the ranks (one host round trip), then
+  // U_t = Q_t Ut_t; each problem runs the same kernels as alone, so the bases are the same bits
+  const size_t cnt = count;
+  DBuf Q(ctx.alloc, sizeof(double) * cnt * m * L), T(ctx.alloc, sizeof(double) * cnt * L * L);
+  qr_tall_batched(ctx, count, C, stride, false, m, L, L, Q.d(), (long)m * L, T.d(), (long)L * L);
+  DBuf Ut(ctx.alloc, sizeof(double) * cnt * L * L), V(ctx.alloc, sizeof(double) * cnt * L * L),
+      S(ctx.alloc, sizeof(double) * cnt * L);
+  svd_small_batched(ctx, count, T.d(), (long)L * L, true, L, L, L, V.d(), (long)L * L, S.d(), L, Ut.d(),
+                    (long)L * L);
+  trunc_ranks_sync(ctx, count, S.d(), L, L, delta, k, nullptr);
+  for (int t = 0; t < count; ++t) {
+    if (k[t] == 0) continue;
+    U[t] = DBuf(ctx.alloc, sizeof(double) * (size_t)m * k[t]);
+    gemm(ctx, false, false, m, k[t], L, 1.0, Q.d() + (size_t)t * m * L, L, 0, Ut.d() + (size_t)t * L * L, L, 0, 0.0,
+         U[t].d(), k[t], 0);
+  }
+}
+
 __global__ void k_gather_rows(const double* __restrict__ A, int k, const int* __restrict__ rows, int nr,
                               double* __restrict__ out) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)nr * k; e += (long)gridDim.x * blockDim.x)
