@@ -14,6 +14,10 @@ struct GeoDev {
   const int* span[3];  // per sample coordinate
   const double* B[3];
   const double* D[3];
+  // for the det J pass over the Gauss grid: the third direction's sample coordinates and the
+  // geometry's knot vector in that direction (null elsewhere)
+  const double* xi2 = nullptr;
+  const double* knots2 = nullptr;
 };
 
 struct SourceDev {

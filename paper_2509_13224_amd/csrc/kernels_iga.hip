@@ -842,6 +842,141 @@ __global__ __launch_bounds__(256) void k_detj_lin(GeoDev geo, int Q1, int Q2, lo
   if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
+// The same minimum for geometry degree P2 = 2 or 3 in the third direction, one grid row per
+// lane, by the rational form of k_detj_lin generalised: on a knot span of xi2 every homogeneous
+// sum is a polynomial of degree P2 in the local coordinate t = (xi2 - k_s) / h, with the span's
+// basis polynomials from P2 + 1 equispaced values (Cox-de Boor) and the inverse Vandermonde
+// matrix of those nodes; then M = w dH - H dw has degree 2 P2, det M degree 6 P2 and
+// det J = det M(t) / w(t)^6.  Per point: Horner's rule of degree 6 P2, w(t), one division.
+// Against the direct formula (CPU check on the bumpy cube and the twisted box, degree 3):
+// within 1e-14 of the product of J's column norms.
+template <int P2>
+__global__ __launch_bounds__(256) void k_detj_poly(GeoDev geo, int Q1, int Q2, long rows, double* __restrict__ part) {
+  constexpr int NQ = P2 + 1, NM = 2 * P2 + 1, NMIN = 4 * P2 + 1, NDET = 6 * P2 + 1;
+  __shared__ double red[4];
+  const int p0 = geo.pg[0], p1 = geo.pg[1];
+  const int m1 = geo.m[1], m2 = geo.m[2];
+  double mn = 1e300;
+  for (long row = blockIdx.x * 256L + threadIdx.x; row < rows; row += (long)gridDim.x * 256L) {
+    const int i0 = (int)(row / Q1), i1 = (int)(row % Q1);
+    const int s0 = geo.span[0][i0], s1 = geo.span[1][i1];
+    const double* B0 = geo.B[0] + (long)i0 * (p0 + 1);
+    const double* D0 = geo.D[0] + (long)i0 * (p0 + 1);
+    const double* B1 = geo.B[1] + (long)i1 * (p1 + 1);
+    const double* D1 = geo.D[1] + (long)i1 * (p1 + 1);
+    int cur = -1;
+    double cf[NDET], wc[NQ], ka = 0.0, hinv = 1.0;
+    for (int i = 0; i < NDET; ++i) cf[i] = 0.0;
+    for (int i = 0; i < NQ; ++i) wc[i] = 0.0;
+    for (int i2 = 0; i2 < Q2;) {
+      const int s2 = geo.span[2][i2];
+      if (s2 != cur) {
+        cur = s2;
+        ka = geo.knots2[s2];
+        const double h = geo.knots2[s2 + 1] - ka;
+        hinv = 1.0 / h;
+        // basis polynomials of the span: A[j][c] = coefficient of t^j in N_{s2-P2+c}
+        double A[NQ][NQ];
+        {
+          double vals[NQ][NQ], dummy[NQ];
+          for (int j = 0; j < NQ; ++j) local_basis(geo.knots2, P2, s2, ka + h * ((double)j / P2), vals[j], dummy);
+          // inverse Vandermonde of the nodes j / P2 (rows: powers of t, columns: nodes)
+          const double vi2[3][3] = {{1.0, 0.0, 0.0}, {-3.0, 4.0, -1.0}, {2.0, -4.0, 2.0}};
+          const double vi3[4][4] = {{1.0, 0.0, 0.0, 0.0},
+                                    {-5.5, 9.0, -4.5, 1.0},
+                                    {9.0, -22.5, 18.0, -4.5},
+                                    {-4.5, 13.5, -13.5, 4.5}};
+          for (int j = 0; j < NQ; ++j)
+            for (int c = 0; c < NQ; ++c) {
+              double acc = 0.0;
+              for (int q = 0; q < NQ; ++q) acc += (P2 == 2 ? vi2[j][q] : vi3[j][q]) * vals[q][c];
+              A[j][c] = acc;
+            }
+        }
+        // staged sums of the span's control planes, as polynomials: q[v][sc][j]
+        double q[3][4][NQ];
+        for (int v = 0; v < 3; ++v)
+          for (int sc = 0; sc < 4; ++sc)
+            for (int j = 0; j < NQ; ++j) q[v][sc][j] = 0.0;
+        for (int c = 0; c < NQ; ++c) {
+          double T[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+          for (int a = 0; a <= p0; ++a)
+            for (int b = 0; b <= p1; ++b) {
+              const double wv = B0[a] * B1[b], w0 = D0[a] * B1[b], w1 = B0[a] * D1[b];
+              const double* Pc = geo.Pw + (((long)(s0 - p0 + a) * m1 + (s1 - p1 + b)) * m2 + (s2 - P2 + c)) * 4;
+              for (int sc = 0; sc < 4; ++sc) {
+                T[0][sc] += wv * Pc[sc];
+                T[1][sc] += w0 * Pc[sc];
+                T[2][sc] += w1 * Pc[sc];
+              }
+            }
+          for (int v = 0; v < 3; ++v)
+            for (int sc = 0; sc < 4; ++sc)
+              for (int j = 0; j < NQ; ++j) q[v][sc][j] += A[j][c] * T[v][sc];
+        }
+        // the derivative along xi2 of the value polynomials (degree P2 - 1, top coefficient 0)
+        double g[4][NQ];
+        for (int sc = 0; sc < 4; ++sc) {
+          for (int j = 0; j + 1 < NQ; ++j) g[sc][j] = (j + 1) * q[0][sc][j + 1] * hinv;
+          g[sc][NQ - 1] = 0.0;
+        }
+        // M[k][i] = w D_i,k - H_k D_i,w (degree 2 P2)
+        double M[3][3][NM];
+        for (int k = 0; k < 3; ++k)
+          for (int i = 0; i < 3; ++i) {
+            const double* Dk = i == 0 ? q[1][k] : (i == 1 ? q[2][k] : g[k]);
+            const double* Dw = i == 0 ? q[1][3] : (i == 1 ? q[2][3] : g[3]);
+            double x[NM], y[NM];
+            poly_mul(q[0][3], NQ, Dk, NQ, x);
+            poly_mul(q[0][k], NQ, Dw, NQ, y);
+            for (int e = 0; e < NM; ++e) M[k][i][e] = x[e] - y[e];
+          }
+        double x[NMIN], y[NMIN], mn0[NMIN], mn1[NMIN], mn2[NMIN];
+        poly_mul(M[1][1], NM, M[2][2], NM, x);
+        poly_mul(M[1][2], NM, M[2][1], NM, y);
+        for (int e = 0; e < NMIN; ++e) mn0[e] = x[e] - y[e];
+        poly_mul(M[1][0], NM, M[2][2], NM, x);
+        poly_mul(M[1][2], NM, M[2][0], NM, y);
+        for (int e = 0; e < NMIN; ++e) mn1[e] = x[e] - y[e];
+        poly_mul(M[1][0], NM, M[2][1], NM, x);
+        poly_mul(M[1][1], NM, M[2][0], NM, y);
+        for (int e = 0; e < NMIN; ++e) mn2[e] = x[e] - y[e];
+        double u[NDET];
+        poly_mul(M[0][0], NM, mn0, NMIN, cf);
+        poly_mul(M[0][1], NM, mn1, NMIN, u);
+        for (int e = 0; e < NDET; ++e) cf[e] -= u[e];
+        poly_mul(M[0][2], NM, mn2, NMIN, u);
+        for (int e = 0; e < NDET; ++e) cf[e] += u[e];
+        for (int j = 0; j < NQ; ++j) wc[j] = q[0][3][j];
+      }
+      auto value = [&](double xi) {
+        const double t = (xi - ka) * hinv;
+        double sdet = cf[NDET - 1];
+#pragma unroll
+        for (int e = NDET - 2; e >= 0; --e) sdet = sdet * t + cf[e];
+        double w = wc[NQ - 1];
+#pragma unroll
+        for (int j = NQ - 2; j >= 0; --j) w = w * t + wc[j];
+        const double w2 = w * w;
+        return sdet / (w2 * w2 * w2);
+      };
+      if (i2 + 3 < Q2 && geo.span[2][i2 + 3] == s2) {
+        const double* xv = geo.xi2 + i2;
+        const double v0 = value(xv[0]), v1 = value(xv[1]), v2 = value(xv[2]), v3 = value(xv[3]);
+        mn = fmin(mn, fmin(fmin(v0, v1), fmin(v2, v3)));
+        i2 += 4;
+      } else {
+        mn = fmin(mn, value(geo.xi2[i2]));
+        i2 += 1;
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
 __global__ void k_min_reduce(const double* __restrict__ part, long count, double* __restrict__ out) {
   __shared__ double sh[256];
   double v = 1e300;
@@ -995,16 +1130,23 @@ void launch_detj_min(Context& ctx, const GeoDev& geo, const int* Q, double* min_
   // degree 1 along xi2: a rational function per row and span, about 20 flop a point (the
   // direct formula: 32 (p_g2 + 1) + 40)
   const bool lin = geo.pg[2] == 1;
-  ProfScope prof(ctx, "geometry_detj", (lin ? 20.0 : 32.0 * (geo.pg[2] + 1) + 40.0) * total, 0.0);
+  // degrees 2 and 3: the polynomial form, given the sample coordinates and knots along xi2
+  const bool poly = (geo.pg[2] == 2 || geo.pg[2] == 3) && geo.xi2 && geo.knots2;
+  ProfScope prof(ctx, "geometry_detj",
+                 (lin ? 20.0 : (poly ? 14.0 * geo.pg[2] + 20.0 : 32.0 * (geo.pg[2] + 1) + 40.0)) * total, 0.0);
   // two blocks per compute unit: the kernel loops over rows for its whole duration, so a
   // larger grid would hold every wave slot while the kernels of other streams wait (the
   // degree-1 kernel: one row per lane, 256 rows per block and pass)
-  const int blocks = (int)std::min<long>(lin ? (rows + 255) / 256 : (rows + 3) / 4, 512);
+  const int blocks = (int)std::min<long>(lin || poly ? (rows + 255) / 256 : (rows + 3) / 4, 512);
   const int iters = (int)((rows + 4L * blocks - 1) / (4L * blocks));
   DBuf part(ctx.alloc, sizeof(double) * blocks);
   const size_t lds = sizeof(double) * 4 * 12 * geo.m[2];
   if (lin)
     hipLaunchKernelGGL(k_detj_lin, dim3(blocks), dim3(256), 0, ctx.stream, geo, Q[1], Q[2], rows, part.d());
+  else if (poly && geo.pg[2] == 2)
+    hipLaunchKernelGGL(k_detj_poly<2>, dim3(blocks), dim3(256), 0, ctx.stream, geo, Q[1], Q[2], rows, part.d());
+  else if (poly)
+    hipLaunchKernelGGL(k_detj_poly<3>, dim3(blocks), dim3(256), 0, ctx.stream, geo, Q[1], Q[2], rows, part.d());
   else if (geo.pg[2] == 2)
     hipLaunchKernelGGL(k_detj_rows_reg<2>, dim3(blocks), dim3(256), lds, ctx.stream, geo, 0, Q[1], Q[2], rows, iters,
                        part.d());

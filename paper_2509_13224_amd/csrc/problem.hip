@@ -692,7 +692,10 @@ void Problem::assemble(ttiga_assembly_stats* st) {
   bool done = false;
   if (cross) {
     // det J on the whole grid (the E_DETJ guarantee), then the cross approximation
-    launch_detj_min(c, gd, Q, st8.d());
+    GeoDev gdj = gd;
+    gdj.xi2 = tab_xi[2].d();
+    gdj.knots2 = gknots_d[2].d();
+    launch_detj_min(c, gdj, Q, st8.d());
     double* h = c.host(1);
     TTIGA_HIP(hipMemcpyAsync(h, st8.d(), sizeof(double), hipMemcpyDeviceToHost, c.stream));
     c.sync();

@@ -251,22 +251,35 @@ def _warped_column():
                     ctrl=ctrl, weights=wts)
 
 
-@pytest.mark.parametrize("geo_name", ["warped_column", "ring"])
-def test_detj_pass_degree1_matches_oracle(ctx, geo_name):
-    """Geometries of degree 1 along xi2 take the rational det J pass (per row and knot span a
-    degree-5 polynomial over w^6, evaluated four points at a time): weights varying along xi2
-    over three spans (a division per point, spans changing inside the rows) and the ring
-    (weights constant along xi2: one division per span), 114 Gauss points per direction (not
-    a multiple of four).  The reported minimum lies within 1e-12 of the largest |det J| of the
-    oracle's grid."""
-    say("det J degree 1", geo_name)
-    geo = _warped_column() if geo_name == "warped_column" else W.ring()
+def _annulus_cyclic():
+    """The annulus sector with its parametric axes permuted cyclically (orientation kept):
+    degree (1, 1, 2), the quadratic NURBS direction third."""
+    from workloads.problem import Geometry
+    a = W.annulus_sector(1.0, 2.0, math.pi / 2, 1.0)
+    return Geometry(degree=(a.degree[2], a.degree[0], a.degree[1]), knots=[a.knots[2], a.knots[0], a.knots[1]],
+                    ctrl=np.ascontiguousarray(np.transpose(a.ctrl, (2, 0, 1, 3))),
+                    weights=np.ascontiguousarray(np.transpose(a.weights_or_ones(), (2, 0, 1))))
+
+
+@pytest.mark.parametrize("geo_name", ["warped_column", "ring", "annulus_cyclic", "twisted", "bumpy"])
+def test_detj_pass_rational_matches_oracle(ctx, geo_name):
+    """The det J pass over the whole Gauss grid in its rational form (per row and knot span of
+    xi2, det M(t) / w(t)^6 with det M a polynomial of degree 6 p_g2 - 1, evaluated four points at
+    a time): degree 1 along xi2 with weights varying over three spans (a division per point,
+    spans changing inside the rows) and the ring (weights constant along xi2: one division per
+    span); degree 2 (the annulus with its axes permuted cyclically); degree 3 on one span (the
+    twisted box) and on five (the bumpy cube); 114 Gauss points per direction (not a multiple
+    of four).  The reported minimum lies within 1e-12 of the largest |det J| of the oracle's
+    grid."""
+    say("det J rational", geo_name)
+    geo = {"warped_column": _warped_column, "ring": W.ring, "annulus_cyclic": _annulus_cyclic,
+           "twisted": lambda: W.twisted_box(1.0), "bumpy": W.bumpy_cube}[geo_name]()
     pr = W.small_problem(geo, 40, 2, W.fourier_source(geo, 5))
     h = ctx.problem_create(pr)
     st = h.assemble()
     _, detj = geometry.sample_factors_grid(pr)
     assert detj.shape == (114, 114, 114)
-    say("det J degree 1", geo_name, st["min_detJ"], detj.min())
+    say("det J rational", geo_name, st["min_detJ"], detj.min())
     assert abs(st["min_detJ"] - detj.min()) <= 1e-12 * np.abs(detj).max()
 
 
