@@ -164,6 +164,7 @@ __global__ void __launch_bounds__(256) k_dots(long n, DotArgs a, double* __restr
       for (int v = 0; v < 4; ++v) out[v] = sh[v][0];
     }
     *counter = 0u;
+    __threadfence_system();  // out is host-mapped memory read between graph replays
   }
 }
 

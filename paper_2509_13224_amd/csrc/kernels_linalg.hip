@@ -1121,7 +1121,10 @@ __global__ __launch_bounds__(1024) void k_pchol(int r, const double* __restrict_
     }
     __syncthreads();
   }
-  if (tid == 0) *rank_out = k;
+  if (tid == 0) {
+    *rank_out = k;
+    __threadfence_system();  // rank_out is host-mapped memory
+  }
 }
 
 static bool pchol_lds_fit(int r) {
@@ -1522,7 +1525,18 @@ static int jacobi_group(int m) {
   return m <= 16 ? 8 : 16;
 }
 
-__global__ void k_copy_scalar(const double* __restrict__ src, double* __restrict__ dst) { dst[0] = src[0]; }
+// Device results handed to the host through host-mapped memory: the system-scope fence
+// writes them back past the device caches before the wave ends, so that they are in host
+// memory by the time the host sees the kernel complete (a plain store need not be).
+__global__ void k_publish(const double* __restrict__ src, double* __restrict__ dst, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  __threadfence_system();
+}
+
+void publish_to_host(Context& ctx, const double* src, double* dst_mapped, int n) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, ctx.stream, src, dst_mapped, n);
+  TTIGA_HIP(hipGetLastError());
+}
 
 // ---- one-sided Jacobi over the whole device, for matrices whose columns do not fit in LDS
 // (c > 135: the 1-D eigenbases of long directions, wide R factors).  The columns of W = op(A)
@@ -1689,7 +1703,7 @@ static void svd_rounds(Context& ctx, const double* A, bool transA, int m, int c,
                          f2.d(), reinterpret_cast<unsigned long long*>(mx.d()));
     }
     TTIGA_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, ctx.stream, mx.d(), h);
+    publish_to_host(ctx, mx.d(), h, 1);
     ctx.sync();
     if (!(ctx.host_scratch[0] > 2.220446049250313e-16 * m)) break;  // a sweep without rotations
   }
@@ -1790,6 +1804,7 @@ __global__ void k_trunc_rank(const double* __restrict__ s, int c, double eps_rel
   out[0] = (double)r;
   out[1] = nrm;
   out[2] = delta;
+  __threadfence_system();  // out is host-mapped memory when the host reads the rank
 }
 
 int trunc_rank_sync(Context& ctx, const double* s, int c, double delta, double* norm_out) {

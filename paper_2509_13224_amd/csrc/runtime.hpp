@@ -359,6 +359,9 @@ void tt_mode_product(Context& ctx, TT& x, int d, const double* Mat, bool trans);
 void tt_axpby(Context& ctx, double alpha, const TT& x, double beta, const TT& y, TT& out);
 void tt_axpby_dev(Context& ctx, const double* alpha, const TT& x, const double* beta, const TT& y,
                   TT& out);
+// copies n device doubles into host-mapped memory (a Context::host_device address) with a
+// system-scope fence, so that they are in host memory once the stream has drained
+void publish_to_host(Context& ctx, const double* src, double* dst_mapped, int n);
 double tt_dot_sync(Context& ctx, const TT& x, const TT& y);
 // out[i] = x_i . y_i for count pairs (count <= 8) with one host synchronisation
 void tt_dots_sync(Context& ctx, const TT* const* x, const TT* const* y, int count, double* out);

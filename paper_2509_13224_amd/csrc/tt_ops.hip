@@ -457,17 +457,23 @@ void tt_dot_dev(Context& ctx, const TT& x, const TT& y, double* out_dev) {
   tt_dot_cores(ctx, x.n, x.r, xc, y.r, yc, out_dev, scratch.d());
 }
 
+// The products land in device memory and one fenced kernel hands them to the host-mapped
+// array (a product kernel's plain stores into host memory need not be visible when the host
+// sees the stream drain).
 double tt_dot_sync(Context& ctx, const TT& x, const TT& y) {
-  double* hd = ctx.host_device(1);
-  tt_dot_dev(ctx, x, y, hd);
-  ctx.sync();
-  return ctx.host_scratch[0];
+  const TT* xp = &x;
+  const TT* yp = &y;
+  double out = 0.0;
+  tt_dots_sync(ctx, &xp, &yp, 1, &out);
+  return out;
 }
 
 void tt_dots_sync(Context& ctx, const TT* const* x, const TT* const* y, int count, double* out) {
   TTIGA_CHECK(count > 0 && count <= 8, TTIGA_E_ARG, "tt_dots_sync: 1..8 pairs");
+  DBuf dev(ctx.alloc, sizeof(double) * count);
+  for (int i = 0; i < count; ++i) tt_dot_dev(ctx, *x[i], *y[i], dev.d() + i);
   double* hd = ctx.host_device(count);
-  for (int i = 0; i < count; ++i) tt_dot_dev(ctx, *x[i], *y[i], hd + i);
+  publish_to_host(ctx, dev.d(), hd, count);
   ctx.sync();
   for (int i = 0; i < count; ++i) out[i] = ctx.host_scratch[i];
 }
